@@ -1,0 +1,377 @@
+"""Incremental 4D-Var inner loop: exact solution, RIOT replica, CG and Lanczos.
+
+Notation (Section 2.1, eq. 3): control dz, increment dx = L dz, B = L L^T,
+innovation d = y - H(x) (eq. 3's sign), G = stacked Jacobians H_t M_{0->t} of
+the observed window, A = L^T G^T R^{-1} G L (the prior-preconditioned Hessian
+minus I, Section 2.2 after eq. 4), gradient at dz = 0 of the outer-loop cost in
+control variables g = v - L^T G^T R^{-1} d. The inner-loop minimiser is
+dz* = -(I + A)^{-1} g.
+
+Observation operator: point values of state variables at window steps; R is
+diagonal (entries 1 / rinv).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import bcov, l96
+
+
+@dataclass
+class Problem:
+    """Statement of one inner-loop problem (eq. 2 / eq. 3 inputs)."""
+
+    n: int
+    nsteps: int
+    h: float
+    F: float
+    obs_step: np.ndarray
+    obs_idx: np.ndarray
+    y: np.ndarray
+    rinv: np.ndarray
+    xb: np.ndarray
+    taps: np.ndarray
+
+    @property
+    def nobs(self) -> int:
+        return int(self.obs_step.size)
+
+
+def realize_l96(w, draws: dict, taps: np.ndarray | None = None) -> tuple[Problem, np.ndarray]:
+    """Build a twin-experiment problem from seeded draws.
+
+    Truth: nonlinear spin-up of the perturbed rest state; observations: truth
+    trajectory sampled at the observation points plus noise; background:
+    truth + L xi. Returns (problem, truth initial state).
+    """
+    if taps is None:
+        taps = bcov.gaussian_taps(w.ell, w.sigma_b)
+    truth0 = l96.forecast(np.asarray(draws["x0"], dtype=np.float64), w.spinup, w.dt, w.forcing)
+    _, states = l96.trajectory(truth0, w.nsteps, w.dt, w.forcing)
+    obs_step = np.asarray(draws["obs_step"])
+    obs_idx = np.asarray(draws["obs_idx"])
+    y = states[obs_step, obs_idx] + draws["obs_noise"]
+    xb = truth0 + bcov.apply_L(draws["bg_noise"], taps)
+    prob = Problem(w.n, w.nsteps, w.dt, w.forcing, obs_step, obs_idx, y,
+                   np.asarray(draws["rinv"], dtype=np.float64), xb, taps)
+    return prob, truth0
+
+
+# --------------------------------------------------------------------------
+# Linearisation (Alg. 3: integrate and store the trajectory, innovation)
+# --------------------------------------------------------------------------
+
+@dataclass
+class Linearization:
+    stages: np.ndarray   # (T, 4, n) RK4 stage states
+    states: np.ndarray   # (T+1, n) trajectory
+    d: np.ndarray        # innovation y - H(x) per observation
+    g: np.ndarray        # control-space gradient v - L^T G^T R^{-1} d
+    J: float             # cost 1/2 v^T v + 1/2 d^T R^{-1} d
+
+
+def adjoint_window(p: Problem, stages: np.ndarray, forcing: np.ndarray) -> np.ndarray:
+    """G^T f: adjoint sweep injecting H_t^T f_t at each observed step.
+
+    ``forcing`` has shape (nobs,) or (nobs, m). Returns lambda_0 (n,) or (n, m).
+    """
+    shape = (p.n,) + forcing.shape[1:]
+    lam = np.zeros(shape)
+    for t in range(p.nsteps, -1, -1):
+        sel = p.obs_step == t
+        if np.any(sel):
+            np.add.at(lam, p.obs_idx[sel], forcing[sel])
+        if t > 0:
+            lam = l96.ad_step(stages[t - 1], lam, p.h)
+    return lam
+
+
+def tangent_window(p: Problem, stages: np.ndarray, dx0: np.ndarray) -> np.ndarray:
+    """G dx0: tangent-linear sweep sampled at the observations -> (nobs,) or (nobs, m)."""
+    out = np.zeros((p.nobs,) + dx0.shape[1:])
+    d = np.array(dx0, dtype=np.float64)
+    for t in range(p.nsteps + 1):
+        sel = np.nonzero(p.obs_step == t)[0]
+        if sel.size:
+            out[sel] = d[p.obs_idx[sel]]
+        if t < p.nsteps:
+            d = l96.tl_step(stages[t], d, p.h)
+    return out
+
+
+def linearize(p: Problem, x: np.ndarray, v: np.ndarray | None = None) -> Linearization:
+    """Outer-loop linearisation at x (Alg. 3 first steps; gradient per eq. 3)."""
+    stages, states = l96.trajectory(x, p.nsteps, p.h, p.F)
+    d = p.y - states[p.obs_step, p.obs_idx]
+    if v is None:
+        v = np.zeros(p.n)
+    lam0 = adjoint_window(p, stages, p.rinv * d)
+    g = v - bcov.apply_L(lam0, p.taps)
+    J = 0.5 * float(v @ v) + 0.5 * float(np.sum(p.rinv * d * d))
+    return Linearization(stages, states, d, g, J)
+
+
+def hvp(p: Problem, lin: Linearization, W: np.ndarray) -> np.ndarray:
+    """Hessian-probe products A W = L^T G^T R^{-1} G L W (Alg. 3, y_i = A w_i)."""
+    W = np.asarray(W, dtype=np.float64)
+    z = tangent_window(p, lin.stages, bcov.apply_L(W, p.taps))
+    rz = (p.rinv[:, None] * z) if z.ndim == 2 else p.rinv * z
+    return bcov.apply_L(adjoint_window(p, lin.stages, rz), p.taps)
+
+
+def dense_A(p: Problem, lin: Linearization, batch: int = 256) -> np.ndarray:
+    """Explicit A formed column by column from HVPs on the identity."""
+    A = np.empty((p.n, p.n))
+    for c0 in range(0, p.n, batch):
+        c1 = min(p.n, c0 + batch)
+        E = np.zeros((p.n, c1 - c0))
+        E[np.arange(c0, c1), np.arange(c1 - c0)] = 1.0
+        A[:, c0:c1] = hvp(p, lin, E)
+    return A
+
+
+def obs_jacobian(p: Problem, lin: Linearization) -> np.ndarray:
+    """G (nobs x n) formed from tangent-linear sweeps of the identity."""
+    return tangent_window(p, lin.stages, np.eye(p.n))
+
+
+# --------------------------------------------------------------------------
+# Exact inner-loop solution and posterior covariance
+# --------------------------------------------------------------------------
+
+@dataclass
+class Exact:
+    lam: np.ndarray    # eigenvalues of A, descending
+    V: np.ndarray      # eigenvectors (columns)
+    dz: np.ndarray     # -(I + A)^{-1} g
+    dx: np.ndarray     # L dz
+    dofs: float        # trace(A (I + A)^{-1})
+
+
+def exact_solve(p: Problem, A: np.ndarray, g: np.ndarray) -> Exact:
+    """Exact minimiser of eq. 3 by Cholesky, and the exact spectrum by eigh."""
+    Asym = 0.5 * (A + A.T)
+    lam, V = np.linalg.eigh(Asym)
+    lam, V = lam[::-1], V[:, ::-1]
+    C = np.linalg.cholesky(np.eye(p.n) + Asym)
+    dz = -np.linalg.solve(C.T, np.linalg.solve(C, g))
+    dx = bcov.apply_L(dz, p.taps)
+    dofs = float(np.sum(lam / (1.0 + lam)))
+    return Exact(lam, V, dz, dx, dofs)
+
+
+def exact_posterior(p: Problem, A: np.ndarray):
+    """Exact posterior covariances: control space (I+A)^{-1} and state space L P_z L^T."""
+    Pz = np.linalg.inv(np.eye(p.n) + 0.5 * (A + A.T))
+    Lm = bcov.dense_L(p.n, p.taps)
+    return Pz, Lm @ Pz @ Lm.T
+
+
+# --------------------------------------------------------------------------
+# RIOT: randomized SVD of A (Alg. 3, precond = false)
+# --------------------------------------------------------------------------
+
+@dataclass
+class RSVD:
+    lam: np.ndarray     # Ritz values, descending (m)
+    V: np.ndarray       # Ritz vectors Q Z (n x m)
+    Q: np.ndarray       # orthonormal basis of Y
+    Y: np.ndarray       # final Hessian-probe block
+    K: np.ndarray       # symmetrised single-pass estimate of Q^T A Q
+    k_asym: float       # ||K - K^T|| / ||K|| before symmetrisation
+
+
+def orth(Y: np.ndarray) -> np.ndarray:
+    """Householder QR of Y with R's diagonal made positive (unique Q for full rank)."""
+    Q, R = np.linalg.qr(Y)
+    s = np.sign(np.diag(R))
+    s[s == 0] = 1.0
+    return Q * s
+
+
+def rsvd(apply_A, Omega: np.ndarray, q: int = 0) -> RSVD:
+    """Randomized eigendecomposition of A as in Alg. 3.
+
+    Y = A Omega; q power steps (Q0 = orth(Y), Omega_eff = Q0, Y = A Q0; the
+    power step is Halko et al.'s subspace iteration, which the algorithm itself
+    does not list); Q = orth(Y); solve K (Q^T Omega_eff) = Q^T Y; symmetrise K;
+    K = Z Lambda Z^T; V = Q Z.
+    """
+    Om = np.asarray(Omega, dtype=np.float64)
+    Y = apply_A(Om)
+    for _ in range(q):
+        Om = orth(Y)
+        Y = apply_A(Om)
+    Q = orth(Y)
+    B1 = Q.T @ Y
+    B2 = Q.T @ Om
+    K = np.linalg.solve(B2.T, B1.T).T
+    nk = np.linalg.norm(K)
+    k_asym = float(np.linalg.norm(K - K.T) / nk) if nk > 0 else 0.0
+    K = 0.5 * (K + K.T)
+    lam, Z = np.linalg.eigh(K)
+    lam, Z = lam[::-1], Z[:, ::-1]
+    return RSVD(lam, Q @ Z, Q, Y, K, k_asym)
+
+
+def choose_update(lam_k: float) -> str:
+    """Adaptive rule of eq. 11: LRA when the last kept eigenvalue is >= 1, else LRU."""
+    return "lra" if lam_k >= 1.0 else "lru"
+
+
+def increment(p: Problem, lam: np.ndarray, V: np.ndarray, g: np.ndarray,
+              k: int | None = None, mode: str = "adaptive"):
+    """Adaptive increment (eqs. 8-11 in eq. 10's increment form; Alg. 3 update).
+
+    LRA: dz = -sum_i (1 + l_i)^{-1} v_i v_i^T g
+    LRU: dz = -(I - sum_i l_i / (1 + l_i) v_i v_i^T) g
+    Returns (dz, dx = L dz, dofs = sum l_i / (1 + l_i), mode used).
+    """
+    k = lam.size if k is None else k
+    lk, Vk = lam[:k], V[:, :k]
+    if mode == "adaptive":
+        mode = choose_update(float(lk[-1]))
+    c = Vk.T @ g
+    if mode == "lra":
+        dz = -(Vk @ (c / (1.0 + lk)))
+    elif mode == "lru":
+        dz = -(g - Vk @ (c * lk / (1.0 + lk)))
+    else:
+        raise ValueError(mode)
+    dofs = float(np.sum(lk / (1.0 + lk)))
+    return dz, bcov.apply_L(dz, p.taps), dofs, mode
+
+
+def posterior_cov(p: Problem, lam: np.ndarray, V: np.ndarray, k: int | None = None,
+                  mode: str = "adaptive", dense: bool = False):
+    """Low-rank posterior covariance in state space (eqs. 8, 9 with symmetric L).
+
+    LRU: P_a = B + W diag(-l/(1+l)) W^T;  LRA: P_a = W diag(1/(1+l)) W^T;
+    W = L V. Returns (W, coef, diag(P_a), dense P_a or None, mode).
+    """
+    k = lam.size if k is None else k
+    lk, Vk = lam[:k], V[:, :k]
+    if mode == "adaptive":
+        mode = choose_update(float(lk[-1]))
+    W = bcov.apply_L(Vk, p.taps)
+    Lm = bcov.dense_L(p.n, p.taps)
+    if mode == "lru":
+        coef = -lk / (1.0 + lk)
+        base_diag = np.sum(Lm * Lm, axis=1)
+    else:
+        coef = 1.0 / (1.0 + lk)
+        base_diag = np.zeros(p.n)
+    diag = base_diag + np.sum(W * W * coef[None, :], axis=1)
+    P = None
+    if dense:
+        P = (W * coef[None, :]) @ W.T
+        if mode == "lru":
+            P = P + Lm @ Lm.T
+    return W, coef, diag, P, mode
+
+
+# --------------------------------------------------------------------------
+# Iterative baselines: CG (eq. 4) and the Lanczos form of Alg. 1
+# --------------------------------------------------------------------------
+
+def cg(apply_IA, g: np.ndarray, iters: int, rtol: float = 0.0):
+    """Hestenes-Stiefel CG on (I + A) dz = -g from dz = 0; returns all iterates."""
+    x = np.zeros_like(g)
+    r = -g.copy()
+    pdir = r.copy()
+    rr = float(r @ r)
+    r0 = np.sqrt(rr)
+    its = []
+    for _ in range(iters):
+        qv = apply_IA(pdir)
+        alpha = rr / float(pdir @ qv)
+        x = x + alpha * pdir
+        r = r - alpha * qv
+        its.append(x.copy())
+        rr_new = float(r @ r)
+        if rtol > 0 and np.sqrt(rr_new) <= rtol * r0:
+            break
+        pdir = r + (rr_new / rr) * pdir
+        rr = rr_new
+    return np.array(its).T if its else np.zeros((g.size, 0))
+
+
+def krylov_minimizer(apply_A, g: np.ndarray, q: int) -> np.ndarray:
+    """eq. 4: dz_q = [Q Q^T (A + I) Q Q^T]^+ b over the Krylov basis of {b, A b, ...}.
+
+    b = -g here (eq. 3's right-hand side in this sign convention); the basis
+    is orthonormalised column by column with two Gram-Schmidt passes.
+    """
+    b = -g
+    cols = [b / np.linalg.norm(b)]
+    for _ in range(1, q):
+        w = apply_A(cols[-1])
+        for _ in range(2):
+            for c in cols:
+                w = w - (c @ w) * c
+        cols.append(w / np.linalg.norm(w))
+    Q = np.array(cols).T
+    M = Q.T @ (apply_A(Q) + Q)
+    return Q @ np.linalg.solve(M, Q.T @ b)
+
+
+def lanczos_varcg(apply_A, g: np.ndarray, m: int):
+    """Alg. 1 inner loop: m Lanczos steps with full re-orthogonalisation.
+
+    Returns (dz, ritz values, ritz vectors U = Q Z). With b = g (the gradient),
+    the increment is dz = -sum (1 + l_i)^{-1} u_i u_i^T b.
+    """
+    n = g.size
+    Q = np.zeros((n, m + 1))
+    alpha = np.zeros(m)
+    beta = np.zeros(m)
+    Q[:, 0] = g / np.linalg.norm(g)
+    used = m
+    for i in range(m):
+        w = apply_A(Q[:, i])
+        alpha[i] = Q[:, i] @ w
+        r = w - alpha[i] * Q[:, i]
+        if i > 0:
+            r = r - beta[i - 1] * Q[:, i - 1]
+        for _ in range(2):
+            r = r - Q[:, :i + 1] @ (Q[:, :i + 1].T @ r)
+        beta[i] = np.linalg.norm(r)
+        if beta[i] <= 1e-14 * max(1.0, abs(alpha[i])):
+            used = i + 1
+            break
+        Q[:, i + 1] = r / beta[i]
+    T = np.diag(alpha[:used]) + np.diag(beta[:used - 1], 1) + np.diag(beta[:used - 1], -1)
+    lam, Z = np.linalg.eigh(T)
+    U = Q[:, :used] @ Z
+    dz = -(U @ ((U.T @ g) / (1.0 + lam)))
+    return dz, lam[::-1], U[:, ::-1]
+
+
+# --------------------------------------------------------------------------
+# Outer loop (Alg. 3 with precond = false) and the full cost of eq. 2
+# --------------------------------------------------------------------------
+
+def cost(p: Problem, v: np.ndarray) -> float:
+    """eq. 2 written in control variables: x = x_b + L v."""
+    x = p.xb + bcov.apply_L(v, p.taps)
+    _, states = l96.trajectory(x, p.nsteps, p.h, p.F)
+    d = p.y - states[p.obs_step, p.obs_idx]
+    return 0.5 * float(v @ v) + 0.5 * float(np.sum(p.rinv * d * d))
+
+
+def outer_loop(p: Problem, n_outer: int, solver) -> list[dict]:
+    """Run n_outer outer loops; solver(lin) -> dz. Records J before each loop."""
+    v = np.zeros(p.n)
+    x = p.xb.copy()
+    hist = []
+    for k in range(n_outer):
+        lin = linearize(p, x, v)
+        dz = solver(k, lin)
+        hist.append({"J": lin.J, "gnorm": float(np.linalg.norm(lin.g))})
+        v = v + dz
+        x = x + bcov.apply_L(dz, p.taps)
+    hist.append({"J": cost(p, v), "gnorm": float("nan")})
+    return hist

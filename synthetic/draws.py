@@ -1,0 +1,122 @@
+"""Workload parameters and seeded random draws.
+
+Nothing here integrates a model or applies a covariance: the module only
+states sizes and draws numbers. Streams come from
+``numpy.random.SeedSequence(seed).spawn`` in a fixed order so that every
+consumer that asks for the same (seed, stream) pair gets the same numbers:
+
+    stream 0  initial-condition perturbation of the truth spin-up
+    stream 1  observation noise
+    stream 2  background-error draw (multiplied by B^{1/2} by the consumer)
+    stream 3  probe blocks, one child stream per outer loop
+    stream 4  per-problem structure of batched workloads
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, replace
+
+import numpy as np
+
+_N_STREAMS = 6
+
+
+@dataclass(frozen=True)
+class L96Workload:
+    """Sizes of one Lorenz-96 4D-Var inner-loop workload.
+
+    Observation layout: variables i with i % var_stride == 0 (0-based) are
+    observed at steps step_stride, 2*step_stride, ..., nsteps (step 0 is not
+    observed). Observation errors are N(0, obs_sigma^2), R = obs_sigma^2 I.
+    The background covariance is a Gaussian correlation of length ``ell``
+    cells scaled by sigma_b^2.
+    """
+
+    name: str
+    n: int
+    nsteps: int
+    dt: float = 0.05
+    forcing: float = 8.0
+    spinup: int = 1000
+    spinup_sigma: float = 0.1  # std of the N(0, 0.01) initial perturbation
+    var_stride: int = 2
+    step_stride: int = 4
+    obs_sigma: float = 1.0
+    ell: float = 2.0
+    sigma_b: float = 1.0
+    k: int = 20
+    p_os: int = 10
+    q: int = 1
+    outer: int = 3
+
+    @property
+    def m(self) -> int:
+        return self.k + self.p_os
+
+    @property
+    def nobs(self) -> int:
+        nv = (self.n + self.var_stride - 1) // self.var_stride
+        return nv * (self.nsteps // self.step_stride)
+
+
+WORKLOADS = {
+    # Lorenz-96, n=40, window 40 steps, 200 observations, rank 20 + 10, q=1.
+    "l96_n40": L96Workload("l96_n40", n=40, nsteps=40, var_stride=2, step_stride=4,
+                           ell=2.0, k=20, p_os=10, q=1, outer=3),
+    # Lorenz-96, n=4096, window 100 steps, every 4th variable every 5 steps,
+    # length-8 correlation, 256 + 16 probes.
+    "l96_n4096": L96Workload("l96_n4096", n=4096, nsteps=100, var_stride=4,
+                             step_stride=5, ell=8.0, k=256, p_os=16, q=0, outer=1),
+    # Cycled Lorenz-96 window, n=2048, 50 steps, every 2nd variable every 5 steps.
+    "l96_n2048": L96Workload("l96_n2048", n=2048, nsteps=50, var_stride=2,
+                             step_stride=5, ell=8.0, k=112, p_os=16, q=0, outer=1),
+}
+
+
+def workload(name: str, **overrides) -> L96Workload:
+    """Return a named workload, optionally with some fields replaced."""
+    w = WORKLOADS[name]
+    return replace(w, **overrides) if overrides else w
+
+
+def obs_locations(n: int, nsteps: int, var_stride: int, step_stride: int):
+    """Observation (step, variable) pairs, sorted by step then variable."""
+    steps = np.arange(step_stride, nsteps + 1, step_stride, dtype=np.int32)
+    vars_ = np.arange(0, n, var_stride, dtype=np.int32)
+    obs_step = np.repeat(steps, vars_.size).astype(np.int32)
+    obs_idx = np.tile(vars_, steps.size).astype(np.int32)
+    return obs_step, obs_idx
+
+
+def _streams(seed: int):
+    return np.random.SeedSequence(seed).spawn(_N_STREAMS)
+
+
+def l96_draws(w: L96Workload, seed: int) -> dict:
+    """Random draws that define one realisation of a Lorenz-96 workload.
+
+    Returns standard-normal noise arrays; scaling by the workload's sigmas
+    is plain multiplication, done here so every consumer uses identical
+    numbers. The background draw is left unscaled (the consumer multiplies
+    it by its own B^{1/2}).
+    """
+    ss = _streams(seed)
+    g0 = np.random.default_rng(ss[0])
+    g1 = np.random.default_rng(ss[1])
+    g2 = np.random.default_rng(ss[2])
+    obs_step, obs_idx = obs_locations(w.n, w.nsteps, w.var_stride, w.step_stride)
+    return {
+        "x0": w.forcing + w.spinup_sigma * g0.standard_normal(w.n),
+        "obs_noise": w.obs_sigma * g1.standard_normal(obs_step.size),
+        "bg_noise": g2.standard_normal(w.n),
+        "obs_step": obs_step,
+        "obs_idx": obs_idx,
+        "rinv": np.full(obs_step.size, 1.0 / (w.obs_sigma ** 2)),
+    }
+
+
+def probe_block(seed: int, outer: int, n: int, m: int) -> np.ndarray:
+    """Gaussian probe block Omega (n x m, Fortran order) for one outer loop."""
+    ss = _streams(seed)[3].spawn(outer + 1)[outer]
+    g = np.random.default_rng(ss)
+    return np.asfortranarray(g.standard_normal((n, m)))

@@ -1,0 +1,167 @@
+"""Pins of the oracle's inner-loop solvers: exact solve, RSVD, increments, covariance, CG.
+
+Each pin is a mathematical fact independent of the oracle's own code paths:
+primal/dual (Woodbury) equality, exactness at full rank, exactness for exact
+low-rank operators, the Halko et al. range-finder bound, Krylov minimisation
+of CG, and published Philox test vectors.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bcov, fourdvar, philox
+from synthetic import l96_draws, probe_block, workload
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = workload("l96_n40")
+    p, _ = fourdvar.realize_l96(w, l96_draws(w, 0))
+    lin = fourdvar.linearize(p, p.xb)
+    A = fourdvar.dense_A(p, lin)
+    return w, p, lin, A
+
+
+def test_primal_equals_dual(c1):
+    # Woodbury: L (I + A)^{-1} L G^T R^{-1} d = B G^T (G B G^T + R)^{-1} d  (dual form of eq. 3)
+    _, p, lin, A = c1
+    G = fourdvar.obs_jacobian(p, lin)
+    Lm = bcov.dense_L(p.n, p.taps)
+    B = Lm @ Lm.T
+    R = np.diag(1.0 / p.rinv)
+    dual = B @ G.T @ np.linalg.solve(G @ B @ G.T + R, lin.d)
+    ex = fourdvar.exact_solve(p, A, lin.g)
+    assert np.linalg.norm(ex.dx - dual) <= 1e-9 * np.linalg.norm(dual)
+    # and A itself is L^T G^T R^{-1} G L built from the explicit Jacobian
+    A2 = Lm.T @ G.T @ (p.rinv[:, None] * G) @ Lm
+    assert np.linalg.norm(A - A2) <= 1e-11 * np.linalg.norm(A2)
+
+
+def test_rsvd_exact_at_full_rank(c1):
+    _, p, lin, A = c1
+    Om = probe_block(0, 0, p.n, p.n)
+    r = fourdvar.rsvd(lambda W: A @ W, Om, q=0)
+    ex = fourdvar.exact_solve(p, A, lin.g)
+    assert np.allclose(r.lam, ex.lam, rtol=0, atol=1e-9 * ex.lam[0])
+    for mode in ("lra", "lru"):
+        dz, dx, dofs, _ = fourdvar.increment(p, r.lam, r.V, lin.g, mode=mode)
+        assert np.linalg.norm(dz - ex.dz) <= 1e-7 * np.linalg.norm(ex.dz)
+    assert abs(dofs - np.trace(A @ np.linalg.inv(np.eye(p.n) + A))) < 1e-8
+
+
+def test_rsvd_exact_for_exact_low_rank():
+    rng = np.random.default_rng(11)
+    n, r, m = 60, 10, 15
+    U, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    s = np.logspace(3, -1, r)
+    A = (U * s) @ U.T
+    res = fourdvar.rsvd(lambda W: A @ W, rng.standard_normal((n, m)), q=0)
+    assert np.allclose(res.lam[:r], s, rtol=1e-10)
+    assert np.all(np.abs(res.lam[r:]) < 1e-10 * s[0])
+    P = res.V[:, :r] @ res.V[:, :r].T
+    assert np.linalg.norm(P - U @ U.T) < 1e-10
+
+
+def test_range_finder_within_halko_bound():
+    # Halko, Martinsson & Tropp (2011) Thm 10.6: E||(I - QQ^T) A|| <=
+    # (1 + sqrt(k/(p-1))) s_{k+1} + e sqrt(k+p)/p (sum_{j>k} s_j^2)^{1/2}
+    rng = np.random.default_rng(12)
+    n, k, p_os = 80, 10, 5
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = 1.0 / (1.0 + np.arange(n)) ** 1.5
+    A = (U * s) @ U.T
+    bound = (1 + math.sqrt(k / (p_os - 1))) * s[k] + math.e * math.sqrt(k + p_os) / p_os * math.sqrt(np.sum(s[k:] ** 2))
+    errs = []
+    for seed in range(20):
+        res = fourdvar.rsvd(lambda W: A @ W, np.random.default_rng(seed).standard_normal((n, k + p_os)))
+        errs.append(np.linalg.norm(A - res.Q @ (res.Q.T @ A), 2))
+    assert np.median(errs) <= bound
+    assert np.median(errs) >= s[k + p_os] * 0.99  # cannot beat the optimal rank-(k+p) error
+
+
+def test_rsvd_power_iteration_improves(c1):
+    _, p, lin, A = c1
+    ex = fourdvar.exact_solve(p, A, lin.g)
+    Om = probe_block(1, 0, p.n, 30)
+    e = []
+    for q in (0, 1):
+        r = fourdvar.rsvd(lambda W: A @ W, Om, q=q)
+        dz, *_ = fourdvar.increment(p, r.lam, r.V, lin.g)
+        e.append(np.linalg.norm(dz - ex.dz) / np.linalg.norm(ex.dz))
+    assert e[1] < e[0]
+    assert e[1] < 1e-5
+
+
+def test_posterior_cov_exact_at_full_rank(c1):
+    _, p, lin, A = c1
+    ex = fourdvar.exact_solve(p, A, lin.g)
+    _, Px = fourdvar.exact_posterior(p, A)
+    for mode in ("lra", "lru"):
+        W, coef, diag, P, _ = fourdvar.posterior_cov(p, ex.lam, ex.V, mode=mode, dense=True)
+        assert np.linalg.norm(P - Px) <= 1e-9 * np.linalg.norm(Px)
+        assert np.allclose(diag, np.diag(Px), atol=1e-10)
+
+
+def test_lru_better_than_lra_when_truncated_low(c1):
+    # With the last kept eigenvalue below 1 (eq. 11's LRU branch) the full-rank LRU
+    # keeps the prior in unresolved directions and beats LRA's rank-k truncation.
+    _, p, lin, A = c1
+    ex = fourdvar.exact_solve(p, A, lin.g)
+    k = int(np.sum(ex.lam >= 1.0)) + 5
+    e = {}
+    for mode in ("lra", "lru"):
+        dz, *_ = fourdvar.increment(p, ex.lam, ex.V, lin.g, k=k, mode=mode)
+        e[mode] = np.linalg.norm(dz - ex.dz)
+    assert e["lru"] < e["lra"]
+    assert fourdvar.choose_update(1.0) == "lra" and fourdvar.choose_update(0.999) == "lru"
+
+
+def test_cg_iterates_are_krylov_minimisers(c1):
+    _, p, lin, A = c1
+    its = fourdvar.cg(lambda x: x + A @ x, lin.g, 6)
+    for q in (1, 3, 6):
+        kq = fourdvar.krylov_minimizer(lambda x: A @ x, lin.g, q)
+        assert np.linalg.norm(its[:, q - 1] - kq) <= 1e-8 * np.linalg.norm(kq)
+
+
+def test_cg_and_lanczos_reach_exact_solution():
+    # well-conditioned small problem: both Krylov methods terminate at the exact minimiser
+    w = workload("l96_n40", n=16, nsteps=6, var_stride=2, step_stride=2)
+    p, _ = fourdvar.realize_l96(w, l96_draws(w, 3))
+    lin = fourdvar.linearize(p, p.xb)
+    A = fourdvar.dense_A(p, lin)
+    ex = fourdvar.exact_solve(p, A, lin.g)
+    its = fourdvar.cg(lambda x: x + A @ x, lin.g, p.n)
+    assert np.linalg.norm(its[:, -1] - ex.dz) <= 1e-8 * np.linalg.norm(ex.dz)
+    dz, lam, _ = fourdvar.lanczos_varcg(lambda x: A @ x, lin.g, p.n)
+    assert np.linalg.norm(dz - ex.dz) <= 1e-8 * np.linalg.norm(ex.dz)
+
+
+def test_outer_loops_decrease_cost(c1):
+    w, p, _, _ = c1
+    def solver(k, lin):
+        A = fourdvar.dense_A(p, lin)
+        return fourdvar.exact_solve(p, A, lin.g).dz
+    hist = fourdvar.outer_loop(p, 3, solver)
+    J = [h["J"] for h in hist]
+    assert J[1] < J[0] and J[3] <= J[2] * (1 + 1e-9)
+
+
+def test_philox_known_answers():
+    with open(os.path.join(GOLDEN, "philox_kat.txt")) as f:
+        rows = [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        assert philox.philox4x32_10(v[0:4], v[4:6]) == tuple(v[6:10])
+
+
+def test_philox_normals_moments():
+    z = philox.normal_block(200, 50, seed=1234, stream=3)
+    assert z.shape == (200, 50)
+    assert abs(z.mean()) < 0.03 and abs(z.std() - 1.0) < 0.03

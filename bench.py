@@ -1,0 +1,310 @@
+#!/usr/bin/env python
+"""Benchmark of the RIOT inner loop on one MI355X.
+
+One step = one pass of the whole inner loop on the stored synthetic problem:
+linearise (trajectory, innovation, gradient), randomized eigendecomposition of
+the prior-preconditioned Hessian with device-drawn Philox probes (batched
+TL/AD Hessian-probe products, CholeskyQR, K solve, eigen-solve, Ritz
+vectors), adaptive increment and low-rank posterior covariance factors.
+
+Prints one JSON line. `value` is Hessian-vector products per second over the
+whole step (m (1 + q) products per step). The `roofline` object covers the
+dominant kernel, the batched TL/AD integration, timed with HIP events on the
+stream it runs on. The `cpu_baseline` object times the FP64 CPU oracle on a
+bounded sample of the same workload. The `inner_loop` object reports the time
+to reach a relative increment error target, RSVD against plain GPU CG, using
+the stored exact solution of the same problem as the yardstick.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU_TFLOPS = 78.6   # 256 CU x 2.4 GHz x 128 FP64 flop/clk (FMA = 2)
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (k, p_os, q) of the randomized eigendecomposition
+    "l96_n4096": (256, 16, 0),
+    "l96_n40": (20, 10, 1),
+}
+
+
+def tlad_flops_per_column(n: int, T: int, nobs: int) -> float:
+    """Algorithmic FP64 flops of one TL + AD window sweep (FMA = 2 flops).
+
+    Per state element and RK4 step: TL 37 (four Jacobian products at 6, three
+    stage updates at 2, the final combination 7), AD 41 (four transposed
+    Jacobian products at 7, stage and accumulation updates 13); plus one
+    multiply per observation for R^{-1}.
+    """
+    return float(n) * T * (37 + 41) + nobs
+
+
+def hvp_flops(n: int, T: int, nobs: int, w: int) -> float:
+    """Flops of one Hessian-vector product: TL/AD sweep plus L and L^T (3w + 1 each)."""
+    return tlad_flops_per_column(n, T, nobs) + 2.0 * n * (3 * w + 1)
+
+
+def load_problem(name: str, seed: int):
+    path = os.path.join(ROOT, "tests", "golden", f"ref_{name}_s{seed}.npz")
+    if not os.path.exists(path):
+        raise SystemExit(f"missing {path}: run `python tests/golden/make_refs.py {name}`")
+    z = np.load(path, allow_pickle=False)
+    return {k: z[k] for k in z.files}
+
+
+def cpu_baseline(prob: dict, m: int, budget_s: float = 15.0) -> dict:
+    """Time the oracle's Hessian-probe products on a bounded sample of the same problem."""
+    from oracle import fourdvar
+    from synthetic import probe_block
+
+    p = fourdvar.Problem(int(prob["n"]), int(prob["nsteps"]), float(prob["dt"]), float(prob["forcing"]),
+                         prob["obs_step"], prob["obs_idx"], prob["y"], prob["rinv"], prob["xb"],
+                         prob["taps"])
+    lin = fourdvar.linearize(p, p.xb)
+    cols, done, t_used = 8, 0, 0.0
+    while True:
+        W = probe_block(11, done, p.n, cols)
+        t0 = time.perf_counter()
+        fourdvar.hvp(p, lin, W)
+        t_used += time.perf_counter() - t0
+        done += cols
+        if t_used > budget_s or done >= m:
+            break
+    return {"value": done / t_used, "unit": "HVP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} Hessian-probe products (NumPy FP64, one process) on the same "
+                      f"n={p.n}, T={p.nsteps} problem, {t_used:.1f} s",
+            "host_cores_visible": len(os.sched_getaffinity(0))}
+
+
+ACCURACY_SWEEP = {
+    # (m, q) settings tried in order of cost for the RSVD side
+    "l96_n4096": [(272, 0), (272, 1), (544, 0), (544, 1), (1088, 0), (1088, 1)],
+    "l96_n40": [(20, 0), (20, 1), (30, 0), (30, 1), (35, 1), (40, 0)],
+}
+
+
+def time_to_accuracy(r, prob, xb, dev, target=1e-6, trials=3, cg_max=None, reps=5):
+    """Inner-loop seconds to a relative increment error target, RSVD against plain GPU CG.
+
+    Error = ||dx - dx*|| / ||dx*|| against the stored exact minimiser dx* of the
+    same problem (eq. 3). The FP64 floor of that reference (two exact solves
+    disagreeing) bounds what can be certified: the target used is
+    max(target, 10 x floor). Timing starts with the trajectory already resident
+    (the linearisation is included in both legs) and ends with dz resident.
+    """
+    import torch
+    from paper_1906_01413_amd import empty_colmajor
+
+    n, T = r.n, r.nsteps
+    dxs = np.asarray(prob["dx"])
+    floor = float(prob["floor"])
+    tgt = max(target, 10.0 * floor)
+    name = "l96_n4096" if n == 4096 else "l96_n40"
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn, nrep):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(nrep):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b) / 1e3)
+        return float(np.median(ts))
+
+    def err_of(dx):
+        return float(np.linalg.norm(dx.cpu().numpy() - dxs) / np.linalg.norm(dxs))
+
+    d, g, _ = r.linearize(xb, want_cost=False)
+    rs_best = None
+    for (m, q) in ACCURACY_SWEEP[name]:
+        if m > r.m_max or m > n:
+            continue
+        errs = []
+        for s in range(trials):
+            lam, V, _ = r.rsvd(m - min(16, m // 3), min(16, m // 3), q=q, seed=77 + s, want_info=False)
+            _, dx, _, mode = r.increment(lam, V, g)
+            errs.append(err_of(dx))
+        emax = max(errs)
+
+        def run(m=m, q=q):
+            r.linearize(xb, want_cost=False, out=(d, g))
+            lam, V, _ = r.rsvd(m - min(16, m // 3), min(16, m // 3), q=q, seed=77, want_info=False)
+            r.increment(lam, V, g, want_host=False)
+        sec = timed(run, reps)
+        rec = {"m": m, "q": q, "max_err": emax, "seconds": sec, "mode": mode}
+        if rs_best is None or emax < rs_best["max_err"]:
+            rs_best = dict(rec)
+        if emax <= tgt:
+            rs_best = dict(rec)
+            rs_best["reached"] = True
+            break
+    rs_best.setdefault("reached", False)
+
+    # plain CG: find the first iterate within the target, then time that many iterations
+    cg_max = cg_max or (6000 if n >= 1024 else 400)
+    dz, its, used = r.cg(g, cg_max, rtol=0.0, record=True)
+    dxi = r.apply_L(its).cpu().numpy()
+    errs = np.linalg.norm(dxi - dxs[:, None], axis=0) / np.linalg.norm(dxs)
+    hit = np.nonzero(errs <= tgt)[0]
+    nstar = int(hit[0]) + 1 if hit.size else used
+    cg = {"iters": nstar, "err": float(errs[nstar - 1]), "reached": bool(hit.size),
+          "best_err": float(errs.min()), "best_iter": int(np.argmin(errs)) + 1}
+
+    def run_cg(nstar=nstar):
+        r.linearize(xb, want_cost=False, out=(d, g))
+        r.cg(g, nstar, rtol=0.0, record=False)
+    cg["seconds"] = timed(run_cg, max(2, reps // 2))
+    del its, dxi
+    out = {"target": target, "target_used": tgt, "reference_floor": floor,
+           "error": "||dx - dx*|| / ||dx*|| against the oracle's exact minimiser",
+           "rsvd": rs_best, "cg": cg}
+    if rs_best["reached"] and cg["reached"]:
+        out["speedup_rsvd_over_cg"] = cg["seconds"] / rs_best["seconds"]
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="l96_n4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the time-to-accuracy sweep")
+    ap.add_argument("--hvp-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design note, not a measured path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1906_01413_amd import Riot, empty_colmajor
+
+    k, p_os, q = WORKLOADS[args.workload]
+    m = k + p_os
+    prob = load_problem(args.workload, args.seed)
+    n, T = int(prob["n"]), int(prob["nsteps"])
+    nobs = int(prob["obs_step"].size)
+    w = int(prob["taps"].size - 1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prec = 1 if args.prec == "fp32" else 0
+    r = Riot(n, T, float(prob["dt"]), float(prob["forcing"]), prob["obs_step"], prob["obs_idx"],
+             prob["y"], prob["rinv"], prob["taps"], m_max=max(m, 1088 if n >= 1088 else m),
+             prec=prec)
+    xb = torch.tensor(prob["xb"], device=dev)
+    d = torch.empty(max(nobs, 1), dtype=torch.float64, device=dev)
+    g = torch.empty(n, dtype=torch.float64, device=dev)
+    lam = torch.empty(m, dtype=torch.float64, device=dev)
+    V = empty_colmajor(n, m, dev)
+    dz = torch.empty(n, dtype=torch.float64, device=dev)
+    dx = torch.empty(n, dtype=torch.float64, device=dev)
+    Wc = empty_colmajor(n, m, dev)
+    coef = torch.empty(m, dtype=torch.float64, device=dev)
+    diag = torch.empty(n, dtype=torch.float64, device=dev)
+
+    def step(i):
+        r.linearize(xb, want_cost=False, out=(d, g))
+        r.rsvd(k, p_os, q=q, Omega=None, seed=1000 + i, want_info=False, lam=lam, V=V)
+        r.increment(lam, V, g, k=m, want_host=False, dz=dz, dx=dx)
+        r.posterior_cov(lam, V, k=m, want_host=False, out=(Wc, coef, diag))
+
+    print(f"[bench] workload {args.workload} n={n} T={T} m={m} q={q} prec={args.prec}: warmup",
+          file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for i in range(args.steps):
+        step(args.warmup + i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    hvps_per_step = m * (1 + q)
+    value = hvps_per_step / (ms_step / 1e3)
+    print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step (wall {wall:.3f} s)",
+          file=sys.stderr, flush=True)
+
+    # dominant kernel: the batched TL/AD sweep alone (riot_gn_apply is exactly one launch)
+    Xin = empty_colmajor(n, m, dev)
+    Xin.copy_(torch.randn(n, m, dtype=torch.float64, device=dev))
+    Yout = empty_colmajor(n, m, dev)
+    for _ in range(3):
+        r.gn_apply(Xin, out=Yout)
+    torch.cuda.synchronize()
+    h0, h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    h0.record(stream)
+    for _ in range(args.hvp_reps):
+        r.gn_apply(Xin, out=Yout)
+    h1.record(stream)
+    torch.cuda.synchronize()
+    ms_tlad = h0.elapsed_time(h1) / args.hvp_reps
+    flops = tlad_flops_per_column(n, T, nobs) * m
+    achieved = flops / (ms_tlad / 1e3) / 1e12
+    # full Hessian-probe product (L, TL/AD, L^T) for the HVP-only rate
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a0.record(stream)
+    for _ in range(args.hvp_reps):
+        r.hess_apply(Xin, out=Yout)
+    a1.record(stream)
+    torch.cuda.synchronize()
+    ms_hvp = a0.elapsed_time(a1) / args.hvp_reps
+    print(f"[bench] TL/AD kernel {ms_tlad:.3f} ms per {m}-column launch, "
+          f"{achieved:.2f} TFLOP/s; Hessian-probe block {ms_hvp:.3f} ms", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "Hess-vec products/s; inner-loop s to 1e-6 rel. increment err, RSVD vs CG",
+        "value": value,
+        "unit": "HVP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 0 else "f32 TL/AD, f64 linear algebra",
+        "data": "synthetic (seeded Lorenz-96 twin experiment built by the CPU oracle)",
+        "config": {"workload": f"Lorenz-96 n={n}, T={T} RK4 steps dt={float(prob['dt'])}, "
+                               f"{nobs} obs, RSVD m={m} (k={k}+{p_os}), q={q}",
+                   "n": n, "nsteps": T, "nobs": nobs, "m": m, "q": q, "seed": args.seed},
+        "hvp_only": {"value": m / (ms_hvp / 1e3), "unit": "HVP/s",
+                     "ms_per_block": ms_hvp, "flops_per_hvp": hvp_flops(n, T, nobs, w)},
+        "roofline": {"bound": "alu", "kernel": "tlad_kernel (batched TL+AD sweep)",
+                     "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": None,
+                     "ms_per_launch": ms_tlad, "flops_per_launch": flops},
+    }
+
+    if not args.no_accuracy:
+        out["inner_loop"] = time_to_accuracy(r, prob, xb, dev)
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, m)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * riot.h - C ABI of the RIOT inner loop of incremental 4D-Var on MI355X (gfx950).
+ *
+ * Method: Bousserez, Guerrette & Henze, "Enhanced parallelization of the
+ * incremental 4D-Var data assimilation algorithm using the Randomized
+ * Incremental Optimal Technique (RIOT)", arXiv 1906.01413.
+ *
+ * Problem statement (Section 2.1, eqs. 2-3): background x_b, B = L L^T with L
+ * a symmetric circulant (banded half-kernel l_0..l_w on a periodic grid),
+ * observations y of state variables at window steps with diagonal R, forecast
+ * model = Lorenz-96 (Section 3.1.1) integrated with RK4. Control variable dz,
+ * increment dx = L dz. The prior-preconditioned Hessian (minus I) is
+ * A = L^T G^T R^{-1} G L where G stacks the tangent-linear observation
+ * Jacobians of the window (Section 2.2, text after eq. 4).
+ *
+ * Conventions shared by every entry point:
+ *  - Device pointers are caller-owned (for example torch tensors). Matrices are
+ *    column-major with leading dimension n (state-sized) or m (m x m).
+ *  - The caller allocates one device workspace of riot_workspace_bytes() bytes
+ *    and passes it to riot_init; the library allocates no device memory of its
+ *    own and never frees caller memory. riot_free releases host state only.
+ *  - Every call enqueues work on the HIP stream given to riot_init and returns
+ *    once enqueued, except where a host output pointer (J_host, dofs_host,
+ *    info, used, mode_used) is non-NULL: then the call synchronises the stream
+ *    to fill it.
+ *  - Errors are returned as riot_status; nothing aborts and no exception
+ *    crosses the ABI. Argument errors are detected before any work is
+ *    enqueued. Numerical failures detected on the device (breakdown,
+ *    non-finite values) are reported by the calls that synchronise.
+ *  - One handle per stream; a handle is not re-entrant.
+ */
+#ifndef RIOT_H
+#define RIOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct riot_handle riot_handle;
+
+typedef enum {
+    RIOT_OK = 0,
+    RIOT_E_ARG = -1,        /* invalid argument or size */
+    RIOT_E_HIP = -2,        /* a HIP runtime call failed */
+    RIOT_E_NOT_SPD = -3,    /* Cholesky breakdown even after the shifted retry */
+    RIOT_E_SINGULAR = -4,   /* singular projected probe matrix Q^T Omega */
+    RIOT_E_NONFINITE = -5,  /* NaN or Inf in a result */
+    RIOT_E_NOCONV = -6,     /* iteration cap reached (eigen-solver) */
+    RIOT_E_STATE = -7,      /* call order violated (e.g. no linearisation yet) */
+    RIOT_E_WORKSPACE = -8   /* workspace too small or misaligned */
+} riot_status;
+
+typedef enum {
+    RIOT_FP64 = 0,        /* TL/AD in double precision */
+    RIOT_FP32_TLAD = 1    /* TL/AD states in single precision; inputs, outputs and all
+                             linear algebra stay double precision */
+} riot_precision;
+
+typedef enum {
+    RIOT_ADAPTIVE = 0,    /* eq. 11: LRA if the last kept eigenvalue >= 1, else LRU */
+    RIOT_LRA = 1,         /* eq. 9 */
+    RIOT_LRU = 2          /* eq. 8 */
+} riot_update;
+
+/* Problem statement (eqs. 2-3). All pointers are HOST pointers, copied at init. */
+typedef struct {
+    int32_t n;                 /* state dimension, >= 4 */
+    int32_t nsteps;            /* window length T in RK4 steps, >= 0 */
+    double dt;                 /* RK4 step */
+    double forcing;            /* Lorenz-96 forcing F */
+    int32_t nobs;              /* number of observations p, >= 0 */
+    const int32_t *obs_step;   /* [nobs] window step of each observation, 0..nsteps */
+    const int32_t *obs_idx;    /* [nobs] observed state variable, 0..n-1 */
+    const double *y;           /* [nobs] observed values */
+    const double *rinv;        /* [nobs] diagonal of R^{-1}, > 0 */
+    int32_t l_halfwidth;       /* w >= 0: L has taps at offsets -w..w */
+    const double *l_taps;      /* [w+1] half-kernel l_0..l_w of the symmetric circulant L */
+    int32_t m_max;             /* largest probe block used with this handle, >= 1 */
+    riot_precision prec;       /* precision of the TL/AD integrations */
+    int32_t elems_per_lane;    /* 0 = choose automatically, else 1, 2, 4, 8 or 16
+                                  (n must be divisible by it and n / it <= 1024) */
+} riot_desc;
+
+/* Diagnostics of one randomized eigendecomposition (host struct). */
+typedef struct {
+    int32_t chol_shifts;       /* CholeskyQR passes that needed the shifted form */
+    int32_t qr_passes;         /* CholeskyQR passes applied to the final block */
+    double k_asym;             /* ||K - K^T||_F / ||K||_F before symmetrisation */
+    double orth_err;           /* ||Q^T Q - I||_F after the last pass */
+} riot_rsvd_info;
+
+/* Bytes of device workspace needed for this problem (0 if the descriptor is invalid). */
+size_t riot_workspace_bytes(const riot_desc *desc);
+
+/* Create a handle. `workspace` is a device buffer of at least riot_workspace_bytes(desc)
+ * bytes aligned to 256 bytes; it must stay allocated until riot_free. `hip_stream` is a
+ * hipStream_t (NULL = default stream). The observation and covariance data are copied to
+ * the workspace on that stream. */
+riot_status riot_init(const riot_desc *desc, void *workspace, size_t bytes,
+                      void *hip_stream, riot_handle **out);
+
+/* Release host state (the workspace stays the caller's). NULL is accepted. */
+void riot_free(riot_handle *h);
+
+/* Human-readable name of a status code (static string). */
+const char *riot_status_str(riot_status s);
+
+/* Outer-loop linearisation at state x (Alg. 3: integrate and store the trajectory,
+ * innovation; gradient of eq. 3 at dz = 0).
+ *   x    [n]     device, state x_{k-1} to linearise about
+ *   v    [n]     device, accumulated control increment v_{k-1}, or NULL for v = 0
+ *   d    [nobs]  device out, innovation y - H(M(x)) in the descriptor's order (eq. 3 sign)
+ *   grad [n]     device out, g = v - L^T G^T R^{-1} d
+ *   J_host       host out or NULL: 1/2 v^T v + 1/2 d^T R^{-1} d (eq. 2 in control variables)
+ * Stores the RK4 trajectory in the workspace for the calls below. */
+riot_status riot_linearize(riot_handle *h, const double *x, const double *v,
+                           double *d, double *grad, double *J_host);
+
+/* Batched Hessian-probe products (Alg. 3: y_i = A w_i for all probes at once).
+ *   m        number of columns, 1..m_max
+ *   W [n x m] device, probes (column-major, ld n)
+ *   Y [n x m] device out, A W (+ W when add_identity != 0); may not alias W.
+ * Requires riot_linearize first (RIOT_E_STATE otherwise). */
+riot_status riot_hess_apply(riot_handle *h, int32_t m, const double *W, double *Y,
+                            int32_t add_identity);
+
+/* Randomized eigendecomposition of A (Alg. 3 with precond = false).
+ * m = k + p_os probes, 1 <= m <= min(m_max, n). Omega [n x m] device or NULL: NULL draws
+ * N(0,1) probes with Philox4x32-10 keyed by `seed` (stream 0). q >= 0 power steps:
+ * Q0 = orth(Y), Omega_eff = Q0, Y = A Q0 (Halko et al. subspace iteration).
+ * Then Q = orth(Y) by CholeskyQR2 (shifted CholeskyQR3 when the Gram matrix is not
+ * numerically positive definite), K solves K (Q^T Omega_eff) = Q^T Y, K <- (K + K^T)/2,
+ * K = Z diag(lambda) Z^T, V = Q Z.
+ *   lambda [m]     device out, Ritz values in descending order
+ *   V      [n x m] device out, Ritz vectors
+ *   info           host out or NULL (synchronises)
+ * Requires riot_linearize first. */
+riot_status riot_rsvd(riot_handle *h, int32_t k, int32_t p_os, int32_t q,
+                      const double *Omega, uint64_t seed,
+                      double *lambda, double *V, riot_rsvd_info *info);
+
+/* Adaptive increment (eqs. 8-11 used in eq. 10; Alg. 3 update) from the k leading Ritz pairs:
+ *   LRA: dz = -sum_i (1 + l_i)^{-1} v_i v_i^T g
+ *   LRU: dz = -(I - sum_i l_i / (1 + l_i) v_i v_i^T) g
+ *   lambda [>=k] device, V [n x >=k] device, grad [n] device
+ *   dz [n], dx [n] device out (dx = L dz)
+ *   dofs_host  host out or NULL: sum_i l_i / (1 + l_i) (degrees of freedom for signal)
+ *   mode_used  host out or NULL: RIOT_LRA or RIOT_LRU as applied */
+riot_status riot_increment(riot_handle *h, int32_t k, const double *lambda, const double *V,
+                           const double *grad, riot_update mode, double *dz, double *dx,
+                           double *dofs_host, int32_t *mode_used);
+
+/* Low-rank posterior error covariance in state space (eqs. 8-9, L symmetric):
+ *   LRU: P_a = B + W diag(coef) W^T, coef_i = -l_i / (1 + l_i)
+ *   LRA: P_a = W diag(coef) W^T,     coef_i = 1 / (1 + l_i)
+ * with W = L V[:, :k].
+ *   W [n x k] device out; coef [k] device out
+ *   diag  [n] device out or NULL: diagonal of P_a
+ *   dense [n x n] device out or NULL: P_a itself
+ *   mode_used host out or NULL (synchronises when mode is RIOT_ADAPTIVE) */
+riot_status riot_posterior_cov(riot_handle *h, int32_t k, const double *lambda, const double *V,
+                               riot_update mode, double *W, double *coef, double *diag,
+                               double *dense, int32_t *mode_used);
+
+/* Plain conjugate gradients on (I + A) dz = -g from dz = 0 (the iterative baseline of
+ * eq. 4 / Alg. 1), all iterations in one device-resident launch.
+ *   grad [n] device; iters >= 0; stops early once ||r|| <= rtol ||r_0|| (rtol <= 0: never)
+ *   dz [n] device out; iterates [n x iters] device out or NULL (iterate j in column j)
+ *   used host out or NULL: iterations performed (synchronises)
+ * Requires riot_linearize first. */
+riot_status riot_cg(riot_handle *h, const double *grad, int32_t iters, double rtol,
+                    double *dz, double *iterates, int32_t *used);
+
+/* Tangent-linear observation operator of the window (Section 2.1: "only TL and AD model
+ * integrations are necessary"): Z = G X, i.e. column j holds H_t M_{0->t} X[:, j] at every
+ * observation, in the descriptor's observation order.
+ *   X [n x m] device (state space, no L applied), Z [nobs x m] device out (ld nobs).
+ * Requires riot_linearize first. 1 <= m <= m_max. */
+riot_status riot_tl_apply(riot_handle *h, int32_t m, const double *X, double *Z);
+
+/* Adjoint of riot_tl_apply: X = G^T Fo.
+ *   Fo [nobs x m] device (ld nobs), X [n x m] device out. Requires riot_linearize first. */
+riot_status riot_ad_apply(riot_handle *h, int32_t m, const double *Fo, double *X);
+
+/* State-space Gauss-Newton product Y = G^T R^{-1} G X (A = L^T (G^T R^{-1} G) L without the
+ * L factors): one TL and one AD integration per column, all columns in one launch.
+ *   X, Y [n x m] device (may not alias). Requires riot_linearize first. */
+riot_status riot_gn_apply(riot_handle *h, int32_t m, const double *X, double *Y);
+
+/* Nonlinear forecast x(nsteps) from x0 with the handle's model (RK4, dt, F).
+ * Used to build twin experiments and to cycle analyses. x0, xout [n] device. */
+riot_status riot_forecast(riot_handle *h, const double *x0, int32_t nsteps, double *xout);
+
+/* Y = L X for m columns (X, Y [n x m] device; may not alias). */
+riot_status riot_apply_L(riot_handle *h, int32_t m, const double *X, double *Y);
+
+/* Philox4x32-10 standard normals: out [n x m] device, entry e = col*n + row; pair j of
+ * entries (2j, 2j+1) uses counter (j, stream) and key `seed` (Salmon et al. 2011). */
+riot_status riot_philox_normal(riot_handle *h, int32_t n, int32_t m, uint64_t seed,
+                               uint64_t stream, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RIOT_H */

@@ -66,3 +66,40 @@ def normal_block(n: int, m: int, seed: int, stream: int = 0) -> np.ndarray:
     for j in range((total + 1) // 2):
         flat[2 * j], flat[2 * j + 1] = normal_pair(j, seed, stream)
     return flat[:total].reshape((m, n)).T.copy(order="F")
+
+
+def philox4x32_10_vec(c0, c1, c2, c3, k0, k1):
+    """Vectorised philox4x32_10 over uint64 arrays holding 32-bit words (same definition)."""
+    M = np.uint64(_MASK)
+    c0, c1, c2, c3 = (np.asarray(v, dtype=np.uint64) & M for v in (c0, c1, c2, c3))
+    k0 = np.uint64(int(k0) & _MASK)
+    k1 = np.uint64(int(k1) & _MASK)
+    for r in range(10):
+        if r:
+            k0 = (k0 + np.uint64(_W0)) & M
+            k1 = (k1 + np.uint64(_W1)) & M
+        p0 = np.uint64(_M0) * c0
+        p1 = np.uint64(_M1) * c2
+        hi0, lo0 = p0 >> np.uint64(32), p0 & M
+        hi1, lo1 = p1 >> np.uint64(32), p1 & M
+        c0, c1, c2, c3 = (hi1 ^ c1 ^ k0), lo1, (hi0 ^ c3 ^ k1), lo0
+    return c0, c1, c2, c3
+
+
+def normal_columns(n: int, cols, seed: int, stream: int = 0) -> np.ndarray:
+    """Selected columns of the column-major N(0,1) block of normal_block (vectorised)."""
+    cols = np.asarray(cols, dtype=np.int64)
+    e = (cols[None, :] * n + np.arange(n)[:, None]).ravel(order="F")
+    j = (e // 2).astype(np.uint64)
+    x0, x1, x2, x3 = philox4x32_10_vec(j & np.uint64(_MASK), j >> np.uint64(32),
+                                      np.full_like(j, stream & _MASK),
+                                      np.full_like(j, (stream >> 32) & _MASK),
+                                      seed & _MASK, (seed >> 32) & _MASK)
+    u1 = (((x1 << np.uint64(32)) | x0) >> np.uint64(11)).astype(np.float64)
+    u2 = (((x3 << np.uint64(32)) | x2) >> np.uint64(11)).astype(np.float64)
+    u1 = (u1 + 0.5) * 2.0 ** -53
+    u2 = (u2 + 0.5) * 2.0 ** -53
+    r = np.sqrt(-2.0 * np.log(u1))
+    t = 2.0 * np.pi * u2
+    z = np.where(e % 2 == 0, r * np.cos(t), r * np.sin(t))
+    return z.reshape((n, cols.size), order="F")

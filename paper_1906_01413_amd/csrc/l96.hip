@@ -1,0 +1,818 @@
+// Lorenz-96 nonlinear, tangent-linear and adjoint integrations for gfx950.
+//
+// Model: Section 3.1.1 (Lorenz-96, periodic), integrated with classical RK4.
+// Hessian-probe product (Alg. 3, y_i = A w_i with A = L^T G^T R^{-1} G L):
+// one TL sweep over the window collecting R^{-1}-weighted observation values,
+// one AD sweep injecting them at the observed steps. Each member (probe) runs
+// in one workgroup with its state in registers; the periodic halo is exchanged
+// through LDS once per RK4 stage.
+
+#include "riot_internal.h"
+
+namespace riot {
+namespace {
+
+constexpr int kLdsSlots = 4;
+
+__device__ __forceinline__ int slot_of(int jj, int E) {
+  if (jj == 0) return 0;
+  if (jj == 1) return 1;
+  if (jj == E - 2) return 2;
+  return 3;
+}
+
+// LDS offsets of the four neighbours a-2, a-1, a+E, a+E+1 of thread l.
+template <int E>
+struct HaloMap {
+  int off[4];
+  __device__ void init(int l, int n, int NT) {
+    const int a = l * E;
+    const int g[4] = {a - 2, a - 1, a + E, a + E + 1};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int gg = g[k] % n;
+      if (gg < 0) gg += n;
+      off[k] = slot_of(gg % E, E) * NT + gg / E;
+    }
+  }
+};
+
+// Write this thread's boundary values, barrier, read the neighbours'.
+// All threads of the block must call it (inactive ones pass active=false).
+template <typename Real, int E>
+__device__ __forceinline__ void exchange(Real *lds, int &parity, int NT, int l, bool active,
+                                         const HaloMap<E> &hm, const Real (&v)[E], Real &hl2,
+                                         Real &hl1, Real &hr1, Real &hr2) {
+  Real *b = lds + parity * kLdsSlots * NT;
+  if (active) {
+    b[0 * NT + l] = v[0];
+    b[1 * NT + l] = v[E > 1 ? 1 : 0];
+    b[2 * NT + l] = v[E > 1 ? E - 2 : 0];
+    b[3 * NT + l] = v[E - 1];
+  }
+  __syncthreads();
+  if (active) {
+    hl2 = b[hm.off[0]];
+    hl1 = b[hm.off[1]];
+    hr1 = b[hm.off[2]];
+    hr2 = b[hm.off[3]];
+  }
+  parity ^= 1;
+}
+
+// Load the (E + 4)-value extended base state xe[k] = x[a - 2 + k] of one stage block.
+template <typename Real, int E>
+__device__ __forceinline__ void load_base(const Real *__restrict__ blk, int NT, int l,
+                                          Real (&xe)[E + 4]) {
+#pragma unroll
+  for (int j = 0; j < E; ++j) xe[2 + j] = blk[j * NT + l];
+  xe[0] = blk[(E + 0) * NT + l];
+  xe[1] = blk[(E + 1) * NT + l];
+  xe[E + 2] = blk[(E + 2) * NT + l];
+  xe[E + 3] = blk[(E + 3) * NT + l];
+}
+
+// d = J(x) e : (J e)_i = (e_{i+1} - e_{i-2}) x_{i-1} + (x_{i+1} - x_{i-2}) e_{i-1} - e_i
+template <typename Real, int E>
+__device__ __forceinline__ void tl_jac(const Real (&xe)[E + 4], const Real (&e)[E], Real hl2,
+                                       Real hl1, Real hr1, Real (&d)[E]) {
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const Real em2 = (j >= 2) ? e[j - 2] : (j == 0 ? hl2 : hl1);
+    const Real em1 = (j >= 1) ? e[j - 1] : hl1;
+    const Real ep1 = (j + 1 < E) ? e[j + 1] : hr1;
+    d[j] = (ep1 - em2) * xe[j + 1] + (xe[j + 3] - xe[j]) * em1 - e[j];
+  }
+}
+
+// s = J(x)^T w : (J^T w)_i = x_{i-2} w_{i-1} - x_{i+1} w_{i+2} + (x_{i+2} - x_{i-1}) w_{i+1} - w_i
+template <typename Real, int E>
+__device__ __forceinline__ void ad_jac(const Real (&xe)[E + 4], const Real (&w)[E], Real hl1,
+                                       Real hr1, Real hr2, Real (&s)[E]) {
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const Real wm1 = (j >= 1) ? w[j - 1] : hl1;
+    const Real wp1 = (j + 1 < E) ? w[j + 1] : hr1;
+    const Real wp2 = (j + 2 < E) ? w[j + 2] : (j + 2 == E ? hr1 : hr2);
+    s[j] = xe[j] * wm1 - xe[j + 3] * wp2 + (xe[j + 4] - xe[j + 1]) * wp1 - w[j];
+  }
+}
+
+// Nonlinear tendency on the extended state: f_i = (x_{i+1} - x_{i-2}) x_{i-1} - x_i + F
+template <int E>
+__device__ __forceinline__ void tendency(const double (&xe)[E + 4], double F, double (&f)[E]) {
+#pragma unroll
+  for (int j = 0; j < E; ++j) f[j] = (xe[j + 3] - xe[j]) * xe[j + 1] - xe[j + 2] + F;
+}
+
+template <typename Real>
+__device__ __forceinline__ const Real *stage_block(const ModelView &mv, int t, int s) {
+  return reinterpret_cast<const Real *>(mv.xs) +
+         (size_t)(t * 4 + s) * (size_t)(mv.E + 4) * (size_t)mv.NT;
+}
+
+// ---------------------------------------------------------------------------
+// Nonlinear trajectory (one workgroup).
+// ---------------------------------------------------------------------------
+
+template <int E>
+__device__ void store_block(double *xs64, float *xs32, int t, int s, int E_, int NT, int l,
+                            const double (&v)[E], double hl2, double hl1, double hr1, double hr2) {
+  const size_t base = (size_t)(t * 4 + s) * (size_t)(E_ + 4) * NT;
+  double *b = xs64 + base;
+#pragma unroll
+  for (int j = 0; j < E; ++j) b[j * NT + l] = v[j];
+  b[(E + 0) * NT + l] = hl2;
+  b[(E + 1) * NT + l] = hl1;
+  b[(E + 2) * NT + l] = hr1;
+  b[(E + 3) * NT + l] = hr2;
+  if (xs32) {
+    float *c = xs32 + base;
+#pragma unroll
+    for (int j = 0; j < E; ++j) c[j * NT + l] = (float)v[j];
+    c[(E + 0) * NT + l] = (float)hl2;
+    c[(E + 1) * NT + l] = (float)hl1;
+    c[(E + 2) * NT + l] = (float)hr1;
+    c[(E + 3) * NT + l] = (float)hr2;
+  }
+}
+
+template <int E>
+__global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
+    trajectory_kernel(ModelView mv, int nsteps, const double *__restrict__ x0,
+                      double *__restrict__ xout, double *__restrict__ xs64,
+                      float *__restrict__ xs32) {
+  extern __shared__ double lds_d[];
+  const int l = threadIdx.x;
+  const int NT = mv.NT;
+  const bool active = l < mv.A;
+  const int a = l * E;
+  HaloMap<E> hm;
+  if (active) hm.init(l, mv.n, NT);
+  int parity = 0;
+  const double h = mv.h, F = mv.F;
+  double x[E], xs[E], acc[E], k[E], xe[E + 4];
+  double hl2 = 0, hl1 = 0, hr1 = 0, hr2 = 0;
+#pragma unroll
+  for (int j = 0; j < E; ++j) x[j] = active ? x0[a + j] : 0.0;
+
+  auto build = [&](const double (&v)[E]) {
+    xe[0] = hl2;
+    xe[1] = hl1;
+#pragma unroll
+    for (int j = 0; j < E; ++j) xe[2 + j] = v[j];
+    xe[E + 2] = hr1;
+    xe[E + 3] = hr2;
+  };
+
+  for (int t = 0; t < nsteps; ++t) {
+    // stage 1
+    exchange<double, E>(lds_d, parity, NT, l, active, hm, x, hl2, hl1, hr1, hr2);
+    if (active) {
+      build(x);
+      if (xs64) store_block<E>(xs64, xs32, t, 0, E, NT, l, x, hl2, hl1, hr1, hr2);
+      tendency<E>(xe, F, k);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        acc[j] = k[j];
+        xs[j] = x[j] + (0.5 * h) * k[j];
+      }
+    }
+    // stage 2
+    exchange<double, E>(lds_d, parity, NT, l, active, hm, xs, hl2, hl1, hr1, hr2);
+    if (active) {
+      build(xs);
+      if (xs64) store_block<E>(xs64, xs32, t, 1, E, NT, l, xs, hl2, hl1, hr1, hr2);
+      tendency<E>(xe, F, k);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        acc[j] += 2.0 * k[j];
+        xs[j] = x[j] + (0.5 * h) * k[j];
+      }
+    }
+    // stage 3
+    exchange<double, E>(lds_d, parity, NT, l, active, hm, xs, hl2, hl1, hr1, hr2);
+    if (active) {
+      build(xs);
+      if (xs64) store_block<E>(xs64, xs32, t, 2, E, NT, l, xs, hl2, hl1, hr1, hr2);
+      tendency<E>(xe, F, k);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        acc[j] += 2.0 * k[j];
+        xs[j] = x[j] + h * k[j];
+      }
+    }
+    // stage 4
+    exchange<double, E>(lds_d, parity, NT, l, active, hm, xs, hl2, hl1, hr1, hr2);
+    if (active) {
+      build(xs);
+      if (xs64) store_block<E>(xs64, xs32, t, 3, E, NT, l, xs, hl2, hl1, hr1, hr2);
+      tendency<E>(xe, F, k);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        acc[j] += k[j];
+        x[j] = x[j] + (h / 6.0) * acc[j];
+      }
+    }
+  }
+  if (xs64) {
+    exchange<double, E>(lds_d, parity, NT, l, active, hm, x, hl2, hl1, hr1, hr2);
+    if (active) store_block<E>(xs64, xs32, nsteps, 0, E, NT, l, x, hl2, hl1, hr1, hr2);
+  }
+  if (xout && active) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) xout[a + j] = x[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Member TL/AD sweep (device function shared by the batched kernel and CG).
+// ---------------------------------------------------------------------------
+
+template <typename Real, int E>
+struct Member {
+  const ModelView &mv;
+  Real *lds;
+  int l, NT;
+  bool active;
+  HaloMap<E> hm;
+  int parity;
+
+  __device__ Member(const ModelView &m, Real *lds_, int l_)
+      : mv(m), lds(lds_), l(l_), NT(m.NT), active(l_ < m.A), parity(0) {
+    if (active) hm.init(l, mv.n, NT);
+  }
+
+  // TL of one observed step: f[u] = wgt[u] * dx_i (weighted) or dx_i for observed elements.
+  __device__ __forceinline__ void tl_store(int k, const Real (&dl)[E], Real *__restrict__ f,
+                                           bool weighted) {
+    const int us = mv.ustart[k * NT + l];
+    const unsigned mask = (unsigned)mv.umask[k * NT + l];
+    const Real *wgt = reinterpret_cast<const Real *>(mv.wgt);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      if ((mask >> j) & 1u) {
+        const int u = us + __popc(mask & ((1u << j) - 1u));
+        f[u] = weighted ? wgt[u] * dl[j] : dl[j];
+      }
+    }
+  }
+
+  __device__ __forceinline__ void ad_inject(int k, Real (&lam)[E], const Real *__restrict__ f) {
+    const int us = mv.ustart[k * NT + l];
+    const unsigned mask = (unsigned)mv.umask[k * NT + l];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      if ((mask >> j) & 1u) {
+        const int u = us + __popc(mask & ((1u << j) - 1u));
+        lam[j] += f[u];
+      }
+    }
+  }
+
+  // Tangent-linear sweep from dl (in registers) over the whole window, storing forcing.
+  __device__ void tl_sweep(Real (&dl)[E], Real *__restrict__ f, bool weighted) {
+    const Real h = (Real)mv.h;
+    const Real h2 = (Real)(0.5 * mv.h);
+    const Real h6 = (Real)(mv.h / 6.0);
+    Real xe[E + 4], e[E], d[E], acc[E];
+    Real hl2 = 0, hl1 = 0, hr1 = 0, hr2 = 0;
+    for (int t = 0; t <= mv.T; ++t) {
+      const int k = mv.stepk[t];
+      if (k >= 0 && active) tl_store(k, dl, f, weighted);
+      if (t == mv.T) break;
+      // stage 1
+      exchange<Real, E>(lds, parity, NT, l, active, hm, dl, hl2, hl1, hr1, hr2);
+      if (active) {
+        load_base<Real, E>(stage_block<Real>(mv, t, 0), NT, l, xe);
+        tl_jac<Real, E>(xe, dl, hl2, hl1, hr1, d);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          acc[j] = d[j];
+          e[j] = dl[j] + h2 * d[j];
+        }
+      }
+      // stage 2
+      exchange<Real, E>(lds, parity, NT, l, active, hm, e, hl2, hl1, hr1, hr2);
+      if (active) {
+        load_base<Real, E>(stage_block<Real>(mv, t, 1), NT, l, xe);
+        tl_jac<Real, E>(xe, e, hl2, hl1, hr1, d);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          acc[j] += (Real)2 * d[j];
+          e[j] = dl[j] + h2 * d[j];
+        }
+      }
+      // stage 3
+      exchange<Real, E>(lds, parity, NT, l, active, hm, e, hl2, hl1, hr1, hr2);
+      if (active) {
+        load_base<Real, E>(stage_block<Real>(mv, t, 2), NT, l, xe);
+        tl_jac<Real, E>(xe, e, hl2, hl1, hr1, d);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          acc[j] += (Real)2 * d[j];
+          e[j] = dl[j] + h * d[j];
+        }
+      }
+      // stage 4
+      exchange<Real, E>(lds, parity, NT, l, active, hm, e, hl2, hl1, hr1, hr2);
+      if (active) {
+        load_base<Real, E>(stage_block<Real>(mv, t, 3), NT, l, xe);
+        tl_jac<Real, E>(xe, e, hl2, hl1, hr1, d);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          acc[j] += d[j];
+          dl[j] = dl[j] + h6 * acc[j];
+        }
+      }
+    }
+  }
+
+  // Adjoint sweep over the whole window with forcing f injected at observed steps.
+  __device__ void ad_sweep(Real (&lam)[E], const Real *__restrict__ f) {
+    const Real h = (Real)mv.h;
+    const Real h2 = (Real)(0.5 * mv.h);
+    const Real h3 = (Real)(mv.h / 3.0);
+    const Real h6 = (Real)(mv.h / 6.0);
+    Real xe[E + 4], lp[E], a[E], s[E];
+    Real hl2 = 0, hl1 = 0, hr1 = 0, hr2 = 0;
+#pragma unroll
+    for (int j = 0; j < E; ++j) lam[j] = 0;
+    for (int t = mv.T; t >= 0; --t) {
+      const int k = mv.stepk[t];
+      if (k >= 0 && active) ad_inject(k, lam, f);
+      if (t == 0) break;
+      const int ts = t - 1;
+      // adjoint of stage 4 input
+      if (active) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          lp[j] = lam[j];
+          a[j] = h6 * lp[j];
+        }
+      }
+      exchange<Real, E>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
+      if (active) {
+        load_base<Real, E>(stage_block<Real>(mv, ts, 3), NT, l, xe);
+        ad_jac<Real, E>(xe, a, hl1, hr1, hr2, s);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          lam[j] = lp[j] + s[j];
+          a[j] = h3 * lp[j] + h * s[j];
+        }
+      }
+      // stage 3
+      exchange<Real, E>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
+      if (active) {
+        load_base<Real, E>(stage_block<Real>(mv, ts, 2), NT, l, xe);
+        ad_jac<Real, E>(xe, a, hl1, hr1, hr2, s);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          lam[j] += s[j];
+          a[j] = h3 * lp[j] + h2 * s[j];
+        }
+      }
+      // stage 2
+      exchange<Real, E>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
+      if (active) {
+        load_base<Real, E>(stage_block<Real>(mv, ts, 1), NT, l, xe);
+        ad_jac<Real, E>(xe, a, hl1, hr1, hr2, s);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          lam[j] += s[j];
+          a[j] = h6 * lp[j] + h2 * s[j];
+        }
+      }
+      // stage 1
+      exchange<Real, E>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
+      if (active) {
+        load_base<Real, E>(stage_block<Real>(mv, ts, 0), NT, l, xe);
+        ad_jac<Real, E>(xe, a, hl1, hr1, hr2, s);
+#pragma unroll
+        for (int j = 0; j < E; ++j) lam[j] += s[j];
+      }
+    }
+  }
+
+  // One member. mode 0: TL (R^{-1}-weighted store) then AD -> lam0; mode 1: AD forced by
+  // the shared fsrc -> lam0; mode 2: TL only, raw observed values into f; mode 3: AD forced
+  // by this member's own f -> lam0. dx0 and lam0 use the natural layout (double).
+  __device__ void run(int mode, const double *__restrict__ dx0, double *__restrict__ lam0,
+                      Real *__restrict__ f, const Real *__restrict__ fsrc) {
+    const int a = l * E;
+    Real v[E];
+    if (mode == 0 || mode == 2) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = active ? (Real)dx0[a + j] : (Real)0;
+      tl_sweep(v, f, mode == 0);
+      if (mode == 2) return;
+      // each forcing value is re-read by the thread that stored it; the barrier only
+      // separates the two sweeps' LDS traffic
+      __syncthreads();
+      ad_sweep(v, f);
+    } else {
+      ad_sweep(v, mode == 1 ? fsrc : f);
+    }
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) lam0[a + j] = (double)v[j];
+    }
+  }
+};
+
+template <typename Real, int E>
+__global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
+    tlad_kernel(ModelView mv, int mode, const double *__restrict__ dx0, double *__restrict__ lam0,
+                Real *__restrict__ f, const Real *__restrict__ fsrc) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  Real *lds = reinterpret_cast<Real *>(lds_raw);
+  const int mem = blockIdx.x;
+  Member<Real, E> M(mv, lds, threadIdx.x);
+  M.run(mode, dx0 + (size_t)mem * mv.n, lam0 + (size_t)mem * mv.n,
+        f + (size_t)mem * (size_t)mv.U, fsrc);
+}
+
+// ---------------------------------------------------------------------------
+// Innovation, gradient forcing and cost.
+// ---------------------------------------------------------------------------
+
+template <typename Real>
+__global__ void innovation_kernel(ModelView mv, const double *__restrict__ xs64, int U,
+                                  const int *__restrict__ obs_step, const int *__restrict__ obs_idx,
+                                  const double *__restrict__ y, const double *__restrict__ rinv,
+                                  const int *__restrict__ u_optr, const int *__restrict__ u_olist,
+                                  double *__restrict__ d, Real *__restrict__ fgrad) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= U) return;
+  double acc = 0.0;
+  for (int q = u_optr[u]; q < u_optr[u + 1]; ++q) {
+    const int o = u_olist[q];
+    const int t = obs_step[o];
+    const int i = obs_idx[o];
+    const int l = i / mv.E, j = i - l * mv.E;
+    const double xv = xs64[(size_t)(t * 4) * (size_t)(mv.E + 4) * mv.NT + (size_t)j * mv.NT + l];
+    const double dv = y[o] - xv;
+    d[o] = dv;
+    acc += rinv[o] * dv;
+  }
+  fgrad[u] = (Real)acc;
+}
+
+// Z[o, j] = f_j[u(o)] : raw TL values back in the caller's observation order.
+template <typename Real>
+__global__ void obs_gather_kernel(int nobs, int U, int m, const int *__restrict__ u_of_o,
+                                  const Real *__restrict__ f, double *__restrict__ Z) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)nobs * m) return;
+  const int o = (int)(idx % nobs), j = (int)(idx / nobs);
+  Z[idx] = (double)f[(size_t)j * U + u_of_o[o]];
+}
+
+// f_j[u] = sum_{o in u} F[o, j] : observation-space forcing folded onto unique pairs.
+template <typename Real>
+__global__ void obs_scatter_kernel(int nobs, int U, int m, const int *__restrict__ u_optr,
+                                   const int *__restrict__ u_olist, const double *__restrict__ Fo,
+                                   Real *__restrict__ f) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)U * m) return;
+  const int u = (int)(idx % U), j = (int)(idx / U);
+  double s = 0.0;
+  for (int q = u_optr[u]; q < u_optr[u + 1]; ++q) s += Fo[(size_t)j * nobs + u_olist[q]];
+  f[idx] = (Real)s;
+}
+
+__device__ double block_sum(double v, double *red) {
+  // wave reduction then cross-wave through LDS, fixed order
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int k = 0; k < nw; ++k) s += red[k];
+  __syncthreads();
+  return s;
+}
+
+__global__ void __launch_bounds__(1024)
+    cost_kernel(int n, const double *__restrict__ v, int nobs, const double *__restrict__ d,
+                const double *__restrict__ rinv, double *__restrict__ out) {
+  __shared__ double red[16];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    if (v) a += v[i] * v[i];
+  for (int o = threadIdx.x; o < nobs; o += blockDim.x) b += rinv[o] * d[o] * d[o];
+  const double sa = block_sum(a, red);
+  const double sb = block_sum(b, red);
+  if (threadIdx.x == 0) out[0] = 0.5 * sa + 0.5 * sb;
+}
+
+// ---------------------------------------------------------------------------
+// L (symmetric circulant, half-kernel taps) applied to columns.
+// ---------------------------------------------------------------------------
+
+// Workgroup-cooperative L x for one column; ext must hold n + 2w doubles of LDS
+// (or be nullptr to read x from global memory with modular indexing).
+__device__ void apply_L_column(int n, int w, const double *__restrict__ taps,
+                               const double *__restrict__ x, double *__restrict__ y,
+                               const double *__restrict__ z, int mode, double *ext) {
+  if (ext) {
+    for (int k = threadIdx.x; k < n + 2 * w; k += blockDim.x) {
+      int src = (k - w) % n;
+      if (src < 0) src += n;
+      ext[k] = x[src];
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double acc;
+    if (ext) {
+      acc = taps[0] * ext[i + w];
+      for (int dd = 1; dd <= w; ++dd) acc += taps[dd] * (ext[i + w + dd] + ext[i + w - dd]);
+    } else {
+      acc = taps[0] * x[i];
+      for (int dd = 1; dd <= w; ++dd) {
+        int ip = (i + dd) % n;
+        int im = (i - dd) % n;
+        if (im < 0) im += n;
+        acc += taps[dd] * (x[ip] + x[im]);
+      }
+    }
+    if (mode == 1)
+      acc += z[i];
+    else if (mode == 2)
+      acc = (z ? z[i] : 0.0) - acc;
+    y[i] = acc;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256)
+    apply_L_kernel(int n, int w, const double *__restrict__ taps, const double *__restrict__ X,
+                   double *__restrict__ Y, const double *__restrict__ Z, int mode, int use_lds) {
+  extern __shared__ double ext[];
+  const size_t c = blockIdx.x;
+  apply_L_column(n, w, taps, X + c * n, Y + c * n, Z ? Z + c * n : nullptr, mode,
+                 use_lds ? ext : nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Conjugate gradients: one workgroup, all iterations in one launch.
+// ---------------------------------------------------------------------------
+
+template <typename Real, int E>
+__global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
+    cg_kernel(ModelView mv, int w, const double *__restrict__ taps, const double *__restrict__ g,
+              int iters, double rtol, double *__restrict__ x, double *__restrict__ iterates,
+              double *__restrict__ vs, Real *__restrict__ f, int *__restrict__ used,
+              int ext_off_bytes, int use_lds_ext) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ double red[16];
+  Real *lds = reinterpret_cast<Real *>(lds_raw);
+  double *ext = use_lds_ext ? reinterpret_cast<double *>(lds_raw + ext_off_bytes) : nullptr;
+  const int n = mv.n;
+  double *r = vs, *p = vs + n, *q = vs + 2 * n, *tmp = vs + 3 * n, *lam = vs + 4 * n;
+  Member<Real, E> M(mv, lds, threadIdx.x);
+
+  double rr_part = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double ri = -g[i];
+    x[i] = 0.0;
+    r[i] = ri;
+    p[i] = ri;
+    rr_part += ri * ri;
+  }
+  double rr = block_sum(rr_part, red);
+  const double r0 = sqrt(rr);
+  int it = 0;
+  for (; it < iters; ++it) {
+    // q = (I + A) p = p + L^T G^T R^{-1} G L p
+    apply_L_column(n, w, taps, p, tmp, nullptr, 0, ext);
+    M.run(0, tmp, lam, f, nullptr);
+    __syncthreads();
+    apply_L_column(n, w, taps, lam, q, p, 1, ext);
+    double pq_part = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) pq_part += p[i] * q[i];
+    const double pq = block_sum(pq_part, red);
+    const double alpha = rr / pq;
+    double rn_part = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      x[i] += alpha * p[i];
+      const double ri = r[i] - alpha * q[i];
+      r[i] = ri;
+      rn_part += ri * ri;
+      if (iterates) iterates[(size_t)it * n + i] = x[i];
+    }
+    const double rr_new = block_sum(rn_part, red);
+    if (rtol > 0.0 && sqrt(rr_new) <= rtol * r0) {
+      ++it;
+      break;
+    }
+    const double beta = rr_new / rr;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = r[i] + beta * p[i];
+    rr = rr_new;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) used[0] = it;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC 2011) and Box-Muller normals.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t p0 = (uint64_t)M0 * c[0];
+    const uint64_t p1 = (uint64_t)M1 * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__global__ void philox_normal_kernel(long long total, uint64_t seed, uint64_t stream,
+                                     double *__restrict__ out) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long pairs = (total + 1) / 2;
+  if (j >= pairs) return;
+  uint32_t c[4] = {(uint32_t)j, (uint32_t)((unsigned long long)j >> 32), (uint32_t)stream,
+                   (uint32_t)(stream >> 32)};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint64_t v1 = (((uint64_t)c[1] << 32) | c[0]) >> 11;
+  const uint64_t v2 = (((uint64_t)c[3] << 32) | c[2]) >> 11;
+  const double u1 = ((double)v1 + 0.5) * 0x1.0p-53;
+  const double u2 = ((double)v2 + 0.5) * 0x1.0p-53;
+  const double r = sqrt(-2.0 * log(u1));
+  const double th = 2.0 * 3.14159265358979323846 * u2;
+  out[2 * j] = r * cos(th);
+  if (2 * j + 1 < total) out[2 * j + 1] = r * sin(th);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+#define RIOT_DISPATCH_E(E_, CALL) \
+  switch (E_) {                   \
+    case 1: {                     \
+      constexpr int EE = 1;       \
+      CALL;                       \
+    } break;                      \
+    case 2: {                     \
+      constexpr int EE = 2;       \
+      CALL;                       \
+    } break;                      \
+    case 4: {                     \
+      constexpr int EE = 4;       \
+      CALL;                       \
+    } break;                      \
+    case 8: {                     \
+      constexpr int EE = 8;       \
+      CALL;                       \
+    } break;                      \
+    case 16: {                    \
+      constexpr int EE = 16;      \
+      CALL;                       \
+    } break;                      \
+    default:                      \
+      return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_trajectory(const ModelView &mv, int nsteps, const double *x0, double *xout,
+                             double *xs64, float *xs32, hipStream_t st) {
+  const size_t lds = (size_t)kLdsSlots * 2 * mv.NT * sizeof(double);
+  RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL(trajectory_kernel<EE>, dim3(1), dim3(mv.NT), lds, st,
+                                           mv, nsteps, x0, xout, xs64, xs32));
+  return hipGetLastError();
+}
+
+hipError_t launch_innovation(const ModelView &mv, const double *xs64, int nobs, const int *obs_step,
+                             const int *obs_idx, const double *y, const double *rinv,
+                             const int *u_optr, const int *u_olist, double *d, void *fgrad,
+                             bool fp32, hipStream_t st) {
+  (void)nobs;
+  if (mv.U == 0) return hipSuccess;
+  const int bs = 256;
+  const int grid = (mv.U + bs - 1) / bs;
+  if (fp32)
+    hipLaunchKernelGGL(innovation_kernel<float>, dim3(grid), dim3(bs), 0, st, mv, xs64, mv.U,
+                       obs_step, obs_idx, y, rinv, u_optr, u_olist, d,
+                       reinterpret_cast<float *>(fgrad));
+  else
+    hipLaunchKernelGGL(innovation_kernel<double>, dim3(grid), dim3(bs), 0, st, mv, xs64, mv.U,
+                       obs_step, obs_idx, y, rinv, u_optr, u_olist, d,
+                       reinterpret_cast<double *>(fgrad));
+  return hipGetLastError();
+}
+
+hipError_t launch_cost(int n, const double *v, int nobs, const double *d, const double *rinv,
+                       double *out, hipStream_t st) {
+  hipLaunchKernelGGL(cost_kernel, dim3(1), dim3(1024), 0, st, n, v, nobs, d, rinv, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_tlad(const ModelView &mv, int m, int mode, const double *dx0, double *lam0,
+                       void *f, const void *fsrc, bool fp32, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  if (fp32) {
+    const size_t lds = (size_t)kLdsSlots * 2 * mv.NT * sizeof(float);
+    RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((tlad_kernel<float, EE>), dim3(m), dim3(mv.NT), lds,
+                                             st, mv, mode, dx0, lam0,
+                                             reinterpret_cast<float *>(f),
+                                             reinterpret_cast<const float *>(fsrc)));
+  } else {
+    const size_t lds = (size_t)kLdsSlots * 2 * mv.NT * sizeof(double);
+    RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((tlad_kernel<double, EE>), dim3(m), dim3(mv.NT), lds,
+                                             st, mv, mode, dx0, lam0,
+                                             reinterpret_cast<double *>(f),
+                                             reinterpret_cast<const double *>(fsrc)));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_obs_gather(int nobs, int U, int m, const int *u_of_o, const void *f, double *Z,
+                             bool fp32, hipStream_t st) {
+  const size_t tot = (size_t)nobs * m;
+  if (tot == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((tot + 255) / 256);
+  if (fp32)
+    hipLaunchKernelGGL(obs_gather_kernel<float>, dim3(grid), dim3(256), 0, st, nobs, U, m, u_of_o,
+                       reinterpret_cast<const float *>(f), Z);
+  else
+    hipLaunchKernelGGL(obs_gather_kernel<double>, dim3(grid), dim3(256), 0, st, nobs, U, m, u_of_o,
+                       reinterpret_cast<const double *>(f), Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_obs_scatter(int nobs, int U, int m, const int *u_optr, const int *u_olist,
+                              const double *Fo, void *f, bool fp32, hipStream_t st) {
+  const size_t tot = (size_t)U * m;
+  if (tot == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((tot + 255) / 256);
+  if (fp32)
+    hipLaunchKernelGGL(obs_scatter_kernel<float>, dim3(grid), dim3(256), 0, st, nobs, U, m, u_optr,
+                       u_olist, Fo, reinterpret_cast<float *>(f));
+  else
+    hipLaunchKernelGGL(obs_scatter_kernel<double>, dim3(grid), dim3(256), 0, st, nobs, U, m, u_optr,
+                       u_olist, Fo, reinterpret_cast<double *>(f));
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_L(int n, int w, const double *taps, int m, const double *X, double *Y,
+                          const double *Z, int mode, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  const size_t lds = (size_t)(n + 2 * w) * sizeof(double);
+  const int use_lds = lds <= 60 * 1024 ? 1 : 0;
+  hipLaunchKernelGGL(apply_L_kernel, dim3(m), dim3(256), use_lds ? lds : 0, st, n, w, taps, X, Y,
+                     Z, mode, use_lds);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg(const ModelView &mv, int w, const double *taps, const double *g, int iters,
+                     double rtol, double *x, double *iterates, double *vec_scratch, void *f,
+                     int *used, bool fp32, hipStream_t st) {
+  const size_t xb = (size_t)kLdsSlots * 2 * mv.NT * (fp32 ? sizeof(float) : sizeof(double));
+  const size_t ext_off = (xb + 255) / 256 * 256;
+  const size_t ext_bytes = (size_t)(mv.n + 2 * w) * sizeof(double);
+  const int use_ext = (ext_off + ext_bytes) <= 60 * 1024 ? 1 : 0;
+  const size_t lds = use_ext ? ext_off + ext_bytes : xb;
+  if (fp32) {
+    RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((cg_kernel<float, EE>), dim3(1), dim3(mv.NT), lds, st,
+                                             mv, w, taps, g, iters, rtol, x, iterates, vec_scratch,
+                                             reinterpret_cast<float *>(f), used, (int)ext_off,
+                                             use_ext));
+  } else {
+    RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((cg_kernel<double, EE>), dim3(1), dim3(mv.NT), lds,
+                                             st, mv, w, taps, g, iters, rtol, x, iterates,
+                                             vec_scratch, reinterpret_cast<double *>(f), used,
+                                             (int)ext_off, use_ext));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_philox_normal(long long total, uint64_t seed, uint64_t stream, double *out,
+                                hipStream_t st) {
+  if (total <= 0) return hipSuccess;
+  const long long pairs = (total + 1) / 2;
+  const int bs = 256;
+  const long long grid = (pairs + bs - 1) / bs;
+  hipLaunchKernelGGL(philox_normal_kernel, dim3((unsigned)grid), dim3(bs), 0, st, total, seed,
+                     stream, out);
+  return hipGetLastError();
+}
+
+}  // namespace riot

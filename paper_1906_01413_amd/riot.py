@@ -1,0 +1,302 @@
+"""Thin Python binding of the RIOT C ABI (include/riot.h).
+
+Argument marshalling only: every step of the inner loop runs in the HIP
+library libriot.so. PyTorch supplies device memory and the stream. Matrices
+follow the C ABI's column-major convention: an n x m block is a float64 CUDA
+tensor of shape (n, m) with strides (1, n) (``colmajor`` below builds one).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libriot.so")
+
+RIOT_OK = 0
+STATUS = {0: "RIOT_OK", -1: "RIOT_E_ARG", -2: "RIOT_E_HIP", -3: "RIOT_E_NOT_SPD",
+          -4: "RIOT_E_SINGULAR", -5: "RIOT_E_NONFINITE", -6: "RIOT_E_NOCONV",
+          -7: "RIOT_E_STATE", -8: "RIOT_E_WORKSPACE"}
+FP64, FP32_TLAD = 0, 1
+ADAPTIVE, LRA, LRU = 0, 1, 2
+MODES = {"adaptive": ADAPTIVE, "lra": LRA, "lru": LRU}
+
+EXPORTS = ("riot_workspace_bytes", "riot_init", "riot_free", "riot_status_str",
+           "riot_linearize", "riot_hess_apply", "riot_rsvd", "riot_increment",
+           "riot_posterior_cov", "riot_cg", "riot_forecast", "riot_apply_L",
+           "riot_philox_normal", "riot_tl_apply", "riot_ad_apply", "riot_gn_apply")
+
+
+class RiotError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("nsteps", ctypes.c_int32),
+        ("dt", ctypes.c_double), ("forcing", ctypes.c_double),
+        ("nobs", ctypes.c_int32),
+        ("obs_step", ctypes.POINTER(ctypes.c_int32)), ("obs_idx", ctypes.POINTER(ctypes.c_int32)),
+        ("y", ctypes.POINTER(ctypes.c_double)), ("rinv", ctypes.POINTER(ctypes.c_double)),
+        ("l_halfwidth", ctypes.c_int32), ("l_taps", ctypes.POINTER(ctypes.c_double)),
+        ("m_max", ctypes.c_int32), ("prec", ctypes.c_int32), ("elems_per_lane", ctypes.c_int32),
+    ]
+
+
+class _RsvdInfo(ctypes.Structure):
+    _fields_ = [("chol_shifts", ctypes.c_int32), ("qr_passes", ctypes.c_int32),
+                ("k_asym", ctypes.c_double), ("orth_err", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str | None = None) -> ctypes.CDLL:
+    """Load libriot.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or _LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"libriot.so not found at {p}: build it with "
+                          "`python paper_1906_01413_amd/build_lib.py` (no CPU fallback exists)")
+    lib = ctypes.CDLL(p)
+    vp, i32, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+    sig = {
+        "riot_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(_Desc)]),
+        "riot_init": (i32, [ctypes.POINTER(_Desc), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+        "riot_free": (None, [vp]),
+        "riot_status_str": (ctypes.c_char_p, [i32]),
+        "riot_linearize": (i32, [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]),
+        "riot_hess_apply": (i32, [vp, i32, vp, vp, i32]),
+        "riot_rsvd": (i32, [vp, i32, i32, i32, vp, u64, vp, vp, ctypes.POINTER(_RsvdInfo)]),
+        "riot_increment": (i32, [vp, i32, vp, vp, vp, i32, vp, vp, ctypes.POINTER(dbl),
+                                 ctypes.POINTER(i32)]),
+        "riot_posterior_cov": (i32, [vp, i32, vp, vp, i32, vp, vp, vp, vp, ctypes.POINTER(i32)]),
+        "riot_cg": (i32, [vp, vp, i32, dbl, vp, vp, ctypes.POINTER(i32)]),
+        "riot_forecast": (i32, [vp, vp, i32, vp]),
+        "riot_apply_L": (i32, [vp, i32, vp, vp]),
+        "riot_philox_normal": (i32, [vp, i32, i32, u64, u64, vp]),
+        "riot_tl_apply": (i32, [vp, i32, vp, vp]),
+        "riot_ad_apply": (i32, [vp, i32, vp, vp]),
+        "riot_gn_apply": (i32, [vp, i32, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != RIOT_OK:
+        raise RiotError(status, where)
+
+
+def colmajor(x, device="cuda") -> torch.Tensor:
+    """float64 tensor of shape (n, m) with column-major strides (1, n)."""
+    t = torch.as_tensor(x, dtype=torch.float64)
+    if t.dim() == 1:
+        return t.to(device).contiguous()
+    return t.t().contiguous().t().to(device) if t.device.type != "cuda" else t.t().contiguous().t()
+
+
+def empty_colmajor(n: int, m: int, device="cuda") -> torch.Tensor:
+    return torch.empty((m, n), dtype=torch.float64, device=device).t()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.dtype == torch.float64
+    if t.dim() == 2:
+        assert t.stride(0) == 1 and t.stride(1) == t.shape[0], "expected column-major (1, n) strides"
+    else:
+        assert t.is_contiguous()
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class RsvdInfo:
+    chol_shifts: int
+    qr_passes: int
+    k_asym: float
+    orth_err: float
+
+
+class Riot:
+    """One inner-loop problem (eqs. 2-3) bound to a device workspace and a stream."""
+
+    def __init__(self, n, nsteps, dt, forcing, obs_step, obs_idx, y, rinv, taps, m_max,
+                 prec=FP64, elems_per_lane=0, device="cuda"):
+        self.lib = load_library()
+        self.n, self.nsteps, self.m_max = int(n), int(nsteps), int(m_max)
+        self.device = torch.device(device)
+        self._obs_step = np.ascontiguousarray(obs_step, dtype=np.int32)
+        self._obs_idx = np.ascontiguousarray(obs_idx, dtype=np.int32)
+        self._y = np.ascontiguousarray(y, dtype=np.float64)
+        self._rinv = np.ascontiguousarray(rinv, dtype=np.float64)
+        self._taps = np.ascontiguousarray(taps, dtype=np.float64)
+        self.nobs = int(self._obs_step.size)
+        d = _Desc()
+        d.n, d.nsteps, d.dt, d.forcing, d.nobs = self.n, self.nsteps, float(dt), float(forcing), self.nobs
+        P = lambda a, c: a.ctypes.data_as(ctypes.POINTER(c))  # noqa: E731
+        d.obs_step, d.obs_idx = P(self._obs_step, ctypes.c_int32), P(self._obs_idx, ctypes.c_int32)
+        d.y, d.rinv = P(self._y, ctypes.c_double), P(self._rinv, ctypes.c_double)
+        d.l_halfwidth = int(self._taps.size - 1)
+        d.l_taps = P(self._taps, ctypes.c_double)
+        d.m_max, d.prec, d.elems_per_lane = self.m_max, int(prec), int(elems_per_lane)
+        self._desc = d
+        nbytes = self.lib.riot_workspace_bytes(ctypes.byref(d))
+        if nbytes == 0:
+            raise RiotError(-1, "riot_workspace_bytes")
+        self.workspace_bytes = int(nbytes)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(self.lib.riot_init(ctypes.byref(d), ctypes.c_void_p(aligned), ctypes.c_size_t(nbytes),
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "riot_init")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.riot_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls ---------------------------------------------------------------
+    def linearize(self, x, v=None, want_cost=True, out=None):
+        x = colmajor(x, self.device)
+        v = None if v is None else colmajor(v, self.device)
+        if out is None:
+            d = torch.empty(max(self.nobs, 1), dtype=torch.float64, device=self.device)
+            g = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        else:
+            d, g = out
+        J = ctypes.c_double(0.0)
+        _check(self.lib.riot_linearize(self.h, _ptr(x), _ptr(v), _ptr(d), _ptr(g),
+                                       ctypes.byref(J) if want_cost else None), "riot_linearize")
+        return d[: self.nobs], g, (J.value if want_cost else None)
+
+    def hess_apply(self, W, add_identity=False, out=None):
+        W = colmajor(W, self.device)
+        if W.dim() == 1:
+            W = W.reshape(-1, 1).t().contiguous().t()
+        m = W.shape[1]
+        Y = empty_colmajor(self.n, m, self.device) if out is None else out
+        _check(self.lib.riot_hess_apply(self.h, m, _ptr(W), _ptr(Y), int(bool(add_identity))),
+               "riot_hess_apply")
+        return Y
+
+    def rsvd(self, k, p_os, q=0, Omega=None, seed=0, want_info=True, lam=None, V=None):
+        m = k + p_os
+        Om = None if Omega is None else colmajor(Omega, self.device)
+        lam = torch.empty(m, dtype=torch.float64, device=self.device) if lam is None else lam
+        V = empty_colmajor(self.n, m, self.device) if V is None else V
+        info = _RsvdInfo()
+        _check(self.lib.riot_rsvd(self.h, k, p_os, q, _ptr(Om), ctypes.c_uint64(seed), _ptr(lam),
+                                  _ptr(V), ctypes.byref(info) if want_info else None), "riot_rsvd")
+        inf = RsvdInfo(info.chol_shifts, info.qr_passes, info.k_asym, info.orth_err) if want_info else None
+        return lam, V, inf
+
+    def increment(self, lam, V, g, k=None, mode="adaptive", want_host=True, dz=None, dx=None):
+        k = lam.numel() if k is None else k
+        dz = torch.empty(self.n, dtype=torch.float64, device=self.device) if dz is None else dz
+        dx = torch.empty(self.n, dtype=torch.float64, device=self.device) if dx is None else dx
+        dofs = ctypes.c_double(0.0)
+        mu = ctypes.c_int32(0)
+        _check(self.lib.riot_increment(self.h, k, _ptr(lam), _ptr(V), _ptr(g), MODES[mode], _ptr(dz),
+                                       _ptr(dx), ctypes.byref(dofs) if want_host else None,
+                                       ctypes.byref(mu) if want_host else None), "riot_increment")
+        used = {LRA: "lra", LRU: "lru"}.get(mu.value) if want_host else None
+        return dz, dx, (dofs.value if want_host else None), used
+
+    def posterior_cov(self, lam, V, k=None, mode="adaptive", diag=True, dense=False,
+                      want_host=True, out=None):
+        k = lam.numel() if k is None else k
+        if out is None:
+            W = empty_colmajor(self.n, k, self.device)
+            coef = torch.empty(k, dtype=torch.float64, device=self.device)
+            dg = torch.empty(self.n, dtype=torch.float64, device=self.device) if diag else None
+        else:
+            W, coef, dg = out
+        P = empty_colmajor(self.n, self.n, self.device) if dense else None
+        mu = ctypes.c_int32(0)
+        _check(self.lib.riot_posterior_cov(self.h, k, _ptr(lam), _ptr(V), MODES[mode], _ptr(W),
+                                           _ptr(coef), _ptr(dg), _ptr(P),
+                                           ctypes.byref(mu) if want_host else None),
+               "riot_posterior_cov")
+        return W, coef, dg, P, ({LRA: "lra", LRU: "lru"}.get(mu.value) if want_host else None)
+
+    def cg(self, g, iters, rtol=0.0, record=False):
+        dz = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        its = empty_colmajor(self.n, max(iters, 1), self.device) if record else None
+        used = ctypes.c_int32(0)
+        _check(self.lib.riot_cg(self.h, _ptr(g), int(iters), float(rtol), _ptr(dz), _ptr(its),
+                                ctypes.byref(used)), "riot_cg")
+        return dz, (its[:, : used.value] if record else None), used.value
+
+    def forecast(self, x0, nsteps):
+        x0 = colmajor(x0, self.device)
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(self.lib.riot_forecast(self.h, _ptr(x0), int(nsteps), _ptr(out)), "riot_forecast")
+        return out
+
+    def apply_L(self, X):
+        X = colmajor(X, self.device)
+        vec = X.dim() == 1
+        if vec:
+            X = X.reshape(-1, 1).t().contiguous().t()
+        Y = empty_colmajor(self.n, X.shape[1], self.device)
+        _check(self.lib.riot_apply_L(self.h, X.shape[1], _ptr(X), _ptr(Y)), "riot_apply_L")
+        return Y[:, 0] if vec else Y
+
+    def _block(self, X):
+        X = colmajor(X, self.device)
+        if X.dim() == 1:
+            X = X.reshape(-1, 1).t().contiguous().t()
+        return X
+
+    def tl_apply(self, X):
+        """Z = G X (observations x columns)."""
+        X = self._block(X)
+        Z = empty_colmajor(max(self.nobs, 1), X.shape[1], self.device)
+        _check(self.lib.riot_tl_apply(self.h, X.shape[1], _ptr(X), _ptr(Z)), "riot_tl_apply")
+        return Z[: self.nobs]
+
+    def ad_apply(self, Fo):
+        """X = G^T Fo."""
+        Fo = self._block(Fo)
+        X = empty_colmajor(self.n, Fo.shape[1], self.device)
+        _check(self.lib.riot_ad_apply(self.h, Fo.shape[1], _ptr(Fo), _ptr(X)), "riot_ad_apply")
+        return X
+
+    def gn_apply(self, X, out=None):
+        """Y = G^T R^{-1} G X."""
+        X = self._block(X)
+        Y = empty_colmajor(self.n, X.shape[1], self.device) if out is None else out
+        _check(self.lib.riot_gn_apply(self.h, X.shape[1], _ptr(X), _ptr(Y)), "riot_gn_apply")
+        return Y
+
+    def philox_normal(self, n, m, seed, stream=0):
+        out = empty_colmajor(n, m, self.device)
+        _check(self.lib.riot_philox_normal(self.h, n, m, ctypes.c_uint64(seed), ctypes.c_uint64(stream),
+                                           _ptr(out)), "riot_philox_normal")
+        return out

@@ -131,6 +131,7 @@ def time_to_accuracy(r, prob, xb, dev, target=1e-6, trials=3, cg_max=None, reps=
 
     d, g, _ = r.linearize(xb, want_cost=False)
     rs_best = None
+    sweep = []
     for (m, q) in ACCURACY_SWEEP[name]:
         if m > r.m_max or m > n:
             continue
@@ -147,6 +148,9 @@ def time_to_accuracy(r, prob, xb, dev, target=1e-6, trials=3, cg_max=None, reps=
             r.increment(lam, V, g, want_host=False)
         sec = timed(run, reps)
         rec = {"m": m, "q": q, "max_err": emax, "seconds": sec, "mode": mode}
+        sweep.append(rec)
+        print(f"[bench] accuracy sweep m={m} q={q}: max err {emax:.2e}, {sec*1e3:.2f} ms, {mode}",
+              file=sys.stderr, flush=True)
         if rs_best is None or emax < rs_best["max_err"]:
             rs_best = dict(rec)
         if emax <= tgt:
@@ -172,7 +176,7 @@ def time_to_accuracy(r, prob, xb, dev, target=1e-6, trials=3, cg_max=None, reps=
     del its, dxi
     out = {"target": target, "target_used": tgt, "reference_floor": floor,
            "error": "||dx - dx*|| / ||dx*|| against the oracle's exact minimiser",
-           "rsvd": rs_best, "cg": cg}
+           "rsvd": rs_best, "cg": cg, "rsvd_sweep": sweep}
     if rs_best["reached"] and cg["reached"]:
         out["speedup_rsvd_over_cg"] = cg["seconds"] / rs_best["seconds"]
     return out

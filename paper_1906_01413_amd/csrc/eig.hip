@@ -1,0 +1,842 @@
+// Symmetric eigen-solver for the m x m matrix K of the randomized eigendecomposition
+// (Alg. 3: K = Z Lambda Z^T), FP64, for gfx950.
+//
+//  1. Householder tridiagonalisation Q^T K Q = T (one workgroup; reflectors kept).
+//  2. Root representation: T - sigma I = L D L^T positive definite, sigma just below
+//     the smallest eigenvalue (found by bisection with Sturm counts).
+//  3. Eigenvalues of L D L^T to high relative accuracy: one wave per eigenvalue,
+//     64-way multisection with negative counts from the stationary qd transform
+//     (geometric brackets first, then uniform ones).
+//  4. Eigenvectors: twisted factorisation of L D L^T - mu I (stationary and
+//     progressive qd transforms, twist index of the smallest gamma) with two
+//     Rayleigh-quotient corrections; one thread per eigenvalue.
+//  5. Eigenvalues closer than a relative gap of 1e-3 are treated as a cluster:
+//     their vectors are re-orthonormalised and rotated by a small Rayleigh-Ritz
+//     (Jacobi) solve on T restricted to the cluster.
+//  6. Back-transformation by the reflectors and descending order.
+//
+// Steps 2-4 follow the relatively-robust-representation approach of Dhillon &
+// Parlett (2004) for the tridiagonal eigenproblem.
+
+#include "riot_internal.h"
+
+namespace riot {
+namespace {
+
+__device__ double wsum(double v, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int k = 0; k < nw; ++k) s += red[k];
+  __syncthreads();
+  return s;
+}
+
+// work layout (doubles): Aw[m*m] Hv[m*m] Z[m*m] d[m] e[m] D[m] Ls[m] LLD[m] mu[m] misc[16]
+//                        scratch for the vector kernel: 4 * m * m
+struct EigLayout {
+  size_t Aw, Hv, Z, d, e, D, Ls, LLD, mu, misc, scr, total;
+  __host__ __device__ EigLayout(int m) {
+    const size_t mm = (size_t)m * m;
+    Aw = 0;
+    Hv = mm;
+    Z = 2 * mm;
+    d = 3 * mm;
+    e = d + m;
+    D = e + m;
+    Ls = D + m;
+    LLD = Ls + m;
+    mu = LLD + m;
+    misc = mu + m;
+    scr = misc + 16;
+    total = scr + 4 * mm;
+  }
+};
+
+constexpr int kTriThreads = 512;
+
+// ---------------------------------------------------------------------------
+// 1. Householder tridiagonalisation (full storage, one workgroup).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kTriThreads)
+    tridiag_kernel(int m, const double *__restrict__ K, double *__restrict__ work) {
+  extern __shared__ double sh[];
+  EigLayout Lw(m);
+  double *Aw = work + Lw.Aw, *Hv = work + Lw.Hv, *dg = work + Lw.d, *eg = work + Lw.e;
+  double *vs = sh, *ps = sh + m, *part = sh + 2 * m;
+  __shared__ double red[16];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (size_t idx = tid; idx < (size_t)m * m; idx += nt) {
+    Aw[idx] = K[idx];
+    Hv[idx] = 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k + 2 < m; ++k) {
+    const int R = m - k - 1;
+    double part_s = 0.0;
+    for (int i = tid; i < R; i += nt) {
+      const double x = Aw[(size_t)k * m + k + 1 + i];
+      vs[i] = x;
+      part_s += x * x;
+    }
+    const double sig2 = wsum(part_s, red);
+    const double sig = sqrt(sig2);
+    const double x0 = vs[0];
+    __syncthreads();
+    if (sig == 0.0) {
+      if (tid == 0) {
+        dg[k] = Aw[(size_t)k * m + k];
+        eg[k] = 0.0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const double alpha = (x0 >= 0.0) ? -sig : sig;
+    const double vn = sqrt(2.0 * (sig2 - alpha * x0));
+    if (tid == 0) vs[0] = x0 - alpha;
+    __syncthreads();
+    for (int i = tid; i < R; i += nt) {
+      const double v = vs[i] / vn;
+      vs[i] = v;
+      Hv[(size_t)k * m + k + 1 + i] = v;
+    }
+    __syncthreads();
+    // p = S v: thread groups split the column range of each row
+    const int groups = max(1, nt / R);
+    if (R <= nt) {
+      const int i = tid % R, g = tid / R;
+      double acc = 0.0;
+      if (g < groups)
+        for (int j = g; j < R; j += groups)
+          acc += Aw[(size_t)(k + 1 + j) * m + (k + 1 + i)] * vs[j];
+      if (tid < R * groups) part[tid] = acc;
+      __syncthreads();
+      for (int ii = tid; ii < R; ii += nt) {
+        double s = 0.0;
+        for (int gg = 0; gg < groups; ++gg) s += part[gg * R + ii];
+        ps[ii] = s;
+      }
+    } else {
+      for (int i = tid; i < R; i += nt) {
+        double s = 0.0;
+        for (int j = 0; j < R; ++j) s += Aw[(size_t)(k + 1 + j) * m + (k + 1 + i)] * vs[j];
+        ps[i] = s;
+      }
+    }
+    __syncthreads();
+    double kp = 0.0;
+    for (int i = tid; i < R; i += nt) kp += vs[i] * ps[i];
+    const double Kv = wsum(kp, red);
+    for (int i = tid; i < R; i += nt) ps[i] = ps[i] - Kv * vs[i];
+    __syncthreads();
+    const size_t tot = (size_t)R * R;
+    for (size_t idx = tid; idx < tot; idx += nt) {
+      const int i = (int)(idx % R), j = (int)(idx / R);
+      Aw[(size_t)(k + 1 + j) * m + (k + 1 + i)] -= 2.0 * (vs[i] * ps[j] + ps[i] * vs[j]);
+    }
+    if (tid == 0) {
+      dg[k] = Aw[(size_t)k * m + k];
+      eg[k] = alpha;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (m >= 2) {
+      dg[m - 2] = Aw[(size_t)(m - 2) * m + m - 2];
+      dg[m - 1] = Aw[(size_t)(m - 1) * m + m - 1];
+      eg[m - 2] = Aw[(size_t)(m - 2) * m + m - 1];
+    } else {
+      dg[0] = Aw[0];
+    }
+    eg[m - 1] = 0.0;
+  }
+}
+
+// Register-resident variant for small m. Columns j and m-1-j of the lower triangle
+// are paired (together m + 1 entries); a group of Tp threads owns one pair, thread tl
+// of the group holding entries r = tl + Tp q of the pair's concatenated rows, so each
+// thread has one run in column j0 and one in column j1 with rows advancing by Tp.
+// The rank-2 update of step k is applied lazily during step k + 1 and the symmetric
+// product uses one FP64 LDS atomic per entry plus one per run. No matrix traffic
+// leaves the CU.
+constexpr int kRegThreads = 1024;
+constexpr int kRegQ = 40;
+
+__host__ __device__ inline int reg_pairs(int m) { return (m + 1) / 2; }
+__host__ __device__ inline int reg_tp(int m) { return kRegThreads / reg_pairs(m); }
+__host__ inline bool reg_fits(int m) {
+  const int tp = reg_tp(m);
+  return m >= 3 && tp >= 1 && (m + 1 + tp - 1) / tp <= kRegQ;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(kRegThreads)
+    tridiag_reg_kernel(int m, const double *__restrict__ K, double *__restrict__ work) {
+  extern __shared__ double sh[];
+  EigLayout Lw(m);
+  double *Hv = work + Lw.Hv, *dg = work + Lw.d, *eg = work + Lw.e;
+  double *v = sh, *w = sh + m, *p = sh + 2 * m, *x = sh + 3 * m;
+  const int tid = threadIdx.x;
+  const int Tp = reg_tp(m), pairs = reg_pairs(m);
+  const int pr = tid / Tp, tl = tid - pr * Tp;
+  const bool own = pr < pairs;
+  const int j0 = own ? pr : 0;
+  const int j1 = m - 1 - j0;             // == j0 for the middle column of odd m
+  const int len0 = m - j0;               // rows j0..m-1
+  const bool has1 = own && (j1 != j0);   // second column present
+  const int base0 = j0 + tl, base1 = j1 + tl - len0;
+  // first q that falls in column j1
+  const int qs = own ? max(0, (len0 - tl + Tp - 1) / Tp) : 0;
+  double a[kRegQ];
+#pragma unroll
+  for (int q = 0; q < kRegQ; ++q) {
+    a[q] = 0.0;
+    if (!own) continue;
+    if (q < qs) {
+      const int i = base0 + Tp * q;
+      a[q] = K[(size_t)j0 * m + i];
+    } else if (has1) {
+      const int i = base1 + Tp * q;
+      if (i < m) a[q] = K[(size_t)j1 * m + i];
+    }
+  }
+  for (int i = tid; i < m; i += kRegThreads) {
+    v[i] = 0.0;
+    w[i] = 0.0;
+  }
+  for (size_t idx = tid; idx < (size_t)m * m; idx += kRegThreads) Hv[idx] = 0.0;
+  __syncthreads();
+  for (int k = 0; k + 2 < m; ++k) {
+    // phase 1: pending rank-2 update of step k-1 on columns >= k; gather column k
+    if (own && (j0 >= k || (has1 && j1 >= k))) {
+      int b0 = base0, b1 = base1;
+      // keep the per-entry row indices out of registers across steps (recomputed per phase)
+      asm volatile("" : "+v"(b0), "+v"(b1));
+      const double vj0 = v[j0], wj0 = w[j0], vj1 = v[j1], wj1 = w[j1];
+#pragma unroll
+      for (int q = 0; q < kRegQ; ++q) {
+        if (q < qs) {
+          if (j0 >= k) {
+            const int i = b0 + Tp * q;
+            a[q] -= 2.0 * (v[i] * wj0 + w[i] * vj0);
+            if (j0 == k) x[i] = a[q];
+          }
+        } else if (has1 && j1 >= k) {
+          const int i = b1 + Tp * q;
+          if (i < m) {
+            a[q] -= 2.0 * (v[i] * wj1 + w[i] * vj1);
+            if (j1 == k) x[i] = a[q];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // phase 2 (wave 0): Householder vector of column k
+    if (tid < 64) {
+      double s2 = 0.0;
+      for (int i = k + 1 + tid; i < m; i += 64) s2 += x[i] * x[i];
+      s2 = wave_sum(s2);
+      const double sig = sqrt(s2);
+      const double x0 = x[k + 1];
+      const double alpha = (x0 >= 0.0) ? -sig : sig;
+      const double vn = sqrt(2.0 * (s2 - alpha * x0));
+      for (int i = tid; i < m; i += 64) {
+        double vi = 0.0;
+        if (sig != 0.0 && i > k) vi = ((i == k + 1) ? (x0 - alpha) : x[i]) / vn;
+        v[i] = vi;
+        p[i] = 0.0;
+        if (i > k) Hv[(size_t)k * m + i] = vi;
+      }
+      if (tid == 0) {
+        dg[k] = x[k];
+        eg[k] = (sig != 0.0) ? alpha : 0.0;
+      }
+    }
+    __syncthreads();
+    // phase 3: p = S v over columns > k; row halves by atomics, column halves per run
+    if (own && (j0 > k || (has1 && j1 > k))) {
+      int b0 = base0, b1 = base1;
+      asm volatile("" : "+v"(b0), "+v"(b1));
+      const double vj0 = v[j0], vj1 = v[j1];
+      double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < kRegQ; ++q) {
+        if (q < qs) {
+          if (j0 > k) {
+            const int i = b0 + Tp * q;
+            atomicAdd(&p[i], a[q] * vj0);
+            if (i != j0) c0 += a[q] * v[i];
+          }
+        } else if (has1 && j1 > k) {
+          const int i = b1 + Tp * q;
+          if (i < m) {
+            atomicAdd(&p[i], a[q] * vj1);
+            if (i != j1) c1 += a[q] * v[i];
+          }
+        }
+      }
+      if (j0 > k && c0 != 0.0) atomicAdd(&p[j0], c0);
+      if (has1 && j1 > k && c1 != 0.0) atomicAdd(&p[j1], c1);
+    }
+    __syncthreads();
+    // phase 4 (wave 0): w = p - (v^T p) v
+    if (tid < 64) {
+      double kp = 0.0;
+      for (int i = k + 1 + tid; i < m; i += 64) kp += v[i] * p[i];
+      kp = wave_sum(kp);
+      for (int i = tid; i < m; i += 64) w[i] = (i > k) ? p[i] - kp * v[i] : 0.0;
+    }
+    __syncthreads();
+  }
+  // last pending update on the trailing 2 x 2 block, then its entries
+  const int kl = m - 2;
+  if (own) {
+    const double vj0 = v[j0], wj0 = w[j0], vj1 = v[j1], wj1 = w[j1];
+#pragma unroll
+    for (int q = 0; q < kRegQ; ++q) {
+      int i = -1, j = -1;
+      double vj = 0.0, wj = 0.0;
+      if (q < qs) {
+        i = base0 + Tp * q;
+        j = j0;
+        vj = vj0;
+        wj = wj0;
+      } else if (has1) {
+        i = base1 + Tp * q;
+        j = j1;
+        vj = vj1;
+        wj = wj1;
+      }
+      if (j >= kl && i < m && i >= 0) {
+        const double val = a[q] - 2.0 * (v[i] * wj + w[i] * vj);
+        if (i == j) dg[i] = val;
+        if (i == j + 1) eg[j] = val;
+      }
+    }
+  }
+  if (tid == 0) eg[m - 1] = 0.0;
+}
+
+// Sturm count of T - x I (number of eigenvalues below x).
+__device__ int sturm_count(int m, const double *d, const double *e, double x, double pivmin) {
+  int c = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0) ++c;
+  for (int i = 1; i < m; ++i) {
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0) ++c;
+  }
+  return c;
+}
+
+// Negative count of L D L^T - tau I (stationary qd transform).
+__device__ int negcount(int m, const double *D, const double *LLD, double tau, double pivmin) {
+  int c = 0;
+  double s = -tau;
+  for (int i = 0; i < m - 1; ++i) {
+    double dp = D[i] + s;
+    if (fabs(dp) < pivmin) dp = -pivmin;
+    if (dp < 0) ++c;
+    s = LLD[i] * (s / dp) - tau;
+  }
+  double dp = D[m - 1] + s;
+  if (fabs(dp) < pivmin) dp = -pivmin;
+  if (dp < 0) ++c;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// 2. Root representation (one workgroup of 64 threads).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) root_kernel(int m, double *__restrict__ work,
+                                                  int *__restrict__ flag) {
+  EigLayout Lw(m);
+  extern __shared__ double rsh[];
+  double *dg = rsh, *eg = rsh + m, *Dl = rsh + 2 * m, *Ll = rsh + 3 * m;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    dg[i] = work[Lw.d + i];
+    eg[i] = work[Lw.e + i];
+  }
+  __syncthreads();
+  double *D = work + Lw.D, *Ls = work + Lw.Ls, *LLD = work + Lw.LLD, *misc = work + Lw.misc;
+  __shared__ double sh_lo, sh_hi, sh_sigma;
+  __shared__ int sh_ok;
+  const int lane = threadIdx.x;
+  // Gershgorin bounds and the norm
+  if (lane == 0) {
+    double gl = dg[0], gu = dg[0], tn = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double r = (i > 0 ? fabs(eg[i - 1]) : 0.0) + (i < m - 1 ? fabs(eg[i]) : 0.0);
+      gl = fmin(gl, dg[i] - r);
+      gu = fmax(gu, dg[i] + r);
+    }
+    tn = fmax(fabs(gl), fabs(gu));
+    sh_lo = gl - 2.0 * 0x1.0p-52 * tn - 1e-300;
+    sh_hi = gu + 2.0 * 0x1.0p-52 * tn + 1e-300;
+    misc[0] = tn;
+    misc[1] = gl;
+    misc[2] = gu;
+  }
+  __syncthreads();
+  const double tn = misc[0];
+  const double pivmin = 1e-290 * fmax(1.0, tn * tn);
+  // smallest eigenvalue by 64-way multisection on Sturm counts
+  for (int round = 0; round < 14; ++round) {
+    const double lo = sh_lo, hi = sh_hi;
+    const double x = lo + (hi - lo) * (lane + 1) / 65.0;
+    const int c = sturm_count(m, dg, eg, x, pivmin);
+    // smallest lane whose point has at least one eigenvalue below it
+    const unsigned long long bal = __ballot(c >= 1);
+    __syncthreads();
+    if (lane == 0) {
+      if (bal == 0ull) {
+        sh_lo = lo + (hi - lo) * 64.0 / 65.0;
+      } else {
+        const int first = __ffsll((long long)bal) - 1;
+        sh_hi = lo + (hi - lo) * (first + 1) / 65.0;
+        if (first > 0) sh_lo = lo + (hi - lo) * first / 65.0;
+      }
+    }
+    __syncthreads();
+  }
+  // sigma below the spectrum; retry lower until L D L^T is positive definite
+  if (lane == 0) {
+    const double lmin = sh_lo;
+    double margin = fmax(1e-3 * fabs(lmin), 64.0 * 0x1.0p-52 * tn) + 1e-300;
+    bool ok = false;
+    double sigma = lmin;
+    for (int tries = 0; tries < 60 && !ok; ++tries) {
+      sigma = lmin - margin;
+      ok = true;
+      double dprev = dg[0] - sigma;
+      if (!(dprev > 0.0)) ok = false;
+      Dl[0] = dprev;
+      for (int i = 0; i < m - 1 && ok; ++i) {
+        const double l = eg[i] / Dl[i];
+        Ll[i] = l;
+        const double dn = dg[i + 1] - sigma - l * eg[i];
+        Dl[i + 1] = dn;
+        if (!(dn > 0.0) || !isfinite(dn)) ok = false;
+      }
+      margin *= 2.0;
+    }
+    Ll[m - 1] = 0.0;
+    misc[3] = sigma;
+    sh_ok = ok ? 1 : 0;
+    // upper bound of the shifted spectrum
+    misc[4] = (sh_hi > sigma ? misc[2] - sigma : 1.0) * (1.0 + 1e-12) + 1e-300;
+  }
+  __syncthreads();
+  for (int i = lane; i < m; i += 64) {
+    D[i] = Dl[i];
+    Ls[i] = Ll[i];
+    LLD[i] = Ll[i] * Ll[i] * Dl[i];
+  }
+  if (lane == 0 && !sh_ok) flag[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// 3. Eigenvalues of L D L^T: one wave per eigenvalue index (ascending).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) bisect_kernel(int m, double *__restrict__ work) {
+  EigLayout Lw(m);
+  extern __shared__ double bsh[];
+  double *D = bsh, *LLD = bsh + m;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    D[i] = work[Lw.D + i];
+    LLD[i] = work[Lw.LLD + i];
+  }
+  __syncthreads();
+  const double *misc = work + Lw.misc;
+  double *mu = work + Lw.mu;
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= m) return;
+  const double tn = misc[0];
+  const double pivmin = 1e-290 * fmax(1.0, tn * tn);
+  double lo = 0.0, hi = misc[4];
+  // geometric brackets: points hi * 2^-(lane+1); the eigenvalue index j is the (j+1)-th smallest
+  for (int g = 0; g < 4; ++g) {
+    const double x = hi * exp2(-(double)(lane + 1));
+    const int c = negcount(m, D, LLD, x, pivmin);
+    // largest lane k with count(x_k) >= j+1 gives hi = x_k; next lane gives lo
+    const unsigned long long bal = __ballot(c >= j + 1);
+    if (bal == 0ull) {  // eigenvalue above hi/2
+      lo = hi * 0.5;
+      break;
+    }
+    const int last = 63 - __clzll((long long)bal);
+    const double xh = hi * exp2(-(double)(last + 1));
+    if (last < 63) {
+      lo = hi * exp2(-(double)(last + 2));
+      hi = xh;
+      break;
+    }
+    hi = xh;  // still below every geometric point: continue further down
+  }
+  // uniform 64-way multisection
+  for (int round = 0; round < 10; ++round) {
+    const double x = lo + (hi - lo) * (lane + 1) / 65.0;
+    const int c = negcount(m, D, LLD, x, pivmin);
+    const unsigned long long bal = __ballot(c >= j + 1);
+    double nlo = lo, nhi = hi;
+    if (bal == 0ull) {
+      nlo = lo + (hi - lo) * 64.0 / 65.0;
+    } else {
+      const int first = __ffsll((long long)bal) - 1;
+      nhi = lo + (hi - lo) * (first + 1) / 65.0;
+      if (first > 0) nlo = lo + (hi - lo) * first / 65.0;
+    }
+    lo = nlo;
+    hi = nhi;
+    if (hi - lo <= 2.0 * 0x1.0p-53 * hi) break;
+  }
+  if (lane == 0) mu[j] = 0.5 * (lo + hi);
+}
+
+// ---------------------------------------------------------------------------
+// 4. Eigenvectors by twisted factorisation: one thread per eigenvalue. The
+//    per-eigenvalue arrays live in scratch laid out [i][j] (coalesced in j).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) vector_kernel(int m, double *__restrict__ work) {
+  EigLayout Lw(m);
+  extern __shared__ double vsh[];
+  double *D = vsh, *Ls = vsh + m, *LLD = vsh + 2 * m;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    D[i] = work[Lw.D + i];
+    Ls[i] = work[Lw.Ls + i];
+    LLD[i] = work[Lw.LLD + i];
+  }
+  __syncthreads();
+  double *__restrict__ mu = work + Lw.mu;
+  double *__restrict__ Z = work + Lw.Z;
+  double *__restrict__ Lp = work + Lw.scr;
+  double *__restrict__ Um = work + Lw.scr + (size_t)m * m;
+  double *__restrict__ sv = work + Lw.scr + 2 * (size_t)m * m;
+  double *__restrict__ pv = work + Lw.scr + 3 * (size_t)m * m;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const double tiny = 1e-300;
+  double lam = mu[j];
+  int r = 0;
+  double nrm2 = 1.0;
+  for (int it = 0; it < 3; ++it) {
+    // stationary: L D L^T - lam I = L+ D+ L+^T
+    double s = -lam;
+    for (int i = 0; i < m - 1; ++i) {
+      sv[(size_t)i * m + j] = s;
+      double dp = D[i] + s;
+      if (fabs(dp) < tiny) dp = -tiny;
+      const double lp = D[i] * Ls[i] / dp;
+      Lp[(size_t)i * m + j] = lp;
+      s = lp * Ls[i] * s - lam;
+    }
+    sv[(size_t)(m - 1) * m + j] = s;
+    // progressive: L D L^T - lam I = U- D- U-^T
+    double p = D[m - 1] - lam;
+    pv[(size_t)(m - 1) * m + j] = p;
+    for (int i = m - 2; i >= 0; --i) {
+      double dm = LLD[i] + p;
+      if (fabs(dm) < tiny) dm = -tiny;
+      const double t = D[i] / dm;
+      Um[(size_t)i * m + j] = Ls[i] * t;
+      p = p * t - lam;
+      pv[(size_t)i * m + j] = p;
+    }
+    // twist index
+    double gmin = 0.0;
+    r = 0;
+    for (int k = 0; k < m; ++k) {
+      const double gk = sv[(size_t)k * m + j] + pv[(size_t)k * m + j] + lam;
+      if (k == 0 || fabs(gk) < fabs(gmin)) {
+        gmin = gk;
+        r = k;
+      }
+    }
+    // vector with z_r = 1
+    nrm2 = 1.0;
+    Z[(size_t)j * m + r] = 1.0;
+    double z = 1.0;
+    for (int i = r - 1; i >= 0; --i) {
+      z = -Lp[(size_t)i * m + j] * z;
+      Z[(size_t)j * m + i] = z;
+      nrm2 += z * z;
+    }
+    z = 1.0;
+    for (int i = r; i < m - 1; ++i) {
+      z = -Um[(size_t)i * m + j] * z;
+      Z[(size_t)j * m + i + 1] = z;
+      nrm2 += z * z;
+    }
+    // Rayleigh-quotient correction of lam (gamma_r / ||z||^2)
+    const double corr = gmin / nrm2;
+    if (!(fabs(corr) > 2.0 * 0x1.0p-53 * fabs(lam))) break;
+    lam += corr;
+  }
+  const double inv = 1.0 / sqrt(nrm2);
+  for (int i = 0; i < m; ++i) Z[(size_t)j * m + i] *= inv;
+  mu[j] = lam;
+}
+
+// ---------------------------------------------------------------------------
+// 5. Clusters (relative gap < 1e-3): Gram-Schmidt and Rayleigh-Ritz (one workgroup).
+// ---------------------------------------------------------------------------
+constexpr int kMaxCluster = 48;
+
+__global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict__ work,
+                                                      int *__restrict__ flag) {
+  EigLayout Lw(m);
+  const double *dg = work + Lw.d, *eg = work + Lw.e, *misc = work + Lw.misc;
+  double *mu = work + Lw.mu, *Z = work + Lw.Z;
+  double *W = work + Lw.scr;  // m x kMaxCluster
+  __shared__ double H[kMaxCluster][kMaxCluster + 1];
+  __shared__ double Vc[kMaxCluster][kMaxCluster + 1];
+  __shared__ double red[16];
+  __shared__ int cl_end;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double sigma = misc[3];
+  int a = 0;
+  while (a < m) {
+    if (tid == 0) {
+      int b = a;
+      while (b + 1 < m && b + 1 - a < kMaxCluster &&
+             fabs(mu[b + 1] - mu[b]) < 1e-3 * fmax(fabs(mu[b + 1]), fabs(mu[b])))
+        ++b;
+      cl_end = b;
+    }
+    __syncthreads();
+    const int b = cl_end;
+    __syncthreads();
+    const int c = b - a + 1;
+    if (c >= 2) {
+      // modified Gram-Schmidt, two passes; a collapsed vector is replaced by a probe
+      for (int q = 0; q < c; ++q) {
+        double *zq = Z + (size_t)(a + q) * m;
+        int replaced = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int pp = 0; pp < q; ++pp) {
+            const double *zp = Z + (size_t)(a + pp) * m;
+            double part = 0.0;
+            for (int i = tid; i < m; i += nt) part += zp[i] * zq[i];
+            const double dot = wsum(part, red);
+            for (int i = tid; i < m; i += nt) zq[i] -= dot * zp[i];
+            __syncthreads();
+          }
+          double part = 0.0;
+          for (int i = tid; i < m; i += nt) part += zq[i] * zq[i];
+          const double nn = sqrt(wsum(part, red));
+          if (nn < 1e-6 && pass == 0 && replaced < 2) {
+            ++replaced;
+            for (int i = tid; i < m; i += nt) {
+              unsigned h = (unsigned)(i * 2654435761u) ^ (unsigned)((a + q) * 40503u + 1u);
+              h ^= h >> 13;
+              h *= 0x5bd1e995u;
+              h ^= h >> 15;
+              zq[i] = ((double)(h & 0xffffu) / 65536.0) - 0.5;
+            }
+            __syncthreads();
+            pass = -1;  // orthogonalise the probe again from scratch
+            continue;
+          }
+          for (int i = tid; i < m; i += nt) zq[i] /= nn;
+          __syncthreads();
+        }
+      }
+      // W = T Z_c and H = Z_c^T T Z_c
+      for (int q = 0; q < c; ++q) {
+        const double *zq = Z + (size_t)(a + q) * m;
+        for (int i = tid; i < m; i += nt) {
+          double v = dg[i] * zq[i];
+          if (i > 0) v += eg[i - 1] * zq[i - 1];
+          if (i < m - 1) v += eg[i] * zq[i + 1];
+          W[(size_t)q * m + i] = v;
+        }
+      }
+      __syncthreads();
+      for (int pq = 0; pq < c * c; ++pq) {
+        const int p = pq % c, q = pq / c;
+        if (p > q) continue;
+        const double *zp = Z + (size_t)(a + p) * m;
+        double part = 0.0;
+        for (int i = tid; i < m; i += nt) part += zp[i] * W[(size_t)q * m + i];
+        const double v = wsum(part, red);
+        if (tid == 0) {
+          H[p][q] = v;
+          H[q][p] = v;
+        }
+      }
+      __syncthreads();
+      // cyclic Jacobi on H (c x c) by thread 0
+      if (tid == 0) {
+        for (int p = 0; p < c; ++p)
+          for (int q = 0; q < c; ++q) Vc[p][q] = (p == q) ? 1.0 : 0.0;
+        for (int sweep = 0; sweep < 30; ++sweep) {
+          double off = 0.0, dn = 0.0;
+          for (int p = 0; p < c; ++p)
+            for (int q = 0; q < c; ++q) (p == q ? dn : off) += H[p][q] * H[p][q];
+          if (off <= 1e-32 * dn) break;
+          for (int p = 0; p < c - 1; ++p)
+            for (int q = p + 1; q < c; ++q) {
+              if (H[p][q] == 0.0) continue;
+              const double th = (H[q][q] - H[p][p]) / (2.0 * H[p][q]);
+              const double t = copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
+              const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+              for (int k = 0; k < c; ++k) {
+                const double hp = H[k][p], hq = H[k][q];
+                H[k][p] = cs * hp - sn * hq;
+                H[k][q] = sn * hp + cs * hq;
+              }
+              for (int k = 0; k < c; ++k) {
+                const double hp = H[p][k], hq = H[q][k];
+                H[p][k] = cs * hp - sn * hq;
+                H[q][k] = sn * hp + cs * hq;
+              }
+              for (int k = 0; k < c; ++k) {
+                const double vp = Vc[k][p], vq = Vc[k][q];
+                Vc[k][p] = cs * vp - sn * vq;
+                Vc[k][q] = sn * vp + cs * vq;
+              }
+            }
+        }
+        // ascending order inside the cluster (selection sort of the diagonal)
+        for (int p = 0; p < c; ++p) {
+          int best = p;
+          for (int q = p + 1; q < c; ++q)
+            if (H[q][q] < H[best][best]) best = q;
+          if (best != p) {
+            const double t = H[p][p];
+            H[p][p] = H[best][best];
+            H[best][best] = t;
+            for (int k = 0; k < c; ++k) {
+              const double v = Vc[k][p];
+              Vc[k][p] = Vc[k][best];
+              Vc[k][best] = v;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // Z_c <- Z_c Vc (through W as temporary), eigenvalues of the cluster
+      for (int q = 0; q < c; ++q)
+        for (int i = tid; i < m; i += nt) {
+          double v = 0.0;
+          for (int p = 0; p < c; ++p) v += Z[(size_t)(a + p) * m + i] * Vc[p][q];
+          W[(size_t)q * m + i] = v;
+        }
+      __syncthreads();
+      for (int q = 0; q < c; ++q)
+        for (int i = tid; i < m; i += nt) Z[(size_t)(a + q) * m + i] = W[(size_t)q * m + i];
+      if (tid == 0)
+        for (int q = 0; q < c; ++q) mu[a + q] = H[q][q] - sigma;
+      __syncthreads();
+    }
+    a = b + 1;
+  }
+  (void)flag;
+}
+
+// ---------------------------------------------------------------------------
+// 6. Back-transformation Z <- H_0 ... H_{m-3} Z, eigenvalues lam = mu + sigma in
+//    descending order. One wave per column.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+    backtransform_kernel(int m, const double *__restrict__ work, double *__restrict__ lam,
+                         double *__restrict__ Vout) {
+  EigLayout Lw(m);
+  const double *Hv = work + Lw.Hv, *Z = work + Lw.Z, *mu = work + Lw.mu, *misc = work + Lw.misc;
+  const int lane = threadIdx.x & 63;
+  const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (col >= m) return;
+  constexpr int kMaxPer = 17;  // m <= 1088
+  double z[kMaxPer];
+#pragma unroll
+  for (int q = 0; q < kMaxPer; ++q) {
+    const int i = lane + 64 * q;
+    z[q] = (i < m) ? Z[(size_t)col * m + i] : 0.0;
+  }
+  double vc[kMaxPer], vn[kMaxPer];
+  if (m >= 3) {
+#pragma unroll
+    for (int q = 0; q < kMaxPer; ++q) {
+      const int i = lane + 64 * q;
+      vc[q] = (i < m) ? Hv[(size_t)(m - 3) * m + i] : 0.0;
+    }
+  }
+  for (int k = m - 3; k >= 0; --k) {
+    // load the next reflector before the dependent reduction of this one
+#pragma unroll
+    for (int q = 0; q < kMaxPer; ++q) {
+      const int i = lane + 64 * q;
+      vn[q] = (k > 0 && i < m) ? Hv[(size_t)(k - 1) * m + i] : 0.0;
+    }
+    double dot = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxPer; ++q) {
+      const int i = lane + 64 * q;
+      if (i > k && i < m) dot += vc[q] * z[q];
+    }
+    for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
+#pragma unroll
+    for (int q = 0; q < kMaxPer; ++q) {
+      const int i = lane + 64 * q;
+      if (i > k && i < m) z[q] -= 2.0 * dot * vc[q];
+      vc[q] = vn[q];
+    }
+  }
+  // ascending index col -> descending position m-1-col (ties keep a stable order)
+  const double lj = mu[col] + misc[3];
+  int rank = 0;
+  for (int i = lane; i < m; i += 64) {
+    const double li = mu[i] + misc[3];
+    rank += (li > lj || (li == lj && i > col)) ? 1 : 0;
+  }
+  for (int o = 32; o > 0; o >>= 1) rank += __shfl_xor(rank, o, 64);
+  if (lane == 0) lam[rank] = lj;
+#pragma unroll
+  for (int q = 0; q < kMaxPer; ++q) {
+    const int i = lane + 64 * q;
+    if (i < m) Vout[(size_t)rank * m + i] = z[q];
+  }
+}
+
+}  // namespace
+
+size_t eig_work_doubles(int m) { return EigLayout(m).total; }
+
+hipError_t launch_eig(int m, const double *K, double *lam, double *Z, double *work, int *flag,
+                      hipStream_t st) {
+  if (m < 1 || m > 1088) return hipErrorInvalidValue;
+  if (reg_fits(m))
+    hipLaunchKernelGGL(tridiag_reg_kernel, dim3(1), dim3(kRegThreads), (size_t)4 * m * sizeof(double),
+                       st, m, K, work);
+  else
+    hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kTriThreads),
+                       (size_t)(2 * m + kTriThreads) * sizeof(double), st, m, K, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(root_kernel, dim3(1), dim3(64), (size_t)4 * m * sizeof(double), st, m, work,
+                     flag);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(bisect_kernel, dim3((m + 3) / 4), dim3(256), (size_t)2 * m * sizeof(double), st,
+                     m, work);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(vector_kernel, dim3((m + 63) / 64), dim3(64), (size_t)3 * m * sizeof(double), st,
+                     m, work);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(cluster_kernel, dim3(1), dim3(256), 0, st, m, work, flag);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(backtransform_kernel, dim3((m + 3) / 4), dim3(256), 0, st, m, work, lam, Z);
+  return hipGetLastError();
+}
+
+}  // namespace riot

@@ -150,6 +150,387 @@ __device__ int wg_argmax_abs(double v, int idx, double *redv, int *redi, double 
 }
 
 // ---------------------------------------------------------------------------
+// 32 x 32 wave-level MFMA block product: acc += op(A)[0:32, 0:K] op(B)[0:K, 0:32],
+// op(A)[i][k] = TA ? A[k + i*lda] : A[i + k*lda], op(B)[k][j] = TB ? B[j + k*ldb] : B[k + j*ldb].
+// Rows >= mA and columns >= nB read as zero. The lane owning result register r
+// of tile (rt, ct) holds element (16 rt + l/16 + 4 r, 16 ct + l%16).
+// ---------------------------------------------------------------------------
+
+template <bool TA, bool TB>
+__device__ __forceinline__ void mma32_load(const double *__restrict__ A, int lda,
+                                           const double *__restrict__ B, int ldb, int K, int mA,
+                                           int nB, int k0, double (&av)[4][2], double (&bv)[4][2]) {
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lg = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int kk = k0 + 4 * s + lg;
+    const bool kin = kk < K;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int row = 16 * rt + li;
+      av[s][rt] = (kin && row < mA) ? (TA ? A[kk + (size_t)row * lda] : A[row + (size_t)kk * lda]) : 0.0;
+    }
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int col = 16 * ct + li;
+      bv[s][ct] = (kin && col < nB) ? (TB ? B[col + (size_t)kk * ldb] : B[kk + (size_t)col * ldb]) : 0.0;
+    }
+  }
+}
+
+// The contraction runs in chunks of 16 (four MFMA k-steps); the operands of the next
+// chunk are loaded before the current chunk's MFMAs are issued.
+template <bool TA, bool TB>
+__device__ __forceinline__ void wave_mma32(const double *__restrict__ A, int lda,
+                                           const double *__restrict__ B, int ldb, int K, int mA,
+                                           int nB, d4 (&acc)[2][2]) {
+  if (K <= 0) return;
+  double av[4][2], bv[4][2], an[4][2], bn[4][2];
+  mma32_load<TA, TB>(A, lda, B, ldb, K, mA, nB, 0, av, bv);
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const bool more = k0 + 16 < K;
+    if (more) mma32_load<TA, TB>(A, lda, B, ldb, K, mA, nB, k0 + 16, an, bn);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][rt], bv[s][ct], acc[rt][ct], 0, 0, 0);
+    if (more) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          av[s][t] = an[s][t];
+          bv[s][t] = bn[s][t];
+        }
+    }
+  }
+}
+
+__device__ __forceinline__ void zero_acc(d4 (&acc)[2][2]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+constexpr int kCholThreads = 512;
+constexpr int kPB = 32;  // panel width of the blocked factorizations
+constexpr int kStageRows = 320;  // panel rows staged in LDS by the Cholesky
+
+// ---------------------------------------------------------------------------
+// Blocked Cholesky G + s I = L L^T (lower, column-major), one workgroup.
+// mode 0: s = 0; mode 1: s = shift_rel ||G||_F; mode 2: s = 0, restarted with the
+// shift on breakdown. Per 32-column panel: the diagonal block is factored in LDS,
+// the panel below by row-wise forward substitution, the trailing lower triangle
+// updated with FP64 MFMA (one wave per 32 x 32 tile).
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kCholThreads)
+    chol_blocked_kernel(int m, const double *__restrict__ G, double *__restrict__ L,
+                        double shift_rel, int mode, int *__restrict__ flag,
+                        int *__restrict__ shifts) {
+  __shared__ double D[kPB][kPB + 1];
+  __shared__ double Dinv[kPB];
+  __shared__ double Pn[kPB * (kStageRows + 1)];
+  __shared__ double red[16];
+  __shared__ int bad;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int wave = tid >> 6, nwaves = nt >> 6;
+  double fro = 0.0;
+  if (mode != 0) {
+    double part = 0.0;
+    for (size_t idx = tid; idx < (size_t)m * m; idx += nt) part += G[idx] * G[idx];
+    fro = sqrt(wg_sum(part, red));
+  }
+  // mode 2: a pivot below the shift is replaced by the shift (modified Cholesky), so a
+  // nearly singular Gram matrix is factored in one pass instead of being restarted
+  const double floor_piv = (mode == 2) ? shift_rel * fro : 0.0;
+  __shared__ int modified;
+  if (tid == 0) modified = 0;
+  const int attempts = 1;
+  for (int att = 0; att < attempts; ++att) {
+    const bool shifted = (mode == 1);
+    const double s = shifted ? shift_rel * fro : 0.0;
+    if (shifted && tid == 0 && shifts) shifts[0] += 1;
+    for (size_t idx = tid; idx < (size_t)m * m; idx += nt) {
+      const int i = (int)(idx % m), j = (int)(idx / m);
+      L[idx] = (i >= j) ? (G[idx] + (i == j ? s : 0.0)) : 0.0;
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int kb = 0; kb < m && !bad; kb += kPB) {
+      const int nb = min(kPB, m - kb);
+      // 1. diagonal block in LDS, factored by wave 0 alone (no workgroup barriers inside)
+      for (int idx = tid; idx < nb * nb; idx += nt) {
+        const int i = idx % nb, j = idx / nb;
+        D[i][j] = (i >= j) ? L[(size_t)(kb + j) * m + kb + i] : 0.0;
+      }
+      __syncthreads();
+      if (wave == 0) {
+        // lane i keeps row i of the diagonal block in registers; column k is broadcast
+        // through LDS once per step (independent reads, no read-modify-write chains)
+        const int lane = tid & 63;
+        double r[kPB];
+#pragma unroll
+        for (int j = 0; j < kPB; ++j) r[j] = (lane < nb && j <= lane) ? D[lane][j] : 0.0;
+        bool fail = false;
+#pragma unroll
+        for (int k = 0; k < kPB; ++k) {
+          if (k < nb && !fail) {
+            double piv = __shfl(r[k], k, 64);
+            if (!isfinite(piv)) fail = true;
+            if (floor_piv > 0.0 && !(piv > floor_piv)) {
+              piv = floor_piv;
+              if (lane == 0) modified = 1;
+            }
+            if (!(piv > 0.0)) fail = true;
+            if (!fail) {
+              const double rkk = sqrt(piv), rinv = 1.0 / rkk;
+              if (lane > k) r[k] *= rinv;
+              if (lane == k) r[k] = rkk;
+              if (lane < nb) D[lane][k] = r[k];  // column k for the other lanes
+              asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+              if (lane > k && lane < nb) {
+                const double lik = r[k];
+#pragma unroll
+                for (int j = k + 1; j < kPB; ++j)
+                  if (j <= lane) r[j] -= lik * D[j][k];
+              }
+              asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            }
+          }
+        }
+        if (fail && lane == 0) bad = 1;
+        if (lane < nb) {
+#pragma unroll
+          for (int j = 0; j < kPB; ++j)
+            if (j <= lane) D[lane][j] = r[j];
+          Dinv[lane] = 1.0 / D[lane][lane];
+        }
+      }
+      __syncthreads();
+      if (bad) break;
+      for (int idx = tid; idx < nb * nb; idx += nt) {
+        const int i = idx % nb, j = idx / nb;
+        if (i >= j) L[(size_t)(kb + j) * m + kb + i] = D[i][j];
+      }
+      // 2. panel rows below: x L11^T = a  (forward substitution per row)
+      for (int i = kb + nb + tid; i < m; i += nt) {
+        // keep the LDS reads of the diagonal block inside the row loop (no hoisting)
+        asm volatile("" ::: "memory");
+        double x[kPB];
+#pragma unroll
+        for (int j = 0; j < kPB; ++j) {
+          if (j < nb) {
+            double a = L[(size_t)(kb + j) * m + i];
+#pragma unroll
+            for (int t = 0; t < j; ++t) a -= x[t] * D[j][t];
+            x[j] = a * Dinv[j];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kPB; ++j)
+          if (j < nb) L[(size_t)(kb + j) * m + i] = x[j];
+      }
+      __syncthreads();
+      // 3. trailing update A22 -= L21 L21^T on the lower 32 x 32 tiles; the panel
+      //    L21 is staged in LDS when it fits (MFMA operands then come from LDS)
+      const int r0 = kb + nb;
+      const int prow = m - r0;
+      const bool staged = prow <= kStageRows;
+      if (staged) {
+        for (int idx = tid; idx < prow * nb; idx += nt) {
+          const int i = idx % prow, j = idx / prow;
+          Pn[j * (kStageRows + 1) + i] = L[(size_t)(kb + j) * m + r0 + i];
+        }
+      }
+      __syncthreads();
+      const int nt32 = (prow + 31) / 32;
+      const int ntiles = nt32 * (nt32 + 1) / 2;
+      for (int t = wave; t < ntiles; t += nwaves) {
+        int I = 0, rem = t;
+        while (rem > I) {
+          rem -= I + 1;
+          ++I;
+        }
+        const int J = rem;  // tile (I, J) with J <= I
+        const int i0 = r0 + 32 * I, j0 = r0 + 32 * J;
+        d4 acc[2][2];
+        zero_acc(acc);
+        if (staged)
+          wave_mma32<false, true>(Pn + 32 * I, kStageRows + 1, Pn + 32 * J, kStageRows + 1, nb,
+                                  m - i0, m - j0, acc);
+        else
+          wave_mma32<false, true>(L + (size_t)kb * m + i0, m, L + (size_t)kb * m + j0, m, nb,
+                                  m - i0, m - j0, acc);
+        const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = i0 + 16 * rt + lg + 4 * r, col = j0 + 16 * ct + li;
+              if (row < m && col < m && row >= col) L[(size_t)col * m + row] -= acc[rt][ct][r];
+            }
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    if (!bad) {
+      if (tid == 0 && modified && shifts) shifts[0] += 1;
+      return;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) flag[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// X <- X L^{-T} for X (rows x m, leading dimension ldx) and lower-triangular L (m x m):
+// the right-hand triangular solve of CholeskyQR (Q = Y R^{-1} with R = L^T). One wave
+// per block of 32 rows; per 32-column block jb the wave forms
+// B = X[:, jb] - Q[:, <jb] L[jb, <jb]^T with FP64 MFMA, then solves B = Q_jb L_jb^T
+// row by row in LDS. Rows are independent, so X is overwritten in place.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64)
+    trsm_rlt_kernel(int rows, int m, double *__restrict__ X, int ldx, const double *__restrict__ L) {
+  __shared__ double B[32][33];
+  __shared__ double Ld[32][33];
+  const int lane = threadIdx.x, li = lane & 15, lg = lane >> 4;
+  const int r0 = blockIdx.x * 32;
+  const int nr = min(32, rows - r0);
+  for (int jb = 0; jb * 32 < m; ++jb) {
+    const int c0 = jb * 32, nc = min(32, m - c0);
+    d4 acc[2][2];
+    zero_acc(acc);
+    if (c0 > 0)  // Q[:, 0:c0] L[c0:c0+32, 0:c0]^T
+      wave_mma32<false, true>(X + r0 + (size_t)0 * ldx, ldx, L + c0, m, c0, nr, nc, acc);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * rt + lg + 4 * r, col = 16 * ct + li;
+          double v = 0.0;
+          if (row < nr && col < nc) v = X[(size_t)(c0 + col) * ldx + r0 + row] - acc[rt][ct][r];
+          B[row][col] = v;
+        }
+    for (int idx = lane; idx < 32 * 32; idx += 64) {
+      const int i = idx & 31, j = idx >> 5;
+      Ld[i][j] = (i < nc && j < nc && i >= j) ? L[(size_t)(c0 + j) * m + c0 + i] : 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // lane = row: q L_jb^T = b  ->  q_j = (b_j - sum_{t<j} q_t L[j][t]) / L[j][j]
+    if (lane < nr) {
+      double q[32];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        if (j < nc) {
+          double a = B[lane][j];
+#pragma unroll
+          for (int t = 0; t < j; ++t) a -= q[t] * Ld[j][t];
+          q[j] = a / Ld[j][j];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 32; ++j)
+        if (j < nc) X[(size_t)(c0 + j) * ldx + r0 + lane] = q[j];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Blocked inverse of a lower-triangular L (column-major): X = L^{-1}.
+// Diagonal 32 x 32 blocks are inverted by substitution in LDS; then, block row
+// by block row, X_ij = -X_ii (sum_{k=j}^{i-1} L_ik X_kj) with FP64 MFMA.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kCholThreads)
+    trinv_lower_blocked_kernel(int m, const double *__restrict__ L, double *__restrict__ X) {
+  __shared__ double S[kCholThreads / 64][kPB][kPB + 1];  // per-wave staging of one 32 x 32 block
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int wave = tid >> 6, nwaves = nt >> 6, lane = tid & 63;
+  const int nbk = (m + kPB - 1) / kPB;
+  for (size_t idx = tid; idx < (size_t)m * m; idx += nt) X[idx] = 0.0;
+  __syncthreads();
+  // diagonal blocks: staged in LDS; lane c of a half-wave solves column c of L_ii x = e_c
+  for (int b0 = wave * 2; b0 < nbk; b0 += 2 * nwaves) {
+    const int half = lane >> 5, c = lane & 31;
+    const int b = b0 + half;
+    if (b < nbk) {
+      const int k0 = b * kPB, nb = min(kPB, m - k0);
+      if (c < nb) {
+        double x[kPB];
+#pragma unroll
+        for (int i = 0; i < kPB; ++i) {
+          if (i < nb) {
+            double a = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int t = 0; t < i; ++t) a -= L[(size_t)(k0 + t) * m + k0 + i] * x[t];
+            x[i] = (i < c) ? 0.0 : a / L[(size_t)(k0 + i) * m + k0 + i];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < kPB; ++i)
+          if (i < nb && i >= c) X[(size_t)(k0 + c) * m + k0 + i] = x[i];
+      }
+    }
+  }
+  __syncthreads();
+  const int li = lane & 15, lg = lane >> 4;
+  for (int bi = 1; bi < nbk; ++bi) {
+    const int i0 = bi * kPB, ni = min(kPB, m - i0);
+    for (int bj = wave; bj < bi; bj += nwaves) {
+      const int j0 = bj * kPB;
+      d4 acc[2][2];
+      zero_acc(acc);
+      // T = sum_{k=j}^{i-1} L_ik X_kj  (rows i0.., cols j0.., K over rows j0..i0-1)
+      wave_mma32<false, false>(L + (size_t)j0 * m + i0, m, X + (size_t)j0 * m + j0, m, i0 - j0, ni,
+                               kPB, acc);
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) S[wave][16 * rt + lg + 4 * r][16 * ct + li] = acc[rt][ct][r];
+      // the block is re-read by other lanes of the same wave
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // X_ij = -X_ii T : X_ii from global, T from LDS (row-major, stride kPB + 1)
+      zero_acc(acc);
+      wave_mma32<false, true>(X + (size_t)i0 * m + i0, m, &S[wave][0][0], kPB + 1, ni, ni, kPB,
+                              acc);
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = i0 + 16 * rt + lg + 4 * r, col = j0 + 16 * ct + li;
+            if (row < m && col < m) X[(size_t)col * m + row] = -acc[rt][ct][r];
+          }
+      // S[wave] is rewritten by this wave's next block
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Cholesky: G + s I = R^T R, R upper triangular (right-looking).
 // ---------------------------------------------------------------------------
 
@@ -306,26 +687,43 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
-__global__ void __launch_bounds__(1024) symmetrize_kernel(int m, double *__restrict__ K,
-                                                          double *__restrict__ asym) {
+// K <- (K + K^T)/2 over the strict lower triangle, many workgroups; per-block partial
+// sums of ||K - K^T||^2 and ||K||^2 are reduced by symmetrize_norm_kernel in fixed order.
+__global__ void __launch_bounds__(256) symmetrize_kernel(int m, double *__restrict__ K,
+                                                         double *__restrict__ part) {
   __shared__ double red[16];
+  const size_t tot = (size_t)m * m;
   double pa = 0.0, pk = 0.0;
-  for (size_t idx = threadIdx.x; idx < (size_t)m * m; idx += blockDim.x) {
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(idx % m), j = (int)(idx / m);
-    const double a = K[idx], b = K[(size_t)i * m + j];
-    pa += (a - b) * (a - b);
+    const double a = K[idx];
     pk += a * a;
-  }
-  const double sa = wg_sum(pa, red), sk = wg_sum(pk, red);
-  for (size_t idx = threadIdx.x; idx < (size_t)m * m; idx += blockDim.x) {
-    const int i = (int)(idx % m), j = (int)(idx / m);
-    if (i < j) {
-      const double v = 0.5 * (K[idx] + K[(size_t)i * m + j]);
+    if (i > j) {
+      const double b = K[(size_t)i * m + j];
+      pa += 2.0 * (a - b) * (a - b);
+      const double v = 0.5 * (a + b);
       K[idx] = v;
       K[(size_t)i * m + j] = v;
     }
   }
-  if (threadIdx.x == 0) asym[0] = sk > 0.0 ? sqrt(sa / sk) : 0.0;
+  const double sa = wg_sum(pa, red);
+  const double sk = wg_sum(pk, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sa;
+    part[2 * blockIdx.x + 1] = sk;
+  }
+}
+
+__global__ void symmetrize_norm_kernel(int nblk, const double *__restrict__ part,
+                                       double *__restrict__ asym) {
+  if (threadIdx.x != 0) return;
+  double sa = 0.0, sk = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    sa += part[2 * b];
+    sk += part[2 * b + 1];
+  }
+  asym[0] = sk > 0.0 ? sqrt(sa / sk) : 0.0;
 }
 
 __global__ void __launch_bounds__(1024) orth_err_kernel(int m, const double *__restrict__ G,
@@ -738,6 +1136,24 @@ hipError_t launch_cholesky(int m, const double *G, double *R, double shift_rel, 
   return hipGetLastError();
 }
 
+hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_rel, int mode,
+                               int *flag, int *shifts, hipStream_t st) {
+  hipLaunchKernelGGL(chol_blocked_kernel, dim3(1), dim3(kCholThreads), 0, st, m, G, L, shift_rel,
+                     mode, flag, shifts);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_rlt(int rows, int m, double *X, int ldx, const double *L, hipStream_t st) {
+  if (rows <= 0 || m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(trsm_rlt_kernel, dim3((rows + 31) / 32), dim3(64), 0, st, rows, m, X, ldx, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_trinv_lower(int m, const double *L, double *X, hipStream_t st) {
+  hipLaunchKernelGGL(trinv_lower_blocked_kernel, dim3(1), dim3(kCholThreads), 0, st, m, L, X);
+  return hipGetLastError();
+}
+
 hipError_t launch_trinv_upper(int m, const double *R, double *Rinv, hipStream_t st) {
   hipLaunchKernelGGL(trinv_upper_kernel, dim3(1), dim3(1024), (size_t)m * sizeof(double), st, m, R,
                      Rinv);
@@ -751,8 +1167,12 @@ hipError_t launch_gj_inverse(int m, const double *M, double *Minv, double *work,
   return hipGetLastError();
 }
 
-hipError_t launch_symmetrize(int m, double *K, double *asym, hipStream_t st) {
-  hipLaunchKernelGGL(symmetrize_kernel, dim3(1), dim3(1024), 0, st, m, K, asym);
+hipError_t launch_symmetrize(int m, double *K, double *asym, double *part, hipStream_t st) {
+  const int nblk = 64;
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(nblk), dim3(256), 0, st, m, K, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(symmetrize_norm_kernel, dim3(1), dim3(64), 0, st, nblk, part, asym);
   return hipGetLastError();
 }
 

@@ -182,7 +182,7 @@ size_t carve(riot_handle &h, void *base) {
   h.K = c.take<double>(m2);
   h.Zs = c.take<double>(m2);
   h.gjw = c.take<double>(2 * m2);
-  h.sywork = c.take<double>(syev_work_doubles(mm));
+  h.sywork = c.take<double>(eig_work_doubles(mm));
   h.partial = c.take<double>(std::max((size_t)kSplitK * m2, (size_t)kSplitK * mm));
   h.cvec = c.take<double>(mm);
   h.scal = c.take<double>(16);
@@ -247,26 +247,27 @@ riot_status read_flag(riot_handle *h, int idx, int *out) {
   return RIOT_OK;
 }
 
-// Q = orth(Yin) by CholeskyQR: one shifted pass followed by two plain passes
-// (shifted CholeskyQR3); with shift == false the shifted pass is skipped.
-riot_status cholqr(riot_handle *h, int m, const double *Yin, double *Qout, bool shifted,
-                   int flag_idx) {
-  const int n = h->d.n;
+// Q = orth(Xin) (rows x m, leading dimension rows) by CholeskyQR: the first pass
+// shifted when `shifted` (shifted CholeskyQR3), every later pass plain with a
+// device-side fallback to the shift on breakdown. Each pass computes G = X^T X,
+// G (+ s I) = L L^T and X <- X L^{-T}; a companion C (mc x m, ld mc) receives the same
+// right factors, C <- C L^{-T}, so that X_in M = Q and C_in M = C_out for one M.
+riot_status cholqr(riot_handle *h, int rows, int m, const double *Xin, double *Qout, bool shifted,
+                   int flag_idx, double *comp = nullptr, int mc = 0) {
   hipStream_t st = h->st;
   const double u = 0x1.0p-53;
-  const double srel = 11.0 * ((double)m * n + (double)m * (m + 1)) * u;
+  const double srel = 11.0 * ((double)m * rows + (double)m * (m + 1)) * u;
   const int passes = shifted ? 3 : 2;
-  const double *src = Yin;
+  if (Qout != Xin)
+    RIOT_HIP(hipMemcpyAsync(Qout, Xin, (size_t)rows * m * sizeof(double), hipMemcpyDeviceToDevice,
+                            st));
   for (int pass = 0; pass < passes; ++pass) {
-    RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, src, n, src, n, 0.0, h->G, m, h->partial, kSplitK, st));
-    // first pass shifted (shifted CholeskyQR3); later passes fall back to the shift on breakdown
-    RIOT_HIP(launch_cholesky(m, h->G, h->R, srel, (shifted && pass == 0) ? 1 : 2,
-                             h->flags + flag_idx, h->flags + 4, st));
-    RIOT_HIP(launch_trinv_upper(m, h->R, h->Rinv, st));
-    // alternate buffers so that the last pass lands in Qout
-    double *dst = ((passes - 1 - pass) % 2 == 0) ? Qout : h->Qt;
-    RIOT_HIP(gemm_f64(0, 0, n, m, m, 1.0, src, n, h->Rinv, m, 0.0, dst, n, nullptr, 1, st));
-    src = dst;
+    RIOT_HIP(gemm_f64(1, 0, m, m, rows, 1.0, Qout, rows, Qout, rows, 0.0, h->G, m, h->partial,
+                      kSplitK, st));
+    RIOT_HIP(launch_chol_blocked(m, h->G, h->R, srel, (shifted && pass == 0) ? 1 : 2,
+                                 h->flags + flag_idx, h->flags + 4, st));
+    RIOT_HIP(launch_trsm_rlt(rows, m, Qout, rows, h->R, st));
+    if (comp) RIOT_HIP(launch_trsm_rlt(mc, m, comp, mc, h->R, st));
   }
   return RIOT_OK;
 }
@@ -428,21 +429,23 @@ riot_status riot_rsvd(riot_handle *h, int32_t k, int32_t p_os, int32_t q, const 
   if (rs != RIOT_OK) return rs;
   const double *Om_eff = Om;
   for (int it = 0; it < q; ++it) {
-    rs = cholqr(h, m, h->Y, h->Q0, true, 0);
+    rs = cholqr(h, n, m, h->Y, h->Q0, true, 0);
     if (rs != RIOT_OK) return rs;
     rs = hess_apply_impl(h, m, h->Q0, h->Y, 0);
     if (rs != RIOT_OK) return rs;
     Om_eff = h->Q0;
   }
-  rs = cholqr(h, m, h->Y, h->Q, true, 0);
+  rs = cholqr(h, n, m, h->Y, h->Q, true, 0);
   if (rs != RIOT_OK) return rs;
-  // B1 = Q^T Y, B2 = Q^T Omega_eff, K = B1 B2^{-1}
+  // B1 = Q^T Y, B2 = Q^T Omega_eff. K solves K B2 = B1: with B2 M = Q2 orthogonal (CholeskyQR
+  // of the square B2 carrying B1 as companion, B1 M -> B1'), B2^{-1} = M Q2^T and K = B1' Q2^T.
   RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, h->Q, n, h->Y, n, 0.0, h->B1, m, h->partial, kSplitK, st));
   RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, h->Q, n, Om_eff, n, 0.0, h->B2, m, h->partial, kSplitK, st));
-  RIOT_HIP(launch_gj_inverse(m, h->B2, h->B2i, h->gjw, h->flags + 1, st));
-  RIOT_HIP(gemm_f64(0, 0, m, m, m, 1.0, h->B1, m, h->B2i, m, 0.0, h->K, m, nullptr, 1, st));
-  RIOT_HIP(launch_symmetrize(m, h->K, h->scal + 1, st));
-  RIOT_HIP(launch_syev(m, h->K, lambda, h->Zs, h->sywork, h->flags + 2, st));
+  rs = cholqr(h, m, m, h->B2, h->Zs, false, 1, h->B1, m);
+  if (rs != RIOT_OK) return rs;
+  RIOT_HIP(gemm_f64(0, 1, m, m, m, 1.0, h->B1, m, h->Zs, m, 0.0, h->K, m, nullptr, 1, st));
+  RIOT_HIP(launch_symmetrize(m, h->K, h->scal + 1, h->partial, st));
+  RIOT_HIP(launch_eig(m, h->K, lambda, h->Zs, h->sywork, h->flags + 2, st));
   RIOT_HIP(gemm_f64(0, 0, n, m, m, 1.0, h->Q, n, h->Zs, m, 0.0, V, n, nullptr, 1, st));
   RIOT_HIP(launch_check_finite(m, lambda, h->flags + 3, st));
   RIOT_HIP(launch_check_finite((long long)n * m, V, h->flags + 3, st));

@@ -96,6 +96,16 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
 hipError_t launch_cholesky(int m, const double *G, double *R, double shift_rel, int mode,
                            int *flag, int *shifts, hipStream_t st);
 
+// Blocked Cholesky G + s I = L L^T (lower), same modes as launch_cholesky.
+hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_rel, int mode,
+                               int *flag, int *shifts, hipStream_t st);
+
+// X <- X L^{-T} in place (X rows x m, leading dimension ldx; L lower m x m).
+hipError_t launch_trsm_rlt(int rows, int m, double *X, int ldx, const double *L, hipStream_t st);
+
+// Blocked inverse of a lower-triangular L.
+hipError_t launch_trinv_lower(int m, const double *L, double *X, hipStream_t st);
+
 // Inverse of upper-triangular R (m x m).
 hipError_t launch_trinv_upper(int m, const double *R, double *Rinv, hipStream_t st);
 
@@ -105,7 +115,8 @@ hipError_t launch_gj_inverse(int m, const double *M, double *Minv, double *work,
                              hipStream_t st);
 
 // K <- (K + K^T)/2 and asym[0] = ||K - K^T||_F / ||K||_F (before symmetrisation).
-hipError_t launch_symmetrize(int m, double *K, double *asym, hipStream_t st);
+// part: 128 doubles of scratch.
+hipError_t launch_symmetrize(int m, double *K, double *asym, double *part, hipStream_t st);
 
 // ||Q^T Q - I||_F from the Gram matrix G = Q^T Q -> out[0].
 hipError_t launch_orth_err(int m, const double *G, double *out, hipStream_t st);
@@ -115,6 +126,13 @@ hipError_t launch_orth_err(int m, const double *G, double *out, hipStream_t st);
 size_t syev_work_doubles(int m);
 hipError_t launch_syev(int m, const double *K, double *lam, double *Z, double *work, int *flag,
                        hipStream_t st);
+
+// Symmetric eigendecomposition (eig.hip): tridiagonalisation, relatively robust
+// representation, multisection bisection, twisted-factorisation vectors, cluster
+// Rayleigh-Ritz, back-transformation. Eigenvalues descending. flag[0] = 1 on failure.
+size_t eig_work_doubles(int m);
+hipError_t launch_eig(int m, const double *K, double *lam, double *Z, double *work, int *flag,
+                      hipStream_t st);
 
 // Increment helpers: c = V^T g handled by gemm_f64; these combine.
 // dz = -(V (c .* a)) [lra] or dz = -(g - V (c .* a)) [lru], a = coefficient per pair.

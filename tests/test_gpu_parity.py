@@ -222,3 +222,27 @@ def test_argument_errors(c1):
         r.hess_apply(np.zeros((p.n, 5)))  # more columns than m_max
     with pytest.raises(RiotError):
         r.rsvd(4, 1)
+
+
+def test_rsvd_degenerate_spectrum_closed_form():
+    # Rest state, every variable observed, R = r I: A is circulant with 2-fold degenerate
+    # eigenvalues l_w^2 sum_s |R(h mu_w)|^{2 s} / r. Full-rank RSVD must return them and an
+    # orthonormal eigenbasis even inside the degenerate pairs.
+    n, T, h, F, r = 24, 8, 0.05, 8.0, 0.5
+    taps = bcov.gaussian_taps(2.0, 0.7)
+    steps = [0, 3, 8]
+    obs_step = np.repeat(np.array(steps, dtype=np.int32), n)
+    obs_idx = np.tile(np.arange(n, dtype=np.int32), len(steps))
+    p = fourdvar.Problem(n, T, h, F, obs_step, obs_idx, np.full(obs_step.size, F),
+                         np.full(obs_step.size, 1.0 / r), np.full(n, F), taps)
+    om = 2 * np.pi * np.arange(n) / n
+    mu = F * (np.exp(1j * om) - np.exp(-2j * om)) - 1.0
+    R4 = 1 + h * mu + (h * mu) ** 2 / 2 + (h * mu) ** 3 / 6 + (h * mu) ** 4 / 24
+    lw = taps[0] + 2 * sum(taps[d] * np.cos(om * d) for d in range(1, taps.size))
+    expect = np.sort(lw * lw * sum(np.abs(R4) ** (2 * s) for s in steps) / r)[::-1]
+    g = riot_for(p, m_max=n)
+    g.linearize(p.xb)
+    lam, V, info = g.rsvd(n - 4, 4, q=0, Omega=probe_block(4, 0, n, n))
+    lam, V = to_np(lam), to_np(V)
+    assert np.max(np.abs(lam - expect)) <= 1e-9 * expect[0]
+    assert np.max(np.abs(V.T @ V - np.eye(n))) < 1e-11

@@ -81,13 +81,15 @@ typedef struct {
     int32_t m_max;             /* largest probe block used with this handle, >= 1 */
     riot_precision prec;       /* precision of the TL/AD integrations */
     int32_t elems_per_lane;    /* 0 = choose automatically, else 1, 2, 4, 8 or 16
-                                  (n must be divisible by it and n / it <= 1024) */
+                                  (n must be divisible by it; n / it <= 512 for 8 and 16,
+                                  <= 1024 otherwise) */
 } riot_desc;
 
 /* Diagnostics of one randomized eigendecomposition (host struct). */
 typedef struct {
-    int32_t chol_shifts;       /* CholeskyQR passes that needed the shifted form */
-    int32_t qr_passes;         /* CholeskyQR passes applied to the final block */
+    int32_t chol_shifts;       /* Cholesky factorisations that were shifted or had a pivot
+                                  replaced, over the whole call */
+    int32_t qr_passes;         /* CholeskyQR passes applied to the final block Y */
     double k_asym;             /* ||K - K^T||_F / ||K||_F before symmetrisation */
     double orth_err;           /* ||Q^T Q - I||_F after the last pass */
 } riot_rsvd_info;
@@ -131,9 +133,11 @@ riot_status riot_hess_apply(riot_handle *h, int32_t m, const double *W, double *
  * m = k + p_os probes, 1 <= m <= min(m_max, n). Omega [n x m] device or NULL: NULL draws
  * N(0,1) probes with Philox4x32-10 keyed by `seed` (stream 0). q >= 0 power steps:
  * Q0 = orth(Y), Omega_eff = Q0, Y = A Q0 (Halko et al. subspace iteration).
- * Then Q = orth(Y) by CholeskyQR2 (shifted CholeskyQR3 when the Gram matrix is not
- * numerically positive definite), K solves K (Q^T Omega_eff) = Q^T Y, K <- (K + K^T)/2,
- * K = Z diag(lambda) Z^T, V = Q Z.
+ * Then Q = orth(Y) by CholeskyQR: a shifted first pass, then passes that replace pivots
+ * below the shift, repeated on the device until two consecutive passes replace none (at
+ * most 8), so that graded or numerically rank-deficient sketches still give an orthonormal
+ * Q. K solves K (Q^T Omega_eff) = Q^T Y through the same adaptive CholeskyQR of
+ * Q^T Omega_eff carrying Q^T Y, K <- (K + K^T)/2, K = Z diag(lambda) Z^T, V = Q Z.
  *   lambda [m]     device out, Ritz values in descending order
  *   V      [n x m] device out, Ritz vectors
  *   info           host out or NULL (synchronises)

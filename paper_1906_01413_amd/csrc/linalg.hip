@@ -27,7 +27,9 @@ template <int TA, int TB>
 __global__ void __launch_bounds__(64)
     gemm_mfma_kernel(int M, int N, int K, const double *__restrict__ A, int lda,
                      const double *__restrict__ B, int ldb, double *__restrict__ C, int ldc,
-                     double alpha, double beta, int kchunk, double *__restrict__ partial) {
+                     double alpha, double beta, int kchunk, double *__restrict__ partial,
+                     const int *__restrict__ run) {
+  if (run && run[0] == 0) return;  // predicated launch: the whole grid skips uniformly
   const int lane = threadIdx.x;
   const int li = lane & 15, lg = lane >> 4;
   const int m0 = blockIdx.x * 32, n0 = blockIdx.y * 32;
@@ -87,7 +89,9 @@ __global__ void __launch_bounds__(64)
 }
 
 __global__ void splitk_reduce_kernel(int M, int N, int splits, const double *__restrict__ partial,
-                                     double alpha, double beta, double *__restrict__ C, int ldc) {
+                                     double alpha, double beta, double *__restrict__ C, int ldc,
+                                     const int *__restrict__ run) {
+  if (run && run[0] == 0) return;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t MN = (size_t)M * N;
   if (idx >= MN) return;
@@ -232,7 +236,9 @@ constexpr int kStageRows = 320;  // panel rows staged in LDS by the Cholesky
 __global__ void __launch_bounds__(kCholThreads)
     chol_blocked_kernel(int m, const double *__restrict__ G, double *__restrict__ L,
                         double shift_rel, int mode, int *__restrict__ flag,
-                        int *__restrict__ shifts) {
+                        int *__restrict__ shifts, const int *__restrict__ run,
+                        int *__restrict__ modflag) {
+  if (run && run[0] == 0) return;
   __shared__ double D[kPB][kPB + 1];
   __shared__ double Dinv[kPB];
   __shared__ double Pn[kPB * (kStageRows + 1)];
@@ -383,6 +389,7 @@ __global__ void __launch_bounds__(kCholThreads)
     __syncthreads();
     if (!bad) {
       if (tid == 0 && modified && shifts) shifts[0] += 1;
+      if (tid == 0 && modified && modflag) modflag[0] = 1;
       return;
     }
     __syncthreads();
@@ -398,7 +405,9 @@ __global__ void __launch_bounds__(kCholThreads)
 // row by row in LDS. Rows are independent, so X is overwritten in place.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(64)
-    trsm_rlt_kernel(int rows, int m, double *__restrict__ X, int ldx, const double *__restrict__ L) {
+    trsm_rlt_kernel(int rows, int m, double *__restrict__ X, int ldx, const double *__restrict__ L,
+                    const int *__restrict__ run) {
+  if (run && run[0] == 0) return;
   __shared__ double B[32][33];
   __shared__ double Ld[32][33];
   const int lane = threadIdx.x, li = lane & 15, lg = lane >> 4;
@@ -1096,7 +1105,7 @@ __global__ void check_finite_kernel(long long count, const double *__restrict__ 
 
 hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const double *A, int lda,
                     const double *B, int ldb, double beta, double *C, int ldc, double *partial,
-                    int splitk, hipStream_t st) {
+                    int splitk, hipStream_t st, const int *run) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (K <= 0) splitk = 1;
   if (splitk < 1 || !partial) splitk = 1;
@@ -1108,7 +1117,7 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   double *part = splits > 1 ? partial : nullptr;
 #define RIOT_GEMM(TA_, TB_)                                                                  \
   hipLaunchKernelGGL((gemm_mfma_kernel<TA_, TB_>), grid, dim3(64), 0, st, M, N, K, A, lda, B, \
-                     ldb, C, ldc, alpha, beta, kchunk, part)
+                     ldb, C, ldc, alpha, beta, kchunk, part, run)
   if (ta == 0 && tb == 0)
     RIOT_GEMM(0, 0);
   else if (ta == 1 && tb == 0)
@@ -1123,7 +1132,7 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   if (splits > 1) {
     const size_t MN = (size_t)M * N;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st,
-                       M, N, splits, partial, alpha, beta, C, ldc);
+                       M, N, splits, partial, alpha, beta, C, ldc, run);
     e = hipGetLastError();
   }
   return e;
@@ -1137,15 +1146,51 @@ hipError_t launch_cholesky(int m, const double *G, double *R, double shift_rel, 
 }
 
 hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_rel, int mode,
-                               int *flag, int *shifts, hipStream_t st) {
+                               int *flag, int *shifts, hipStream_t st, const int *run,
+                               int *modflag) {
   hipLaunchKernelGGL(chol_blocked_kernel, dim3(1), dim3(kCholThreads), 0, st, m, G, L, shift_rel,
-                     mode, flag, shifts);
+                     mode, flag, shifts, run, modflag);
   return hipGetLastError();
 }
 
-hipError_t launch_trsm_rlt(int rows, int m, double *X, int ldx, const double *L, hipStream_t st) {
+hipError_t launch_trsm_rlt(int rows, int m, double *X, int ldx, const double *L, hipStream_t st,
+                           const int *run) {
   if (rows <= 0 || m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(trsm_rlt_kernel, dim3((rows + 31) / 32), dim3(64), 0, st, rows, m, X, ldx, L);
+  hipLaunchKernelGGL(trsm_rlt_kernel, dim3((rows + 31) / 32), dim3(64), 0, st, rows, m, X, ldx, L,
+                     run);
+  return hipGetLastError();
+}
+
+// CholeskyQR pass control, one thread. cq[0]: further passes run; cq[1]: consecutive
+// clean passes (plain Cholesky, no pivot replaced); cq[2]: a pivot was replaced in the
+// pass just finished. Two clean passes in a row leave the block orthonormal to rounding.
+__global__ void cholqr_ctrl_kernel(int *cq, int pass_was_shifted, int *count) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (cq[0] == 0) return;
+  if (count) count[0] += 1;
+  if (pass_was_shifted || cq[2])
+    cq[1] = 0;
+  else
+    cq[1] += 1;
+  cq[2] = 0;
+  if (cq[1] >= 2) cq[0] = 0;
+}
+
+__global__ void cholqr_reset_kernel(int *cq) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    cq[0] = 1;
+    cq[1] = 0;
+    cq[2] = 0;
+  }
+}
+
+hipError_t launch_cholqr_reset(int *cq, hipStream_t st) {
+  hipLaunchKernelGGL(cholqr_reset_kernel, dim3(1), dim3(64), 0, st, cq);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholqr_ctrl(int *cq, int pass_was_shifted, int *count, hipStream_t st) {
+  hipLaunchKernelGGL(cholqr_ctrl_kernel, dim3(1), dim3(64), 0, st, cq, pass_was_shifted, count);
   return hipGetLastError();
 }
 

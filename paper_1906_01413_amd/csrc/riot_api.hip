@@ -247,27 +247,37 @@ riot_status read_flag(riot_handle *h, int idx, int *out) {
   return RIOT_OK;
 }
 
-// Q = orth(Xin) (rows x m, leading dimension rows) by CholeskyQR: the first pass
-// shifted when `shifted` (shifted CholeskyQR3), every later pass plain with a
-// device-side fallback to the shift on breakdown. Each pass computes G = X^T X,
-// G (+ s I) = L L^T and X <- X L^{-T}; a companion C (mc x m, ld mc) receives the same
-// right factors, C <- C L^{-T}, so that X_in M = Q and C_in M = C_out for one M.
+// Q = orth(Xin) (rows x m, leading dimension rows) by CholeskyQR. Each pass computes
+// G = X^T X, G (+ s I) = L L^T and X <- X L^{-T}; a companion C (mc x m, ld mc) receives
+// the same right factors, C <- C L^{-T}, so that X_in M = Q and C_in M = C_out for one M.
+// The first pass is shifted when `shifted` (s = 11 (m rows + m (m+1)) u ||G||_F, which
+// never breaks down); later passes replace any pivot below that shift by it. Passes repeat
+// on the device until two in a row are plain with no pivot replaced, which leaves Q
+// orthonormal to rounding, at most kMaxCholQRPasses: a sketch whose singular values span
+// more than the FP64 range of one shifted pass (graded spectra, numerically rank-deficient
+// blocks) gets further passes instead of a non-orthonormal Q. Passes beyond the last
+// needed one are launched but return at once (device flag), so nothing synchronises.
+constexpr int kMaxCholQRPasses = 8;
+
 riot_status cholqr(riot_handle *h, int rows, int m, const double *Xin, double *Qout, bool shifted,
-                   int flag_idx, double *comp = nullptr, int mc = 0) {
+                   int flag_idx, double *comp = nullptr, int mc = 0, int *count = nullptr) {
   hipStream_t st = h->st;
   const double u = 0x1.0p-53;
   const double srel = 11.0 * ((double)m * rows + (double)m * (m + 1)) * u;
-  const int passes = shifted ? 3 : 2;
+  int *cq = h->flags + 12;
   if (Qout != Xin)
     RIOT_HIP(hipMemcpyAsync(Qout, Xin, (size_t)rows * m * sizeof(double), hipMemcpyDeviceToDevice,
                             st));
-  for (int pass = 0; pass < passes; ++pass) {
+  RIOT_HIP(launch_cholqr_reset(cq, st));
+  for (int pass = 0; pass < kMaxCholQRPasses; ++pass) {
+    const bool sh = shifted && pass == 0;
     RIOT_HIP(gemm_f64(1, 0, m, m, rows, 1.0, Qout, rows, Qout, rows, 0.0, h->G, m, h->partial,
-                      kSplitK, st));
-    RIOT_HIP(launch_chol_blocked(m, h->G, h->R, srel, (shifted && pass == 0) ? 1 : 2,
-                                 h->flags + flag_idx, h->flags + 4, st));
-    RIOT_HIP(launch_trsm_rlt(rows, m, Qout, rows, h->R, st));
-    if (comp) RIOT_HIP(launch_trsm_rlt(mc, m, comp, mc, h->R, st));
+                      kSplitK, st, cq));
+    RIOT_HIP(launch_chol_blocked(m, h->G, h->R, srel, sh ? 1 : 2, h->flags + flag_idx,
+                                 h->flags + 4, st, cq, cq + 2));
+    RIOT_HIP(launch_trsm_rlt(rows, m, Qout, rows, h->R, st, cq));
+    if (comp) RIOT_HIP(launch_trsm_rlt(mc, m, comp, mc, h->R, st, cq));
+    RIOT_HIP(launch_cholqr_ctrl(cq, sh ? 1 : 0, count, st));
   }
   return RIOT_OK;
 }
@@ -435,7 +445,7 @@ riot_status riot_rsvd(riot_handle *h, int32_t k, int32_t p_os, int32_t q, const 
     if (rs != RIOT_OK) return rs;
     Om_eff = h->Q0;
   }
-  rs = cholqr(h, n, m, h->Y, h->Q, true, 0);
+  rs = cholqr(h, n, m, h->Y, h->Q, true, 0, nullptr, 0, h->flags + 5);
   if (rs != RIOT_OK) return rs;
   // B1 = Q^T Y, B2 = Q^T Omega_eff. K solves K B2 = B1: with B2 M = Q2 orthogonal (CholeskyQR
   // of the square B2 carrying B1 as companion, B1 M -> B1'), B2^{-1} = M Q2^T and K = B1' Q2^T.
@@ -452,13 +462,13 @@ riot_status riot_rsvd(riot_handle *h, int32_t k, int32_t p_os, int32_t q, const 
   if (info) {
     RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, h->Q, n, h->Q, n, 0.0, h->G, m, h->partial, kSplitK, st));
     RIOT_HIP(launch_orth_err(m, h->G, h->scal + 2, st));
-    int fl[5];
+    int fl[6];
     double sc[3];
-    RIOT_HIP(hipMemcpyAsync(fl, h->flags, 5 * sizeof(int), hipMemcpyDeviceToHost, st));
+    RIOT_HIP(hipMemcpyAsync(fl, h->flags, 6 * sizeof(int), hipMemcpyDeviceToHost, st));
     RIOT_HIP(hipMemcpyAsync(sc, h->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
     RIOT_HIP(hipStreamSynchronize(st));
     info->chol_shifts = fl[4];
-    info->qr_passes = 3;
+    info->qr_passes = fl[5];
     info->k_asym = sc[1];
     info->orth_err = sc[2];
     if (fl[0]) return RIOT_E_NOT_SPD;

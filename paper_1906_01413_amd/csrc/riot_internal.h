@@ -86,9 +86,11 @@ hipError_t launch_philox_normal(long long total, uint64_t seed, uint64_t stream,
 // ta/tb: 0 = no transpose, 1 = transpose. For ta = 1 and tb = 0 (A^T B, the
 // Gram/projection shape) the contraction is split over `splitk` partial
 // buffers reduced in fixed order (partial must hold splitk * M * N doubles).
+// run: optional device flag; when it holds 0 the launched kernels return at once
+// (predicated launches that keep a data-dependent loop free of host synchronisation).
 hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const double *A, int lda,
                     const double *B, int ldb, double beta, double *C, int ldc, double *partial,
-                    int splitk, hipStream_t st);
+                    int splitk, hipStream_t st, const int *run = nullptr);
 
 // Upper Cholesky factor R of G + s I (R^T R). mode 0: s = 0; mode 1: s = shift_rel * ||G||_F;
 // mode 2: s = 0 first, restarted with the shift on breakdown. flag[0] = 1 when the last
@@ -98,10 +100,16 @@ hipError_t launch_cholesky(int m, const double *G, double *R, double shift_rel, 
 
 // Blocked Cholesky G + s I = L L^T (lower), same modes as launch_cholesky.
 hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_rel, int mode,
-                               int *flag, int *shifts, hipStream_t st);
+                               int *flag, int *shifts, hipStream_t st, const int *run = nullptr,
+                               int *modflag = nullptr);
+// CholeskyQR pass control (see cholqr in the API layer): reset, then one call per pass;
+// count (optional) is incremented once per pass that ran.
+hipError_t launch_cholqr_reset(int *cq, hipStream_t st);
+hipError_t launch_cholqr_ctrl(int *cq, int pass_was_shifted, int *count, hipStream_t st);
 
 // X <- X L^{-T} in place (X rows x m, leading dimension ldx; L lower m x m).
-hipError_t launch_trsm_rlt(int rows, int m, double *X, int ldx, const double *L, hipStream_t st);
+hipError_t launch_trsm_rlt(int rows, int m, double *X, int ldx, const double *L, hipStream_t st,
+                           const int *run = nullptr);
 
 // Blocked inverse of a lower-triangular L.
 hipError_t launch_trinv_lower(int m, const double *L, double *X, hipStream_t st);

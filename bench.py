@@ -207,6 +207,85 @@ def time_to_accuracy(r, prob, xb, dev, target=1e-6, trials=3, cg_max=None, reps=
     return out
 
 
+def batch_leg(nprob: int, seed: int, dev, reps: int = 5) -> dict:
+    """Many uneven problems at once: inputs built with the library, then autotune, one
+    instrumented probe-product launch (load balance), eager runs and graph replays."""
+    import torch
+    from paper_1906_01413_amd import RiotBatch, gaussian_taps
+    from synthetic import batch_workloads
+
+    t_setup = time.perf_counter()
+    bw = batch_workloads(nprob, seed)
+    taps = gaussian_taps(2.0, 1.0)
+    specs = []
+    for w, dr in bw:
+        specs.append(dict(n=w.n, nsteps=w.nsteps, dt=w.dt, forcing=w.forcing, obs_step=dr["obs_step"],
+                          obs_idx=dr["obs_idx"], y=np.zeros(dr["obs_step"].size), rinv=dr["rinv"],
+                          taps=taps, m=w.m))
+    # twin experiment through the library: truth spin-up by riot_forecast, truth
+    # observations from the innovation at the truth with y = 0 (d = -H(x)), background
+    # truth + L xi by riot_apply_L
+    b0 = RiotBatch(specs, device=dev)
+    truth, xb = [], []
+    with torch.cuda.stream(b0.stream):
+        for j, (w, dr) in enumerate(bw):
+            r = b0.problem(j)
+            t0 = r.forecast(torch.tensor(dr["x0"], device=dev), w.spinup)
+            truth.append(t0)
+            xb.append(t0 + r.apply_L(torch.tensor(dr["bg_noise"], device=dev)))
+        for j in range(nprob):
+            b0.vec(j, b0.x).copy_(truth[j])
+    b0.run(seed)
+    torch.cuda.synchronize()
+    dpack = b0.d.cpu().numpy()
+    for j, (w, dr) in enumerate(bw):
+        o0 = int(b0.off_obs[j])
+        specs[j]["y"] = -dpack[o0: o0 + dr["obs_step"].size] + dr["obs_noise"]
+    del b0
+    torch.cuda.empty_cache()
+    b = RiotBatch(specs, device=dev)
+    with torch.cuda.stream(b.stream):
+        for j in range(nprob):
+            b.vec(j, b.x).copy_(xb[j])
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    wg, wave, ms_tuned = b.autotune()
+    ms_prof, busy, ntiles = b.profile()
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        a, c = ev(), ev()
+        a.record(b.stream)
+        for _ in range(n):
+            fn()
+        c.record(b.stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(c) / n
+
+    ms_eager = timed(lambda: b.run(seed), reps)
+    b.capture(seed)
+    ms_graph = timed(b.replay, reps)
+    sum_m = int(sum(b.m))
+    flops = sum(mj * tlad_flops_per_column(nj, tj, ob)
+                for mj, nj, tj, ob in zip(b.m, b.n, b.nsteps, b.nobs))
+    ach = flops / (ms_tuned / 1e3) / 1e12
+    return {
+        "workload": f"{nprob} independent Lorenz-96 inner loops, n in 40..2048, T in 20..200, "
+                    f"25-50% of variables observed every 4 steps, m = min(n/2,128)+8",
+        "problems": nprob, "sum_m": sum_m, "sum_n": int(sum(b.n)),
+        "pipeline_ms_graph": ms_graph, "pipeline_ms_eager": ms_eager,
+        "hvp_per_s": sum_m / (ms_graph / 1e3),
+        "hvp_launch_ms": ms_tuned,
+        "hvp_launch_hvp_per_s": sum_m / (ms_tuned / 1e3),
+        "tlad_tflops": ach, "tlad_frac_fp64_peak": ach / PEAK_FP64_VALU_TFLOPS,
+        "load_balance": busy, "tiles": ntiles, "profiled_launch_ms": ms_prof,
+        "layout": {"workgroups": wg, "member_per_wave_max_threads": wave},
+        "setup_s": setup_s,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +297,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the time-to-accuracy sweep")
     ap.add_argument("--hvp-reps", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=1000,
+                    help="problems in the batched-uneven leg (0 skips it)")
     ap.add_argument("--counter-pass", action="store_true",
                     help="only launch the TL/AD kernel three times and a 256 MiB device copy "
                          "(calibration), for rocprofv3 --pmc runs; prints no JSON")
@@ -352,6 +433,14 @@ def main():
 
     if not args.no_accuracy:
         out["inner_loop"] = time_to_accuracy(r, prob, xb, dev)
+
+    if args.batch > 0:
+        print(f"[bench] batched leg: {args.batch} problems", file=sys.stderr, flush=True)
+        out["batch"] = batch_leg(args.batch, args.seed, dev)
+        bl = out["batch"]
+        print(f"[bench] batch: pipeline {bl['pipeline_ms_graph']:.2f} ms (graph), "
+              f"{bl['pipeline_ms_eager']:.2f} ms (eager); probe products {bl['hvp_launch_ms']:.2f} ms, "
+              f"load balance {bl['load_balance']:.3f}, layout {bl['layout']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, m)

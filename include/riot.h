@@ -206,6 +206,88 @@ riot_status riot_apply_L(riot_handle *h, int32_t m, const double *X, double *Y);
 riot_status riot_philox_normal(riot_handle *h, int32_t n, int32_t m, uint64_t seed,
                                uint64_t stream, double *out);
 
+/* ------------------------------------------------------------------------------------
+ * Batches of independent inner-loop problems.
+ *
+ * Many Lorenz-96 4D-Var problems of different sizes (n a multiple of 8, n <= 2048; window
+ * length, observations and B per problem; m = m_max probes per problem, m <= min(n, 278))
+ * run the inner loop of Alg. 3 (first outer loop: v = 0, no power steps, all m Ritz pairs,
+ * adaptive LRA/LRU update) together:
+ *   - trajectories, innovations and gradients: one launch each over all problems;
+ *   - the Hessian-probe products of all probes of all problems: one persistent launch
+ *     whose workgroups take (problem, member) tiles, longest integrations first; problems
+ *     with n <= 512 can run one member per wave instead of one per workgroup;
+ *   - CholeskyQR, projections, K, eigen-solve, Ritz vectors, increment: batched launches;
+ *   - the whole sequence can be captured once into a HIP graph and replayed.
+ * Problem j's data live in batch-owned packed device buffers: vectors (x, grad, dz, dx) at
+ * offset sum_{i<j} n_i, lambda at sum_{i<j} m_i, Ritz vectors V (n_j x m_j column-major) at
+ * sum_{i<j} n_i m_i, innovations d at sum_{i<j} max(nobs_i, 1). Probes are Philox normals
+ * keyed by the run's seed, stream j for problem j (the same draws as riot_philox_normal with
+ * that seed and stream).
+ * ---------------------------------------------------------------------------------- */
+typedef struct riot_batch riot_batch;
+
+typedef struct {
+    double *x;       /* [sum n] device in: linearisation state of every problem */
+    double *grad;    /* [sum n] device out: gradient g_j (eq. 3, v = 0) */
+    double *lambda;  /* [sum m] device out: Ritz values, descending per problem */
+    double *V;       /* [sum n m] device out: Ritz vectors */
+    double *dz;      /* [sum n] device out: control increment */
+    double *dx;      /* [sum n] device out: state increment L dz */
+    double *d;       /* [sum max(nobs,1)] device out: innovations */
+} riot_batch_io;
+
+/* Half-kernel taps l_0 .. l_w of the Gaussian square root used for B (host function):
+ * l_d = c exp(-d^2 / ell^2), w = ceil(6.25 ell), c such that sum_{|d|<=w} l_d^2 = sigma_b^2,
+ * so that B = L L^T has the correlation exp(-d^2 / (2 ell^2)) (the paper asks for Gaussian
+ * correlations, Sec. 3.1, without fixing a square root). Returns w (with taps = NULL: the
+ * half-width only), or -1 for invalid arguments or max_taps < w + 1. */
+int32_t riot_gaussian_taps(double ell, double sigma_b, int32_t max_taps, double *taps);
+
+/* Workspace bytes for a batch (0 if a descriptor is unusable in a batch). Every
+ * descriptor's elems_per_lane is ignored (8 is used); all must share `prec`. */
+size_t riot_batch_workspace_bytes(int32_t nprob, const riot_desc *descs);
+
+/* Create a batch in a caller-allocated device workspace (256-byte aligned). Synchronises
+ * `hip_stream` (uploads of the per-problem tables). Graph capture needs a stream other than
+ * the legacy default stream. */
+riot_status riot_batch_init(int32_t nprob, const riot_desc *descs, void *workspace,
+                            size_t bytes, void *hip_stream, riot_batch **out);
+void riot_batch_free(riot_batch *b);
+
+/* Device pointers of the packed buffers (valid until riot_batch_free). */
+riot_status riot_batch_buffers(riot_batch *b, riot_batch_io *io);
+
+/* One inner loop for every problem (stream-ordered, no synchronisation): reads io.x,
+ * writes grad, d, lambda, V, dz, dx. RIOT_E_STATE once a graph has been captured. */
+riot_status riot_batch_run(riot_batch *b, uint64_t seed);
+
+/* Layout of the persistent TL/AD launch: `workgroups` resident workgroups of 256 threads;
+ * problems whose n / 8 <= wave_max_threads (<= 64) run one member per wave, the others one
+ * member per workgroup (0: none per wave). */
+riot_status riot_batch_set_layout(riot_batch *b, int32_t workgroups, int32_t wave_max_threads);
+
+/* Autotuner: times the probe-product launch of this batch for workgroups in {1, 2, 3} x
+ * compute units and member-per-wave on or off, keeps the fastest and reports it (host
+ * pointers may be NULL). Synchronises; overwrites the batch's probe buffers. */
+riot_status riot_batch_autotune(riot_batch *b, int32_t *workgroups_out,
+                                int32_t *wave_max_threads_out, float *ms_out);
+
+/* Capture riot_batch_run(b, seed) into a HIP graph; riot_batch_replay launches it. */
+riot_status riot_batch_capture(riot_batch *b, uint64_t seed);
+riot_status riot_batch_replay(riot_batch *b);
+
+/* One timed probe-product launch of the batch (current probes) with per-tile device
+ * clocks: ms = its duration (HIP events), busy_frac = the slots' busy time over the
+ * slots available for the whole launch (load balance), tiles = number of tiles. Host
+ * pointers may be NULL. Synchronises; allocates a small timing buffer (not for use under
+ * graph capture). */
+riot_status riot_batch_profile(riot_batch *b, float *ms, double *busy_frac, int32_t *tiles);
+
+/* The handle of problem j inside the batch (owned by the batch: do not riot_free it). Its
+ * single-problem calls work on the same workspace, e.g. for checks. */
+riot_status riot_batch_problem(riot_batch *b, int32_t j, riot_handle **h);
+
 #ifdef __cplusplus
 }
 #endif

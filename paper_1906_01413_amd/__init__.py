@@ -4,4 +4,5 @@ The compute path is the HIP library ``libriot.so`` (C ABI in include/riot.h);
 ``riot`` is its ctypes binding. Importing this package does not touch the GPU.
 """
 
-from .riot import Riot, RiotError, load_library, colmajor, empty_colmajor  # noqa: F401
+from .riot import (Riot, RiotBatch, RiotError, load_library, colmajor, empty_colmajor,  # noqa: F401
+                   gaussian_taps)

@@ -63,7 +63,9 @@ constexpr int kTriThreads = 512;
 // 1. Householder tridiagonalisation (full storage, one workgroup).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kTriThreads)
-    tridiag_kernel(int m, const double *__restrict__ K, double *__restrict__ work) {
+    tridiag_kernel(int m, const double *__restrict__ K, double *__restrict__ work,
+                   const EigJob *__restrict__ jobs) {
+  if (jobs) m = jobs[blockIdx.y].m, K = jobs[blockIdx.y].K, work = jobs[blockIdx.y].work;
   extern __shared__ double sh[];
   EigLayout Lw(m);
   double *Aw = work + Lw.Aw, *Hv = work + Lw.Hv, *dg = work + Lw.d, *eg = work + Lw.e;
@@ -179,7 +181,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 __global__ void __launch_bounds__(kRegThreads)
-    tridiag_reg_kernel(int m, const double *__restrict__ K, double *__restrict__ work) {
+    tridiag_reg_kernel(int m, const double *__restrict__ K, double *__restrict__ work,
+                       const EigJob *__restrict__ jobs) {
+  if (jobs) m = jobs[blockIdx.y].m, K = jobs[blockIdx.y].K, work = jobs[blockIdx.y].work;
   extern __shared__ double sh[];
   EigLayout Lw(m);
   double *Hv = work + Lw.Hv, *dg = work + Lw.d, *eg = work + Lw.e;
@@ -359,7 +363,9 @@ __device__ int negcount(int m, const double *D, const double *LLD, double tau, d
 // 2. Root representation (one workgroup of 64 threads).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) root_kernel(int m, double *__restrict__ work,
-                                                  int *__restrict__ flag) {
+                                                  int *__restrict__ flag,
+                                                  const EigJob *__restrict__ jobs) {
+  if (jobs) m = jobs[blockIdx.y].m, work = jobs[blockIdx.y].work, flag = jobs[blockIdx.y].flag;
   EigLayout Lw(m);
   extern __shared__ double rsh[];
   double *dg = rsh, *eg = rsh + m, *Dl = rsh + 2 * m, *Ll = rsh + 3 * m;
@@ -448,7 +454,10 @@ __global__ void __launch_bounds__(64) root_kernel(int m, double *__restrict__ wo
 // ---------------------------------------------------------------------------
 // 3. Eigenvalues of L D L^T: one wave per eigenvalue index (ascending).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) bisect_kernel(int m, double *__restrict__ work) {
+__global__ void __launch_bounds__(256) bisect_kernel(int m, double *__restrict__ work,
+                                                     const EigJob *__restrict__ jobs) {
+  if (jobs) m = jobs[blockIdx.y].m, work = jobs[blockIdx.y].work;
+  if ((int)blockIdx.x * (int)(blockDim.x >> 6) >= m) return;
   EigLayout Lw(m);
   extern __shared__ double bsh[];
   double *D = bsh, *LLD = bsh + m;
@@ -508,7 +517,10 @@ __global__ void __launch_bounds__(256) bisect_kernel(int m, double *__restrict__
 // 4. Eigenvectors by twisted factorisation: one thread per eigenvalue. The
 //    per-eigenvalue arrays live in scratch laid out [i][j] (coalesced in j).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) vector_kernel(int m, double *__restrict__ work) {
+__global__ void __launch_bounds__(64) vector_kernel(int m, double *__restrict__ work,
+                                                    const EigJob *__restrict__ jobs) {
+  if (jobs) m = jobs[blockIdx.y].m, work = jobs[blockIdx.y].work;
+  if ((int)(blockIdx.x * blockDim.x) >= m) return;
   EigLayout Lw(m);
   extern __shared__ double vsh[];
   double *D = vsh, *Ls = vsh + m, *LLD = vsh + 2 * m;
@@ -594,7 +606,9 @@ __global__ void __launch_bounds__(64) vector_kernel(int m, double *__restrict__ 
 constexpr int kMaxCluster = 48;
 
 __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict__ work,
-                                                      int *__restrict__ flag) {
+                                                      int *__restrict__ flag,
+                                                      const EigJob *__restrict__ jobs) {
+  if (jobs) m = jobs[blockIdx.y].m, work = jobs[blockIdx.y].work, flag = jobs[blockIdx.y].flag;
   EigLayout Lw(m);
   const double *dg = work + Lw.d, *eg = work + Lw.e, *misc = work + Lw.misc;
   double *mu = work + Lw.mu, *Z = work + Lw.Z;
@@ -751,7 +765,11 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
     backtransform_kernel(int m, const double *__restrict__ work, double *__restrict__ lam,
-                         double *__restrict__ Vout) {
+                         double *__restrict__ Vout, const EigJob *__restrict__ jobs) {
+  if (jobs) {
+    const EigJob &J = jobs[blockIdx.y];
+    m = J.m, work = J.work, lam = J.lam, Vout = J.Z;
+  }
   EigLayout Lw(m);
   const double *Hv = work + Lw.Hv, *Z = work + Lw.Z, *mu = work + Lw.mu, *misc = work + Lw.misc;
   const int lane = threadIdx.x & 63;
@@ -818,25 +836,50 @@ hipError_t launch_eig(int m, const double *K, double *lam, double *Z, double *wo
   if (m < 1 || m > 1088) return hipErrorInvalidValue;
   if (reg_fits(m))
     hipLaunchKernelGGL(tridiag_reg_kernel, dim3(1), dim3(kRegThreads), (size_t)4 * m * sizeof(double),
-                       st, m, K, work);
+                       st, m, K, work, nullptr);
   else
     hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kTriThreads),
-                       (size_t)(2 * m + kTriThreads) * sizeof(double), st, m, K, work);
+                       (size_t)(2 * m + kTriThreads) * sizeof(double), st, m, K, work, nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(root_kernel, dim3(1), dim3(64), (size_t)4 * m * sizeof(double), st, m, work,
-                     flag);
+                     flag, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(bisect_kernel, dim3((m + 3) / 4), dim3(256), (size_t)2 * m * sizeof(double), st,
-                     m, work);
+                     m, work, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(vector_kernel, dim3((m + 63) / 64), dim3(64), (size_t)3 * m * sizeof(double), st,
-                     m, work);
+                     m, work, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(cluster_kernel, dim3(1), dim3(256), 0, st, m, work, flag);
+  hipLaunchKernelGGL(cluster_kernel, dim3(1), dim3(256), 0, st, m, work, flag, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(backtransform_kernel, dim3((m + 3) / 4), dim3(256), 0, st, m, work, lam, Z);
+  hipLaunchKernelGGL(backtransform_kernel, dim3((m + 3) / 4), dim3(256), 0, st, m, work, lam, Z, nullptr);
   return hipGetLastError();
 }
+
+// Batched: every problem's m must satisfy the register-resident tridiagonalisation bound.
+hipError_t launch_eig_batched(int nprob, int maxm, const EigJob *jobs, hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  if (maxm < 1 || !reg_fits(maxm)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tridiag_reg_kernel, dim3(1, nprob), dim3(kRegThreads),
+                     (size_t)4 * maxm * sizeof(double), st, 0, nullptr, nullptr, jobs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(root_kernel, dim3(1, nprob), dim3(64), (size_t)4 * maxm * sizeof(double), st,
+                     0, nullptr, nullptr, jobs);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(bisect_kernel, dim3((maxm + 3) / 4, nprob), dim3(256),
+                     (size_t)2 * maxm * sizeof(double), st, 0, nullptr, jobs);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(vector_kernel, dim3((maxm + 63) / 64, nprob), dim3(64),
+                     (size_t)3 * maxm * sizeof(double), st, 0, nullptr, jobs);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(cluster_kernel, dim3(1, nprob), dim3(256), 0, st, 0, nullptr, nullptr, jobs);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(backtransform_kernel, dim3((maxm + 3) / 4, nprob), dim3(256), 0, st, 0,
+                     nullptr, nullptr, nullptr, jobs);
+  return hipGetLastError();
+}
+
 
 }  // namespace riot

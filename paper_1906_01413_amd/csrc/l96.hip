@@ -37,9 +37,21 @@ struct HaloMap {
   }
 };
 
+// Barrier for a halo exchange: the workgroup, or (WAVE) only the calling wave, whose LDS
+// operations complete in issue order, so waiting for its own writes is enough.
+template <bool WAVE>
+__device__ __forceinline__ void member_sync() {
+  if constexpr (WAVE) {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
 // Write this thread's boundary values, barrier, read the neighbours'.
-// All threads of the block must call it (inactive ones pass active=false).
-template <typename Real, int E>
+// All threads of the block (of the wave, WAVE) must call it (inactive ones pass active=false).
+template <typename Real, int E, bool WAVE = false>
 __device__ __forceinline__ void exchange(Real *lds, int &parity, int NT, int l, bool active,
                                          const HaloMap<E> &hm, const Real (&v)[E], Real &hl2,
                                          Real &hl1, Real &hr1, Real &hr2) {
@@ -50,7 +62,7 @@ __device__ __forceinline__ void exchange(Real *lds, int &parity, int NT, int l, 
     b[2 * NT + l] = v[E > 1 ? E - 2 : 0];
     b[3 * NT + l] = v[E - 1];
   }
-  __syncthreads();
+  member_sync<WAVE>();
   if (active) {
     hl2 = b[hm.off[0]];
     hl1 = b[hm.off[1]];
@@ -141,7 +153,11 @@ template <int E>
 __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
     trajectory_kernel(ModelView mv, int nsteps, const double *__restrict__ x0,
                       double *__restrict__ xout, double *__restrict__ xs64,
-                      float *__restrict__ xs32) {
+                      float *__restrict__ xs32, const TrajJob *__restrict__ jobs) {
+  if (jobs) {  // batched: one workgroup per problem (blockDim may exceed the problem's NT)
+    const TrajJob &J = jobs[blockIdx.x];
+    mv = J.mv, nsteps = J.mv.T, x0 = J.x0, xout = nullptr, xs64 = J.xs64, xs32 = J.xs32;
+  }
   extern __shared__ double lds_d[];
   const int l = threadIdx.x;
   const int NT = mv.NT;
@@ -229,7 +245,7 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
 // Member TL/AD sweep (device function shared by the batched kernel and CG).
 // ---------------------------------------------------------------------------
 
-template <typename Real, int E>
+template <typename Real, int E, bool WAVE = false>
 struct Member {
   const ModelView &mv;
   Real *lds;
@@ -282,7 +298,7 @@ struct Member {
       if (k >= 0 && active) tl_store(k, dl, f, weighted);
       if (t == mv.T) break;
       // stage 1
-      exchange<Real, E>(lds, parity, NT, l, active, hm, dl, hl2, hl1, hr1, hr2);
+      exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, dl, hl2, hl1, hr1, hr2);
       if (active) {
         load_base<Real, E>(stage_block<Real>(mv, t, 0), NT, l, xe);
         tl_jac<Real, E>(xe, dl, hl2, hl1, hr1, d);
@@ -293,7 +309,7 @@ struct Member {
         }
       }
       // stage 2
-      exchange<Real, E>(lds, parity, NT, l, active, hm, e, hl2, hl1, hr1, hr2);
+      exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, e, hl2, hl1, hr1, hr2);
       if (active) {
         load_base<Real, E>(stage_block<Real>(mv, t, 1), NT, l, xe);
         tl_jac<Real, E>(xe, e, hl2, hl1, hr1, d);
@@ -304,7 +320,7 @@ struct Member {
         }
       }
       // stage 3
-      exchange<Real, E>(lds, parity, NT, l, active, hm, e, hl2, hl1, hr1, hr2);
+      exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, e, hl2, hl1, hr1, hr2);
       if (active) {
         load_base<Real, E>(stage_block<Real>(mv, t, 2), NT, l, xe);
         tl_jac<Real, E>(xe, e, hl2, hl1, hr1, d);
@@ -315,7 +331,7 @@ struct Member {
         }
       }
       // stage 4
-      exchange<Real, E>(lds, parity, NT, l, active, hm, e, hl2, hl1, hr1, hr2);
+      exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, e, hl2, hl1, hr1, hr2);
       if (active) {
         load_base<Real, E>(stage_block<Real>(mv, t, 3), NT, l, xe);
         tl_jac<Real, E>(xe, e, hl2, hl1, hr1, d);
@@ -351,7 +367,7 @@ struct Member {
           a[j] = h6 * lp[j];
         }
       }
-      exchange<Real, E>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
+      exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
       if (active) {
         load_base<Real, E>(stage_block<Real>(mv, ts, 3), NT, l, xe);
         ad_jac<Real, E>(xe, a, hl1, hr1, hr2, s);
@@ -362,7 +378,7 @@ struct Member {
         }
       }
       // stage 3
-      exchange<Real, E>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
+      exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
       if (active) {
         load_base<Real, E>(stage_block<Real>(mv, ts, 2), NT, l, xe);
         ad_jac<Real, E>(xe, a, hl1, hr1, hr2, s);
@@ -373,7 +389,7 @@ struct Member {
         }
       }
       // stage 2
-      exchange<Real, E>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
+      exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
       if (active) {
         load_base<Real, E>(stage_block<Real>(mv, ts, 1), NT, l, xe);
         ad_jac<Real, E>(xe, a, hl1, hr1, hr2, s);
@@ -384,7 +400,7 @@ struct Member {
         }
       }
       // stage 1
-      exchange<Real, E>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
+      exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
       if (active) {
         load_base<Real, E>(stage_block<Real>(mv, ts, 0), NT, l, xe);
         ad_jac<Real, E>(xe, a, hl1, hr1, hr2, s);
@@ -408,7 +424,7 @@ struct Member {
       if (mode == 2) return;
       // each forcing value is re-read by the thread that stored it; the barrier only
       // separates the two sweeps' LDS traffic
-      __syncthreads();
+      member_sync<WAVE>();
       ad_sweep(v, f);
     } else {
       ad_sweep(v, mode == 1 ? fsrc : f);
@@ -433,6 +449,75 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
 }
 
 // ---------------------------------------------------------------------------
+// Persistent TL/AD over a batch of independent problems (8 elements per lane). Phase 1:
+// each workgroup takes whole-workgroup tiles (one member of a problem with NT > 64) from
+// an atomic counter; phase 2: each wave takes member-per-wave tiles (NT <= 64, the halo
+// exchanged inside the wave without workgroup barriers) from a second counter. The tile
+// lists are in decreasing cost order, so the longest integrations start first and the
+// short ones fill the tail. Every wave leaves once both lists are exhausted.
+// ---------------------------------------------------------------------------
+
+template <typename Real>
+__device__ __forceinline__ void run_tile(int mode, const TladProb &P, int mem, Real *lds, int l,
+                                         bool wave_layout) {
+  constexpr int E = 8;
+  const ModelView mv = P.mv;
+  const size_t n = (size_t)mv.n, U = (size_t)mv.U;
+  const double *dx0 = P.dx0 ? P.dx0 + (size_t)mem * n : nullptr;
+  double *lam0 = P.lam0 ? P.lam0 + (size_t)mem * n : nullptr;
+  Real *f = P.f ? reinterpret_cast<Real *>(P.f) + (size_t)mem * U : nullptr;
+  const Real *fsrc = reinterpret_cast<const Real *>(P.fsrc);
+  if (wave_layout) {
+    Member<Real, E, true> M(mv, lds, l);
+    M.run(mode, dx0, lam0, f, fsrc);
+  } else {
+    Member<Real, E, false> M(mv, lds, l);
+    M.run(mode, dx0, lam0, f, fsrc);
+  }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(256)
+    tlad_persistent_kernel(int mode, const TladProb *__restrict__ probs,
+                           const TladTile *__restrict__ wg_tiles, int n_wg,
+                           const TladTile *__restrict__ wave_tiles, int n_wave,
+                           int *__restrict__ counters, long long *__restrict__ clk) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  Real *lds = reinterpret_cast<Real *>(lds_raw);
+  __shared__ int tile_sh;
+  for (;;) {
+    if (threadIdx.x == 0) tile_sh = atomicAdd(&counters[0], 1);
+    __syncthreads();
+    const int t = tile_sh;
+    __syncthreads();  // every thread has its tile before thread 0 fetches the next
+    if (t >= n_wg) break;
+    const TladTile tile = wg_tiles[t];
+    const long long c0 = clk ? wall_clock64() : 0;
+    run_tile<Real>(mode, probs[tile.prob], tile.mem, lds, threadIdx.x, false);
+    __syncthreads();  // the tile's LDS traffic is over before the next tile starts
+    if (clk && threadIdx.x == 0) {
+      clk[2 * t] = c0;
+      clk[2 * t + 1] = wall_clock64();
+    }
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  Real *wlds = lds + (size_t)wave * kLdsSlots * 2 * 64;
+  for (;;) {
+    int t = 0;
+    if (lane == 0) t = atomicAdd(&counters[1], 1);
+    t = __shfl(t, 0, 64);
+    if (t >= n_wave) break;
+    const TladTile tile = wave_tiles[t];
+    const long long c0 = clk ? wall_clock64() : 0;
+    run_tile<Real>(mode, probs[tile.prob], tile.mem, wlds, lane, true);
+    if (clk && lane == 0) {
+      clk[2 * (n_wg + t)] = c0;
+      clk[2 * (n_wg + t) + 1] = wall_clock64();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Innovation, gradient forcing and cost.
 // ---------------------------------------------------------------------------
 
@@ -441,7 +526,14 @@ __global__ void innovation_kernel(ModelView mv, const double *__restrict__ xs64,
                                   const int *__restrict__ obs_step, const int *__restrict__ obs_idx,
                                   const double *__restrict__ y, const double *__restrict__ rinv,
                                   const int *__restrict__ u_optr, const int *__restrict__ u_olist,
-                                  double *__restrict__ d, Real *__restrict__ fgrad) {
+                                  double *__restrict__ d, Real *__restrict__ fgrad,
+                                  const InnovJob *__restrict__ jobs) {
+  if (jobs) {  // batched: blockIdx.y selects the problem
+    const InnovJob &J = jobs[blockIdx.y];
+    mv = J.mv, xs64 = J.xs64, U = J.mv.U, obs_step = J.obs_step, obs_idx = J.obs_idx, y = J.y;
+    rinv = J.rinv, u_optr = J.u_optr, u_olist = J.u_olist, d = J.d;
+    fgrad = reinterpret_cast<Real *>(J.fgrad);
+  }
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= U) return;
   double acc = 0.0;
@@ -550,9 +642,15 @@ __device__ void apply_L_column(int n, int w, const double *__restrict__ taps,
 
 __global__ void __launch_bounds__(256)
     apply_L_kernel(int n, int w, const double *__restrict__ taps, const double *__restrict__ X,
-                   double *__restrict__ Y, const double *__restrict__ Z, int mode, int use_lds) {
+                   double *__restrict__ Y, const double *__restrict__ Z, int mode, int use_lds,
+                   const ApplyLJobE *__restrict__ jobs) {
   extern __shared__ double ext[];
   const size_t c = blockIdx.x;
+  if (jobs) {  // batched: blockIdx.y selects the problem, blockIdx.x the column
+    const ApplyLJobE &J = jobs[blockIdx.y];
+    if ((int)c >= J.m) return;
+    n = J.n, w = J.w, taps = J.taps, X = J.X, Y = J.Y, Z = J.Z, mode = J.mode;
+  }
   apply_L_column(n, w, taps, X + c * n, Y + c * n, Z ? Z + c * n : nullptr, mode,
                  use_lds ? ext : nullptr);
 }
@@ -643,7 +741,11 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 }
 
 __global__ void philox_normal_kernel(long long total, uint64_t seed, uint64_t stream,
-                                     double *__restrict__ out) {
+                                     double *__restrict__ out, const PhiloxJob *__restrict__ jobs) {
+  if (jobs) {  // batched: blockIdx.y selects the problem (its own stream)
+    const PhiloxJob &J = jobs[blockIdx.y];
+    total = J.total, stream = J.stream, out = J.out;
+  }
   const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long pairs = (total + 1) / 2;
   if (j >= pairs) return;
@@ -696,7 +798,7 @@ hipError_t launch_trajectory(const ModelView &mv, int nsteps, const double *x0, 
                              double *xs64, float *xs32, hipStream_t st) {
   const size_t lds = (size_t)kLdsSlots * 2 * mv.NT * sizeof(double);
   RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL(trajectory_kernel<EE>, dim3(1), dim3(mv.NT), lds, st,
-                                           mv, nsteps, x0, xout, xs64, xs32));
+                                           mv, nsteps, x0, xout, xs64, xs32, nullptr));
   return hipGetLastError();
 }
 
@@ -711,11 +813,11 @@ hipError_t launch_innovation(const ModelView &mv, const double *xs64, int nobs, 
   if (fp32)
     hipLaunchKernelGGL(innovation_kernel<float>, dim3(grid), dim3(bs), 0, st, mv, xs64, mv.U,
                        obs_step, obs_idx, y, rinv, u_optr, u_olist, d,
-                       reinterpret_cast<float *>(fgrad));
+                       reinterpret_cast<float *>(fgrad), nullptr);
   else
     hipLaunchKernelGGL(innovation_kernel<double>, dim3(grid), dim3(bs), 0, st, mv, xs64, mv.U,
                        obs_step, obs_idx, y, rinv, u_optr, u_olist, d,
-                       reinterpret_cast<double *>(fgrad));
+                       reinterpret_cast<double *>(fgrad), nullptr);
   return hipGetLastError();
 }
 
@@ -778,7 +880,7 @@ hipError_t launch_apply_L(int n, int w, const double *taps, int m, const double 
   const size_t lds = (size_t)(n + 2 * w) * sizeof(double);
   const int use_lds = lds <= 60 * 1024 ? 1 : 0;
   hipLaunchKernelGGL(apply_L_kernel, dim3(m), dim3(256), use_lds ? lds : 0, st, n, w, taps, X, Y,
-                     Z, mode, use_lds);
+                     Z, mode, use_lds, nullptr);
   return hipGetLastError();
 }
 
@@ -811,7 +913,83 @@ hipError_t launch_philox_normal(long long total, uint64_t seed, uint64_t stream,
   const int bs = 256;
   const long long grid = (pairs + bs - 1) / bs;
   hipLaunchKernelGGL(philox_normal_kernel, dim3((unsigned)grid), dim3(bs), 0, st, total, seed,
-                     stream, out);
+                     stream, out, nullptr);
+  return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched launchers (E = 8, workgroups of 256 threads, NT <= 256 per problem)
+// ---------------------------------------------------------------------------
+
+constexpr int kBatchThreads = 256;
+
+hipError_t launch_trajectory_batched(int nprob, const TrajJob *jobs, hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  const size_t lds = (size_t)kLdsSlots * 2 * kBatchThreads * sizeof(double);
+  hipLaunchKernelGGL(trajectory_kernel<8>, dim3(nprob), dim3(kBatchThreads), lds, st, ModelView{}, 0,
+                     nullptr, nullptr, nullptr, nullptr, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_innovation_batched(int nprob, int maxU, const InnovJob *jobs, bool fp32,
+                                     hipStream_t st) {
+  if (nprob <= 0 || maxU <= 0) return hipSuccess;
+  const dim3 grid((maxU + 255) / 256, nprob);
+  if (fp32)
+    hipLaunchKernelGGL(innovation_kernel<float>, grid, dim3(256), 0, st, ModelView{}, nullptr, 0,
+                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, jobs);
+  else
+    hipLaunchKernelGGL(innovation_kernel<double>, grid, dim3(256), 0, st, ModelView{}, nullptr, 0,
+                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_tlad_persistent(int nwg, int mode, const TladProb *probs, const TladTile *wg_tiles,
+                                  int n_wg, const TladTile *wave_tiles, int n_wave, int *counters,
+                                  bool fp32, hipStream_t st, long long *clk) {
+  if (nwg <= 0 || (n_wg <= 0 && n_wave <= 0)) return hipSuccess;
+  hipError_t e = launch_zero_ints(counters, 2, st);
+  if (e != hipSuccess) return e;
+  const size_t lds =
+      (size_t)kLdsSlots * 2 * kBatchThreads * (fp32 ? sizeof(float) : sizeof(double));
+  if (fp32)
+    hipLaunchKernelGGL(tlad_persistent_kernel<float>, dim3(nwg), dim3(kBatchThreads), lds, st, mode,
+                       probs, wg_tiles, n_wg, wave_tiles, n_wave, counters, clk);
+  else
+    hipLaunchKernelGGL(tlad_persistent_kernel<double>, dim3(nwg), dim3(kBatchThreads), lds, st,
+                       mode, probs, wg_tiles, n_wg, wave_tiles, n_wave, counters, clk);
+  return hipGetLastError();
+}
+
+int tlad_persistent_resident_per_cu(bool fp32) {
+  int nb = 0;
+  const size_t lds =
+      (size_t)kLdsSlots * 2 * kBatchThreads * (fp32 ? sizeof(float) : sizeof(double));
+  const hipError_t e =
+      fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tlad_persistent_kernel<float>,
+                                                          kBatchThreads, lds)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tlad_persistent_kernel<double>,
+                                                          kBatchThreads, lds);
+  return e == hipSuccess ? nb : 0;
+}
+
+hipError_t launch_apply_L_batched(int nprob, int maxm, int maxext, const ApplyLJobE *jobs,
+                                  hipStream_t st) {
+  if (nprob <= 0 || maxm <= 0) return hipSuccess;
+  const size_t lds = (size_t)maxext * sizeof(double);
+  if (lds > 60 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(apply_L_kernel, dim3(maxm, nprob), dim3(256), lds, st, 0, 0, nullptr, nullptr,
+                     nullptr, nullptr, 0, 1, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox_batched(int nprob, long long maxtotal, uint64_t seed,
+                                 const PhiloxJob *jobs, hipStream_t st) {
+  if (nprob <= 0 || maxtotal <= 0) return hipSuccess;
+  const long long pairs = (maxtotal + 1) / 2;
+  hipLaunchKernelGGL(philox_normal_kernel, dim3((unsigned)((pairs + 255) / 256), nprob), dim3(256),
+                     0, st, 0LL, seed, 0ULL, nullptr, jobs);
   return hipGetLastError();
 }
 

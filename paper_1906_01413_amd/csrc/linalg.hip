@@ -28,12 +28,21 @@ __global__ void __launch_bounds__(64)
     gemm_mfma_kernel(int M, int N, int K, const double *__restrict__ A, int lda,
                      const double *__restrict__ B, int ldb, double *__restrict__ C, int ldc,
                      double alpha, double beta, int kchunk, double *__restrict__ partial,
-                     const int *__restrict__ run) {
+                     const int *__restrict__ run, const GemmJob *__restrict__ jobs) {
+  int kz = blockIdx.z;
+  if (jobs) {  // batched: blockIdx.z selects the problem, no split over K
+    const GemmJob &J = jobs[blockIdx.z];
+    M = J.M, N = J.N, K = J.K, A = J.A, lda = J.lda, B = J.B, ldb = J.ldb, C = J.C, ldc = J.ldc;
+    run = J.run;
+    kchunk = K;
+    partial = nullptr;
+    kz = 0;
+  }
   if (run && run[0] == 0) return;  // predicated launch: the whole grid skips uniformly
   const int lane = threadIdx.x;
   const int li = lane & 15, lg = lane >> 4;
   const int m0 = blockIdx.x * 32, n0 = blockIdx.y * 32;
-  const int kz = blockIdx.z;
+  if (m0 >= M || n0 >= N) return;
   const int kbeg = kz * kchunk;
   const int kend = min(K, kbeg + kchunk);
   d4 acc[2][2];
@@ -237,7 +246,12 @@ __global__ void __launch_bounds__(kCholThreads)
     chol_blocked_kernel(int m, const double *__restrict__ G, double *__restrict__ L,
                         double shift_rel, int mode, int *__restrict__ flag,
                         int *__restrict__ shifts, const int *__restrict__ run,
-                        int *__restrict__ modflag) {
+                        int *__restrict__ modflag, const CholJob *__restrict__ jobs) {
+  if (jobs) {  // batched: blockIdx.y selects the problem
+    const CholJob &J = jobs[blockIdx.y];
+    m = J.m, G = J.G, L = J.L, shift_rel = J.shift_rel, flag = J.flag, shifts = J.shifts;
+    run = J.run, modflag = J.modflag;
+  }
   if (run && run[0] == 0) return;
   __shared__ double D[kPB][kPB + 1];
   __shared__ double Dinv[kPB];
@@ -406,8 +420,13 @@ __global__ void __launch_bounds__(kCholThreads)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(64)
     trsm_rlt_kernel(int rows, int m, double *__restrict__ X, int ldx, const double *__restrict__ L,
-                    const int *__restrict__ run) {
+                    const int *__restrict__ run, const TrsmJob *__restrict__ jobs) {
+  if (jobs) {  // batched: blockIdx.y selects the problem
+    const TrsmJob &J = jobs[blockIdx.y];
+    rows = J.rows, m = J.m, X = J.X, ldx = J.ldx, L = J.L, run = J.run;
+  }
   if (run && run[0] == 0) return;
+  if ((int)blockIdx.x * 32 >= rows) return;
   __shared__ double B[32][33];
   __shared__ double Ld[32][33];
   const int lane = threadIdx.x, li = lane & 15, lg = lane >> 4;
@@ -465,236 +484,13 @@ __global__ void __launch_bounds__(64)
 // by block row, X_ij = -X_ii (sum_{k=j}^{i-1} L_ik X_kj) with FP64 MFMA.
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kCholThreads)
-    trinv_lower_blocked_kernel(int m, const double *__restrict__ L, double *__restrict__ X) {
-  __shared__ double S[kCholThreads / 64][kPB][kPB + 1];  // per-wave staging of one 32 x 32 block
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int wave = tid >> 6, nwaves = nt >> 6, lane = tid & 63;
-  const int nbk = (m + kPB - 1) / kPB;
-  for (size_t idx = tid; idx < (size_t)m * m; idx += nt) X[idx] = 0.0;
-  __syncthreads();
-  // diagonal blocks: staged in LDS; lane c of a half-wave solves column c of L_ii x = e_c
-  for (int b0 = wave * 2; b0 < nbk; b0 += 2 * nwaves) {
-    const int half = lane >> 5, c = lane & 31;
-    const int b = b0 + half;
-    if (b < nbk) {
-      const int k0 = b * kPB, nb = min(kPB, m - k0);
-      if (c < nb) {
-        double x[kPB];
-#pragma unroll
-        for (int i = 0; i < kPB; ++i) {
-          if (i < nb) {
-            double a = (i == c) ? 1.0 : 0.0;
-#pragma unroll
-            for (int t = 0; t < i; ++t) a -= L[(size_t)(k0 + t) * m + k0 + i] * x[t];
-            x[i] = (i < c) ? 0.0 : a / L[(size_t)(k0 + i) * m + k0 + i];
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < kPB; ++i)
-          if (i < nb && i >= c) X[(size_t)(k0 + c) * m + k0 + i] = x[i];
-      }
-    }
-  }
-  __syncthreads();
-  const int li = lane & 15, lg = lane >> 4;
-  for (int bi = 1; bi < nbk; ++bi) {
-    const int i0 = bi * kPB, ni = min(kPB, m - i0);
-    for (int bj = wave; bj < bi; bj += nwaves) {
-      const int j0 = bj * kPB;
-      d4 acc[2][2];
-      zero_acc(acc);
-      // T = sum_{k=j}^{i-1} L_ik X_kj  (rows i0.., cols j0.., K over rows j0..i0-1)
-      wave_mma32<false, false>(L + (size_t)j0 * m + i0, m, X + (size_t)j0 * m + j0, m, i0 - j0, ni,
-                               kPB, acc);
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) S[wave][16 * rt + lg + 4 * r][16 * ct + li] = acc[rt][ct][r];
-      // the block is re-read by other lanes of the same wave
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // X_ij = -X_ii T : X_ii from global, T from LDS (row-major, stride kPB + 1)
-      zero_acc(acc);
-      wave_mma32<false, true>(X + (size_t)i0 * m + i0, m, &S[wave][0][0], kPB + 1, ni, ni, kPB,
-                              acc);
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = i0 + 16 * rt + lg + 4 * r, col = j0 + 16 * ct + li;
-            if (row < m && col < m) X[(size_t)col * m + row] = -acc[rt][ct][r];
-          }
-      // S[wave] is rewritten by this wave's next block
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    __syncthreads();
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Cholesky: G + s I = R^T R, R upper triangular (right-looking).
 // ---------------------------------------------------------------------------
 
-// mode 0: plain; mode 1: shifted (s = shift_rel * ||G||_F); mode 2: plain, and on
-// breakdown restart from G with the shift. Each shifted attempt increments *shifts.
-__global__ void __launch_bounds__(1024)
-    cholesky_kernel(int m, const double *__restrict__ G, double *__restrict__ R, double shift_rel,
-                    int mode, int *__restrict__ flag, int *__restrict__ shifts) {
-  extern __shared__ double rowk[];
-  __shared__ double red[16];
-  double fro = 0.0;
-  if (mode != 0) {
-    double part = 0.0;
-    for (size_t idx = threadIdx.x; idx < (size_t)m * m; idx += blockDim.x) part += G[idx] * G[idx];
-    fro = sqrt(wg_sum(part, red));
-  }
-  const int attempts = (mode == 2) ? 2 : 1;
-  for (int att = 0; att < attempts; ++att) {
-    const bool shifted = (mode == 1) || (mode == 2 && att == 1);
-    const double s = shifted ? shift_rel * fro : 0.0;
-    if (shifted && threadIdx.x == 0 && shifts) shifts[0] += 1;
-    for (size_t idx = threadIdx.x; idx < (size_t)m * m; idx += blockDim.x) {
-      const int i = (int)(idx % m), j = (int)(idx / m);
-      R[idx] = (i <= j) ? (G[idx] + (i == j ? s : 0.0)) : 0.0;
-    }
-    __syncthreads();
-    bool ok = true;
-    for (int k = 0; k < m; ++k) {
-      const double piv = R[(size_t)k * m + k];
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        ok = false;  // uniform: every thread read the same pivot
-        break;
-      }
-      const double rkk = sqrt(piv);
-      const double inv = 1.0 / rkk;
-      for (int j = k + threadIdx.x; j < m; j += blockDim.x) {
-        const double v = (j == k) ? rkk : R[(size_t)j * m + k] * inv;
-        rowk[j] = v;
-      }
-      __syncthreads();
-      for (int j = k + threadIdx.x; j < m; j += blockDim.x) R[(size_t)j * m + k] = rowk[j];
-      const int len = m - k - 1;
-      const size_t tot = (size_t)len * len;
-      for (size_t idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int i = k + 1 + (int)(idx % len), j = k + 1 + (int)(idx / len);
-        if (i <= j) R[(size_t)j * m + i] -= rowk[i] * rowk[j];
-      }
-      __syncthreads();
-    }
-    if (ok) return;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) flag[0] = 1;
-}
 
-// Upper-triangular inverse by column-oriented back substitution on all columns at once.
-__global__ void __launch_bounds__(1024)
-    trinv_upper_kernel(int m, const double *__restrict__ R, double *__restrict__ X) {
-  extern __shared__ double colr[];
-  for (size_t idx = threadIdx.x; idx < (size_t)m * m; idx += blockDim.x) {
-    const int i = (int)(idx % m), j = (int)(idx / m);
-    X[idx] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int i = m - 1; i >= 0; --i) {
-    const double inv = 1.0 / R[(size_t)i * m + i];
-    for (int r = threadIdx.x; r < i; r += blockDim.x) colr[r] = R[(size_t)i * m + r];
-    // scale row i of X (columns j >= i)
-    for (int j = i + threadIdx.x; j < m; j += blockDim.x) X[(size_t)j * m + i] *= inv;
-    __syncthreads();
-    // X[r, j] -= R[r, i] * X[i, j] for r < i <= j
-    const size_t tot = (size_t)i * (m - i);
-    for (size_t idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-      const int r = (int)(idx % i), j = i + (int)(idx / i);
-      X[(size_t)j * m + r] -= colr[r] * X[(size_t)j * m + i];
-    }
-    __syncthreads();
-  }
-}
 
-// Gauss-Jordan inverse with partial pivoting. work = [W | X] (2 m x m).
-__global__ void __launch_bounds__(1024)
-    gj_inverse_kernel(int m, const double *__restrict__ Min, double *__restrict__ Minv,
-                      double *__restrict__ work, int *__restrict__ flag) {
-  extern __shared__ double sh[];
-  double *prow_w = sh;      // pivot row of W (m)
-  double *prow_x = sh + m;  // pivot row of X (m)
-  double *colk = sh + 2 * m;
-  __shared__ double redv[16];
-  __shared__ int redi[16];
-  double *W = work, *X = Minv;
-  for (size_t idx = threadIdx.x; idx < (size_t)m * m; idx += blockDim.x) {
-    const int i = (int)(idx % m), j = (int)(idx / m);
-    W[idx] = Min[idx];
-    X[idx] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int k = 0; k < m; ++k) {
-    // pivot search in column k, rows k..m-1
-    double best = -1.0;
-    int cand = -1;
-    double cv = 0.0;
-    for (int i = k + threadIdx.x; i < m; i += blockDim.x) {
-      const double v = fabs(W[(size_t)k * m + i]);
-      if (v > best || cand < 0) {
-        best = v;
-        cand = i;
-        cv = v;
-      }
-    }
-    double pv;
-    const int p = wg_argmax_abs(cand >= 0 ? cv : 0.0, cand, redv, redi, &pv);
-    if (!(pv > 0.0) || !isfinite(pv) || p < 0) {
-      if (threadIdx.x == 0) flag[0] = 1;
-      return;
-    }
-    // swap rows k and p (W columns k..m-1, X all columns), load pivot rows
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
-      if (j >= k) {
-        const double a = W[(size_t)j * m + k], b = W[(size_t)j * m + p];
-        W[(size_t)j * m + k] = b;
-        W[(size_t)j * m + p] = a;
-      }
-      const double c = X[(size_t)j * m + k], d = X[(size_t)j * m + p];
-      X[(size_t)j * m + k] = d;
-      X[(size_t)j * m + p] = c;
-    }
-    __syncthreads();
-    const double inv = 1.0 / W[(size_t)k * m + k];
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
-      const double wv = (j >= k) ? W[(size_t)j * m + k] * inv : 0.0;
-      const double xv = X[(size_t)j * m + k] * inv;
-      prow_w[j] = wv;
-      prow_x[j] = xv;
-      if (j >= k) W[(size_t)j * m + k] = wv;
-      X[(size_t)j * m + k] = xv;
-    }
-    for (int i = threadIdx.x; i < m; i += blockDim.x) colk[i] = W[(size_t)k * m + i];
-    __syncthreads();
-    // eliminate column k from every other row
-    const size_t tot = (size_t)m * m;
-    for (size_t idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-      const int i = (int)(idx % m), j = (int)(idx / m);
-      if (i == k) continue;
-      const double c = colk[i];
-      if (c == 0.0) continue;
-      if (j > k) W[idx] -= c * prow_w[j];
-      X[idx] -= c * prow_x[j];
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < m; i += blockDim.x)
-      if (i != k) W[(size_t)k * m + i] = 0.0;
-    __syncthreads();
-  }
-}
 
 // K <- (K + K^T)/2 over the strict lower triangle, many workgroups; per-block partial
 // sums of ||K - K^T||^2 and ||K||^2 are reduced by symmetrize_norm_kernel in fixed order.
@@ -749,264 +545,6 @@ __global__ void __launch_bounds__(1024) orth_err_kernel(int m, const double *__r
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric eigen-solver: Householder tridiagonalisation, implicit QL with
-// Wilkinson-type shifts (the QL sweep's rotations are generated by one thread
-// and applied to the rows of Z by all threads), back-transformation by the
-// Householder reflectors (one wave per column) and a descending sort.
-// ---------------------------------------------------------------------------
-
-// work layout: Aw [m*m] | Hv [m*m] | Z [m*m] | d [m] | e [m]
-__host__ __device__ size_t syev_layout(int m, size_t off[5]) {
-  const size_t mm = (size_t)m * m;
-  off[0] = 0;
-  off[1] = mm;
-  off[2] = 2 * mm;
-  off[3] = 3 * mm;
-  off[4] = 3 * mm + m;
-  return 3 * mm + 2 * (size_t)m;
-}
-
-__global__ void __launch_bounds__(1024)
-    tridiag_ql_kernel(int m, const double *__restrict__ K, double *__restrict__ work,
-                      int *__restrict__ flag) {
-  extern __shared__ double sh[];
-  size_t off[5];
-  syev_layout(m, off);
-  double *Aw = work + off[0], *Hv = work + off[1], *Z = work + off[2];
-  double *dg = work + off[3], *eg = work + off[4];
-  double *vs = sh;          // Householder vector (m)
-  double *ps = sh + m;      // p / w (m)
-  double *cs = sh + 2 * m;  // rotation cosines (m)
-  double *sn = sh + 3 * m;  // rotation sines (m)
-  double *part = sh + 4 * m;  // symv partials (blockDim)
-  __shared__ double red[16];
-  __shared__ int ctl[4];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const size_t mm = (size_t)m * m;
-  for (size_t idx = tid; idx < mm; idx += nt) {
-    Aw[idx] = K[idx];
-    Hv[idx] = 0.0;
-  }
-  __syncthreads();
-  // ---- tridiagonalisation ----
-  for (int k = 0; k + 2 < m; ++k) {
-    const int R = m - k - 1;  // length of the trailing block
-    double part_s = 0.0;
-    for (int i = tid; i < R; i += nt) {
-      const double x = Aw[(size_t)k * m + k + 1 + i];
-      vs[i] = x;
-      part_s += x * x;
-    }
-    const double sig2 = wg_sum(part_s, red);
-    const double sig = sqrt(sig2);
-    const double x0 = vs[0];
-    __syncthreads();
-    if (sig == 0.0) {
-      if (tid == 0) {
-        dg[k] = Aw[(size_t)k * m + k];
-        eg[k] = 0.0;
-      }
-      __syncthreads();
-      continue;
-    }
-    const double alpha = (x0 >= 0.0) ? -sig : sig;
-    // v = x - alpha e1, normalised: ||v||^2 = sig^2 - 2 alpha x0 + alpha^2 = 2 (sig^2 - alpha x0)
-    const double vn = sqrt(2.0 * (sig2 - alpha * x0));
-    if (tid == 0) vs[0] = x0 - alpha;
-    __syncthreads();
-    for (int i = tid; i < R; i += nt) {
-      const double v = vs[i] / vn;
-      vs[i] = v;
-      Hv[(size_t)k * m + k + 1 + i] = v;
-    }
-    __syncthreads();
-    // p = S v with S = Aw[k+1:, k+1:] (thread groups split the column range)
-    const int groups = max(1, nt / R);
-    {
-      const int i = tid % R, g = tid / R;
-      double acc = 0.0;
-      if (g < groups) {
-        for (int j = g; j < R; j += groups)
-          acc += Aw[(size_t)(k + 1 + j) * m + (k + 1 + i)] * vs[j];
-      }
-      if (tid < R * groups) part[tid] = acc;
-      // rows beyond nt (R > nt) handled by the loop below
-    }
-    __syncthreads();
-    if (R <= nt) {
-      for (int i = tid; i < R; i += nt) {
-        double s = 0.0;
-        for (int g = 0; g < groups; ++g) s += part[g * R + i];
-        ps[i] = s;
-      }
-    } else {
-      for (int i = tid; i < R; i += nt) {
-        double s = 0.0;
-        for (int j = 0; j < R; ++j) s += Aw[(size_t)(k + 1 + j) * m + (k + 1 + i)] * vs[j];
-        ps[i] = s;
-      }
-    }
-    __syncthreads();
-    double kp = 0.0;
-    for (int i = tid; i < R; i += nt) kp += vs[i] * ps[i];
-    const double Kv = wg_sum(kp, red);
-    for (int i = tid; i < R; i += nt) ps[i] = ps[i] - Kv * vs[i];
-    __syncthreads();
-    const size_t tot = (size_t)R * R;
-    for (size_t idx = tid; idx < tot; idx += nt) {
-      const int i = (int)(idx % R), j = (int)(idx / R);
-      Aw[(size_t)(k + 1 + j) * m + (k + 1 + i)] -= 2.0 * (vs[i] * ps[j] + ps[i] * vs[j]);
-    }
-    if (tid == 0) {
-      dg[k] = Aw[(size_t)k * m + k];
-      eg[k] = alpha;
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (m >= 2) {
-      dg[m - 2] = Aw[(size_t)(m - 2) * m + m - 2];
-      dg[m - 1] = Aw[(size_t)(m - 1) * m + m - 1];
-      eg[m - 2] = Aw[(size_t)(m - 2) * m + m - 1];
-    } else {
-      dg[0] = Aw[0];
-    }
-    eg[m - 1] = 0.0;
-  }
-  // Z = I (eigenvectors of T, column-major)
-  for (size_t idx = tid; idx < mm; idx += nt) {
-    const int i = (int)(idx % m), j = (int)(idx / m);
-    Z[idx] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  // ---- implicit QL on (d, e) ----
-  const double eps = 0x1.0p-52;
-  for (int l = 0; l < m; ++l) {
-    int iter = 0;
-    while (true) {
-      if (tid == 0) {
-        int mmi;
-        for (mmi = l; mmi < m - 1; ++mmi) {
-          const double dd = fabs(dg[mmi]) + fabs(dg[mmi + 1]);
-          if (fabs(eg[mmi]) <= eps * dd) break;
-        }
-        ctl[0] = mmi;  // end of the unreduced block
-        ctl[1] = -1;   // lowest rotation index applied (none)
-        ctl[2] = 0;    // failure
-        if (mmi != l) {
-          if (iter >= 60) {
-            ctl[2] = 1;
-          } else {
-            double g = (dg[l + 1] - dg[l]) / (2.0 * eg[l]);
-            double r = hypot(g, 1.0);
-            g = dg[mmi] - dg[l] + eg[l] / (g + copysign(r, g));
-            double s = 1.0, c = 1.0, p = 0.0;
-            int i;
-            bool under = false;
-            for (i = mmi - 1; i >= l; --i) {
-              double f = s * eg[i];
-              const double b = c * eg[i];
-              r = hypot(f, g);
-              eg[i + 1] = r;
-              if (r == 0.0) {
-                dg[i + 1] -= p;
-                eg[mmi] = 0.0;
-                under = true;
-                break;
-              }
-              s = f / r;
-              c = g / r;
-              g = dg[i + 1] - p;
-              r = (dg[i] - g) * s + 2.0 * c * b;
-              p = s * r;
-              dg[i + 1] = g + p;
-              g = c * r - b;
-              cs[i] = c;
-              sn[i] = s;
-            }
-            ctl[1] = under ? i + 1 : l;
-            if (!under) {
-              dg[l] -= p;
-              eg[l] = g;
-              eg[mmi] = 0.0;
-            }
-          }
-        }
-      }
-      __syncthreads();
-      const int mmi = ctl[0], lo = ctl[1], failed = ctl[2];
-      __syncthreads();  // everyone has read ctl before thread 0 rewrites it
-      if (failed) {
-        if (tid == 0) flag[0] = 1;
-        return;
-      }
-      if (mmi == l) break;
-      ++iter;
-      // apply rotations i = mmi-1 .. lo to columns (i, i+1) of every row of Z
-      for (int row = tid; row < m; row += nt) {
-        double carry = Z[(size_t)mmi * m + row];
-        for (int i = mmi - 1; i >= lo; --i) {
-          const double zi = Z[(size_t)i * m + row];
-          Z[(size_t)(i + 1) * m + row] = sn[i] * zi + cs[i] * carry;
-          carry = cs[i] * zi - sn[i] * carry;
-        }
-        Z[(size_t)lo * m + row] = carry;
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// Back-transformation Z <- H_0 ... H_{m-3} Z and descending sort into (lam, Vout).
-// One wave per column of Z.
-__global__ void __launch_bounds__(256)
-    syev_backtransform_kernel(int m, const double *__restrict__ work, double *__restrict__ lam,
-                              double *__restrict__ Vout) {
-  size_t off[5];
-  syev_layout(m, off);
-  const double *Hv = work + off[1], *Z = work + off[2], *dg = work + off[3];
-  const int lane = threadIdx.x & 63;
-  const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (col >= m) return;
-  constexpr int kMaxPer = 17;  // m <= 1088
-  double z[kMaxPer];
-#pragma unroll
-  for (int q = 0; q < kMaxPer; ++q) {
-    const int i = lane + 64 * q;
-    z[q] = (i < m) ? Z[(size_t)col * m + i] : 0.0;
-  }
-  for (int k = m - 3; k >= 0; --k) {
-    const double *v = Hv + (size_t)k * m;
-    double dot = 0.0;
-#pragma unroll
-    for (int q = 0; q < kMaxPer; ++q) {
-      const int i = lane + 64 * q;
-      if (i > k && i < m) dot += v[i] * z[q];
-    }
-    for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
-#pragma unroll
-    for (int q = 0; q < kMaxPer; ++q) {
-      const int i = lane + 64 * q;
-      if (i > k && i < m) z[q] -= 2.0 * dot * v[i];
-    }
-  }
-  // rank in descending order (ties by index)
-  const double dj = dg[col];
-  int rank = 0;
-  for (int i = lane; i < m; i += 64) {
-    const double di = dg[i];
-    rank += (di > dj || (di == dj && i < col)) ? 1 : 0;
-  }
-  for (int o = 32; o > 0; o >>= 1) rank += __shfl_xor(rank, o, 64);
-  if (lane == 0) lam[rank] = dj;
-#pragma unroll
-  for (int q = 0; q < kMaxPer; ++q) {
-    const int i = lane + 64 * q;
-    if (i < m) Vout[(size_t)rank * m + i] = z[q];
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Increment, covariance and utility kernels
 // ---------------------------------------------------------------------------
 
@@ -1019,7 +557,12 @@ __device__ __forceinline__ bool use_lru(int mode_lru, const double *lam, int k) 
 __global__ void increment_kernel(int n, int k, const double *__restrict__ lam,
                                  const double *__restrict__ V, const double *__restrict__ c,
                                  const double *__restrict__ g, int mode_lru,
-                                 double *__restrict__ dz, double *__restrict__ dofs) {
+                                 double *__restrict__ dz, double *__restrict__ dofs,
+                                 const IncJob *__restrict__ jobs) {
+  if (jobs) {  // batched: blockIdx.y selects the problem
+    const IncJob &J = jobs[blockIdx.y];
+    n = J.n, k = J.k, lam = J.lam, V = J.V, c = J.c, g = J.g, dz = J.dz, dofs = J.dofs;
+  }
   const bool lru = use_lru(mode_lru, lam, k);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -1117,7 +660,7 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   double *part = splits > 1 ? partial : nullptr;
 #define RIOT_GEMM(TA_, TB_)                                                                  \
   hipLaunchKernelGGL((gemm_mfma_kernel<TA_, TB_>), grid, dim3(64), 0, st, M, N, K, A, lda, B, \
-                     ldb, C, ldc, alpha, beta, kchunk, part, run)
+                     ldb, C, ldc, alpha, beta, kchunk, part, run, nullptr)
   if (ta == 0 && tb == 0)
     RIOT_GEMM(0, 0);
   else if (ta == 1 && tb == 0)
@@ -1138,18 +681,11 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   return e;
 }
 
-hipError_t launch_cholesky(int m, const double *G, double *R, double shift_rel, int mode,
-                           int *flag, int *shifts, hipStream_t st) {
-  hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(1024), (size_t)m * sizeof(double), st, m, G, R,
-                     shift_rel, mode, flag, shifts);
-  return hipGetLastError();
-}
-
 hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_rel, int mode,
                                int *flag, int *shifts, hipStream_t st, const int *run,
                                int *modflag) {
   hipLaunchKernelGGL(chol_blocked_kernel, dim3(1), dim3(kCholThreads), 0, st, m, G, L, shift_rel,
-                     mode, flag, shifts, run, modflag);
+                     mode, flag, shifts, run, modflag, nullptr);
   return hipGetLastError();
 }
 
@@ -1157,7 +693,7 @@ hipError_t launch_trsm_rlt(int rows, int m, double *X, int ldx, const double *L,
                            const int *run) {
   if (rows <= 0 || m <= 0) return hipSuccess;
   hipLaunchKernelGGL(trsm_rlt_kernel, dim3((rows + 31) / 32), dim3(64), 0, st, rows, m, X, ldx, L,
-                     run);
+                     run, nullptr);
   return hipGetLastError();
 }
 
@@ -1194,24 +730,6 @@ hipError_t launch_cholqr_ctrl(int *cq, int pass_was_shifted, int *count, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_trinv_lower(int m, const double *L, double *X, hipStream_t st) {
-  hipLaunchKernelGGL(trinv_lower_blocked_kernel, dim3(1), dim3(kCholThreads), 0, st, m, L, X);
-  return hipGetLastError();
-}
-
-hipError_t launch_trinv_upper(int m, const double *R, double *Rinv, hipStream_t st) {
-  hipLaunchKernelGGL(trinv_upper_kernel, dim3(1), dim3(1024), (size_t)m * sizeof(double), st, m, R,
-                     Rinv);
-  return hipGetLastError();
-}
-
-hipError_t launch_gj_inverse(int m, const double *M, double *Minv, double *work, int *flag,
-                             hipStream_t st) {
-  hipLaunchKernelGGL(gj_inverse_kernel, dim3(1), dim3(1024), (size_t)3 * m * sizeof(double), st, m,
-                     M, Minv, work, flag);
-  return hipGetLastError();
-}
-
 hipError_t launch_symmetrize(int m, double *K, double *asym, double *part, hipStream_t st) {
   const int nblk = 64;
   hipLaunchKernelGGL(symmetrize_kernel, dim3(nblk), dim3(256), 0, st, m, K, part);
@@ -1226,29 +744,11 @@ hipError_t launch_orth_err(int m, const double *G, double *out, hipStream_t st) 
   return hipGetLastError();
 }
 
-size_t syev_work_doubles(int m) {
-  size_t off[5];
-  return syev_layout(m, off);
-}
-
-hipError_t launch_syev(int m, const double *K, double *lam, double *Z, double *work, int *flag,
-                       hipStream_t st) {
-  if (m > 1088) return hipErrorInvalidValue;
-  const size_t lds = (size_t)(4 * m + 1024) * sizeof(double);
-  hipLaunchKernelGGL(tridiag_ql_kernel, dim3(1), dim3(1024), lds, st, m, K, work, flag);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int cols_per_block = 4;
-  hipLaunchKernelGGL(syev_backtransform_kernel, dim3((m + cols_per_block - 1) / cols_per_block),
-                     dim3(64 * cols_per_block), 0, st, m, work, lam, Z);
-  return hipGetLastError();
-}
-
 hipError_t launch_increment_combine(int n, int k, const double *lam, const double *V,
                                     const double *c, const double *g, int mode_lru, double *dz,
                                     double *dofs, hipStream_t st) {
   hipLaunchKernelGGL(increment_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, k, lam, V, c, g,
-                     mode_lru, dz, dofs);
+                     mode_lru, dz, dofs, nullptr);
   return hipGetLastError();
 }
 
@@ -1292,6 +792,124 @@ hipError_t launch_check_finite(long long count, const double *x, int *flag, hipS
   long long blocks = (count + 255) / 256;
   if (blocks > 1024) blocks = 1024;
   hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)blocks), dim3(256), 0, st, count, x, flag);
+  return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched launches (one job per problem; see the job structs in the internal header)
+// ---------------------------------------------------------------------------
+
+__global__ void cholqr_reset_batched_kernel(const CqJob *__restrict__ jobs) {
+  if (threadIdx.x == 0) {
+    int *cq = jobs[blockIdx.x].cq;
+    cq[0] = 1;
+    cq[1] = 0;
+    cq[2] = 0;
+  }
+}
+
+__global__ void cholqr_ctrl_batched_kernel(const CqJob *__restrict__ jobs, int pass_was_shifted) {
+  if (threadIdx.x != 0) return;
+  int *cq = jobs[blockIdx.x].cq;
+  if (cq[0] == 0) return;
+  int *count = jobs[blockIdx.x].count;
+  if (count) count[0] += 1;
+  if (pass_was_shifted || cq[2])
+    cq[1] = 0;
+  else
+    cq[1] += 1;
+  cq[2] = 0;
+  if (cq[1] >= 2) cq[0] = 0;
+}
+
+// K <- (K + K^T) / 2, one workgroup per problem.
+__global__ void __launch_bounds__(256) symmetrize_batched_kernel(const SymJob *__restrict__ jobs) {
+  const int m = jobs[blockIdx.x].m;
+  double *K = jobs[blockIdx.x].K;
+  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+    const int i = idx % m, j = idx / m;
+    if (i > j) {
+      const double a = 0.5 * (K[(size_t)j * m + i] + K[(size_t)i * m + j]);
+      K[(size_t)j * m + i] = a;
+      K[(size_t)i * m + j] = a;
+    }
+  }
+}
+
+__global__ void copy_batched_kernel(const CopyJob *__restrict__ jobs) {
+  const CopyJob &J = jobs[blockIdx.y];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < J.count;
+       i += (long long)gridDim.x * blockDim.x)
+    J.dst[i] = J.src[i];
+}
+
+hipError_t launch_gemm_batched(int ta, int tb, int nprob, int maxM, int maxN, double alpha,
+                               double beta, const GemmJob *jobs, hipStream_t st) {
+  if (nprob <= 0 || maxM <= 0 || maxN <= 0) return hipSuccess;
+  dim3 grid((maxM + 31) / 32, (maxN + 31) / 32, nprob);
+#define RIOT_GEMMB(TA_, TB_)                                                                    \
+  hipLaunchKernelGGL((gemm_mfma_kernel<TA_, TB_>), grid, dim3(64), 0, st, 0, 0, 0, nullptr, 0,   \
+                     nullptr, 0, nullptr, 0, alpha, beta, 0, nullptr, nullptr, jobs)
+  if (ta == 0 && tb == 0)
+    RIOT_GEMMB(0, 0);
+  else if (ta == 1 && tb == 0)
+    RIOT_GEMMB(1, 0);
+  else if (ta == 0 && tb == 1)
+    RIOT_GEMMB(0, 1);
+  else
+    RIOT_GEMMB(1, 1);
+#undef RIOT_GEMMB
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_batched(int nprob, int mode, const CholJob *jobs, hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(chol_blocked_kernel, dim3(1, nprob), dim3(kCholThreads), 0, st, 0, nullptr,
+                     nullptr, 0.0, mode, nullptr, nullptr, nullptr, nullptr, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_batched(int nprob, int maxrows, const TrsmJob *jobs, hipStream_t st) {
+  if (nprob <= 0 || maxrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(trsm_rlt_kernel, dim3((maxrows + 31) / 32, nprob), dim3(64), 0, st, 0, 0,
+                     nullptr, 0, nullptr, nullptr, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholqr_reset_batched(int nprob, const CqJob *jobs, hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cholqr_reset_batched_kernel, dim3(nprob), dim3(64), 0, st, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholqr_ctrl_batched(int nprob, int pass_was_shifted, const CqJob *jobs,
+                                      hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cholqr_ctrl_batched_kernel, dim3(nprob), dim3(64), 0, st, jobs,
+                     pass_was_shifted);
+  return hipGetLastError();
+}
+
+hipError_t launch_symmetrize_batched(int nprob, const SymJob *jobs, hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(symmetrize_batched_kernel, dim3(nprob), dim3(256), 0, st, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_increment_batched(int nprob, int maxn, int mode_lru, const IncJob *jobs,
+                                    hipStream_t st) {
+  if (nprob <= 0 || maxn <= 0) return hipSuccess;
+  hipLaunchKernelGGL(increment_kernel, dim3((maxn + 255) / 256, nprob), dim3(256), 0, st, 0, 0,
+                     nullptr, nullptr, nullptr, nullptr, mode_lru, nullptr, nullptr, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_batched(int nprob, long long maxcount, const CopyJob *jobs,
+                               hipStream_t st) {
+  if (nprob <= 0 || maxcount <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((maxcount + 255) / 256, 64);
+  hipLaunchKernelGGL(copy_batched_kernel, dim3((unsigned)blocks, nprob), dim3(256), 0, st, jobs);
   return hipGetLastError();
 }
 

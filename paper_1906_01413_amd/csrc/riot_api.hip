@@ -113,6 +113,7 @@ struct riot_handle {
   riot_desc d{};
   hipStream_t st = nullptr;
   int E = 0, NT = 0, A = 0, S = 0, U = 0, w = 0;
+  int cus = 256;  // compute units of the device the handle was created on
   bool fp32 = false;
   bool linearized = false;
   double base_diag = 0.0;
@@ -128,9 +129,9 @@ struct riot_handle {
   float *xs32 = nullptr;
   void *fgrad = nullptr, *f = nullptr;
   double *LW = nullptr, *LAM = nullptr;
-  double *Om = nullptr, *Y = nullptr, *Q = nullptr, *Q0 = nullptr, *Qt = nullptr;
-  double *G = nullptr, *R = nullptr, *Rinv = nullptr, *B1 = nullptr, *B2 = nullptr,
-         *B2i = nullptr, *K = nullptr, *Zs = nullptr, *gjw = nullptr, *sywork = nullptr;
+  double *Om = nullptr, *Y = nullptr, *Q = nullptr, *Q0 = nullptr;
+  double *G = nullptr, *R = nullptr, *B1 = nullptr, *B2 = nullptr, *K = nullptr, *Zs = nullptr,
+         *sywork = nullptr;
   double *partial = nullptr, *cvec = nullptr, *scal = nullptr, *cgv = nullptr;
   int *flags = nullptr;
   ModelView mv{};
@@ -171,17 +172,13 @@ size_t carve(riot_handle &h, void *base) {
   h.Y = c.take<double>(nm);
   h.Q = c.take<double>(nm);
   h.Q0 = c.take<double>(nm);
-  h.Qt = c.take<double>(nm);
   const size_t m2 = (size_t)mm * mm;
   h.G = c.take<double>(m2);
   h.R = c.take<double>(m2);
-  h.Rinv = c.take<double>(m2);
   h.B1 = c.take<double>(m2);
   h.B2 = c.take<double>(m2);
-  h.B2i = c.take<double>(m2);
   h.K = c.take<double>(m2);
   h.Zs = c.take<double>(m2);
-  h.gjw = c.take<double>(2 * m2);
   h.sywork = c.take<double>(eig_work_doubles(mm));
   h.partial = c.take<double>(std::max((size_t)kSplitK * m2, (size_t)kSplitK * mm));
   h.cvec = c.take<double>(mm);
@@ -303,44 +300,43 @@ size_t riot_workspace_bytes(const riot_desc *desc) {
   return carve(h, nullptr);
 }
 
-riot_status riot_init(const riot_desc *desc, void *workspace, size_t bytes, void *hip_stream,
-                      riot_handle **out) {
-  if (!out) return RIOT_E_ARG;
-  *out = nullptr;
-  if (!desc_valid(desc) || !workspace) return RIOT_E_ARG;
-  if (reinterpret_cast<uintptr_t>(workspace) % 256) return RIOT_E_WORKSPACE;
-  riot_handle *h = new (std::nothrow) riot_handle();
-  if (!h) return RIOT_E_ARG;
+// Set up a handle in `workspace` (shared by riot_init and the batch): carve, host tables,
+// uploads. Synchronises the stream before returning (the host tables are local).
+static riot_status init_handle(riot_handle *h, const riot_desc *desc, void *workspace,
+                               size_t bytes, hipStream_t st) {
   ObsPlan plan;
-  if (!prepare(*h, desc, &plan)) {
-    delete h;
-    return RIOT_E_ARG;
-  }
+  if (!prepare(*h, desc, &plan)) return RIOT_E_ARG;
   const size_t need = carve(*h, nullptr);
-  if (bytes < need) {
-    delete h;
-    return RIOT_E_WORKSPACE;
-  }
+  if (bytes < need) return RIOT_E_WORKSPACE;
   carve(*h, workspace);
-  h->st = static_cast<hipStream_t>(hip_stream);
+  h->st = st;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0)
+      h->cus = cus;
+  }
   fill_view(*h);
   const riot_desc &d = h->d;
   const int n = d.n, w = h->w;
-  // host-side tables
+  // host-side tables: the first row of L (wrapped taps) and of B = L L^T
   std::vector<double> lrow(n, 0.0), brow(n, 0.0);
   for (int dd = -w; dd <= w; ++dd) {
     int j = dd % n;
     if (j < 0) j += n;
     lrow[j] += d.l_taps[std::abs(dd)];
   }
+  std::vector<int> nz;
+  for (int j = 0; j < n; ++j)
+    if (lrow[j] != 0.0) nz.push_back(j);
   for (int dd = 0; dd < n; ++dd) {
     double s = 0.0;
-    for (int j = 0; j < n; ++j) s += lrow[j] * lrow[(j + dd) % n];
+    for (int j : nz) s += lrow[j] * lrow[(j + dd) % n];
     brow[dd] = s;
   }
   h->base_diag = brow[0];
   std::vector<float> wgt32(plan.wgt.begin(), plan.wgt.end());
-  hipStream_t st = h->st;
   riot_status rs = RIOT_OK;
   auto cp = [&](void *dst, const void *src, size_t b) {
     if (b && hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, st) != hipSuccess) rs = RIOT_E_HIP;
@@ -368,6 +364,19 @@ riot_status riot_init(const riot_desc *desc, void *workspace, size_t bytes, void
   h->d.y = nullptr;
   h->d.rinv = nullptr;
   h->d.l_taps = nullptr;
+  return rs;
+}
+
+riot_status riot_init(const riot_desc *desc, void *workspace, size_t bytes, void *hip_stream,
+                      riot_handle **out) {
+  if (!out) return RIOT_E_ARG;
+  *out = nullptr;
+  if (!desc_valid(desc) || !workspace) return RIOT_E_ARG;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return RIOT_E_WORKSPACE;
+  riot_handle *h = new (std::nothrow) riot_handle();
+  if (!h) return RIOT_E_ARG;
+  const riot_status rs =
+      init_handle(h, desc, workspace, bytes, static_cast<hipStream_t>(hip_stream));
   if (rs != RIOT_OK) {
     delete h;
     return rs;
@@ -588,6 +597,596 @@ riot_status riot_philox_normal(riot_handle *h, int32_t n, int32_t m, uint64_t se
                                uint64_t stream, double *out) {
   if (!h || !out || n < 1 || m < 1) return RIOT_E_ARG;
   RIOT_HIP(launch_philox_normal((long long)n * m, seed, stream, out, h->st));
+  return RIOT_OK;
+}
+
+
+// ===========================================================================
+// Batches of independent problems (a persistent TL/AD launch over all probes of all
+// problems, batched linear algebra, graph capture of the whole inner loop).
+// ===========================================================================
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kBatchMaxN = 2048;  // NT <= 256 threads at 8 elements per lane
+constexpr int kBatchMaxM = 278;   // register-resident tridiagonalisation bound
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+struct riot_batch {
+  int nprob = 0;
+  hipStream_t st = nullptr;
+  bool fp32 = false;
+  int cus = 256;
+  std::vector<riot_handle *> hs;
+  std::vector<int> n, m, T, nobs;
+  std::vector<size_t> off_n, off_m, off_nm, off_obs;
+  size_t tot_n = 0, tot_m = 0, tot_nm = 0, tot_obs = 0;
+  int maxn = 0, maxm = 0, maxU = 0, maxext = 0;
+  // packed caller-visible buffers
+  double *X = nullptr, *Gr = nullptr, *Lam = nullptr, *V = nullptr, *Dz = nullptr, *Dx = nullptr,
+         *D = nullptr;
+  // device job tables
+  riot::TrajJob *traj = nullptr;
+  riot::InnovJob *innov = nullptr;
+  riot::TladProb *grad_probs = nullptr, *hvp_probs = nullptr;
+  riot::TladTile *tiles = nullptr;  // [grad wg | grad wave | hvp wg | hvp wave]
+  int n_grad_wg = 0, n_grad_wave = 0, n_hvp_wg = 0, n_hvp_wave = 0, tile_cap = 0;
+  int *counters = nullptr;
+  riot::ApplyLJobE *aL_grad = nullptr, *aL_in = nullptr, *aL_out = nullptr, *aL_dx = nullptr;
+  riot::PhiloxJob *philox = nullptr;
+  riot::CopyJob *cp_Y = nullptr, *cp_B2 = nullptr;
+  riot::CqJob *cq_Y = nullptr, *cq_B2 = nullptr;
+  riot::GemmJob *gram_Q = nullptr, *gram_Z = nullptr, *g_B1 = nullptr, *g_B2 = nullptr,
+                *g_K = nullptr, *g_V = nullptr, *g_c = nullptr;
+  riot::CholJob *ch_Q = nullptr, *ch_Z = nullptr;
+  riot::TrsmJob *tr_Q = nullptr, *tr_Z = nullptr, *tr_B1 = nullptr;
+  riot::SymJob *sym = nullptr;
+  riot::EigJob *eig = nullptr;
+  riot::IncJob *inc = nullptr;
+  // layout chosen by riot_batch_autotune (or the defaults)
+  int nwg = 0;
+  int wave_max_nt = 64;  // problems with NT <= this use member-per-wave tiles (0: none)
+  uint64_t seed = 0;
+  hipGraphExec_t graph = nullptr;
+  ~riot_batch() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    for (auto *h : hs) delete h;
+  }
+};
+
+namespace {
+
+template <typename T>
+riot_status upload(T *dst, const std::vector<T> &src, hipStream_t st) {
+  if (src.empty()) return RIOT_OK;
+  return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st) ==
+                 hipSuccess
+             ? RIOT_OK
+             : RIOT_E_HIP;
+}
+
+bool batch_desc_ok(const riot_desc &d) {
+  return desc_valid(&d) && d.n % 8 == 0 && d.n <= kBatchMaxN && d.m_max <= kBatchMaxM &&
+         d.m_max <= d.n;
+}
+
+// Workspace of the batch-level part: packed buffers and job tables.
+struct BatchCarve {
+  size_t off = 0;
+  char *base;
+  explicit BatchCarve(void *b) : base(static_cast<char *>(b)) {}
+  template <typename T>
+  T *take(size_t count) {
+    off = align256(off);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += std::max<size_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+size_t batch_carve(riot_batch &b, void *base, size_t tiles_cap) {
+  BatchCarve c(base);
+  const size_t P = b.nprob;
+  b.X = c.take<double>(b.tot_n);
+  b.Gr = c.take<double>(b.tot_n);
+  b.Dz = c.take<double>(b.tot_n);
+  b.Dx = c.take<double>(b.tot_n);
+  b.Lam = c.take<double>(b.tot_m);
+  b.V = c.take<double>(b.tot_nm);
+  b.D = c.take<double>(b.tot_obs);
+  b.traj = c.take<riot::TrajJob>(P);
+  b.innov = c.take<riot::InnovJob>(P);
+  b.grad_probs = c.take<riot::TladProb>(P);
+  b.hvp_probs = c.take<riot::TladProb>(P);
+  b.tiles = c.take<riot::TladTile>(tiles_cap);
+  b.counters = c.take<int>(4);
+  b.aL_grad = c.take<riot::ApplyLJobE>(P);
+  b.aL_in = c.take<riot::ApplyLJobE>(P);
+  b.aL_out = c.take<riot::ApplyLJobE>(P);
+  b.aL_dx = c.take<riot::ApplyLJobE>(P);
+  b.philox = c.take<riot::PhiloxJob>(P);
+  b.cp_Y = c.take<riot::CopyJob>(P);
+  b.cp_B2 = c.take<riot::CopyJob>(P);
+  b.cq_Y = c.take<riot::CqJob>(P);
+  b.cq_B2 = c.take<riot::CqJob>(P);
+  b.gram_Q = c.take<riot::GemmJob>(P);
+  b.gram_Z = c.take<riot::GemmJob>(P);
+  b.g_B1 = c.take<riot::GemmJob>(P);
+  b.g_B2 = c.take<riot::GemmJob>(P);
+  b.g_K = c.take<riot::GemmJob>(P);
+  b.g_V = c.take<riot::GemmJob>(P);
+  b.g_c = c.take<riot::GemmJob>(P);
+  b.ch_Q = c.take<riot::CholJob>(P);
+  b.ch_Z = c.take<riot::CholJob>(P);
+  b.tr_Q = c.take<riot::TrsmJob>(P);
+  b.tr_Z = c.take<riot::TrsmJob>(P);
+  b.tr_B1 = c.take<riot::TrsmJob>(P);
+  b.sym = c.take<riot::SymJob>(P);
+  b.eig = c.take<riot::EigJob>(P);
+  b.inc = c.take<riot::IncJob>(P);
+  return align256(c.off);
+}
+
+// Tile lists of the two persistent launches for the current layout: longest first.
+riot_status batch_build_tiles(riot_batch &b) {
+  std::vector<int> order(b.nprob);
+  for (int j = 0; j < b.nprob; ++j) order[j] = j;
+  auto cost = [&](int j) { return (double)b.T[j] * (double)b.n[j]; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost(a) > cost(c); });
+  std::vector<riot::TladTile> gw, gv, hw, hv;
+  for (int j : order) {
+    const bool wave = b.hs[j]->NT <= b.wave_max_nt;
+    (wave ? gv : gw).push_back({j, 0});
+    for (int i = 0; i < b.m[j]; ++i) (wave ? hv : hw).push_back({j, i});
+  }
+  std::vector<riot::TladTile> all;
+  all.insert(all.end(), gw.begin(), gw.end());
+  all.insert(all.end(), gv.begin(), gv.end());
+  all.insert(all.end(), hw.begin(), hw.end());
+  all.insert(all.end(), hv.begin(), hv.end());
+  if ((int)all.size() > b.tile_cap) return RIOT_E_ARG;
+  b.n_grad_wg = (int)gw.size();
+  b.n_grad_wave = (int)gv.size();
+  b.n_hvp_wg = (int)hw.size();
+  b.n_hvp_wave = (int)hv.size();
+  return upload(b.tiles, all, b.st);
+}
+
+riot_status batch_tables(riot_batch &b) {
+  const int P = b.nprob;
+  std::vector<riot::TrajJob> traj(P);
+  std::vector<riot::InnovJob> innov(P);
+  std::vector<riot::TladProb> gp(P), hp(P);
+  std::vector<riot::ApplyLJobE> aG(P), aI(P), aO(P), aD(P);
+  std::vector<riot::PhiloxJob> ph(P);
+  std::vector<riot::CopyJob> cY(P), cB(P);
+  std::vector<riot::CqJob> qY(P), qB(P);
+  std::vector<riot::GemmJob> gQ(P), gZ(P), g1(P), g2(P), gK(P), gV(P), gc(P);
+  std::vector<riot::CholJob> hQ(P), hZ(P);
+  std::vector<riot::TrsmJob> tQ(P), tZ(P), t1(P);
+  std::vector<riot::SymJob> sy(P);
+  std::vector<riot::EigJob> eg(P);
+  std::vector<riot::IncJob> ic(P);
+  const double u = 0x1.0p-53;
+  for (int j = 0; j < P; ++j) {
+    riot_handle &h = *b.hs[j];
+    const int n = b.n[j], m = b.m[j];
+    double *x = b.X + b.off_n[j], *g = b.Gr + b.off_n[j];
+    double *lam = b.Lam + b.off_m[j], *V = b.V + b.off_nm[j];
+    double *d = b.D + b.off_obs[j];
+    traj[j] = {h.mv, x, h.xs64, h.xs32};
+    innov[j] = {h.mv, h.xs64, h.obs_step, h.obs_idx, h.u_optr, h.u_olist, h.y, h.rinv, d, h.fgrad};
+    gp[j] = {h.mv, nullptr, h.LAM, nullptr, h.fgrad};
+    hp[j] = {h.mv, h.LW, h.LAM, h.f, nullptr};
+    aG[j] = {n, h.w, 1, h.taps, h.LAM, g, nullptr, 2};
+    aI[j] = {n, h.w, m, h.taps, h.Om, h.LW, nullptr, 0};
+    aO[j] = {n, h.w, m, h.taps, h.LAM, h.Y, nullptr, 0};
+    aD[j] = {n, h.w, 1, h.taps, b.Dz + b.off_n[j], b.Dx + b.off_n[j], nullptr, 0};
+    ph[j] = {(long long)n * m, (unsigned long long)j, h.Om};
+    cY[j] = {(long long)n * m, h.Y, h.Q};
+    cB[j] = {(long long)m * m, h.B2, h.Zs};
+    int *cq1 = h.flags + 12, *cq2 = h.flags + 12;
+    qY[j] = {cq1, h.flags + 5};
+    qB[j] = {cq2, nullptr};
+    gQ[j] = {m, m, n, h.Q, n, h.Q, n, h.G, m, cq1};
+    gZ[j] = {m, m, m, h.Zs, m, h.Zs, m, h.G, m, cq2};
+    g1[j] = {m, m, n, h.Q, n, h.Y, n, h.B1, m, nullptr};
+    g2[j] = {m, m, n, h.Q, n, h.Om, n, h.B2, m, nullptr};
+    gK[j] = {m, m, m, h.B1, m, h.Zs, m, h.K, m, nullptr};
+    gV[j] = {n, m, m, h.Q, n, h.Zs, m, V, n, nullptr};
+    gc[j] = {m, 1, n, V, n, g, n, h.cvec, m, nullptr};
+    const double srelY = 11.0 * ((double)m * n + (double)m * (m + 1)) * u;
+    const double srelZ = 11.0 * ((double)m * m + (double)m * (m + 1)) * u;
+    hQ[j] = {m, h.G, h.R, srelY, h.flags + 0, h.flags + 4, cq1, cq1 + 2};
+    hZ[j] = {m, h.G, h.R, srelZ, h.flags + 1, h.flags + 4, cq2, cq2 + 2};
+    tQ[j] = {n, m, h.Q, n, h.R, cq1};
+    tZ[j] = {m, m, h.Zs, m, h.R, cq2};
+    t1[j] = {m, m, h.B1, m, h.R, cq2};
+    sy[j] = {m, h.K};
+    eg[j] = {m, h.K, lam, h.Zs, h.sywork, h.flags + 2};
+    ic[j] = {n, m, lam, V, h.cvec, g, b.Dz + b.off_n[j], h.scal + 4};
+  }
+  riot_status rs = RIOT_OK;
+  auto up = [&](auto *dst, const auto &src) {
+    if (rs == RIOT_OK) rs = upload(dst, src, b.st);
+  };
+  up(b.traj, traj);
+  up(b.innov, innov);
+  up(b.grad_probs, gp);
+  up(b.hvp_probs, hp);
+  up(b.aL_grad, aG);
+  up(b.aL_in, aI);
+  up(b.aL_out, aO);
+  up(b.aL_dx, aD);
+  up(b.philox, ph);
+  up(b.cp_Y, cY);
+  up(b.cp_B2, cB);
+  up(b.cq_Y, qY);
+  up(b.cq_B2, qB);
+  up(b.gram_Q, gQ);
+  up(b.gram_Z, gZ);
+  up(b.g_B1, g1);
+  up(b.g_B2, g2);
+  up(b.g_K, gK);
+  up(b.g_V, gV);
+  up(b.g_c, gc);
+  up(b.ch_Q, hQ);
+  up(b.ch_Z, hZ);
+  up(b.tr_Q, tQ);
+  up(b.tr_Z, tZ);
+  up(b.tr_B1, t1);
+  up(b.sym, sy);
+  up(b.eig, eg);
+  up(b.inc, ic);
+  if (rs == RIOT_OK) rs = batch_build_tiles(b);
+  if (hipStreamSynchronize(b.st) != hipSuccess) rs = RIOT_E_HIP;
+  return rs;
+}
+
+#define RIOT_BHIP(call)                        \
+  do {                                         \
+    if ((call) != hipSuccess) return RIOT_E_HIP; \
+  } while (0)
+
+riot_status batch_hvp(riot_batch &b, int mode, long long *clk = nullptr) {
+  const riot::TladTile *t = b.tiles;
+  if (mode == 1)
+    return riot::launch_tlad_persistent(b.nwg, 1, b.grad_probs, t, b.n_grad_wg, t + b.n_grad_wg,
+                                        b.n_grad_wave, b.counters, b.fp32, b.st) == hipSuccess
+               ? RIOT_OK
+               : RIOT_E_HIP;
+  const riot::TladTile *th = t + b.n_grad_wg + b.n_grad_wave;
+  return riot::launch_tlad_persistent(b.nwg, mode, b.hvp_probs, th, b.n_hvp_wg, th + b.n_hvp_wg,
+                                      b.n_hvp_wave, b.counters + 2, b.fp32, b.st, clk) == hipSuccess
+             ? RIOT_OK
+             : RIOT_E_HIP;
+}
+
+// Adaptive CholeskyQR of every problem's block (see cholqr): X_j <- orth(X_j), companion
+// C_j receiving the same right factors.
+riot_status batch_cholqr(riot_batch &b, const riot::CqJob *cq, const riot::GemmJob *gram,
+                         const riot::CholJob *ch, const riot::TrsmJob *tr, const riot::TrsmJob *comp,
+                         int maxrows, bool shifted) {
+  hipStream_t st = b.st;
+  RIOT_BHIP(riot::launch_cholqr_reset_batched(b.nprob, cq, st));
+  for (int pass = 0; pass < 8; ++pass) {
+    const bool sh = shifted && pass == 0;
+    RIOT_BHIP(riot::launch_gemm_batched(1, 0, b.nprob, b.maxm, b.maxm, 1.0, 0.0, gram, st));
+    RIOT_BHIP(riot::launch_chol_batched(b.nprob, sh ? 1 : 2, ch, st));
+    RIOT_BHIP(riot::launch_trsm_batched(b.nprob, maxrows, tr, st));
+    if (comp) RIOT_BHIP(riot::launch_trsm_batched(b.nprob, b.maxm, comp, st));
+    RIOT_BHIP(riot::launch_cholqr_ctrl_batched(b.nprob, sh ? 1 : 0, cq, st));
+  }
+  return RIOT_OK;
+}
+
+riot_status batch_pipeline(riot_batch &b) {
+  hipStream_t st = b.st;
+  riot_status rs;
+  // a1-a2: trajectories, innovations, gradients g = -L G^T R^{-1} d (first outer loop)
+  RIOT_BHIP(riot::launch_trajectory_batched(b.nprob, b.traj, st));
+  RIOT_BHIP(riot::launch_innovation_batched(b.nprob, b.maxU, b.innov, b.fp32, st));
+  if ((rs = batch_hvp(b, 1)) != RIOT_OK) return rs;
+  RIOT_BHIP(riot::launch_apply_L_batched(b.nprob, 1, b.maxext, b.aL_grad, st));
+  // a3-a4: probes and Hessian-probe products
+  RIOT_BHIP(riot::launch_philox_batched(b.nprob, (long long)b.maxn * b.maxm, b.seed, b.philox, st));
+  RIOT_BHIP(riot::launch_apply_L_batched(b.nprob, b.maxm, b.maxext, b.aL_in, st));
+  if ((rs = batch_hvp(b, 0)) != RIOT_OK) return rs;
+  RIOT_BHIP(riot::launch_apply_L_batched(b.nprob, b.maxm, b.maxext, b.aL_out, st));
+  // a6: Q = orth(Y)
+  RIOT_BHIP(riot::launch_copy_batched(b.nprob, (long long)b.maxn * b.maxm, b.cp_Y, st));
+  if ((rs = batch_cholqr(b, b.cq_Y, b.gram_Q, b.ch_Q, b.tr_Q, nullptr, b.maxn, true)) != RIOT_OK)
+    return rs;
+  // a7: projections and K
+  RIOT_BHIP(riot::launch_gemm_batched(1, 0, b.nprob, b.maxm, b.maxm, 1.0, 0.0, b.g_B1, st));
+  RIOT_BHIP(riot::launch_gemm_batched(1, 0, b.nprob, b.maxm, b.maxm, 1.0, 0.0, b.g_B2, st));
+  RIOT_BHIP(riot::launch_copy_batched(b.nprob, (long long)b.maxm * b.maxm, b.cp_B2, st));
+  if ((rs = batch_cholqr(b, b.cq_B2, b.gram_Z, b.ch_Z, b.tr_Z, b.tr_B1, b.maxm, false)) != RIOT_OK)
+    return rs;
+  RIOT_BHIP(riot::launch_gemm_batched(0, 1, b.nprob, b.maxm, b.maxm, 1.0, 0.0, b.g_K, st));
+  RIOT_BHIP(riot::launch_symmetrize_batched(b.nprob, b.sym, st));
+  // a8: eigen-solve and Ritz vectors
+  RIOT_BHIP(riot::launch_eig_batched(b.nprob, b.maxm, b.eig, st));
+  RIOT_BHIP(riot::launch_gemm_batched(0, 0, b.nprob, b.maxn, b.maxm, 1.0, 0.0, b.g_V, st));
+  // a9: adaptive increment from all m Ritz pairs, dx = L dz
+  RIOT_BHIP(riot::launch_gemm_batched(1, 0, b.nprob, b.maxm, 1, 1.0, 0.0, b.g_c, st));
+  RIOT_BHIP(riot::launch_increment_batched(b.nprob, b.maxn, 2, b.inc, st));
+  RIOT_BHIP(riot::launch_apply_L_batched(b.nprob, 1, b.maxext, b.aL_dx, st));
+  return RIOT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t riot_batch_workspace_bytes(int32_t nprob, const riot_desc *descs) {
+  if (nprob < 1 || !descs) return 0;
+  size_t tot = 0, tn = 0, tm = 0, tnm = 0, tobs = 0, tiles = 0;
+  for (int j = 0; j < nprob; ++j) {
+    riot_desc d = descs[j];
+    d.elems_per_lane = 8;
+    if (!batch_desc_ok(d)) return 0;
+    const size_t w = riot_workspace_bytes(&d);
+    if (!w) return 0;
+    tot += align256(w);
+    tn += d.n;
+    tm += d.m_max;
+    tnm += (size_t)d.n * d.m_max;
+    tobs += std::max(d.nobs, 1);
+    tiles += 1 + d.m_max;
+  }
+  riot_batch b;
+  b.nprob = nprob;
+  b.tot_n = tn, b.tot_m = tm, b.tot_nm = tnm, b.tot_obs = tobs;
+  return tot + batch_carve(b, nullptr, tiles) + 256;
+}
+
+riot_status riot_batch_init(int32_t nprob, const riot_desc *descs, void *workspace, size_t bytes,
+                            void *hip_stream, riot_batch **out) {
+  if (!out) return RIOT_E_ARG;
+  *out = nullptr;
+  if (nprob < 1 || !descs || !workspace) return RIOT_E_ARG;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return RIOT_E_WORKSPACE;
+  const size_t need = riot_batch_workspace_bytes(nprob, descs);
+  if (!need) return RIOT_E_ARG;
+  if (bytes < need) return RIOT_E_WORKSPACE;
+  riot_batch *b = new (std::nothrow) riot_batch();
+  if (!b) return RIOT_E_ARG;
+  b->nprob = nprob;
+  b->st = static_cast<hipStream_t>(hip_stream);
+  b->fp32 = descs[0].prec == RIOT_FP32_TLAD;
+  char *base = static_cast<char *>(workspace);
+  size_t off = 0;
+  riot_status rs = RIOT_OK;
+  for (int j = 0; j < nprob && rs == RIOT_OK; ++j) {
+    riot_desc d = descs[j];
+    d.elems_per_lane = 8;
+    if ((d.prec == RIOT_FP32_TLAD) != b->fp32) {
+      rs = RIOT_E_ARG;
+      break;
+    }
+    riot_handle *h = new (std::nothrow) riot_handle();
+    if (!h) {
+      rs = RIOT_E_ARG;
+      break;
+    }
+    b->hs.push_back(h);
+    const size_t w = riot_workspace_bytes(&d);
+    rs = init_handle(h, &d, base + off, w, b->st);
+    off += align256(w);
+    b->n.push_back(d.n);
+    b->m.push_back(d.m_max);
+    b->T.push_back(d.nsteps);
+    b->nobs.push_back(d.nobs);
+    b->off_n.push_back(b->tot_n);
+    b->off_m.push_back(b->tot_m);
+    b->off_nm.push_back(b->tot_nm);
+    b->off_obs.push_back(b->tot_obs);
+    b->tot_n += d.n;
+    b->tot_m += d.m_max;
+    b->tot_nm += (size_t)d.n * d.m_max;
+    b->tot_obs += std::max(d.nobs, 1);
+    b->maxn = std::max(b->maxn, d.n);
+    b->maxm = std::max(b->maxm, d.m_max);
+    b->maxU = std::max(b->maxU, h->U);
+    b->maxext = std::max(b->maxext, d.n + 2 * h->w);
+    b->cus = h->cus;
+  }
+  if (rs == RIOT_OK) {
+    for (int j = 0; j < nprob; ++j) b->tile_cap += 1 + b->m[j];
+    batch_carve(*b, base + off, b->tile_cap);
+    b->nwg = 2 * b->cus;
+    rs = batch_tables(*b);
+  }
+  if (rs != RIOT_OK) {
+    delete b;
+    return rs;
+  }
+  *out = b;
+  return RIOT_OK;
+}
+
+void riot_batch_free(riot_batch *b) { delete b; }
+
+riot_status riot_batch_buffers(riot_batch *b, riot_batch_io *io) {
+  if (!b || !io) return RIOT_E_ARG;
+  io->x = b->X;
+  io->grad = b->Gr;
+  io->lambda = b->Lam;
+  io->V = b->V;
+  io->dz = b->Dz;
+  io->dx = b->Dx;
+  io->d = b->D;
+  return RIOT_OK;
+}
+
+riot_status riot_batch_run(riot_batch *b, uint64_t seed) {
+  if (!b) return RIOT_E_ARG;
+  if (b->graph) return RIOT_E_STATE;
+  b->seed = seed;
+  const riot_status rs = batch_pipeline(*b);
+  if (rs == RIOT_OK)
+    for (auto *h : b->hs) h->linearized = true;  // trajectories are stored for every problem
+  return rs;
+}
+
+riot_status riot_batch_set_layout(riot_batch *b, int32_t workgroups, int32_t wave_max_threads) {
+  if (!b || workgroups < 1 || wave_max_threads < 0 || wave_max_threads > 64) return RIOT_E_ARG;
+  if (b->graph) return RIOT_E_STATE;
+  b->nwg = workgroups;
+  b->wave_max_nt = wave_max_threads;
+  const riot_status rs = batch_build_tiles(*b);
+  if (rs != RIOT_OK) return rs;
+  return hipStreamSynchronize(b->st) == hipSuccess ? RIOT_OK : RIOT_E_HIP;
+}
+
+riot_status riot_batch_autotune(riot_batch *b, int32_t *workgroups_out,
+                                int32_t *wave_max_threads_out, float *ms_out) {
+  if (!b) return RIOT_E_ARG;
+  if (b->graph) return RIOT_E_STATE;
+  // inputs of the timed launches: the current trajectories and deterministic probes
+  b->seed = 0x5eedULL;
+  RIOT_BHIP(riot::launch_trajectory_batched(b->nprob, b->traj, b->st));
+  RIOT_BHIP(riot::launch_philox_batched(b->nprob, (long long)b->maxn * b->maxm, b->seed, b->philox,
+                                        b->st));
+  RIOT_BHIP(riot::launch_apply_L_batched(b->nprob, b->maxm, b->maxext, b->aL_in, b->st));
+  hipEvent_t e0, e1;
+  RIOT_BHIP(hipEventCreate(&e0));
+  RIOT_BHIP(hipEventCreate(&e1));
+  const int cand_wg[3] = {b->cus, 2 * b->cus, 3 * b->cus};
+  const int cand_wave[2] = {0, 64};
+  float best = 1e30f;
+  int best_wg = b->nwg, best_wave = b->wave_max_nt;
+  riot_status rs = RIOT_OK;
+  for (int wv : cand_wave) {
+    for (int wg : cand_wg) {
+      b->nwg = wg;
+      b->wave_max_nt = wv;
+      if ((rs = batch_build_tiles(*b)) != RIOT_OK) break;
+      float ms = 1e30f;
+      for (int rep = 0; rep < 3 && rs == RIOT_OK; ++rep) {
+        if (hipEventRecord(e0, b->st) != hipSuccess) rs = RIOT_E_HIP;
+        if (rs == RIOT_OK) rs = batch_hvp(*b, 0);
+        if (rs == RIOT_OK && hipEventRecord(e1, b->st) != hipSuccess) rs = RIOT_E_HIP;
+        if (rs == RIOT_OK && hipEventSynchronize(e1) != hipSuccess) rs = RIOT_E_HIP;
+        float t = 0.f;
+        if (rs == RIOT_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rs = RIOT_E_HIP;
+        if (rep > 0) ms = std::min(ms, t);  // the first run is a warm-up
+      }
+      if (rs != RIOT_OK) break;
+      if (ms < best) best = ms, best_wg = wg, best_wave = wv;
+    }
+    if (rs != RIOT_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rs != RIOT_OK) return rs;
+  b->nwg = best_wg;
+  b->wave_max_nt = best_wave;
+  if ((rs = batch_build_tiles(*b)) != RIOT_OK) return rs;
+  if (hipStreamSynchronize(b->st) != hipSuccess) return RIOT_E_HIP;
+  if (workgroups_out) *workgroups_out = best_wg;
+  if (wave_max_threads_out) *wave_max_threads_out = best_wave;
+  if (ms_out) *ms_out = best;
+  return RIOT_OK;
+}
+
+riot_status riot_batch_capture(riot_batch *b, uint64_t seed) {
+  if (!b) return RIOT_E_ARG;
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  if (b->st == nullptr) return RIOT_E_STATE;  // the legacy default stream cannot be captured
+  b->seed = seed;
+  RIOT_BHIP(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+  const riot_status rs = batch_pipeline(*b);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(b->st, &g);
+  if (rs != RIOT_OK || ec != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return rs != RIOT_OK ? rs : RIOT_E_HIP;
+  }
+  for (auto *h : b->hs) h->linearized = true;
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return RIOT_E_HIP;
+  b->graph = ex;
+  return RIOT_OK;
+}
+
+riot_status riot_batch_replay(riot_batch *b) {
+  if (!b || !b->graph) return RIOT_E_STATE;
+  return hipGraphLaunch(b->graph, b->st) == hipSuccess ? RIOT_OK : RIOT_E_HIP;
+}
+
+riot_status riot_batch_profile(riot_batch *b, float *ms, double *busy_frac, int32_t *tiles) {
+  if (!b) return RIOT_E_ARG;
+  if (b->graph) return RIOT_E_STATE;
+  const int nt = b->n_hvp_wg + b->n_hvp_wave;
+  if (nt == 0) return RIOT_E_STATE;
+  long long *clk = nullptr;
+  if (hipMalloc(&clk, (size_t)2 * nt * sizeof(long long)) != hipSuccess) return RIOT_E_HIP;
+  hipEvent_t e0, e1;
+  riot_status rs = RIOT_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rs = RIOT_E_HIP;
+  if (rs == RIOT_OK && hipEventRecord(e0, b->st) != hipSuccess) rs = RIOT_E_HIP;
+  if (rs == RIOT_OK) rs = batch_hvp(*b, 0, clk);
+  if (rs == RIOT_OK && hipEventRecord(e1, b->st) != hipSuccess) rs = RIOT_E_HIP;
+  std::vector<long long> t(2 * (size_t)nt);
+  if (rs == RIOT_OK && hipMemcpyAsync(t.data(), clk, t.size() * sizeof(long long),
+                                      hipMemcpyDeviceToHost, b->st) != hipSuccess)
+    rs = RIOT_E_HIP;
+  if (rs == RIOT_OK && hipStreamSynchronize(b->st) != hipSuccess) rs = RIOT_E_HIP;
+  float el = 0.f;
+  if (rs == RIOT_OK && hipEventElapsedTime(&el, e0, e1) != hipSuccess) rs = RIOT_E_HIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(clk);
+  if (rs != RIOT_OK) return rs;
+  // busy time of every slot (a workgroup tile occupies four waves, a wave tile one) over
+  // the slots available (four waves per workgroup that can be resident) times the makespan
+  long long lo = t[0], hi = t[1];
+  double busy = 0.0;
+  for (int i = 0; i < nt; ++i) {
+    lo = std::min(lo, t[2 * i]);
+    hi = std::max(hi, t[2 * i + 1]);
+    busy += (double)(t[2 * i + 1] - t[2 * i]) * (i < b->n_hvp_wg ? 4.0 : 1.0);
+  }
+  // workgroups resident at once: the launch's, capped by what the compute units hold
+  const int per_cu = riot::tlad_persistent_resident_per_cu(b->fp32);
+  const double slots = 4.0 * std::min(b->nwg, per_cu > 0 ? per_cu * b->cus : b->nwg);
+  if (ms) *ms = el;
+  if (busy_frac) *busy_frac = hi > lo ? busy / (slots * (double)(hi - lo)) : 0.0;
+  if (tiles) *tiles = nt;
+  return RIOT_OK;
+}
+
+int32_t riot_gaussian_taps(double ell, double sigma_b, int32_t max_taps, double *taps) {
+  if (!(ell > 0.0) || !(sigma_b > 0.0) || !std::isfinite(ell) || !std::isfinite(sigma_b))
+    return -1;
+  const int w = (int)std::ceil(6.25 * ell);
+  if (!taps) return w;
+  if (max_taps < w + 1) return -1;
+  double s2 = 0.0;
+  for (int d = -w; d <= w; ++d) {
+    const double k = std::exp(-(double)d * d / (ell * ell));
+    s2 += k * k;
+  }
+  const double c = sigma_b / std::sqrt(s2);
+  for (int d = 0; d <= w; ++d) taps[d] = c * std::exp(-(double)d * d / (ell * ell));
+  return w;
+}
+
+riot_status riot_batch_problem(riot_batch *b, int32_t j, riot_handle **h) {
+  if (!b || !h || j < 0 || j >= b->nprob) return RIOT_E_ARG;
+  *h = b->hs[j];
   return RIOT_OK;
 }
 

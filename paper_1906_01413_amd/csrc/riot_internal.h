@@ -11,6 +11,67 @@
 namespace riot {
 
 // ---------------------------------------------------------------------------
+// Batched launches: one job per problem, the problem taken from a grid dimension,
+// so that one launch serves a whole batch of independent, differently sized problems.
+// ---------------------------------------------------------------------------
+struct GemmJob {
+  int M, N, K;
+  const double *A;
+  int lda;
+  const double *B;
+  int ldb;
+  double *C;
+  int ldc;
+  const int *run;  // optional predicate (0: skip this problem)
+};
+struct CholJob {
+  int m;
+  const double *G;
+  double *L;
+  double shift_rel;
+  int *flag, *shifts;
+  const int *run;
+  int *modflag;
+};
+struct TrsmJob {
+  int rows, m;
+  double *X;
+  int ldx;
+  const double *L;
+  const int *run;
+};
+struct CqJob {
+  int *cq;
+  int *count;
+};
+struct SymJob {
+  int m;
+  double *K;
+};
+struct EigJob {
+  int m;
+  const double *K;
+  double *lam, *Z, *work;
+  int *flag;
+};
+struct IncJob {
+  int n, k;
+  const double *lam, *V, *c, *g;
+  double *dz, *dofs;
+};
+struct CopyJob {
+  long long count;
+  const double *src;
+  double *dst;
+};
+struct PhiloxJob {
+  long long total;
+  unsigned long long stream;
+  double *out;
+};
+
+
+// ---------------------------------------------------------------------------
 // Lorenz-96 member layout.
 //
 // One probe ("member") of the batched TL/AD integration is owned by one
@@ -35,7 +96,62 @@ struct ModelView {
 
 inline size_t stage_block_elems(int E, int NT) { return (size_t)(E + 4) * NT; }
 
+// Batched model jobs (E = 8 for every problem of a batch).
+struct TrajJob {
+  ModelView mv;
+  const double *x0;
+  double *xs64;
+  float *xs32;
+};
+struct InnovJob {
+  ModelView mv;
+  const double *xs64;
+  const int *obs_step, *obs_idx, *u_optr, *u_olist;
+  const double *y, *rinv;
+  double *d;
+  void *fgrad;
+};
+// One problem of a persistent TL/AD launch: members j = 0 .. m-1 read dx0 + j n, write
+// lam0 + j n and use f + j U (mode 0/2/3); mode 1 reads the shared forcing fsrc.
+struct TladProb {
+  ModelView mv;
+  const double *dx0;
+  double *lam0;
+  void *f;
+  const void *fsrc;
+};
+// One tile of a persistent TL/AD launch: member `mem` of problem `prob`.
+struct TladTile {
+  int prob, mem;
+};
+struct ApplyLJobE {
+  int n, w, m;
+  const double *taps, *X;
+  double *Y;
+  const double *Z;
+  int mode;
+};
+
 // Launch helpers implemented in l96.hip -------------------------------------
+
+// Batched model launches. Persistent TL/AD: `nwg` workgroups of 256 threads first take
+// whole-workgroup tiles (one member per workgroup) from wg_tiles through counters[0],
+// then each wave takes wave tiles (one member per wave, problems with NT <= 64) from
+// wave_tiles through counters[1]. Tiles are processed in list order (longest first).
+hipError_t launch_trajectory_batched(int nprob, const TrajJob *jobs, hipStream_t st);
+hipError_t launch_innovation_batched(int nprob, int maxU, const InnovJob *jobs, bool fp32,
+                                     hipStream_t st);
+// clk (optional): per tile, start and end of its integration on the device's constant-rate
+// clock (wall_clock64), wg tiles first, then wave tiles.
+hipError_t launch_tlad_persistent(int nwg, int mode, const TladProb *probs, const TladTile *wg_tiles,
+                                  int n_wg, const TladTile *wave_tiles, int n_wave, int *counters,
+                                  bool fp32, hipStream_t st, long long *clk = nullptr);
+// Workgroups of the persistent TL/AD kernel that fit one compute unit at once.
+int tlad_persistent_resident_per_cu(bool fp32);
+hipError_t launch_apply_L_batched(int nprob, int maxm, int maxext, const ApplyLJobE *jobs,
+                                  hipStream_t st);
+hipError_t launch_philox_batched(int nprob, long long maxtotal, uint64_t seed,
+                                 const PhiloxJob *jobs, hipStream_t st);
 
 // Nonlinear RK4 trajectory. When store != 0 the stage blocks of every step are
 // written (FP64 and, when xs32 != nullptr, FP32 copies), plus block (T, 0) = x_T.
@@ -95,13 +211,26 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
 // Upper Cholesky factor R of G + s I (R^T R). mode 0: s = 0; mode 1: s = shift_rel * ||G||_F;
 // mode 2: s = 0 first, restarted with the shift on breakdown. flag[0] = 1 when the last
 // attempt breaks down (non-positive or non-finite pivot); shifts[0] counts shifted attempts.
-hipError_t launch_cholesky(int m, const double *G, double *R, double shift_rel, int mode,
-                           int *flag, int *shifts, hipStream_t st);
 
 // Blocked Cholesky G + s I = L L^T (lower), same modes as launch_cholesky.
 hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_rel, int mode,
                                int *flag, int *shifts, hipStream_t st, const int *run = nullptr,
                                int *modflag = nullptr);
+// Batched forms of the launches above (jobs: device array of nprob entries; max*: largest
+// size over the batch, which sets the grid).
+hipError_t launch_gemm_batched(int ta, int tb, int nprob, int maxM, int maxN, double alpha,
+                               double beta, const GemmJob *jobs, hipStream_t st);
+hipError_t launch_chol_batched(int nprob, int mode, const CholJob *jobs, hipStream_t st);
+hipError_t launch_trsm_batched(int nprob, int maxrows, const TrsmJob *jobs, hipStream_t st);
+hipError_t launch_cholqr_reset_batched(int nprob, const CqJob *jobs, hipStream_t st);
+hipError_t launch_cholqr_ctrl_batched(int nprob, int pass_was_shifted, const CqJob *jobs,
+                                      hipStream_t st);
+hipError_t launch_symmetrize_batched(int nprob, const SymJob *jobs, hipStream_t st);
+hipError_t launch_eig_batched(int nprob, int maxm, const EigJob *jobs, hipStream_t st);
+hipError_t launch_increment_batched(int nprob, int maxn, int mode_lru, const IncJob *jobs,
+                                    hipStream_t st);
+hipError_t launch_copy_batched(int nprob, long long maxcount, const CopyJob *jobs, hipStream_t st);
+
 // CholeskyQR pass control (see cholqr in the API layer): reset, then one call per pass;
 // count (optional) is incremented once per pass that ran.
 hipError_t launch_cholqr_reset(int *cq, hipStream_t st);
@@ -112,15 +241,11 @@ hipError_t launch_trsm_rlt(int rows, int m, double *X, int ldx, const double *L,
                            const int *run = nullptr);
 
 // Blocked inverse of a lower-triangular L.
-hipError_t launch_trinv_lower(int m, const double *L, double *X, hipStream_t st);
 
 // Inverse of upper-triangular R (m x m).
-hipError_t launch_trinv_upper(int m, const double *R, double *Rinv, hipStream_t st);
 
 // Inverse of a general m x m matrix by Gauss-Jordan elimination with partial pivoting.
 // work holds 2*m*m doubles; flag[0] = 1 when a zero pivot is met.
-hipError_t launch_gj_inverse(int m, const double *M, double *Minv, double *work, int *flag,
-                             hipStream_t st);
 
 // K <- (K + K^T)/2 and asym[0] = ||K - K^T||_F / ||K||_F (before symmetrisation).
 // part: 128 doubles of scratch.
@@ -128,12 +253,6 @@ hipError_t launch_symmetrize(int m, double *K, double *asym, double *part, hipSt
 
 // ||Q^T Q - I||_F from the Gram matrix G = Q^T Q -> out[0].
 hipError_t launch_orth_err(int m, const double *G, double *out, hipStream_t st);
-
-// Symmetric eigendecomposition K = Z diag(lam) Z^T, eigenvalues descending.
-// work must hold syev_work_doubles(m) doubles; flag[0] = 1 on non-convergence.
-size_t syev_work_doubles(int m);
-hipError_t launch_syev(int m, const double *K, double *lam, double *Z, double *work, int *flag,
-                       hipStream_t st);
 
 // Symmetric eigendecomposition (eig.hip): tridiagonalisation, relatively robust
 // representation, multisection bisection, twisted-factorisation vectors, cluster

@@ -29,7 +29,10 @@ MODES = {"adaptive": ADAPTIVE, "lra": LRA, "lru": LRU}
 EXPORTS = ("riot_workspace_bytes", "riot_init", "riot_free", "riot_status_str",
            "riot_linearize", "riot_hess_apply", "riot_rsvd", "riot_increment",
            "riot_posterior_cov", "riot_cg", "riot_forecast", "riot_apply_L",
-           "riot_philox_normal", "riot_tl_apply", "riot_ad_apply", "riot_gn_apply")
+           "riot_philox_normal", "riot_tl_apply", "riot_ad_apply", "riot_gn_apply",
+           "riot_batch_workspace_bytes", "riot_batch_init", "riot_batch_free", "riot_batch_buffers",
+           "riot_batch_run", "riot_batch_set_layout", "riot_batch_autotune", "riot_batch_capture",
+           "riot_batch_replay", "riot_batch_problem", "riot_batch_profile", "riot_gaussian_taps")
 
 
 class RiotError(RuntimeError):
@@ -48,6 +51,10 @@ class _Desc(ctypes.Structure):
         ("l_halfwidth", ctypes.c_int32), ("l_taps", ctypes.POINTER(ctypes.c_double)),
         ("m_max", ctypes.c_int32), ("prec", ctypes.c_int32), ("elems_per_lane", ctypes.c_int32),
     ]
+
+
+class _BatchIO(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("x", "grad", "lambda_", "V", "dz", "dx", "d")]
 
 
 class _RsvdInfo(ctypes.Structure):
@@ -87,6 +94,21 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "riot_tl_apply": (i32, [vp, i32, vp, vp]),
         "riot_ad_apply": (i32, [vp, i32, vp, vp]),
         "riot_gn_apply": (i32, [vp, i32, vp, vp]),
+        "riot_batch_workspace_bytes": (ctypes.c_size_t, [i32, ctypes.POINTER(_Desc)]),
+        "riot_batch_init": (i32, [i32, ctypes.POINTER(_Desc), vp, ctypes.c_size_t, vp,
+                                  ctypes.POINTER(vp)]),
+        "riot_batch_free": (None, [vp]),
+        "riot_batch_buffers": (i32, [vp, ctypes.POINTER(_BatchIO)]),
+        "riot_batch_run": (i32, [vp, u64]),
+        "riot_batch_set_layout": (i32, [vp, i32, i32]),
+        "riot_batch_autotune": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                      ctypes.POINTER(ctypes.c_float)]),
+        "riot_batch_capture": (i32, [vp, u64]),
+        "riot_batch_replay": (i32, [vp]),
+        "riot_batch_problem": (i32, [vp, i32, ctypes.POINTER(vp)]),
+        "riot_gaussian_taps": (i32, [dbl, dbl, i32, vp]),
+        "riot_batch_profile": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(dbl),
+                                     ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -119,7 +141,9 @@ def _ptr(t):
         return None
     assert t.is_cuda and t.dtype == torch.float64
     if t.dim() == 2:
-        assert t.stride(0) == 1 and t.stride(1) == t.shape[0], "expected column-major (1, n) strides"
+        # a single column's second stride is immaterial (torch reports 1 or n)
+        assert t.stride(0) == 1 and (t.shape[1] == 1 or t.stride(1) == t.shape[0]), \
+            "expected column-major (1, n) strides"
     else:
         assert t.is_contiguous()
     return ctypes.c_void_p(t.data_ptr())
@@ -171,9 +195,18 @@ class Riot:
         self.h = h
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and not getattr(self, "_borrowed", False):
             self.lib.riot_free(self.h)
-            self.h = None
+        self.h = None
+
+    @classmethod
+    def _bind(cls, lib, h, n, nsteps, m_max, nobs, device, stream, owner):
+        """Wrap a handle owned by someone else (a batch's problem); it is never freed here."""
+        self = cls.__new__(cls)
+        self.lib, self.h, self._borrowed, self._owner = lib, h, True, owner
+        self.n, self.nsteps, self.m_max, self.nobs = int(n), int(nsteps), int(m_max), int(nobs)
+        self.device, self.stream = device, stream
+        return self
 
     def __del__(self):
         try:
@@ -300,3 +333,135 @@ class Riot:
         _check(self.lib.riot_philox_normal(self.h, n, m, ctypes.c_uint64(seed), ctypes.c_uint64(stream),
                                            _ptr(out)), "riot_philox_normal")
         return out
+
+
+def gaussian_taps(ell, sigma_b):
+    """Half-kernel taps of the library's Gaussian square root of B (riot_gaussian_taps)."""
+    lib = load_library()
+    w = lib.riot_gaussian_taps(float(ell), float(sigma_b), 0, None)
+    if w < 0:
+        raise RiotError(-1, "riot_gaussian_taps")
+    taps = np.empty(w + 1)
+    lib.riot_gaussian_taps(float(ell), float(sigma_b), w + 1, taps.ctypes.data_as(ctypes.c_void_p))
+    return taps
+
+
+class RiotBatch:
+    """Many independent inner-loop problems run together (C ABI riot_batch_*).
+
+    problems: sequence of dicts with keys n, nsteps, dt, forcing, obs_step, obs_idx, y,
+    rinv, taps, m. The batch owns packed device buffers; `x`, `grad`, `lam`, `V`, `dz`,
+    `dx`, `d` are torch views of them (problem j's slices via vec/lam_of/V_of). All calls
+    run on the batch's own stream (non-default, so that the pipeline can be captured).
+    """
+
+    def __init__(self, problems, prec=FP64, device="cuda"):
+        self.lib = load_library()
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.P = len(problems)
+        descs = (_Desc * self.P)()
+        self._keep = []
+        self.n, self.m, self.nsteps, self.nobs = [], [], [], []
+        P = lambda a, c: a.ctypes.data_as(ctypes.POINTER(c))  # noqa: E731
+        for j, pr in enumerate(problems):
+            arrs = [np.ascontiguousarray(pr["obs_step"], dtype=np.int32),
+                    np.ascontiguousarray(pr["obs_idx"], dtype=np.int32),
+                    np.ascontiguousarray(pr["y"], dtype=np.float64),
+                    np.ascontiguousarray(pr["rinv"], dtype=np.float64),
+                    np.ascontiguousarray(pr["taps"], dtype=np.float64)]
+            self._keep.append(arrs)
+            d = descs[j]
+            d.n, d.nsteps, d.dt, d.forcing = int(pr["n"]), int(pr["nsteps"]), float(pr["dt"]), float(pr["forcing"])
+            d.nobs = int(arrs[0].size)
+            d.obs_step, d.obs_idx = P(arrs[0], ctypes.c_int32), P(arrs[1], ctypes.c_int32)
+            d.y, d.rinv = P(arrs[2], ctypes.c_double), P(arrs[3], ctypes.c_double)
+            d.l_halfwidth, d.l_taps = int(arrs[4].size - 1), P(arrs[4], ctypes.c_double)
+            d.m_max, d.prec, d.elems_per_lane = int(pr["m"]), int(prec), 8
+            self.n.append(d.n), self.m.append(d.m_max), self.nsteps.append(d.nsteps)
+            self.nobs.append(d.nobs)
+        nbytes = self.lib.riot_batch_workspace_bytes(self.P, descs)
+        if nbytes == 0:
+            raise RiotError(-1, "riot_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        b = ctypes.c_void_p()
+        _check(self.lib.riot_batch_init(self.P, descs, ctypes.c_void_p(aligned), ctypes.c_size_t(nbytes),
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(b)),
+               "riot_batch_init")
+        self.b = b
+        io = _BatchIO()
+        _check(self.lib.riot_batch_buffers(self.b, ctypes.byref(io)), "riot_batch_buffers")
+        self.off_n = np.concatenate([[0], np.cumsum(self.n)]).astype(np.int64)
+        self.off_m = np.concatenate([[0], np.cumsum(self.m)]).astype(np.int64)
+        self.off_nm = np.concatenate([[0], np.cumsum(np.asarray(self.n) * np.asarray(self.m))]).astype(np.int64)
+        self.off_obs = np.concatenate([[0], np.cumsum(np.maximum(self.nobs, 1))]).astype(np.int64)
+
+        def view(ptr, count):
+            off = ptr - base
+            return self.workspace[off: off + 8 * count].view(torch.float64)
+        tn, tm, tnm = int(self.off_n[-1]), int(self.off_m[-1]), int(self.off_nm[-1])
+        self.x, self.grad = view(io.x, tn), view(io.grad, tn)
+        self.lam, self.V = view(io.lambda_, tm), view(io.V, tnm)
+        self.dz, self.dx = view(io.dz, tn), view(io.dx, tn)
+        self.d = view(io.d, int(self.off_obs[-1]))
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.lib.riot_batch_free(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # packed slices of problem j
+    def vec(self, j, t):
+        return t[int(self.off_n[j]): int(self.off_n[j + 1])]
+
+    def lam_of(self, j):
+        return self.lam[int(self.off_m[j]): int(self.off_m[j + 1])]
+
+    def V_of(self, j):
+        return self.V[int(self.off_nm[j]): int(self.off_nm[j + 1])].view(self.m[j], self.n[j]).t()
+
+    def set_x(self, xs):
+        with torch.cuda.stream(self.stream):
+            for j, x in enumerate(xs):
+                self.vec(j, self.x).copy_(torch.as_tensor(x, dtype=torch.float64))
+
+    def run(self, seed=0):
+        _check(self.lib.riot_batch_run(self.b, ctypes.c_uint64(seed)), "riot_batch_run")
+
+    def set_layout(self, workgroups, wave_max_threads):
+        _check(self.lib.riot_batch_set_layout(self.b, int(workgroups), int(wave_max_threads)),
+               "riot_batch_set_layout")
+
+    def autotune(self):
+        wg, wv, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+        _check(self.lib.riot_batch_autotune(self.b, ctypes.byref(wg), ctypes.byref(wv), ctypes.byref(ms)),
+               "riot_batch_autotune")
+        return wg.value, wv.value, ms.value
+
+    def capture(self, seed=0):
+        _check(self.lib.riot_batch_capture(self.b, ctypes.c_uint64(seed)), "riot_batch_capture")
+
+    def replay(self):
+        _check(self.lib.riot_batch_replay(self.b), "riot_batch_replay")
+
+    def profile(self):
+        """(ms, load balance, tiles) of one instrumented probe-product launch."""
+        ms, bf, nt = ctypes.c_float(), ctypes.c_double(), ctypes.c_int32()
+        _check(self.lib.riot_batch_profile(self.b, ctypes.byref(ms), ctypes.byref(bf), ctypes.byref(nt)),
+               "riot_batch_profile")
+        return ms.value, bf.value, nt.value
+
+    def problem(self, j):
+        """A Riot bound to problem j's handle inside the batch (same stream and workspace)."""
+        h = ctypes.c_void_p()
+        _check(self.lib.riot_batch_problem(self.b, int(j), ctypes.byref(h)), "riot_batch_problem")
+        return Riot._bind(self.lib, h, self.n[j], self.nsteps[j], self.m[j], self.nobs[j], self.device,
+                          self.stream, self)

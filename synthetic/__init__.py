@@ -14,4 +14,6 @@ from .draws import (  # noqa: F401
     obs_locations,
     l96_draws,
     probe_block,
+    batch_workloads,
+    BATCH_N_VALUES,
 )

@@ -120,3 +120,44 @@ def probe_block(seed: int, outer: int, n: int, m: int) -> np.ndarray:
     ss = _streams(seed)[3].spawn(outer + 1)[outer]
     g = np.random.default_rng(ss)
     return np.asfortranarray(g.standard_normal((n, m)))
+
+
+# Batches of independent Lorenz-96 problems of uneven size: n uniform on
+# {40, 80, ..., 2040} plus 2048, window uniform on 20..200 steps, a random
+# fraction rho ~ U[0.25, 0.5] of the variables observed every 4th step, R = I,
+# Gaussian B of length 2 cells, m = min(n/2, 128) + 8 probes. The truth is spun
+# up 300 steps (about 40 e-folding times of the model's leading Lyapunov mode),
+# shorter than the single-problem recipe to keep a 1000-problem batch cheap.
+BATCH_N_VALUES = tuple(range(40, 2041, 40)) + (2048,)
+
+
+def batch_workloads(nprob: int, seed: int):
+    """Per-problem (workload, draws) of a seeded batch of uneven problems."""
+    ss = _streams(seed)[4]
+    rng = np.random.default_rng(ss)
+    sizes = rng.choice(np.asarray(BATCH_N_VALUES), size=nprob)
+    steps = rng.integers(20, 201, size=nprob)
+    rhos = rng.uniform(0.25, 0.5, size=nprob)
+    child = ss.spawn(nprob)
+    out = []
+    for j in range(nprob):
+        n, T, rho = int(sizes[j]), int(steps[j]), float(rhos[j])
+        m = min(n // 2, 128) + 8
+        w = L96Workload(f"batch{j}", n=n, nsteps=T, spinup=300, var_stride=1, step_stride=4,
+                        ell=2.0, sigma_b=1.0, k=m - 8, p_os=8, q=0, outer=1)
+        g = np.random.default_rng(child[j])
+        nv = int(round(rho * n))
+        vars_ = np.sort(g.choice(n, size=nv, replace=False)).astype(np.int32)
+        st = np.arange(4, T + 1, 4, dtype=np.int32)
+        obs_step = np.repeat(st, nv).astype(np.int32)
+        obs_idx = np.tile(vars_, st.size).astype(np.int32)
+        draws = {
+            "x0": w.forcing + w.spinup_sigma * g.standard_normal(n),
+            "obs_noise": w.obs_sigma * g.standard_normal(obs_step.size),
+            "bg_noise": g.standard_normal(n),
+            "obs_step": obs_step,
+            "obs_idx": obs_idx,
+            "rinv": np.ones(obs_step.size),
+        }
+        out.append((w, draws))
+    return out

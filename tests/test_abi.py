@@ -85,3 +85,16 @@ def test_status_strings_and_null_handles():
     out = vp()
     assert lib.riot_init(None, vp(256), 1024, None, ctypes.byref(out)) == -1
     lib.riot_free(None)
+
+
+def test_gaussian_taps_host_helper_matches_oracle():
+    """riot_gaussian_taps (host code, no GPU) against the oracle's square-root taps."""
+    import numpy as np
+
+    from oracle.bcov import gaussian_taps as oracle_taps
+    from paper_1906_01413_amd import gaussian_taps
+
+    for ell, sb in ((2.0, 1.0), (8.0, 1.0), (1.5, 0.7)):
+        a, b = gaussian_taps(ell, sb), oracle_taps(ell, sb)
+        assert a.size == b.size
+        assert np.max(np.abs(a - b)) <= 1e-15 * np.max(np.abs(b))

@@ -83,6 +83,9 @@ typedef struct {
     int32_t elems_per_lane;    /* 0 = choose automatically, else 1, 2, 4, 8 or 16
                                   (n must be divisible by it; n / it <= 512 for 8 and 16,
                                   <= 1024 otherwise) */
+    int32_t ckpt_stride;       /* 0 = the handle stores the whole window's trajectory (every
+                                  call); c > 0 = it stores c steps at a time and only the
+                                  riot_ckpt_* calls (plus forecast, apply_L, philox) apply */
 } riot_desc;
 
 /* Diagnostics of one randomized eigendecomposition (host struct). */
@@ -236,6 +239,26 @@ typedef struct {
     double *dx;      /* [sum n] device out: state increment L dz */
     double *d;       /* [sum max(nobs,1)] device out: innovations */
 } riot_batch_io;
+
+/* ------------------------------------------------------------------------------------
+ * Checkpointed model derivatives (handles with ckpt_stride = c > 0): the observation map
+ * x_0 -> y(x_0) = {H_t M_{0->t} x_0}, its tangent and its adjoint over the window, with the
+ * trajectory kept only at every c-th step. The adjoint recomputes each segment's RK4 stage
+ * states from its checkpoint, last segment first, and runs the exact discrete adjoint
+ * through it; an observation at a segment boundary belongs to the earlier segment.
+ *   ckpt   [n x (nseg+1)] device, nseg = ceil(nsteps / c): column s = x at step s c,
+ *          the last column = x at step nsteps (written by riot_ckpt_forward)
+ *   obs    [nobs] observed values H_t x_t (forward)
+ *   dX0, gX0 [n x m] and dObs, gObs [nobs x m] device, column-major
+ * m <= m_max. Calls are stream-ordered.
+ * ---------------------------------------------------------------------------------- */
+riot_status riot_ckpt_forward(riot_handle *h, const double *x0, double *ckpt, double *obs);
+/* dObs = G dX0 (G = stacked H_t M_{0->t} tangent-linear maps at the checkpointed trajectory) */
+riot_status riot_ckpt_tangent(riot_handle *h, int32_t m, const double *ckpt, const double *dX0,
+                              double *dObs);
+/* gX0 = G^T gObs (vector-Jacobian product of the observation map) */
+riot_status riot_ckpt_adjoint(riot_handle *h, int32_t m, const double *ckpt, const double *gObs,
+                              double *gX0);
 
 /* Half-kernel taps l_0 .. l_w of the Gaussian square root used for B (host function):
  * l_d = c exp(-d^2 / ell^2), w = ceil(6.25 ell), c such that sum_{|d|<=w} l_d^2 = sigma_b^2,

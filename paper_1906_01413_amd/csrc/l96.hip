@@ -287,7 +287,7 @@ struct Member {
   }
 
   // Tangent-linear sweep from dl (in registers) over the whole window, storing forcing.
-  __device__ void tl_sweep(Real (&dl)[E], Real *__restrict__ f, bool weighted) {
+  __device__ void tl_sweep(Real (&dl)[E], Real *__restrict__ f, bool weighted, bool skip0) {
     const Real h = (Real)mv.h;
     const Real h2 = (Real)(0.5 * mv.h);
     const Real h6 = (Real)(mv.h / 6.0);
@@ -295,7 +295,7 @@ struct Member {
     Real hl2 = 0, hl1 = 0, hr1 = 0, hr2 = 0;
     for (int t = 0; t <= mv.T; ++t) {
       const int k = mv.stepk[t];
-      if (k >= 0 && active) tl_store(k, dl, f, weighted);
+      if (k >= 0 && active && !(skip0 && t == 0)) tl_store(k, dl, f, weighted);
       if (t == mv.T) break;
       // stage 1
       exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, dl, hl2, hl1, hr1, hr2);
@@ -345,18 +345,20 @@ struct Member {
   }
 
   // Adjoint sweep over the whole window with forcing f injected at observed steps.
-  __device__ void ad_sweep(Real (&lam)[E], const Real *__restrict__ f) {
+  __device__ void ad_sweep(Real (&lam)[E], const Real *__restrict__ f, bool skip0, bool init) {
     const Real h = (Real)mv.h;
     const Real h2 = (Real)(0.5 * mv.h);
     const Real h3 = (Real)(mv.h / 3.0);
     const Real h6 = (Real)(mv.h / 6.0);
     Real xe[E + 4], lp[E], a[E], s[E];
     Real hl2 = 0, hl1 = 0, hr1 = 0, hr2 = 0;
+    if (!init) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) lam[j] = 0;
+      for (int j = 0; j < E; ++j) lam[j] = 0;
+    }
     for (int t = mv.T; t >= 0; --t) {
       const int k = mv.stepk[t];
-      if (k >= 0 && active) ad_inject(k, lam, f);
+      if (k >= 0 && active && !(skip0 && t == 0)) ad_inject(k, lam, f);
       if (t == 0) break;
       const int ts = t - 1;
       // adjoint of stage 4 input
@@ -410,24 +412,41 @@ struct Member {
     }
   }
 
-  // One member. mode 0: TL (R^{-1}-weighted store) then AD -> lam0; mode 1: AD forced by
-  // the shared fsrc -> lam0; mode 2: TL only, raw observed values into f; mode 3: AD forced
-  // by this member's own f -> lam0. dx0 and lam0 use the natural layout (double).
+  // One member. Base mode (mode & 7): 0 = TL (R^{-1}-weighted store) then AD -> lam0;
+  // 1 = AD forced by the shared fsrc -> lam0; 2 = TL only, raw observed values into f;
+  // 3 = AD forced by this member's own f -> lam0. Flags: kTladSkip0 = no store or injection
+  // at the window's step 0 (a checkpoint segment after the first, whose step 0 is the
+  // previous segment's last step); kTladInitLam = the AD starts from dx0 instead of zero;
+  // kTladOutState = mode 2 writes the final tangent state into lam0. dx0 and lam0 use the
+  // natural layout (double).
   __device__ void run(int mode, const double *__restrict__ dx0, double *__restrict__ lam0,
                       Real *__restrict__ f, const Real *__restrict__ fsrc) {
+    const int base = mode & 7;
+    const bool skip0 = (mode & kTladSkip0) != 0;
     const int a = l * E;
     Real v[E];
-    if (mode == 0 || mode == 2) {
+    if (base == 0 || base == 2) {
 #pragma unroll
       for (int j = 0; j < E; ++j) v[j] = active ? (Real)dx0[a + j] : (Real)0;
-      tl_sweep(v, f, mode == 0);
-      if (mode == 2) return;
+      tl_sweep(v, f, base == 0, skip0);
+      if (base == 2) {
+        if ((mode & kTladOutState) && active) {
+#pragma unroll
+          for (int j = 0; j < E; ++j) lam0[a + j] = (double)v[j];
+        }
+        return;
+      }
       // each forcing value is re-read by the thread that stored it; the barrier only
       // separates the two sweeps' LDS traffic
       member_sync<WAVE>();
-      ad_sweep(v, f);
+      ad_sweep(v, f, skip0, false);
     } else {
-      ad_sweep(v, mode == 1 ? fsrc : f);
+      const bool init = (mode & kTladInitLam) != 0;
+      if (init) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = active ? (Real)dx0[a + j] : (Real)0;
+      }
+      ad_sweep(v, base == 1 ? fsrc : f, skip0, init);
     }
     if (active) {
 #pragma unroll
@@ -548,6 +567,20 @@ __global__ void innovation_kernel(ModelView mv, const double *__restrict__ xs64,
     acc += rinv[o] * dv;
   }
   fgrad[u] = (Real)acc;
+}
+
+// Observed values of a stored window segment: out[o] = x_t[i] for the observations whose
+// step t lies in (lo, lo + T] (and t = lo when include_lo), read from block (t - lo, 0).
+__global__ void obs_value_kernel(ModelView mv, const double *__restrict__ xs64, int nobs,
+                                 const int *__restrict__ obs_step, const int *__restrict__ obs_idx,
+                                 int lo, int include_lo, double *__restrict__ out) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nobs) return;
+  const int t = obs_step[o];
+  if (t < lo || t > lo + mv.T || (t == lo && !include_lo)) return;
+  const int i = obs_idx[o];
+  const int l = i / mv.E, j = i - l * mv.E;
+  out[o] = xs64[(size_t)((t - lo) * 4) * (size_t)(mv.E + 4) * mv.NT + (size_t)j * mv.NT + l];
 }
 
 // Z[o, j] = f_j[u(o)] : raw TL values back in the caller's observation order.
@@ -843,6 +876,15 @@ hipError_t launch_tlad(const ModelView &mv, int m, int mode, const double *dx0, 
                                              reinterpret_cast<double *>(f),
                                              reinterpret_cast<const double *>(fsrc)));
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_obs_value(const ModelView &mv, const double *xs64, int nobs, const int *obs_step,
+                            const int *obs_idx, int lo, bool include_lo, double *out,
+                            hipStream_t st) {
+  if (nobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(obs_value_kernel, dim3((nobs + 255) / 256), dim3(256), 0, st, mv, xs64, nobs,
+                     obs_step, obs_idx, lo, include_lo ? 1 : 0, out);
   return hipGetLastError();
 }
 

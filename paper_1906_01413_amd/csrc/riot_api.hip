@@ -160,7 +160,9 @@ size_t carve(riot_handle &h, void *base) {
   h.u_of_o = c.take<int>(std::max(d.nobs, 1));
   h.y = c.take<double>(std::max(d.nobs, 1));
   h.rinv = c.take<double>(std::max(d.nobs, 1));
-  const size_t blk = (size_t)(T + 1) * 4 * stage_block_elems(h.E, h.NT);
+  // the whole window's stage blocks, or one checkpoint segment's
+  const int Tst = d.ckpt_stride > 0 ? d.ckpt_stride : T;
+  const size_t blk = (size_t)(Tst + 1) * 4 * stage_block_elems(h.E, h.NT);
   h.xs64 = c.take<double>(blk);
   h.xs32 = h.fp32 ? c.take<float>(blk) : nullptr;
   h.fgrad = c.take<char>(U1 * Rs);
@@ -197,6 +199,7 @@ bool desc_valid(const riot_desc *d) {
   if (d->prec != RIOT_FP64 && d->prec != RIOT_FP32_TLAD) return false;
   if (choose_E(d->n, d->elems_per_lane) == 0) return false;
   if (d->m_max > 1088) return false;
+  if (d->ckpt_stride < 0 || d->ckpt_stride > std::max(d->nsteps, 1)) return false;
   return true;
 }
 
@@ -405,6 +408,7 @@ const char *riot_status_str(riot_status s) {
 riot_status riot_linearize(riot_handle *h, const double *x, const double *v, double *d,
                            double *grad, double *J_host) {
   if (!h || !x || !grad || (h->d.nobs > 0 && !d)) return RIOT_E_ARG;
+  if (h->d.ckpt_stride > 0) return RIOT_E_STATE;  // only a segment of the window fits
   const riot_desc &ds = h->d;
   hipStream_t st = h->st;
   RIOT_HIP(launch_trajectory(h->mv, ds.nsteps, x, nullptr, h->xs64, h->xs32, st));
@@ -574,6 +578,96 @@ riot_status riot_ad_apply(riot_handle *h, int32_t m, const double *Fo, double *X
   return RIOT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Checkpointed observation map, tangent and adjoint
+// ---------------------------------------------------------------------------
+
+static ModelView segment_view(const riot_handle *h, int s, int steps) {
+  ModelView mv = h->mv;
+  mv.T = steps;
+  mv.stepk = h->stepk + (size_t)s * h->d.ckpt_stride;
+  return mv;
+}
+
+static int segment_steps(const riot_handle *h, int s) {
+  const int c = h->d.ckpt_stride, T = h->d.nsteps;
+  return std::min(c, T - s * c);
+}
+
+static int segment_count(const riot_handle *h) {
+  const int c = h->d.ckpt_stride, T = h->d.nsteps;
+  return T > 0 ? (T + c - 1) / c : 0;
+}
+
+riot_status riot_ckpt_forward(riot_handle *h, const double *x0, double *ckpt, double *obs) {
+  if (!h || !x0 || !ckpt || (h->d.nobs > 0 && !obs)) return RIOT_E_ARG;
+  if (h->d.ckpt_stride <= 0) return RIOT_E_STATE;
+  const int n = h->d.n, c = h->d.ckpt_stride, ns = segment_count(h);
+  hipStream_t st = h->st;
+  RIOT_HIP(hipMemcpyAsync(ckpt, x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (ns == 0) {
+    RIOT_HIP(launch_trajectory(segment_view(h, 0, 0), 0, x0, nullptr, h->xs64, h->xs32, st));
+    RIOT_HIP(launch_obs_value(segment_view(h, 0, 0), h->xs64, h->d.nobs, h->obs_step, h->obs_idx,
+                              0, true, obs, st));
+    return RIOT_OK;
+  }
+  for (int s = 0; s < ns; ++s) {
+    const int steps = segment_steps(h, s);
+    const ModelView mv = segment_view(h, s, steps);
+    RIOT_HIP(launch_trajectory(mv, steps, ckpt + (size_t)s * n, ckpt + (size_t)(s + 1) * n,
+                               h->xs64, h->xs32, st));
+    RIOT_HIP(launch_obs_value(mv, h->xs64, h->d.nobs, h->obs_step, h->obs_idx, s * c, s == 0, obs,
+                              st));
+  }
+  return RIOT_OK;
+}
+
+riot_status riot_ckpt_tangent(riot_handle *h, int32_t m, const double *ckpt, const double *dX0,
+                              double *dObs) {
+  if (!h || !ckpt || !dX0 || (h->d.nobs > 0 && !dObs) || m < 1 || m > h->d.m_max)
+    return RIOT_E_ARG;
+  if (h->d.ckpt_stride <= 0) return RIOT_E_STATE;
+  const int n = h->d.n, ns = std::max(segment_count(h), 1);
+  hipStream_t st = h->st;
+  // tangent states ping-pong between two n x m blocks of the workspace
+  const double *cur = dX0;
+  double *bufs[2] = {h->LW, h->LAM};
+  for (int s = 0; s < ns; ++s) {
+    const int steps = segment_count(h) ? segment_steps(h, s) : 0;
+    const ModelView mv = segment_view(h, s, steps);
+    RIOT_HIP(launch_trajectory(mv, steps, ckpt + (size_t)s * n, nullptr, h->xs64, h->xs32, st));
+    double *next = bufs[s & 1];
+    RIOT_HIP(launch_tlad(mv, m, 2 | kTladOutState | (s > 0 ? kTladSkip0 : 0), cur, next, h->f,
+                         nullptr, h->fp32, st));
+    cur = next;
+  }
+  RIOT_HIP(launch_obs_gather(h->d.nobs, h->U, m, h->u_of_o, h->f, dObs, h->fp32, st));
+  return RIOT_OK;
+}
+
+riot_status riot_ckpt_adjoint(riot_handle *h, int32_t m, const double *ckpt, const double *gObs,
+                              double *gX0) {
+  if (!h || !ckpt || !gX0 || (h->d.nobs > 0 && !gObs) || m < 1 || m > h->d.m_max)
+    return RIOT_E_ARG;
+  if (h->d.ckpt_stride <= 0) return RIOT_E_STATE;
+  const int n = h->d.n, ns = std::max(segment_count(h), 1);
+  hipStream_t st = h->st;
+  RIOT_HIP(launch_obs_scatter(h->d.nobs, h->U, m, h->u_optr, h->u_olist, gObs, h->f, h->fp32, st));
+  // adjoint states ping-pong between two n x m blocks; the last segment starts from zero
+  double *bufs[2] = {h->LW, h->LAM};
+  const double *cur = nullptr;
+  for (int s = ns - 1, i = 0; s >= 0; --s, ++i) {
+    const int steps = segment_count(h) ? segment_steps(h, s) : 0;
+    const ModelView mv = segment_view(h, s, steps);
+    RIOT_HIP(launch_trajectory(mv, steps, ckpt + (size_t)s * n, nullptr, h->xs64, h->xs32, st));
+    double *next = s == 0 ? gX0 : bufs[i & 1];
+    const int mode = 3 | (cur ? kTladInitLam : 0) | (s > 0 ? kTladSkip0 : 0);
+    RIOT_HIP(launch_tlad(mv, m, mode, cur, next, h->f, nullptr, h->fp32, st));
+    cur = next;
+  }
+  return RIOT_OK;
+}
+
 riot_status riot_gn_apply(riot_handle *h, int32_t m, const double *X, double *Y) {
   if (!h || !X || !Y || X == Y || m < 1 || m > h->d.m_max) return RIOT_E_ARG;
   if (!h->linearized) return RIOT_E_STATE;
@@ -672,7 +766,7 @@ riot_status upload(T *dst, const std::vector<T> &src, hipStream_t st) {
 
 bool batch_desc_ok(const riot_desc &d) {
   return desc_valid(&d) && d.n % 8 == 0 && d.n <= kBatchMaxN && d.m_max <= kBatchMaxM &&
-         d.m_max <= d.n;
+         d.m_max <= d.n && d.ckpt_stride == 0;
 }
 
 // Workspace of the batch-level part: packed buffers and job tables.

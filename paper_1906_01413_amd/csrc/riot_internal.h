@@ -169,6 +169,10 @@ hipError_t launch_innovation(const ModelView &mv, const double *xs64, int nobs, 
 hipError_t launch_cost(int n, const double *v, int nobs, const double *d, const double *rinv,
                        double *out, hipStream_t st);
 
+// Flags or-ed into the TL/AD mode (see Member::run): skip step 0 of the window, start the
+// AD from dx0, return the final tangent state of a TL-only sweep.
+constexpr int kTladSkip0 = 8, kTladInitLam = 16, kTladOutState = 32;
+
 // Member TL/AD integrations. mode: 0 = TL then AD with R^{-1}-weighted forcing from the TL
 // pass (probe product), 1 = AD only with shared forcing `fsrc` (gradient), 2 = TL only
 // (raw observed values into f), 3 = AD only with each member's own forcing f.
@@ -176,6 +180,11 @@ hipError_t launch_cost(int n, const double *v, int nobs, const double *d, const 
 // f: per-member forcing scratch [m x U] (Real). fp32 selects the Real type.
 hipError_t launch_tlad(const ModelView &mv, int m, int mode, const double *dx0, double *lam0,
                        void *f, const void *fsrc, bool fp32, hipStream_t st);
+
+// Observed values x_t[i] of a stored segment whose step 0 is window step lo (see kernel).
+hipError_t launch_obs_value(const ModelView &mv, const double *xs64, int nobs, const int *obs_step,
+                            const int *obs_idx, int lo, bool include_lo, double *out,
+                            hipStream_t st);
 
 // Observation-space values <-> per-member unique-pair buffers (caller order o).
 hipError_t launch_obs_gather(int nobs, int U, int m, const int *u_of_o, const void *f, double *Z,

@@ -32,7 +32,8 @@ EXPORTS = ("riot_workspace_bytes", "riot_init", "riot_free", "riot_status_str",
            "riot_philox_normal", "riot_tl_apply", "riot_ad_apply", "riot_gn_apply",
            "riot_batch_workspace_bytes", "riot_batch_init", "riot_batch_free", "riot_batch_buffers",
            "riot_batch_run", "riot_batch_set_layout", "riot_batch_autotune", "riot_batch_capture",
-           "riot_batch_replay", "riot_batch_problem", "riot_batch_profile", "riot_gaussian_taps")
+           "riot_batch_replay", "riot_batch_problem", "riot_batch_profile", "riot_gaussian_taps",
+           "riot_ckpt_forward", "riot_ckpt_tangent", "riot_ckpt_adjoint")
 
 
 class RiotError(RuntimeError):
@@ -50,6 +51,7 @@ class _Desc(ctypes.Structure):
         ("y", ctypes.POINTER(ctypes.c_double)), ("rinv", ctypes.POINTER(ctypes.c_double)),
         ("l_halfwidth", ctypes.c_int32), ("l_taps", ctypes.POINTER(ctypes.c_double)),
         ("m_max", ctypes.c_int32), ("prec", ctypes.c_int32), ("elems_per_lane", ctypes.c_int32),
+        ("ckpt_stride", ctypes.c_int32),
     ]
 
 
@@ -107,6 +109,9 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "riot_batch_replay": (i32, [vp]),
         "riot_batch_problem": (i32, [vp, i32, ctypes.POINTER(vp)]),
         "riot_gaussian_taps": (i32, [dbl, dbl, i32, vp]),
+        "riot_ckpt_forward": (i32, [vp, vp, vp, vp]),
+        "riot_ckpt_tangent": (i32, [vp, i32, vp, vp, vp]),
+        "riot_ckpt_adjoint": (i32, [vp, i32, vp, vp, vp]),
         "riot_batch_profile": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(dbl),
                                      ctypes.POINTER(i32)]),
     }
@@ -161,7 +166,7 @@ class Riot:
     """One inner-loop problem (eqs. 2-3) bound to a device workspace and a stream."""
 
     def __init__(self, n, nsteps, dt, forcing, obs_step, obs_idx, y, rinv, taps, m_max,
-                 prec=FP64, elems_per_lane=0, device="cuda"):
+                 prec=FP64, elems_per_lane=0, device="cuda", ckpt_stride=0):
         self.lib = load_library()
         self.n, self.nsteps, self.m_max = int(n), int(nsteps), int(m_max)
         self.device = torch.device(device)
@@ -179,6 +184,8 @@ class Riot:
         d.l_halfwidth = int(self._taps.size - 1)
         d.l_taps = P(self._taps, ctypes.c_double)
         d.m_max, d.prec, d.elems_per_lane = self.m_max, int(prec), int(elems_per_lane)
+        d.ckpt_stride = int(ckpt_stride)
+        self.ckpt_stride = int(ckpt_stride)
         self._desc = d
         nbytes = self.lib.riot_workspace_bytes(ctypes.byref(d))
         if nbytes == 0:
@@ -327,6 +334,39 @@ class Riot:
         Y = empty_colmajor(self.n, X.shape[1], self.device) if out is None else out
         _check(self.lib.riot_gn_apply(self.h, X.shape[1], _ptr(X), _ptr(Y)), "riot_gn_apply")
         return Y
+
+    # -- checkpointed observation map (handles built with ckpt_stride > 0) ----
+    def n_checkpoints(self):
+        c = self.ckpt_stride
+        return (self.nsteps + c - 1) // c + 1 if self.nsteps > 0 else 1
+
+    def ckpt_forward(self, x0):
+        """(checkpoints n x (nseg+1), observed values [nobs]) of the window from x0."""
+        x0 = colmajor(x0, self.device)
+        ck = empty_colmajor(self.n, self.n_checkpoints(), self.device)
+        obs = torch.empty(max(self.nobs, 1), dtype=torch.float64, device=self.device)
+        _check(self.lib.riot_ckpt_forward(self.h, _ptr(x0), _ptr(ck), _ptr(obs)), "riot_ckpt_forward")
+        return ck, obs[: self.nobs]
+
+    def ckpt_tangent(self, ck, dX0):
+        """dObs [nobs x m] = G dX0 on the checkpointed trajectory."""
+        dX0 = self._block(dX0)
+        m = dX0.shape[1]
+        dObs = empty_colmajor(max(self.nobs, 1), m, self.device)
+        _check(self.lib.riot_ckpt_tangent(self.h, m, _ptr(ck), _ptr(dX0), _ptr(dObs)),
+               "riot_ckpt_tangent")
+        return dObs[: self.nobs]
+
+    def ckpt_adjoint(self, ck, gObs):
+        """gX0 [n x m] = G^T gObs on the checkpointed trajectory."""
+        gObs = colmajor(gObs, self.device)
+        if gObs.dim() == 1:
+            gObs = gObs.reshape(-1, 1).t().contiguous().t()
+        m = gObs.shape[1]
+        gX0 = empty_colmajor(self.n, m, self.device)
+        _check(self.lib.riot_ckpt_adjoint(self.h, m, _ptr(ck), _ptr(gObs), _ptr(gX0)),
+               "riot_ckpt_adjoint")
+        return gX0
 
     def philox_normal(self, n, m, seed, stream=0):
         out = empty_colmajor(n, m, self.device)

@@ -16,4 +16,6 @@ from .draws import (  # noqa: F401
     probe_block,
     batch_workloads,
     BATCH_N_VALUES,
+    advdiff_draws,
+    ADV_GRIDS,
 )

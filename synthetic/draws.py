@@ -161,3 +161,63 @@ def batch_workloads(nprob: int, seed: int):
         }
         out.append((w, draws))
     return out
+
+
+# Tracer source inversion on a periodic 2-D grid: grid sizes, wind, diffusion, control
+# blocks, observation tracks. "ad2_n512": 512 x 512 cells, 96 steps of dt = 0.1 (Courant
+# number (7 + 1) 0.1 + 4 K dt = 0.84), 4 x 4-cell control blocks x 4 time blocks = 65536
+# controls, 10 random-walk tracks of 400 samples. "ad2_n64": a small version for checks.
+ADV_GRIDS = {
+    "ad2_n512": dict(N=512, T=96, dt=0.1, u0=5.0, u1=2.0, v=1.0, K=0.1, block=4, ntb=4,
+                     tracks=10, samples=400),
+    "ad2_n64": dict(N=64, T=24, dt=0.1, u0=5.0, u1=2.0, v=1.0, K=0.1, block=4, ntb=4,
+                    tracks=10, samples=40),
+}
+
+
+def advdiff_draws(name: str, seed: int) -> dict:
+    """Seeded inputs of one source-inversion problem: grid, prior emission field E (a sum
+    of periodic Gaussian bumps on a floor), observation tracks (one-cell random-walk moves,
+    sample times uniform on 1..T, sorted), control-space draw xi, observation noise, and
+    the B parameters (exponential correlation length 3 blocks, sigma 0.5, R sigma = 10 %)."""
+    spec = dict(ADV_GRIDS[name])
+    tracks, samples = spec.pop("tracks"), spec.pop("samples")
+    N, T = spec["N"], spec["T"]
+    ss = _streams(seed)
+    g = np.random.default_rng(ss[5])
+    yy, xx = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    E = np.full((N, N), 0.1)
+    for _ in range(8):
+        cy, cx = g.uniform(0, N, size=2)
+        r = g.uniform(N / 32, N / 8)
+        a = g.uniform(0.5, 2.0)
+        dy = np.minimum(np.abs(yy - cy), N - np.abs(yy - cy))
+        dx = np.minimum(np.abs(xx - cx), N - np.abs(xx - cx))
+        E += a * np.exp(-(dy * dy + dx * dx) / (2.0 * r * r))
+    steps = np.array([[0, 1], [0, -1], [1, 0], [-1, 0]])
+    ot, oy, ox = [], [], []
+    for _ in range(tracks):
+        pos = g.integers(0, N, size=2)
+        times = np.sort(g.integers(1, T + 1, size=samples))
+        for k in range(samples):
+            if k:
+                pos = (pos + steps[g.integers(0, 4)]) % N
+            ot.append(times[k])
+            oy.append(pos[0])
+            ox.append(pos[1])
+    nb = N // spec["block"]
+    ncontrol = spec["ntb"] * nb * nb
+    gx = np.random.default_rng(ss[2])
+    gn = np.random.default_rng(ss[1])
+    return {
+        "grid": spec,
+        "E": E,
+        "obs_t": np.asarray(ot, dtype=np.int32),
+        "obs_y": np.asarray(oy, dtype=np.int32),
+        "obs_x": np.asarray(ox, dtype=np.int32),
+        "xi": gx.standard_normal(ncontrol),
+        "obs_noise": gn.standard_normal(len(ot)),
+        "ell": 3.0,
+        "sigma": 0.5,
+        "rel_err": 0.1,
+    }

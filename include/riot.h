@@ -260,6 +260,75 @@ riot_status riot_ckpt_tangent(riot_handle *h, int32_t m, const double *ckpt, con
 riot_status riot_ckpt_adjoint(riot_handle *h, int32_t m, const double *ckpt, const double *gObs,
                               double *gX0);
 
+/* ------------------------------------------------------------------------------------
+ * Sketch handle: the steps of Alg. 3 after the Hessian-probe products, for an operator
+ * whose products the caller computes (e.g. riot_tracer_hess_apply, or a learned probe
+ * basis). Device pointers, column-major, leading dimension n.
+ * ---------------------------------------------------------------------------------- */
+typedef struct riot_sketch riot_sketch;
+size_t riot_sketch_workspace_bytes(int32_t n, int32_t m_max);  /* 0: invalid (m_max <= n, 1088) */
+riot_status riot_sketch_init(int32_t n, int32_t m_max, void *workspace, size_t bytes,
+                             void *hip_stream, riot_sketch **out);
+void riot_sketch_free(riot_sketch *s);
+/* From Y = A Omega [n x m]: Q = orth(Y) (adaptive CholeskyQR), K solves
+ * K (Q^T Omega) = Q^T Y, K <- (K + K^T)/2 = Z diag(lambda) Z^T, V = Q Z (lambda descending). */
+riot_status riot_sketch_eig(riot_sketch *s, int32_t m, const double *Omega, const double *Y,
+                            double *lambda, double *V, riot_rsvd_info *info);
+/* dz from the k leading Ritz pairs: LRA -sum (1+l)^{-1} v v^T g, LRU -(I - sum l/(1+l) v v^T) g,
+ * adaptive = eq. 11 (no L applied: the caller maps dz to its own space). */
+riot_status riot_sketch_increment(riot_sketch *s, int32_t k, const double *lambda,
+                                  const double *V, const double *grad, riot_update mode,
+                                  double *dz, double *dofs_host, int32_t *mode_used);
+
+/* ------------------------------------------------------------------------------------
+ * Tracer source inversion on a periodic 2-D grid (the character of the paper's
+ * black-carbon inversions, Sec. 3.2: a transport model, emissions through a lognormal
+ * transform of the controls, point observations along aircraft tracks, p << n).
+ * Concentration c on an N x N periodic grid (index [y][x], x fastest, dx = 1), c_0 = 0:
+ *   c_{t+1} = A c_t + dt E * exp(up(s_tau(t))),
+ * A = explicit upwind advection by u(y) = u0 + u1 sin(2 pi y / N) along x and v along y
+ * (both >= 0) plus 5-point diffusion K; Courant number dt (u0 + |u1| + v) + 4 K dt <= 1.
+ * Controls s: ntb time blocks (nsteps / ntb steps each) x (N/block)^2 spatial blocks,
+ * [tau][by][bx]; up() repeats a block value over its block x block cells (block 1, 2, 4).
+ * Observations: c_{t_o}[y_o][x_o], t_o in 1..nsteps. B = sigma^2 (C1 kron C1) per time
+ * block, L = sigma (L1 kron L1) with L1 the caller's symmetric square root of the 1-D
+ * correlation (N/block x N/block). The inner loop's operator is A_s = L G^T R^{-1} G L with
+ * G the Jacobian of the observations at the base controls (Alg. 3 with this model).
+ * ---------------------------------------------------------------------------------- */
+typedef struct riot_tracer riot_tracer;
+typedef struct {
+    int32_t N;                 /* grid side, a multiple of 64 */
+    int32_t nsteps;            /* window steps, a multiple of ntb */
+    double dt, u0, u1, v, K;   /* step, wind, diffusion */
+    int32_t block, ntb;        /* control block side in cells; time blocks */
+    const double *E;           /* [N*N] host: prior emission field */
+    int32_t nobs;
+    const int32_t *obs_t, *obs_y, *obs_x;  /* [nobs] host: step (1..nsteps) and cell */
+    const double *y, *rinv;    /* [nobs] host: observed values, diagonal of R^{-1} */
+    const double *L1;          /* [(N/block)^2] host, symmetric */
+    double sigma;
+    int32_t m_max;             /* largest member block of tangent / adjoint / Hessian calls */
+} riot_tracer_desc;
+
+size_t riot_tracer_workspace_bytes(const riot_tracer_desc *desc);
+riot_status riot_tracer_init(const riot_tracer_desc *desc, void *workspace, size_t bytes,
+                             void *hip_stream, riot_tracer **out);
+void riot_tracer_free(riot_tracer *h);
+/* obs [nobs] = H(M(s)) for controls s [ncontrol] (device); s becomes the base of the
+ * derivatives below. */
+riot_status riot_tracer_forward(riot_tracer *h, const double *s, double *obs);
+/* dObs [nobs x m] = G dS [ncontrol x m]; gS [ncontrol x m] = G^T gObs [nobs x m] */
+riot_status riot_tracer_tangent(riot_tracer *h, int32_t m, const double *dS, double *dObs);
+riot_status riot_tracer_adjoint(riot_tracer *h, int32_t m, const double *gObs, double *gS);
+/* S = L Z [ncontrol x m] (S must not alias Z) */
+riot_status riot_tracer_apply_L(riot_tracer *h, int32_t m, const double *Z, double *S);
+/* Y = L G^T R^{-1} G L W [ncontrol x m] at the base (Y must not alias W) */
+riot_status riot_tracer_hess_apply(riot_tracer *h, int32_t m, const double *W, double *Y);
+/* grad = v - L G^T R^{-1} d, d = y - H(M(s_b)) (eq. 3), v nullable (zero); d_out [nobs]
+ * device or NULL; J_host = 1/2 v^T v + 1/2 d^T R^{-1} d or NULL (synchronises). */
+riot_status riot_tracer_gradient(riot_tracer *h, const double *v, double *grad, double *d_out,
+                                 double *J_host);
+
 /* Half-kernel taps l_0 .. l_w of the Gaussian square root used for B (host function):
  * l_d = c exp(-d^2 / ell^2), w = ceil(6.25 ell), c such that sum_{|d|<=w} l_d^2 = sigma_b^2,
  * so that B = L L^T has the correlation exp(-d^2 / (2 ell^2)) (the paper asks for Gaussian

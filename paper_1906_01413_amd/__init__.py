@@ -4,5 +4,5 @@ The compute path is the HIP library ``libriot.so`` (C ABI in include/riot.h);
 ``riot`` is its ctypes binding. Importing this package does not touch the GPU.
 """
 
-from .riot import (Riot, RiotBatch, RiotError, load_library, colmajor, empty_colmajor,  # noqa: F401
-                   gaussian_taps)
+from .riot import (Riot, RiotBatch, RiotError, Sketch, Tracer, load_library, colmajor,  # noqa: F401
+                   empty_colmajor, gaussian_taps)

@@ -1,4 +1,4 @@
-"""PyTorch differentiation of the observation map through the HIP TL/AD kernels.
+"""PyTorch differentiation of observation maps through the HIP TL/AD kernels.
 
 ``observe(x0, handle)`` returns the model's observed values y(x0) = {H_t M_{0->t} x0}
 over the assimilation window (Sec. 2.1). Its backward pass (vector-Jacobian product) is
@@ -39,3 +39,38 @@ def observe(x0: torch.Tensor, handle) -> torch.Tensor:
     if handle.ckpt_stride <= 0:
         raise ValueError("observe() needs a handle created with ckpt_stride > 0")
     return _Observe.apply(x0, handle)
+
+
+class _TracerObserve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, s, tracer):
+        obs = tracer.forward(s.detach())
+        ctx.tracer = tracer
+        ctx.version = tracer.base_version
+        ctx.save_for_backward(s.detach())
+        ctx.s_fwd = s.detach()
+        return obs.clone()
+
+    @staticmethod
+    def _rebase(ctx, s):
+        # the handle linearises at the controls of its latest forward call
+        if ctx.tracer.base_version != ctx.version:
+            ctx.tracer.forward(s)
+            ctx.version = ctx.tracer.base_version
+
+    @staticmethod
+    def backward(ctx, g_obs):
+        (s,) = ctx.saved_tensors
+        _TracerObserve._rebase(ctx, s)
+        return ctx.tracer.adjoint(g_obs.detach().contiguous())[:, 0].clone(), None
+
+    @staticmethod
+    def jvp(ctx, ds, _):
+        _TracerObserve._rebase(ctx, ctx.s_fwd)
+        return ctx.tracer.tangent(ds.detach().reshape(-1, 1))[:, 0].clone()
+
+
+def observe_tracer(s: torch.Tensor, tracer) -> torch.Tensor:
+    """Observed concentrations of the tracer model for controls s (differentiable in s:
+    backward = the model's adjoint, jvp = its tangent, at s)."""
+    return _TracerObserve.apply(s, tracer)

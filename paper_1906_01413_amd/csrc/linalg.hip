@@ -28,8 +28,17 @@ __global__ void __launch_bounds__(64)
     gemm_mfma_kernel(int M, int N, int K, const double *__restrict__ A, int lda,
                      const double *__restrict__ B, int ldb, double *__restrict__ C, int ldc,
                      double alpha, double beta, int kchunk, double *__restrict__ partial,
-                     const int *__restrict__ run, const GemmJob *__restrict__ jobs) {
+                     const int *__restrict__ run, const GemmJob *__restrict__ jobs,
+                     long long sA = 0, long long sB = 0, long long sC = 0) {
   int kz = blockIdx.z;
+  if (sA | sB | sC) {  // strided batch: blockIdx.z selects the matrices, no split over K
+    A += sA * blockIdx.z;
+    B += sB * blockIdx.z;
+    C += sC * blockIdx.z;
+    kchunk = K;
+    partial = nullptr;
+    kz = 0;
+  }
   if (jobs) {  // batched: blockIdx.z selects the problem, no split over K
     const GemmJob &J = jobs[blockIdx.z];
     M = J.M, N = J.N, K = J.K, A = J.A, lda = J.lda, B = J.B, ldb = J.ldb, C = J.C, ldc = J.ldc;
@@ -660,7 +669,7 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   double *part = splits > 1 ? partial : nullptr;
 #define RIOT_GEMM(TA_, TB_)                                                                  \
   hipLaunchKernelGGL((gemm_mfma_kernel<TA_, TB_>), grid, dim3(64), 0, st, M, N, K, A, lda, B, \
-                     ldb, C, ldc, alpha, beta, kchunk, part, run, nullptr)
+                     ldb, C, ldc, alpha, beta, kchunk, part, run, nullptr, 0, 0, 0)
   if (ta == 0 && tb == 0)
     RIOT_GEMM(0, 0);
   else if (ta == 1 && tb == 0)
@@ -850,7 +859,7 @@ hipError_t launch_gemm_batched(int ta, int tb, int nprob, int maxM, int maxN, do
   dim3 grid((maxM + 31) / 32, (maxN + 31) / 32, nprob);
 #define RIOT_GEMMB(TA_, TB_)                                                                    \
   hipLaunchKernelGGL((gemm_mfma_kernel<TA_, TB_>), grid, dim3(64), 0, st, 0, 0, 0, nullptr, 0,   \
-                     nullptr, 0, nullptr, 0, alpha, beta, 0, nullptr, nullptr, jobs)
+                     nullptr, 0, nullptr, 0, alpha, beta, 0, nullptr, nullptr, jobs, 0, 0, 0)
   if (ta == 0 && tb == 0)
     RIOT_GEMMB(0, 0);
   else if (ta == 1 && tb == 0)
@@ -910,6 +919,29 @@ hipError_t launch_copy_batched(int nprob, long long maxcount, const CopyJob *job
   if (nprob <= 0 || maxcount <= 0) return hipSuccess;
   const long long blocks = std::min<long long>((maxcount + 255) / 256, 64);
   hipLaunchKernelGGL(copy_batched_kernel, dim3((unsigned)blocks, nprob), dim3(256), 0, st, jobs);
+  return hipGetLastError();
+}
+
+
+hipError_t gemm_f64_strided(int ta, int tb, int M, int N, int K, double alpha, const double *A,
+                            int lda, long long sA, const double *B, int ldb, long long sB,
+                            double beta, double *C, int ldc, long long sC, int batch,
+                            hipStream_t st) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if (!(sA | sB | sC)) return hipErrorInvalidValue;
+  dim3 grid((M + 31) / 32, (N + 31) / 32, batch);
+#define RIOT_GEMMS(TA_, TB_)                                                                  \
+  hipLaunchKernelGGL((gemm_mfma_kernel<TA_, TB_>), grid, dim3(64), 0, st, M, N, K, A, lda, B, \
+                     ldb, C, ldc, alpha, beta, K, nullptr, nullptr, nullptr, sA, sB, sC)
+  if (ta == 0 && tb == 0)
+    RIOT_GEMMS(0, 0);
+  else if (ta == 1 && tb == 0)
+    RIOT_GEMMS(1, 0);
+  else if (ta == 0 && tb == 1)
+    RIOT_GEMMS(0, 1);
+  else
+    RIOT_GEMMS(1, 1);
+#undef RIOT_GEMMS
   return hipGetLastError();
 }
 

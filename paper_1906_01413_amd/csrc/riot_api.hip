@@ -137,6 +137,19 @@ struct riot_handle {
   ModelView mv{};
 };
 
+// Buffers of the RSVD linear algebra (CholeskyQR, projections, K, eigen-solve), shared by
+// a problem handle and a standalone sketch handle.
+struct LaSpace {
+  hipStream_t st;
+  double *Q, *G, *R, *B1, *B2, *K, *Zs, *sywork, *partial, *scal, *cvec;
+  int *flags;
+};
+
+inline LaSpace la_of(riot_handle *h) {
+  return {h->st, h->Q, h->G, h->R, h->B1, h->B2, h->K, h->Zs, h->sywork, h->partial, h->scal,
+          h->cvec, h->flags};
+}
+
 namespace {
 
 // Carve (or size) every region of the workspace.
@@ -259,25 +272,87 @@ riot_status read_flag(riot_handle *h, int idx, int *out) {
 // needed one are launched but return at once (device flag), so nothing synchronises.
 constexpr int kMaxCholQRPasses = 8;
 
-riot_status cholqr(riot_handle *h, int rows, int m, const double *Xin, double *Qout, bool shifted,
-                   int flag_idx, double *comp = nullptr, int mc = 0, int *count = nullptr) {
-  hipStream_t st = h->st;
+riot_status cholqr(const LaSpace &h, int rows, int m, const double *Xin, double *Qout,
+                   bool shifted, int flag_idx, double *comp = nullptr, int mc = 0,
+                   int *count = nullptr) {
+  hipStream_t st = h.st;
   const double u = 0x1.0p-53;
   const double srel = 11.0 * ((double)m * rows + (double)m * (m + 1)) * u;
-  int *cq = h->flags + 12;
+  int *cq = h.flags + 12;
   if (Qout != Xin)
     RIOT_HIP(hipMemcpyAsync(Qout, Xin, (size_t)rows * m * sizeof(double), hipMemcpyDeviceToDevice,
                             st));
   RIOT_HIP(launch_cholqr_reset(cq, st));
   for (int pass = 0; pass < kMaxCholQRPasses; ++pass) {
     const bool sh = shifted && pass == 0;
-    RIOT_HIP(gemm_f64(1, 0, m, m, rows, 1.0, Qout, rows, Qout, rows, 0.0, h->G, m, h->partial,
+    RIOT_HIP(gemm_f64(1, 0, m, m, rows, 1.0, Qout, rows, Qout, rows, 0.0, h.G, m, h.partial,
                       kSplitK, st, cq));
-    RIOT_HIP(launch_chol_blocked(m, h->G, h->R, srel, sh ? 1 : 2, h->flags + flag_idx,
-                                 h->flags + 4, st, cq, cq + 2));
-    RIOT_HIP(launch_trsm_rlt(rows, m, Qout, rows, h->R, st, cq));
-    if (comp) RIOT_HIP(launch_trsm_rlt(mc, m, comp, mc, h->R, st, cq));
+    RIOT_HIP(launch_chol_blocked(m, h.G, h.R, srel, sh ? 1 : 2, h.flags + flag_idx, h.flags + 4,
+                                 st, cq, cq + 2));
+    RIOT_HIP(launch_trsm_rlt(rows, m, Qout, rows, h.R, st, cq));
+    if (comp) RIOT_HIP(launch_trsm_rlt(mc, m, comp, mc, h.R, st, cq));
     RIOT_HIP(launch_cholqr_ctrl(cq, sh ? 1 : 0, count, st));
+  }
+  return RIOT_OK;
+}
+
+// Alg. 3 from a finished sketch: Q = orth(Y); B1 = Q^T Y, B2 = Q^T Omega_eff; K solves
+// K B2 = B1 (CholeskyQR of the square B2 carrying B1 as companion: B2 M = Q2, B1 M -> B1',
+// so B2^{-1} = M Q2^T and K = B1' Q2^T); K <- (K + K^T)/2 = Z diag(lambda) Z^T; V = Q Z.
+// The caller zeroes la.flags first.
+riot_status sketch_eig(const LaSpace &la, int n, int m, const double *Y, const double *Om_eff,
+                       double *lambda, double *V, riot_rsvd_info *info) {
+  hipStream_t st = la.st;
+  riot_status rs = cholqr(la, n, m, Y, la.Q, true, 0, nullptr, 0, la.flags + 5);
+  if (rs != RIOT_OK) return rs;
+  RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, la.Q, n, Y, n, 0.0, la.B1, m, la.partial, kSplitK, st));
+  RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, la.Q, n, Om_eff, n, 0.0, la.B2, m, la.partial, kSplitK,
+                    st));
+  rs = cholqr(la, m, m, la.B2, la.Zs, false, 1, la.B1, m);
+  if (rs != RIOT_OK) return rs;
+  RIOT_HIP(gemm_f64(0, 1, m, m, m, 1.0, la.B1, m, la.Zs, m, 0.0, la.K, m, nullptr, 1, st));
+  RIOT_HIP(launch_symmetrize(m, la.K, la.scal + 1, la.partial, st));
+  RIOT_HIP(launch_eig(m, la.K, lambda, la.Zs, la.sywork, la.flags + 2, st));
+  RIOT_HIP(gemm_f64(0, 0, n, m, m, 1.0, la.Q, n, la.Zs, m, 0.0, V, n, nullptr, 1, st));
+  RIOT_HIP(launch_check_finite(m, lambda, la.flags + 3, st));
+  RIOT_HIP(launch_check_finite((long long)n * m, V, la.flags + 3, st));
+  if (info) {
+    RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, la.Q, n, la.Q, n, 0.0, la.G, m, la.partial, kSplitK, st));
+    RIOT_HIP(launch_orth_err(m, la.G, la.scal + 2, st));
+    int fl[6];
+    double sc[3];
+    RIOT_HIP(hipMemcpyAsync(fl, la.flags, 6 * sizeof(int), hipMemcpyDeviceToHost, st));
+    RIOT_HIP(hipMemcpyAsync(sc, la.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    RIOT_HIP(hipStreamSynchronize(st));
+    info->chol_shifts = fl[4];
+    info->qr_passes = fl[5];
+    info->k_asym = sc[1];
+    info->orth_err = sc[2];
+    if (fl[0]) return RIOT_E_NOT_SPD;
+    if (fl[1]) return RIOT_E_SINGULAR;
+    if (fl[2]) return RIOT_E_NOCONV;
+    if (fl[3]) return RIOT_E_NONFINITE;
+  }
+  return RIOT_OK;
+}
+
+// dz from the k leading Ritz pairs (eqs. 8-11; no L): c = V^T g, then the LRA/LRU combination.
+riot_status sketch_increment(const LaSpace &la, int n, int k, const double *lambda,
+                             const double *V, const double *grad, riot_update mode, double *dz,
+                             double *dofs_host, int32_t *mode_used) {
+  hipStream_t st = la.st;
+  RIOT_HIP(gemm_f64(1, 0, k, 1, n, 1.0, V, n, grad, n, 0.0, la.cvec, k, la.partial, kSplitK, st));
+  const int ml = mode == RIOT_LRA ? 0 : (mode == RIOT_LRU ? 1 : 2);
+  RIOT_HIP(launch_increment_combine(n, k, lambda, V, la.cvec, grad, ml, dz, la.scal + 4, st));
+  if (mode_used) RIOT_HIP(launch_choose_mode(k, lambda, la.flags + 8, st));
+  if (dofs_host || mode_used) {
+    int mu = 0;
+    if (dofs_host)
+      RIOT_HIP(hipMemcpyAsync(dofs_host, la.scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+    if (mode_used)
+      RIOT_HIP(hipMemcpyAsync(&mu, la.flags + 8, sizeof(int), hipMemcpyDeviceToHost, st));
+    RIOT_HIP(hipStreamSynchronize(st));
+    if (mode_used) *mode_used = (mode == RIOT_ADAPTIVE) ? mu : (int32_t)mode;
   }
   return RIOT_OK;
 }
@@ -452,44 +527,13 @@ riot_status riot_rsvd(riot_handle *h, int32_t k, int32_t p_os, int32_t q, const 
   if (rs != RIOT_OK) return rs;
   const double *Om_eff = Om;
   for (int it = 0; it < q; ++it) {
-    rs = cholqr(h, n, m, h->Y, h->Q0, true, 0);
+    rs = cholqr(la_of(h), n, m, h->Y, h->Q0, true, 0);
     if (rs != RIOT_OK) return rs;
     rs = hess_apply_impl(h, m, h->Q0, h->Y, 0);
     if (rs != RIOT_OK) return rs;
     Om_eff = h->Q0;
   }
-  rs = cholqr(h, n, m, h->Y, h->Q, true, 0, nullptr, 0, h->flags + 5);
-  if (rs != RIOT_OK) return rs;
-  // B1 = Q^T Y, B2 = Q^T Omega_eff. K solves K B2 = B1: with B2 M = Q2 orthogonal (CholeskyQR
-  // of the square B2 carrying B1 as companion, B1 M -> B1'), B2^{-1} = M Q2^T and K = B1' Q2^T.
-  RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, h->Q, n, h->Y, n, 0.0, h->B1, m, h->partial, kSplitK, st));
-  RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, h->Q, n, Om_eff, n, 0.0, h->B2, m, h->partial, kSplitK, st));
-  rs = cholqr(h, m, m, h->B2, h->Zs, false, 1, h->B1, m);
-  if (rs != RIOT_OK) return rs;
-  RIOT_HIP(gemm_f64(0, 1, m, m, m, 1.0, h->B1, m, h->Zs, m, 0.0, h->K, m, nullptr, 1, st));
-  RIOT_HIP(launch_symmetrize(m, h->K, h->scal + 1, h->partial, st));
-  RIOT_HIP(launch_eig(m, h->K, lambda, h->Zs, h->sywork, h->flags + 2, st));
-  RIOT_HIP(gemm_f64(0, 0, n, m, m, 1.0, h->Q, n, h->Zs, m, 0.0, V, n, nullptr, 1, st));
-  RIOT_HIP(launch_check_finite(m, lambda, h->flags + 3, st));
-  RIOT_HIP(launch_check_finite((long long)n * m, V, h->flags + 3, st));
-  if (info) {
-    RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, h->Q, n, h->Q, n, 0.0, h->G, m, h->partial, kSplitK, st));
-    RIOT_HIP(launch_orth_err(m, h->G, h->scal + 2, st));
-    int fl[6];
-    double sc[3];
-    RIOT_HIP(hipMemcpyAsync(fl, h->flags, 6 * sizeof(int), hipMemcpyDeviceToHost, st));
-    RIOT_HIP(hipMemcpyAsync(sc, h->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-    RIOT_HIP(hipStreamSynchronize(st));
-    info->chol_shifts = fl[4];
-    info->qr_passes = fl[5];
-    info->k_asym = sc[1];
-    info->orth_err = sc[2];
-    if (fl[0]) return RIOT_E_NOT_SPD;
-    if (fl[1]) return RIOT_E_SINGULAR;
-    if (fl[2]) return RIOT_E_NOCONV;
-    if (fl[3]) return RIOT_E_NONFINITE;
-  }
-  return RIOT_OK;
+  return sketch_eig(la_of(h), n, m, h->Y, Om_eff, lambda, V, info);
 }
 
 riot_status riot_increment(riot_handle *h, int32_t k, const double *lambda, const double *V,
@@ -499,18 +543,19 @@ riot_status riot_increment(riot_handle *h, int32_t k, const double *lambda, cons
     return RIOT_E_ARG;
   if (mode != RIOT_ADAPTIVE && mode != RIOT_LRA && mode != RIOT_LRU) return RIOT_E_ARG;
   const int n = h->d.n;
-  hipStream_t st = h->st;
-  RIOT_HIP(gemm_f64(1, 0, k, 1, n, 1.0, V, n, grad, n, 0.0, h->cvec, k, h->partial, kSplitK, st));
-  const int ml = mode == RIOT_LRA ? 0 : (mode == RIOT_LRU ? 1 : 2);
-  RIOT_HIP(launch_increment_combine(n, k, lambda, V, h->cvec, grad, ml, dz, h->scal + 4, st));
-  RIOT_HIP(launch_apply_L(n, h->w, h->taps, 1, dz, dx, nullptr, 0, st));
-  if (mode_used) RIOT_HIP(launch_choose_mode(k, lambda, h->flags + 8, st));
+  // dx = L dz is enqueued before any host synchronisation of the increment
+  riot_status rs = sketch_increment(la_of(h), n, k, lambda, V, grad, mode, dz, nullptr, nullptr);
+  if (rs != RIOT_OK) return rs;
+  RIOT_HIP(launch_apply_L(n, h->w, h->taps, 1, dz, dx, nullptr, 0, h->st));
   if (dofs_host || mode_used) {
+    LaSpace la = la_of(h);
+    hipStream_t st = h->st;
     int mu = 0;
+    if (mode_used) RIOT_HIP(launch_choose_mode(k, lambda, la.flags + 8, st));
     if (dofs_host)
-      RIOT_HIP(hipMemcpyAsync(dofs_host, h->scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+      RIOT_HIP(hipMemcpyAsync(dofs_host, la.scal + 4, sizeof(double), hipMemcpyDeviceToHost, st));
     if (mode_used)
-      RIOT_HIP(hipMemcpyAsync(&mu, h->flags + 8, sizeof(int), hipMemcpyDeviceToHost, st));
+      RIOT_HIP(hipMemcpyAsync(&mu, la.flags + 8, sizeof(int), hipMemcpyDeviceToHost, st));
     RIOT_HIP(hipStreamSynchronize(st));
     if (mode_used) *mode_used = (mode == RIOT_ADAPTIVE) ? mu : (int32_t)mode;
   }
@@ -1282,6 +1327,85 @@ riot_status riot_batch_problem(riot_batch *b, int32_t j, riot_handle **h) {
   if (!b || !h || j < 0 || j >= b->nprob) return RIOT_E_ARG;
   *h = b->hs[j];
   return RIOT_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Standalone sketch handle: Alg. 3's steps after the Hessian-probe products, for any
+// operator whose products the caller computes (another model, a learned probe basis).
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+struct riot_sketch {
+  LaSpace la{};
+  int n = 0, m_max = 0;
+};
+
+namespace {
+
+size_t sketch_carve(riot_sketch &s, void *base) {
+  Carver c(base);
+  const size_t n = s.n, m = s.m_max, m2 = m * m;
+  LaSpace &la = s.la;
+  la.Q = c.take<double>(n * m);
+  la.G = c.take<double>(m2);
+  la.R = c.take<double>(m2);
+  la.B1 = c.take<double>(m2);
+  la.B2 = c.take<double>(m2);
+  la.K = c.take<double>(m2);
+  la.Zs = c.take<double>(m2);
+  la.sywork = c.take<double>(eig_work_doubles((int)m));
+  la.partial = c.take<double>((size_t)kSplitK * std::max(m2, m));
+  la.cvec = c.take<double>(m);
+  la.scal = c.take<double>(16);
+  la.flags = c.take<int>(16);
+  return c.off + 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t riot_sketch_workspace_bytes(int32_t n, int32_t m_max) {
+  if (n < 1 || m_max < 1 || m_max > 1088 || m_max > n) return 0;
+  riot_sketch s;
+  s.n = n, s.m_max = m_max;
+  return sketch_carve(s, nullptr);
+}
+
+riot_status riot_sketch_init(int32_t n, int32_t m_max, void *workspace, size_t bytes,
+                             void *hip_stream, riot_sketch **out) {
+  if (!out) return RIOT_E_ARG;
+  *out = nullptr;
+  const size_t need = riot_sketch_workspace_bytes(n, m_max);
+  if (!need || !workspace) return RIOT_E_ARG;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return RIOT_E_WORKSPACE;
+  if (bytes < need) return RIOT_E_WORKSPACE;
+  riot_sketch *s = new (std::nothrow) riot_sketch();
+  if (!s) return RIOT_E_ARG;
+  s->n = n, s->m_max = m_max;
+  sketch_carve(*s, workspace);
+  s->la.st = static_cast<hipStream_t>(hip_stream);
+  *out = s;
+  return RIOT_OK;
+}
+
+void riot_sketch_free(riot_sketch *s) { delete s; }
+
+riot_status riot_sketch_eig(riot_sketch *s, int32_t m, const double *Omega, const double *Y,
+                            double *lambda, double *V, riot_rsvd_info *info) {
+  if (!s || !Omega || !Y || !lambda || !V || m < 1 || m > s->m_max) return RIOT_E_ARG;
+  RIOT_HIP(launch_zero_ints(s->la.flags, 16, s->la.st));
+  return sketch_eig(s->la, s->n, m, Y, Omega, lambda, V, info);
+}
+
+riot_status riot_sketch_increment(riot_sketch *s, int32_t k, const double *lambda,
+                                  const double *V, const double *grad, riot_update mode,
+                                  double *dz, double *dofs_host, int32_t *mode_used) {
+  if (!s || !lambda || !V || !grad || !dz || k < 1 || k > s->m_max) return RIOT_E_ARG;
+  if (mode != RIOT_ADAPTIVE && mode != RIOT_LRA && mode != RIOT_LRU) return RIOT_E_ARG;
+  return sketch_increment(s->la, s->n, k, lambda, V, grad, mode, dz, dofs_host, mode_used);
 }
 
 }  // extern "C"

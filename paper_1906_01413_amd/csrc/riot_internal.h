@@ -225,6 +225,12 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
 hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_rel, int mode,
                                int *flag, int *shifts, hipStream_t st, const int *run = nullptr,
                                int *modflag = nullptr);
+// C_b = alpha op(A_b) op(B_b) + beta C_b for b < batch, with A_b = A + b sA (likewise B, C).
+hipError_t gemm_f64_strided(int ta, int tb, int M, int N, int K, double alpha, const double *A,
+                            int lda, long long sA, const double *B, int ldb, long long sB,
+                            double beta, double *C, int ldc, long long sC, int batch,
+                            hipStream_t st);
+
 // Batched forms of the launches above (jobs: device array of nprob entries; max*: largest
 // size over the batch, which sets the grid).
 hipError_t launch_gemm_batched(int ta, int tb, int nprob, int maxM, int maxN, double alpha,

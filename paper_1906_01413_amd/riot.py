@@ -33,7 +33,12 @@ EXPORTS = ("riot_workspace_bytes", "riot_init", "riot_free", "riot_status_str",
            "riot_batch_workspace_bytes", "riot_batch_init", "riot_batch_free", "riot_batch_buffers",
            "riot_batch_run", "riot_batch_set_layout", "riot_batch_autotune", "riot_batch_capture",
            "riot_batch_replay", "riot_batch_problem", "riot_batch_profile", "riot_gaussian_taps",
-           "riot_ckpt_forward", "riot_ckpt_tangent", "riot_ckpt_adjoint")
+           "riot_ckpt_forward", "riot_ckpt_tangent", "riot_ckpt_adjoint",
+           "riot_sketch_workspace_bytes", "riot_sketch_init", "riot_sketch_free", "riot_sketch_eig",
+           "riot_sketch_increment",
+           "riot_tracer_workspace_bytes", "riot_tracer_init", "riot_tracer_free", "riot_tracer_forward",
+           "riot_tracer_tangent", "riot_tracer_adjoint", "riot_tracer_apply_L", "riot_tracer_hess_apply",
+           "riot_tracer_gradient")
 
 
 class RiotError(RuntimeError):
@@ -57,6 +62,21 @@ class _Desc(ctypes.Structure):
 
 class _BatchIO(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in ("x", "grad", "lambda_", "V", "dz", "dx", "d")]
+
+
+class _TracerDesc(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int32), ("nsteps", ctypes.c_int32),
+        ("dt", ctypes.c_double), ("u0", ctypes.c_double), ("u1", ctypes.c_double),
+        ("v", ctypes.c_double), ("K", ctypes.c_double),
+        ("block", ctypes.c_int32), ("ntb", ctypes.c_int32),
+        ("E", ctypes.POINTER(ctypes.c_double)), ("nobs", ctypes.c_int32),
+        ("obs_t", ctypes.POINTER(ctypes.c_int32)), ("obs_y", ctypes.POINTER(ctypes.c_int32)),
+        ("obs_x", ctypes.POINTER(ctypes.c_int32)),
+        ("y", ctypes.POINTER(ctypes.c_double)), ("rinv", ctypes.POINTER(ctypes.c_double)),
+        ("L1", ctypes.POINTER(ctypes.c_double)), ("sigma", ctypes.c_double),
+        ("m_max", ctypes.c_int32),
+    ]
 
 
 class _RsvdInfo(ctypes.Structure):
@@ -112,6 +132,22 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "riot_ckpt_forward": (i32, [vp, vp, vp, vp]),
         "riot_ckpt_tangent": (i32, [vp, i32, vp, vp, vp]),
         "riot_ckpt_adjoint": (i32, [vp, i32, vp, vp, vp]),
+        "riot_sketch_workspace_bytes": (ctypes.c_size_t, [i32, i32]),
+        "riot_sketch_init": (i32, [i32, i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+        "riot_sketch_free": (None, [vp]),
+        "riot_sketch_eig": (i32, [vp, i32, vp, vp, vp, vp, ctypes.POINTER(_RsvdInfo)]),
+        "riot_sketch_increment": (i32, [vp, i32, vp, vp, vp, i32, vp, ctypes.POINTER(dbl),
+                                        ctypes.POINTER(i32)]),
+        "riot_tracer_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(_TracerDesc)]),
+        "riot_tracer_init": (i32, [ctypes.POINTER(_TracerDesc), vp, ctypes.c_size_t, vp,
+                                   ctypes.POINTER(vp)]),
+        "riot_tracer_free": (None, [vp]),
+        "riot_tracer_forward": (i32, [vp, vp, vp]),
+        "riot_tracer_tangent": (i32, [vp, i32, vp, vp]),
+        "riot_tracer_adjoint": (i32, [vp, i32, vp, vp]),
+        "riot_tracer_apply_L": (i32, [vp, i32, vp, vp]),
+        "riot_tracer_hess_apply": (i32, [vp, i32, vp, vp]),
+        "riot_tracer_gradient": (i32, [vp, vp, vp, vp, ctypes.POINTER(dbl)]),
         "riot_batch_profile": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(dbl),
                                      ctypes.POINTER(i32)]),
     }
@@ -505,3 +541,159 @@ class RiotBatch:
         _check(self.lib.riot_batch_problem(self.b, int(j), ctypes.byref(h)), "riot_batch_problem")
         return Riot._bind(self.lib, h, self.n[j], self.nsteps[j], self.m[j], self.nobs[j], self.device,
                           self.stream, self)
+
+
+def _aligned_workspace(nbytes, device):
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    return ws, (ws.data_ptr() + 255) // 256 * 256
+
+
+def _cols(t, rows, device):
+    t = colmajor(t, device)
+    if t.dim() == 1:
+        t = t.reshape(-1, 1).t().contiguous().t()
+    assert t.shape[0] == rows
+    return t
+
+
+class Sketch:
+    """Alg. 3 after the probe products, for any operator (C ABI riot_sketch_*)."""
+
+    def __init__(self, n, m_max, device="cuda"):
+        self.lib = load_library()
+        self.n, self.m_max, self.device = int(n), int(m_max), torch.device(device)
+        nb = self.lib.riot_sketch_workspace_bytes(self.n, self.m_max)
+        if nb == 0:
+            raise RiotError(-1, "riot_sketch_workspace_bytes")
+        self.workspace, base = _aligned_workspace(nb, self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(self.lib.riot_sketch_init(self.n, self.m_max, ctypes.c_void_p(base), ctypes.c_size_t(nb),
+                                         ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "riot_sketch_init")
+        self.h = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.lib.riot_sketch_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def eig(self, Omega, Y, want_info=True):
+        Om, Yc = _cols(Omega, self.n, self.device), _cols(Y, self.n, self.device)
+        m = Om.shape[1]
+        lam = torch.empty(m, dtype=torch.float64, device=self.device)
+        V = empty_colmajor(self.n, m, self.device)
+        info = _RsvdInfo()
+        _check(self.lib.riot_sketch_eig(self.h, m, _ptr(Om), _ptr(Yc), _ptr(lam), _ptr(V),
+                                        ctypes.byref(info) if want_info else None), "riot_sketch_eig")
+        return lam, V, (RsvdInfo(info.chol_shifts, info.qr_passes, info.k_asym, info.orth_err)
+                        if want_info else None)
+
+    def increment(self, lam, V, g, k=None, mode="adaptive"):
+        k = V.shape[1] if k is None else int(k)
+        dz = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        dofs, mu = ctypes.c_double(), ctypes.c_int32()
+        _check(self.lib.riot_sketch_increment(self.h, k, _ptr(lam), _ptr(V), _ptr(colmajor(g, self.device)),
+                                              MODES[mode], _ptr(dz), ctypes.byref(dofs), ctypes.byref(mu)),
+               "riot_sketch_increment")
+        return dz, dofs.value, {LRA: "lra", LRU: "lru"}[mu.value]
+
+
+class Tracer:
+    """Tracer source inversion on a periodic 2-D grid (C ABI riot_tracer_*).
+
+    grid: dict with N, T, dt, u0, u1, v, K, block, ntb. Controls are [ntb][by][bx]
+    flattened (ncontrol,), observation vectors follow the caller's observation order.
+    """
+
+    def __init__(self, grid, E, obs_t, obs_y, obs_x, y, rinv, L1, sigma, m_max, device="cuda"):
+        self.lib = load_library()
+        self.device = torch.device(device)
+        g = dict(grid)
+        self.N, self.T, self.block, self.ntb = int(g["N"]), int(g["T"]), int(g["block"]), int(g["ntb"])
+        self.Nb = self.N // self.block
+        self.ncontrol = self.ntb * self.Nb * self.Nb
+        self.m_max = int(m_max)
+        keep = [np.ascontiguousarray(E, dtype=np.float64),
+                np.ascontiguousarray(obs_t, dtype=np.int32), np.ascontiguousarray(obs_y, dtype=np.int32),
+                np.ascontiguousarray(obs_x, dtype=np.int32), np.ascontiguousarray(y, dtype=np.float64),
+                np.ascontiguousarray(rinv, dtype=np.float64), np.ascontiguousarray(L1, dtype=np.float64)]
+        self.nobs = int(keep[1].size)
+        P = lambda a, c: a.ctypes.data_as(ctypes.POINTER(c))  # noqa: E731
+        d = _TracerDesc()
+        d.N, d.nsteps, d.dt, d.u0, d.u1, d.v, d.K = (self.N, self.T, float(g["dt"]), float(g["u0"]),
+                                                      float(g["u1"]), float(g["v"]), float(g["K"]))
+        d.block, d.ntb = self.block, self.ntb
+        d.E, d.nobs = P(keep[0], ctypes.c_double), self.nobs
+        d.obs_t, d.obs_y, d.obs_x = (P(keep[1], ctypes.c_int32), P(keep[2], ctypes.c_int32),
+                                     P(keep[3], ctypes.c_int32))
+        d.y, d.rinv, d.L1 = P(keep[4], ctypes.c_double), P(keep[5], ctypes.c_double), P(keep[6], ctypes.c_double)
+        d.sigma, d.m_max = float(sigma), self.m_max
+        nb = self.lib.riot_tracer_workspace_bytes(ctypes.byref(d))
+        if nb == 0:
+            raise RiotError(-1, "riot_tracer_workspace_bytes")
+        self.workspace_bytes = int(nb)
+        self.workspace, base = _aligned_workspace(nb, self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(self.lib.riot_tracer_init(ctypes.byref(d), ctypes.c_void_p(base), ctypes.c_size_t(nb),
+                                         ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "riot_tracer_init")
+        self.h = h
+        self.base_version = 0
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.lib.riot_tracer_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def forward(self, s):
+        """Observed concentrations for controls s; s becomes the derivatives' base."""
+        s = colmajor(s, self.device)
+        obs = torch.empty(max(self.nobs, 1), dtype=torch.float64, device=self.device)
+        _check(self.lib.riot_tracer_forward(self.h, _ptr(s), _ptr(obs)), "riot_tracer_forward")
+        self.base_version += 1
+        return obs[: self.nobs]
+
+    def _m(self, X, rows):
+        X = _cols(X, rows, self.device)
+        return X, X.shape[1]
+
+    def tangent(self, dS):
+        dS, m = self._m(dS, self.ncontrol)
+        out = empty_colmajor(max(self.nobs, 1), m, self.device)
+        _check(self.lib.riot_tracer_tangent(self.h, m, _ptr(dS), _ptr(out)), "riot_tracer_tangent")
+        return out[: self.nobs]
+
+    def adjoint(self, gObs):
+        gObs, m = self._m(gObs, self.nobs)
+        out = empty_colmajor(self.ncontrol, m, self.device)
+        _check(self.lib.riot_tracer_adjoint(self.h, m, _ptr(gObs), _ptr(out)), "riot_tracer_adjoint")
+        return out
+
+    def apply_L(self, Z):
+        Z, m = self._m(Z, self.ncontrol)
+        out = empty_colmajor(self.ncontrol, m, self.device)
+        _check(self.lib.riot_tracer_apply_L(self.h, m, _ptr(Z), _ptr(out)), "riot_tracer_apply_L")
+        return out
+
+    def hess_apply(self, W, out=None):
+        W, m = self._m(W, self.ncontrol)
+        Y = empty_colmajor(self.ncontrol, m, self.device) if out is None else out
+        _check(self.lib.riot_tracer_hess_apply(self.h, m, _ptr(W), _ptr(Y)), "riot_tracer_hess_apply")
+        return Y
+
+    def gradient(self, v=None, want_cost=True):
+        g = torch.empty(self.ncontrol, dtype=torch.float64, device=self.device)
+        d = torch.empty(max(self.nobs, 1), dtype=torch.float64, device=self.device)
+        J = ctypes.c_double()
+        vv = None if v is None else colmajor(v, self.device)
+        _check(self.lib.riot_tracer_gradient(self.h, _ptr(vv), _ptr(g), _ptr(d),
+                                             ctypes.byref(J) if want_cost else None), "riot_tracer_gradient")
+        return g, d[: self.nobs], (J.value if want_cost else None)

@@ -1,0 +1,143 @@
+"""Tracer source inversion on the GPU against the FP64 oracle (64 x 64 grid, 24 steps,
+1024 controls, 400 observations on random-walk tracks), plus the same products at the
+benchmarked size checked by properties (dot-product identity, symmetry of the Hessian
+product) and the RSVD of this model's Hessian through the sketch handle against the
+oracle's RSVD on the same probes.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import advdiff, fourdvar
+from synthetic import advdiff_draws
+from tests._problems import rel, to_np
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _tracer(p, m_max=8):
+    from paper_1906_01413_amd import Tracer
+    g = p.grid
+    grid = dict(N=g.N, T=g.T, dt=g.dt, u0=g.u0, u1=g.u1, v=g.v, K=g.K, block=g.block, ntb=g.ntb)
+    return Tracer(grid, p.E, p.obs.t, p.obs.y, p.obs.x, p.y, p.rinv, p.L1, p.sigma, m_max)
+
+
+@pytest.fixture(scope="module")
+def small():
+    p = advdiff.realize(advdiff_draws("ad2_n64", 0))
+    return p, _tracer(p, m_max=40)
+
+
+def test_tracer_forward_tangent_adjoint_match_oracle(small):
+    p, tr = small
+    g = p.grid
+    rng = np.random.default_rng(1)
+    s0 = 0.3 * rng.standard_normal(g.ncontrol)
+    obs = tr.forward(s0)
+    ref, _ = advdiff.forward(g, p.E, s0, p.obs)
+    assert rel(to_np(obs), ref) < 1e-12
+    dS = rng.standard_normal((g.ncontrol, 3))
+    assert rel(to_np(tr.tangent(dS)), advdiff.tangent(g, p.E, s0, p.obs, dS)) < 1e-12
+    f = rng.standard_normal((p.obs.t.size, 3))
+    gS = tr.adjoint(f)
+    assert rel(to_np(gS), advdiff.adjoint(g, p.E, s0, p.obs, f)) < 1e-12
+    lhs = np.sum(to_np(tr.tangent(dS)) * f)
+    rhs = np.sum(dS * to_np(gS))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_tracer_prior_root_hessian_gradient_match_oracle(small):
+    p, tr = small
+    g = p.grid
+    rng = np.random.default_rng(2)
+    Z = rng.standard_normal((g.ncontrol, 4))
+    assert rel(to_np(tr.apply_L(Z)), advdiff.apply_L(g, p.L1, p.sigma, Z)) < 1e-13
+    sb = np.zeros(g.ncontrol)
+    tr.forward(sb)
+    assert rel(to_np(tr.hess_apply(Z)), advdiff.hvp(p, sb, Z)) < 1e-11
+    gr, d, J = tr.gradient()
+    assert rel(to_np(gr), advdiff.gradient(p, sb)) < 1e-12
+    hx, _ = advdiff.forward(g, p.E, sb, p.obs)
+    Jo = 0.5 * np.sum(p.rinv * (p.y - hx) ** 2)
+    assert abs(J - Jo) <= 1e-12 * Jo
+
+
+def test_tracer_rsvd_through_sketch_matches_oracle(small):
+    """Alg. 3 for this model: Y = A Omega by the tracer, the rest by the sketch handle;
+    against the oracle's RSVD of the same Hessian on the same probes."""
+    from paper_1906_01413_amd import Sketch
+    p, tr = small
+    g = p.grid
+    m = 40
+    sb = np.zeros(g.ncontrol)
+    tr.forward(sb)
+    Om = np.random.default_rng(3).standard_normal((g.ncontrol, m))
+    Y = tr.hess_apply(Om)
+    sk = Sketch(g.ncontrol, m)
+    lam, V, info = sk.eig(Om, Y)
+    ro = fourdvar.rsvd(lambda X: advdiff.hvp(p, sb, X), Om, q=0)
+    assert info.orth_err < 1e-12
+    assert np.max(np.abs(to_np(lam) - ro.lam)) <= 1e-9 * abs(ro.lam[0])
+    gr, _, _ = tr.gradient()
+    dz, dofs, mode = sk.increment(lam, V, gr)
+    # oracle increment in control space (no L: the tracer's increment is ds = L dz)
+    lam_o, V_o = ro.lam, ro.V
+    c = V_o.T @ advdiff.gradient(p, sb)
+    if lam_o[-1] >= 1.0:
+        dzo = -V_o @ (c / (1.0 + lam_o))
+    else:
+        dzo = -(advdiff.gradient(p, sb) - V_o @ (c * lam_o / (1.0 + lam_o)))
+    assert mode == ("lra" if lam_o[-1] >= 1.0 else "lru")
+    assert rel(to_np(dz), dzo) < 1e-9
+
+
+def test_tracer_autograd_matches_finite_differences_and_gradient(small):
+    from paper_1906_01413_amd.autograd import observe_tracer
+    p, tr = small
+    g = p.grid
+    y = torch.tensor(p.y, device="cuda")
+    rinv = torch.tensor(p.rinv, device="cuda")
+
+    def loss(s):
+        d = y - observe_tracer(s, tr)
+        return 0.5 * torch.sum(rinv * d * d)
+
+    s0 = torch.zeros(g.ncontrol, device="cuda", dtype=torch.float64, requires_grad=True)
+    (gs,) = torch.autograd.grad(loss(s0), s0)
+    rng = np.random.default_rng(4)
+    for _ in range(2):
+        u = torch.tensor(rng.standard_normal(g.ncontrol), device="cuda")
+        eps = 1e-5
+        with torch.no_grad():
+            fd = (loss(s0 + eps * u) - loss(s0 - eps * u)).item() / (2 * eps)
+        an = torch.dot(gs, u).item()
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1.0), (fd, an)
+    # control-space 4D-Var gradient (v = 0) = L (d loss / d s)
+    tr.forward(np.zeros(g.ncontrol))
+    gr, _, _ = tr.gradient()
+    assert rel(to_np(tr.apply_L(gs))[:, 0], to_np(gr)) < 1e-12
+
+
+def test_tracer_full_size_products_are_consistent():
+    """512 x 512 grid, 96 steps, 65536 controls, 4000 observations: adjoint identity and
+    symmetry of the Hessian product at the benchmarked size."""
+    p_d = advdiff_draws("ad2_n512", 0)
+    from paper_1906_01413_amd import Tracer
+    gp = p_d["grid"]
+    nb = gp["N"] // gp["block"]
+    L1 = advdiff.sqrt_corr_1d(nb, p_d["ell"])
+    tr = Tracer(gp, p_d["E"], p_d["obs_t"], p_d["obs_y"], p_d["obs_x"],
+                np.ones(p_d["obs_t"].size), np.ones(p_d["obs_t"].size), L1, p_d["sigma"], 4)
+    nc = tr.ncontrol
+    tr.forward(np.zeros(nc))
+    rng = np.random.default_rng(6)
+    dS = rng.standard_normal((nc, 2))
+    f = rng.standard_normal((tr.nobs, 2))
+    lhs = np.sum(to_np(tr.tangent(dS)) * f)
+    rhs = np.sum(dS * to_np(tr.adjoint(f)))
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+    W = rng.standard_normal((nc, 2))
+    HW = to_np(tr.hess_apply(W))
+    a, b = np.dot(W[:, 0], HW[:, 1]), np.dot(W[:, 1], HW[:, 0])
+    assert abs(a - b) <= 1e-11 * max(abs(a), abs(b))

@@ -286,6 +286,81 @@ def batch_leg(nprob: int, seed: int, dev, reps: int = 5) -> dict:
     }
 
 
+def tracer_leg(seed: int, dev, m: int = 512, reps: int = 3) -> dict:
+    """Source inversion at 512 x 512 cells, 96 steps, 65536 controls, 4000 observations:
+    inputs built with the library (twin experiment: s_true = L xi, y from the forward
+    model, R sigma = 10 %), then m Hessian-probe products, the RSVD through the sketch
+    handle and the increment, timed with HIP events."""
+    import torch
+    from paper_1906_01413_amd import Sketch, Tracer, exp_corr_sqrt
+    from synthetic import advdiff_draws
+
+    t_setup = time.perf_counter()
+    dr = advdiff_draws("ad2_n512", seed)
+    gp = dr["grid"]
+    L1 = exp_corr_sqrt(gp["N"] // gp["block"], dr["ell"])
+    nobs = dr["obs_t"].size
+    ones = np.ones(nobs)
+    t0 = Tracer(gp, dr["E"], dr["obs_t"], dr["obs_y"], dr["obs_x"], ones, ones, L1, dr["sigma"], 1,
+                device=dev)
+    s_true = t0.apply_L(torch.tensor(dr["xi"], device=dev))[:, 0]
+    y_true = t0.forward(s_true).cpu().numpy()
+    del t0
+    sig = dr["rel_err"] * y_true
+    y = y_true + sig * dr["obs_noise"]
+    tr = Tracer(gp, dr["E"], dr["obs_t"], dr["obs_y"], dr["obs_x"], y, 1.0 / (sig * sig), L1,
+                dr["sigma"], m, device=dev)
+    nc = tr.ncontrol
+    tr.forward(torch.zeros(nc, dtype=torch.float64, device=dev))
+    g, _, J = tr.gradient()
+    gen = torch.Generator(device=dev).manual_seed(seed)
+    Om = torch.randn(m, nc, dtype=torch.float64, device=dev, generator=gen).t()
+    Y = torch.empty(m, nc, dtype=torch.float64, device=dev).t()
+    sk = Sketch(nc, m, device=dev)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(n):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    ms_hvp = timed(lambda: tr.hess_apply(Om, out=Y), reps)
+    res = {}
+
+    def inner():
+        tr.hess_apply(Om, out=Y)
+        lam, V, _ = sk.eig(Om, Y, want_info=False)
+        res["lv"] = (lam, V)
+
+    ms_inner = timed(inner, reps)
+    lam, V = res["lv"]
+    dz, dofs, mode = sk.increment(lam, V, g)
+    N, T = gp["N"], gp["T"]
+    # bytes one probe must move per step: read and write the field in the TL and in the AD
+    byts = 32.0 * N * N * T * m
+    bw = byts / (ms_hvp / 1e3) / 1e9
+    return {
+        "workload": f"tracer source inversion: {N}x{N} periodic grid, {T} steps, {nc} controls, "
+                    f"{nobs} track observations, {m} probes",
+        "probes": m, "hvp_ms": ms_hvp, "hvp_per_s": m / (ms_hvp / 1e3),
+        "inner_loop_ms": ms_inner, "dofs": dofs, "mode": mode, "cost_J": J,
+        "roofline": {"bound": "hbm", "achieved": bw, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": bw / PEAK_HBM_GBS,
+                     "algorithmic_bytes": byts,
+                     "note": "32 N^2 bytes per probe and step: one field read and written in "
+                             "the tangent and in the adjoint sweep"},
+        "setup_s": setup_s,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +374,8 @@ def main():
     ap.add_argument("--hvp-reps", type=int, default=20)
     ap.add_argument("--batch", type=int, default=1000,
                     help="problems in the batched-uneven leg (0 skips it)")
+    ap.add_argument("--tracer", type=int, default=1,
+                    help="run the tracer source-inversion leg (0 skips it)")
     ap.add_argument("--counter-pass", action="store_true",
                     help="only launch the TL/AD kernel three times and a 256 MiB device copy "
                          "(calibration), for rocprofv3 --pmc runs; prints no JSON")
@@ -441,6 +518,14 @@ def main():
         print(f"[bench] batch: pipeline {bl['pipeline_ms_graph']:.2f} ms (graph), "
               f"{bl['pipeline_ms_eager']:.2f} ms (eager); probe products {bl['hvp_launch_ms']:.2f} ms, "
               f"load balance {bl['load_balance']:.3f}, layout {bl['layout']}", file=sys.stderr, flush=True)
+
+    if args.tracer:
+        print("[bench] tracer source-inversion leg", file=sys.stderr, flush=True)
+        out["tracer"] = tracer_leg(args.seed, dev)
+        tl = out["tracer"]
+        print(f"[bench] tracer: {tl['probes']} probe products {tl['hvp_ms']:.1f} ms "
+              f"({tl['roofline']['achieved']:.0f} GB/s), inner loop {tl['inner_loop_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, m)

@@ -310,6 +310,11 @@ typedef struct {
     int32_t m_max;             /* largest member block of tangent / adjoint / Hessian calls */
 } riot_tracer_desc;
 
+/* Host helper: the symmetric square root L1 [n x n] of the periodic 1-D exponential
+ * correlation C1[i,j] = exp(-min(|i-j|, n-|i-j|) / ell), from the circulant's cosine
+ * spectrum (eigenvalues clipped at 0). */
+riot_status riot_exp_corr_sqrt(int32_t n, double ell, double *L1);
+
 size_t riot_tracer_workspace_bytes(const riot_tracer_desc *desc);
 riot_status riot_tracer_init(const riot_tracer_desc *desc, void *workspace, size_t bytes,
                              void *hip_stream, riot_tracer **out);

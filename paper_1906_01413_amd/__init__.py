@@ -5,4 +5,4 @@ The compute path is the HIP library ``libriot.so`` (C ABI in include/riot.h);
 """
 
 from .riot import (Riot, RiotBatch, RiotError, Sketch, Tracer, load_library, colmajor,  # noqa: F401
-                   empty_colmajor, gaussian_taps)
+                   empty_colmajor, exp_corr_sqrt, gaussian_taps)

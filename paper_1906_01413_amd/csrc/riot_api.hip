@@ -1307,6 +1307,29 @@ riot_status riot_batch_profile(riot_batch *b, float *ms, double *busy_frac, int3
   return RIOT_OK;
 }
 
+riot_status riot_exp_corr_sqrt(int32_t n, double ell, double *L1) {
+  if (n < 1 || !(ell > 0.0) || !L1) return RIOT_E_ARG;
+  // C1[i,j] = exp(-d/ell) with periodic d is a symmetric circulant: its eigenvalues are
+  // the cosine transform of its first row, its eigenvectors the Fourier modes, so
+  // L1[i,j] = (1/n) sum_k sqrt(max(l_k, 0)) cos(2 pi k (i - j) / n).
+  const double tw = 2.0 * 3.14159265358979323846 / n;
+  std::vector<double> row(n), lam(n), col(n);
+  for (int d = 0; d < n; ++d) row[d] = std::exp(-std::min(d, n - d) / ell);
+  for (int k = 0; k < n; ++k) {
+    double s = 0.0;
+    for (int d = 0; d < n; ++d) s += row[d] * std::cos(tw * ((long long)k * d % n));
+    lam[k] = std::sqrt(std::max(s, 0.0));
+  }
+  for (int d = 0; d < n; ++d) {
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += lam[k] * std::cos(tw * ((long long)k * d % n));
+    col[d] = s / n;
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) L1[(size_t)i * n + j] = col[(i - j + n) % n];
+  return RIOT_OK;
+}
+
 int32_t riot_gaussian_taps(double ell, double sigma_b, int32_t max_taps, double *taps) {
   if (!(ell > 0.0) || !(sigma_b > 0.0) || !std::isfinite(ell) || !std::isfinite(sigma_b))
     return -1;

@@ -38,7 +38,7 @@ EXPORTS = ("riot_workspace_bytes", "riot_init", "riot_free", "riot_status_str",
            "riot_sketch_increment",
            "riot_tracer_workspace_bytes", "riot_tracer_init", "riot_tracer_free", "riot_tracer_forward",
            "riot_tracer_tangent", "riot_tracer_adjoint", "riot_tracer_apply_L", "riot_tracer_hess_apply",
-           "riot_tracer_gradient")
+           "riot_tracer_gradient", "riot_exp_corr_sqrt")
 
 
 class RiotError(RuntimeError):
@@ -148,6 +148,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "riot_tracer_apply_L": (i32, [vp, i32, vp, vp]),
         "riot_tracer_hess_apply": (i32, [vp, i32, vp, vp]),
         "riot_tracer_gradient": (i32, [vp, vp, vp, vp, ctypes.POINTER(dbl)]),
+        "riot_exp_corr_sqrt": (i32, [i32, dbl, vp]),
         "riot_batch_profile": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(dbl),
                                      ctypes.POINTER(i32)]),
     }
@@ -420,6 +421,14 @@ def gaussian_taps(ell, sigma_b):
     taps = np.empty(w + 1)
     lib.riot_gaussian_taps(float(ell), float(sigma_b), w + 1, taps.ctypes.data_as(ctypes.c_void_p))
     return taps
+
+
+def exp_corr_sqrt(n, ell):
+    """Library square root of the periodic 1-D exponential correlation (riot_exp_corr_sqrt)."""
+    L1 = np.empty((int(n), int(n)))
+    _check(load_library().riot_exp_corr_sqrt(int(n), float(ell), L1.ctypes.data_as(ctypes.c_void_p)),
+           "riot_exp_corr_sqrt")
+    return L1
 
 
 class RiotBatch:

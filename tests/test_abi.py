@@ -98,3 +98,16 @@ def test_gaussian_taps_host_helper_matches_oracle():
         a, b = gaussian_taps(ell, sb), oracle_taps(ell, sb)
         assert a.size == b.size
         assert np.max(np.abs(a - b)) <= 1e-15 * np.max(np.abs(b))
+
+
+def test_exp_corr_sqrt_host_helper_matches_oracle():
+    """riot_exp_corr_sqrt (circulant cosine spectrum, host code) against the oracle's
+    eigendecomposition-based square root."""
+    import numpy as np
+
+    from oracle.advdiff import sqrt_corr_1d
+    from paper_1906_01413_amd import exp_corr_sqrt
+
+    for n, ell in ((16, 3.0), (128, 3.0), (37, 1.5)):
+        a, b = exp_corr_sqrt(n, ell), sqrt_corr_1d(n, ell)
+        assert np.max(np.abs(a - b)) < 1e-12, (n, ell)

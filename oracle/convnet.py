@@ -1,0 +1,93 @@
+"""Sketch-proposal network and its training loss (test oracle, plain NumPy FP64).
+
+Test infrastructure only: nothing in the product path imports this module.
+
+A 1-D periodic convolutional network maps a background state x (n,) to k basis vectors
+N (n, k) that are used as RIOT probes in place of Gaussian ones. Layers l = 1..L:
+  z_l[c, i] = b_l[c] + sum_{c', j} W_l[c, c', j] h_{l-1}[c', (i + j - r) mod n],
+  h_l = relu(z_l) for l < L, h_L = z_L,
+with h_0 = x as one channel, width 2 r + 1. N[:, c] = h_L[c, :].
+
+Loss (subspace capture of the leading Hessian eigenvectors V (n, k) with weights w):
+  loss(N) = - sum_i w_i v_i^T P v_i / sum_i w_i,   P = N (N^T N)^{-1} N^T,
+whose gradient is  d loss / d N = -(2 / sum w) (I - P) M N (N^T N)^{-1},  M = V diag(w) V^T.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+
+def conv1d(x: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """z[c, i] = b[c] + sum_{c', j} W[c, c', j] x[c', (i + j - r) mod n] (x: (cin, n))."""
+    cout, cin, width = W.shape
+    r = width // 2
+    n = x.shape[1]
+    z = np.repeat(b[:, None], n, axis=1).astype(np.float64)
+    for j in range(width):
+        shifted = np.roll(x, -(j - r), axis=1)  # shifted[c', i] = x[c', (i + j - r) mod n]
+        z += W[:, :, j] @ shifted
+    return z
+
+
+def conv1d_backward(x: np.ndarray, W: np.ndarray, gz: np.ndarray):
+    """Gradients (gx, gW, gb) of sum(gz * conv1d(x, W, b))."""
+    cout, cin, width = W.shape
+    r = width // 2
+    gW = np.zeros_like(W, dtype=np.float64)
+    gx = np.zeros_like(x, dtype=np.float64)
+    for j in range(width):
+        shifted = np.roll(x, -(j - r), axis=1)
+        gW[:, :, j] = gz @ shifted.T
+        gx += np.roll(W[:, :, j].T @ gz, j - r, axis=1)
+    return gx, gW, gz.sum(axis=1)
+
+
+def forward(params, x: np.ndarray):
+    """Network output N (n, k) and the per-layer activations (for backward)."""
+    h = x[None, :].astype(np.float64)
+    acts = [h]
+    for li, (W, b) in enumerate(params):
+        z = conv1d(h, W, b)
+        h = np.maximum(z, 0.0) if li < len(params) - 1 else z
+        acts.append(h)
+    return h.T.copy(), acts
+
+
+def backward(params, acts, gN: np.ndarray):
+    """Parameter gradients [(gW, gb)] of sum(gN * N)."""
+    g = gN.T.copy()
+    grads = [None] * len(params)
+    for li in range(len(params) - 1, -1, -1):
+        W, b = params[li]
+        if li < len(params) - 1:
+            g = g * (acts[li + 1] > 0.0)  # relu'
+        gx, gW, gb = conv1d_backward(acts[li], W, g)
+        grads[li] = (gW, gb)
+        g = gx
+    return grads
+
+
+def capture_loss(N: np.ndarray, V: np.ndarray, w: np.ndarray):
+    """(loss, d loss / d N) of the weighted subspace capture (module doc)."""
+    G = N.T @ N
+    Gi = np.linalg.inv(G)
+    A = V.T @ N                      # a_i = N^T v_i
+    sw = float(np.sum(w))
+    loss = -float(np.sum(w * np.einsum("ij,jk,ik->i", A, Gi, A))) / sw
+    MN = V @ (w[:, None] * A)        # M N
+    X = MN @ Gi
+    PX = N @ (Gi @ (N.T @ X))
+    return loss, -(2.0 / sw) * (X - PX)
+
+
+def init_params(rng, channels=64, layers=4, width=9, k=64):
+    """He-normal weights, zero biases; the last layer has k output channels."""
+    params = []
+    cin = 1
+    for li in range(layers):
+        cout = k if li == layers - 1 else channels
+        W = rng.standard_normal((cout, cin, width)) * np.sqrt(2.0 / (cin * width))
+        params.append((W, np.zeros(cout)))
+        cin = cout
+    return params

@@ -1,0 +1,69 @@
+"""Pins of the sketch-proposal network oracle (oracle/convnet.py)."""
+
+import numpy as np
+
+from oracle import convnet
+
+
+def test_conv1d_is_a_circulant_matrix_product():
+    """One input and one output channel: the layer is x -> C x with C circulant."""
+    rng = np.random.default_rng(0)
+    n, width = 11, 5
+    r = width // 2
+    W = rng.standard_normal((1, 1, width))
+    x = rng.standard_normal((1, n))
+    C = np.zeros((n, n))
+    for i in range(n):
+        for j in range(width):
+            C[i, (i + j - r) % n] += W[0, 0, j]
+    z = convnet.conv1d(x, W, np.array([0.3]))
+    assert np.max(np.abs(z[0] - (C @ x[0] + 0.3))) < 1e-14
+
+
+def _fd_check(f, x, g, rng, eps=1e-6):
+    d = rng.standard_normal(x.shape)
+    fd = (f(x + eps * d) - f(x - eps * d)) / (2 * eps)
+    an = float(np.sum(g * d))
+    return abs(fd - an) / max(abs(an), 1e-12)
+
+
+def test_network_gradients_match_central_differences():
+    rng = np.random.default_rng(1)
+    n = 16
+    params = convnet.init_params(rng, channels=3, layers=3, width=5, k=2)
+    x = rng.standard_normal(n)
+    gN = rng.standard_normal((n, 2))
+    N, acts = convnet.forward(params, x)
+    grads = convnet.backward(params, acts, gN)
+    for li in range(len(params)):
+        W, b = params[li]
+
+        def fW(Wp, li=li):
+            p = [(Wp if i == li else params[i][0], params[i][1]) for i in range(len(params))]
+            return float(np.sum(gN * convnet.forward(p, x)[0]))
+
+        def fb(bp, li=li):
+            p = [(params[i][0], bp if i == li else params[i][1]) for i in range(len(params))]
+            return float(np.sum(gN * convnet.forward(p, x)[0]))
+
+        assert _fd_check(fW, W, grads[li][0], rng) < 1e-7
+        assert _fd_check(fb, b, grads[li][1], rng) < 1e-7
+
+
+def test_capture_loss_invariances_and_gradient():
+    rng = np.random.default_rng(2)
+    n, k = 30, 4
+    V = np.linalg.qr(rng.standard_normal((n, k)))[0]
+    w = rng.uniform(0.2, 1.0, k)
+    # a basis containing span(V) captures everything: loss = -1
+    N = np.hstack([V @ rng.standard_normal((k, k)), rng.standard_normal((n, 2))])
+    assert abs(convnet.capture_loss(N, V, w)[0] + 1.0) < 1e-12
+    # a basis orthogonal to span(V) captures nothing
+    Q = np.linalg.qr(np.hstack([V, rng.standard_normal((n, 3))]))[0][:, k:]
+    assert abs(convnet.capture_loss(Q, V, w)[0]) < 1e-12
+    # invariant to a change of basis of span(N)
+    N = rng.standard_normal((n, 5))
+    R = rng.standard_normal((5, 5)) + 3 * np.eye(5)
+    assert abs(convnet.capture_loss(N, V, w)[0] - convnet.capture_loss(N @ R, V, w)[0]) < 1e-12
+    loss, g = convnet.capture_loss(N, V, w)
+    assert _fd_check(lambda Np: convnet.capture_loss(Np, V, w)[0], N, g, rng) < 1e-7

@@ -3,10 +3,11 @@
 Test infrastructure only: nothing in the product path imports this module.
 
 A 1-D periodic convolutional network maps a background state x (n,) to k basis vectors
-N (n, k) that are used as RIOT probes in place of Gaussian ones. Layers l = 1..L:
+N (n, k) that are used as RIOT probes in place of Gaussian ones. Input h_0 = x minus its
+mean, over its standard deviation (one channel). Layers l = 1..L:
   z_l[c, i] = b_l[c] + sum_{c', j} W_l[c, c', j] h_{l-1}[c', (i + j - r) mod n],
   h_l = relu(z_l) for l < L, h_L = z_L,
-with h_0 = x as one channel, width 2 r + 1. N[:, c] = h_L[c, :].
+width 2 r + 1. N[:, c] = h_L[c, :].
 
 Loss (subspace capture of the leading Hessian eigenvectors V (n, k) with weights w):
   loss(N) = - sum_i w_i v_i^T P v_i / sum_i w_i,   P = N (N^T N)^{-1} N^T,
@@ -43,9 +44,15 @@ def conv1d_backward(x: np.ndarray, W: np.ndarray, gz: np.ndarray):
     return gx, gW, gz.sum(axis=1)
 
 
+def standardize(x: np.ndarray) -> np.ndarray:
+    """The network's input: x minus its mean over the grid, divided by its standard deviation."""
+    x = np.asarray(x, dtype=np.float64)
+    return (x - x.mean()) / x.std()
+
+
 def forward(params, x: np.ndarray):
-    """Network output N (n, k) and the per-layer activations (for backward)."""
-    h = x[None, :].astype(np.float64)
+    """Network output N (n, k) for the standardized input, and the per-layer activations."""
+    h = standardize(x)[None, :]
     acts = [h]
     for li, (W, b) in enumerate(params):
         z = conv1d(h, W, b)

@@ -113,6 +113,11 @@ void riot_free(riot_handle *h);
 /* Human-readable name of a status code (static string). */
 const char *riot_status_str(riot_status s);
 
+/* Replace the observed values y (eq. 2) for the next assimilation cycle; locations, error
+ * variances and the prior stay. y [nobs] device, in the descriptor's order. The handle
+ * must be linearised again before the calls that need it (RIOT_E_STATE otherwise). */
+riot_status riot_set_obs(riot_handle *h, const double *y);
+
 /* Outer-loop linearisation at state x (Alg. 3: integrate and store the trajectory,
  * innovation; gradient of eq. 3 at dz = 0).
  *   x    [n]     device, state x_{k-1} to linearise about
@@ -149,6 +154,15 @@ riot_status riot_rsvd(riot_handle *h, int32_t k, int32_t p_os, int32_t q,
                       const double *Omega, uint64_t seed,
                       double *lambda, double *V, riot_rsvd_info *info);
 
+/* Projected residual of a sketch (the quality check of a probe basis, Section 2.2's view of
+ * RIOT as finding the dominant invariant subspace of A):
+ *   rho = ||A Q - Q (Q^T A Q)||_F / ||A Q||_F
+ *   Q  [n x m] device, orthonormal columns (e.g. the Ritz vectors V of riot_rsvd)
+ *   AQ [n x m] device, A Q (riot_hess_apply with add_identity = 0)
+ *   rho_host   host out (synchronises). 1 <= m <= min(m_max, n). */
+riot_status riot_proj_residual(riot_handle *h, int32_t m, const double *Q, const double *AQ,
+                               double *rho_host);
+
 /* Adaptive increment (eqs. 8-11 used in eq. 10; Alg. 3 update) from the k leading Ritz pairs:
  *   LRA: dz = -sum_i (1 + l_i)^{-1} v_i v_i^T g
  *   LRU: dz = -(I - sum_i l_i / (1 + l_i) v_i v_i^T) g
@@ -181,8 +195,8 @@ riot_status riot_posterior_cov(riot_handle *h, int32_t k, const double *lambda, 
 riot_status riot_cg(riot_handle *h, const double *grad, int32_t iters, double rtol,
                     double *dz, double *iterates, int32_t *used);
 
-/* Tangent-linear observation operator of the window (Section 2.1: "only TL and AD model
- * integrations are necessary"): Z = G X, i.e. column j holds H_t M_{0->t} X[:, j] at every
+/* Tangent-linear observation operator of the window (Section 2.1: the inner loop needs the
+ * TL and AD integrations only, never the full Jacobian): Z = G X, i.e. column j holds H_t M_{0->t} X[:, j] at every
  * observation, in the descriptor's observation order.
  *   X [n x m] device (state space, no L applied), Z [nobs x m] device out (ld nobs).
  * Requires riot_linearize first. 1 <= m <= m_max. */
@@ -276,6 +290,9 @@ riot_status riot_sketch_eig(riot_sketch *s, int32_t m, const double *Omega, cons
                             double *lambda, double *V, riot_rsvd_info *info);
 /* dz from the k leading Ritz pairs: LRA -sum (1+l)^{-1} v v^T g, LRU -(I - sum l/(1+l) v v^T) g,
  * adaptive = eq. 11 (no L applied: the caller maps dz to its own space). */
+/* riot_proj_residual on the sketch handle's workspace (any operator A). */
+riot_status riot_sketch_residual(riot_sketch *s, int32_t m, const double *Q, const double *AQ,
+                                 double *rho_host);
 riot_status riot_sketch_increment(riot_sketch *s, int32_t k, const double *lambda,
                                   const double *V, const double *grad, riot_update mode,
                                   double *dz, double *dofs_host, int32_t *mode_used);
@@ -384,6 +401,65 @@ riot_status riot_batch_profile(riot_batch *b, float *ms, double *busy_frac, int3
 /* The handle of problem j inside the batch (owned by the batch: do not riot_free it). Its
  * single-problem calls work on the same workspace, e.g. for checks. */
 riot_status riot_batch_problem(riot_batch *b, int32_t j, riot_handle **h);
+
+/* ------------------------------------------------------------------------------------
+ * Learned sketch proposal. Alg. 3 draws its probe block Omega at random; the sketch only
+ * has to span the dominant eigenvectors of A (Section 2.2), so a network trained on the
+ * eigenvectors of earlier cycles may propose most of the block. This network is a 1-D
+ * periodic convolution stack on the state's grid (FP32 weights and activations):
+ *   h_0 = (x - mean(x)) / std(x)                       (one channel; x must not be constant)
+ *   z_l[c, i] = b_l[c] + sum_{c', j} W_l[c, c', j] h_{l-1}[c', (i + j - r) mod n]
+ *   h_l = max(z_l, 0) for l < L, N[:, c] = z_L[c, :]   (width 2 r + 1, k output channels)
+ * Parameters: one flat FP32 array, per layer W_l [cout][cin][width] then b_l [cout]; layer
+ * 1 has cin = 1, the last cout = k, the others cout = channels.
+ * Training loss (eigenvalue-weighted subspace capture; a reading, the paper has no net):
+ *   loss = -sum_i w_i v_i^T P v_i / sum_i w_i,  P = N (N^T N)^{-1} N^T,
+ *   d loss / d N = -(2 / sum w) (I - P) V diag(w) V^T N (N^T N)^{-1},
+ * evaluated in FP64 (Gram matrix, Cholesky, triangular solves on the FP64 MFMA GEMMs).
+ * All data pointers are DEVICE pointers; a batch of states is [batch][n], network outputs
+ * [batch][k][n] (each sample an n x k column-major block), V [batch][k][n], w [batch][k].
+ * The network keeps the activations of its last forward call for the backward call.
+ * ---------------------------------------------------------------------------------- */
+typedef struct riot_net riot_net;
+
+typedef struct {
+    int32_t n;          /* grid points, multiple of 64 */
+    int32_t layers;     /* convolution layers L, 1..16 */
+    int32_t channels;   /* hidden channels, 1..64 */
+    int32_t k;          /* proposed basis vectors (output channels), 1..64, <= n */
+    int32_t width;      /* kernel width 2 r + 1, odd, <= 11 */
+    int32_t batch_max;  /* largest batch of states per call, >= 1 */
+} riot_net_desc;
+
+size_t riot_net_workspace_bytes(const riot_net_desc *desc);  /* 0: invalid descriptor */
+riot_status riot_net_init(const riot_net_desc *desc, void *workspace, size_t bytes,
+                          void *hip_stream, riot_net **out);
+void riot_net_free(riot_net *h);
+int64_t riot_net_param_count(const riot_net *h);
+/* Copy parameters and/or gradients in ([count] device each; either may be NULL), e.g. to
+ * start from given weights or to apply Adam to gradients reduced elsewhere. */
+riot_status riot_net_set_params(riot_net *h, const float *params, const float *grads);
+/* Copy the parameters and/or the last gradients out (either pointer may be NULL). */
+riot_status riot_net_get_params(riot_net *h, float *params, float *grads);
+/* N = net(x) for a batch of states x [batch][n] (FP64). N [batch][k][n] FP32 out or NULL;
+ * N64 FP64 out or NULL: sample s, column c at N64 + (s * k + c) * ld64 (ld64 >= n), so a
+ * single state's proposal can fill the first k columns of an n x m probe block. */
+riot_status riot_net_forward(riot_net *h, int32_t batch, const double *x, float *N,
+                             double *N64, int32_t ld64);
+/* Parameter gradients (summed over the batch) of sum(gN * N) at the last forward call's
+ * batch; gN [batch][k][n]. Overwrites the gradient buffer. */
+riot_status riot_net_backward(riot_net *h, int32_t batch, const float *gN);
+/* One Adam step (bias-corrected; step counts from 1, step 1 clears the moments). */
+riot_status riot_net_adam(riot_net *h, float lr, float beta1, float beta2, float eps,
+                          int32_t step);
+/* Capture loss of each sample and its gradient gN [batch][k][n] (FP32 out) for network
+ * outputs N, targets V (orthonormal columns) and weights w >= 0 (sum > 0). loss_host:
+ * [batch] host out or NULL (synchronises). N must have full column rank (else NaN). */
+riot_status riot_net_capture_loss(riot_net *h, int32_t batch, const float *N, const double *V,
+                                  const double *w, double *loss_host, float *gN);
+/* forward + capture loss + backward + Adam (beta1 0.9, beta2 0.999, eps 1e-8) on one batch. */
+riot_status riot_net_train_step(riot_net *h, int32_t batch, const double *x, const double *V,
+                                const double *w, float lr, int32_t step, double *loss_host);
 
 #ifdef __cplusplus
 }

@@ -88,13 +88,13 @@ def capture_loss(N: np.ndarray, V: np.ndarray, w: np.ndarray):
     return loss, -(2.0 / sw) * (X - PX)
 
 
-def init_params(rng, channels=64, layers=4, width=9, k=64):
-    """He-normal weights, zero biases; the last layer has k output channels."""
-    params = []
-    cin = 1
-    for li in range(layers):
-        cout = k if li == layers - 1 else channels
-        W = rng.standard_normal((cout, cin, width)) * np.sqrt(2.0 / (cin * width))
-        params.append((W, np.zeros(cout)))
-        cin = cout
-    return params
+def adam(p: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, t: int, lr: float,
+         beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam step (Kingma and Ba, 2015) at step t >= 1 with bias-corrected moments:
+    m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2, p <- p - lr m_hat / (sqrt(v_hat) + eps),
+    m_hat = m / (1 - b1^t), v_hat = v / (1 - b2^t). Returns (p, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** t)
+    vh = v / (1.0 - beta2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v

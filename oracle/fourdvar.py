@@ -217,6 +217,13 @@ def rsvd(apply_A, Omega: np.ndarray, q: int = 0) -> RSVD:
     return RSVD(lam, Q @ Z, Q, Y, K, k_asym)
 
 
+def proj_residual(Q: np.ndarray, AQ: np.ndarray) -> float:
+    """||A Q - Q Q^T A Q||_F / ||A Q||_F for orthonormal Q: zero exactly when span(Q) is an
+    invariant subspace of A (the quality measure of a sketch basis)."""
+    R = AQ - Q @ (Q.T @ AQ)
+    return float(np.linalg.norm(R) / np.linalg.norm(AQ))
+
+
 def choose_update(lam_k: float) -> str:
     """Adaptive rule of eq. 11: LRA when the last kept eigenvalue is >= 1, else LRU."""
     return "lra" if lam_k >= 1.0 else "lru"

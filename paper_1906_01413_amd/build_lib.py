@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["l96.hip", "linalg.hip", "eig.hip", "riot_api.hip", "tracer.hip"]
+SOURCES = ["l96.hip", "linalg.hip", "eig.hip", "riot_api.hip", "tracer.hip", "net.hip"]
 LIB = os.path.join(HERE, "libriot.so")
 
 FLAGS = [

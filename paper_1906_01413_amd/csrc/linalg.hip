@@ -553,6 +553,22 @@ __global__ void __launch_bounds__(1024) orth_err_kernel(int m, const double *__r
   if (threadIdx.x == 0) out[0] = sqrt(s);
 }
 
+// out[0] = ||R||_F / ||A||_F over count elements (one workgroup, fixed summation order).
+__global__ void __launch_bounds__(1024) fro_ratio_kernel(long long count,
+                                                         const double *__restrict__ R,
+                                                         const double *__restrict__ A,
+                                                         double *__restrict__ out) {
+  __shared__ double red[16];
+  double pr = 0.0, pa = 0.0;
+  for (long long idx = threadIdx.x; idx < count; idx += blockDim.x) {
+    pr += R[idx] * R[idx];
+    pa += A[idx] * A[idx];
+  }
+  const double sr = wg_sum(pr, red);
+  const double sa = wg_sum(pa, red);
+  if (threadIdx.x == 0) out[0] = sqrt(sr) / sqrt(sa);
+}
+
 // ---------------------------------------------------------------------------
 // Increment, covariance and utility kernels
 // ---------------------------------------------------------------------------
@@ -750,6 +766,12 @@ hipError_t launch_symmetrize(int m, double *K, double *asym, double *part, hipSt
 
 hipError_t launch_orth_err(int m, const double *G, double *out, hipStream_t st) {
   hipLaunchKernelGGL(orth_err_kernel, dim3(1), dim3(1024), 0, st, m, G, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fro_ratio(long long count, const double *R, const double *A, double *out,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(fro_ratio_kernel, dim3(1), dim3(1024), 0, st, count, R, A, out);
   return hipGetLastError();
 }
 

@@ -357,6 +357,20 @@ riot_status sketch_increment(const LaSpace &la, int n, int k, const double *lamb
   return RIOT_OK;
 }
 
+// Projected residual rho = ||A Q - Q Q^T A Q||_F / ||A Q||_F of an orthonormal block Q
+// (Q and AQ n x m, column-major): how far span(Q) is from an invariant subspace of A.
+riot_status proj_residual(const LaSpace &la, int n, int m, const double *Q, const double *AQ,
+                          double *rho_host) {
+  hipStream_t st = la.st;
+  RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, Q, n, AQ, n, 0.0, la.K, m, la.partial, kSplitK, st));
+  RIOT_HIP(hipMemcpyAsync(la.Q, AQ, (size_t)n * m * sizeof(double), hipMemcpyDeviceToDevice, st));
+  RIOT_HIP(gemm_f64(0, 0, n, m, m, -1.0, Q, n, la.K, m, 1.0, la.Q, n, la.partial, 1, st));
+  RIOT_HIP(launch_fro_ratio((long long)n * m, la.Q, AQ, la.scal + 6, st));
+  RIOT_HIP(hipMemcpyAsync(rho_host, la.scal + 6, sizeof(double), hipMemcpyDeviceToHost, st));
+  RIOT_HIP(hipStreamSynchronize(st));
+  return RIOT_OK;
+}
+
 riot_status hess_apply_impl(riot_handle *h, int m, const double *W, double *Y, int add_identity) {
   const int n = h->d.n;
   hipStream_t st = h->st;
@@ -480,6 +494,15 @@ const char *riot_status_str(riot_status s) {
   return "unknown riot_status";
 }
 
+riot_status riot_set_obs(riot_handle *h, const double *y) {
+  if (!h || (h->d.nobs > 0 && !y)) return RIOT_E_ARG;
+  if (h->d.nobs > 0)
+    RIOT_HIP(hipMemcpyAsync(h->y, y, (size_t)h->d.nobs * sizeof(double),
+                            hipMemcpyDeviceToDevice, h->st));
+  h->linearized = false;  // the stored innovation belongs to the old values
+  return RIOT_OK;
+}
+
 riot_status riot_linearize(riot_handle *h, const double *x, const double *v, double *d,
                            double *grad, double *J_host) {
   if (!h || !x || !grad || (h->d.nobs > 0 && !d)) return RIOT_E_ARG;
@@ -534,6 +557,13 @@ riot_status riot_rsvd(riot_handle *h, int32_t k, int32_t p_os, int32_t q, const 
     Om_eff = h->Q0;
   }
   return sketch_eig(la_of(h), n, m, h->Y, Om_eff, lambda, V, info);
+}
+
+riot_status riot_proj_residual(riot_handle *h, int32_t m, const double *Q, const double *AQ,
+                               double *rho_host) {
+  if (!h || !Q || !AQ || !rho_host || m < 1 || m > h->d.m_max || m > h->d.n) return RIOT_E_ARG;
+  if (Q == h->Q || AQ == h->Q) return RIOT_E_ARG;
+  return proj_residual(la_of(h), h->d.n, m, Q, AQ, rho_host);
 }
 
 riot_status riot_increment(riot_handle *h, int32_t k, const double *lambda, const double *V,
@@ -1421,6 +1451,13 @@ riot_status riot_sketch_eig(riot_sketch *s, int32_t m, const double *Omega, cons
   if (!s || !Omega || !Y || !lambda || !V || m < 1 || m > s->m_max) return RIOT_E_ARG;
   RIOT_HIP(launch_zero_ints(s->la.flags, 16, s->la.st));
   return sketch_eig(s->la, s->n, m, Y, Omega, lambda, V, info);
+}
+
+riot_status riot_sketch_residual(riot_sketch *s, int32_t m, const double *Q, const double *AQ,
+                                 double *rho_host) {
+  if (!s || !Q || !AQ || !rho_host || m < 1 || m > s->m_max) return RIOT_E_ARG;
+  if (Q == s->la.Q || AQ == s->la.Q) return RIOT_E_ARG;
+  return proj_residual(s->la, s->n, m, Q, AQ, rho_host);
 }
 
 riot_status riot_sketch_increment(riot_sketch *s, int32_t k, const double *lambda,

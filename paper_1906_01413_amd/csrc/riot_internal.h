@@ -266,6 +266,9 @@ hipError_t launch_trsm_rlt(int rows, int m, double *X, int ldx, const double *L,
 // part: 128 doubles of scratch.
 hipError_t launch_symmetrize(int m, double *K, double *asym, double *part, hipStream_t st);
 
+// out[0] = ||R||_F / ||A||_F over count contiguous doubles.
+hipError_t launch_fro_ratio(long long count, const double *R, const double *A, double *out,
+                            hipStream_t st);
 // ||Q^T Q - I||_F from the Gram matrix G = Q^T Q -> out[0].
 hipError_t launch_orth_err(int m, const double *G, double *out, hipStream_t st);
 

@@ -38,7 +38,10 @@ EXPORTS = ("riot_workspace_bytes", "riot_init", "riot_free", "riot_status_str",
            "riot_sketch_increment",
            "riot_tracer_workspace_bytes", "riot_tracer_init", "riot_tracer_free", "riot_tracer_forward",
            "riot_tracer_tangent", "riot_tracer_adjoint", "riot_tracer_apply_L", "riot_tracer_hess_apply",
-           "riot_tracer_gradient", "riot_exp_corr_sqrt")
+           "riot_tracer_gradient", "riot_exp_corr_sqrt", "riot_set_obs", "riot_proj_residual",
+           "riot_sketch_residual", "riot_net_workspace_bytes", "riot_net_init", "riot_net_free",
+           "riot_net_param_count", "riot_net_set_params", "riot_net_get_params", "riot_net_forward",
+           "riot_net_backward", "riot_net_adam", "riot_net_capture_loss", "riot_net_train_step")
 
 
 class RiotError(RuntimeError):
@@ -77,6 +80,10 @@ class _TracerDesc(ctypes.Structure):
         ("L1", ctypes.POINTER(ctypes.c_double)), ("sigma", ctypes.c_double),
         ("m_max", ctypes.c_int32),
     ]
+
+
+class _NetDesc(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in ("n", "layers", "channels", "k", "width", "batch_max")]
 
 
 class _RsvdInfo(ctypes.Structure):
@@ -151,6 +158,23 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "riot_exp_corr_sqrt": (i32, [i32, dbl, vp]),
         "riot_batch_profile": (i32, [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(dbl),
                                      ctypes.POINTER(i32)]),
+        "riot_set_obs": (i32, [vp, vp]),
+        "riot_proj_residual": (i32, [vp, i32, vp, vp, ctypes.POINTER(dbl)]),
+        "riot_sketch_residual": (i32, [vp, i32, vp, vp, ctypes.POINTER(dbl)]),
+        "riot_net_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(_NetDesc)]),
+        "riot_net_init": (i32, [ctypes.POINTER(_NetDesc), vp, ctypes.c_size_t, vp,
+                                ctypes.POINTER(vp)]),
+        "riot_net_free": (None, [vp]),
+        "riot_net_param_count": (ctypes.c_int64, [vp]),
+        "riot_net_set_params": (i32, [vp, vp, vp]),
+        "riot_net_get_params": (i32, [vp, vp, vp]),
+        "riot_net_forward": (i32, [vp, i32, vp, vp, vp, i32]),
+        "riot_net_backward": (i32, [vp, i32, vp]),
+        "riot_net_adam": (i32, [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, i32]),
+        "riot_net_capture_loss": (i32, [vp, i32, vp, vp, vp, ctypes.POINTER(dbl), vp]),
+        "riot_net_train_step": (i32, [vp, i32, vp, vp, vp, ctypes.c_float, i32,
+                                      ctypes.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -282,6 +306,20 @@ class Riot:
                "riot_hess_apply")
         return Y
 
+    def set_obs(self, y):
+        """New observed values (same locations); linearize again before the next products."""
+        y = colmajor(np.ascontiguousarray(y, dtype=np.float64) if not torch.is_tensor(y) else y,
+                     self.device)
+        assert y.numel() == self.nobs
+        _check(self.lib.riot_set_obs(self.h, _ptr(y)), "riot_set_obs")
+
+    def proj_residual(self, Q, AQ):
+        """||A Q - Q Q^T A Q||_F / ||A Q||_F for orthonormal Q and AQ = hess_apply(Q)."""
+        rho = ctypes.c_double()
+        _check(self.lib.riot_proj_residual(self.h, Q.shape[1], _ptr(Q), _ptr(AQ), ctypes.byref(rho)),
+               "riot_proj_residual")
+        return rho.value
+
     def rsvd(self, k, p_os, q=0, Omega=None, seed=0, want_info=True, lam=None, V=None):
         m = k + p_os
         Om = None if Omega is None else colmajor(Omega, self.device)
@@ -405,8 +443,9 @@ class Riot:
                "riot_ckpt_adjoint")
         return gX0
 
-    def philox_normal(self, n, m, seed, stream=0):
-        out = empty_colmajor(n, m, self.device)
+    def philox_normal(self, n, m, seed, stream=0, out=None):
+        out = empty_colmajor(n, m, self.device) if out is None else out
+        assert out.shape == (n, m)
         _check(self.lib.riot_philox_normal(self.h, n, m, ctypes.c_uint64(seed), ctypes.c_uint64(stream),
                                            _ptr(out)), "riot_philox_normal")
         return out
@@ -609,6 +648,143 @@ class Sketch:
                                               MODES[mode], _ptr(dz), ctypes.byref(dofs), ctypes.byref(mu)),
                "riot_sketch_increment")
         return dz, dofs.value, {LRA: "lra", LRU: "lru"}[mu.value]
+
+
+    def residual(self, Q, AQ):
+        """||A Q - Q Q^T A Q||_F / ||A Q||_F (riot_sketch_residual)."""
+        Qc, AQc = _cols(Q, self.n, self.device), _cols(AQ, self.n, self.device)
+        rho = ctypes.c_double()
+        _check(self.lib.riot_sketch_residual(self.h, Qc.shape[1], _ptr(Qc), _ptr(AQc),
+                                             ctypes.byref(rho)), "riot_sketch_residual")
+        return rho.value
+
+
+class ProposalNet:
+    """Learned sketch proposal: periodic 1-D conv net, its training and inference kernels
+    (C ABI riot_net_*). States x: (batch, n) float64; outputs N: (batch, k, n) float32."""
+
+    def __init__(self, n, k=64, channels=64, layers=4, width=9, batch_max=32, device="cuda"):
+        self.lib = load_library()
+        d = _NetDesc()
+        d.n, d.layers, d.channels, d.k, d.width, d.batch_max = (
+            int(n), int(layers), int(channels), int(k), int(width), int(batch_max))
+        self.n, self.k, self.channels, self.layers, self.width = d.n, d.k, d.channels, d.layers, d.width
+        self.batch_max, self.device = d.batch_max, torch.device(device)
+        nb = self.lib.riot_net_workspace_bytes(ctypes.byref(d))
+        if nb == 0:
+            raise RiotError(-1, "riot_net_workspace_bytes")
+        self.workspace, base = _aligned_workspace(nb, self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(self.lib.riot_net_init(ctypes.byref(d), ctypes.c_void_p(base), ctypes.c_size_t(nb),
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "riot_net_init")
+        self.h = h
+        self.nparams = int(self.lib.riot_net_param_count(self.h))
+        self.step = 0
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.lib.riot_net_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def layer_shapes(self):
+        """[(cout, cin, width)] per layer, in the flat parameter order."""
+        out, cin = [], 1
+        for li in range(self.layers):
+            cout = self.k if li == self.layers - 1 else self.channels
+            out.append((cout, cin, self.width))
+            cin = cout
+        return out
+
+    @staticmethod
+    def _f64(t):
+        assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+        return ctypes.c_void_p(t.data_ptr())
+
+    @staticmethod
+    def _f32(t):
+        assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _flat(self, t):
+        if t is None:
+            return None
+        t = torch.as_tensor(t, dtype=torch.float32).to(self.device).contiguous()
+        assert t.numel() == self.nparams
+        return t
+
+    def set_params(self, flat=None, grads=None):
+        """Parameters (a new start: Adam's step count restarts) and/or gradients."""
+        p, g = self._flat(flat), self._flat(grads)
+        _check(self.lib.riot_net_set_params(self.h, None if p is None else self._f32(p),
+                                            None if g is None else self._f32(g)),
+               "riot_net_set_params")
+        if p is not None:
+            self.step = 0
+
+    def params(self):
+        p = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+        g = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+        _check(self.lib.riot_net_get_params(self.h, self._f32(p), self._f32(g)), "riot_net_get_params")
+        return p, g
+
+    def _states(self, x):
+        x = torch.as_tensor(x, dtype=torch.float64).to(self.device)
+        x = x.reshape(-1, self.n).contiguous()
+        assert 1 <= x.shape[0] <= self.batch_max
+        return x
+
+    def forward(self, x):
+        x = self._states(x)
+        N = torch.empty((x.shape[0], self.k, self.n), dtype=torch.float32, device=self.device)
+        _check(self.lib.riot_net_forward(self.h, x.shape[0], self._f64(x), self._f32(N), None, 0),
+               "riot_net_forward")
+        return N
+
+    def propose(self, x, Omega):
+        """The network's k columns for one state x into Omega[:, :k] (FP64, column-major)."""
+        x = self._states(x)
+        assert x.shape[0] == 1 and Omega.stride(0) == 1 and Omega.shape[1] >= self.k
+        _check(self.lib.riot_net_forward(self.h, 1, self._f64(x), None, ctypes.c_void_p(Omega.data_ptr()),
+                                         Omega.stride(1)), "riot_net_forward")
+        return Omega
+
+    def backward(self, gN):
+        gN = gN.to(torch.float32).contiguous()
+        _check(self.lib.riot_net_backward(self.h, gN.shape[0], self._f32(gN)), "riot_net_backward")
+        return self.params()[1]
+
+    def capture_loss(self, N, V, w):
+        """(loss per sample (numpy), gN) for N (batch, k, n) f32, V (batch, k, n) f64, w (batch, k)."""
+        N = N.to(torch.float32).contiguous()
+        V = torch.as_tensor(V, dtype=torch.float64).to(self.device).contiguous()
+        w = torch.as_tensor(w, dtype=torch.float64).to(self.device).contiguous()
+        b = N.shape[0]
+        loss = (ctypes.c_double * b)()
+        gN = torch.empty_like(N)
+        _check(self.lib.riot_net_capture_loss(self.h, b, self._f32(N), self._f64(V), self._f64(w), loss,
+                                              self._f32(gN)), "riot_net_capture_loss")
+        return np.array(loss[:]), gN
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        _check(self.lib.riot_net_adam(self.h, lr, beta1, beta2, eps, self.step), "riot_net_adam")
+
+    def train_step(self, x, V, w, lr):
+        """One Adam step on a batch; returns the per-sample losses before the step."""
+        x = self._states(x)
+        V = torch.as_tensor(V, dtype=torch.float64).to(self.device).contiguous()
+        w = torch.as_tensor(w, dtype=torch.float64).to(self.device).contiguous()
+        b = x.shape[0]
+        loss = (ctypes.c_double * b)()
+        self.step += 1
+        _check(self.lib.riot_net_train_step(self.h, b, self._f64(x), self._f64(V), self._f64(w), lr, self.step, loss),
+               "riot_net_train_step")
+        return np.array(loss[:])
 
 
 class Tracer:

@@ -18,4 +18,7 @@ from .draws import (  # noqa: F401
     BATCH_N_VALUES,
     advdiff_draws,
     ADV_GRIDS,
+    CYCLED,
+    cycled_draws,
+    net_init,
 )

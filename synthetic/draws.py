@@ -10,6 +10,7 @@ consumer that asks for the same (seed, stream) pair gets the same numbers:
     stream 2  background-error draw (multiplied by B^{1/2} by the consumer)
     stream 3  probe blocks, one child stream per outer loop
     stream 4  per-problem structure of batched workloads
+    stream 5  tracer source-inversion structure; cycled-run observation noise
 """
 
 from __future__ import annotations
@@ -67,7 +68,8 @@ WORKLOADS = {
     # length-8 correlation, 256 + 16 probes.
     "l96_n4096": L96Workload("l96_n4096", n=4096, nsteps=100, var_stride=4,
                              step_stride=5, ell=8.0, k=256, p_os=16, q=0, outer=1),
-    # Cycled Lorenz-96 window, n=2048, 50 steps, every 2nd variable every 5 steps.
+    # Cycled Lorenz-96 window, n=2048, 50 steps, every 2nd variable every 5 steps
+    # (10240 observations), length-8 correlation; run for CYCLED["cycles"] windows.
     "l96_n2048": L96Workload("l96_n2048", n=2048, nsteps=50, var_stride=2,
                              step_stride=5, ell=8.0, k=112, p_os=16, q=0, outer=1),
 }
@@ -221,3 +223,43 @@ def advdiff_draws(name: str, seed: int) -> dict:
         "sigma": 0.5,
         "rel_err": 0.1,
     }
+
+
+# Cycled Lorenz-96 with a learned sketch proposal: the windows of "l96_n2048" chained for
+# 200 cycles (the analysis at a window's start, forecast 50 steps, is the next
+# background). Cycles 1..100 provide training data (leading Hessian eigenvectors),
+# cycles 101..200 compare the learned proposal (k_net network columns plus p_gauss
+# Gaussian probes) with Gaussian sketches of the same size and of m_ref probes. The
+# network: `layers` periodic conv1d layers of `width` taps and `channels` channels.
+CYCLED = dict(workload="l96_n2048", cycles=200, train_cycles=100, k_net=64, p_gauss=16,
+              m_ref=128, exact_every=10, layers=4, channels=64, width=9)
+
+
+def cycled_draws(seed: int, cycles: int) -> dict:
+    """Truth spin-up perturbation, first-background draw (unscaled) and per-cycle
+    observation noise (cycles x nobs) of the cycled n = 2048 run."""
+    w = WORKLOADS[CYCLED["workload"]]
+    ss = _streams(seed)
+    g0 = np.random.default_rng(ss[0])
+    g2 = np.random.default_rng(ss[2])
+    g5 = np.random.default_rng(ss[5])
+    obs_step, obs_idx = obs_locations(w.n, w.nsteps, w.var_stride, w.step_stride)
+    return {
+        "x0": w.forcing + w.spinup_sigma * g0.standard_normal(w.n),
+        "bg_noise": g2.standard_normal(w.n),
+        "obs_noise": w.obs_sigma * g5.standard_normal((cycles, obs_step.size)),
+        "obs_step": obs_step,
+        "obs_idx": obs_idx,
+        "rinv": np.full(obs_step.size, 1.0 / (w.obs_sigma ** 2)),
+    }
+
+
+def net_init(seed: int, shapes) -> list:
+    """He-normal weights (std sqrt(2 / (cin * width))) and zero biases for conv layers of
+    the given (cout, cin, width) shapes."""
+    g = np.random.default_rng(np.random.SeedSequence(seed).spawn(1)[0])
+    out = []
+    for cout, cin, width in shapes:
+        W = g.standard_normal((cout, cin, width)) * np.sqrt(2.0 / (cin * width))
+        out.append((W, np.zeros(cout)))
+    return out

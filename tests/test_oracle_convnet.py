@@ -3,6 +3,7 @@
 import numpy as np
 
 from oracle import convnet
+from synthetic import net_init
 
 
 def test_conv1d_is_a_circulant_matrix_product():
@@ -30,7 +31,7 @@ def _fd_check(f, x, g, rng, eps=1e-6):
 def test_network_gradients_match_central_differences():
     rng = np.random.default_rng(1)
     n = 16
-    params = convnet.init_params(rng, channels=3, layers=3, width=5, k=2)
+    params = net_init(7, [(3, 1, 5), (3, 3, 5), (2, 3, 5)])
     x = rng.standard_normal(n)
     gN = rng.standard_normal((n, 2))
     N, acts = convnet.forward(params, x)
@@ -67,3 +68,33 @@ def test_capture_loss_invariances_and_gradient():
     assert abs(convnet.capture_loss(N, V, w)[0] - convnet.capture_loss(N @ R, V, w)[0]) < 1e-12
     loss, g = convnet.capture_loss(N, V, w)
     assert _fd_check(lambda Np: convnet.capture_loss(Np, V, w)[0], N, g, rng) < 1e-7
+
+
+def test_network_is_shift_equivariant_and_scale_invariant():
+    """Periodic convolutions commute with cyclic shifts of the grid, and the standardized
+    input makes the output independent of an affine change a x + c (a > 0) of the state."""
+    params = net_init(8, [(4, 1, 5), (4, 4, 5), (3, 4, 5)])
+    x = np.random.default_rng(3).standard_normal(32)
+    N, _ = convnet.forward(params, x)
+    Ns, _ = convnet.forward(params, np.roll(x, 5))
+    assert np.max(np.abs(Ns - np.roll(N, 5, axis=0))) < 1e-12
+    Na, _ = convnet.forward(params, 3.0 * x + 7.0)
+    assert np.max(np.abs(Na - N)) < 1e-12
+
+
+def test_adam_first_step_and_fixed_point():
+    """Bias correction makes the first step lr g / (|g| + eps) (about lr sign(g)); a zero
+    gradient with zero moments leaves the parameters unchanged; on f = 1/2 ||p||^2 the
+    iteration approaches the minimiser."""
+    rng = np.random.default_rng(4)
+    p = rng.standard_normal(50)
+    g = rng.standard_normal(50)
+    z = np.zeros(50)
+    p1, m1, v1 = convnet.adam(p, g, z, z, 1, 0.01)
+    assert np.max(np.abs((p - p1) - 0.01 * g / (np.abs(g) + 1e-8))) < 1e-15
+    p2, _, _ = convnet.adam(p, z, z, z, 1, 0.01)
+    assert np.array_equal(p2, p)
+    q, m, v = p.copy(), z.copy(), z.copy()
+    for t in range(1, 3001):
+        q, m, v = convnet.adam(q, q, m, v, t, 0.01)
+    assert np.max(np.abs(q)) < 1e-2 * np.max(np.abs(p))

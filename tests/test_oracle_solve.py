@@ -165,3 +165,22 @@ def test_philox_normals_moments():
     z = philox.normal_block(200, 50, seed=1234, stream=3)
     assert z.shape == (200, 50)
     assert abs(z.mean()) < 0.03 and abs(z.std() - 1.0) < 0.03
+
+
+def test_proj_residual_closed_form():
+    """A = diag-like symmetric with eigenpairs (l1, v1), (l2, v2); Q = cos t v1 + sin t v2:
+    A Q - Q Q^T A Q has norm |l1 - l2| |sin t cos t| and ||A Q||^2 = l1^2 cos^2 + l2^2 sin^2.
+    An invariant subspace gives zero."""
+    rng = np.random.default_rng(5)
+    n = 12
+    U = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    lam = np.linspace(9.0, 0.5, n)
+    A = (U * lam) @ U.T
+    t = 0.37
+    q = np.cos(t) * U[:, 0] + np.sin(t) * U[:, 1]
+    Q = q[:, None]
+    want = abs(lam[0] - lam[1]) * abs(np.sin(t) * np.cos(t)) / np.sqrt(
+        lam[0] ** 2 * np.cos(t) ** 2 + lam[1] ** 2 * np.sin(t) ** 2)
+    assert abs(fourdvar.proj_residual(Q, A @ Q) - want) < 1e-14
+    V = U[:, [2, 5, 7]]
+    assert fourdvar.proj_residual(V, A @ V) < 1e-14

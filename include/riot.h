@@ -409,9 +409,12 @@ riot_status riot_batch_problem(riot_batch *b, int32_t j, riot_handle **h);
  * periodic convolution stack on the state's grid (FP32 weights and activations):
  *   h_0 = (x - mean(x)) / std(x)                       (one channel; x must not be constant)
  *   z_l[c, i] = b_l[c] + sum_{c', j} W_l[c, c', j] h_{l-1}[c', (i + j - r) mod n]
- *   h_l = max(z_l, 0) for l < L, N[:, c] = z_L[c, :]   (width 2 r + 1, k output channels)
+ *   h_l = max(z_l, 0) for l < L                         (width 2 r + 1)
+ *   N[i, c S + q] = z_L[c, i] if i lies in segment q, else 0   (localized output head)
+ * An equivariant network alone gives fields over the whole grid; the head lets span(N)
+ * hold structures at different places independently (S segments of n / S points).
  * Parameters: one flat FP32 array, per layer W_l [cout][cin][width] then b_l [cout]; layer
- * 1 has cin = 1, the last cout = k, the others cout = channels.
+ * 1 has cin = 1, the last cout = k / S, the others cout = channels.
  * Training loss (eigenvalue-weighted subspace capture; a reading, the paper has no net):
  *   loss = -sum_i w_i v_i^T P v_i / sum_i w_i,  P = N (N^T N)^{-1} N^T,
  *   d loss / d N = -(2 / sum w) (I - P) V diag(w) V^T N (N^T N)^{-1},
@@ -429,6 +432,9 @@ typedef struct {
     int32_t k;          /* proposed basis vectors (output channels), 1..64, <= n */
     int32_t width;      /* kernel width 2 r + 1, odd, <= 11 */
     int32_t batch_max;  /* largest batch of states per call, >= 1 */
+    int32_t segments;   /* S >= 1 (divides n and k): the last layer has k / S channels and
+                           column c S + q of N is channel c on the q-th block of n / S
+                           consecutive grid points, zero elsewhere (S = 1: N = z_L^T) */
 } riot_net_desc;
 
 size_t riot_net_workspace_bytes(const riot_net_desc *desc);  /* 0: invalid descriptor */

@@ -7,7 +7,9 @@ N (n, k) that are used as RIOT probes in place of Gaussian ones. Input h_0 = x m
 mean, over its standard deviation (one channel). Layers l = 1..L:
   z_l[c, i] = b_l[c] + sum_{c', j} W_l[c, c', j] h_{l-1}[c', (i + j - r) mod n],
   h_l = relu(z_l) for l < L, h_L = z_L,
-width 2 r + 1. N[:, c] = h_L[c, :].
+width 2 r + 1. Output head with S segments (S = 1: N[:, c] = h_L[c, :]): column c S + q of
+N is channel c of h_L on the q-th block of n / S consecutive grid points and zero elsewhere,
+so that span(N) can hold structures at different places independently.
 
 Loss (subspace capture of the leading Hessian eigenvectors V (n, k) with weights w):
   loss(N) = - sum_i w_i v_i^T P v_i / sum_i w_i,   P = N (N^T N)^{-1} N^T,
@@ -50,7 +52,20 @@ def standardize(x: np.ndarray) -> np.ndarray:
     return (x - x.mean()) / x.std()
 
 
-def forward(params, x: np.ndarray):
+def localize(z: np.ndarray, segments: int) -> np.ndarray:
+    """Output head: N[i, c S + q] = z[c, i] for grid points i in segment q (the q-th block
+    of n / S consecutive points), zero elsewhere. S = 1 gives N = z^T."""
+    kch, n = z.shape
+    seg = np.arange(n) // (n // segments)
+    N = np.zeros((n, kch * segments))
+    for c in range(kch):
+        for q in range(segments):
+            on = seg == q
+            N[on, c * segments + q] = z[c, on]
+    return N
+
+
+def forward(params, x: np.ndarray, segments: int = 1):
     """Network output N (n, k) for the standardized input, and the per-layer activations."""
     h = standardize(x)[None, :]
     acts = [h]
@@ -58,12 +73,19 @@ def forward(params, x: np.ndarray):
         z = conv1d(h, W, b)
         h = np.maximum(z, 0.0) if li < len(params) - 1 else z
         acts.append(h)
-    return h.T.copy(), acts
+    return localize(h, segments), acts
 
 
-def backward(params, acts, gN: np.ndarray):
+def backward(params, acts, gN: np.ndarray, segments: int = 1):
     """Parameter gradients [(gW, gb)] of sum(gN * N)."""
-    g = gN.T.copy()
+    n = gN.shape[0]
+    seg = np.arange(n) // (n // segments)
+    kch = gN.shape[1] // segments
+    g = np.zeros((kch, n))
+    for c in range(kch):   # transpose of localize
+        for q in range(segments):
+            on = seg == q
+            g[c, on] = gN[on, c * segments + q]
     grads = [None] * len(params)
     for li in range(len(params) - 1, -1, -1):
         W, b = params[li]

@@ -93,6 +93,30 @@ __global__ void __launch_bounds__(256)
   for (int q = 0; q < 4; ++q) zo[q] = relu ? fmaxf(acc[q], 0.f) : acc[q];
 }
 
+// Localized output head: N[s][c S + q][i] = z[s][c][i] for grid points i of segment q
+// (n / S consecutive points), 0 elsewhere; z has k / S channels.
+__global__ void segment_out_kernel(int n, int kch, int S, long long total,
+                                   const float *__restrict__ z, float *__restrict__ N) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int k = kch * S;
+  const int i = (int)(e % n), col = (int)((e / n) % k);
+  const long long s = e / ((long long)n * k);
+  const int c = col / S, q = col - c * S;
+  N[e] = (i / (n / S) == q) ? z[(s * kch + c) * n + i] : 0.f;
+}
+
+// Its transpose: gz[s][c][i] = gN[s][c S + (segment of i)][i].
+__global__ void segment_grad_kernel(int n, int kch, int S, long long total,
+                                    const float *__restrict__ gN, float *__restrict__ gz) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int i = (int)(e % n), c = (int)((e / n) % kch);
+  const long long s = e / ((long long)n * kch);
+  const int q = i / (n / S);
+  gz[e] = gN[(s * kch * S + (long long)c * S + q) * n + i];
+}
+
 // Wt[ci][co][j'] = W[co][ci][width - 1 - j']: the backward-data pass is a forward
 // convolution of the output gradient with these weights.
 __global__ void flip_transpose_kernel(int cin, int cout, int width, const float *__restrict__ W,
@@ -110,35 +134,71 @@ __global__ void relu_mask_kernel(long long count, const float *__restrict__ act,
   if (i < count && !(act[i] > 0.f)) g[i] = 0.f;
 }
 
-// gW[co][ci][j] = sum_s sum_i g[s][co][i] h[s][ci][(i + j - r) mod n], gb[co] = sum g;
-// one workgroup per output channel, one thread per (ci, j), FP64 sums in a fixed order.
-__global__ void conv_bwd_weight_kernel(int n, int cin, int cout, int width, int batch,
-                                       const float *__restrict__ g, const float *__restrict__ h,
-                                       float *__restrict__ gW, float *__restrict__ gb) {
-  const int co = blockIdx.x, r = width / 2;
-  const int t = threadIdx.x;
-  if (t < cin * width) {
-    const int ci = t / width, j = t - ci * width;
-    double acc = 0.0;
-    for (int s = 0; s < batch; ++s) {
-      const float *gr = g + ((size_t)s * cout + co) * n;
-      const float *hr = h + ((size_t)s * cin + ci) * n;
-      for (int i = 0; i < n; ++i) {
-        int k = i + j - r;
-        k = k < 0 ? k + n : (k >= n ? k - n : k);
-        acc += (double)gr[i] * (double)hr[k];
-      }
-    }
-    gW[((size_t)co * cin + ci) * width + j] = (float)acc;
+// Weight gradient gW[co][ci][j] = sum_s sum_i g[s][co][i] h[s][ci][(i + j - r) mod n] and
+// bias gradient gb[co] = sum_s sum_i g[s][co][i], in two passes with a fixed summation
+// order. Pass 1: a workgroup takes one chunk of CP grid points of one sample, 16 output
+// and 16 input channels; g rows and h rows (with the halo) are staged in LDS, thread
+// (co, ci) slides a W-wide register window along the chunk and keeps W FP32 sums.
+// Pass 2 adds the chunks' partial sums in FP64, chunk by chunk.
+template <int W>
+__global__ void __launch_bounds__(256)
+    conv_bwd_weight_part_kernel(int n, int cin, int cout, int CP, int chunks_per_sample,
+                                const float *__restrict__ g, const float *__restrict__ h,
+                                float *__restrict__ part_w, float *__restrict__ part_b) {
+  extern __shared__ float sh[];
+  constexpr int r = W / 2;
+  const int span = CP + W - 1, hld = span + 1;  // odd row stride: no LDS bank conflicts
+  float *Gs = sh;                              // [16][CP]
+  float *Hs = sh + 16 * CP;                    // [16][hld]
+  const int chunk = blockIdx.x, s = chunk / chunks_per_sample;
+  const int i0 = (chunk - s * chunks_per_sample) * CP;
+  const int ci0 = blockIdx.y * 16, co0 = blockIdx.z * 16;
+  for (int e = threadIdx.x; e < 16 * CP; e += blockDim.x) {
+    const int cl = e / CP, p = e - cl * CP;
+    Gs[e] = (co0 + cl < cout) ? g[((size_t)s * cout + co0 + cl) * n + i0 + p] : 0.f;
   }
-  if (t == cin * width) {  // the launch has at least cin * width + 1 threads
-    double acc = 0.0;
-    for (int s = 0; s < batch; ++s) {
-      const float *gr = g + ((size_t)s * cout + co) * n;
-      for (int i = 0; i < n; ++i) acc += gr[i];
-    }
-    gb[co] = (float)acc;
+  for (int e = threadIdx.x; e < 16 * span; e += blockDim.x) {
+    const int cl = e / span, p = e - cl * span;
+    int gi = i0 + p - r;
+    gi = gi < 0 ? gi + n : (gi >= n ? gi - n : gi);
+    Hs[cl * hld + p] = (ci0 + cl < cin) ? h[((size_t)s * cin + ci0 + cl) * n + gi] : 0.f;
   }
+  __syncthreads();
+  const int col = threadIdx.x / 16, cil = threadIdx.x % 16;
+  const float *gr = Gs + col * CP;
+  const float *hr = Hs + cil * hld;
+  float acc[W], win[W];
+  float accb = 0.f;
+#pragma unroll
+  for (int q = 0; q < W; ++q) acc[q] = 0.f;
+#pragma unroll
+  for (int q = 0; q < W - 1; ++q) win[q + 1] = hr[q];
+  for (int p = 0; p < CP; ++p) {
+#pragma unroll
+    for (int q = 0; q < W - 1; ++q) win[q] = win[q + 1];
+    win[W - 1] = hr[p + W - 1];
+    const float gp = gr[p];
+    accb += gp;
+#pragma unroll
+    for (int q = 0; q < W; ++q) acc[q] = fmaf(gp, win[q], acc[q]);
+  }
+  const int co = co0 + col, ci = ci0 + cil;
+  if (co < cout && ci < cin) {
+    float *o = part_w + ((size_t)chunk * cout + co) * cin * W + (size_t)ci * W;
+#pragma unroll
+    for (int q = 0; q < W; ++q) o[q] = acc[q];
+  }
+  if (blockIdx.y == 0 && cil == 0 && co < cout) part_b[(size_t)chunk * cout + co] = accb;
+}
+
+// out[e] = sum over chunks c = 0, 1, ... of part[c * count + e] (FP64, in chunk order).
+__global__ void chunk_sum_kernel(long long count, int chunks, const float *__restrict__ part,
+                                 float *__restrict__ out) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  double acc = 0.0;
+  for (int c = 0; c < chunks; ++c) acc += (double)part[(size_t)c * count + e];
+  out[e] = (float)acc;
 }
 
 __global__ void adam_kernel(long long count, float *__restrict__ p, const float *__restrict__ g,
@@ -186,11 +246,10 @@ __global__ void scale_rows_kernel(int k, int batch, const double *__restrict__ w
   WA[i] = w[(size_t)s * k + row] * A[i];
 }
 
-// gN[s] = -(2 / sum w) (X - PX) as FP32; loss[s] = -(1 / sum w) sum_i w_i sum_j C_ij A_ij
-__global__ void capture_finish_kernel(int n, int k, int batch, const double *__restrict__ w,
-                                      const double *__restrict__ X, const double *__restrict__ PX,
-                                      const double *__restrict__ C, const double *__restrict__ A,
-                                      float *__restrict__ gN, double *__restrict__ loss) {
+// gN[s] = -(2 / sum w) (X - PX) as FP32
+__global__ void capture_grad_kernel(int n, int k, const double *__restrict__ w,
+                                    const double *__restrict__ X, const double *__restrict__ PX,
+                                    float *__restrict__ gN) {
   const int s = blockIdx.y;
   double sw = 0.0;
   for (int i = 0; i < k; ++i) sw += w[(size_t)s * k + i];
@@ -198,15 +257,29 @@ __global__ void capture_finish_kernel(int n, int k, int batch, const double *__r
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nk;
        e += (size_t)gridDim.x * blockDim.x)
     gN[s * nk + e] = (float)(-(2.0 / sw) * (X[s * nk + e] - PX[s * nk + e]));
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const size_t kk = (size_t)k * k;
-    double acc = 0.0;
-    for (int i = 0; i < k; ++i) {
-      double row = 0.0;
-      for (int j = 0; j < k; ++j) row += C[s * kk + (size_t)j * k + i] * A[s * kk + (size_t)j * k + i];
-      acc += w[(size_t)s * k + i] * row;
-    }
-    loss[s] = -acc / sw;
+}
+
+// loss[s] = -(1 / sum w) sum_i w_i sum_j C_ij A_ij (C, A column-major k x k per sample);
+// one workgroup per sample, fixed-order tree reduction.
+__global__ void __launch_bounds__(256)
+    capture_value_kernel(int k, const double *__restrict__ w, const double *__restrict__ C,
+                         const double *__restrict__ A, double *__restrict__ loss) {
+  __shared__ double red[256];
+  const int s = blockIdx.x;
+  const size_t kk = (size_t)k * k;
+  double acc = 0.0;
+  for (size_t e = threadIdx.x; e < kk; e += blockDim.x)
+    acc += w[(size_t)s * k + e % k] * C[s * kk + e] * A[s * kk + e];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double sw = 0.0;
+    for (int i = 0; i < k; ++i) sw += w[(size_t)s * k + i];
+    loss[s] = -red[0] / sw;
   }
 }
 
@@ -225,6 +298,8 @@ struct riot_net {
   float *x0 = nullptr;               // standardized inputs [batch][n]
   std::vector<float *> acts;         // per layer outputs [batch][cout][n]
   float *g0 = nullptr, *g1 = nullptr, *Wt = nullptr, *gN = nullptr;
+  float *Nout = nullptr;             // network output after the head [batch][k][n]
+  float *wpart = nullptr;            // per-chunk partial weight and bias gradients
   // loss workspace (FP64)
   double *Nd = nullptr, *G = nullptr, *Lc = nullptr, *Z = nullptr, *Gi = nullptr, *A = nullptr,
          *WA = nullptr, *C = nullptr, *Y1 = nullptr, *Y2 = nullptr, *MN = nullptr, *X = nullptr,
@@ -237,6 +312,9 @@ struct riot_net {
 namespace {
 
 size_t n256(size_t b) { return (b + 255) / 256 * 256; }
+
+// grid points per chunk of the weight-gradient pass (divides n)
+int chunk_points(int n) { return n % 256 == 0 ? 256 : (n % 128 == 0 ? 128 : 64); }
 
 struct NCarve {
   char *base;
@@ -254,7 +332,9 @@ struct NCarve {
 bool net_desc_ok(const riot_net_desc *d) {
   return d && d->n >= 64 && d->n % 64 == 0 && d->layers >= 1 && d->layers <= 16 &&
          d->channels >= 1 && d->channels <= 64 && d->k >= 1 && d->k <= 64 && d->k <= d->n &&
-         d->width >= 1 && d->width % 2 == 1 && d->width <= riot::kMaxWidth && d->batch_max >= 1;
+         d->width >= 1 && d->width % 2 == 1 && d->width <= riot::kMaxWidth &&
+         d->batch_max >= 1 && d->segments >= 1 && d->n % d->segments == 0 &&
+         d->k % d->segments == 0;
 }
 
 size_t net_carve(riot_net &h, void *base) {
@@ -265,7 +345,7 @@ size_t net_carve(riot_net &h, void *base) {
   int ci = 1;
   int maxc = 1;
   for (int l = 0; l < d.layers; ++l) {
-    const int co = (l == d.layers - 1) ? d.k : d.channels;
+    const int co = (l == d.layers - 1) ? d.k / d.segments : d.channels;
     h.cin.push_back(ci), h.cout.push_back(co);
     h.woff.push_back(np);
     np += (long long)co * ci * d.width;
@@ -287,6 +367,14 @@ size_t net_carve(riot_net &h, void *base) {
   h.g1 = c.take<float>(B * maxc * n);
   h.Wt = c.take<float>((size_t)maxc * maxc * d.width);
   h.gN = c.take<float>(B * k * n);
+  h.Nout = c.take<float>(B * k * n);
+  {
+    const size_t chunks = B * (n / chunk_points((int)n));
+    size_t mx = 0;
+    for (int l = 0; l < d.layers; ++l)
+      mx = std::max(mx, (size_t)h.cout[l] * h.cin[l] * d.width + h.cout[l]);
+    h.wpart = c.take<float>(chunks * mx);
+  }
   h.Nd = c.take<double>(B * n * k);
   h.G = c.take<double>(B * kk);
   h.Lc = c.take<double>(B * kk);
@@ -319,6 +407,40 @@ riot_status conv_forward(riot_net *h, int batch, const float *in, int cin, int c
                      sizeof(float);
   hipLaunchKernelGGL(riot::conv_fwd_kernel, dim3(n / riot::kCX, (cout + riot::kCC - 1) / riot::kCC, batch),
                      dim3(256), lds, h->st, n, cin, cout, width, in, W, b, out, relu ? 1 : 0);
+  NET_HIP(hipGetLastError());
+  return RIOT_OK;
+}
+
+template <int W>
+void launch_wgrad_part(dim3 grid, size_t lds, hipStream_t st, int n, int cin, int cout, int CP,
+                       int cps, const float *g, const float *hin, float *pw, float *pb) {
+  hipLaunchKernelGGL(riot::conv_bwd_weight_part_kernel<W>, grid, dim3(256), lds, st, n, cin, cout,
+                     CP, cps, g, hin, pw, pb);
+}
+
+riot_status weight_grad(riot_net *h, int batch, int cin, int cout, const float *g,
+                        const float *hin, float *gW, float *gb) {
+  const int n = h->d.n, W = h->d.width, CP = chunk_points(n), cps = n / CP;
+  const int chunks = batch * cps;
+  const dim3 grid(chunks, (cin + 15) / 16, (cout + 15) / 16);
+  const size_t lds = (16 * (size_t)CP + 16 * (size_t)(CP + W)) * sizeof(float);
+  float *pw = h->wpart, *pb = h->wpart + (size_t)chunks * cout * cin * W;
+  switch (W) {
+    case 1: launch_wgrad_part<1>(grid, lds, h->st, n, cin, cout, CP, cps, g, hin, pw, pb); break;
+    case 3: launch_wgrad_part<3>(grid, lds, h->st, n, cin, cout, CP, cps, g, hin, pw, pb); break;
+    case 5: launch_wgrad_part<5>(grid, lds, h->st, n, cin, cout, CP, cps, g, hin, pw, pb); break;
+    case 7: launch_wgrad_part<7>(grid, lds, h->st, n, cin, cout, CP, cps, g, hin, pw, pb); break;
+    case 9: launch_wgrad_part<9>(grid, lds, h->st, n, cin, cout, CP, cps, g, hin, pw, pb); break;
+    case 11: launch_wgrad_part<11>(grid, lds, h->st, n, cin, cout, CP, cps, g, hin, pw, pb); break;
+    default: return RIOT_E_ARG;
+  }
+  NET_HIP(hipGetLastError());
+  const long long cw = (long long)cout * cin * W;
+  hipLaunchKernelGGL(riot::chunk_sum_kernel, dim3(riot::nblocks(cw)), dim3(256), 0, h->st, cw,
+                     chunks, pw, gW);
+  NET_HIP(hipGetLastError());
+  hipLaunchKernelGGL(riot::chunk_sum_kernel, dim3(riot::nblocks(cout)), dim3(256), 0, h->st,
+                     (long long)cout, chunks, pb, gb);
   NET_HIP(hipGetLastError());
   return RIOT_OK;
 }
@@ -413,10 +535,12 @@ riot_status riot_net_forward(riot_net *h, int32_t batch, const double *x, float 
     if (rs != RIOT_OK) return rs;
     in = out;
   }
-  const float *res = h->acts[h->d.layers - 1];
-  if (N)
-    NET_HIP(hipMemcpyAsync(N, res, (size_t)batch * k * n * sizeof(float), hipMemcpyDeviceToDevice,
-                           h->st));
+  const int S = h->d.segments;
+  const long long tot = (long long)batch * k * n;
+  float *res = N ? N : h->Nout;
+  hipLaunchKernelGGL(riot::segment_out_kernel, dim3(riot::nblocks(tot)), dim3(256), 0, h->st, n,
+                     k / S, S, tot, h->acts[h->d.layers - 1], res);
+  NET_HIP(hipGetLastError());
   if (N64) {
     hipLaunchKernelGGL(riot::widen_kernel, dim3(riot::nblocks((long long)batch * k * n)), dim3(256),
                        0, h->st, n, (long long)batch * k, res, N64, ld64);
@@ -428,8 +552,11 @@ riot_status riot_net_forward(riot_net *h, int32_t batch, const double *x, float 
 riot_status riot_net_backward(riot_net *h, int32_t batch, const float *gN) {
   if (!h || !gN || batch < 1 || batch > h->d.batch_max) return RIOT_E_ARG;
   const int n = h->d.n, width = h->d.width, L = h->d.layers;
-  NET_HIP(hipMemcpyAsync(h->g0, gN, (size_t)batch * h->d.k * n * sizeof(float),
-                         hipMemcpyDeviceToDevice, h->st));
+  const int S = h->d.segments, kch = h->d.k / S;
+  const long long tot = (long long)batch * kch * n;
+  hipLaunchKernelGGL(riot::segment_grad_kernel, dim3(riot::nblocks(tot)), dim3(256), 0, h->st, n,
+                     kch, S, tot, gN, h->g0);
+  NET_HIP(hipGetLastError());
   float *g = h->g0, *gnext = h->g1;
   for (int l = L - 1; l >= 0; --l) {
     const int ci = h->cin[l], co = h->cout[l];
@@ -439,11 +566,11 @@ riot_status riot_net_backward(riot_net *h, int32_t batch, const float *gN) {
       NET_HIP(hipGetLastError());
     }
     const float *hin = l == 0 ? h->x0 : h->acts[l - 1];
-    const int threads = std::max(64, (ci * width + 1 + 63) / 64 * 64);
-    hipLaunchKernelGGL(riot::conv_bwd_weight_kernel, dim3(co), dim3(std::min(threads, 1024)), 0,
-                       h->st, n, ci, co, width, batch, g, hin, h->grads + h->woff[l],
-                       h->grads + h->boff[l]);
-    NET_HIP(hipGetLastError());
+    {
+      riot_status rs = weight_grad(h, batch, ci, co, g, hin, h->grads + h->woff[l],
+                                   h->grads + h->boff[l]);
+      if (rs != RIOT_OK) return rs;
+    }
     if (l > 0) {
       hipLaunchKernelGGL(riot::flip_transpose_kernel, dim3(riot::nblocks((long long)ci * co * width)),
                          dim3(256), 0, h->st, ci, co, width, h->params + h->woff[l], h->Wt);
@@ -507,8 +634,11 @@ riot_status riot_net_capture_loss(riot_net *h, int32_t batch, const float *N, co
                                  batch, st));
   NET_HIP(riot::gemm_f64_strided(0, 0, k, k, k, 1.0, h->A, k, kk, h->Gi, k, kk, 0.0, h->C, k, kk,
                                  batch, st));
-  hipLaunchKernelGGL(riot::capture_finish_kernel, dim3(64, batch), dim3(256), 0, st, n, k, batch,
-                     w, h->X, h->PX, h->C, h->A, gN, h->loss);
+  hipLaunchKernelGGL(riot::capture_grad_kernel, dim3(64, batch), dim3(256), 0, st, n, k, w, h->X,
+                     h->PX, gN);
+  NET_HIP(hipGetLastError());
+  hipLaunchKernelGGL(riot::capture_value_kernel, dim3(batch), dim3(256), 0, st, k, w, h->C, h->A,
+                     h->loss);
   NET_HIP(hipGetLastError());
   if (loss_host) {
     NET_HIP(hipMemcpyAsync(loss_host, h->loss, batch * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -522,8 +652,7 @@ riot_status riot_net_train_step(riot_net *h, int32_t batch, const double *x, con
   if (!h || !x || !V || !w || batch < 1 || batch > h->d.batch_max || step < 1) return RIOT_E_ARG;
   riot_status rs = riot_net_forward(h, batch, x, nullptr, nullptr, 0);
   if (rs != RIOT_OK) return rs;
-  const float *N = h->acts[h->d.layers - 1];
-  rs = riot_net_capture_loss(h, batch, N, V, w, loss_host, h->gN);
+  rs = riot_net_capture_loss(h, batch, h->Nout, V, w, loss_host, h->gN);
   if (rs != RIOT_OK) return rs;
   rs = riot_net_backward(h, batch, h->gN);
   if (rs != RIOT_OK) return rs;

@@ -112,20 +112,31 @@ def collect(exp: CycledL96, cycles: int, k_net: int, m_ref: int, seed: int):
     return X, V, lam, np.asarray(rho_ref)
 
 
-def train(net: ProposalNet, X, V, lam, steps: int, batch: int, lr: float, seed: int):
+def train(net: ProposalNet, X, V, lam, steps: int, batch: int, lr: float, seed: int,
+          shift_step: int = 0):
     """Adam on the eigenvalue-weighted capture loss over the collected cycles; returns the
-    mean batch loss per step."""
+    mean batch loss per step. shift_step > 0: each sample is rotated by a random multiple
+    of shift_step grid points (state and eigenvectors together), an exact symmetry of the
+    problem when the model is translation invariant and the observation network repeats
+    with that period."""
     rng = np.random.default_rng(seed)
-    ncyc = X.shape[0]
+    ncyc, n = X.shape
     losses = []
     order = rng.permutation(ncyc)
     pos = 0
+    ar = torch.arange(n, device=X.device)
     for _ in range(steps):
         if pos + batch > ncyc:
             order, pos = rng.permutation(ncyc), 0
         idx = torch.as_tensor(order[pos: pos + batch], device=X.device)
         pos += batch
-        losses.append(float(np.mean(net.train_step(X[idx], V[idx], lam[idx], lr))))
+        xb, Vb, wb = X[idx], V[idx], lam[idx]
+        if shift_step:
+            s = torch.as_tensor(rng.integers(0, n // shift_step, batch) * shift_step, device=X.device)
+            src = (ar[None, :] - s[:, None]) % n          # rolled[b, i] = orig[b, i - s_b]
+            xb = torch.gather(xb, 1, src)
+            Vb = torch.gather(Vb, 2, src[:, None, :].expand_as(Vb))
+        losses.append(float(np.mean(net.train_step(xb, Vb, wb, lr))))
     return np.asarray(losses)
 
 
@@ -172,6 +183,11 @@ def evaluate(exp: CycledL96, net: ProposalNet, cycles: int, k_net: int, p_gauss:
                                want_info=False)
             for key, (lm, Vm, _) in res.items():
                 st.capture[key] = weighted_capture(Vm, Vq[:, :k_net], lq[:k_net])
+            # the network's own columns, before the Hessian acts on them
+            Qn = torch.as_tensor(np.linalg.qr(Om[:, :k_net].cpu().numpy())[0])
+            st.capture["net_columns"] = weighted_capture(Qn, Vq[:, :k_net], lq[:k_net])
+            st.capture["net_columns_unweighted"] = weighted_capture(
+                Qn, Vq[:, :k_net], torch.ones(k_net, dtype=torch.float64))
         exp.advance(incs["gauss_ref"] if st.fallback else incs["learned"])
         out.append(st)
     return out
@@ -181,6 +197,10 @@ def summarize(stats):
     """Medians and means over the evaluated cycles."""
     keys = list(stats[0].rho)
     s = {"cycles": len(stats), "fallbacks": int(sum(x.fallback for x in stats))}
+    for extra in ("net_columns", "net_columns_unweighted"):
+        vals = [x.capture[extra] for x in stats if extra in x.capture]
+        if vals:
+            s[extra + "_capture_mean"] = float(np.mean(vals))
     for key in keys:
         s[key] = {
             "rho_median": float(np.median([x.rho[key] for x in stats])),

@@ -83,7 +83,8 @@ class _TracerDesc(ctypes.Structure):
 
 
 class _NetDesc(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_int32) for k in ("n", "layers", "channels", "k", "width", "batch_max")]
+    _fields_ = [(k, ctypes.c_int32) for k in ("n", "layers", "channels", "k", "width", "batch_max",
+                                              "segments")]
 
 
 class _RsvdInfo(ctypes.Structure):
@@ -663,12 +664,14 @@ class ProposalNet:
     """Learned sketch proposal: periodic 1-D conv net, its training and inference kernels
     (C ABI riot_net_*). States x: (batch, n) float64; outputs N: (batch, k, n) float32."""
 
-    def __init__(self, n, k=64, channels=64, layers=4, width=9, batch_max=32, device="cuda"):
+    def __init__(self, n, k=64, channels=64, layers=4, width=9, batch_max=32, segments=1,
+                 device="cuda"):
         self.lib = load_library()
         d = _NetDesc()
-        d.n, d.layers, d.channels, d.k, d.width, d.batch_max = (
-            int(n), int(layers), int(channels), int(k), int(width), int(batch_max))
+        d.n, d.layers, d.channels, d.k, d.width, d.batch_max, d.segments = (
+            int(n), int(layers), int(channels), int(k), int(width), int(batch_max), int(segments))
         self.n, self.k, self.channels, self.layers, self.width = d.n, d.k, d.channels, d.layers, d.width
+        self.segments = d.segments
         self.batch_max, self.device = d.batch_max, torch.device(device)
         nb = self.lib.riot_net_workspace_bytes(ctypes.byref(d))
         if nb == 0:
@@ -695,7 +698,7 @@ class ProposalNet:
         """[(cout, cin, width)] per layer, in the flat parameter order."""
         out, cin = [], 1
         for li in range(self.layers):
-            cout = self.k if li == self.layers - 1 else self.channels
+            cout = self.k // self.segments if li == self.layers - 1 else self.channels
             out.append((cout, cin, self.width))
             cin = cout
         return out

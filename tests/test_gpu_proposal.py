@@ -35,9 +35,10 @@ def _unflat(flat, shapes):
     return out
 
 
-def _net(n, k, channels, layers, width, batch, seed):
+def _net(n, k, channels, layers, width, batch, seed, segments=1):
     from paper_1906_01413_amd import ProposalNet
-    net = ProposalNet(n, k=k, channels=channels, layers=layers, width=width, batch_max=batch)
+    net = ProposalNet(n, k=k, channels=channels, layers=layers, width=width, batch_max=batch,
+                      segments=segments)
     params = net_init(seed, net.layer_shapes())
     # biases drawn too, so that the bias paths are exercised; both sides see FP32 values
     rng = np.random.default_rng(seed + 1)
@@ -52,32 +53,38 @@ def _states(batch, n, seed):
     return 8.0 + 3.0 * np.random.default_rng(seed).standard_normal((batch, n))
 
 
-SMALL = dict(n=192, k=5, channels=20, layers=3, width=5, batch=3)
+# 3 grid tiles of 64 points, a ragged channel tile (20 = 16 + 4); without and with the
+# localized head (3 segments of 64 points, 2 channels each)
+CONFIGS = {
+    "plain": dict(n=192, k=5, channels=20, layers=3, width=5, batch=3, segments=1),
+    "segmented": dict(n=192, k=6, channels=20, layers=3, width=5, batch=3, segments=3),
+}
 
 
-@pytest.fixture(scope="module")
-def small():
-    net, params = _net(**SMALL, seed=11)
-    return net, params, _states(SMALL["batch"], SMALL["n"], 12)
+@pytest.fixture(scope="module", params=list(CONFIGS))
+def small(request):
+    cfg = CONFIGS[request.param]
+    net, params = _net(**cfg, seed=11)
+    return net, params, _states(cfg["batch"], cfg["n"], 12), cfg
 
 
 def test_forward_matches_oracle(small):
-    net, params, X = small
+    net, params, X, cfg = small
     N = to_np(net.forward(X))
     for s in range(X.shape[0]):
-        ref, _ = convnet.forward(params, X[s])
+        ref, _ = convnet.forward(params, X[s], cfg["segments"])
         assert rel(N[s], ref.T) < 1e-5, s
 
 
 def test_backward_matches_oracle(small):
-    net, params, X = small
-    gN = np.random.default_rng(13).standard_normal((X.shape[0], SMALL["k"], SMALL["n"])).astype(np.float32)
+    net, params, X, cfg = small
+    gN = np.random.default_rng(13).standard_normal((X.shape[0], cfg["k"], cfg["n"])).astype(np.float32)
     net.forward(X)
     g = to_np(net.backward(torch.tensor(gN, device="cuda")))
     ref = None
     for s in range(X.shape[0]):
-        _, acts = convnet.forward(params, X[s])
-        gs = convnet.backward(params, acts, gN[s].astype(np.float64).T)
+        _, acts = convnet.forward(params, X[s], cfg["segments"])
+        gs = convnet.backward(params, acts, gN[s].astype(np.float64).T, cfg["segments"])
         ref = gs if ref is None else [(a + c, b + d) for (a, b), (c, d) in zip(ref, gs)]
     for (gW, gb), (rW, rb) in zip(_unflat(g, net.layer_shapes()), ref):
         assert rel(gW, rW) < 1e-4
@@ -85,8 +92,8 @@ def test_backward_matches_oracle(small):
 
 
 def test_capture_loss_matches_oracle(small):
-    net, _, _ = small
-    b, k, n = SMALL["batch"], SMALL["k"], SMALL["n"]
+    net, _, _, cfg = small
+    b, k, n = cfg["batch"], cfg["k"], cfg["n"]
     rng = np.random.default_rng(14)
     N = rng.standard_normal((b, k, n)).astype(np.float32)
     V = np.stack([np.linalg.qr(rng.standard_normal((n, k)))[0].T for _ in range(b)])
@@ -100,7 +107,7 @@ def test_capture_loss_matches_oracle(small):
 
 
 def test_adam_matches_oracle(small):
-    net, params, _ = small
+    net, params, _, _ = small
     rng = np.random.default_rng(15)
     p = _flat(params)
     m = np.zeros_like(p)
@@ -119,17 +126,17 @@ def test_adam_matches_oracle(small):
 
 
 def test_train_step_is_the_composition_and_lowers_the_loss(small):
-    net, params, X = small
+    net, params, X, cfg = small
     from paper_1906_01413_amd import ProposalNet
-    b, k, n = SMALL["batch"], SMALL["k"], SMALL["n"]
+    b, k, n, S = cfg["batch"], cfg["k"], cfg["n"], cfg["segments"]
     # targets a network of this shape can reach: the orthonormalised outputs of another
     # ("teacher") network, evaluated by the oracle
     teacher = net_init(99, [(c, ci, wd) for c, ci, wd in net.layer_shapes()])
-    V = np.stack([np.linalg.qr(convnet.forward(teacher, X[s])[0])[0].T for s in range(b)])
+    V = np.stack([np.linalg.qr(convnet.forward(teacher, X[s], S)[0])[0].T for s in range(b)])
     w = np.random.default_rng(16).uniform(0.5, 2.0, (b, k))
     # the same step by the separate calls on a second network with the same start
-    twin = ProposalNet(n, k=k, channels=SMALL["channels"], layers=SMALL["layers"],
-                       width=SMALL["width"], batch_max=b)
+    twin = ProposalNet(n, k=k, channels=cfg["channels"], layers=cfg["layers"],
+                       width=cfg["width"], batch_max=b, segments=S)
     twin.set_params(_flat(params).astype(np.float32))
     net.set_params(_flat(params).astype(np.float32))
     l0 = net.train_step(X, V, w, 1e-2)
@@ -145,20 +152,22 @@ def test_train_step_is_the_composition_and_lowers_the_loss(small):
     net.set_params(_flat(params).astype(np.float32))
 
 
-def test_full_size_network_matches_oracle():
+@pytest.mark.parametrize("segments", [1, 16])
+def test_full_size_network_matches_oracle(segments):
     """n = 2048, 4 layers x 64 channels, width 9, k = 64, two states."""
-    net, params = _net(n=2048, k=64, channels=64, layers=4, width=9, batch=2, seed=21)
+    net, params = _net(n=2048, k=64, channels=64, layers=4, width=9, batch=2, seed=21,
+                       segments=segments)
     X = _states(2, 2048, 22)
     N = to_np(net.forward(X))
     gN = np.random.default_rng(23).standard_normal((2, 64, 2048)).astype(np.float32)
     g = to_np(net.backward(torch.tensor(gN, device="cuda")))
     ref, near0 = None, 0
     for s in range(2):
-        No, acts = convnet.forward(params, X[s])
+        No, acts = convnet.forward(params, X[s], segments)
         assert rel(N[s], No.T) < 1e-5
         for a in acts[1:-1]:
             near0 += int(np.sum((a > 0) & (a < 1e-5 * np.max(np.abs(a)))))
-        gs = convnet.backward(params, acts, gN[s].astype(np.float64).T)
+        gs = convnet.backward(params, acts, gN[s].astype(np.float64).T, segments)
         ref = gs if ref is None else [(a + c, b + d) for (a, b), (c, d) in zip(ref, gs)]
     # a hidden unit whose FP32 and FP64 ReLU decisions differ contributes one term of
     # the same size as the others to a few gradient sums. Units within 1e-5 of zero on

@@ -1,6 +1,7 @@
 """Pins of the sketch-proposal network oracle (oracle/convnet.py)."""
 
 import numpy as np
+import pytest
 
 from oracle import convnet
 from synthetic import net_init
@@ -28,24 +29,40 @@ def _fd_check(f, x, g, rng, eps=1e-6):
     return abs(fd - an) / max(abs(an), 1e-12)
 
 
-def test_network_gradients_match_central_differences():
+def test_localized_head_partitions_the_channels():
+    """Columns c S + q, q = 0..S-1, have disjoint supports (blocks of n / S points) and
+    sum to channel c."""
+    z = np.random.default_rng(6).standard_normal((3, 24))
+    N = convnet.localize(z, 4)
+    assert N.shape == (24, 12)
+    for c in range(3):
+        cols = N[:, c * 4: c * 4 + 4]
+        assert np.array_equal(cols.sum(axis=1), z[c])
+        assert np.all(np.count_nonzero(cols, axis=1) <= 1)
+        for q in range(4):
+            assert np.all(cols[:q * 6, q] == 0) and np.all(cols[q * 6 + 6:, q] == 0)
+    assert np.array_equal(convnet.localize(z, 1), z.T)
+
+
+@pytest.mark.parametrize("segments", [1, 2])
+def test_network_gradients_match_central_differences(segments):
     rng = np.random.default_rng(1)
     n = 16
     params = net_init(7, [(3, 1, 5), (3, 3, 5), (2, 3, 5)])
     x = rng.standard_normal(n)
-    gN = rng.standard_normal((n, 2))
-    N, acts = convnet.forward(params, x)
-    grads = convnet.backward(params, acts, gN)
+    gN = rng.standard_normal((n, 2 * segments))
+    N, acts = convnet.forward(params, x, segments)
+    grads = convnet.backward(params, acts, gN, segments)
     for li in range(len(params)):
         W, b = params[li]
 
         def fW(Wp, li=li):
             p = [(Wp if i == li else params[i][0], params[i][1]) for i in range(len(params))]
-            return float(np.sum(gN * convnet.forward(p, x)[0]))
+            return float(np.sum(gN * convnet.forward(p, x, segments)[0]))
 
         def fb(bp, li=li):
             p = [(params[i][0], bp if i == li else params[i][1]) for i in range(len(params))]
-            return float(np.sum(gN * convnet.forward(p, x)[0]))
+            return float(np.sum(gN * convnet.forward(p, x, segments)[0]))
 
         assert _fd_check(fW, W, grads[li][0], rng) < 1e-7
         assert _fd_check(fb, b, grads[li][1], rng) < 1e-7

@@ -34,14 +34,14 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM-side traffic of one 272-column TL/AD launch at n = 4096, T = 100 (E = 16), from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch). Each counter is scaled by
-# what it reads for a plain 256 MiB device copy (FETCH_SIZE 131093 KiB for 262144 KiB read,
+# what it reads for a plain 256 MiB device copy (FETCH_SIZE 131087 KiB for 262144 KiB read,
 # WRITE_SIZE 262144 KiB for 262144 KiB written). Valid only for the kernel source it was
 # measured on (sha256 of l96.hip); any other source reports traffic as null.
 TLAD_COUNTERS = {
-    "l96_sha256": "3a93824f80ce415fdec25bbdc4e1a445a9b8e2781dadbbf5ae5b7a247c40521e",
+    "l96_sha256": "1021cfd9cd5daad2efb1a4b0bcc264dd72875db210992fc289bb9a97a652677e",
     "n": 4096, "nsteps": 100, "m": 272,
-    "fetch_kib": 244457.8, "write_kib": 52224.0,
-    "fetch_scale": 262144.0 / 131093.1, "write_scale": 1.0,
+    "fetch_kib": 244203.1, "write_kib": 52224.0,
+    "fetch_scale": 262144.0 / 131087.25, "write_scale": 1.0,
 }
 
 WORKLOADS = {
@@ -361,6 +361,26 @@ def tracer_leg(seed: int, dev, m: int = 512, reps: int = 3) -> dict:
     }
 
 
+def proposal_leg(seed: int) -> dict:
+    """Cycled Lorenz-96 n = 2048 (window 50 steps, 10240 observations per window): training
+    data from cycles 1-100, GPU training of the proposal network, cycles 101-200 judged
+    learned (64 + 16 probes) against Gaussian 80 and Gaussian 128."""
+    from paper_1906_01413_amd import proposal
+    from synthetic import CYCLED, cycled_draws, net_init, workload
+
+    cfg = dict(CYCLED)
+    w = workload(cfg["workload"])
+    s = proposal.run_experiment(w, cycled_draws(seed, cfg["cycles"]), cfg,
+                                net_init(seed + 3, proposal.net_shapes(cfg)), seed=seed)
+    s["workload"] = (f"cycled Lorenz-96 n={w.n}, window {w.nsteps} steps, "
+                     f"{cfg['train_cycles']} training + {cfg['cycles'] - cfg['train_cycles']} test cycles; "
+                     f"net {cfg['layers']}x{cfg['channels']} conv1d width {cfg['width']}, "
+                     f"{cfg['snapshots']} input fields, {cfg['segments']}-segment head, "
+                     f"k={cfg['k_net']} + {cfg['p_gauss']} Gaussian vs Gaussian "
+                     f"{cfg['k_net'] + cfg['p_gauss']} and {cfg['m_ref']}")
+    return s
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,6 +396,8 @@ def main():
                     help="problems in the batched-uneven leg (0 skips it)")
     ap.add_argument("--tracer", type=int, default=1,
                     help="run the tracer source-inversion leg (0 skips it)")
+    ap.add_argument("--proposal", type=int, default=1,
+                    help="run the cycled learned-proposal leg (0 skips it)")
     ap.add_argument("--counter-pass", action="store_true",
                     help="only launch the TL/AD kernel three times and a 256 MiB device copy "
                          "(calibration), for rocprofv3 --pmc runs; prints no JSON")
@@ -526,6 +548,15 @@ def main():
         print(f"[bench] tracer: {tl['probes']} probe products {tl['hvp_ms']:.1f} ms "
               f"({tl['roofline']['achieved']:.0f} GB/s), inner loop {tl['inner_loop_ms']:.1f} ms",
               file=sys.stderr, flush=True)
+
+    if args.proposal:
+        print("[bench] cycled learned-proposal leg", file=sys.stderr, flush=True)
+        out["proposal"] = proposal_leg(args.seed)
+        pl = out["proposal"]
+        print(f"[bench] proposal: train {pl['train_ms_per_step']:.2f} ms/step, columns capture "
+              f"{pl['net_columns_capture_mean']:.3f} (random {pl['random_columns_capture']:.3f}), "
+              f"rho learned/gauss {pl['rho_ratio_learned_over_gauss_m_median']:.3f}, "
+              f"fallbacks {pl['fallbacks']}/{pl['cycles']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, m)

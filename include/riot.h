@@ -407,19 +407,19 @@ riot_status riot_batch_problem(riot_batch *b, int32_t j, riot_handle **h);
  * has to span the dominant eigenvectors of A (Section 2.2), so a network trained on the
  * eigenvectors of earlier cycles may propose most of the block. This network is a 1-D
  * periodic convolution stack on the state's grid (FP32 weights and activations):
- *   h_0 = (x - mean(x)) / std(x)                       (one channel; x must not be constant)
+ *   h_0[c] = (x[c] - mean(x[c])) / std(x[c])           (C0 input rows; none constant)
  *   z_l[c, i] = b_l[c] + sum_{c', j} W_l[c, c', j] h_{l-1}[c', (i + j - r) mod n]
  *   h_l = max(z_l, 0) for l < L                         (width 2 r + 1)
  *   N[i, c S + q] = z_L[c, i] if i lies in segment q, else 0   (localized output head)
  * An equivariant network alone gives fields over the whole grid; the head lets span(N)
  * hold structures at different places independently (S segments of n / S points).
  * Parameters: one flat FP32 array, per layer W_l [cout][cin][width] then b_l [cout]; layer
- * 1 has cin = 1, the last cout = k / S, the others cout = channels.
+ * 1 has cin = C0, the last cout = k / S, the others cout = channels.
  * Training loss (eigenvalue-weighted subspace capture; a reading, the paper has no net):
  *   loss = -sum_i w_i v_i^T P v_i / sum_i w_i,  P = N (N^T N)^{-1} N^T,
  *   d loss / d N = -(2 / sum w) (I - P) V diag(w) V^T N (N^T N)^{-1},
  * evaluated in FP64 (Gram matrix, Cholesky, triangular solves on the FP64 MFMA GEMMs).
- * All data pointers are DEVICE pointers; a batch of states is [batch][n], network outputs
+ * All data pointers are DEVICE pointers; a batch of inputs is [batch][C0][n], network outputs
  * [batch][k][n] (each sample an n x k column-major block), V [batch][k][n], w [batch][k].
  * The network keeps the activations of its last forward call for the backward call.
  * ---------------------------------------------------------------------------------- */
@@ -435,6 +435,7 @@ typedef struct {
     int32_t segments;   /* S >= 1 (divides n and k): the last layer has k / S channels and
                            column c S + q of N is channel c on the q-th block of n / S
                            consecutive grid points, zero elsewhere (S = 1: N = z_L^T) */
+    int32_t in_channels;/* C0, 1..64: fields per input sample (e.g. states along the window) */
 } riot_net_desc;
 
 size_t riot_net_workspace_bytes(const riot_net_desc *desc);  /* 0: invalid descriptor */
@@ -447,7 +448,7 @@ int64_t riot_net_param_count(const riot_net *h);
 riot_status riot_net_set_params(riot_net *h, const float *params, const float *grads);
 /* Copy the parameters and/or the last gradients out (either pointer may be NULL). */
 riot_status riot_net_get_params(riot_net *h, float *params, float *grads);
-/* N = net(x) for a batch of states x [batch][n] (FP64). N [batch][k][n] FP32 out or NULL;
+/* N = net(x) for a batch of inputs x [batch][C0][n] (FP64). N [batch][k][n] FP32 out or NULL;
  * N64 FP64 out or NULL: sample s, column c at N64 + (s * k + c) * ld64 (ld64 >= n), so a
  * single state's proposal can fill the first k columns of an n x m probe block. */
 riot_status riot_net_forward(riot_net *h, int32_t batch, const double *x, float *N,

@@ -3,8 +3,9 @@
 Test infrastructure only: nothing in the product path imports this module.
 
 A 1-D periodic convolutional network maps a background state x (n,) to k basis vectors
-N (n, k) that are used as RIOT probes in place of Gaussian ones. Input h_0 = x minus its
-mean, over its standard deviation (one channel). Layers l = 1..L:
+N (n, k) that are used as RIOT probes in place of Gaussian ones. Input h_0: each of the C0
+input rows (e.g. states along the window) minus its mean, over its standard deviation.
+Layers l = 1..L:
   z_l[c, i] = b_l[c] + sum_{c', j} W_l[c, c', j] h_{l-1}[c', (i + j - r) mod n],
   h_l = relu(z_l) for l < L, h_L = z_L,
 width 2 r + 1. Output head with S segments (S = 1: N[:, c] = h_L[c, :]): column c S + q of
@@ -47,9 +48,10 @@ def conv1d_backward(x: np.ndarray, W: np.ndarray, gz: np.ndarray):
 
 
 def standardize(x: np.ndarray) -> np.ndarray:
-    """The network's input: x minus its mean over the grid, divided by its standard deviation."""
-    x = np.asarray(x, dtype=np.float64)
-    return (x - x.mean()) / x.std()
+    """The network's input: each row of x (C0, n) minus its mean over the grid, divided by
+    its standard deviation; a single state (n,) is one row."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    return (x - x.mean(axis=1, keepdims=True)) / x.std(axis=1, keepdims=True)
 
 
 def localize(z: np.ndarray, segments: int) -> np.ndarray:
@@ -67,7 +69,7 @@ def localize(z: np.ndarray, segments: int) -> np.ndarray:
 
 def forward(params, x: np.ndarray, segments: int = 1):
     """Network output N (n, k) for the standardized input, and the per-layer activations."""
-    h = standardize(x)[None, :]
+    h = standardize(x)
     acts = [h]
     for li, (W, b) in enumerate(params):
         z = conv1d(h, W, b)

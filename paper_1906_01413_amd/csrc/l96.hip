@@ -419,10 +419,13 @@ struct Member {
   // previous segment's last step); kTladInitLam = the AD starts from dx0 instead of zero;
   // kTladOutState = mode 2 writes the final tangent state into lam0. dx0 and lam0 use the
   // natural layout (double).
+  // FLAGS = false compiles the flag tests out (the single-window hot path, whose register
+  // budget is full at 16 elements per lane).
+  template <bool FLAGS = true>
   __device__ void run(int mode, const double *__restrict__ dx0, double *__restrict__ lam0,
                       Real *__restrict__ f, const Real *__restrict__ fsrc) {
-    const int base = mode & 7;
-    const bool skip0 = (mode & kTladSkip0) != 0;
+    const int base = FLAGS ? (mode & 7) : mode;
+    const bool skip0 = FLAGS && (mode & kTladSkip0) != 0;
     const int a = l * E;
     Real v[E];
     if (base == 0 || base == 2) {
@@ -430,7 +433,7 @@ struct Member {
       for (int j = 0; j < E; ++j) v[j] = active ? (Real)dx0[a + j] : (Real)0;
       tl_sweep(v, f, base == 0, skip0);
       if (base == 2) {
-        if ((mode & kTladOutState) && active) {
+        if (FLAGS && (mode & kTladOutState) && active) {
 #pragma unroll
           for (int j = 0; j < E; ++j) lam0[a + j] = (double)v[j];
         }
@@ -441,7 +444,7 @@ struct Member {
       member_sync<WAVE>();
       ad_sweep(v, f, skip0, false);
     } else {
-      const bool init = (mode & kTladInitLam) != 0;
+      const bool init = FLAGS && (mode & kTladInitLam) != 0;
       if (init) {
 #pragma unroll
         for (int j = 0; j < E; ++j) v[j] = active ? (Real)dx0[a + j] : (Real)0;
@@ -455,7 +458,7 @@ struct Member {
   }
 };
 
-template <typename Real, int E>
+template <typename Real, int E, bool FLAGS>
 __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
     tlad_kernel(ModelView mv, int mode, const double *__restrict__ dx0, double *__restrict__ lam0,
                 Real *__restrict__ f, const Real *__restrict__ fsrc) {
@@ -463,8 +466,8 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
   Real *lds = reinterpret_cast<Real *>(lds_raw);
   const int mem = blockIdx.x;
   Member<Real, E> M(mv, lds, threadIdx.x);
-  M.run(mode, dx0 + (size_t)mem * mv.n, lam0 + (size_t)mem * mv.n,
-        f + (size_t)mem * (size_t)mv.U, fsrc);
+  M.template run<FLAGS>(mode, dx0 + (size_t)mem * mv.n, lam0 + (size_t)mem * mv.n,
+                        f + (size_t)mem * (size_t)mv.U, fsrc);
 }
 
 // ---------------------------------------------------------------------------
@@ -720,7 +723,7 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
   for (; it < iters; ++it) {
     // q = (I + A) p = p + L^T G^T R^{-1} G L p
     apply_L_column(n, w, taps, p, tmp, nullptr, 0, ext);
-    M.run(0, tmp, lam, f, nullptr);
+    M.template run<false>(0, tmp, lam, f, nullptr);
     __syncthreads();
     apply_L_column(n, w, taps, lam, q, p, 1, ext);
     double pq_part = 0.0;
@@ -863,18 +866,33 @@ hipError_t launch_cost(int n, const double *v, int nobs, const double *d, const 
 hipError_t launch_tlad(const ModelView &mv, int m, int mode, const double *dx0, double *lam0,
                        void *f, const void *fsrc, bool fp32, hipStream_t st) {
   if (m <= 0) return hipSuccess;
+  const bool flags = (mode & ~7) != 0;
   if (fp32) {
     const size_t lds = (size_t)kLdsSlots * 2 * mv.NT * sizeof(float);
-    RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((tlad_kernel<float, EE>), dim3(m), dim3(mv.NT), lds,
-                                             st, mv, mode, dx0, lam0,
-                                             reinterpret_cast<float *>(f),
-                                             reinterpret_cast<const float *>(fsrc)));
+    if (flags) {
+      RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((tlad_kernel<float, EE, true>), dim3(m),
+                                               dim3(mv.NT), lds, st, mv, mode, dx0, lam0,
+                                               reinterpret_cast<float *>(f),
+                                               reinterpret_cast<const float *>(fsrc)));
+    } else {
+      RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((tlad_kernel<float, EE, false>), dim3(m),
+                                               dim3(mv.NT), lds, st, mv, mode, dx0, lam0,
+                                               reinterpret_cast<float *>(f),
+                                               reinterpret_cast<const float *>(fsrc)));
+    }
   } else {
     const size_t lds = (size_t)kLdsSlots * 2 * mv.NT * sizeof(double);
-    RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((tlad_kernel<double, EE>), dim3(m), dim3(mv.NT), lds,
-                                             st, mv, mode, dx0, lam0,
-                                             reinterpret_cast<double *>(f),
-                                             reinterpret_cast<const double *>(fsrc)));
+    if (flags) {
+      RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((tlad_kernel<double, EE, true>), dim3(m),
+                                               dim3(mv.NT), lds, st, mv, mode, dx0, lam0,
+                                               reinterpret_cast<double *>(f),
+                                               reinterpret_cast<const double *>(fsrc)));
+    } else {
+      RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((tlad_kernel<double, EE, false>), dim3(m),
+                                               dim3(mv.NT), lds, st, mv, mode, dx0, lam0,
+                                               reinterpret_cast<double *>(f),
+                                               reinterpret_cast<const double *>(fsrc)));
+    }
   }
   return hipGetLastError();
 }

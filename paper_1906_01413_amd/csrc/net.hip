@@ -21,7 +21,8 @@ constexpr int kCX = 64;   // grid points per tile
 constexpr int kCC = 16;   // output channels per tile
 constexpr int kMaxWidth = 11;  // keeps a tile's LDS within 64 KiB at 64 channels
 
-// Per-sample standardization (x - mean) / std of FP64 states into FP32 channels.
+// Per-row standardization (x - mean) / std of FP64 input rows (one workgroup per sample and
+// input channel) into FP32.
 __global__ void __launch_bounds__(256)
     standardize_kernel(int n, const double *__restrict__ x, float *__restrict__ out) {
   __shared__ double red[256];
@@ -295,7 +296,7 @@ struct riot_net {
   std::vector<long long> woff, boff;  // per layer offsets into the flat parameters
   std::vector<int> cin, cout;
   float *params = nullptr, *grads = nullptr, *am = nullptr, *av = nullptr;
-  float *x0 = nullptr;               // standardized inputs [batch][n]
+  float *x0 = nullptr;               // standardized inputs [batch][in_channels][n]
   std::vector<float *> acts;         // per layer outputs [batch][cout][n]
   float *g0 = nullptr, *g1 = nullptr, *Wt = nullptr, *gN = nullptr;
   float *Nout = nullptr;             // network output after the head [batch][k][n]
@@ -334,7 +335,7 @@ bool net_desc_ok(const riot_net_desc *d) {
          d->channels >= 1 && d->channels <= 64 && d->k >= 1 && d->k <= 64 && d->k <= d->n &&
          d->width >= 1 && d->width % 2 == 1 && d->width <= riot::kMaxWidth &&
          d->batch_max >= 1 && d->segments >= 1 && d->n % d->segments == 0 &&
-         d->k % d->segments == 0;
+         d->k % d->segments == 0 && d->in_channels >= 1 && d->in_channels <= 64;
 }
 
 size_t net_carve(riot_net &h, void *base) {
@@ -342,7 +343,7 @@ size_t net_carve(riot_net &h, void *base) {
   const riot_net_desc &d = h.d;
   h.woff.clear(), h.boff.clear(), h.cin.clear(), h.cout.clear();
   long long np = 0;
-  int ci = 1;
+  int ci = d.in_channels;
   int maxc = 1;
   for (int l = 0; l < d.layers; ++l) {
     const int co = (l == d.layers - 1) ? d.k / d.segments : d.channels;
@@ -360,7 +361,7 @@ size_t net_carve(riot_net &h, void *base) {
   h.grads = c.take<float>(np);
   h.am = c.take<float>(np);
   h.av = c.take<float>(np);
-  h.x0 = c.take<float>(B * n);
+  h.x0 = c.take<float>(B * d.in_channels * n);
   h.acts.assign(d.layers, nullptr);
   for (int l = 0; l < d.layers; ++l) h.acts[l] = c.take<float>(B * h.cout[l] * n);
   h.g0 = c.take<float>(B * maxc * n);
@@ -524,7 +525,8 @@ riot_status riot_net_forward(riot_net *h, int32_t batch, const double *x, float 
   if (!h || !x || batch < 1 || batch > h->d.batch_max) return RIOT_E_ARG;
   const int n = h->d.n, k = h->d.k;
   if (N64 && ld64 < n) return RIOT_E_ARG;
-  hipLaunchKernelGGL(riot::standardize_kernel, dim3(batch), dim3(256), 0, h->st, n, x, h->x0);
+  hipLaunchKernelGGL(riot::standardize_kernel, dim3(batch * h->d.in_channels), dim3(256), 0, h->st,
+                     n, x, h->x0);
   NET_HIP(hipGetLastError());
   const float *in = h->x0;
   for (int l = 0; l < h->d.layers; ++l) {

@@ -65,6 +65,16 @@ class CycledL96:
         _, g, J = r.linearize(self.xb)
         return g.clone(), J
 
+    def window_states(self, snapshots: int):
+        """The network's input for this cycle: the background forecast at `snapshots` evenly
+        spaced steps of the window (step 0 = x_b), shape (snapshots, n)."""
+        xs = [self.xb]
+        if snapshots > 1:
+            stride = self.w.nsteps // (snapshots - 1)
+            for _ in range(snapshots - 1):
+                xs.append(self.r.forecast(xs[-1], stride))
+        return torch.stack(xs)
+
     def advance(self, dx):
         """Analysis x_a = x_b + dx at the window start; both runs forecast one window."""
         T = self.w.nsteps
@@ -89,19 +99,19 @@ def weighted_capture(Q, Vref, w):
     return float(np.sum(wh * c) / np.sum(wh))
 
 
-def collect(exp: CycledL96, cycles: int, k_net: int, m_ref: int, seed: int):
+def collect(exp: CycledL96, cycles: int, k_net: int, m_ref: int, seed: int, snapshots: int = 1):
     """Cycles 1..cycles with the reference sketch (m_ref Gaussian probes, one power step):
     the leading k_net Ritz pairs of each cycle are the training targets. Also records the
     projected residual of a plain m_ref-probe sketch (q = 0), whose median over these
     cycles is the proposal's fallback threshold."""
     n, r = exp.w.n, exp.r
-    X = torch.empty((cycles, n), dtype=torch.float64, device=exp.dev)
+    X = torch.empty((cycles, snapshots, n), dtype=torch.float64, device=exp.dev)
     V = torch.empty((cycles, k_net, n), dtype=torch.float64, device=exp.dev)
     lam = torch.empty((cycles, k_net), dtype=torch.float64, device=exp.dev)
     rho_ref = []
     for c in range(cycles):
         g, _ = exp.observe()
-        X[c] = exp.xb
+        X[c] = exp.window_states(snapshots)
         lq, Vq, _ = r.rsvd(m_ref - 16, 16, q=1, seed=seed + 7919 * c, want_info=False)
         V[c] = Vq.t()[:k_net]
         lam[c] = lq[:k_net]
@@ -120,7 +130,7 @@ def train(net: ProposalNet, X, V, lam, steps: int, batch: int, lr: float, seed: 
     problem when the model is translation invariant and the observation network repeats
     with that period."""
     rng = np.random.default_rng(seed)
-    ncyc, n = X.shape
+    ncyc, n = X.shape[0], X.shape[-1]
     losses = []
     order = rng.permutation(ncyc)
     pos = 0
@@ -134,14 +144,14 @@ def train(net: ProposalNet, X, V, lam, steps: int, batch: int, lr: float, seed: 
         if shift_step:
             s = torch.as_tensor(rng.integers(0, n // shift_step, batch) * shift_step, device=X.device)
             src = (ar[None, :] - s[:, None]) % n          # rolled[b, i] = orig[b, i - s_b]
-            xb = torch.gather(xb, 1, src)
+            xb = torch.gather(xb, 2, src[:, None, :].expand_as(xb))
             Vb = torch.gather(Vb, 2, src[:, None, :].expand_as(Vb))
         losses.append(float(np.mean(net.train_step(xb, Vb, wb, lr))))
     return np.asarray(losses)
 
 
 def evaluate(exp: CycledL96, net: ProposalNet, cycles: int, k_net: int, p_gauss: int, m_ref: int,
-             tau: float, exact_every: int, seed: int, Vref_q: int = 1):
+             tau: float, exact_every: int, seed: int, Vref_q: int = 1, snapshots: int = 1):
     """Cycles after training. At each background the learned block [N(x_b), G_p] (m =
     k_net + p_gauss), a Gaussian block of the same size and a Gaussian block of m_ref are
     sketched on the same A; rho judges each. The cycle advances with the learned result,
@@ -158,7 +168,7 @@ def evaluate(exp: CycledL96, net: ProposalNet, cycles: int, k_net: int, p_gauss:
         res = {}
 
         def learned():
-            net.propose(exp.xb, Om)
+            net.propose(exp.window_states(snapshots), Om)
             r.philox_normal(n, p_gauss, seed + 31 * exp.cycle + 3, out=Om[:, k_net:])
             return r.rsvd(k_net, p_gauss, q=0, Omega=Om, want_info=False)
 
@@ -211,4 +221,55 @@ def summarize(stats):
         if errs:
             s[key]["dx_err_mean"] = float(np.mean(errs))
             s[key]["capture_mean"] = float(np.mean(caps))
+    return s
+
+
+def net_shapes(cfg: dict):
+    """(cout, cin, width) of each layer of the configured network, in parameter order."""
+    C, W, L = cfg["channels"], cfg["width"], cfg["layers"]
+    cins = [cfg["snapshots"]] + [C] * (L - 1)
+    couts = [C] * (L - 1) + [cfg["k_net"] // cfg["segments"]]
+    return [(co, ci, W) for co, ci in zip(couts, cins)]
+
+
+def run_experiment(w, draws, cfg: dict, init_params, seed: int = 0, train_cycles=None,
+                   test_cycles=None, train_steps=None, device="cuda"):
+    """The whole cycled comparison: collect training data over train_cycles cycles, train
+    the network from init_params ([(W, b)] per layer) on the GPU, then evaluate on
+    test_cycles further cycles. Returns a summary dict (times in seconds)."""
+    train_cycles = cfg["train_cycles"] if train_cycles is None else train_cycles
+    test_cycles = cfg["cycles"] - cfg["train_cycles"] if test_cycles is None else test_cycles
+    train_steps = cfg["train_steps"] if train_steps is None else train_steps
+    k, snap = cfg["k_net"], cfg["snapshots"]
+    t0 = time.perf_counter()
+    exp = CycledL96(w, draws, cfg["m_ref"], device=device)
+    X, V, lam, rho_ref = collect(exp, train_cycles, k, cfg["m_ref"], seed + 1, snapshots=snap)
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    net = ProposalNet(w.n, k=k, channels=cfg["channels"], layers=cfg["layers"],
+                      width=cfg["width"], batch_max=cfg["batch"], segments=cfg["segments"],
+                      in_channels=snap, device=device)
+    net.set_params(np.concatenate([np.concatenate([np.ravel(W), b]) for W, b in init_params]))
+    t0 = time.perf_counter()
+    losses = train(net, X, V, lam, train_steps, cfg["batch"], cfg["lr"], seed + 2,
+                   shift_step=cfg["shift_step"])
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    tau = float(np.median(rho_ref))
+    t0 = time.perf_counter()
+    stats = evaluate(exp, net, test_cycles, k, cfg["p_gauss"], cfg["m_ref"], tau,
+                     cfg["exact_every"], seed + 5, snapshots=snap)
+    t_eval = time.perf_counter() - t0
+    s = summarize(stats)
+    s.update({
+        "train_cycles": train_cycles, "test_cycles": test_cycles, "train_steps": train_steps,
+        "tau_rho_gauss_ref_median": tau,
+        "train_loss_first": float(losses[0]), "train_loss_last": float(np.mean(losses[-20:])),
+        # a random k-dimensional subspace holds k / n of any fixed vector's energy on average
+        "random_columns_capture": k / w.n,
+        "rho_ratio_learned_over_gauss_m_median": float(np.median(
+            [x.rho["learned"] / x.rho["gauss_m"] for x in stats])),
+        "collect_s": t_collect, "train_s": t_train, "train_ms_per_step": 1e3 * t_train / train_steps,
+        "evaluate_s": t_eval,
+    })
     return s

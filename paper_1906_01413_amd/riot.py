@@ -84,7 +84,7 @@ class _TracerDesc(ctypes.Structure):
 
 class _NetDesc(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in ("n", "layers", "channels", "k", "width", "batch_max",
-                                              "segments")]
+                                              "segments", "in_channels")]
 
 
 class _RsvdInfo(ctypes.Structure):
@@ -662,16 +662,18 @@ class Sketch:
 
 class ProposalNet:
     """Learned sketch proposal: periodic 1-D conv net, its training and inference kernels
-    (C ABI riot_net_*). States x: (batch, n) float64; outputs N: (batch, k, n) float32."""
+    (C ABI riot_net_*). Inputs x: (batch, in_channels, n) float64 (or (batch, n) with one
+    input channel); outputs N: (batch, k, n) float32."""
 
     def __init__(self, n, k=64, channels=64, layers=4, width=9, batch_max=32, segments=1,
-                 device="cuda"):
+                 in_channels=1, device="cuda"):
         self.lib = load_library()
         d = _NetDesc()
-        d.n, d.layers, d.channels, d.k, d.width, d.batch_max, d.segments = (
-            int(n), int(layers), int(channels), int(k), int(width), int(batch_max), int(segments))
+        d.n, d.layers, d.channels, d.k, d.width, d.batch_max, d.segments, d.in_channels = (
+            int(n), int(layers), int(channels), int(k), int(width), int(batch_max), int(segments),
+            int(in_channels))
         self.n, self.k, self.channels, self.layers, self.width = d.n, d.k, d.channels, d.layers, d.width
-        self.segments = d.segments
+        self.segments, self.in_channels = d.segments, d.in_channels
         self.batch_max, self.device = d.batch_max, torch.device(device)
         nb = self.lib.riot_net_workspace_bytes(ctypes.byref(d))
         if nb == 0:
@@ -696,7 +698,7 @@ class ProposalNet:
 
     def layer_shapes(self):
         """[(cout, cin, width)] per layer, in the flat parameter order."""
-        out, cin = [], 1
+        out, cin = [], self.in_channels
         for li in range(self.layers):
             cout = self.k // self.segments if li == self.layers - 1 else self.channels
             out.append((cout, cin, self.width))
@@ -737,7 +739,7 @@ class ProposalNet:
 
     def _states(self, x):
         x = torch.as_tensor(x, dtype=torch.float64).to(self.device)
-        x = x.reshape(-1, self.n).contiguous()
+        x = x.reshape(-1, self.in_channels, self.n).contiguous()
         assert 1 <= x.shape[0] <= self.batch_max
         return x
 

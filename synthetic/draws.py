@@ -230,9 +230,13 @@ def advdiff_draws(name: str, seed: int) -> dict:
 # background). Cycles 1..100 provide training data (leading Hessian eigenvectors),
 # cycles 101..200 compare the learned proposal (k_net network columns plus p_gauss
 # Gaussian probes) with Gaussian sketches of the same size and of m_ref probes. The
-# network: `layers` periodic conv1d layers of `width` taps and `channels` channels.
+# network: `layers` periodic conv1d layers of `width` taps and `channels` channels, input
+# the background forecast at `snapshots` evenly spaced steps of the window, output head
+# of `segments` segments; Adam for `train_steps` steps of `batch` cycles at rate `lr`,
+# samples rotated by random multiples of `shift_step` points (the observation period).
 CYCLED = dict(workload="l96_n2048", cycles=200, train_cycles=100, k_net=64, p_gauss=16,
-              m_ref=128, exact_every=10, layers=4, channels=64, width=9)
+              m_ref=128, exact_every=10, layers=4, channels=64, width=9, snapshots=6,
+              segments=16, train_steps=4000, batch=16, lr=1e-3, shift_step=2)
 
 
 def cycled_draws(seed: int, cycles: int) -> dict:

@@ -97,6 +97,12 @@ def test_network_is_shift_equivariant_and_scale_invariant():
     assert np.max(np.abs(Ns - np.roll(N, 5, axis=0))) < 1e-12
     Na, _ = convnet.forward(params, 3.0 * x + 7.0)
     assert np.max(np.abs(Na - N)) < 1e-12
+    # several input rows: each row is standardized on its own
+    p2 = net_init(9, [(4, 2, 5), (3, 4, 5)])
+    X2 = np.random.default_rng(4).standard_normal((2, 32))
+    N2, _ = convnet.forward(p2, X2)
+    N2a, _ = convnet.forward(p2, np.stack([0.5 * X2[0] - 1.0, 4.0 * X2[1] + 2.0]))
+    assert np.max(np.abs(N2a - N2)) < 1e-12
 
 
 def test_adam_first_step_and_fixed_point():

@@ -84,6 +84,54 @@ __device__ __forceinline__ void load_base(const Real *__restrict__ blk, int NT, 
   xe[E + 3] = blk[(E + 3) * NT + l];
 }
 
+// The same load through a buffer resource over the whole trajectory: the row offset is a
+// scalar (SGPR) and the lane offset one VGPR, so no per-row 64-bit vector address is
+// formed or kept live across the window loop. Reads past the resource return 0.
+struct TrajRsrc {
+  __amdgpu_buffer_rsrc_t r;
+  int row_bytes;  // NT * sizeof(Real)
+};
+
+template <typename Real>
+__device__ __forceinline__ TrajRsrc traj_rsrc(const ModelView &mv) {
+  const long long bytes = (long long)(mv.T + 1) * 4 * (mv.E + 4) * mv.NT * (long long)sizeof(Real);
+  const int nrec = bytes > 0x7fffffffLL ? 0x7fffffff : (int)bytes;
+  // dword 3 = 0x00020000: raw 32-bit data format of the gfx9 family
+  return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(mv.xs), (short)0, nrec, 0x00020000),
+          mv.NT * (int)sizeof(Real)};
+}
+
+template <typename Real>
+__device__ __forceinline__ Real buf_load(const TrajRsrc &tr, int voff, int soff);
+template <>
+__device__ __forceinline__ double buf_load<double>(const TrajRsrc &tr, int voff, int soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(tr.r, voff, soff, 0);
+  double d;
+  __builtin_memcpy(&d, &v, sizeof(d));
+  return d;
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(const TrajRsrc &tr, int voff, int soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b32(tr.r, voff, soff, 0);
+  float f;
+  __builtin_memcpy(&f, &v, sizeof(f));
+  return f;
+}
+
+// Stage block (t, s) into xe, as load_base.
+template <typename Real, int E>
+__device__ __forceinline__ void load_base_buf(const TrajRsrc &tr, int t, int s, int l,
+                                              Real (&xe)[E + 4]) {
+  const int blk = (t * 4 + s) * (E + 4) * tr.row_bytes;
+  const int voff = l * (int)sizeof(Real);
+#pragma unroll
+  for (int j = 0; j < E; ++j) xe[2 + j] = buf_load<Real>(tr, voff, blk + j * tr.row_bytes);
+  xe[0] = buf_load<Real>(tr, voff, blk + (E + 0) * tr.row_bytes);
+  xe[1] = buf_load<Real>(tr, voff, blk + (E + 1) * tr.row_bytes);
+  xe[E + 2] = buf_load<Real>(tr, voff, blk + (E + 2) * tr.row_bytes);
+  xe[E + 3] = buf_load<Real>(tr, voff, blk + (E + 3) * tr.row_bytes);
+}
+
 // d = J(x) e : (J e)_i = (e_{i+1} - e_{i-2}) x_{i-1} + (x_{i+1} - x_{i-2}) e_{i-1} - e_i
 template <typename Real, int E>
 __device__ __forceinline__ void tl_jac(const Real (&xe)[E + 4], const Real (&e)[E], Real hl2,
@@ -293,14 +341,15 @@ struct Member {
     const Real h6 = (Real)(mv.h / 6.0);
     Real xe[E + 4], e[E], d[E], acc[E];
     Real hl2 = 0, hl1 = 0, hr1 = 0, hr2 = 0;
+    const TrajRsrc tr = traj_rsrc<Real>(mv);
     for (int t = 0; t <= mv.T; ++t) {
       const int k = mv.stepk[t];
       if (k >= 0 && active && !(skip0 && t == 0)) tl_store(k, dl, f, weighted);
       if (t == mv.T) break;
       // stage 1
+      load_base_buf<Real, E>(tr, t, 0, l, xe);
       exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, dl, hl2, hl1, hr1, hr2);
       if (active) {
-        load_base<Real, E>(stage_block<Real>(mv, t, 0), NT, l, xe);
         tl_jac<Real, E>(xe, dl, hl2, hl1, hr1, d);
 #pragma unroll
         for (int j = 0; j < E; ++j) {
@@ -309,9 +358,9 @@ struct Member {
         }
       }
       // stage 2
+      load_base_buf<Real, E>(tr, t, 1, l, xe);
       exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, e, hl2, hl1, hr1, hr2);
       if (active) {
-        load_base<Real, E>(stage_block<Real>(mv, t, 1), NT, l, xe);
         tl_jac<Real, E>(xe, e, hl2, hl1, hr1, d);
 #pragma unroll
         for (int j = 0; j < E; ++j) {
@@ -320,9 +369,9 @@ struct Member {
         }
       }
       // stage 3
+      load_base_buf<Real, E>(tr, t, 2, l, xe);
       exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, e, hl2, hl1, hr1, hr2);
       if (active) {
-        load_base<Real, E>(stage_block<Real>(mv, t, 2), NT, l, xe);
         tl_jac<Real, E>(xe, e, hl2, hl1, hr1, d);
 #pragma unroll
         for (int j = 0; j < E; ++j) {
@@ -331,9 +380,9 @@ struct Member {
         }
       }
       // stage 4
+      load_base_buf<Real, E>(tr, t, 3, l, xe);
       exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, e, hl2, hl1, hr1, hr2);
       if (active) {
-        load_base<Real, E>(stage_block<Real>(mv, t, 3), NT, l, xe);
         tl_jac<Real, E>(xe, e, hl2, hl1, hr1, d);
 #pragma unroll
         for (int j = 0; j < E; ++j) {
@@ -352,6 +401,7 @@ struct Member {
     const Real h6 = (Real)(mv.h / 6.0);
     Real xe[E + 4], lp[E], a[E], s[E];
     Real hl2 = 0, hl1 = 0, hr1 = 0, hr2 = 0;
+    const TrajRsrc tr = traj_rsrc<Real>(mv);
     if (!init) {
 #pragma unroll
       for (int j = 0; j < E; ++j) lam[j] = 0;
@@ -369,9 +419,9 @@ struct Member {
           a[j] = h6 * lp[j];
         }
       }
+      load_base_buf<Real, E>(tr, ts, 3, l, xe);
       exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
       if (active) {
-        load_base<Real, E>(stage_block<Real>(mv, ts, 3), NT, l, xe);
         ad_jac<Real, E>(xe, a, hl1, hr1, hr2, s);
 #pragma unroll
         for (int j = 0; j < E; ++j) {
@@ -380,9 +430,9 @@ struct Member {
         }
       }
       // stage 3
+      load_base_buf<Real, E>(tr, ts, 2, l, xe);
       exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
       if (active) {
-        load_base<Real, E>(stage_block<Real>(mv, ts, 2), NT, l, xe);
         ad_jac<Real, E>(xe, a, hl1, hr1, hr2, s);
 #pragma unroll
         for (int j = 0; j < E; ++j) {
@@ -391,9 +441,9 @@ struct Member {
         }
       }
       // stage 2
+      load_base_buf<Real, E>(tr, ts, 1, l, xe);
       exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
       if (active) {
-        load_base<Real, E>(stage_block<Real>(mv, ts, 1), NT, l, xe);
         ad_jac<Real, E>(xe, a, hl1, hr1, hr2, s);
 #pragma unroll
         for (int j = 0; j < E; ++j) {
@@ -402,9 +452,9 @@ struct Member {
         }
       }
       // stage 1
+      load_base_buf<Real, E>(tr, ts, 0, l, xe);
       exchange<Real, E, WAVE>(lds, parity, NT, l, active, hm, a, hl2, hl1, hr1, hr2);
       if (active) {
-        load_base<Real, E>(stage_block<Real>(mv, ts, 0), NT, l, xe);
         ad_jac<Real, E>(xe, a, hl1, hr1, hr2, s);
 #pragma unroll
         for (int j = 0; j < E; ++j) lam[j] += s[j];

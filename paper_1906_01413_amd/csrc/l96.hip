@@ -293,7 +293,9 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
 // Member TL/AD sweep (device function shared by the batched kernel and CG).
 // ---------------------------------------------------------------------------
 
-template <typename Real, int E, bool WAVE = false>
+// FULL: every thread of the member owns state (n = E * NT), so the activity tests compile
+// away and each RK4 stage is one straight-line block.
+template <typename Real, int E, bool WAVE = false, bool FULL = false>
 struct Member {
   const ModelView &mv;
   Real *lds;
@@ -303,7 +305,7 @@ struct Member {
   int parity;
 
   __device__ Member(const ModelView &m, Real *lds_, int l_)
-      : mv(m), lds(lds_), l(l_), NT(m.NT), active(l_ < m.A), parity(0) {
+      : mv(m), lds(lds_), l(l_), NT(m.NT), active(FULL || l_ < m.A), parity(0) {
     if (active) hm.init(l, mv.n, NT);
   }
 
@@ -508,14 +510,14 @@ struct Member {
   }
 };
 
-template <typename Real, int E, bool FLAGS>
+template <typename Real, int E, bool FLAGS, bool FULL>
 __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
     tlad_kernel(ModelView mv, int mode, const double *__restrict__ dx0, double *__restrict__ lam0,
                 Real *__restrict__ f, const Real *__restrict__ fsrc) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   Real *lds = reinterpret_cast<Real *>(lds_raw);
   const int mem = blockIdx.x;
-  Member<Real, E> M(mv, lds, threadIdx.x);
+  Member<Real, E, false, FULL> M(mv, lds, threadIdx.x);
   M.template run<FLAGS>(mode, dx0 + (size_t)mem * mv.n, lam0 + (size_t)mem * mv.n,
                         f + (size_t)mem * (size_t)mv.U, fsrc);
 }
@@ -917,33 +919,32 @@ hipError_t launch_tlad(const ModelView &mv, int m, int mode, const double *dx0, 
                        void *f, const void *fsrc, bool fp32, hipStream_t st) {
   if (m <= 0) return hipSuccess;
   const bool flags = (mode & ~7) != 0;
+  const bool full = mv.A == mv.NT;
+#define RIOT_TLAD(R_, F_, U_)                                                                   \
+  RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((tlad_kernel<R_, EE, F_, U_>), dim3(m), dim3(mv.NT), \
+                                           lds, st, mv, mode, dx0, lam0,                        \
+                                           reinterpret_cast<R_ *>(f),                           \
+                                           reinterpret_cast<const R_ *>(fsrc)))
   if (fp32) {
     const size_t lds = (size_t)kLdsSlots * 2 * mv.NT * sizeof(float);
     if (flags) {
-      RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((tlad_kernel<float, EE, true>), dim3(m),
-                                               dim3(mv.NT), lds, st, mv, mode, dx0, lam0,
-                                               reinterpret_cast<float *>(f),
-                                               reinterpret_cast<const float *>(fsrc)));
+      RIOT_TLAD(float, true, false);
+    } else if (full) {
+      RIOT_TLAD(float, false, true);
     } else {
-      RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((tlad_kernel<float, EE, false>), dim3(m),
-                                               dim3(mv.NT), lds, st, mv, mode, dx0, lam0,
-                                               reinterpret_cast<float *>(f),
-                                               reinterpret_cast<const float *>(fsrc)));
+      RIOT_TLAD(float, false, false);
     }
   } else {
     const size_t lds = (size_t)kLdsSlots * 2 * mv.NT * sizeof(double);
     if (flags) {
-      RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((tlad_kernel<double, EE, true>), dim3(m),
-                                               dim3(mv.NT), lds, st, mv, mode, dx0, lam0,
-                                               reinterpret_cast<double *>(f),
-                                               reinterpret_cast<const double *>(fsrc)));
+      RIOT_TLAD(double, true, false);
+    } else if (full) {
+      RIOT_TLAD(double, false, true);
     } else {
-      RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((tlad_kernel<double, EE, false>), dim3(m),
-                                               dim3(mv.NT), lds, st, mv, mode, dx0, lam0,
-                                               reinterpret_cast<double *>(f),
-                                               reinterpret_cast<const double *>(fsrc)));
+      RIOT_TLAD(double, false, false);
     }
   }
+#undef RIOT_TLAD
   return hipGetLastError();
 }
 

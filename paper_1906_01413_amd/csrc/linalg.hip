@@ -1,12 +1,13 @@
 // Dense FP64 linear algebra of the RSVD stages (Alg. 3: orthonormal basis of Y,
 // solve for K, eigendecomposition of K, Ritz vectors) for gfx950.
 //
-//  - gemm_f64: tall-skinny products (Y^T Y, Q^T Y, Q^T Omega, Y R^{-1}, Q Z, W C W^T)
-//    on the FP64 matrix cores (v_mfma_f64_16x16x4_f64), split-K with a
-//    fixed-order reduction for the A^T B shape.
-//  - small m x m factorizations: one workgroup each (Cholesky with optional
-//    diagonal shift, triangular inverse, Gauss-Jordan inverse with partial
-//    pivoting, Householder tridiagonalisation + implicit QL eigen-solver).
+//  - gemm_f64: tall-skinny products (Y^T Y, Q^T Y, Q^T Omega, Q Z, W C W^T) on the
+//    FP64 matrix cores (v_mfma_f64_16x16x4_f64), split-K with a fixed-order
+//    reduction for the A^T B shape; a strided-batched form.
+//  - the m x m Cholesky of CholeskyQR (one workgroup; shifted and modified-pivot
+//    modes) and the right-hand triangular solve Q = Y L^{-T};
+//  - CholeskyQR pass control, symmetrisation, increment and covariance kernels, and
+//    their batched forms. The eigen-solver is in eig.hip.
 
 #include "riot_internal.h"
 
@@ -245,10 +246,11 @@ constexpr int kStageRows = 320;  // panel rows staged in LDS by the Cholesky
 
 // ---------------------------------------------------------------------------
 // Blocked Cholesky G + s I = L L^T (lower, column-major), one workgroup.
-// mode 0: s = 0; mode 1: s = shift_rel ||G||_F; mode 2: s = 0, restarted with the
-// shift on breakdown. Per 32-column panel: the diagonal block is factored in LDS,
-// the panel below by row-wise forward substitution, the trailing lower triangle
-// updated with FP64 MFMA (one wave per 32 x 32 tile).
+// mode 0: s = 0; mode 1: s = shift_rel ||G||_F; mode 2: s = 0, and a pivot that is not
+// above shift_rel ||G||_F is replaced by that value (modified Cholesky). Per 32-column
+// panel: the diagonal block is factored in LDS, the panel below by row-wise forward
+// substitution, the trailing lower triangle updated with FP64 MFMA (one wave per
+// 32 x 32 tile).
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kCholThreads)
@@ -487,16 +489,6 @@ __global__ void __launch_bounds__(64)
   }
 }
 
-// ---------------------------------------------------------------------------
-// Blocked inverse of a lower-triangular L (column-major): X = L^{-1}.
-// Diagonal 32 x 32 blocks are inverted by substitution in LDS; then, block row
-// by block row, X_ij = -X_ii (sum_{k=j}^{i-1} L_ik X_kj) with FP64 MFMA.
-// ---------------------------------------------------------------------------
-
-
-// ---------------------------------------------------------------------------
-// Cholesky: G + s I = R^T R, R upper triangular (right-looking).
-// ---------------------------------------------------------------------------
 
 
 

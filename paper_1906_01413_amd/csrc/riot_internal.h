@@ -217,11 +217,10 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
                     const double *B, int ldb, double beta, double *C, int ldc, double *partial,
                     int splitk, hipStream_t st, const int *run = nullptr);
 
-// Upper Cholesky factor R of G + s I (R^T R). mode 0: s = 0; mode 1: s = shift_rel * ||G||_F;
-// mode 2: s = 0 first, restarted with the shift on breakdown. flag[0] = 1 when the last
-// attempt breaks down (non-positive or non-finite pivot); shifts[0] counts shifted attempts.
-
-// Blocked Cholesky G + s I = L L^T (lower), same modes as launch_cholesky.
+// Blocked Cholesky G + s I = L L^T (lower, column-major). mode 0: s = 0; mode 1:
+// s = shift_rel * ||G||_F; mode 2: s = 0 with every pivot not above shift_rel * ||G||_F
+// replaced by that value (modflag[0] = 1 when one was). flag[0] = 1 on breakdown
+// (non-positive or non-finite pivot); shifts[0] counts shifted or modified factorizations.
 hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_rel, int mode,
                                int *flag, int *shifts, hipStream_t st, const int *run = nullptr,
                                int *modflag = nullptr);
@@ -254,13 +253,6 @@ hipError_t launch_cholqr_ctrl(int *cq, int pass_was_shifted, int *count, hipStre
 // X <- X L^{-T} in place (X rows x m, leading dimension ldx; L lower m x m).
 hipError_t launch_trsm_rlt(int rows, int m, double *X, int ldx, const double *L, hipStream_t st,
                            const int *run = nullptr);
-
-// Blocked inverse of a lower-triangular L.
-
-// Inverse of upper-triangular R (m x m).
-
-// Inverse of a general m x m matrix by Gauss-Jordan elimination with partial pivoting.
-// work holds 2*m*m doubles; flag[0] = 1 when a zero pivot is met.
 
 // K <- (K + K^T)/2 and asym[0] = ||K - K^T||_F / ||K||_F (before symmetrisation).
 // part: 128 doubles of scratch.

@@ -493,6 +493,101 @@ __global__ void __launch_bounds__(64)
 
 
 
+// ---------------------------------------------------------------------------
+// The same X <- X L^{-T} through the inverses of L's 32 x 32 diagonal blocks, so that
+// every step is a matrix-core product instead of a row-by-row substitution.
+// trsm_diag_inv_kernel: block b of L (rows and columns 32 b ...) staged in LDS; lane c
+// solves L_bb x = e_c by forward substitution; dinv + 1024 b holds L_bb^{-1}
+// column-major (ld 32), zero outside the block.
+// trsm_rlt_inv_kernel: four waves per 32-row block of X; per column block jb the waves
+// split the contraction X[:, <c0] L[jb, <c0]^T four ways, wave 0 adds the partial
+// products, forms B = X[:, jb] - (sum) in LDS and writes X[:, jb] = B L_jb^{-T}.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64)
+    trsm_diag_inv_kernel(int m, const double *__restrict__ L, double *__restrict__ dinv,
+                         const int *__restrict__ run) {
+  if (run && run[0] == 0) return;
+  __shared__ double Lb[32][33];
+  const int lane = threadIdx.x, b = blockIdx.x, c0 = 32 * b, nb = min(32, m - c0);
+  for (int idx = lane; idx < 32 * 32; idx += 64) {
+    const int i = idx & 31, t = idx >> 5;
+    Lb[i][t] = (i < nb && t <= i) ? L[(size_t)(c0 + t) * m + c0 + i] : 0.0;
+  }
+  __syncthreads();
+  if (lane >= 32) return;
+  const int c = lane;
+  double x[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    double acc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int t = 0; t < i; ++t) acc -= Lb[i][t] * x[t];  // x[t] = 0 for t < c
+    x[i] = (i >= c && i < nb) ? acc / Lb[i][i] : 0.0;
+  }
+  double *o = dinv + (size_t)b * 1024 + (size_t)c * 32;
+#pragma unroll
+  for (int i = 0; i < 32; ++i) o[i] = x[i];
+}
+
+__global__ void __launch_bounds__(256)
+    trsm_rlt_inv_kernel(int rows, int m, double *__restrict__ X, int ldx,
+                        const double *__restrict__ L, const double *__restrict__ dinv,
+                        const int *__restrict__ run) {
+  if (run && run[0] == 0) return;
+  __shared__ double red[4][32][33];
+  __shared__ double Bm[32 * 33];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lg = lane >> 4;
+  const int r0 = blockIdx.x * 32;
+  if (r0 >= rows) return;
+  const int nr = min(32, rows - r0);
+  for (int jb = 0; jb * 32 < m; ++jb) {
+    const int c0 = jb * 32, nc = min(32, m - c0);
+    // 1. wave w: X[r0:, k0:k1] L[c0:, k0:k1]^T over its quarter of [0, c0)
+    const int k0 = (c0 * wave) / 4, k1 = (c0 * (wave + 1)) / 4;
+    d4 acc[2][2];
+    zero_acc(acc);
+    if (k1 > k0)
+      wave_mma32<false, true>(X + r0 + (size_t)k0 * ldx, ldx, L + c0 + (size_t)k0 * m, m, k1 - k0,
+                              nr, nc, acc);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[wave][16 * rt + lg + 4 * r][16 * ct + li] = acc[rt][ct][r];
+    __syncthreads();
+    if (wave == 0) {
+      // 2. B = X[:, jb] - sum of the partial products, column-major in LDS
+      for (int idx = lane; idx < 32 * 32; idx += 64) {
+        const int i = idx & 31, j = idx >> 5;
+        double v = 0.0;
+        if (i < nr && j < nc)
+          v = X[(size_t)(c0 + j) * ldx + r0 + i] - (red[0][i][j] + red[1][i][j] + red[2][i][j] +
+                                                     red[3][i][j]);
+        Bm[i + 33 * j] = v;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // 3. X[:, jb] = B L_jb^{-T}
+      d4 q[2][2];
+      zero_acc(q);
+      wave_mma32<false, true>(Bm, 33, dinv + (size_t)jb * 1024, 32, nc, nr, nc, q);
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * rt + lg + 4 * r, col = 16 * ct + li;
+            if (row < nr && col < nc) X[(size_t)(c0 + col) * ldx + r0 + row] = q[rt][ct][r];
+          }
+    }
+    __syncthreads();
+  }
+}
+
 // K <- (K + K^T)/2 over the strict lower triangle, many workgroups; per-block partial
 // sums of ||K - K^T||^2 and ||K||^2 are reduced by symmetrize_norm_kernel in fixed order.
 __global__ void __launch_bounds__(256) symmetrize_kernel(int m, double *__restrict__ K,
@@ -703,6 +798,21 @@ hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_r
                                int *modflag) {
   hipLaunchKernelGGL(chol_blocked_kernel, dim3(1), dim3(kCholThreads), 0, st, m, G, L, shift_rel,
                      mode, flag, shifts, run, modflag, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_diag_inv(int m, const double *L, double *dinv, hipStream_t st,
+                                const int *run) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(trsm_diag_inv_kernel, dim3((m + 31) / 32), dim3(64), 0, st, m, L, dinv, run);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_rlt_inv(int rows, int m, double *X, int ldx, const double *L,
+                               const double *dinv, hipStream_t st, const int *run) {
+  if (rows <= 0 || m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(trsm_rlt_inv_kernel, dim3((rows + 31) / 32), dim3(256), 0, st, rows, m, X,
+                     ldx, L, dinv, run);
   return hipGetLastError();
 }
 

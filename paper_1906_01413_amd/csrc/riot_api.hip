@@ -19,6 +19,12 @@ namespace {
 
 constexpr int kSplitK = 16;
 
+// Scratch of the linear algebra: the split-K partial products of an m x m Gram matrix,
+// later reused for the inverses of the Cholesky factor's 32 x 32 diagonal blocks.
+inline size_t partial_doubles(size_t m) {
+  return std::max((size_t)kSplitK * std::max(m * m, m), (m + 31) / 32 * 1024);
+}
+
 // Bump allocator over the caller's workspace (base == nullptr: size only).
 struct Carver {
   char *base;
@@ -195,7 +201,7 @@ size_t carve(riot_handle &h, void *base) {
   h.K = c.take<double>(m2);
   h.Zs = c.take<double>(m2);
   h.sywork = c.take<double>(eig_work_doubles(mm));
-  h.partial = c.take<double>(std::max((size_t)kSplitK * m2, (size_t)kSplitK * mm));
+  h.partial = c.take<double>(partial_doubles(mm));
   h.cvec = c.take<double>(mm);
   h.scal = c.take<double>(16);
   h.cgv = c.take<double>((size_t)5 * n);
@@ -289,8 +295,10 @@ riot_status cholqr(const LaSpace &h, int rows, int m, const double *Xin, double 
                       kSplitK, st, cq));
     RIOT_HIP(launch_chol_blocked(m, h.G, h.R, srel, sh ? 1 : 2, h.flags + flag_idx, h.flags + 4,
                                  st, cq, cq + 2));
-    RIOT_HIP(launch_trsm_rlt(rows, m, Qout, rows, h.R, st, cq));
-    if (comp) RIOT_HIP(launch_trsm_rlt(mc, m, comp, mc, h.R, st, cq));
+    // the Gram's split-K buffer is free here: it holds the diagonal-block inverses
+    RIOT_HIP(launch_trsm_diag_inv(m, h.R, h.partial, st, cq));
+    RIOT_HIP(launch_trsm_rlt_inv(rows, m, Qout, rows, h.R, h.partial, st, cq));
+    if (comp) RIOT_HIP(launch_trsm_rlt_inv(mc, m, comp, mc, h.R, h.partial, st, cq));
     RIOT_HIP(launch_cholqr_ctrl(cq, sh ? 1 : 0, count, st));
   }
   return RIOT_OK;
@@ -1409,7 +1417,7 @@ size_t sketch_carve(riot_sketch &s, void *base) {
   la.K = c.take<double>(m2);
   la.Zs = c.take<double>(m2);
   la.sywork = c.take<double>(eig_work_doubles((int)m));
-  la.partial = c.take<double>((size_t)kSplitK * std::max(m2, m));
+  la.partial = c.take<double>(partial_doubles(m));
   la.cvec = c.take<double>(m);
   la.scal = c.take<double>(16);
   la.flags = c.take<int>(16);

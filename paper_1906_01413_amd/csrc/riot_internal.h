@@ -253,6 +253,12 @@ hipError_t launch_cholqr_ctrl(int *cq, int pass_was_shifted, int *count, hipStre
 // X <- X L^{-T} in place (X rows x m, leading dimension ldx; L lower m x m).
 hipError_t launch_trsm_rlt(int rows, int m, double *X, int ldx, const double *L, hipStream_t st,
                            const int *run = nullptr);
+// The same through the inverses of L's 32 x 32 diagonal blocks: launch_trsm_diag_inv
+// writes them to dinv (ceil(m / 32) * 1024 doubles), launch_trsm_rlt_inv uses them.
+hipError_t launch_trsm_diag_inv(int m, const double *L, double *dinv, hipStream_t st,
+                                const int *run = nullptr);
+hipError_t launch_trsm_rlt_inv(int rows, int m, double *X, int ldx, const double *L,
+                               const double *dinv, hipStream_t st, const int *run = nullptr);
 
 // K <- (K + K^T)/2 and asym[0] = ||K - K^T||_F / ||K||_F (before symmetrisation).
 // part: 128 doubles of scratch.

@@ -244,13 +244,21 @@ constexpr int kCholThreads = 512;
 constexpr int kPB = 32;  // panel width of the blocked factorizations
 constexpr int kStageRows = 320;  // panel rows staged in LDS by the Cholesky
 
+// Value of a double held by lane `src` of the wave (src uniform), via two v_readlane_b32.
+__device__ __forceinline__ double readlane_d(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // ---------------------------------------------------------------------------
 // Blocked Cholesky G + s I = L L^T (lower, column-major), one workgroup.
 // mode 0: s = 0; mode 1: s = shift_rel ||G||_F; mode 2: s = 0, and a pivot that is not
 // above shift_rel ||G||_F is replaced by that value (modified Cholesky). Per 32-column
-// panel: the diagonal block is factored in LDS, the panel below by row-wise forward
-// substitution, the trailing lower triangle updated with FP64 MFMA (one wave per
-// 32 x 32 tile).
+// panel: wave 0 factors the diagonal block in registers and inverts the factor; the
+// panel below is X = A21 L11^{-T} on the FP64 matrix cores; the trailing lower triangle
+// is updated with FP64 MFMA (one wave per 32 x 32 tile).
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kCholThreads)
@@ -265,7 +273,7 @@ __global__ void __launch_bounds__(kCholThreads)
   }
   if (run && run[0] == 0) return;
   __shared__ double D[kPB][kPB + 1];
-  __shared__ double Dinv[kPB];
+  __shared__ double Di[kPB][kPB + 1];  // Di[k][j] = (L11^{-1})[j][k]
   __shared__ double Pn[kPB * (kStageRows + 1)];
   __shared__ double red[16];
   __shared__ int bad;
@@ -302,8 +310,8 @@ __global__ void __launch_bounds__(kCholThreads)
       }
       __syncthreads();
       if (wave == 0) {
-        // lane i keeps row i of the diagonal block in registers; column k is broadcast
-        // through LDS once per step (independent reads, no read-modify-write chains)
+        // lane i keeps row i of the diagonal block in registers; the pivot and column k
+        // are broadcast from the owning lanes' registers (v_readlane), not through LDS
         const int lane = tid & 63;
         double r[kPB];
 #pragma unroll
@@ -312,7 +320,7 @@ __global__ void __launch_bounds__(kCholThreads)
 #pragma unroll
         for (int k = 0; k < kPB; ++k) {
           if (k < nb && !fail) {
-            double piv = __shfl(r[k], k, 64);
+            double piv = readlane_d(r[k], k);  // uniform: every lane sees the same pivot
             if (!isfinite(piv)) fail = true;
             if (floor_piv > 0.0 && !(piv > floor_piv)) {
               piv = floor_piv;
@@ -323,15 +331,12 @@ __global__ void __launch_bounds__(kCholThreads)
               const double rkk = sqrt(piv), rinv = 1.0 / rkk;
               if (lane > k) r[k] *= rinv;
               if (lane == k) r[k] = rkk;
-              if (lane < nb) D[lane][k] = r[k];  // column k for the other lanes
-              asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-              if (lane > k && lane < nb) {
-                const double lik = r[k];
+              const double lik = r[k];
 #pragma unroll
-                for (int j = k + 1; j < kPB; ++j)
-                  if (j <= lane) r[j] -= lik * D[j][k];
+              for (int j = k + 1; j < kPB; ++j) {
+                const double ljk = readlane_d(lik, j);
+                if (j <= lane && lane < nb) r[j] -= lik * ljk;
               }
-              asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
             }
           }
         }
@@ -340,7 +345,23 @@ __global__ void __launch_bounds__(kCholThreads)
 #pragma unroll
           for (int j = 0; j < kPB; ++j)
             if (j <= lane) D[lane][j] = r[j];
-          Dinv[lane] = 1.0 / D[lane][lane];
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        __builtin_amdgcn_wave_barrier();
+        // inverse of the factor: lane c solves L11 x = e_c (x in registers, L11 read as
+        // LDS broadcasts); Di[c][i] = (L11^{-1})[i][c]
+        if (!fail && lane < kPB) {
+          const int c = lane;
+          double x[kPB];
+#pragma unroll
+          for (int i = 0; i < kPB; ++i) {
+            double acc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int t = 0; t < i; ++t) acc -= D[i][t] * x[t];  // x[t] = 0 for t < c
+            x[i] = (i >= c && i < nb) ? acc / D[i][i] : 0.0;
+          }
+#pragma unroll
+          for (int i = 0; i < kPB; ++i) Di[c][i] = x[i];
         }
       }
       __syncthreads();
@@ -349,37 +370,48 @@ __global__ void __launch_bounds__(kCholThreads)
         const int i = idx % nb, j = idx / nb;
         if (i >= j) L[(size_t)(kb + j) * m + kb + i] = D[i][j];
       }
-      // 2. panel rows below: x L11^T = a  (forward substitution per row)
-      for (int i = kb + nb + tid; i < m; i += nt) {
-        // keep the LDS reads of the diagonal block inside the row loop (no hoisting)
-        asm volatile("" ::: "memory");
-        double x[kPB];
-#pragma unroll
-        for (int j = 0; j < kPB; ++j) {
-          if (j < nb) {
-            double a = L[(size_t)(kb + j) * m + i];
-#pragma unroll
-            for (int t = 0; t < j; ++t) a -= x[t] * D[j][t];
-            x[j] = a * Dinv[j];
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < kPB; ++j)
-          if (j < nb) L[(size_t)(kb + j) * m + i] = x[j];
-      }
-      __syncthreads();
-      // 3. trailing update A22 -= L21 L21^T on the lower 32 x 32 tiles; the panel
-      //    L21 is staged in LDS when it fits (MFMA operands then come from LDS)
+      // 2. panel rows below: X = A21 L11^{-T}, one 32-row MFMA tile per wave (the panel is
+      //    staged in LDS first when it fits; the result goes to L and to the staged copy)
       const int r0 = kb + nb;
       const int prow = m - r0;
       const bool staged = prow <= kStageRows;
       if (staged) {
-        for (int idx = tid; idx < prow * nb; idx += nt) {
-          const int i = idx % prow, j = idx / prow;
-          Pn[j * (kStageRows + 1) + i] = L[(size_t)(kb + j) * m + r0 + i];
+        for (int jj = wave; jj < nb; jj += nwaves)
+          for (int ii = tid & 63; ii < prow; ii += 64)
+            Pn[jj * (kStageRows + 1) + ii] = L[(size_t)(kb + jj) * m + r0 + ii];
+      }
+      __syncthreads();
+      {
+        const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
+        const int npt = (prow + 31) / 32;
+        for (int I = wave; I < npt; I += nwaves) {
+          const int i0 = 32 * I;
+          d4 acc[2][2];
+          zero_acc(acc);
+          if (staged)
+            wave_mma32<false, true>(Pn + i0, kStageRows + 1, &Di[0][0], kPB + 1, nb, prow - i0,
+                                    nb, acc);
+          else
+            wave_mma32<false, true>(L + (size_t)kb * m + r0 + i0, m, &Di[0][0], kPB + 1, nb,
+                                    prow - i0, nb, acc);
+          // the MFMAs consumed every operand load of this wave's rows: overwrite them
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+              for (int rr = 0; rr < 4; ++rr) {
+                const int row = i0 + 16 * rt + lg + 4 * rr, col = 16 * ct + li;
+                if (row < prow && col < nb) {
+                  L[(size_t)(kb + col) * m + r0 + row] = acc[rt][ct][rr];
+                  if (staged) Pn[col * (kStageRows + 1) + row] = acc[rt][ct][rr];
+                }
+              }
         }
       }
       __syncthreads();
+      // 3. trailing update A22 -= L21 L21^T on the lower 32 x 32 tiles (MFMA operands
+      //    from the staged panel when it fits)
       const int nt32 = (prow + 31) / 32;
       const int ntiles = nt32 * (nt32 + 1) / 2;
       for (int t = wave; t < ntiles; t += nwaves) {

@@ -10,8 +10,9 @@
 // adjoint need the base emissions only, never a stored trajectory.
 //
 // Layout: fields [member][y][x] (x fastest); controls [member][time block][by][bx].
-// Each step is one launch over (tile, member): a 64 x 4 tile of cells plus a one-cell
-// halo is staged in LDS, so every row segment is read as one coalesced 512-byte run.
+// Each step is one launch over (tile, member): a 64 x 16 tile of cells plus a one-cell
+// halo is staged in LDS, so every row segment is read as one coalesced 512-byte run; each
+// thread computes four rows of the tile.
 
 #include <algorithm>
 #include <cmath>
@@ -23,7 +24,9 @@
 namespace riot {
 namespace {
 
-constexpr int kTX = 64, kTY = 4;  // cell tile (threads = kTX * kTY)
+// cell tile kTX x kTY, threads kTX x kWY; thread (lx, ly) owns rows ly + kWY r, r < kRY
+constexpr int kTX = 64, kWY = 4, kRY = 4, kTY = kWY * kRY;
+constexpr int kThreads = kTX * kWY;
 constexpr int kHX = kTX + 2, kHY = kTY + 2;
 
 struct TracerView {
@@ -37,7 +40,7 @@ __device__ __forceinline__ int wrap(int i, int N) { return i < 0 ? i + N : (i >=
 // Stage the tile of `f` with its halo in LDS (row-major, kHY x kHX).
 __device__ __forceinline__ void stage_tile(const double *__restrict__ f, int N, int x0, int y0,
                                            double *t) {
-  for (int k = threadIdx.x; k < kHX * kHY; k += kTX * kTY) {
+  for (int k = threadIdx.x; k < kHX * kHY; k += kThreads) {
     const int ty = k / kHX, tx = k - ty * kHX;
     t[k] = f[(size_t)wrap(y0 + ty - 1, N) * N + wrap(x0 + tx - 1, N)];
   }
@@ -45,7 +48,7 @@ __device__ __forceinline__ void stage_tile(const double *__restrict__ f, int N, 
 
 // out = A in + dt W * up(bv): one step of the forward model (W = E, bv = exp(s_tau)) or of
 // the tangent-linear model (W = E exp(up(s_b,tau)), bv = ds_tau). in may be nullptr (zero).
-__global__ void __launch_bounds__(kTX *kTY)
+__global__ void __launch_bounds__(kThreads)
     tracer_step_kernel(TracerView tv, const double *__restrict__ in, double *__restrict__ out,
                        const double *__restrict__ W, const double *__restrict__ bv,
                        long long bv_stride) {
@@ -54,21 +57,29 @@ __global__ void __launch_bounds__(kTX *kTY)
   const size_t NN = (size_t)N * N;
   const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, mem = blockIdx.z;
   const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
-  const int x = x0 + lx, y = y0 + ly;
-  double acc = 0.0;
+  const int x = x0 + lx;
   if (in) {
     stage_tile(in + mem * NN, N, x0, y0, t);
     __syncthreads();
-    const int c = (ly + 1) * kHX + lx + 1;
-    acc = tv.a0[y] * t[c] + tv.aW[y] * t[c - 1] + tv.aS * t[c - kHX] + tv.aE * t[c + 1] +
-          tv.aN * t[c + kHX];
   }
-  const double e = bv[mem * bv_stride + (size_t)(y / tv.block) * tv.Nb + x / tv.block];
-  out[mem * NN + (size_t)y * N + x] = acc + tv.dt * W[(size_t)y * N + x] * e;
+  const double *bvm = bv + mem * bv_stride;
+#pragma unroll
+  for (int r = 0; r < kRY; ++r) {
+    const int yl = ly + kWY * r, y = y0 + yl;
+    double acc = 0.0;
+    if (in) {
+      const int c = (yl + 1) * kHX + lx + 1;
+      acc = tv.a0[y] * t[c] + tv.aW[y] * t[c - 1] + tv.aS * t[c - kHX] + tv.aE * t[c + 1] +
+            tv.aN * t[c + kHX];
+    }
+    const double e = bvm[(size_t)(y / tv.block) * tv.Nb + x / tv.block];
+    out[mem * NN + (size_t)y * N + x] = acc + tv.dt * W[(size_t)y * N + x] * e;
+  }
 }
 
-// lam_out = A^T lam_in, and gS_tau += down(dt W * lam_in) per 4 x 4 block (fixed order).
-__global__ void __launch_bounds__(kTX *kTY)
+// lam_out = A^T lam_in, and gS_tau += down(dt W * lam_in) per block x block cells
+// (each control block of the tile summed row by row by one thread: fixed order).
+__global__ void __launch_bounds__(kThreads)
     tracer_adjoint_kernel(TracerView tv, const double *__restrict__ lam_in,
                           double *__restrict__ lam_out, const double *__restrict__ W,
                           double *__restrict__ gS, long long gS_stride) {
@@ -78,21 +89,24 @@ __global__ void __launch_bounds__(kTX *kTY)
   const size_t NN = (size_t)N * N;
   const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, mem = blockIdx.z;
   const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
-  const int x = x0 + lx, y = y0 + ly;
+  const int x = x0 + lx;
   stage_tile(lam_in + mem * NN, N, x0, y0, t);
   __syncthreads();
-  const int c = (ly + 1) * kHX + lx + 1;
-  if (lam_out)
-    lam_out[mem * NN + (size_t)y * N + x] = tv.a0[y] * t[c] + tv.aW[y] * t[c + 1] +
-                                            tv.aS * t[c + kHX] + tv.aE * t[c - 1] +
-                                            tv.aN * t[c - kHX];
-  w[ly][lx] = tv.dt * W[(size_t)y * N + x] * t[c];
+#pragma unroll
+  for (int r = 0; r < kRY; ++r) {
+    const int yl = ly + kWY * r, y = y0 + yl;
+    const int c = (yl + 1) * kHX + lx + 1;
+    if (lam_out)
+      lam_out[mem * NN + (size_t)y * N + x] = tv.a0[y] * t[c] + tv.aW[y] * t[c + 1] +
+                                              tv.aS * t[c + kHX] + tv.aE * t[c - 1] +
+                                              tv.aN * t[c - kHX];
+    w[yl][lx] = tv.dt * W[(size_t)y * N + x] * t[c];
+  }
   __syncthreads();
-  // one thread per control block of the tile sums its cells row by row
   const int b = tv.block;
   const int nbx = kTX / b, nby = kTY / b;
-  if ((int)threadIdx.x < nbx * nby) {
-    const int bxl = threadIdx.x % nbx, byl = threadIdx.x / nbx;
+  for (int cb = threadIdx.x; cb < nbx * nby; cb += kThreads) {
+    const int bxl = cb % nbx, byl = cb / nbx;
     double s = 0.0;
     for (int r = 0; r < b; ++r)
       for (int q = 0; q < b; ++q) s += w[byl * b + r][bxl * b + q];
@@ -298,7 +312,7 @@ riot_status tracer_forward_sweep(riot_tracer *h, int m, const double *Wfield, lo
   for (int t = 0; t < d.nsteps; ++t) {
     const int tau = t / tv.spb;
     double *next = bufs[t & 1];
-    hipLaunchKernelGGL(riot::tracer_step_kernel, grid, dim3(riot::kTX * riot::kTY), 0, h->st, tv,
+    hipLaunchKernelGGL(riot::tracer_step_kernel, grid, dim3(riot::kThreads), 0, h->st, tv,
                        cur, next, Wfield + Wstride * tau, bv + (size_t)tau * Nbb, bv_stride);
     TR_HIP(hipGetLastError());
     // observations of step t + 1 (the state just computed)
@@ -338,7 +352,7 @@ riot_status tracer_adjoint_sweep(riot_tracer *h, int m, const double *f, double 
     }
     // lam is the adjoint of c_t, produced by step t-1 with emissions of block tau(t-1)
     const int tau = (t - 1) / tv.spb;
-    hipLaunchKernelGGL(riot::tracer_adjoint_kernel, grid, dim3(riot::kTX * riot::kTY), 0, h->st,
+    hipLaunchKernelGGL(riot::tracer_adjoint_kernel, grid, dim3(riot::kThreads), 0, h->st,
                        tv, lam, t > 1 ? other : nullptr, h->Wb + NN * tau, gS + (size_t)tau * Nbb,
                        (long long)h->ncontrol);
     TR_HIP(hipGetLastError());

@@ -115,6 +115,150 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two steps per launch (temporal blocking): the input tile is staged with a two-cell halo,
+// the intermediate field is computed on the tile plus a one-cell ring and kept in LDS,
+// and only the second step's field goes back to memory, so each field is read and
+// written once per two steps. Observations of the intermediate state are taken (forward)
+// or injected (adjoint) inside the launch.
+// ---------------------------------------------------------------------------
+constexpr int kGX = kTX + 4, kGY = kTY + 4;  // input tile with a two-cell halo
+
+__device__ __forceinline__ void stage_tile2(const double *__restrict__ f, int N, int x0, int y0,
+                                            double *t) {
+  for (int k = threadIdx.x; k < kGX * kGY; k += kThreads) {
+    const int ty = k / kGX, tx = k - ty * kGX;
+    t[k] = f[(size_t)wrap(y0 + ty - 2, N) * N + wrap(x0 + tx - 2, N)];
+  }
+}
+
+// out = A (A in + dt W0 up(bv0)) + dt W1 up(bv1) (steps t and t + 1; in may be nullptr);
+// obs[mem nobs + orig[o]] = intermediate field at cell[o] for o in [beg, end).
+__global__ void __launch_bounds__(kThreads)
+    tracer_step2_kernel(TracerView tv, const double *__restrict__ in, double *__restrict__ out,
+                        const double *__restrict__ W0, const double *__restrict__ bv0,
+                        const double *__restrict__ W1, const double *__restrict__ bv1,
+                        long long bv_stride, int beg, int end, const int *__restrict__ cell,
+                        const int *__restrict__ orig, int nobs, double *__restrict__ obs) {
+  __shared__ double t0[kGX * kGY];
+  __shared__ double t1[kHX * kHY];
+  const int N = tv.N;
+  const size_t NN = (size_t)N * N;
+  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, mem = blockIdx.z;
+  if (in) {
+    stage_tile2(in + mem * NN, N, x0, y0, t0);
+    __syncthreads();
+  }
+  const double *b0m = bv0 + mem * bv_stride, *b1m = bv1 + mem * bv_stride;
+  // intermediate field on the tile and a one-cell ring (kHY x kHX, wrapped coordinates)
+  for (int k = threadIdx.x; k < kHX * kHY; k += kThreads) {
+    const int ry = k / kHX, rx = k - ry * kHX;
+    const int y = wrap(y0 + ry - 1, N), x = wrap(x0 + rx - 1, N);
+    double acc = 0.0;
+    if (in) {
+      const int c = (ry + 1) * kGX + rx + 1;
+      acc = tv.a0[y] * t0[c] + tv.aW[y] * t0[c - 1] + tv.aS * t0[c - kGX] + tv.aE * t0[c + 1] +
+            tv.aN * t0[c + kGX];
+    }
+    t1[k] = acc + tv.dt * W0[(size_t)y * N + x] * b0m[(size_t)(y / tv.block) * tv.Nb + x / tv.block];
+  }
+  __syncthreads();
+  if (obs) {
+    for (int o = beg + (int)threadIdx.x; o < end; o += kThreads) {
+      const int cy = cell[o] / N, cx = cell[o] - cy * N;
+      if (cy >= y0 && cy < y0 + kTY && cx >= x0 && cx < x0 + kTX)
+        obs[(size_t)mem * nobs + orig[o]] = t1[(cy - y0 + 1) * kHX + cx - x0 + 1];
+    }
+  }
+  const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
+  const int x = x0 + lx;
+#pragma unroll
+  for (int r = 0; r < kRY; ++r) {
+    const int yl = ly + kWY * r, y = y0 + yl;
+    const int c = (yl + 1) * kHX + lx + 1;
+    const double acc = tv.a0[y] * t1[c] + tv.aW[y] * t1[c - 1] + tv.aS * t1[c - kHX] +
+                       tv.aE * t1[c + 1] + tv.aN * t1[c + kHX];
+    out[mem * NN + (size_t)y * N + x] =
+        acc + tv.dt * W1[(size_t)y * N + x] * b1m[(size_t)(y / tv.block) * tv.Nb + x / tv.block];
+  }
+}
+
+// Adjoint of two steps (states t -> t-1 -> t-2): lam1 = A^T lam_in on the tile and a ring,
+// gS1 += down(dt W1 lam_in) (step t-1's emissions), the observation forcing of state t-1
+// added to lam1 (unique cells u in [ubeg, uend)), lam_out = A^T lam1 (may be nullptr),
+// gS0 += down(dt W0 lam1) (step t-2's emissions). Block sums in a fixed order. gS1 and gS0
+// are the same block when both steps use one control time block, so they may alias.
+__global__ void __launch_bounds__(kThreads)
+    tracer_adjoint2_kernel(TracerView tv, const double *__restrict__ lam_in,
+                           double *__restrict__ lam_out, const double *__restrict__ W1,
+                           const double *__restrict__ W0, double *gS1, double *gS0,
+                           long long gS_stride, int ubeg, int uend,
+                           const int *__restrict__ ucell, const int *__restrict__ uptr,
+                           const int *__restrict__ orig, const double *__restrict__ f, int nobs) {
+  __shared__ double t0[kGX * kGY];
+  __shared__ double t1[kHX * kHY];
+  __shared__ double w1[kTY][kTX];
+  __shared__ double w0[kTY][kTX];
+  const int N = tv.N;
+  const size_t NN = (size_t)N * N;
+  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, mem = blockIdx.z;
+  stage_tile2(lam_in + mem * NN, N, x0, y0, t0);
+  __syncthreads();
+  for (int k = threadIdx.x; k < kHX * kHY; k += kThreads) {
+    const int ry = k / kHX, rx = k - ry * kHX;
+    const int y = wrap(y0 + ry - 1, N);
+    const int c = (ry + 1) * kGX + rx + 1;
+    t1[k] = tv.a0[y] * t0[c] + tv.aW[y] * t0[c + 1] + tv.aS * t0[c + kGX] + tv.aE * t0[c - 1] +
+            tv.aN * t0[c - kGX];
+  }
+  const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
+  const int x = x0 + lx;
+#pragma unroll
+  for (int r = 0; r < kRY; ++r) {
+    const int yl = ly + kWY * r, y = y0 + yl;
+    w1[yl][lx] = tv.dt * W1[(size_t)y * N + x] * t0[(yl + 2) * kGX + lx + 2];
+  }
+  __syncthreads();
+  // a cell may sit at two ring positions when the ring spans the whole period (N = kTX):
+  // the forcing goes to every copy
+  for (int u = ubeg + (int)threadIdx.x; u < uend; u += kThreads) {
+    const int cy = ucell[u] / N, cx = ucell[u] - cy * N;
+    const int ry0 = wrap(cy - (y0 - 1), N), rx0 = wrap(cx - (x0 - 1), N);
+    if (ry0 < kHY && rx0 < kHX) {
+      double sum = 0.0;
+      for (int k = uptr[u]; k < uptr[u + 1]; ++k) sum += f[(size_t)mem * nobs + orig[k]];
+      for (int ry = ry0; ry < kHY; ry += N)
+        for (int rx = rx0; rx < kHX; rx += N) t1[ry * kHX + rx] += sum;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRY; ++r) {
+    const int yl = ly + kWY * r, y = y0 + yl;
+    const int c = (yl + 1) * kHX + lx + 1;
+    if (lam_out)
+      lam_out[mem * NN + (size_t)y * N + x] = tv.a0[y] * t1[c] + tv.aW[y] * t1[c + 1] +
+                                              tv.aS * t1[c + kHX] + tv.aE * t1[c - 1] +
+                                              tv.aN * t1[c - kHX];
+    w0[yl][lx] = tv.dt * W0[(size_t)y * N + x] * t1[c];
+  }
+  __syncthreads();
+  const int b = tv.block;
+  const int nbx = kTX / b, nby = kTY / b;
+  for (int cb = threadIdx.x; cb < nbx * nby; cb += kThreads) {
+    const int bxl = cb % nbx, byl = cb / nbx;
+    double s1 = 0.0, s0 = 0.0;
+    for (int r = 0; r < b; ++r)
+      for (int q = 0; q < b; ++q) {
+        s1 += w1[byl * b + r][bxl * b + q];
+        s0 += w0[byl * b + r][bxl * b + q];
+      }
+    const size_t off = (size_t)((y0 / b) + byl) * tv.Nb + (x0 / b) + bxl;
+    gS1[mem * gS_stride + off] += s1;
+    gS0[mem * gS_stride + off] += s0;
+  }
+}
+
 // Observation samples after a step: out[orig[o] + mem nobs] = f[y_o, x_o] for the step's o.
 __global__ void tracer_sample_kernel(int N, int beg, int end, const int *__restrict__ cell,
                                      const int *__restrict__ orig, const double *__restrict__ f,
@@ -305,26 +449,42 @@ riot_status tracer_forward_sweep(riot_tracer *h, int m, const double *Wfield, lo
                                  const double *bv, long long bv_stride, double *obs) {
   const riot_tracer_desc &d = h->d;
   const TracerView &tv = h->tv;
-  const size_t NN = (size_t)d.N * d.N;
   const dim3 grid(d.N / riot::kTX, d.N / riot::kTY, m);
   double *cur = nullptr, *bufs[2] = {h->F0, h->F1};
   const int Nbb = h->Nb * h->Nb;
-  for (int t = 0; t < d.nsteps; ++t) {
-    const int tau = t / tv.spb;
-    double *next = bufs[t & 1];
-    hipLaunchKernelGGL(riot::tracer_step_kernel, grid, dim3(riot::kThreads), 0, h->st, tv,
-                       cur, next, Wfield + Wstride * tau, bv + (size_t)tau * Nbb, bv_stride);
-    TR_HIP(hipGetLastError());
-    // observations of step t + 1 (the state just computed)
-    const int beg = h->obs_off[t + 2], end = h->obs_off[t + 3];
+  int nb = 0;  // buffers written so far
+  // observations of state s (the field after step s - 1) are [obs_off[s + 1], obs_off[s + 2])
+  auto sample = [&](int s, const double *f) -> riot_status {
+    const int beg = h->obs_off[s + 1], end = h->obs_off[s + 2];
     if (end > beg && obs) {
       hipLaunchKernelGGL(riot::tracer_sample_kernel, dim3(riot::blocks_for(end - beg), m),
-                         dim3(256), 0, h->st, d.N, beg, end, h->cell, h->orig, next, d.nobs, obs);
+                         dim3(256), 0, h->st, d.N, beg, end, h->cell, h->orig, f, d.nobs, obs);
       TR_HIP(hipGetLastError());
     }
+    return RIOT_OK;
+  };
+  int t = 0;
+  for (; t + 1 < d.nsteps; t += 2) {  // steps t and t + 1 in one launch
+    const int tau0 = t / tv.spb, tau1 = (t + 1) / tv.spb;
+    double *next = bufs[(nb++) & 1];
+    hipLaunchKernelGGL(riot::tracer_step2_kernel, grid, dim3(riot::kThreads), 0, h->st, tv, cur,
+                       next, Wfield + Wstride * tau0, bv + (size_t)tau0 * Nbb,
+                       Wfield + Wstride * tau1, bv + (size_t)tau1 * Nbb, bv_stride,
+                       h->obs_off[t + 2], h->obs_off[t + 3], h->cell, h->orig, d.nobs, obs);
+    TR_HIP(hipGetLastError());
+    riot_status rs = sample(t + 2, next);
+    if (rs != RIOT_OK) return rs;
     cur = next;
   }
-  (void)NN;
+  if (t < d.nsteps) {  // odd number of steps: the last one alone
+    const int tau = t / tv.spb;
+    double *next = bufs[(nb++) & 1];
+    hipLaunchKernelGGL(riot::tracer_step_kernel, grid, dim3(riot::kThreads), 0, h->st, tv, cur,
+                       next, Wfield + Wstride * tau, bv + (size_t)tau * Nbb, bv_stride);
+    TR_HIP(hipGetLastError());
+    riot_status rs = sample(t + 1, next);
+    if (rs != RIOT_OK) return rs;
+  }
   return RIOT_OK;
 }
 
@@ -342,7 +502,8 @@ riot_status tracer_adjoint_sweep(riot_tracer *h, int m, const double *f, double 
   TR_HIP(hipGetLastError());
   double *lam = h->F0, *other = h->F1;
   const int Nbb = h->Nb * h->Nb;
-  for (int t = d.nsteps; t >= 1; --t) {
+  // forcing of state t: unique cells [u_off[t], u_off[t + 1])
+  auto inject = [&](int t) -> riot_status {
     const int beg = h->u_off[t], end = h->u_off[t + 1];
     if (end > beg) {
       hipLaunchKernelGGL(riot::tracer_inject_kernel, dim3(riot::blocks_for(end - beg), m),
@@ -350,13 +511,26 @@ riot_status tracer_adjoint_sweep(riot_tracer *h, int m, const double *f, double 
                          d.nobs, lam);
       TR_HIP(hipGetLastError());
     }
-    // lam is the adjoint of c_t, produced by step t-1 with emissions of block tau(t-1)
-    const int tau = (t - 1) / tv.spb;
-    hipLaunchKernelGGL(riot::tracer_adjoint_kernel, grid, dim3(riot::kThreads), 0, h->st,
-                       tv, lam, t > 1 ? other : nullptr, h->Wb + NN * tau, gS + (size_t)tau * Nbb,
-                       (long long)h->ncontrol);
+    return RIOT_OK;
+  };
+  int t = d.nsteps;
+  for (; t >= 2; t -= 2) {  // states t -> t-1 -> t-2 in one launch
+    riot_status rs = inject(t);
+    if (rs != RIOT_OK) return rs;
+    const int tau1 = (t - 1) / tv.spb, tau0 = (t - 2) / tv.spb;
+    hipLaunchKernelGGL(riot::tracer_adjoint2_kernel, grid, dim3(riot::kThreads), 0, h->st, tv,
+                       lam, t > 2 ? other : nullptr, h->Wb + NN * tau1, h->Wb + NN * tau0,
+                       gS + (size_t)tau1 * Nbb, gS + (size_t)tau0 * Nbb, (long long)h->ncontrol,
+                       h->u_off[t - 1], h->u_off[t], h->ucell, h->uptr, h->orig, f, d.nobs);
     TR_HIP(hipGetLastError());
     std::swap(lam, other);
+  }
+  if (t == 1) {  // odd number of steps: the first one alone
+    riot_status rs = inject(1);
+    if (rs != RIOT_OK) return rs;
+    hipLaunchKernelGGL(riot::tracer_adjoint_kernel, grid, dim3(riot::kThreads), 0, h->st, tv, lam,
+                       nullptr, h->Wb, gS, (long long)h->ncontrol);
+    TR_HIP(hipGetLastError());
   }
   return RIOT_OK;
 }

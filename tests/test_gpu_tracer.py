@@ -47,6 +47,27 @@ def test_tracer_forward_tangent_adjoint_match_oracle(small):
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
+def test_tracer_odd_window_and_block_change_inside_a_step_pair():
+    """21 steps in 3 time blocks of 7: the sweeps run steps in pairs with one step left
+    over, and the pair (6, 7) spans two control blocks."""
+    d = advdiff_draws("ad2_n64", 5)
+    d["grid"] = dict(d["grid"], T=21, ntb=3)
+    keep = d["obs_t"] <= 21
+    for key in ("obs_t", "obs_y", "obs_x", "obs_noise"):
+        d[key] = d[key][keep]
+    g = advdiff.Grid(**d["grid"])
+    d["xi"] = np.random.default_rng(7).standard_normal(g.ncontrol)
+    p = advdiff.realize(d)
+    tr = _tracer(p, m_max=3)
+    rng = np.random.default_rng(8)
+    s0 = 0.3 * rng.standard_normal(g.ncontrol)
+    assert rel(to_np(tr.forward(s0)), advdiff.forward(g, p.E, s0, p.obs)[0]) < 1e-12
+    dS = rng.standard_normal((g.ncontrol, 3))
+    assert rel(to_np(tr.tangent(dS)), advdiff.tangent(g, p.E, s0, p.obs, dS)) < 1e-12
+    f = rng.standard_normal((p.obs.t.size, 3))
+    assert rel(to_np(tr.adjoint(f)), advdiff.adjoint(g, p.E, s0, p.obs, f)) < 1e-12
+
+
 def test_tracer_prior_root_hessian_gradient_match_oracle(small):
     p, tr = small
     g = p.grid

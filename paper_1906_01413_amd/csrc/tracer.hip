@@ -30,7 +30,7 @@ constexpr int kThreads = kTX * kWY;
 constexpr int kHX = kTX + 2, kHY = kTY + 2;
 
 struct TracerView {
-  int N, T, block, ntb, Nb, spb;  // spb: steps per time block
+  int N, T, block, bshift, ntb, Nb, spb;  // block = 1 << bshift; spb: steps per time block
   double dt, aS, aE, aN;
   const double *a0, *aW;          // [N] row coefficients
 };
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(kThreads)
       acc = tv.a0[y] * t[c] + tv.aW[y] * t[c - 1] + tv.aS * t[c - kHX] + tv.aE * t[c + 1] +
             tv.aN * t[c + kHX];
     }
-    const double e = bvm[(size_t)(y / tv.block) * tv.Nb + x / tv.block];
+    const double e = bvm[(size_t)(y >> tv.bshift) * tv.Nb + (x >> tv.bshift)];
     out[mem * NN + (size_t)y * N + x] = acc + tv.dt * W[(size_t)y * N + x] * e;
   }
 }
@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(kThreads)
       acc = tv.a0[y] * t0[c] + tv.aW[y] * t0[c - 1] + tv.aS * t0[c - kGX] + tv.aE * t0[c + 1] +
             tv.aN * t0[c + kGX];
     }
-    t1[k] = acc + tv.dt * W0[(size_t)y * N + x] * b0m[(size_t)(y / tv.block) * tv.Nb + x / tv.block];
+    t1[k] = acc + tv.dt * W0[(size_t)y * N + x] * b0m[(size_t)(y >> tv.bshift) * tv.Nb + (x >> tv.bshift)];
   }
   __syncthreads();
   if (obs) {
@@ -179,15 +179,42 @@ __global__ void __launch_bounds__(kThreads)
     const double acc = tv.a0[y] * t1[c] + tv.aW[y] * t1[c - 1] + tv.aS * t1[c - kHX] +
                        tv.aE * t1[c + 1] + tv.aN * t1[c + kHX];
     out[mem * NN + (size_t)y * N + x] =
-        acc + tv.dt * W1[(size_t)y * N + x] * b1m[(size_t)(y / tv.block) * tv.Nb + x / tv.block];
+        acc + tv.dt * W1[(size_t)y * N + x] * b1m[(size_t)(y >> tv.bshift) * tv.Nb + (x >> tv.bshift)];
   }
 }
 
 // Adjoint of two steps (states t -> t-1 -> t-2): lam1 = A^T lam_in on the tile and a ring,
 // gS1 += down(dt W1 lam_in) (step t-1's emissions), the observation forcing of state t-1
 // added to lam1 (unique cells u in [ubeg, uend)), lam_out = A^T lam1 (may be nullptr),
-// gS0 += down(dt W0 lam1) (step t-2's emissions). Block sums in a fixed order. gS1 and gS0
-// are the same block when both steps use one control time block, so they may alias.
+// gS0 += down(dt W0 lam1) (step t-2's emissions). gS1 and gS0 are the same block when both
+// steps use one control time block, so they may alias.
+//
+// Here thread (lx, ly) owns the kRY consecutive rows kRY ly + r, so a control block
+// (side 1, 2 or 4) has all its rows in one thread: its rows are summed in registers and its
+// columns across b adjacent lanes of the wave by shuffles (a fixed tree, so the sums are
+// deterministic), with no LDS for the block sums.
+__device__ __forceinline__ void block_sums_add(double v[kRY], int b, int lx, double *g,
+                                               int Nb) {
+  // g points at the control of this thread's first row and column, (y / b, x / b)
+  if (b == 1) {
+#pragma unroll
+    for (int r = 0; r < kRY; ++r) g[(size_t)r * Nb] += v[r];
+  } else if (b == 2) {
+    double s0 = v[0] + v[1], s1 = v[2] + v[3];
+    s0 += __shfl_xor(s0, 1);
+    s1 += __shfl_xor(s1, 1);
+    if ((lx & 1) == 0) {
+      g[0] += s0;
+      g[Nb] += s1;
+    }
+  } else {
+    double s = (v[0] + v[1]) + (v[2] + v[3]);
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    if ((lx & 3) == 0) g[0] += s;
+  }
+}
+
 __global__ void __launch_bounds__(kThreads)
     tracer_adjoint2_kernel(TracerView tv, const double *__restrict__ lam_in,
                            double *__restrict__ lam_out, const double *__restrict__ W1,
@@ -197,8 +224,6 @@ __global__ void __launch_bounds__(kThreads)
                            const int *__restrict__ orig, const double *__restrict__ f, int nobs) {
   __shared__ double t0[kGX * kGY];
   __shared__ double t1[kHX * kHY];
-  __shared__ double w1[kTY][kTX];
-  __shared__ double w0[kTY][kTX];
   const int N = tv.N;
   const size_t NN = (size_t)N * N;
   const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, mem = blockIdx.z;
@@ -212,12 +237,11 @@ __global__ void __launch_bounds__(kThreads)
             tv.aN * t0[c - kGX];
   }
   const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
-  const int x = x0 + lx;
+  const int x = x0 + lx, yb = y0 + kRY * ly;  // this thread's first row
+  double v[kRY];
 #pragma unroll
-  for (int r = 0; r < kRY; ++r) {
-    const int yl = ly + kWY * r, y = y0 + yl;
-    w1[yl][lx] = tv.dt * W1[(size_t)y * N + x] * t0[(yl + 2) * kGX + lx + 2];
-  }
+  for (int r = 0; r < kRY; ++r)
+    v[r] = tv.dt * W1[(size_t)(yb + r) * N + x] * t0[(kRY * ly + r + 2) * kGX + lx + 2];
   __syncthreads();
   // a cell may sit at two ring positions when the ring spans the whole period (N = kTX):
   // the forcing goes to every copy
@@ -231,32 +255,21 @@ __global__ void __launch_bounds__(kThreads)
         for (int rx = rx0; rx < kHX; rx += N) t1[ry * kHX + rx] += sum;
     }
   }
+  const int sh = tv.bshift;
+  const size_t goff = (size_t)mem * gS_stride + (size_t)(yb >> sh) * tv.Nb + (x >> sh);
+  block_sums_add(v, tv.block, lx, gS1 + goff, tv.Nb);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRY; ++r) {
-    const int yl = ly + kWY * r, y = y0 + yl;
-    const int c = (yl + 1) * kHX + lx + 1;
+    const int y = yb + r;
+    const int c = (kRY * ly + r + 1) * kHX + lx + 1;
     if (lam_out)
       lam_out[mem * NN + (size_t)y * N + x] = tv.a0[y] * t1[c] + tv.aW[y] * t1[c + 1] +
                                               tv.aS * t1[c + kHX] + tv.aE * t1[c - 1] +
                                               tv.aN * t1[c - kHX];
-    w0[yl][lx] = tv.dt * W0[(size_t)y * N + x] * t1[c];
+    v[r] = tv.dt * W0[(size_t)y * N + x] * t1[c];
   }
-  __syncthreads();
-  const int b = tv.block;
-  const int nbx = kTX / b, nby = kTY / b;
-  for (int cb = threadIdx.x; cb < nbx * nby; cb += kThreads) {
-    const int bxl = cb % nbx, byl = cb / nbx;
-    double s1 = 0.0, s0 = 0.0;
-    for (int r = 0; r < b; ++r)
-      for (int q = 0; q < b; ++q) {
-        s1 += w1[byl * b + r][bxl * b + q];
-        s0 += w0[byl * b + r][bxl * b + q];
-      }
-    const size_t off = (size_t)((y0 / b) + byl) * tv.Nb + (x0 / b) + bxl;
-    gS1[mem * gS_stride + off] += s1;
-    gS0[mem * gS_stride + off] += s0;
-  }
+  block_sums_add(v, tv.block, lx, gS0 + goff, tv.Nb);
 }
 
 // Observation samples after a step: out[orig[o] + mem nobs] = f[y_o, x_o] for the step's o.
@@ -297,7 +310,7 @@ __global__ void base_emission_kernel(TracerView tv, const double *__restrict__ E
   const int tau = (int)(i / NN);
   const size_t c = i - (size_t)tau * NN;
   const int y = (int)(c / tv.N), x = (int)(c - (size_t)y * tv.N);
-  W[i] = E[c] * exp(sb[(size_t)tau * tv.Nb * tv.Nb + (size_t)(y / tv.block) * tv.Nb + x / tv.block]);
+  W[i] = E[c] * exp(sb[(size_t)tau * tv.Nb * tv.Nb + (size_t)(y >> tv.bshift) * tv.Nb + (x >> tv.bshift)]);
 }
 
 __global__ void zero_kernel(long long n, double *__restrict__ a) {
@@ -583,6 +596,7 @@ riot_status riot_tracer_init(const riot_tracer_desc *desc, void *workspace, size
   }
   TracerView &tv = h->tv;
   tv.N = d.N, tv.T = d.nsteps, tv.block = d.block, tv.ntb = d.ntb, tv.Nb = h->Nb;
+  tv.bshift = d.block == 4 ? 2 : (d.block == 2 ? 1 : 0);
   tv.spb = d.nsteps / d.ntb;
   tv.dt = d.dt, tv.aS = d.dt * (d.v + d.K), tv.aE = d.dt * d.K, tv.aN = d.dt * d.K;
   tv.a0 = h->a0, tv.aW = h->aW;

@@ -168,12 +168,16 @@ def batch_workloads(nprob: int, seed: int):
 # Tracer source inversion on a periodic 2-D grid: grid sizes, wind, diffusion, control
 # blocks, observation tracks. "ad2_n512": 512 x 512 cells, 96 steps of dt = 0.1 (Courant
 # number (7 + 1) 0.1 + 4 K dt = 0.84), 4 x 4-cell control blocks x 4 time blocks = 65536
-# controls, 10 random-walk tracks of 400 samples. "ad2_n64": a small version for checks.
+# controls, 10 random-walk tracks of 400 samples. "ad2_n64", "ad2_n128_b2": small versions
+# for checks.
 ADV_GRIDS = {
     "ad2_n512": dict(N=512, T=96, dt=0.1, u0=5.0, u1=2.0, v=1.0, K=0.1, block=4, ntb=4,
                      tracks=10, samples=400),
     "ad2_n64": dict(N=64, T=24, dt=0.1, u0=5.0, u1=2.0, v=1.0, K=0.1, block=4, ntb=4,
                     tracks=10, samples=40),
+    # two tiles across x, 2 x 2-cell control blocks
+    "ad2_n128_b2": dict(N=128, T=10, dt=0.1, u0=5.0, u1=2.0, v=1.0, K=0.1, block=2, ntb=2,
+                        tracks=6, samples=30),
 }
 
 

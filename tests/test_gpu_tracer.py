@@ -68,6 +68,36 @@ def test_tracer_odd_window_and_block_change_inside_a_step_pair():
     assert rel(to_np(tr.adjoint(f)), advdiff.adjoint(g, p.E, s0, p.obs, f)) < 1e-12
 
 
+def _variant(name, seed, **grid):
+    """A problem of the named grid with some grid fields changed: observations after the
+    last step dropped, a control draw of the new size."""
+    d = advdiff_draws(name, seed)
+    d["grid"] = dict(d["grid"], **grid)
+    keep = d["obs_t"] <= d["grid"]["T"]
+    for key in ("obs_t", "obs_y", "obs_x", "obs_noise"):
+        d[key] = d[key][keep]
+    g = advdiff.Grid(**d["grid"])
+    d["xi"] = np.random.default_rng(seed + 100).standard_normal(g.ncontrol)
+    return advdiff.realize(d)
+
+
+@pytest.mark.parametrize("name,grid", [("ad2_n64", dict(block=1, T=8, ntb=2)),
+                                       ("ad2_n128_b2", dict())])
+def test_tracer_control_block_sides_one_and_two(name, grid):
+    """Control blocks of 1 x 1 and 2 x 2 cells (the block sums of the adjoint take other
+    paths than for 4 x 4), the second on a grid two tiles wide."""
+    p = _variant(name, 9, **grid)
+    g = p.grid
+    tr = _tracer(p, m_max=2)
+    rng = np.random.default_rng(10)
+    s0 = 0.3 * rng.standard_normal(g.ncontrol)
+    assert rel(to_np(tr.forward(s0)), advdiff.forward(g, p.E, s0, p.obs)[0]) < 1e-12
+    dS = rng.standard_normal((g.ncontrol, 2))
+    assert rel(to_np(tr.tangent(dS)), advdiff.tangent(g, p.E, s0, p.obs, dS)) < 1e-12
+    f = rng.standard_normal((p.obs.t.size, 2))
+    assert rel(to_np(tr.adjoint(f)), advdiff.adjoint(g, p.E, s0, p.obs, f)) < 1e-12
+
+
 def test_tracer_prior_root_hessian_gradient_match_oracle(small):
     p, tr = small
     g = p.grid

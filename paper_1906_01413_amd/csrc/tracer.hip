@@ -134,6 +134,12 @@ __device__ __forceinline__ void stage_tile2(const double *__restrict__ f, int N,
 
 // out = A (A in + dt W0 up(bv0)) + dt W1 up(bv1) (steps t and t + 1; in may be nullptr);
 // obs[mem nobs + orig[o]] = intermediate field at cell[o] for o in [beg, end).
+// Every global load (the input tile, both steps' emission terms, the observation list) is
+// issued before the first barrier, so a workgroup waits for memory once; the ring rows'
+// coefficients a0, aW go to LDS.
+constexpr int kStage2 = (kGX * kGY + kThreads - 1) / kThreads;
+constexpr int kRing = (kHX * kHY + kThreads - 1) / kThreads;
+
 __global__ void __launch_bounds__(kThreads)
     tracer_step2_kernel(TracerView tv, const double *__restrict__ in, double *__restrict__ out,
                         const double *__restrict__ W0, const double *__restrict__ bv0,
@@ -142,44 +148,93 @@ __global__ void __launch_bounds__(kThreads)
                         const int *__restrict__ orig, int nobs, double *__restrict__ obs) {
   __shared__ double t0[kGX * kGY];
   __shared__ double t1[kHX * kHY];
-  const int N = tv.N;
+  __shared__ double ca0[kHY], caW[kHY];
+  const int N = tv.N, sh = tv.bshift, tid = threadIdx.x;
   const size_t NN = (size_t)N * N;
   const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, mem = blockIdx.z;
-  if (in) {
-    stage_tile2(in + mem * NN, N, x0, y0, t0);
-    __syncthreads();
-  }
+  const int lx = tid % kTX, ly = tid / kTX;
+  const int x = x0 + lx;
   const double *b0m = bv0 + mem * bv_stride, *b1m = bv1 + mem * bv_stride;
-  // intermediate field on the tile and a one-cell ring (kHY x kHX, wrapped coordinates)
-  for (int k = threadIdx.x; k < kHX * kHY; k += kThreads) {
-    const int ry = k / kHX, rx = k - ry * kHX;
-    const int y = wrap(y0 + ry - 1, N), x = wrap(x0 + rx - 1, N);
-    double acc = 0.0;
-    if (in) {
-      const int c = (ry + 1) * kGX + rx + 1;
-      acc = tv.a0[y] * t0[c] + tv.aW[y] * t0[c - 1] + tv.aS * t0[c - kGX] + tv.aE * t0[c + 1] +
-            tv.aN * t0[c + kGX];
+  double sv[kStage2];
+  if (in) {
+    const double *src = in + mem * NN;
+#pragma unroll
+    for (int i = 0; i < kStage2; ++i) {
+      const int k = tid + i * kThreads;
+      if (k < kGX * kGY) {
+        const int ty = k / kGX, tx = k - ty * kGX;
+        sv[i] = src[(size_t)wrap(y0 + ty - 2, N) * N + wrap(x0 + tx - 2, N)];
+      }
     }
-    t1[k] = acc + tv.dt * W0[(size_t)y * N + x] * b0m[(size_t)(y >> tv.bshift) * tv.Nb + (x >> tv.bshift)];
+  }
+  double e0[kRing];  // emission term of the first step on the ring cells
+#pragma unroll
+  for (int i = 0; i < kRing; ++i) {
+    const int k = tid + i * kThreads;
+    if (k < kHX * kHY) {
+      const int ry = k / kHX, rx = k - ry * kHX;
+      const int y = wrap(y0 + ry - 1, N), xr = wrap(x0 + rx - 1, N);
+      e0[i] = tv.dt * W0[(size_t)y * N + xr] * b0m[(size_t)(y >> sh) * tv.Nb + (xr >> sh)];
+    }
+  }
+  double e1[kRY];  // emission term of the second step on this thread's cells
+#pragma unroll
+  for (int r = 0; r < kRY; ++r) {
+    const int y = y0 + ly + kWY * r;
+    e1[r] = tv.dt * W1[(size_t)y * N + x] * b1m[(size_t)(y >> sh) * tv.Nb + (x >> sh)];
+  }
+  // observations of the intermediate state: one per thread prefetched (more loop below)
+  const int o = beg + tid;
+  int oc = -1, oo = 0;
+  if (obs && o < end) oc = cell[o], oo = orig[o];
+  if (tid < kHY) {
+    const int y = wrap(y0 + tid - 1, N);
+    ca0[tid] = tv.a0[y];
+    caW[tid] = tv.aW[y];
+  }
+  if (in) {
+#pragma unroll
+    for (int i = 0; i < kStage2; ++i) {
+      const int k = tid + i * kThreads;
+      if (k < kGX * kGY) t0[k] = sv[i];
+    }
   }
   __syncthreads();
-  if (obs) {
-    for (int o = beg + (int)threadIdx.x; o < end; o += kThreads) {
-      const int cy = cell[o] / N, cx = cell[o] - cy * N;
-      if (cy >= y0 && cy < y0 + kTY && cx >= x0 && cx < x0 + kTX)
-        obs[(size_t)mem * nobs + orig[o]] = t1[(cy - y0 + 1) * kHX + cx - x0 + 1];
+  // intermediate field on the tile and a one-cell ring (kHY x kHX, wrapped coordinates)
+#pragma unroll
+  for (int i = 0; i < kRing; ++i) {
+    const int k = tid + i * kThreads;
+    if (k < kHX * kHY) {
+      const int ry = k / kHX, rx = k - ry * kHX;
+      double acc = 0.0;
+      if (in) {
+        const int c = (ry + 1) * kGX + rx + 1;
+        acc = ca0[ry] * t0[c] + caW[ry] * t0[c - 1] + tv.aS * t0[c - kGX] + tv.aE * t0[c + 1] +
+              tv.aN * t0[c + kGX];
+      }
+      t1[k] = acc + e0[i];
     }
   }
-  const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
-  const int x = x0 + lx;
+  __syncthreads();
+  if (oc >= 0) {
+    const int cy = oc / N, cx = oc - cy * N;
+    if (cy >= y0 && cy < y0 + kTY && cx >= x0 && cx < x0 + kTX)
+      obs[(size_t)mem * nobs + oo] = t1[(cy - y0 + 1) * kHX + cx - x0 + 1];
+  }
+  if (obs) {
+    for (int o2 = o + kThreads; o2 < end; o2 += kThreads) {
+      const int cy = cell[o2] / N, cx = cell[o2] - cy * N;
+      if (cy >= y0 && cy < y0 + kTY && cx >= x0 && cx < x0 + kTX)
+        obs[(size_t)mem * nobs + orig[o2]] = t1[(cy - y0 + 1) * kHX + cx - x0 + 1];
+    }
+  }
 #pragma unroll
   for (int r = 0; r < kRY; ++r) {
     const int yl = ly + kWY * r, y = y0 + yl;
     const int c = (yl + 1) * kHX + lx + 1;
-    const double acc = tv.a0[y] * t1[c] + tv.aW[y] * t1[c - 1] + tv.aS * t1[c - kHX] +
+    const double acc = ca0[yl + 1] * t1[c] + caW[yl + 1] * t1[c - 1] + tv.aS * t1[c - kHX] +
                        tv.aE * t1[c + 1] + tv.aN * t1[c + kHX];
-    out[mem * NN + (size_t)y * N + x] =
-        acc + tv.dt * W1[(size_t)y * N + x] * b1m[(size_t)(y >> tv.bshift) * tv.Nb + (x >> tv.bshift)];
+    out[mem * NN + (size_t)y * N + x] = acc + e1[r];
   }
 }
 
@@ -220,54 +275,90 @@ __global__ void __launch_bounds__(kThreads)
                            double *__restrict__ lam_out, const double *__restrict__ W1,
                            const double *__restrict__ W0, double *gS1, double *gS0,
                            long long gS_stride, int ubeg, int uend,
-                           const int *__restrict__ ucell, const int *__restrict__ uptr,
-                           const int *__restrict__ orig, const double *__restrict__ f, int nobs) {
+                           const int *__restrict__ ucell, const double *__restrict__ fu,
+                           int nuniq) {
   __shared__ double t0[kGX * kGY];
   __shared__ double t1[kHX * kHY];
-  const int N = tv.N;
+  __shared__ double ca0[kHY], caW[kHY];
+  const int N = tv.N, tid = threadIdx.x;
   const size_t NN = (size_t)N * N;
   const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, mem = blockIdx.z;
-  stage_tile2(lam_in + mem * NN, N, x0, y0, t0);
-  __syncthreads();
-  for (int k = threadIdx.x; k < kHX * kHY; k += kThreads) {
-    const int ry = k / kHX, rx = k - ry * kHX;
-    const int y = wrap(y0 + ry - 1, N);
-    const int c = (ry + 1) * kGX + rx + 1;
-    t1[k] = tv.a0[y] * t0[c] + tv.aW[y] * t0[c + 1] + tv.aS * t0[c + kGX] + tv.aE * t0[c - 1] +
-            tv.aN * t0[c - kGX];
-  }
-  const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
+  const int lx = tid % kTX, ly = tid / kTX;
   const int x = x0 + lx, yb = y0 + kRY * ly;  // this thread's first row
+  // every global load first: the input tile, both steps' emission fields on this thread's
+  // cells, one forcing entry of state t-1 (more in the loop below)
+  double sv[kStage2];
+  {
+    const double *src = lam_in + mem * NN;
+#pragma unroll
+    for (int i = 0; i < kStage2; ++i) {
+      const int k = tid + i * kThreads;
+      if (k < kGX * kGY) {
+        const int ty = k / kGX, tx = k - ty * kGX;
+        sv[i] = src[(size_t)wrap(y0 + ty - 2, N) * N + wrap(x0 + tx - 2, N)];
+      }
+    }
+  }
+  double w1[kRY], w0[kRY];
+#pragma unroll
+  for (int r = 0; r < kRY; ++r) {
+    w1[r] = W1[(size_t)(yb + r) * N + x];
+    w0[r] = W0[(size_t)(yb + r) * N + x];
+  }
+  const int u = ubeg + tid;
+  int uc = -1;
+  double uf = 0.0;
+  if (u < uend) uc = ucell[u], uf = fu[(size_t)mem * nuniq + u];
+  if (tid < kHY) {
+    const int y = wrap(y0 + tid - 1, N);
+    ca0[tid] = tv.a0[y];
+    caW[tid] = tv.aW[y];
+  }
+#pragma unroll
+  for (int i = 0; i < kStage2; ++i) {
+    const int k = tid + i * kThreads;
+    if (k < kGX * kGY) t0[k] = sv[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kRing; ++i) {
+    const int k = tid + i * kThreads;
+    if (k < kHX * kHY) {
+      const int ry = k / kHX, rx = k - ry * kHX;
+      const int c = (ry + 1) * kGX + rx + 1;
+      t1[k] = ca0[ry] * t0[c] + caW[ry] * t0[c + 1] + tv.aS * t0[c + kGX] + tv.aE * t0[c - 1] +
+              tv.aN * t0[c - kGX];
+    }
+  }
   double v[kRY];
 #pragma unroll
   for (int r = 0; r < kRY; ++r)
-    v[r] = tv.dt * W1[(size_t)(yb + r) * N + x] * t0[(kRY * ly + r + 2) * kGX + lx + 2];
+    v[r] = tv.dt * w1[r] * t0[(kRY * ly + r + 2) * kGX + lx + 2];
   __syncthreads();
-  // a cell may sit at two ring positions when the ring spans the whole period (N = kTX):
-  // the forcing goes to every copy
-  for (int u = ubeg + (int)threadIdx.x; u < uend; u += kThreads) {
-    const int cy = ucell[u] / N, cx = ucell[u] - cy * N;
+  // forcing of state t-1 on the ring; a cell may sit at two ring positions when the ring
+  // spans the whole period (N = kTX): the forcing goes to every copy
+  auto add_forcing = [&](int cellu, double val) {
+    const int cy = cellu / N, cx = cellu - cy * N;
     const int ry0 = wrap(cy - (y0 - 1), N), rx0 = wrap(cx - (x0 - 1), N);
-    if (ry0 < kHY && rx0 < kHX) {
-      double sum = 0.0;
-      for (int k = uptr[u]; k < uptr[u + 1]; ++k) sum += f[(size_t)mem * nobs + orig[k]];
-      for (int ry = ry0; ry < kHY; ry += N)
-        for (int rx = rx0; rx < kHX; rx += N) t1[ry * kHX + rx] += sum;
-    }
-  }
+    for (int ry = ry0; ry < kHY; ry += N)
+      for (int rx = rx0; rx < kHX; rx += N) t1[ry * kHX + rx] += val;
+  };
+  if (uc >= 0) add_forcing(uc, uf);
+  for (int u2 = u + kThreads; u2 < uend; u2 += kThreads)
+    add_forcing(ucell[u2], fu[(size_t)mem * nuniq + u2]);
   const int sh = tv.bshift;
   const size_t goff = (size_t)mem * gS_stride + (size_t)(yb >> sh) * tv.Nb + (x >> sh);
   block_sums_add(v, tv.block, lx, gS1 + goff, tv.Nb);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRY; ++r) {
-    const int y = yb + r;
-    const int c = (kRY * ly + r + 1) * kHX + lx + 1;
+    const int y = yb + r, rr = kRY * ly + r + 1;  // ring row of this cell
+    const int c = rr * kHX + lx + 1;
     if (lam_out)
-      lam_out[mem * NN + (size_t)y * N + x] = tv.a0[y] * t1[c] + tv.aW[y] * t1[c + 1] +
+      lam_out[mem * NN + (size_t)y * N + x] = ca0[rr] * t1[c] + caW[rr] * t1[c + 1] +
                                               tv.aS * t1[c + kHX] + tv.aE * t1[c - 1] +
                                               tv.aN * t1[c - kHX];
-    v[r] = tv.dt * W0[(size_t)y * N + x] * t1[c];
+    v[r] = tv.dt * w0[r] * t1[c];
   }
   block_sums_add(v, tv.block, lx, gS0 + goff, tv.Nb);
 }
@@ -282,17 +373,27 @@ __global__ void tracer_sample_kernel(int N, int beg, int end, const int *__restr
   out[(size_t)mem * nobs + orig[o]] = f[(size_t)mem * N * N + cell[o]];
 }
 
-// Observation forcing of one step: lam[cell_u] += sum of f over the observations of u.
+// Observation forcing gathered per unique cell: fu[mem nuniq + u] = sum of f over the
+// observations of u (all steps at once, before an adjoint sweep).
+__global__ void tracer_gather_kernel(int nuniq, const int *__restrict__ uptr,
+                                     const int *__restrict__ orig, const double *__restrict__ f,
+                                     int nobs, double *__restrict__ fu) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= nuniq) return;
+  const int mem = blockIdx.y;
+  double s = 0.0;
+  for (int k = uptr[u]; k < uptr[u + 1]; ++k) s += f[(size_t)mem * nobs + orig[k]];
+  fu[(size_t)mem * nuniq + u] = s;
+}
+
+// Observation forcing of one step: lam[cell_u] += fu[u] for the step's unique cells.
 __global__ void tracer_inject_kernel(int N, int beg, int end, const int *__restrict__ ucell,
-                                     const int *__restrict__ uptr, const int *__restrict__ orig,
-                                     const double *__restrict__ f, int nobs,
+                                     const double *__restrict__ fu, int nuniq,
                                      double *__restrict__ lam) {
   const int u = beg + blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= end) return;
   const int mem = blockIdx.y;
-  double s = 0.0;
-  for (int k = uptr[u]; k < uptr[u + 1]; ++k) s += f[(size_t)mem * nobs + orig[k]];
-  lam[(size_t)mem * N * N + ucell[u]] += s;
+  lam[(size_t)mem * N * N + ucell[u]] += fu[(size_t)mem * nuniq + u];
 }
 
 // Elementwise helpers.
@@ -380,6 +481,7 @@ struct riot_tracer {
   double *F0 = nullptr, *F1 = nullptr;           // m_max fields each (ping-pong)
   double *CA = nullptr, *CB = nullptr, *CC = nullptr;  // m_max control blocks each
   double *OA = nullptr;                          // m_max observation columns
+  double *FU = nullptr;                          // m_max forcing columns per unique cell
   double *hx = nullptr, *dvec = nullptr, *fvec = nullptr, *scal = nullptr;
   // host tables: observations sorted by step (offsets per step), unique cells per step
   std::vector<int> obs_off, u_off;
@@ -444,6 +546,7 @@ size_t tracer_carve(riot_tracer &h, void *base) {
   h.CB = c.take<double>(nc * m);
   h.CC = c.take<double>(nc * m);
   h.OA = c.take<double>((size_t)std::max(d.nobs, 1) * m);
+  h.FU = c.take<double>((size_t)std::max(d.nobs, 1) * m);
   h.hx = c.take<double>(d.nobs);
   h.dvec = c.take<double>(d.nobs);
   h.fvec = c.take<double>(d.nobs);
@@ -513,6 +616,11 @@ riot_status tracer_adjoint_sweep(riot_tracer *h, int m, const double *f, double 
   hipLaunchKernelGGL(riot::zero_kernel, dim3(riot::blocks_for((long long)h->ncontrol * m)),
                      dim3(256), 0, h->st, (long long)h->ncontrol * m, gS);
   TR_HIP(hipGetLastError());
+  if (h->nuniq > 0) {
+    hipLaunchKernelGGL(riot::tracer_gather_kernel, dim3(riot::blocks_for(h->nuniq), m), dim3(256),
+                       0, h->st, h->nuniq, h->uptr, h->orig, f, d.nobs, h->FU);
+    TR_HIP(hipGetLastError());
+  }
   double *lam = h->F0, *other = h->F1;
   const int Nbb = h->Nb * h->Nb;
   // forcing of state t: unique cells [u_off[t], u_off[t + 1])
@@ -520,8 +628,7 @@ riot_status tracer_adjoint_sweep(riot_tracer *h, int m, const double *f, double 
     const int beg = h->u_off[t], end = h->u_off[t + 1];
     if (end > beg) {
       hipLaunchKernelGGL(riot::tracer_inject_kernel, dim3(riot::blocks_for(end - beg), m),
-                         dim3(256), 0, h->st, d.N, beg, end, h->ucell, h->uptr, h->orig, f,
-                         d.nobs, lam);
+                         dim3(256), 0, h->st, d.N, beg, end, h->ucell, h->FU, h->nuniq, lam);
       TR_HIP(hipGetLastError());
     }
     return RIOT_OK;
@@ -534,7 +641,7 @@ riot_status tracer_adjoint_sweep(riot_tracer *h, int m, const double *f, double 
     hipLaunchKernelGGL(riot::tracer_adjoint2_kernel, grid, dim3(riot::kThreads), 0, h->st, tv,
                        lam, t > 2 ? other : nullptr, h->Wb + NN * tau1, h->Wb + NN * tau0,
                        gS + (size_t)tau1 * Nbb, gS + (size_t)tau0 * Nbb, (long long)h->ncontrol,
-                       h->u_off[t - 1], h->u_off[t], h->ucell, h->uptr, h->orig, f, d.nobs);
+                       h->u_off[t - 1], h->u_off[t], h->ucell, h->FU, h->nuniq);
     TR_HIP(hipGetLastError());
     std::swap(lam, other);
   }

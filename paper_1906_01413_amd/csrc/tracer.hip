@@ -37,6 +37,34 @@ struct TracerView {
 
 __device__ __forceinline__ int wrap(int i, int N) { return i < 0 ? i + N : (i >= N ? i - N : i); }
 
+// Tile of this workgroup. Workgroups are dealt round-robin to the 8 XCDs, each with its own
+// L2; in dispatch order an XCD would get the tiles of one x column only, so its tiles'
+// x-halo lines would never be in its L2. With the remap (when the tile rows split into 8
+// bands) XCD j takes band j of tile rows for every member, x fastest: x neighbours share
+// their halo lines in one L2, and its band of the emission fields stays resident there.
+struct TileId {
+  int x0, y0, mem;
+};
+__device__ __forceinline__ TileId tile_id() {
+  const int gx = gridDim.x, gy = gridDim.y;
+  int id = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  int bx, by, mem;
+  if ((gy & 7) == 0) {
+    const int band = gy >> 3, xcd = id & 7;
+    int q = id >> 3;  // rank of this workgroup among its XCD's
+    bx = q % gx;
+    q /= gx;
+    by = xcd * band + q % band;
+    mem = q / band;
+  } else {
+    bx = id % gx;
+    id /= gx;
+    by = id % gy;
+    mem = id / gy;
+  }
+  return {bx * kTX, by * kTY, mem};
+}
+
 // Stage the tile of `f` with its halo in LDS (row-major, kHY x kHX).
 __device__ __forceinline__ void stage_tile(const double *__restrict__ f, int N, int x0, int y0,
                                            double *t) {
@@ -55,7 +83,8 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ double t[kHX * kHY];
   const int N = tv.N;
   const size_t NN = (size_t)N * N;
-  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, mem = blockIdx.z;
+  const TileId ti = tile_id();
+  const int x0 = ti.x0, y0 = ti.y0, mem = ti.mem;
   const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
   const int x = x0 + lx;
   if (in) {
@@ -87,7 +116,8 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ double w[kTY][kTX];
   const int N = tv.N;
   const size_t NN = (size_t)N * N;
-  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, mem = blockIdx.z;
+  const TileId ti = tile_id();
+  const int x0 = ti.x0, y0 = ti.y0, mem = ti.mem;
   const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
   const int x = x0 + lx;
   stage_tile(lam_in + mem * NN, N, x0, y0, t);
@@ -124,14 +154,6 @@ __global__ void __launch_bounds__(kThreads)
 // ---------------------------------------------------------------------------
 constexpr int kGX = kTX + 4, kGY = kTY + 4;  // input tile with a two-cell halo
 
-__device__ __forceinline__ void stage_tile2(const double *__restrict__ f, int N, int x0, int y0,
-                                            double *t) {
-  for (int k = threadIdx.x; k < kGX * kGY; k += kThreads) {
-    const int ty = k / kGX, tx = k - ty * kGX;
-    t[k] = f[(size_t)wrap(y0 + ty - 2, N) * N + wrap(x0 + tx - 2, N)];
-  }
-}
-
 // out = A (A in + dt W0 up(bv0)) + dt W1 up(bv1) (steps t and t + 1; in may be nullptr);
 // obs[mem nobs + orig[o]] = intermediate field at cell[o] for o in [beg, end).
 // Every global load (the input tile, both steps' emission terms, the observation list) is
@@ -140,6 +162,7 @@ __device__ __forceinline__ void stage_tile2(const double *__restrict__ f, int N,
 constexpr int kStage2 = (kGX * kGY + kThreads - 1) / kThreads;
 constexpr int kRing = (kHX * kHY + kThreads - 1) / kThreads;
 
+template <bool IN>
 __global__ void __launch_bounds__(kThreads)
     tracer_step2_kernel(TracerView tv, const double *__restrict__ in, double *__restrict__ out,
                         const double *__restrict__ W0, const double *__restrict__ bv0,
@@ -151,31 +174,31 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ double ca0[kHY], caW[kHY];
   const int N = tv.N, sh = tv.bshift, tid = threadIdx.x;
   const size_t NN = (size_t)N * N;
-  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, mem = blockIdx.z;
+  const TileId ti = tile_id();
+  const int x0 = ti.x0, y0 = ti.y0, mem = ti.mem;
   const int lx = tid % kTX, ly = tid / kTX;
   const int x = x0 + lx;
   const double *b0m = bv0 + mem * bv_stride, *b1m = bv1 + mem * bv_stride;
+  // Loads past the end of a strip are clamped to its last element and their values
+  // dropped, so that every load is unconditional straight-line code and all of them are
+  // in flight together.
   double sv[kStage2];
-  if (in) {
+  if constexpr (IN) {
     const double *src = in + mem * NN;
 #pragma unroll
     for (int i = 0; i < kStage2; ++i) {
-      const int k = tid + i * kThreads;
-      if (k < kGX * kGY) {
-        const int ty = k / kGX, tx = k - ty * kGX;
-        sv[i] = src[(size_t)wrap(y0 + ty - 2, N) * N + wrap(x0 + tx - 2, N)];
-      }
+      const int k = min(tid + i * kThreads, kGX * kGY - 1);
+      const int ty = k / kGX, tx = k - ty * kGX;
+      sv[i] = src[(size_t)wrap(y0 + ty - 2, N) * N + wrap(x0 + tx - 2, N)];
     }
   }
   double e0[kRing];  // emission term of the first step on the ring cells
 #pragma unroll
   for (int i = 0; i < kRing; ++i) {
-    const int k = tid + i * kThreads;
-    if (k < kHX * kHY) {
-      const int ry = k / kHX, rx = k - ry * kHX;
-      const int y = wrap(y0 + ry - 1, N), xr = wrap(x0 + rx - 1, N);
-      e0[i] = tv.dt * W0[(size_t)y * N + xr] * b0m[(size_t)(y >> sh) * tv.Nb + (xr >> sh)];
-    }
+    const int k = min(tid + i * kThreads, kHX * kHY - 1);
+    const int ry = k / kHX, rx = k - ry * kHX;
+    const int y = wrap(y0 + ry - 1, N), xr = wrap(x0 + rx - 1, N);
+    e0[i] = tv.dt * W0[(size_t)y * N + xr] * b0m[(size_t)(y >> sh) * tv.Nb + (xr >> sh)];
   }
   double e1[kRY];  // emission term of the second step on this thread's cells
 #pragma unroll
@@ -183,16 +206,18 @@ __global__ void __launch_bounds__(kThreads)
     const int y = y0 + ly + kWY * r;
     e1[r] = tv.dt * W1[(size_t)y * N + x] * b1m[(size_t)(y >> sh) * tv.Nb + (x >> sh)];
   }
-  // observations of the intermediate state: one per thread prefetched (more loop below)
+  // observations of the intermediate state: one per thread prefetched (more loop below);
+  // index 0 stands in where there is none (the tables hold at least one entry)
   const int o = beg + tid;
-  int oc = -1, oo = 0;
-  if (obs && o < end) oc = cell[o], oo = orig[o];
+  const bool has_o = obs != nullptr && o < end;
+  const int oc = cell[has_o ? o : 0], oo = orig[has_o ? o : 0];
+  const int yr = wrap(y0 + min(tid, kHY - 1) - 1, N);
+  const double a0r = tv.a0[yr], aWr = tv.aW[yr];
   if (tid < kHY) {
-    const int y = wrap(y0 + tid - 1, N);
-    ca0[tid] = tv.a0[y];
-    caW[tid] = tv.aW[y];
+    ca0[tid] = a0r;
+    caW[tid] = aWr;
   }
-  if (in) {
+  if constexpr (IN) {
 #pragma unroll
     for (int i = 0; i < kStage2; ++i) {
       const int k = tid + i * kThreads;
@@ -207,7 +232,7 @@ __global__ void __launch_bounds__(kThreads)
     if (k < kHX * kHY) {
       const int ry = k / kHX, rx = k - ry * kHX;
       double acc = 0.0;
-      if (in) {
+      if constexpr (IN) {
         const int c = (ry + 1) * kGX + rx + 1;
         acc = ca0[ry] * t0[c] + caW[ry] * t0[c - 1] + tv.aS * t0[c - kGX] + tv.aE * t0[c + 1] +
               tv.aN * t0[c + kGX];
@@ -216,7 +241,7 @@ __global__ void __launch_bounds__(kThreads)
     }
   }
   __syncthreads();
-  if (oc >= 0) {
+  if (has_o) {
     const int cy = oc / N, cx = oc - cy * N;
     if (cy >= y0 && cy < y0 + kTY && cx >= x0 && cx < x0 + kTX)
       obs[(size_t)mem * nobs + oo] = t1[(cy - y0 + 1) * kHX + cx - x0 + 1];
@@ -282,21 +307,21 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ double ca0[kHY], caW[kHY];
   const int N = tv.N, tid = threadIdx.x;
   const size_t NN = (size_t)N * N;
-  const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, mem = blockIdx.z;
+  const TileId ti = tile_id();
+  const int x0 = ti.x0, y0 = ti.y0, mem = ti.mem;
   const int lx = tid % kTX, ly = tid / kTX;
   const int x = x0 + lx, yb = y0 + kRY * ly;  // this thread's first row
   // every global load first: the input tile, both steps' emission fields on this thread's
   // cells, one forcing entry of state t-1 (more in the loop below)
+  // (loads clamped to valid elements and unconditional, as in the forward pair)
   double sv[kStage2];
   {
     const double *src = lam_in + mem * NN;
 #pragma unroll
     for (int i = 0; i < kStage2; ++i) {
-      const int k = tid + i * kThreads;
-      if (k < kGX * kGY) {
-        const int ty = k / kGX, tx = k - ty * kGX;
-        sv[i] = src[(size_t)wrap(y0 + ty - 2, N) * N + wrap(x0 + tx - 2, N)];
-      }
+      const int k = min(tid + i * kThreads, kGX * kGY - 1);
+      const int ty = k / kGX, tx = k - ty * kGX;
+      sv[i] = src[(size_t)wrap(y0 + ty - 2, N) * N + wrap(x0 + tx - 2, N)];
     }
   }
   double w1[kRY], w0[kRY];
@@ -306,13 +331,14 @@ __global__ void __launch_bounds__(kThreads)
     w0[r] = W0[(size_t)(yb + r) * N + x];
   }
   const int u = ubeg + tid;
-  int uc = -1;
-  double uf = 0.0;
-  if (u < uend) uc = ucell[u], uf = fu[(size_t)mem * nuniq + u];
+  const bool has_u = u < uend;
+  const int uc = ucell[has_u ? u : 0];
+  const double uf = fu[(size_t)mem * nuniq + (has_u ? u : 0)];
+  const int yr = wrap(y0 + min(tid, kHY - 1) - 1, N);
+  const double a0r = tv.a0[yr], aWr = tv.aW[yr];
   if (tid < kHY) {
-    const int y = wrap(y0 + tid - 1, N);
-    ca0[tid] = tv.a0[y];
-    caW[tid] = tv.aW[y];
+    ca0[tid] = a0r;
+    caW[tid] = aWr;
   }
 #pragma unroll
   for (int i = 0; i < kStage2; ++i) {
@@ -343,7 +369,7 @@ __global__ void __launch_bounds__(kThreads)
     for (int ry = ry0; ry < kHY; ry += N)
       for (int rx = rx0; rx < kHX; rx += N) t1[ry * kHX + rx] += val;
   };
-  if (uc >= 0) add_forcing(uc, uf);
+  if (has_u) add_forcing(uc, uf);
   for (int u2 = u + kThreads; u2 < uend; u2 += kThreads)
     add_forcing(ucell[u2], fu[(size_t)mem * nuniq + u2]);
   const int sh = tv.bshift;
@@ -583,7 +609,8 @@ riot_status tracer_forward_sweep(riot_tracer *h, int m, const double *Wfield, lo
   for (; t + 1 < d.nsteps; t += 2) {  // steps t and t + 1 in one launch
     const int tau0 = t / tv.spb, tau1 = (t + 1) / tv.spb;
     double *next = bufs[(nb++) & 1];
-    hipLaunchKernelGGL(riot::tracer_step2_kernel, grid, dim3(riot::kThreads), 0, h->st, tv, cur,
+    hipLaunchKernelGGL(cur ? riot::tracer_step2_kernel<true> : riot::tracer_step2_kernel<false>,
+                       grid, dim3(riot::kThreads), 0, h->st, tv, cur,
                        next, Wfield + Wstride * tau0, bv + (size_t)tau0 * Nbb,
                        Wfield + Wstride * tau1, bv + (size_t)tau1 * Nbb, bv_stride,
                        h->obs_off[t + 2], h->obs_off[t + 3], h->cell, h->orig, d.nobs, obs);

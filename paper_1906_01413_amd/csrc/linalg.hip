@@ -243,6 +243,9 @@ __device__ __forceinline__ void zero_acc(d4 (&acc)[2][2]) {
 constexpr int kCholThreads = 512;
 constexpr int kPB = 32;  // panel width of the blocked factorizations
 constexpr int kStageRows = 320;  // panel rows staged in LDS by the Cholesky
+// largest 1-norm condition of a 32 x 32 diagonal block whose panel the Cholesky solves as a
+// product with the block's inverse (about one digit of the panel's residual given up)
+constexpr double kCholInvCond = 16.0;
 
 // Value of a double held by lane `src` of the wave (src uniform), via two v_readlane_b32.
 __device__ __forceinline__ double readlane_d(double v, int src) {
@@ -276,7 +279,7 @@ __global__ void __launch_bounds__(kCholThreads)
   __shared__ double Di[kPB][kPB + 1];  // Di[k][j] = (L11^{-1})[j][k]
   __shared__ double Pn[kPB * (kStageRows + 1)];
   __shared__ double red[16];
-  __shared__ int bad;
+  __shared__ int bad, use_inv;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int wave = tid >> 6, nwaves = nt >> 6;
   double fro = 0.0;
@@ -363,6 +366,22 @@ __global__ void __launch_bounds__(kCholThreads)
 #pragma unroll
           for (int i = 0; i < kPB; ++i) Di[c][i] = x[i];
         }
+        // 1-norm condition of the block, kappa = |L11|_1 |L11^{-1}|_1: lane c sums column c
+        // of the factor and of its inverse
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        __builtin_amdgcn_wave_barrier();
+        double cl = 0.0, ci = 0.0;
+        if (!fail && lane < nb) {
+          for (int i = lane; i < nb; ++i) {
+            cl += fabs(D[i][lane]);
+            ci += fabs(Di[lane][i]);
+          }
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+          cl = fmax(cl, __shfl_xor(cl, off));
+          ci = fmax(ci, __shfl_xor(ci, off));
+        }
+        if (lane == 0) use_inv = (cl * ci <= kCholInvCond);
       }
       __syncthreads();
       if (bad) break;
@@ -370,8 +389,11 @@ __global__ void __launch_bounds__(kCholThreads)
         const int i = idx % nb, j = idx / nb;
         if (i >= j) L[(size_t)(kb + j) * m + kb + i] = D[i][j];
       }
-      // 2. panel rows below: X = A21 L11^{-T}, one 32-row MFMA tile per wave (the panel is
-      //    staged in LDS first when it fits; the result goes to L and to the staged copy)
+      // 2. panel rows below: X L11^T = A21 (the panel is staged in LDS first when it fits;
+      //    the result goes to L and to the staged copy). A well-conditioned block: X =
+      //    A21 L11^{-T}, one 32-row MFMA tile per wave. Otherwise forward substitution per
+      //    row, whose residual stays at rounding level whatever the block's condition (the
+      //    product with the inverse leaves a residual of order kappa times rounding).
       const int r0 = kb + nb;
       const int prow = m - r0;
       const bool staged = prow <= kStageRows;
@@ -381,7 +403,21 @@ __global__ void __launch_bounds__(kCholThreads)
             Pn[jj * (kStageRows + 1) + ii] = L[(size_t)(kb + jj) * m + r0 + ii];
       }
       __syncthreads();
-      {
+      if (!use_inv) {
+        // in place in the panel's own storage (LDS when staged), row by row:
+        // x_j = (a_j - sum_{t<j} x_t L11[j][t]) / L11[j][j]
+        const int ld = staged ? kStageRows + 1 : m;
+        for (int i = tid; i < prow; i += nt) {
+          double *col = staged ? Pn + i : L + (size_t)kb * m + r0 + i;  // element j at col[j ld]
+          for (int j = 0; j < nb; ++j) {
+            double a = col[(size_t)j * ld];
+            for (int t = 0; t < j; ++t) a -= col[(size_t)t * ld] * D[j][t];
+            col[(size_t)j * ld] = a * Di[j][j];  // Di[j][j] = 1 / L11[j][j]
+          }
+          if (staged)
+            for (int j = 0; j < nb; ++j) L[(size_t)(kb + j) * m + r0 + i] = col[j * ld];
+        }
+      } else {
         const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
         const int npt = (prow + 31) / 32;
         for (int I = wave; I < npt; I += nwaves) {
@@ -845,14 +881,6 @@ hipError_t launch_trsm_rlt_inv(int rows, int m, double *X, int ldx, const double
   if (rows <= 0 || m <= 0) return hipSuccess;
   hipLaunchKernelGGL(trsm_rlt_inv_kernel, dim3((rows + 31) / 32), dim3(256), 0, st, rows, m, X,
                      ldx, L, dinv, run);
-  return hipGetLastError();
-}
-
-hipError_t launch_trsm_rlt(int rows, int m, double *X, int ldx, const double *L, hipStream_t st,
-                           const int *run) {
-  if (rows <= 0 || m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(trsm_rlt_kernel, dim3((rows + 31) / 32), dim3(64), 0, st, rows, m, X, ldx, L,
-                     run, nullptr);
   return hipGetLastError();
 }
 

@@ -250,11 +250,9 @@ hipError_t launch_copy_batched(int nprob, long long maxcount, const CopyJob *job
 hipError_t launch_cholqr_reset(int *cq, hipStream_t st);
 hipError_t launch_cholqr_ctrl(int *cq, int pass_was_shifted, int *count, hipStream_t st);
 
-// X <- X L^{-T} in place (X rows x m, leading dimension ldx; L lower m x m).
-hipError_t launch_trsm_rlt(int rows, int m, double *X, int ldx, const double *L, hipStream_t st,
-                           const int *run = nullptr);
-// The same through the inverses of L's 32 x 32 diagonal blocks: launch_trsm_diag_inv
-// writes them to dinv (ceil(m / 32) * 1024 doubles), launch_trsm_rlt_inv uses them.
+// X <- X L^{-T} in place (X rows x m, leading dimension ldx; L lower m x m), through the
+// inverses of L's 32 x 32 diagonal blocks: launch_trsm_diag_inv writes them to dinv
+// (ceil(m / 32) * 1024 doubles), launch_trsm_rlt_inv uses them.
 hipError_t launch_trsm_diag_inv(int m, const double *L, double *dinv, hipStream_t st,
                                 const int *run = nullptr);
 hipError_t launch_trsm_rlt_inv(int rows, int m, double *X, int ldx, const double *L,

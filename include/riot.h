@@ -167,7 +167,7 @@ riot_status riot_proj_residual(riot_handle *h, int32_t m, const double *Q, const
  *   LRA: dz = -sum_i (1 + l_i)^{-1} v_i v_i^T g
  *   LRU: dz = -(I - sum_i l_i / (1 + l_i) v_i v_i^T) g
  *   lambda [>=k] device, V [n x >=k] device, grad [n] device
- *   dz [n], dx [n] device out (dx = L dz)
+ *   dz [n], dx [n] device out (dx = L dz), distinct buffers
  *   dofs_host  host out or NULL: sum_i l_i / (1 + l_i) (degrees of freedom for signal)
  *   mode_used  host out or NULL: RIOT_LRA or RIOT_LRU as applied */
 riot_status riot_increment(riot_handle *h, int32_t k, const double *lambda, const double *V,
@@ -178,7 +178,7 @@ riot_status riot_increment(riot_handle *h, int32_t k, const double *lambda, cons
  *   LRU: P_a = B + W diag(coef) W^T, coef_i = -l_i / (1 + l_i)
  *   LRA: P_a = W diag(coef) W^T,     coef_i = 1 / (1 + l_i)
  * with W = L V[:, :k].
- *   W [n x k] device out; coef [k] device out
+ *   W [n x k] device out, not V; coef [k] device out
  *   diag  [n] device out or NULL: diagonal of P_a
  *   dense [n x n] device out or NULL: P_a itself
  *   mode_used host out or NULL (synchronises when mode is RIOT_ADAPTIVE) */

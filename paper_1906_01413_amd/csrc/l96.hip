@@ -743,6 +743,37 @@ __global__ void __launch_bounds__(256)
                  use_lds ? ext : nullptr);
 }
 
+// The same product for one segment of kLSeg rows of one column per workgroup (grid: column,
+// segment): the segment with its w-row halo on each side is staged in LDS, and the sums run
+// in the order of apply_L_column, so results are identical. A column split into segments
+// gives a block of m columns n / kLSeg times as many workgroups to hide the LDS latency.
+constexpr int kLSeg = 1024;
+
+__global__ void __launch_bounds__(256)
+    apply_L_seg_kernel(int n, int w, const double *__restrict__ taps, const double *__restrict__ X,
+                       double *__restrict__ Y, const double *__restrict__ Z, int mode) {
+  extern __shared__ double ext[];
+  const size_t c = blockIdx.x;
+  const int r0 = blockIdx.y * kLSeg, len = min(kLSeg, n - r0);
+  const double *x = X + c * n;
+  for (int k = threadIdx.x; k < len + 2 * w; k += blockDim.x) {
+    int src = (r0 + k - w) % n;
+    if (src < 0) src += n;
+    ext[k] = x[src];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < len; i += blockDim.x) {
+    double acc = taps[0] * ext[i + w];
+    for (int dd = 1; dd <= w; ++dd) acc += taps[dd] * (ext[i + w + dd] + ext[i + w - dd]);
+    const size_t o = c * n + r0 + i;
+    if (mode == 1)
+      acc += Z[o];
+    else if (mode == 2)
+      acc = (Z ? Z[o] : 0.0) - acc;
+    Y[o] = acc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Conjugate gradients: one workgroup, all iterations in one launch.
 // ---------------------------------------------------------------------------
@@ -988,6 +1019,13 @@ hipError_t launch_obs_scatter(int nobs, int U, int m, const int *u_optr, const i
 hipError_t launch_apply_L(int n, int w, const double *taps, int m, const double *X, double *Y,
                           const double *Z, int mode, hipStream_t st) {
   if (m <= 0) return hipSuccess;
+  const size_t seg_lds = (size_t)(kLSeg + 2 * w) * sizeof(double);
+  if (seg_lds <= 60 * 1024) {
+    const unsigned nseg = (unsigned)((n + kLSeg - 1) / kLSeg);
+    hipLaunchKernelGGL(apply_L_seg_kernel, dim3(m, nseg), dim3(256), seg_lds, st, n, w, taps, X, Y,
+                       Z, mode);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)(n + 2 * w) * sizeof(double);
   const int use_lds = lds <= 60 * 1024 ? 1 : 0;
   hipLaunchKernelGGL(apply_L_kernel, dim3(m), dim3(256), use_lds ? lds : 0, st, n, w, taps, X, Y,

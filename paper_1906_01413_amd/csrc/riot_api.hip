@@ -577,7 +577,8 @@ riot_status riot_proj_residual(riot_handle *h, int32_t m, const double *Q, const
 riot_status riot_increment(riot_handle *h, int32_t k, const double *lambda, const double *V,
                            const double *grad, riot_update mode, double *dz, double *dx,
                            double *dofs_host, int32_t *mode_used) {
-  if (!h || !lambda || !V || !grad || !dz || !dx || k < 1 || k > h->d.n || k > h->d.m_max)
+  if (!h || !lambda || !V || !grad || !dz || !dx || dz == dx || k < 1 || k > h->d.n ||
+      k > h->d.m_max)
     return RIOT_E_ARG;
   if (mode != RIOT_ADAPTIVE && mode != RIOT_LRA && mode != RIOT_LRU) return RIOT_E_ARG;
   const int n = h->d.n;
@@ -603,7 +604,7 @@ riot_status riot_increment(riot_handle *h, int32_t k, const double *lambda, cons
 riot_status riot_posterior_cov(riot_handle *h, int32_t k, const double *lambda, const double *V,
                                riot_update mode, double *W, double *coef, double *diag,
                                double *dense, int32_t *mode_used) {
-  if (!h || !lambda || !V || !W || !coef || k < 1 || k > h->d.n) return RIOT_E_ARG;
+  if (!h || !lambda || !V || !W || !coef || W == V || k < 1 || k > h->d.n) return RIOT_E_ARG;
   if (mode != RIOT_ADAPTIVE && mode != RIOT_LRA && mode != RIOT_LRU) return RIOT_E_ARG;
   if (k > h->d.m_max) return RIOT_E_ARG;
   const int n = h->d.n;

@@ -362,7 +362,7 @@ __device__ int negcount(int m, const double *D, const double *LLD, double tau, d
 // ---------------------------------------------------------------------------
 // 2. Root representation (one workgroup of 64 threads).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) root_kernel(int m, double *__restrict__ work,
+__global__ void __launch_bounds__(256) root_kernel(int m, double *__restrict__ work,
                                                   int *__restrict__ flag,
                                                   const EigJob *__restrict__ jobs) {
   if (jobs) m = jobs[blockIdx.y].m, work = jobs[blockIdx.y].work, flag = jobs[blockIdx.y].flag;
@@ -377,9 +377,10 @@ __global__ void __launch_bounds__(64) root_kernel(int m, double *__restrict__ wo
   double *D = work + Lw.D, *Ls = work + Lw.Ls, *LLD = work + Lw.LLD, *misc = work + Lw.misc;
   __shared__ double sh_lo, sh_hi, sh_sigma;
   __shared__ int sh_ok;
-  const int lane = threadIdx.x;
+  __shared__ int sh_first[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // Gershgorin bounds and the norm
-  if (lane == 0) {
+  if (tid == 0) {
     double gl = dg[0], gu = dg[0], tn = 0.0;
     for (int i = 0; i < m; ++i) {
       const double r = (i > 0 ? fabs(eg[i - 1]) : 0.0) + (i < m - 1 ? fabs(eg[i]) : 0.0);
@@ -396,27 +397,36 @@ __global__ void __launch_bounds__(64) root_kernel(int m, double *__restrict__ wo
   __syncthreads();
   const double tn = misc[0];
   const double pivmin = 1e-290 * fmax(1.0, tn * tn);
-  // smallest eigenvalue by 64-way multisection on Sturm counts
-  for (int round = 0; round < 14; ++round) {
+  // smallest eigenvalue by 256-way multisection on Sturm counts (8 bits per round) until the
+  // bracket is below eps * |T|, far under the shift margin's floor of 64 eps |T| below
+  for (int round = 0; round < 8; ++round) {
     const double lo = sh_lo, hi = sh_hi;
-    const double x = lo + (hi - lo) * (lane + 1) / 65.0;
+    if (hi - lo <= 0x1.0p-52 * tn) break;  // the same shared values in every thread
+    const double x = lo + (hi - lo) * (tid + 1) / 257.0;
     const int c = sturm_count(m, dg, eg, x, pivmin);
-    // smallest lane whose point has at least one eigenvalue below it
+    // smallest point with at least one eigenvalue below it: first lane per wave, then the
+    // first wave that has one
     const unsigned long long bal = __ballot(c >= 1);
+    if (lane == 0) sh_first[wave] = bal ? __ffsll((long long)bal) - 1 : 64;
     __syncthreads();
-    if (lane == 0) {
-      if (bal == 0ull) {
-        sh_lo = lo + (hi - lo) * 64.0 / 65.0;
+    if (tid == 0) {
+      int first = 256;
+      for (int w = 0; w < 4; ++w)
+        if (sh_first[w] < 64) {
+          first = 64 * w + sh_first[w];
+          break;
+        }
+      if (first == 256) {
+        sh_lo = lo + (hi - lo) * 256.0 / 257.0;
       } else {
-        const int first = __ffsll((long long)bal) - 1;
-        sh_hi = lo + (hi - lo) * (first + 1) / 65.0;
-        if (first > 0) sh_lo = lo + (hi - lo) * first / 65.0;
+        sh_hi = lo + (hi - lo) * (first + 1) / 257.0;
+        if (first > 0) sh_lo = lo + (hi - lo) * first / 257.0;
       }
     }
     __syncthreads();
   }
   // sigma below the spectrum; retry lower until L D L^T is positive definite
-  if (lane == 0) {
+  if (tid == 0) {
     const double lmin = sh_lo;
     double margin = fmax(1e-3 * fabs(lmin), 64.0 * 0x1.0p-52 * tn) + 1e-300;
     bool ok = false;
@@ -443,12 +453,12 @@ __global__ void __launch_bounds__(64) root_kernel(int m, double *__restrict__ wo
     misc[4] = (sh_hi > sigma ? misc[2] - sigma : 1.0) * (1.0 + 1e-12) + 1e-300;
   }
   __syncthreads();
-  for (int i = lane; i < m; i += 64) {
+  for (int i = tid; i < m; i += blockDim.x) {
     D[i] = Dl[i];
     Ls[i] = Ll[i];
     LLD[i] = Ll[i] * Ll[i] * Dl[i];
   }
-  if (lane == 0 && !sh_ok) flag[0] = 1;
+  if (tid == 0 && !sh_ok) flag[0] = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -535,7 +545,6 @@ __global__ void __launch_bounds__(64) vector_kernel(int m, double *__restrict__ 
   double *__restrict__ Lp = work + Lw.scr;
   double *__restrict__ Um = work + Lw.scr + (size_t)m * m;
   double *__restrict__ sv = work + Lw.scr + 2 * (size_t)m * m;
-  double *__restrict__ pv = work + Lw.scr + 3 * (size_t)m * m;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
   const double tiny = 1e-300;
@@ -554,37 +563,38 @@ __global__ void __launch_bounds__(64) vector_kernel(int m, double *__restrict__ 
       s = lp * Ls[i] * s - lam;
     }
     sv[(size_t)(m - 1) * m + j] = s;
-    // progressive: L D L^T - lam I = U- D- U-^T
+    // progressive: L D L^T - lam I = U- D- U-^T, with the twist index taken on the way:
+    // r minimises |gamma_k| = |s_k + p_k + lam| (the smallest k among equal values)
     double p = D[m - 1] - lam;
-    pv[(size_t)(m - 1) * m + j] = p;
+    double gmin = sv[(size_t)(m - 1) * m + j] + p + lam;
+    r = m - 1;
+#pragma unroll 4
     for (int i = m - 2; i >= 0; --i) {
+      const double si = sv[(size_t)i * m + j];
       double dm = LLD[i] + p;
       if (fabs(dm) < tiny) dm = -tiny;
       const double t = D[i] / dm;
       Um[(size_t)i * m + j] = Ls[i] * t;
       p = p * t - lam;
-      pv[(size_t)i * m + j] = p;
-    }
-    // twist index
-    double gmin = 0.0;
-    r = 0;
-    for (int k = 0; k < m; ++k) {
-      const double gk = sv[(size_t)k * m + j] + pv[(size_t)k * m + j] + lam;
-      if (k == 0 || fabs(gk) < fabs(gmin)) {
+      const double gk = si + p + lam;
+      if (fabs(gk) <= fabs(gmin)) {
         gmin = gk;
-        r = k;
+        r = i;
       }
     }
-    // vector with z_r = 1
+    // vector with z_r = 1 (the factors' loads do not depend on z: unrolled, they are in
+    // flight together)
     nrm2 = 1.0;
     Z[(size_t)j * m + r] = 1.0;
     double z = 1.0;
+#pragma unroll 8
     for (int i = r - 1; i >= 0; --i) {
       z = -Lp[(size_t)i * m + j] * z;
       Z[(size_t)j * m + i] = z;
       nrm2 += z * z;
     }
     z = 1.0;
+#pragma unroll 8
     for (int i = r; i < m - 1; ++i) {
       z = -Um[(size_t)i * m + j] * z;
       Z[(size_t)j * m + i + 1] = z;
@@ -596,6 +606,7 @@ __global__ void __launch_bounds__(64) vector_kernel(int m, double *__restrict__ 
     lam += corr;
   }
   const double inv = 1.0 / sqrt(nrm2);
+#pragma unroll 8
   for (int i = 0; i < m; ++i) Z[(size_t)j * m + i] *= inv;
   mu[j] = lam;
 }
@@ -842,7 +853,7 @@ hipError_t launch_eig(int m, const double *K, double *lam, double *Z, double *wo
                        (size_t)(2 * m + kTriThreads) * sizeof(double), st, m, K, work, nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(root_kernel, dim3(1), dim3(64), (size_t)4 * m * sizeof(double), st, m, work,
+  hipLaunchKernelGGL(root_kernel, dim3(1), dim3(256), (size_t)4 * m * sizeof(double), st, m, work,
                      flag, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(bisect_kernel, dim3((m + 3) / 4), dim3(256), (size_t)2 * m * sizeof(double), st,
@@ -865,7 +876,7 @@ hipError_t launch_eig_batched(int nprob, int maxm, const EigJob *jobs, hipStream
                      (size_t)4 * maxm * sizeof(double), st, 0, nullptr, nullptr, jobs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(root_kernel, dim3(1, nprob), dim3(64), (size_t)4 * maxm * sizeof(double), st,
+  hipLaunchKernelGGL(root_kernel, dim3(1, nprob), dim3(256), (size_t)4 * maxm * sizeof(double), st,
                      0, nullptr, nullptr, jobs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(bisect_kernel, dim3((maxm + 3) / 4, nprob), dim3(256),

@@ -774,6 +774,9 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
 // 6. Back-transformation Z <- H_0 ... H_{m-3} Z, eigenvalues lam = mu + sigma in
 //    descending order. One wave per column.
 // ---------------------------------------------------------------------------
+// PER entries of the column per lane (64 PER >= m): 5, 9 or 17, chosen from m at launch, so
+// a small m carries no dead entries.
+template <int PER>
 __global__ void __launch_bounds__(256)
     backtransform_kernel(int m, const double *__restrict__ work, double *__restrict__ lam,
                          double *__restrict__ Vout, const EigJob *__restrict__ jobs) {
@@ -786,41 +789,74 @@ __global__ void __launch_bounds__(256)
   const int lane = threadIdx.x & 63;
   const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (col >= m) return;
-  constexpr int kMaxPer = 17;  // m <= 1088
-  double z[kMaxPer];
+  double z[PER];
 #pragma unroll
-  for (int q = 0; q < kMaxPer; ++q) {
+  for (int q = 0; q < PER; ++q) {
     const int i = lane + 64 * q;
     z[q] = (i < m) ? Z[(size_t)col * m + i] : 0.0;
   }
-  double vc[kMaxPer], vn[kMaxPer];
-  if (m >= 3) {
+  // Reflectors applied four at a time, k0, k0 - 1, k0 - 2, k0 - 3 (rows of Hv are zero on
+  // and above the diagonal, and rows k < 0 count as zero): one reduction of the four dots
+  // d_b = v_b^T z and the six products g_bc = v_b^T v_c gives the coefficients
+  // t_b = d_b - 2 sum_{c<b} t_c g_bc of z <- z - 2 sum_b t_b v_b, so a wave waits for one
+  // reduction per four reflectors. The next block's rows load during this one's.
+  constexpr int B = 4, NR = B + B * (B - 1) / 2;
+  auto load_block = [&](int k0, double (&v)[B][PER]) {
 #pragma unroll
-    for (int q = 0; q < kMaxPer; ++q) {
-      const int i = lane + 64 * q;
-      vc[q] = (i < m) ? Hv[(size_t)(m - 3) * m + i] : 0.0;
-    }
-  }
-  for (int k = m - 3; k >= 0; --k) {
-    // load the next reflector before the dependent reduction of this one
+    for (int b = 0; b < B; ++b)
 #pragma unroll
-    for (int q = 0; q < kMaxPer; ++q) {
-      const int i = lane + 64 * q;
-      vn[q] = (k > 0 && i < m) ? Hv[(size_t)(k - 1) * m + i] : 0.0;
-    }
-    double dot = 0.0;
+      for (int q = 0; q < PER; ++q) {
+        const int i = lane + 64 * q, k = k0 - b;
+        v[b][q] = (k >= 0 && i < m) ? Hv[(size_t)k * m + i] : 0.0;
+      }
+  };
+  double vb[B][PER], vn[B][PER];
+  load_block(m - 3, vb);
+  for (int k0 = m - 3; k0 >= 0; k0 -= B) {
+    load_block(k0 - B, vn);
+    double r[NR];
 #pragma unroll
-    for (int q = 0; q < kMaxPer; ++q) {
-      const int i = lane + 64 * q;
-      if (i > k && i < m) dot += vc[q] * z[q];
-    }
-    for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
+    for (int b = 0; b < B; ++b) {
+      double d = 0.0;
 #pragma unroll
-    for (int q = 0; q < kMaxPer; ++q) {
-      const int i = lane + 64 * q;
-      if (i > k && i < m) z[q] -= 2.0 * dot * vc[q];
-      vc[q] = vn[q];
+      for (int q = 0; q < PER; ++q) d += vb[b][q] * z[q];
+      r[b] = d;
     }
+    int g = B;
+#pragma unroll
+    for (int b = 1; b < B; ++b)
+#pragma unroll
+      for (int c = 0; c < b; ++c) {
+        double d = 0.0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) d += vb[b][q] * vb[c][q];
+        r[g++] = d;
+      }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int t = 0; t < NR; ++t) r[t] += __shfl_xor(r[t], o, 64);
+    double tc[B];
+    g = B;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      double t = r[b];
+#pragma unroll
+      for (int c = 0; c < b; ++c) t -= 2.0 * tc[c] * r[g + c];
+      if (b > 0) g += b;
+      tc[b] = t;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      double u = 0.0;
+#pragma unroll
+      for (int b = 0; b < B; ++b) u += tc[b] * vb[b][q];
+      z[q] -= 2.0 * u;
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int q = 0; q < PER; ++q) vb[b][q] = vn[b][q];
   }
   // ascending index col -> descending position m-1-col (ties keep a stable order)
   const double lj = mu[col] + misc[3];
@@ -832,10 +868,21 @@ __global__ void __launch_bounds__(256)
   for (int o = 32; o > 0; o >>= 1) rank += __shfl_xor(rank, o, 64);
   if (lane == 0) lam[rank] = lj;
 #pragma unroll
-  for (int q = 0; q < kMaxPer; ++q) {
+  for (int q = 0; q < PER; ++q) {
     const int i = lane + 64 * q;
     if (i < m) Vout[(size_t)rank * m + i] = z[q];
   }
+}
+
+// back-transform launch with the per-lane count for m (mmax: the largest m of the launch)
+void launch_backtransform(dim3 grid, int mmax, int m, const double *work, double *lam, double *Z,
+                          const EigJob *jobs, hipStream_t st) {
+  if (mmax <= 5 * 64)
+    hipLaunchKernelGGL(backtransform_kernel<5>, grid, dim3(256), 0, st, m, work, lam, Z, jobs);
+  else if (mmax <= 9 * 64)
+    hipLaunchKernelGGL(backtransform_kernel<9>, grid, dim3(256), 0, st, m, work, lam, Z, jobs);
+  else
+    hipLaunchKernelGGL(backtransform_kernel<17>, grid, dim3(256), 0, st, m, work, lam, Z, jobs);
 }
 
 }  // namespace
@@ -864,7 +911,7 @@ hipError_t launch_eig(int m, const double *K, double *lam, double *Z, double *wo
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(cluster_kernel, dim3(1), dim3(256), 0, st, m, work, flag, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(backtransform_kernel, dim3((m + 3) / 4), dim3(256), 0, st, m, work, lam, Z, nullptr);
+  launch_backtransform(dim3((m + 3) / 4), m, m, work, lam, Z, nullptr, st);
   return hipGetLastError();
 }
 
@@ -887,8 +934,7 @@ hipError_t launch_eig_batched(int nprob, int maxm, const EigJob *jobs, hipStream
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(cluster_kernel, dim3(1, nprob), dim3(256), 0, st, 0, nullptr, nullptr, jobs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(backtransform_kernel, dim3((maxm + 3) / 4, nprob), dim3(256), 0, st, 0,
-                     nullptr, nullptr, nullptr, jobs);
+  launch_backtransform(dim3((maxm + 3) / 4, nprob), maxm, 0, nullptr, nullptr, nullptr, jobs, st);
   return hipGetLastError();
 }
 

@@ -277,6 +277,7 @@ __global__ void __launch_bounds__(kCholThreads)
   if (run && run[0] == 0) return;
   __shared__ double D[kPB][kPB + 1];
   __shared__ double Di[kPB][kPB + 1];  // Di[k][j] = (L11^{-1})[j][k]
+  __shared__ double rdg[kPB];          // 1 / L11[k][k]
   __shared__ double Pn[kPB * (kStageRows + 1)];
   __shared__ double red[16];
   __shared__ int bad, use_inv;
@@ -298,9 +299,17 @@ __global__ void __launch_bounds__(kCholThreads)
     const bool shifted = (mode == 1);
     const double s = shifted ? shift_rel * fro : 0.0;
     if (shifted && tid == 0 && shifts) shifts[0] += 1;
-    for (size_t idx = tid; idx < (size_t)m * m; idx += nt) {
-      const int i = (int)(idx % m), j = (int)(idx / m);
-      L[idx] = (i >= j) ? (G[idx] + (i == j ? s : 0.0)) : 0.0;
+    {
+      // (i, j) of idx advanced by nt each iteration without a division per element
+      const int step_i = nt % m, step_j = nt / m;
+      int i = tid % m, j = tid / m;
+#pragma unroll 4
+      for (size_t idx = tid; idx < (size_t)m * m; idx += nt) {
+        L[idx] = (i >= j) ? (G[idx] + (i == j ? s : 0.0)) : 0.0;
+        i += step_i;
+        j += step_j;
+        if (i >= m) i -= m, ++j;
+      }
     }
     if (tid == 0) bad = 0;
     __syncthreads();
@@ -332,6 +341,7 @@ __global__ void __launch_bounds__(kCholThreads)
             if (!(piv > 0.0)) fail = true;
             if (!fail) {
               const double rkk = sqrt(piv), rinv = 1.0 / rkk;
+              if (lane == 0) rdg[k] = rinv;
               if (lane > k) r[k] *= rinv;
               if (lane == k) r[k] = rkk;
               const double lik = r[k];
@@ -354,14 +364,16 @@ __global__ void __launch_bounds__(kCholThreads)
         // inverse of the factor: lane c solves L11 x = e_c (x in registers, L11 read as
         // LDS broadcasts); Di[c][i] = (L11^{-1})[i][c]
         if (!fail && lane < kPB) {
+          // four partial sums per row shorten the dependent chain; the pivots' reciprocals
+          // come from the factorization
           const int c = lane;
           double x[kPB];
 #pragma unroll
           for (int i = 0; i < kPB; ++i) {
-            double acc = (i == c) ? 1.0 : 0.0;
+            double acc[4] = {(i == c) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int t = 0; t < i; ++t) acc -= D[i][t] * x[t];  // x[t] = 0 for t < c
-            x[i] = (i >= c && i < nb) ? acc / D[i][i] : 0.0;
+            for (int t = 0; t < i; ++t) acc[t & 3] -= D[i][t] * x[t];  // x[t] = 0 for t < c
+            x[i] = (i >= c && i < nb) ? ((acc[0] + acc[1]) + (acc[2] + acc[3])) * rdg[i] : 0.0;
           }
 #pragma unroll
           for (int i = 0; i < kPB; ++i) Di[c][i] = x[i];

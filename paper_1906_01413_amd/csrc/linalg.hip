@@ -668,6 +668,78 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// The same solve with the workgroup's 32-row strip of X held in LDS for m <= kStripM: the
+// strip is read once and written once, and the solved column blocks that every later
+// block's contraction needs are LDS operands instead of global re-reads.
+constexpr int kStripM = 288;
+
+__global__ void __launch_bounds__(256)
+    trsm_rlt_inv_strip_kernel(int rows, int m, double *__restrict__ X, int ldx,
+                              const double *__restrict__ L, const double *__restrict__ dinv,
+                              const int *__restrict__ run) {
+  if (run && run[0] == 0) return;
+  __shared__ double xs[kStripM * 33];  // xs[j 33 + i] = X[r0 + i][j]
+  __shared__ double red[4][32][33];
+  __shared__ double Bm[32 * 33];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lg = lane >> 4;
+  const int r0 = blockIdx.x * 32;
+  if (r0 >= rows) return;
+  const int nr = min(32, rows - r0);
+  for (int idx = tid; idx < 32 * m; idx += 256) {
+    const int i = idx & 31, j = idx >> 5;
+    xs[j * 33 + i] = (i < nr) ? X[(size_t)j * ldx + r0 + i] : 0.0;
+  }
+  __syncthreads();
+  for (int jb = 0; jb * 32 < m; ++jb) {
+    const int c0 = jb * 32, nc = min(32, m - c0);
+    // 1. wave w: X[:, k0:k1] L[c0:, k0:k1]^T over its quarter of [0, c0), X from the strip
+    const int k0 = (c0 * wave) / 4, k1 = (c0 * (wave + 1)) / 4;
+    d4 acc[2][2];
+    zero_acc(acc);
+    if (k1 > k0)
+      wave_mma32<false, true>(xs + k0 * 33, 33, L + c0 + (size_t)k0 * m, m, k1 - k0, nr, nc, acc);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[wave][16 * rt + lg + 4 * r][16 * ct + li] = acc[rt][ct][r];
+    __syncthreads();
+    if (wave == 0) {
+      // 2. B = X[:, jb] - sum of the partial products, column-major in LDS
+      for (int idx = lane; idx < 32 * 32; idx += 64) {
+        const int i = idx & 31, j = idx >> 5;
+        double v = 0.0;
+        if (i < nr && j < nc)
+          v = xs[(c0 + j) * 33 + i] - (red[0][i][j] + red[1][i][j] + red[2][i][j] + red[3][i][j]);
+        Bm[i + 33 * j] = v;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // 3. X[:, jb] = B L_jb^{-T}, into the strip
+      d4 q[2][2];
+      zero_acc(q);
+      wave_mma32<false, true>(Bm, 33, dinv + (size_t)jb * 1024, 32, nc, nr, nc, q);
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * rt + lg + 4 * r, col = 16 * ct + li;
+            if (row < nr && col < nc) xs[(c0 + col) * 33 + row] = q[rt][ct][r];
+          }
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < 32 * m; idx += 256) {
+    const int i = idx & 31, j = idx >> 5;
+    if (i < nr) X[(size_t)j * ldx + r0 + i] = xs[j * 33 + i];
+  }
+}
+
 // K <- (K + K^T)/2 over the strict lower triangle, many workgroups; per-block partial
 // sums of ||K - K^T||^2 and ||K||^2 are reduced by symmetrize_norm_kernel in fixed order.
 __global__ void __launch_bounds__(256) symmetrize_kernel(int m, double *__restrict__ K,
@@ -891,8 +963,12 @@ hipError_t launch_trsm_diag_inv(int m, const double *L, double *dinv, hipStream_
 hipError_t launch_trsm_rlt_inv(int rows, int m, double *X, int ldx, const double *L,
                                const double *dinv, hipStream_t st, const int *run) {
   if (rows <= 0 || m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(trsm_rlt_inv_kernel, dim3((rows + 31) / 32), dim3(256), 0, st, rows, m, X,
-                     ldx, L, dinv, run);
+  if (m <= kStripM)
+    hipLaunchKernelGGL(trsm_rlt_inv_strip_kernel, dim3((rows + 31) / 32), dim3(256), 0, st, rows,
+                       m, X, ldx, L, dinv, run);
+  else
+    hipLaunchKernelGGL(trsm_rlt_inv_kernel, dim3((rows + 31) / 32), dim3(256), 0, st, rows, m, X,
+                       ldx, L, dinv, run);
   return hipGetLastError();
 }
 

@@ -345,11 +345,11 @@ __global__ void __launch_bounds__(kCholThreads)
               if (lane > k) r[k] *= rinv;
               if (lane == k) r[k] = rkk;
               const double lik = r[k];
+              // every lane updates every column after k: entries above a lane's diagonal (and
+              // the zero rows past nb) take finite updates that are never read, and no exec
+              // mask changes per column
 #pragma unroll
-              for (int j = k + 1; j < kPB; ++j) {
-                const double ljk = readlane_d(lik, j);
-                if (j <= lane && lane < nb) r[j] -= lik * ljk;
-              }
+              for (int j = k + 1; j < kPB; ++j) r[j] -= lik * readlane_d(lik, j);
             }
           }
         }

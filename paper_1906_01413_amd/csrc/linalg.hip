@@ -313,90 +313,98 @@ __global__ void __launch_bounds__(kCholThreads)
     }
     if (tid == 0) bad = 0;
     __syncthreads();
-    for (int kb = 0; kb < m && !bad; kb += kPB) {
-      const int nb = min(kPB, m - kb);
-      // 1. diagonal block in LDS, factored by wave 0 alone (no workgroup barriers inside)
+    // Factor the diagonal block held in D (lower part, nb x nb) by wave 0 alone: L11 in D,
+    // its inverse in Di, the pivots' reciprocals in rdg, use_inv from the block's condition;
+    // bad = 1 on breakdown. No workgroup barrier inside.
+    auto factor_block = [&](int nb) {
+      // lane i keeps row i of the diagonal block in registers; the pivot and column k
+      // are broadcast from the owning lanes' registers (v_readlane), not through LDS
+      const int lane = tid & 63;
+      double r[kPB];
+#pragma unroll
+      for (int j = 0; j < kPB; ++j) r[j] = (lane < nb && j <= lane) ? D[lane][j] : 0.0;
+      bool fail = false;
+#pragma unroll
+      for (int k = 0; k < kPB; ++k) {
+        if (k < nb && !fail) {
+          double piv = readlane_d(r[k], k);  // uniform: every lane sees the same pivot
+          if (!isfinite(piv)) fail = true;
+          if (floor_piv > 0.0 && !(piv > floor_piv)) {
+            piv = floor_piv;
+            if (lane == 0) modified = 1;
+          }
+          if (!(piv > 0.0)) fail = true;
+          if (!fail) {
+            const double rkk = sqrt(piv), rinv = 1.0 / rkk;
+            if (lane == 0) rdg[k] = rinv;
+            if (lane > k) r[k] *= rinv;
+            if (lane == k) r[k] = rkk;
+            const double lik = r[k];
+            // every lane updates every column after k: entries above a lane's diagonal (and
+            // the zero rows past nb) take finite updates that are never read, and no exec
+            // mask changes per column
+#pragma unroll
+            for (int j = k + 1; j < kPB; ++j) r[j] -= lik * readlane_d(lik, j);
+          }
+        }
+      }
+      if (fail && lane == 0) bad = 1;
+      if (lane < nb) {
+#pragma unroll
+        for (int j = 0; j < kPB; ++j)
+          if (j <= lane) D[lane][j] = r[j];
+      }
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      __builtin_amdgcn_wave_barrier();
+      // inverse of the factor: lane c solves L11 x = e_c (x in registers, L11 read as
+      // LDS broadcasts); Di[c][i] = (L11^{-1})[i][c]
+      if (!fail && lane < kPB) {
+        // four partial sums per row shorten the dependent chain; the pivots' reciprocals
+        // come from the factorization
+        const int c = lane;
+        double x[kPB];
+#pragma unroll
+        for (int i = 0; i < kPB; ++i) {
+          double acc[4] = {(i == c) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int t = 0; t < i; ++t) acc[t & 3] -= D[i][t] * x[t];  // x[t] = 0 for t < c
+          x[i] = (i >= c && i < nb) ? ((acc[0] + acc[1]) + (acc[2] + acc[3])) * rdg[i] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < kPB; ++i) Di[c][i] = x[i];
+      }
+      // 1-norm condition of the block, kappa = |L11|_1 |L11^{-1}|_1: lane c sums column c
+      // of the factor and of its inverse
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      __builtin_amdgcn_wave_barrier();
+      double cl = 0.0, ci = 0.0;
+      if (!fail && lane < nb) {
+        for (int i = lane; i < nb; ++i) {
+          cl += fabs(D[i][lane]);
+          ci += fabs(Di[lane][i]);
+        }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        cl = fmax(cl, __shfl_xor(cl, off));
+        ci = fmax(ci, __shfl_xor(ci, off));
+      }
+      if (lane == 0) use_inv = (cl * ci <= kCholInvCond);
+    };
+    // first diagonal block
+    {
+      const int nb = min(kPB, m);
       for (int idx = tid; idx < nb * nb; idx += nt) {
         const int i = idx % nb, j = idx / nb;
-        D[i][j] = (i >= j) ? L[(size_t)(kb + j) * m + kb + i] : 0.0;
+        D[i][j] = (i >= j) ? L[(size_t)j * m + i] : 0.0;
       }
       __syncthreads();
-      if (wave == 0) {
-        // lane i keeps row i of the diagonal block in registers; the pivot and column k
-        // are broadcast from the owning lanes' registers (v_readlane), not through LDS
-        const int lane = tid & 63;
-        double r[kPB];
-#pragma unroll
-        for (int j = 0; j < kPB; ++j) r[j] = (lane < nb && j <= lane) ? D[lane][j] : 0.0;
-        bool fail = false;
-#pragma unroll
-        for (int k = 0; k < kPB; ++k) {
-          if (k < nb && !fail) {
-            double piv = readlane_d(r[k], k);  // uniform: every lane sees the same pivot
-            if (!isfinite(piv)) fail = true;
-            if (floor_piv > 0.0 && !(piv > floor_piv)) {
-              piv = floor_piv;
-              if (lane == 0) modified = 1;
-            }
-            if (!(piv > 0.0)) fail = true;
-            if (!fail) {
-              const double rkk = sqrt(piv), rinv = 1.0 / rkk;
-              if (lane == 0) rdg[k] = rinv;
-              if (lane > k) r[k] *= rinv;
-              if (lane == k) r[k] = rkk;
-              const double lik = r[k];
-              // every lane updates every column after k: entries above a lane's diagonal (and
-              // the zero rows past nb) take finite updates that are never read, and no exec
-              // mask changes per column
-#pragma unroll
-              for (int j = k + 1; j < kPB; ++j) r[j] -= lik * readlane_d(lik, j);
-            }
-          }
-        }
-        if (fail && lane == 0) bad = 1;
-        if (lane < nb) {
-#pragma unroll
-          for (int j = 0; j < kPB; ++j)
-            if (j <= lane) D[lane][j] = r[j];
-        }
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        __builtin_amdgcn_wave_barrier();
-        // inverse of the factor: lane c solves L11 x = e_c (x in registers, L11 read as
-        // LDS broadcasts); Di[c][i] = (L11^{-1})[i][c]
-        if (!fail && lane < kPB) {
-          // four partial sums per row shorten the dependent chain; the pivots' reciprocals
-          // come from the factorization
-          const int c = lane;
-          double x[kPB];
-#pragma unroll
-          for (int i = 0; i < kPB; ++i) {
-            double acc[4] = {(i == c) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int t = 0; t < i; ++t) acc[t & 3] -= D[i][t] * x[t];  // x[t] = 0 for t < c
-            x[i] = (i >= c && i < nb) ? ((acc[0] + acc[1]) + (acc[2] + acc[3])) * rdg[i] : 0.0;
-          }
-#pragma unroll
-          for (int i = 0; i < kPB; ++i) Di[c][i] = x[i];
-        }
-        // 1-norm condition of the block, kappa = |L11|_1 |L11^{-1}|_1: lane c sums column c
-        // of the factor and of its inverse
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        __builtin_amdgcn_wave_barrier();
-        double cl = 0.0, ci = 0.0;
-        if (!fail && lane < nb) {
-          for (int i = lane; i < nb; ++i) {
-            cl += fabs(D[i][lane]);
-            ci += fabs(Di[lane][i]);
-          }
-        }
-        for (int off = 32; off >= 1; off >>= 1) {
-          cl = fmax(cl, __shfl_xor(cl, off));
-          ci = fmax(ci, __shfl_xor(ci, off));
-        }
-        if (lane == 0) use_inv = (cl * ci <= kCholInvCond);
-      }
+      if (wave == 0) factor_block(nb);
       __syncthreads();
-      if (bad) break;
+    }
+    for (int kb = 0; kb < m && !bad; kb += kPB) {
+      const int nb = min(kPB, m - kb);
+      // 1. the diagonal block, factored (before the loop, or during the previous panel's
+      //    trailing update), goes to L
       for (int idx = tid; idx < nb * nb; idx += nt) {
         const int i = idx % nb, j = idx / nb;
         if (i >= j) L[(size_t)(kb + j) * m + kb + i] = D[i][j];
@@ -459,10 +467,12 @@ __global__ void __launch_bounds__(kCholThreads)
       }
       __syncthreads();
       // 3. trailing update A22 -= L21 L21^T on the lower 32 x 32 tiles (MFMA operands
-      //    from the staged panel when it fits)
+      //    from the staged panel when it fits), with look-ahead: wave 0 updates the next
+      //    diagonal tile (tile 0) into L and D and factors it while the other waves update
+      //    the remaining tiles, so the next panel starts with its diagonal block factored.
       const int nt32 = (prow + 31) / 32;
       const int ntiles = nt32 * (nt32 + 1) / 2;
-      for (int t = wave; t < ntiles; t += nwaves) {
+      auto trailing_tile = [&](int t, bool to_D) {
         int I = 0, rem = t;
         while (rem > I) {
           rem -= I + 1;
@@ -486,8 +496,22 @@ __global__ void __launch_bounds__(kCholThreads)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int row = i0 + 16 * rt + lg + 4 * r, col = j0 + 16 * ct + li;
-              if (row < m && col < m && row >= col) L[(size_t)col * m + row] -= acc[rt][ct][r];
+              if (row < m && col < m && row >= col) {
+                const double v = L[(size_t)col * m + row] - acc[rt][ct][r];
+                L[(size_t)col * m + row] = v;
+                if (to_D) D[row - i0][col - j0] = v;
+              }
             }
+      };
+      if (wave == 0) {
+        if (ntiles > 0) {
+          trailing_tile(0, true);
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+          __builtin_amdgcn_wave_barrier();
+          factor_block(min(kPB, prow));
+        }
+      } else {
+        for (int t = wave; t < ntiles; t += nwaves - 1) trailing_tile(t, false);
       }
       __syncthreads();
     }

@@ -451,7 +451,9 @@ def main():
         return
 
     def step(i):
-        r.linearize(xb, want_cost=False, out=(d, g))
+        # the gradient's adjoint sweep runs on the handle's second stream beside the RSVD,
+        # which needs only the trajectory; the increment waits for it
+        r.linearize(xb, want_cost=False, out=(d, g), defer_gradient=True)
         r.rsvd(k, p_os, q=q, Omega=None, seed=1000 + i, want_info=False, lam=lam, V=V)
         r.increment(lam, V, g, k=m, want_host=False, dz=dz, dx=dx)
         r.posterior_cov(lam, V, k=m, want_host=False, out=(Wc, coef, diag))

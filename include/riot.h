@@ -129,6 +129,18 @@ riot_status riot_set_obs(riot_handle *h, const double *y);
 riot_status riot_linearize(riot_handle *h, const double *x, const double *v,
                            double *d, double *grad, double *J_host);
 
+/* riot_linearize with the gradient's adjoint sweep and its L on a second stream of the
+ * handle (created on first use, default priority), so that they run beside the calls
+ * enqueued next: riot_rsvd and riot_hess_apply need only the trajectory, not the gradient
+ * (Alg. 3 uses g only in the increment). d and J_host are complete as for riot_linearize;
+ * grad is complete in the handle's stream order after riot_join(h). riot_rsvd,
+ * riot_hess_apply, riot_proj_residual and riot_philox_normal do not join; every other call
+ * on the handle joins first. v and grad must stay allocated and unmodified until the join. */
+riot_status riot_linearize_deferred(riot_handle *h, const double *x, const double *v,
+                                    double *d, double *grad, double *J_host);
+/* The handle's stream waits for a deferred gradient (no-op when none is pending). */
+riot_status riot_join(riot_handle *h);
+
 /* Batched Hessian-probe products (Alg. 3: y_i = A w_i for all probes at once).
  *   m        number of columns, 1..m_max
  *   W [n x m] device, probes (column-major, ld n)

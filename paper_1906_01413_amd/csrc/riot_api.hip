@@ -141,6 +141,20 @@ struct riot_handle {
   double *partial = nullptr, *cvec = nullptr, *scal = nullptr, *cgv = nullptr;
   int *flags = nullptr;
   ModelView mv{};
+  // deferred gradient: lambda_0 of the gradient's adjoint sweep, and a second stream with
+  // its fork / done events (created on the first deferred linearisation)
+  double *LAM0 = nullptr;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_grad = nullptr;
+  bool grad_pending = false;
+  ~riot_handle() {
+    if (side) {
+      (void)hipStreamSynchronize(side);
+      (void)hipStreamDestroy(side);
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_grad) (void)hipEventDestroy(ev_grad);
+  }
 };
 
 // Buffers of the RSVD linear algebra (CholeskyQR, projections, K, eigen-solve), shared by
@@ -189,6 +203,7 @@ size_t carve(riot_handle &h, void *base) {
   const size_t nm = (size_t)n * mm;
   h.LW = c.take<double>(nm);
   h.LAM = c.take<double>(nm);
+  h.LAM0 = c.take<double>(n);
   h.Om = c.take<double>(nm);
   h.Y = c.take<double>(nm);
   h.Q = c.take<double>(nm);
@@ -502,8 +517,18 @@ const char *riot_status_str(riot_status s) {
   return "unknown riot_status";
 }
 
+// The handle's stream waits for a deferred gradient (no-op when none is pending).
+static riot_status join_gradient(riot_handle *h) {
+  if (h->grad_pending) {
+    h->grad_pending = false;
+    RIOT_HIP(hipStreamWaitEvent(h->st, h->ev_grad, 0));
+  }
+  return RIOT_OK;
+}
+
 riot_status riot_set_obs(riot_handle *h, const double *y) {
   if (!h || (h->d.nobs > 0 && !y)) return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
   if (h->d.nobs > 0)
     RIOT_HIP(hipMemcpyAsync(h->y, y, (size_t)h->d.nobs * sizeof(double),
                             hipMemcpyDeviceToDevice, h->st));
@@ -511,19 +536,39 @@ riot_status riot_set_obs(riot_handle *h, const double *y) {
   return RIOT_OK;
 }
 
-riot_status riot_linearize(riot_handle *h, const double *x, const double *v, double *d,
-                           double *grad, double *J_host) {
+// Trajectory, innovation and the gradient g = v - L lambda_0 with lambda_0 the adjoint sweep
+// forced by R^{-1} d; with defer, the gradient's sweep and L run on the handle's second
+// stream, beside whatever the caller enqueues next.
+static riot_status linearize_impl(riot_handle *h, const double *x, const double *v, double *d,
+                           double *grad, double *J_host, bool defer) {
   if (!h || !x || !grad || (h->d.nobs > 0 && !d)) return RIOT_E_ARG;
   if (h->d.ckpt_stride > 0) return RIOT_E_STATE;  // only a segment of the window fits
+  riot_status rs = join_gradient(h);
+  if (rs != RIOT_OK) return rs;
   const riot_desc &ds = h->d;
   hipStream_t st = h->st;
   RIOT_HIP(launch_trajectory(h->mv, ds.nsteps, x, nullptr, h->xs64, h->xs32, st));
   if (ds.nobs > 0)
     RIOT_HIP(launch_innovation(h->mv, h->xs64, ds.nobs, h->obs_step, h->obs_idx, h->y, h->rinv,
                                h->u_optr, h->u_olist, d, h->fgrad, h->fp32, st));
-  // gradient: g = v - L lambda_0 with lambda_0 the adjoint sweep forced by R^{-1} d
-  RIOT_HIP(launch_tlad(h->mv, 1, 1, nullptr, h->LAM, nullptr, h->fgrad, h->fp32, st));
-  RIOT_HIP(launch_apply_L(ds.n, h->w, h->taps, 1, h->LAM, grad, v, 2, st));
+  hipStream_t gs = st;
+  if (defer) {
+    if (!h->side) {
+      // default priority, no implicit synchronisation with the null stream
+      RIOT_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+      RIOT_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+      RIOT_HIP(hipEventCreateWithFlags(&h->ev_grad, hipEventDisableTiming));
+    }
+    RIOT_HIP(hipEventRecord(h->ev_fork, st));
+    RIOT_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    gs = h->side;
+  }
+  RIOT_HIP(launch_tlad(h->mv, 1, 1, nullptr, h->LAM0, nullptr, h->fgrad, h->fp32, gs));
+  RIOT_HIP(launch_apply_L(ds.n, h->w, h->taps, 1, h->LAM0, grad, v, 2, gs));
+  if (defer) {
+    RIOT_HIP(hipEventRecord(h->ev_grad, gs));
+    h->grad_pending = true;
+  }
   h->linearized = true;
   if (J_host) {
     RIOT_HIP(launch_cost(ds.n, v, ds.nobs, d, h->rinv, h->scal, st));
@@ -531,6 +576,21 @@ riot_status riot_linearize(riot_handle *h, const double *x, const double *v, dou
     RIOT_HIP(hipStreamSynchronize(st));
   }
   return RIOT_OK;
+}
+
+riot_status riot_linearize(riot_handle *h, const double *x, const double *v, double *d,
+                           double *grad, double *J_host) {
+  return linearize_impl(h, x, v, d, grad, J_host, false);
+}
+
+riot_status riot_linearize_deferred(riot_handle *h, const double *x, const double *v, double *d,
+                                    double *grad, double *J_host) {
+  return linearize_impl(h, x, v, d, grad, J_host, true);
+}
+
+riot_status riot_join(riot_handle *h) {
+  if (!h) return RIOT_E_ARG;
+  return join_gradient(h);
 }
 
 riot_status riot_hess_apply(riot_handle *h, int32_t m, const double *W, double *Y,
@@ -580,6 +640,7 @@ riot_status riot_increment(riot_handle *h, int32_t k, const double *lambda, cons
   if (!h || !lambda || !V || !grad || !dz || !dx || dz == dx || k < 1 || k > h->d.n ||
       k > h->d.m_max)
     return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
   if (mode != RIOT_ADAPTIVE && mode != RIOT_LRA && mode != RIOT_LRU) return RIOT_E_ARG;
   const int n = h->d.n;
   // dx = L dz is enqueued before any host synchronisation of the increment
@@ -605,6 +666,7 @@ riot_status riot_posterior_cov(riot_handle *h, int32_t k, const double *lambda, 
                                riot_update mode, double *W, double *coef, double *diag,
                                double *dense, int32_t *mode_used) {
   if (!h || !lambda || !V || !W || !coef || W == V || k < 1 || k > h->d.n) return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
   if (mode != RIOT_ADAPTIVE && mode != RIOT_LRA && mode != RIOT_LRU) return RIOT_E_ARG;
   if (k > h->d.m_max) return RIOT_E_ARG;
   const int n = h->d.n;
@@ -631,6 +693,7 @@ riot_status riot_posterior_cov(riot_handle *h, int32_t k, const double *lambda, 
 riot_status riot_cg(riot_handle *h, const double *grad, int32_t iters, double rtol, double *dz,
                     double *iterates, int32_t *used) {
   if (!h || !grad || !dz || iters < 0) return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
   if (!h->linearized) return RIOT_E_STATE;
   hipStream_t st = h->st;
   RIOT_HIP(launch_cg(h->mv, h->w, h->taps, grad, iters, rtol, dz, iterates, h->cgv, h->f,
@@ -646,6 +709,7 @@ riot_status riot_cg(riot_handle *h, const double *grad, int32_t iters, double rt
 
 riot_status riot_tl_apply(riot_handle *h, int32_t m, const double *X, double *Z) {
   if (!h || !X || (!Z && h->d.nobs > 0) || m < 1 || m > h->d.m_max) return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
   if (!h->linearized) return RIOT_E_STATE;
   hipStream_t st = h->st;
   RIOT_HIP(launch_tlad(h->mv, m, 2, X, nullptr, h->f, nullptr, h->fp32, st));
@@ -655,6 +719,7 @@ riot_status riot_tl_apply(riot_handle *h, int32_t m, const double *X, double *Z)
 
 riot_status riot_ad_apply(riot_handle *h, int32_t m, const double *Fo, double *X) {
   if (!h || !X || (!Fo && h->d.nobs > 0) || m < 1 || m > h->d.m_max) return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
   if (!h->linearized) return RIOT_E_STATE;
   hipStream_t st = h->st;
   RIOT_HIP(launch_obs_scatter(h->d.nobs, h->U, m, h->u_optr, h->u_olist, Fo, h->f, h->fp32, st));
@@ -685,6 +750,7 @@ static int segment_count(const riot_handle *h) {
 
 riot_status riot_ckpt_forward(riot_handle *h, const double *x0, double *ckpt, double *obs) {
   if (!h || !x0 || !ckpt || (h->d.nobs > 0 && !obs)) return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
   if (h->d.ckpt_stride <= 0) return RIOT_E_STATE;
   const int n = h->d.n, c = h->d.ckpt_stride, ns = segment_count(h);
   hipStream_t st = h->st;
@@ -710,6 +776,7 @@ riot_status riot_ckpt_tangent(riot_handle *h, int32_t m, const double *ckpt, con
                               double *dObs) {
   if (!h || !ckpt || !dX0 || (h->d.nobs > 0 && !dObs) || m < 1 || m > h->d.m_max)
     return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
   if (h->d.ckpt_stride <= 0) return RIOT_E_STATE;
   const int n = h->d.n, ns = std::max(segment_count(h), 1);
   hipStream_t st = h->st;
@@ -733,6 +800,7 @@ riot_status riot_ckpt_adjoint(riot_handle *h, int32_t m, const double *ckpt, con
                               double *gX0) {
   if (!h || !ckpt || !gX0 || (h->d.nobs > 0 && !gObs) || m < 1 || m > h->d.m_max)
     return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
   if (h->d.ckpt_stride <= 0) return RIOT_E_STATE;
   const int n = h->d.n, ns = std::max(segment_count(h), 1);
   hipStream_t st = h->st;
@@ -754,6 +822,7 @@ riot_status riot_ckpt_adjoint(riot_handle *h, int32_t m, const double *ckpt, con
 
 riot_status riot_gn_apply(riot_handle *h, int32_t m, const double *X, double *Y) {
   if (!h || !X || !Y || X == Y || m < 1 || m > h->d.m_max) return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
   if (!h->linearized) return RIOT_E_STATE;
   RIOT_HIP(launch_tlad(h->mv, m, 0, X, Y, h->f, nullptr, h->fp32, h->st));
   return RIOT_OK;
@@ -761,12 +830,14 @@ riot_status riot_gn_apply(riot_handle *h, int32_t m, const double *X, double *Y)
 
 riot_status riot_forecast(riot_handle *h, const double *x0, int32_t nsteps, double *xout) {
   if (!h || !x0 || !xout || nsteps < 0) return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
   RIOT_HIP(launch_trajectory(h->mv, nsteps, x0, xout, nullptr, nullptr, h->st));
   return RIOT_OK;
 }
 
 riot_status riot_apply_L(riot_handle *h, int32_t m, const double *X, double *Y) {
   if (!h || !X || !Y || m < 1 || X == Y) return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
   RIOT_HIP(launch_apply_L(h->d.n, h->w, h->taps, m, X, Y, nullptr, 0, h->st));
   return RIOT_OK;
 }

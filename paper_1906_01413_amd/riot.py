@@ -27,7 +27,8 @@ ADAPTIVE, LRA, LRU = 0, 1, 2
 MODES = {"adaptive": ADAPTIVE, "lra": LRA, "lru": LRU}
 
 EXPORTS = ("riot_workspace_bytes", "riot_init", "riot_free", "riot_status_str",
-           "riot_linearize", "riot_hess_apply", "riot_rsvd", "riot_increment",
+           "riot_linearize", "riot_linearize_deferred", "riot_join", "riot_hess_apply",
+           "riot_rsvd", "riot_increment",
            "riot_posterior_cov", "riot_cg", "riot_forecast", "riot_apply_L",
            "riot_philox_normal", "riot_tl_apply", "riot_ad_apply", "riot_gn_apply",
            "riot_batch_workspace_bytes", "riot_batch_init", "riot_batch_free", "riot_batch_buffers",
@@ -112,6 +113,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "riot_free": (None, [vp]),
         "riot_status_str": (ctypes.c_char_p, [i32]),
         "riot_linearize": (i32, [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]),
+        "riot_linearize_deferred": (i32, [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]),
+        "riot_join": (i32, [vp]),
         "riot_hess_apply": (i32, [vp, i32, vp, vp, i32]),
         "riot_rsvd": (i32, [vp, i32, i32, i32, vp, u64, vp, vp, ctypes.POINTER(_RsvdInfo)]),
         "riot_increment": (i32, [vp, i32, vp, vp, vp, i32, vp, vp, ctypes.POINTER(dbl),
@@ -227,6 +230,8 @@ class RsvdInfo:
 class Riot:
     """One inner-loop problem (eqs. 2-3) bound to a device workspace and a stream."""
 
+    _pending = None  # (v, g) of a deferred gradient, kept allocated until the join
+
     def __init__(self, n, nsteps, dt, forcing, obs_step, obs_idx, y, rinv, taps, m_max,
                  prec=FP64, elems_per_lane=0, device="cuda", ckpt_stride=0):
         self.lib = load_library()
@@ -284,7 +289,11 @@ class Riot:
             pass
 
     # -- calls ---------------------------------------------------------------
-    def linearize(self, x, v=None, want_cost=True, out=None):
+    def linearize(self, x, v=None, want_cost=True, out=None, defer_gradient=False):
+        """Trajectory, innovation and gradient. With defer_gradient the gradient's adjoint
+        sweep runs on the handle's second stream beside the calls that follow (rsvd,
+        hess_apply); g is complete after join(), which increment() and every other call
+        that may read it perform first."""
         x = colmajor(x, self.device)
         v = None if v is None else colmajor(v, self.device)
         if out is None:
@@ -293,9 +302,17 @@ class Riot:
         else:
             d, g = out
         J = ctypes.c_double(0.0)
-        _check(self.lib.riot_linearize(self.h, _ptr(x), _ptr(v), _ptr(d), _ptr(g),
-                                       ctypes.byref(J) if want_cost else None), "riot_linearize")
+        fn = self.lib.riot_linearize_deferred if defer_gradient else self.lib.riot_linearize
+        _check(fn(self.h, _ptr(x), _ptr(v), _ptr(d), _ptr(g),
+                  ctypes.byref(J) if want_cost else None), "riot_linearize")
+        # the second stream reads v and writes g until the join: keep both allocated
+        self._pending = (v, g) if defer_gradient else None
         return d[: self.nobs], g, (J.value if want_cost else None)
+
+    def join(self):
+        """Wait (in the handle's stream order) for a deferred gradient."""
+        _check(self.lib.riot_join(self.h), "riot_join")
+        self._pending = None
 
     def hess_apply(self, W, add_identity=False, out=None):
         W = colmajor(W, self.device)
@@ -341,6 +358,7 @@ class Riot:
         _check(self.lib.riot_increment(self.h, k, _ptr(lam), _ptr(V), _ptr(g), MODES[mode], _ptr(dz),
                                        _ptr(dx), ctypes.byref(dofs) if want_host else None,
                                        ctypes.byref(mu) if want_host else None), "riot_increment")
+        self._pending = None  # the library joined a deferred gradient first
         used = {LRA: "lra", LRU: "lru"}.get(mu.value) if want_host else None
         return dz, dx, (dofs.value if want_host else None), used
 

@@ -42,6 +42,41 @@ def test_fullsize_gradient_and_cost(big):
     assert abs(J - float(z["J"])) <= 1e-11 * abs(float(z["J"]))
 
 
+def test_fullsize_deferred_gradient_equals_inline(big):
+    """riot_linearize_deferred: the gradient's adjoint sweep runs on the handle's second
+    stream beside the RSVD. The inner-loop step (linearise, RSVD, increment) gives bit for bit
+    the same innovation, gradient and cost as with the inline gradient, and the same Ritz
+    values and increment to rounding (the tridiagonalisation accumulates with LDS atomics,
+    whose order varies between runs). After riot_join the gradient is complete without an
+    increment, and a pending one is joined by the next linearisation."""
+    z, p, lin, r, g0, J0 = big
+    xb = torch.tensor(p.xb, device="cuda")
+    v = torch.tensor(0.01 * np.random.default_rng(31).standard_normal(p.n), device="cuda")
+
+    def step(defer):
+        d, g, J = r.linearize(xb, v=v, want_cost=True, defer_gradient=defer)
+        lam, V, _ = r.rsvd(256, 16, q=0, Omega=None, seed=SEED, want_info=False)
+        dz, dx, dofs, mode = r.increment(lam, V, g)
+        return to_np(d), to_np(g), J, to_np(lam), to_np(V), to_np(dx), dofs, mode
+
+    a = step(False)
+    b = step(True)
+    for x, y in zip(a[:3], b[:3]):  # d, g, J
+        assert np.array_equal(x, y)
+    lam_a, lam_b = a[3], b[3]
+    assert np.max(np.abs(lam_a - lam_b)) <= 1e-12 * lam_a[0]
+    assert rel(a[5], b[5]) < 1e-9  # dx
+    assert abs(a[6] - b[6]) <= 1e-10 * a[6] and a[7] == b[7]  # dofs, mode
+    # join without an increment: the gradient is complete in stream order
+    _, g1, _ = r.linearize(xb, v=v, want_cost=False, defer_gradient=True)
+    r.join()
+    assert np.array_equal(to_np(g1), a[1])
+    # a deferred gradient left pending is joined by the next linearisation
+    r.linearize(xb, want_cost=False, defer_gradient=True)
+    _, g2, _ = r.linearize(xb, want_cost=False)
+    assert rel(to_np(g2), z["g"]) < 1e-10
+
+
 def _rounding_floor(p, lin, W):
     """Relative change of the oracle's products when the linearisation state moves by one ulp.
 

@@ -842,25 +842,39 @@ __device__ __forceinline__ bool use_lru(int mode_lru, const double *lam, int k) 
   return !(lam[k - 1] >= 1.0);  // adaptive (eq. 11)
 }
 
-__global__ void increment_kernel(int n, int k, const double *__restrict__ lam,
-                                 const double *__restrict__ V, const double *__restrict__ c,
-                                 const double *__restrict__ g, int mode_lru,
-                                 double *__restrict__ dz, double *__restrict__ dofs,
-                                 const IncJob *__restrict__ jobs) {
+// Rows are split four ways: a workgroup takes 64 rows, wave w sums the columns j = w (mod 4)
+// of each row, and the four partial sums are added in a fixed order through LDS, so a row's
+// dependent chain is k / 4 long (and deterministic).
+constexpr int kRowsPerWg = 64;
+
+__global__ void __launch_bounds__(256)
+    increment_kernel(int n, int k, const double *__restrict__ lam,
+                     const double *__restrict__ V, const double *__restrict__ c,
+                     const double *__restrict__ g, int mode_lru,
+                     double *__restrict__ dz, double *__restrict__ dofs,
+                     const IncJob *__restrict__ jobs) {
   if (jobs) {  // batched: blockIdx.y selects the problem
     const IncJob &J = jobs[blockIdx.y];
     n = J.n, k = J.k, lam = J.lam, V = J.V, c = J.c, g = J.g, dz = J.dz, dofs = J.dofs;
   }
+  __shared__ double part[4][kRowsPerWg];
   const bool lru = use_lru(mode_lru, lam, k);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * kRowsPerWg + r;
+  double s = 0.0;
   if (i < n) {
-    double s = 0.0;
-    for (int j = 0; j < k; ++j) {
+#pragma unroll 4
+    for (int j = w; j < k; j += 4) {
       const double lj = lam[j];
       const double a = lru ? lj / (1.0 + lj) : 1.0 / (1.0 + lj);
       s += V[(size_t)j * n + i] * (c[j] * a);
     }
-    dz[i] = lru ? -(g[i] - s) : -s;
+  }
+  part[w][r] = s;
+  __syncthreads();
+  if (w == 0 && i < n) {
+    const double t = (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
+    dz[i] = lru ? -(g[i] - t) : -t;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && dofs) {
     double d = 0.0;
@@ -873,27 +887,36 @@ __global__ void choose_mode_kernel(int k, const double *__restrict__ lam, int *_
   if (threadIdx.x == 0) out[0] = (lam[k - 1] >= 1.0) ? (int)RIOT_LRA : (int)RIOT_LRU;
 }
 
-__global__ void postcov_diag_kernel(int n, int k, const double *__restrict__ lam,
-                                    const double *__restrict__ W, int mode_lru, double base_diag,
-                                    double *__restrict__ coef, double *__restrict__ diag) {
+// The same four-way split of each row's sum over the k columns of W.
+__global__ void __launch_bounds__(256)
+    postcov_diag_kernel(int n, int k, const double *__restrict__ lam,
+                        const double *__restrict__ W, int mode_lru, double base_diag,
+                        double *__restrict__ coef, double *__restrict__ diag) {
+  __shared__ double part[4][kRowsPerWg];
   const bool lru = use_lru(mode_lru, lam, k);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (blockIdx.x == 0 && coef) {
     for (int j = threadIdx.x; j < k; j += blockDim.x) {
       const double lj = lam[j];
       coef[j] = lru ? -lj / (1.0 + lj) : 1.0 / (1.0 + lj);
     }
   }
-  if (i < n && diag) {
-    double s = lru ? base_diag : 0.0;
-    for (int j = 0; j < k; ++j) {
+  if (!diag) return;
+  const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * kRowsPerWg + r;
+  double s = 0.0;
+  if (i < n) {
+#pragma unroll 4
+    for (int j = w; j < k; j += 4) {
       const double lj = lam[j];
       const double cj = lru ? -lj / (1.0 + lj) : 1.0 / (1.0 + lj);
-      const double w = W[(size_t)j * n + i];
-      s += cj * w * w;
+      const double x = W[(size_t)j * n + i];
+      s += cj * x * x;
     }
-    diag[i] = s;
   }
+  part[w][r] = s;
+  __syncthreads();
+  if (w == 0 && i < n)
+    diag[i] = (lru ? base_diag : 0.0) + ((part[0][r] + part[1][r]) + (part[2][r] + part[3][r]));
 }
 
 __global__ void dense_B_kernel(int n, const double *__restrict__ brow, double beta,
@@ -1052,8 +1075,8 @@ hipError_t launch_fro_ratio(long long count, const double *R, const double *A, d
 hipError_t launch_increment_combine(int n, int k, const double *lam, const double *V,
                                     const double *c, const double *g, int mode_lru, double *dz,
                                     double *dofs, hipStream_t st) {
-  hipLaunchKernelGGL(increment_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, k, lam, V, c, g,
-                     mode_lru, dz, dofs, nullptr);
+  hipLaunchKernelGGL(increment_kernel, dim3((n + kRowsPerWg - 1) / kRowsPerWg), dim3(256), 0, st, n,
+                     k, lam, V, c, g, mode_lru, dz, dofs, nullptr);
   return hipGetLastError();
 }
 
@@ -1064,8 +1087,8 @@ hipError_t launch_choose_mode(int k, const double *lam, int *out, hipStream_t st
 
 hipError_t launch_postcov_diag(int n, int k, const double *lam, const double *W, int mode_lru,
                                double base_diag, double *coef, double *diag, hipStream_t st) {
-  hipLaunchKernelGGL(postcov_diag_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, k, lam, W,
-                     mode_lru, base_diag, coef, diag);
+  hipLaunchKernelGGL(postcov_diag_kernel, dim3((n + kRowsPerWg - 1) / kRowsPerWg), dim3(256), 0, st,
+                     n, k, lam, W, mode_lru, base_diag, coef, diag);
   return hipGetLastError();
 }
 
@@ -1205,8 +1228,8 @@ hipError_t launch_symmetrize_batched(int nprob, const SymJob *jobs, hipStream_t 
 hipError_t launch_increment_batched(int nprob, int maxn, int mode_lru, const IncJob *jobs,
                                     hipStream_t st) {
   if (nprob <= 0 || maxn <= 0) return hipSuccess;
-  hipLaunchKernelGGL(increment_kernel, dim3((maxn + 255) / 256, nprob), dim3(256), 0, st, 0, 0,
-                     nullptr, nullptr, nullptr, nullptr, mode_lru, nullptr, nullptr, jobs);
+  hipLaunchKernelGGL(increment_kernel, dim3((maxn + kRowsPerWg - 1) / kRowsPerWg, nprob), dim3(256), 0,
+                     st, 0, 0, nullptr, nullptr, nullptr, nullptr, mode_lru, nullptr, nullptr, jobs);
   return hipGetLastError();
 }
 

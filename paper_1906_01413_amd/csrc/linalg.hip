@@ -259,9 +259,11 @@ __device__ __forceinline__ double readlane_d(double v, int src) {
 // Blocked Cholesky G + s I = L L^T (lower, column-major), one workgroup.
 // mode 0: s = 0; mode 1: s = shift_rel ||G||_F; mode 2: s = 0, and a pivot that is not
 // above shift_rel ||G||_F is replaced by that value (modified Cholesky). Per 32-column
-// panel: wave 0 factors the diagonal block in registers and inverts the factor; the
-// panel below is X = A21 L11^{-T} on the FP64 matrix cores; the trailing lower triangle
-// is updated with FP64 MFMA (one wave per 32 x 32 tile).
+// panel: wave 0 factors the diagonal block in registers, inverts the factor and takes the
+// block's condition; the panel below is X = A21 L11^{-T}, on the FP64 matrix cores with
+// the inverse when the block is well conditioned, else by forward substitution; the
+// trailing lower triangle is updated with FP64 MFMA (32 x 32 tiles), wave 0 taking the
+// next diagonal tile and factoring it while the other waves update the rest.
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kCholThreads)

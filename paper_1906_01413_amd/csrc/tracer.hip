@@ -10,9 +10,10 @@
 // adjoint need the base emissions only, never a stored trajectory.
 //
 // Layout: fields [member][y][x] (x fastest); controls [member][time block][by][bx].
-// Each step is one launch over (tile, member): a 64 x 16 tile of cells plus a one-cell
-// halo is staged in LDS, so every row segment is read as one coalesced 512-byte run; each
-// thread computes four rows of the tile.
+// The sweeps run two steps per launch over (tile, member): a 64 x 16 tile of cells plus a
+// two-cell halo is staged in LDS (every row segment one coalesced run), the intermediate
+// field stays in LDS, and each thread computes four rows of the tile. An odd last step
+// uses the single-step kernels, which stage a one-cell halo.
 
 #include <algorithm>
 #include <cmath>
@@ -25,6 +26,7 @@ namespace riot {
 namespace {
 
 // cell tile kTX x kTY, threads kTX x kWY; thread (lx, ly) owns rows ly + kWY r, r < kRY
+// (kRY ly + r in the adjoint pair kernel, for its control-block sums)
 constexpr int kTX = 64, kWY = 4, kRY = 4, kTY = kWY * kRY;
 constexpr int kThreads = kTX * kWY;
 constexpr int kHX = kTX + 2, kHY = kTY + 2;

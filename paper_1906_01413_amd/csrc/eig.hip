@@ -524,91 +524,142 @@ __global__ void __launch_bounds__(256) bisect_kernel(int m, double *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// 4. Eigenvectors by twisted factorisation: one thread per eigenvalue. The
-//    per-eigenvalue arrays live in scratch laid out [i][j] (coalesced in j).
+// 4. Eigenvectors by twisted factorisation, two waves per 64 eigenvalues: lane l of both
+//    waves of a workgroup takes eigenvalue j = 64 blockIdx.x + l. Wave 0 runs the
+//    stationary transform (top down) while wave 1 runs the progressive one (bottom up);
+//    each wave scans half of the twist range and the two halves are combined through LDS
+//    (the smaller |gamma|, the smaller index on ties); wave 0 builds the vector above the
+//    twist and wave 1 below it. The per-eigenvalue arrays live in scratch laid out [i][j]
+//    (coalesced in j); workgroup barriers order the exchanges. Every thread runs the three
+//    Rayleigh-quotient passes' barriers; an eigenvalue that has converged skips the work.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) vector_kernel(int m, double *__restrict__ work,
-                                                    const EigJob *__restrict__ jobs) {
+__global__ void __launch_bounds__(128) vector_kernel(int m, double *__restrict__ work,
+                                                     const EigJob *__restrict__ jobs) {
   if (jobs) m = jobs[blockIdx.y].m, work = jobs[blockIdx.y].work;
-  if ((int)(blockIdx.x * blockDim.x) >= m) return;
+  if ((int)(blockIdx.x * 64) >= m) return;
   EigLayout Lw(m);
   extern __shared__ double vsh[];
   double *D = vsh, *Ls = vsh + m, *LLD = vsh + 2 * m;
+  __shared__ double xg[2][64], xn[2][64];
+  __shared__ int xr[2][64];
   for (int i = threadIdx.x; i < m; i += blockDim.x) {
     D[i] = work[Lw.D + i];
     Ls[i] = work[Lw.Ls + i];
     LLD[i] = work[Lw.LLD + i];
   }
   __syncthreads();
-  double *__restrict__ mu = work + Lw.mu;
-  double *__restrict__ Z = work + Lw.Z;
-  double *__restrict__ Lp = work + Lw.scr;
-  double *__restrict__ Um = work + Lw.scr + (size_t)m * m;
-  double *__restrict__ sv = work + Lw.scr + 2 * (size_t)m * m;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m) return;
+  double *mu = work + Lw.mu;
+  double *Z = work + Lw.Z;
+  double *Lp = work + Lw.scr;
+  double *Um = work + Lw.scr + (size_t)m * m;
+  double *sv = work + Lw.scr + 2 * (size_t)m * m;
+  double *pv = work + Lw.scr + 3 * (size_t)m * m;
+  const int l = threadIdx.x & 63, role = threadIdx.x >> 6;  // role: wave-uniform
+  const int j = blockIdx.x * 64 + l;
+  const bool act = j < m;
   const double tiny = 1e-300;
-  double lam = mu[j];
+  double lam = act ? mu[j] : 0.0;
   int r = 0;
   double nrm2 = 1.0;
+  bool done = !act;
   for (int it = 0; it < 3; ++it) {
-    // stationary: L D L^T - lam I = L+ D+ L+^T
-    double s = -lam;
-    for (int i = 0; i < m - 1; ++i) {
-      sv[(size_t)i * m + j] = s;
-      double dp = D[i] + s;
-      if (fabs(dp) < tiny) dp = -tiny;
-      const double lp = D[i] * Ls[i] / dp;
-      Lp[(size_t)i * m + j] = lp;
-      s = lp * Ls[i] * s - lam;
-    }
-    sv[(size_t)(m - 1) * m + j] = s;
-    // progressive: L D L^T - lam I = U- D- U-^T, with the twist index taken on the way:
-    // r minimises |gamma_k| = |s_k + p_k + lam| (the smallest k among equal values)
-    double p = D[m - 1] - lam;
-    double gmin = sv[(size_t)(m - 1) * m + j] + p + lam;
-    r = m - 1;
-#pragma unroll 4
-    for (int i = m - 2; i >= 0; --i) {
-      const double si = sv[(size_t)i * m + j];
-      double dm = LLD[i] + p;
-      if (fabs(dm) < tiny) dm = -tiny;
-      const double t = D[i] / dm;
-      Um[(size_t)i * m + j] = Ls[i] * t;
-      p = p * t - lam;
-      const double gk = si + p + lam;
-      if (fabs(gk) <= fabs(gmin)) {
-        gmin = gk;
-        r = i;
+    if (!done) {
+      if (role == 0) {
+        // stationary: L D L^T - lam I = L+ D+ L+^T
+        double s = -lam;
+        for (int i = 0; i < m - 1; ++i) {
+          sv[(size_t)i * m + j] = s;
+          double dp = D[i] + s;
+          if (fabs(dp) < tiny) dp = -tiny;
+          const double lp = D[i] * Ls[i] / dp;
+          Lp[(size_t)i * m + j] = lp;
+          s = lp * Ls[i] * s - lam;
+        }
+        sv[(size_t)(m - 1) * m + j] = s;
+      } else {
+        // progressive: L D L^T - lam I = U- D- U-^T
+        double p = D[m - 1] - lam;
+        pv[(size_t)(m - 1) * m + j] = p;
+        for (int i = m - 2; i >= 0; --i) {
+          double dm = LLD[i] + p;
+          if (fabs(dm) < tiny) dm = -tiny;
+          const double t = D[i] / dm;
+          Um[(size_t)i * m + j] = Ls[i] * t;
+          p = p * t - lam;
+          pv[(size_t)i * m + j] = p;
+        }
       }
     }
-    // vector with z_r = 1 (the factors' loads do not depend on z: unrolled, they are in
-    // flight together)
-    nrm2 = 1.0;
-    Z[(size_t)j * m + r] = 1.0;
-    double z = 1.0;
-#pragma unroll 8
-    for (int i = r - 1; i >= 0; --i) {
-      z = -Lp[(size_t)i * m + j] * z;
-      Z[(size_t)j * m + i] = z;
-      nrm2 += z * z;
+    __syncthreads();
+    // twist index: r minimises |gamma_k| = |s_k + p_k + lam| (the smallest k on ties); wave 0
+    // scans the lower half of the range
+    if (!done) {
+      const int h = m / 2, k0 = role ? h : 0, k1 = role ? m : h;
+      double gmin = 0.0;
+      int rl = -1;
+#pragma unroll 4
+      for (int k = k0; k < k1; ++k) {
+        const double gk = sv[(size_t)k * m + j] + pv[(size_t)k * m + j] + lam;
+        if (rl < 0 || fabs(gk) < fabs(gmin)) {
+          gmin = gk;
+          rl = k;
+        }
+      }
+      xg[role][l] = gmin;
+      xr[role][l] = rl;
     }
-    z = 1.0;
+    __syncthreads();
+    double gmin = 0.0;
+    if (!done) {
+      const bool take_low = xr[0][l] >= 0 && (xr[1][l] < 0 || fabs(xg[0][l]) <= fabs(xg[1][l]));
+      gmin = take_low ? xg[0][l] : xg[1][l];
+      r = take_low ? xr[0][l] : xr[1][l];
+      // vector with z_r = 1: wave 0 builds z_i for i < r, wave 1 for i > r
+      double part;
+      if (role == 0) {
+        Z[(size_t)j * m + r] = 1.0;
+        part = 1.0;
+        double z = 1.0;
 #pragma unroll 8
-    for (int i = r; i < m - 1; ++i) {
-      z = -Um[(size_t)i * m + j] * z;
-      Z[(size_t)j * m + i + 1] = z;
-      nrm2 += z * z;
+        for (int i = r - 1; i >= 0; --i) {
+          z = -Lp[(size_t)i * m + j] * z;
+          Z[(size_t)j * m + i] = z;
+          part += z * z;
+        }
+      } else {
+        part = 0.0;
+        double z = 1.0;
+#pragma unroll 8
+        for (int i = r; i < m - 1; ++i) {
+          z = -Um[(size_t)i * m + j] * z;
+          Z[(size_t)j * m + i + 1] = z;
+          part += z * z;
+        }
+      }
+      xn[role][l] = part;
     }
-    // Rayleigh-quotient correction of lam (gamma_r / ||z||^2)
-    const double corr = gmin / nrm2;
-    if (!(fabs(corr) > 2.0 * 0x1.0p-53 * fabs(lam))) break;
-    lam += corr;
+    __syncthreads();
+    if (!done) {
+      nrm2 = xn[0][l] + xn[1][l];
+      // Rayleigh-quotient correction of lam (gamma_r / ||z||^2), the same in both waves
+      const double corr = gmin / nrm2;
+      if (!(fabs(corr) > 2.0 * 0x1.0p-53 * fabs(lam)))
+        done = true;
+      else
+        lam += corr;
+    }
+    __syncthreads();  // the exchange buffers are reused by the next pass
   }
+  if (!act) return;
   const double inv = 1.0 / sqrt(nrm2);
+  if (role == 0) {
 #pragma unroll 8
-  for (int i = 0; i < m; ++i) Z[(size_t)j * m + i] *= inv;
-  mu[j] = lam;
+    for (int i = 0; i <= r; ++i) Z[(size_t)j * m + i] *= inv;
+    mu[j] = lam;
+  } else {
+#pragma unroll 8
+    for (int i = r + 1; i < m; ++i) Z[(size_t)j * m + i] *= inv;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -906,7 +957,7 @@ hipError_t launch_eig(int m, const double *K, double *lam, double *Z, double *wo
   hipLaunchKernelGGL(bisect_kernel, dim3((m + 3) / 4), dim3(256), (size_t)2 * m * sizeof(double), st,
                      m, work, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(vector_kernel, dim3((m + 63) / 64), dim3(64), (size_t)3 * m * sizeof(double), st,
+  hipLaunchKernelGGL(vector_kernel, dim3((m + 63) / 64), dim3(128), (size_t)3 * m * sizeof(double), st,
                      m, work, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(cluster_kernel, dim3(1), dim3(256), 0, st, m, work, flag, nullptr);
@@ -929,7 +980,7 @@ hipError_t launch_eig_batched(int nprob, int maxm, const EigJob *jobs, hipStream
   hipLaunchKernelGGL(bisect_kernel, dim3((maxm + 3) / 4, nprob), dim3(256),
                      (size_t)2 * maxm * sizeof(double), st, 0, nullptr, jobs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(vector_kernel, dim3((maxm + 63) / 64, nprob), dim3(64),
+  hipLaunchKernelGGL(vector_kernel, dim3((maxm + 63) / 64, nprob), dim3(128),
                      (size_t)3 * maxm * sizeof(double), st, 0, nullptr, jobs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(cluster_kernel, dim3(1, nprob), dim3(256), 0, st, 0, nullptr, nullptr, jobs);

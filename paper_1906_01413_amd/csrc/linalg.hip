@@ -413,9 +413,10 @@ __global__ void __launch_bounds__(kCholThreads)
       }
       // 2. panel rows below: X L11^T = A21 (the panel is staged in LDS first when it fits;
       //    the result goes to L and to the staged copy). A well-conditioned block: X =
-      //    A21 L11^{-T}, one 32-row MFMA tile per wave. Otherwise forward substitution per
-      //    row, whose residual stays at rounding level whatever the block's condition (the
-      //    product with the inverse leaves a residual of order kappa times rounding).
+      //    A21 L11^{-T}, one 32-row MFMA tile per wave. Otherwise the product with the
+      //    inverse leaves a residual of order kappa times rounding: a staged panel adds one
+      //    refinement step on MFMA, a panel too tall to stage is solved by forward
+      //    substitution per row, whose residual stays at rounding level.
       const int r0 = kb + nb;
       const int prow = m - r0;
       const bool staged = prow <= kStageRows;
@@ -425,19 +426,76 @@ __global__ void __launch_bounds__(kCholThreads)
             Pn[jj * (kStageRows + 1) + ii] = L[(size_t)(kb + jj) * m + r0 + ii];
       }
       __syncthreads();
-      if (!use_inv) {
-        // in place in the panel's own storage (LDS when staged), row by row:
+      if (!use_inv && staged) {
+        // ill-conditioned block, staged panel: X0 = A L11^{-T} (into L; A stays in the staged
+        // copy), R = A - X0 L11^T (into the staged copy), X = X0 + R L11^{-T}: one step of
+        // refinement brings the residual back to rounding level, on the matrix cores
+        const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
+        const int npt = (prow + 31) / 32, ld = kStageRows + 1;
+        for (int I = wave; I < npt; I += nwaves) {
+          const int i0 = 32 * I;
+          d4 acc[2][2];
+          zero_acc(acc);
+          wave_mma32<false, true>(Pn + i0, ld, &Di[0][0], kPB + 1, nb, prow - i0, nb, acc);
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+              for (int rr = 0; rr < 4; ++rr) {
+                const int row = i0 + 16 * rt + lg + 4 * rr, col = 16 * ct + li;
+                if (row < prow && col < nb) L[(size_t)(kb + col) * m + r0 + row] = acc[rt][ct][rr];
+              }
+        }
+        __syncthreads();
+        for (int I = wave; I < npt; I += nwaves) {
+          const int i0 = 32 * I;
+          d4 acc[2][2];
+          zero_acc(acc);
+          wave_mma32<false, false>(L + (size_t)kb * m + r0 + i0, m, &D[0][0], kPB + 1, nb,
+                                   prow - i0, nb, acc);
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+              for (int rr = 0; rr < 4; ++rr) {
+                const int row = i0 + 16 * rt + lg + 4 * rr, col = 16 * ct + li;
+                if (row < prow && col < nb) Pn[col * ld + row] -= acc[rt][ct][rr];
+              }
+        }
+        __syncthreads();
+        for (int I = wave; I < npt; I += nwaves) {
+          const int i0 = 32 * I;
+          d4 acc[2][2];
+          zero_acc(acc);
+          wave_mma32<false, true>(Pn + i0, ld, &Di[0][0], kPB + 1, nb, prow - i0, nb, acc);
+          // the MFMAs consumed every operand load of this wave's rows: overwrite them
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+              for (int rr = 0; rr < 4; ++rr) {
+                const int row = i0 + 16 * rt + lg + 4 * rr, col = 16 * ct + li;
+                if (row < prow && col < nb) {
+                  const size_t o = (size_t)(kb + col) * m + r0 + row;
+                  const double x = L[o] + acc[rt][ct][rr];
+                  L[o] = x;
+                  Pn[col * ld + row] = x;
+                }
+              }
+        }
+      } else if (!use_inv) {
+        // in place in the panel's own storage (global), row by row:
         // x_j = (a_j - sum_{t<j} x_t L11[j][t]) / L11[j][j]
-        const int ld = staged ? kStageRows + 1 : m;
         for (int i = tid; i < prow; i += nt) {
-          double *col = staged ? Pn + i : L + (size_t)kb * m + r0 + i;  // element j at col[j ld]
+          double *col = L + (size_t)kb * m + r0 + i;  // element j at col[j m]
           for (int j = 0; j < nb; ++j) {
-            double a = col[(size_t)j * ld];
-            for (int t = 0; t < j; ++t) a -= col[(size_t)t * ld] * D[j][t];
-            col[(size_t)j * ld] = a * Di[j][j];  // Di[j][j] = 1 / L11[j][j]
+            double a = col[(size_t)j * m];
+            for (int t = 0; t < j; ++t) a -= col[(size_t)t * m] * D[j][t];
+            col[(size_t)j * m] = a * Di[j][j];  // Di[j][j] = 1 / L11[j][j]
           }
-          if (staged)
-            for (int j = 0; j < nb; ++j) L[(size_t)(kb + j) * m + r0 + i] = col[j * ld];
         }
       } else {
         const int lane = tid & 63, li = lane & 15, lg = lane >> 4;

@@ -158,175 +158,240 @@ __global__ void __launch_bounds__(kTriThreads)
   }
 }
 
-// Register-resident variant for small m. Columns j and m-1-j of the lower triangle
-// are paired (together m + 1 entries); a group of Tp threads owns one pair, thread tl
-// of the group holding entries r = tl + Tp q of the pair's concatenated rows, so each
-// thread has one run in column j0 and one in column j1 with rows advancing by Tp.
-// The rank-2 update of step k is applied lazily during step k + 1 and the symmetric
-// product uses one FP64 LDS atomic per entry plus one per run. No matrix traffic
-// leaves the CU.
-constexpr int kRegThreads = 1024;
-constexpr int kRegQ = 40;
+// Register-tile variant. The lower triangle of K is cut into 9 x 9 tiles (R, C), R >= C, one
+// tile per lane (81 FP64 registers); diagonal tiles hold the full symmetric block. Lanes are
+// ordered along the block diagonals d = R - C, so the lanes of one wave have (almost) distinct
+// tile rows and tile columns and the LDS atomics of the symmetric product rarely collide.
+// Step k of the reduction is two phases and two barriers:
+//   phase 1  apply the pending rank-2 update of step k-1, with w = p - (v^T p) v formed per lane
+//            from the (v, p) pairs of step k-1, and gather column k and the partial |x|^2;
+//   phase 2  every lane forms the Householder scalars from |x|^2 and x_{k+1} and its own slices
+//            of v (rows and columns of its tile), and adds its tile's share of p = A v (row sums
+//            and, off the diagonal, column sums) and of v^T A v; the diagonal lanes store v.
+// v and p sit side by side (one 16-byte LDS read per index) and, like |x|^2 and v^T p, are
+// double-buffered by step parity, so each buffer is cleared one phase before it fills. No
+// serial phase runs on a single wave.
+constexpr int kTB = 9;
+constexpr int kTileMaxNb = 31;  // m <= 279
+constexpr int kTileMaxThreads = 512;
 
-__host__ __device__ inline int reg_pairs(int m) { return (m + 1) / 2; }
-__host__ __device__ inline int reg_tp(int m) { return kRegThreads / reg_pairs(m); }
-__host__ inline bool reg_fits(int m) {
-  const int tp = reg_tp(m);
-  return m >= 3 && tp >= 1 && (m + 1 + tp - 1) / tp <= kRegQ;
+__host__ __device__ inline int tile_nb(int m) { return (m + kTB - 1) / kTB; }
+__host__ inline int tile_threads(int m) {
+  const int nb = tile_nb(m);
+  return (nb * (nb + 1) / 2 + 63) / 64 * 64;
+}
+__host__ inline bool tile_fits(int m) { return m >= 3 && tile_nb(m) <= kTileMaxNb; }
+
+template <int S>
+__device__ __forceinline__ double tile_gather(const double (&a)[kTB][kTB], int r0, int k,
+                                              double *xs) {
+  const int kr = k - r0;
+  double s2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < kTB; ++t) {
+    if (t >= kr) xs[r0 + t] = a[t][S];
+    s2 = fma((t > kr) ? a[t][S] : 0.0, a[t][S], s2);
+  }
+  return s2;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// a -= v_r (2 w_c)^T + (2 w_r) v_c^T with w = p - kp v on indices >= k (v is already zero
+// below; p is masked here). Offsets within the tile are compared with k - r0 and k - c0, so
+// no per-row index stays live, and the loads are unconditional.
+__device__ __forceinline__ void tile_update(double (&a)[kTB][kTB], const double2 *vp, double kp,
+                                            int r0, int c0, int k) {
+  const int kr = k - r0, kc = k - c0;
+  double vc[kTB], wc[kTB];
+#pragma unroll
+  for (int s = 0; s < kTB; ++s) {
+    const double2 q = vp[c0 + s];
+    vc[s] = q.x;
+    const double w = 2.0 * (q.y - kp * q.x);
+    wc[s] = (s >= kc) ? w : 0.0;
+  }
+  double2 q = vp[r0];
+#pragma unroll
+  for (int t = 0; t < kTB; ++t) {
+    // the next row's (v, p) is in flight while this row updates; one row ahead only, since
+    // hoisting all of them would spill the tile
+    const double2 qn = vp[r0 + (t + 1 < kTB ? t + 1 : t)];
+    const double w = 2.0 * (q.y - kp * q.x);
+    const double wr = (t >= kr) ? w : 0.0;
+#pragma unroll
+    for (int s = 0; s < kTB; ++s) a[t][s] = fma(-q.x, wc[s], fma(-wr, vc[s], a[t][s]));
+    __builtin_amdgcn_sched_barrier(0);
+    q = qn;
+  }
 }
 
-__global__ void __launch_bounds__(kRegThreads)
-    tridiag_reg_kernel(int m, const double *__restrict__ K, double *__restrict__ work,
-                       const EigJob *__restrict__ jobs) {
+// column k - c0 of the tile into xs (rows >= k); returns the tile's part of |x|^2 below row k
+__device__ __forceinline__ double tile_gather_col(const double (&a)[kTB][kTB], int r0, int c0,
+                                                  int k, double *xs) {
+  switch (k - c0) {
+    case 0: return tile_gather<0>(a, r0, k, xs);
+    case 1: return tile_gather<1>(a, r0, k, xs);
+    case 2: return tile_gather<2>(a, r0, k, xs);
+    case 3: return tile_gather<3>(a, r0, k, xs);
+    case 4: return tile_gather<4>(a, r0, k, xs);
+    case 5: return tile_gather<5>(a, r0, k, xs);
+    case 6: return tile_gather<6>(a, r0, k, xs);
+    case 7: return tile_gather<7>(a, r0, k, xs);
+    default: return tile_gather<8>(a, r0, k, xs);
+  }
+}
+
+// v^T A v is accumulated by LDS atomics spread over kKpSlots words (lane pairs share one), which
+// is cheaper than a wave reduction by shuffles, and summed by broadcast reads when it is used
+constexpr int kKpSlots = 16;
+__device__ __forceinline__ double kp_sum(const double2 *slots) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < kKpSlots / 2; ++i) s += slots[i].x + slots[i].y;
+  return s;
+}
+
+__global__ void __launch_bounds__(kTileMaxThreads)
+    tridiag_tile_kernel(int m, const double *__restrict__ K, double *__restrict__ work,
+                        const EigJob *__restrict__ jobs) {
   if (jobs) m = jobs[blockIdx.y].m, K = jobs[blockIdx.y].K, work = jobs[blockIdx.y].work;
-  extern __shared__ double sh[];
+  __shared__ double2 vpb[2][kTB * kTileMaxNb];
+  __shared__ double xs[kTB * kTileMaxNb];
+  __shared__ double s2b[2];
+  __shared__ double2 kpb[2][kKpSlots / 2];
   EigLayout Lw(m);
   double *Hv = work + Lw.Hv, *dg = work + Lw.d, *eg = work + Lw.e;
-  double *v = sh, *w = sh + m, *p = sh + 2 * m, *x = sh + 3 * m;
-  const int tid = threadIdx.x;
-  const int Tp = reg_tp(m), pairs = reg_pairs(m);
-  const int pr = tid / Tp, tl = tid - pr * Tp;
-  const bool own = pr < pairs;
-  const int j0 = own ? pr : 0;
-  const int j1 = m - 1 - j0;             // == j0 for the middle column of odd m
-  const int len0 = m - j0;               // rows j0..m-1
-  const bool has1 = own && (j1 != j0);   // second column present
-  const int base0 = j0 + tl, base1 = j1 + tl - len0;
-  // first q that falls in column j1
-  const int qs = own ? max(0, (len0 - tl + Tp - 1) / Tp) : 0;
-  double a[kRegQ];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int nb = tile_nb(m), mp = nb * kTB;
+  // lane -> tile along the block diagonals
+  int d = 0, C = tid;
+  while (d < nb && C >= nb - d) C -= nb - (d++);
+  const bool own = d < nb;
+  if (!own) C = 0;
+  const int r0 = (C + d) * kTB, c0 = C * kTB;
+  const bool diag = d == 0;
+  double a[kTB][kTB];
 #pragma unroll
-  for (int q = 0; q < kRegQ; ++q) {
-    a[q] = 0.0;
-    if (!own) continue;
-    if (q < qs) {
-      const int i = base0 + Tp * q;
-      a[q] = K[(size_t)j0 * m + i];
-    } else if (has1) {
-      const int i = base1 + Tp * q;
-      if (i < m) a[q] = K[(size_t)j1 * m + i];
+  for (int t = 0; t < kTB; ++t)
+#pragma unroll
+    for (int s = 0; s < kTB; ++s) {
+      const int i = r0 + t, j = c0 + s;
+      a[t][s] = (own && i < m && j < m) ? K[(size_t)min(i, j) * m + max(i, j)] : 0.0;
     }
+  for (int i = tid; i < mp; i += nt) {
+    vpb[0][i] = make_double2(0.0, 0.0);
+    vpb[1][i] = make_double2(0.0, 0.0);
+    xs[i] = 0.0;
   }
-  for (int i = tid; i < m; i += kRegThreads) {
-    v[i] = 0.0;
-    w[i] = 0.0;
-  }
-  for (size_t idx = tid; idx < (size_t)m * m; idx += kRegThreads) Hv[idx] = 0.0;
+  if (tid < 2) s2b[tid] = 0.0;
+  if (tid < kKpSlots) kpb[tid / (kKpSlots / 2)][tid % (kKpSlots / 2)] = make_double2(0.0, 0.0);
+  for (size_t idx = tid; idx < (size_t)m * m; idx += nt) Hv[idx] = 0.0;
   __syncthreads();
   for (int k = 0; k + 2 < m; ++k) {
-    // phase 1: pending rank-2 update of step k-1 on columns >= k; gather column k
-    if (own && (j0 >= k || (has1 && j1 >= k))) {
-      int b0 = base0, b1 = base1;
-      // keep the per-entry row indices out of registers across steps (recomputed per phase)
-      asm volatile("" : "+v"(b0), "+v"(b1));
-      const double vj0 = v[j0], wj0 = w[j0], vj1 = v[j1], wj1 = w[j1];
+    const int cur = k & 1, prv = cur ^ 1;
+    const int cb = k / kTB;
+    // phase 1
+    if (own && c0 + kTB > k) {
+      if (k > 0) tile_update(a, vpb[prv], kp_sum(kpb[prv]), r0, c0, k);
+      if (C == cb) {
+        const double s2 = tile_gather_col(a, r0, c0, k, xs);
+        if (s2 != 0.0) atomicAdd(&s2b[cur], s2);
+      }
+    }
+    for (int i = tid; i < mp; i += nt) vpb[cur][i] = make_double2(0.0, 0.0);
+    if (tid < kKpSlots / 2) kpb[cur][tid] = make_double2(0.0, 0.0);
+    __syncthreads();
+    // phase 2
+    const double s2 = s2b[cur], x0 = xs[k + 1];
+    const double sig = sqrt(s2);
+    const double alpha = (x0 >= 0.0) ? -sig : sig;
+    const double rvn = (sig != 0.0) ? 1.0 / sqrt(2.0 * (s2 - alpha * x0)) : 0.0;
+    if (tid == 0) {
+      dg[k] = xs[k];
+      eg[k] = (sig != 0.0) ? alpha : 0.0;
+      s2b[prv] = 0.0;
+    }
+    double kpart = 0.0;
+    if (own && c0 + kTB - 1 > k) {
+      // v on the tile's rows and columns, then the row sums, then the column sums; the fences
+      // keep one stage's work from being hoisted into the previous one
+      const int kr = k - r0, kc = k - c0;
+      const double h = x0 - alpha;
+      double vr[kTB], vc[kTB];
 #pragma unroll
-      for (int q = 0; q < kRegQ; ++q) {
-        if (q < qs) {
-          if (j0 >= k) {
-            const int i = b0 + Tp * q;
-            a[q] -= 2.0 * (v[i] * wj0 + w[i] * vj0);
-            if (j0 == k) x[i] = a[q];
+      for (int s = 0; s < kTB; ++s) {
+        const double xv = (s == kc + 1) ? h : xs[c0 + s];
+        vc[s] = (s > kc) ? xv * rvn : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < kTB; ++t) {
+        const double xv = (t == kr + 1) ? h : xs[r0 + t];
+        vr[t] = (t > kr) ? xv * rvn : 0.0;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      // row sums two rows at a time (two independent FMA chains)
+#pragma unroll
+      for (int t = 0; t < kTB; t += 2) {
+        double rp0 = 0.0, rp1 = 0.0;
+#pragma unroll
+        for (int s = 0; s < kTB; ++s) {
+          rp0 = fma(a[t][s], vc[s], rp0);
+          if (t + 1 < kTB) rp1 = fma(a[t + 1][s], vc[s], rp1);
+        }
+        if (t > kr) atomicAdd(&vpb[cur][r0 + t].y, rp0);
+        kpart = fma(vr[t], rp0, kpart);
+        if (t + 1 < kTB) {
+          if (t + 1 > kr) atomicAdd(&vpb[cur][r0 + t + 1].y, rp1);
+          kpart = fma(vr[t + 1], rp1, kpart);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (diag) {
+#pragma unroll
+        for (int t = 0; t < kTB; ++t) {
+          const int i = r0 + t;
+          if (t > kr) vpb[cur][i].x = vr[t];
+          if (t > kr && i < m) Hv[(size_t)k * m + i] = vr[t];
+        }
+      } else {
+        kpart *= 2.0;
+#pragma unroll
+        for (int s = 0; s < kTB; s += 2) {
+          double cp0 = 0.0, cp1 = 0.0;
+#pragma unroll
+          for (int t = 0; t < kTB; ++t) {
+            cp0 = fma(a[t][s], vr[t], cp0);
+            if (s + 1 < kTB) cp1 = fma(a[t][s + 1], vr[t], cp1);
           }
-        } else if (has1 && j1 >= k) {
-          const int i = b1 + Tp * q;
-          if (i < m) {
-            a[q] -= 2.0 * (v[i] * wj1 + w[i] * vj1);
-            if (j1 == k) x[i] = a[q];
-          }
+          if (s > kc) atomicAdd(&vpb[cur][c0 + s].y, cp0);
+          if (s + 1 < kTB && s + 1 > kc) atomicAdd(&vpb[cur][c0 + s + 1].y, cp1);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
-    __syncthreads();
-    // phase 2 (wave 0): Householder vector of column k
-    if (tid < 64) {
-      double s2 = 0.0;
-      for (int i = k + 1 + tid; i < m; i += 64) s2 += x[i] * x[i];
-      s2 = wave_sum(s2);
-      const double sig = sqrt(s2);
-      const double x0 = x[k + 1];
-      const double alpha = (x0 >= 0.0) ? -sig : sig;
-      const double vn = sqrt(2.0 * (s2 - alpha * x0));
-      for (int i = tid; i < m; i += 64) {
-        double vi = 0.0;
-        if (sig != 0.0 && i > k) vi = ((i == k + 1) ? (x0 - alpha) : x[i]) / vn;
-        v[i] = vi;
-        p[i] = 0.0;
-        if (i > k) Hv[(size_t)k * m + i] = vi;
-      }
-      if (tid == 0) {
-        dg[k] = x[k];
-        eg[k] = (sig != 0.0) ? alpha : 0.0;
-      }
-    }
-    __syncthreads();
-    // phase 3: p = S v over columns > k; row halves by atomics, column halves per run
-    if (own && (j0 > k || (has1 && j1 > k))) {
-      int b0 = base0, b1 = base1;
-      asm volatile("" : "+v"(b0), "+v"(b1));
-      const double vj0 = v[j0], vj1 = v[j1];
-      double c0 = 0.0, c1 = 0.0;
-#pragma unroll
-      for (int q = 0; q < kRegQ; ++q) {
-        if (q < qs) {
-          if (j0 > k) {
-            const int i = b0 + Tp * q;
-            atomicAdd(&p[i], a[q] * vj0);
-            if (i != j0) c0 += a[q] * v[i];
-          }
-        } else if (has1 && j1 > k) {
-          const int i = b1 + Tp * q;
-          if (i < m) {
-            atomicAdd(&p[i], a[q] * vj1);
-            if (i != j1) c1 += a[q] * v[i];
-          }
-        }
-      }
-      if (j0 > k && c0 != 0.0) atomicAdd(&p[j0], c0);
-      if (has1 && j1 > k && c1 != 0.0) atomicAdd(&p[j1], c1);
-    }
-    __syncthreads();
-    // phase 4 (wave 0): w = p - (v^T p) v
-    if (tid < 64) {
-      double kp = 0.0;
-      for (int i = k + 1 + tid; i < m; i += 64) kp += v[i] * p[i];
-      kp = wave_sum(kp);
-      for (int i = tid; i < m; i += 64) w[i] = (i > k) ? p[i] - kp * v[i] : 0.0;
+    if (kpart != 0.0) {
+      double2 *slot = &kpb[cur][(tid >> 1) & (kKpSlots / 2 - 1)];
+      atomicAdd((tid & 1) ? &slot->y : &slot->x, kpart);
     }
     __syncthreads();
   }
-  // last pending update on the trailing 2 x 2 block, then its entries
-  const int kl = m - 2;
-  if (own) {
-    const double vj0 = v[j0], wj0 = w[j0], vj1 = v[j1], wj1 = w[j1];
-#pragma unroll
-    for (int q = 0; q < kRegQ; ++q) {
-      int i = -1, j = -1;
-      double vj = 0.0, wj = 0.0;
-      if (q < qs) {
-        i = base0 + Tp * q;
-        j = j0;
-        vj = vj0;
-        wj = wj0;
-      } else if (has1) {
-        i = base1 + Tp * q;
-        j = j1;
-        vj = vj1;
-        wj = wj1;
-      }
-      if (j >= kl && i < m && i >= 0) {
-        const double val = a[q] - 2.0 * (v[i] * wj + w[i] * vj);
-        if (i == j) dg[i] = val;
-        if (i == j + 1) eg[j] = val;
-      }
-    }
+  // pending update of step m - 3, then the trailing 2 x 2 block, one column at a time
+  const int k = m - 2;
+  if (own && c0 + kTB > k) {
+    tile_update(a, vpb[(k - 1) & 1], kp_sum(kpb[(k - 1) & 1]), r0, c0, k);
+    if (C == k / kTB) tile_gather_col(a, r0, c0, k, xs);
   }
-  if (tid == 0) eg[m - 1] = 0.0;
+  __syncthreads();
+  if (tid == 0) {
+    dg[k] = xs[k];
+    eg[k] = xs[k + 1];
+  }
+  __syncthreads();
+  if (own && C == (k + 1) / kTB) tile_gather_col(a, r0, c0, k + 1, xs);
+  __syncthreads();
+  if (tid == 0) {
+    dg[k + 1] = xs[k + 1];
+    eg[k + 1] = 0.0;
+  }
 }
 
 // Sturm count of T - x I (number of eigenvalues below x).
@@ -943,9 +1008,9 @@ size_t eig_work_doubles(int m) { return EigLayout(m).total; }
 hipError_t launch_eig(int m, const double *K, double *lam, double *Z, double *work, int *flag,
                       hipStream_t st) {
   if (m < 1 || m > 1088) return hipErrorInvalidValue;
-  if (reg_fits(m))
-    hipLaunchKernelGGL(tridiag_reg_kernel, dim3(1), dim3(kRegThreads), (size_t)4 * m * sizeof(double),
-                       st, m, K, work, nullptr);
+  if (tile_fits(m))
+    hipLaunchKernelGGL(tridiag_tile_kernel, dim3(1), dim3(tile_threads(m)), 0, st, m, K, work,
+                       nullptr);
   else
     hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kTriThreads),
                        (size_t)(2 * m + kTriThreads) * sizeof(double), st, m, K, work, nullptr);
@@ -966,12 +1031,12 @@ hipError_t launch_eig(int m, const double *K, double *lam, double *Z, double *wo
   return hipGetLastError();
 }
 
-// Batched: every problem's m must satisfy the register-resident tridiagonalisation bound.
+// Batched: every problem's m must satisfy the register-tile tridiagonalisation bound.
 hipError_t launch_eig_batched(int nprob, int maxm, const EigJob *jobs, hipStream_t st) {
   if (nprob <= 0) return hipSuccess;
-  if (maxm < 1 || !reg_fits(maxm)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(tridiag_reg_kernel, dim3(1, nprob), dim3(kRegThreads),
-                     (size_t)4 * maxm * sizeof(double), st, 0, nullptr, nullptr, jobs);
+  if (maxm < 1 || !tile_fits(maxm)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tridiag_tile_kernel, dim3(1, nprob), dim3(tile_threads(maxm)), 0, st, 0,
+                     nullptr, nullptr, jobs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(root_kernel, dim3(1, nprob), dim3(256), (size_t)4 * maxm * sizeof(double), st,

@@ -164,13 +164,14 @@ __global__ void __launch_bounds__(kTriThreads)
 // tile rows and tile columns and the LDS atomics of the symmetric product rarely collide.
 // Step k of the reduction is two phases and two barriers:
 //   phase 1  apply the pending rank-2 update of step k-1, with w = p - (v^T p) v formed per lane
-//            from the (v, p) pairs of step k-1, and gather column k and the partial |x|^2;
+//            from v and p of step k-1, and gather column k and the partial |x|^2; the block
+//            stores reflector k-1 to global memory;
 //   phase 2  every lane forms the Householder scalars from |x|^2 and x_{k+1} and its own slices
 //            of v (rows and columns of its tile), and adds its tile's share of p = A v (row sums
 //            and, off the diagonal, column sums) and of v^T A v; the diagonal lanes store v.
-// v and p sit side by side (one 16-byte LDS read per index) and, like |x|^2 and v^T p, are
-// double-buffered by step parity, so each buffer is cleared one phase before it fills. No
-// serial phase runs on a single wave.
+// v, p, |x|^2 and v^T p are double-buffered by step parity, so each buffer is cleared one phase
+// before it fills. p has a stride of 9 doubles between the tile rows of consecutive lanes, which
+// spreads their atomics over all LDS banks. No serial phase runs on a single wave.
 constexpr int kTB = 9;
 constexpr int kTileMaxNb = 31;  // m <= 279
 constexpr int kTileMaxThreads = 512;
@@ -198,29 +199,30 @@ __device__ __forceinline__ double tile_gather(const double (&a)[kTB][kTB], int r
 // a -= v_r (2 w_c)^T + (2 w_r) v_c^T with w = p - kp v on indices >= k (v is already zero
 // below; p is masked here). Offsets within the tile are compared with k - r0 and k - c0, so
 // no per-row index stays live, and the loads are unconditional.
-__device__ __forceinline__ void tile_update(double (&a)[kTB][kTB], const double2 *vp, double kp,
-                                            int r0, int c0, int k) {
+__device__ __forceinline__ void tile_update(double (&a)[kTB][kTB], const double *vv,
+                                            const double *pp, double kp, int r0, int c0, int k) {
   const int kr = k - r0, kc = k - c0;
   double vc[kTB], wc[kTB];
 #pragma unroll
   for (int s = 0; s < kTB; ++s) {
-    const double2 q = vp[c0 + s];
-    vc[s] = q.x;
-    const double w = 2.0 * (q.y - kp * q.x);
+    vc[s] = vv[c0 + s];
+    const double w = 2.0 * (pp[c0 + s] - kp * vc[s]);
     wc[s] = (s >= kc) ? w : 0.0;
   }
-  double2 q = vp[r0];
+  double v = vv[r0], p = pp[r0];
 #pragma unroll
   for (int t = 0; t < kTB; ++t) {
-    // the next row's (v, p) is in flight while this row updates; one row ahead only, since
+    // the next row's v and p are in flight while this row updates; one row ahead only, since
     // hoisting all of them would spill the tile
-    const double2 qn = vp[r0 + (t + 1 < kTB ? t + 1 : t)];
-    const double w = 2.0 * (q.y - kp * q.x);
+    const int tn = t + 1 < kTB ? t + 1 : t;
+    const double vn = vv[r0 + tn], pn = pp[r0 + tn];
+    const double w = 2.0 * (p - kp * v);
     const double wr = (t >= kr) ? w : 0.0;
 #pragma unroll
-    for (int s = 0; s < kTB; ++s) a[t][s] = fma(-q.x, wc[s], fma(-wr, vc[s], a[t][s]));
+    for (int s = 0; s < kTB; ++s) a[t][s] = fma(-v, wc[s], fma(-wr, vc[s], a[t][s]));
     __builtin_amdgcn_sched_barrier(0);
-    q = qn;
+    v = vn;
+    p = pn;
   }
 }
 
@@ -254,7 +256,7 @@ __global__ void __launch_bounds__(kTileMaxThreads)
     tridiag_tile_kernel(int m, const double *__restrict__ K, double *__restrict__ work,
                         const EigJob *__restrict__ jobs) {
   if (jobs) m = jobs[blockIdx.y].m, K = jobs[blockIdx.y].K, work = jobs[blockIdx.y].work;
-  __shared__ double2 vpb[2][kTB * kTileMaxNb];
+  __shared__ double vb[2][kTB * kTileMaxNb], pb[2][kTB * kTileMaxNb];
   __shared__ double xs[kTB * kTileMaxNb];
   __shared__ double s2b[2];
   __shared__ double2 kpb[2][kKpSlots / 2];
@@ -278,8 +280,8 @@ __global__ void __launch_bounds__(kTileMaxThreads)
       a[t][s] = (own && i < m && j < m) ? K[(size_t)min(i, j) * m + max(i, j)] : 0.0;
     }
   for (int i = tid; i < mp; i += nt) {
-    vpb[0][i] = make_double2(0.0, 0.0);
-    vpb[1][i] = make_double2(0.0, 0.0);
+    vb[0][i] = vb[1][i] = 0.0;
+    pb[0][i] = pb[1][i] = 0.0;
     xs[i] = 0.0;
   }
   if (tid < 2) s2b[tid] = 0.0;
@@ -291,20 +293,25 @@ __global__ void __launch_bounds__(kTileMaxThreads)
     const int cb = k / kTB;
     // phase 1
     if (own && c0 + kTB > k) {
-      if (k > 0) tile_update(a, vpb[prv], kp_sum(kpb[prv]), r0, c0, k);
+      if (k > 0) tile_update(a, vb[prv], pb[prv], kp_sum(kpb[prv]), r0, c0, k);
       if (C == cb) {
         const double s2 = tile_gather_col(a, r0, c0, k, xs);
         if (s2 != 0.0) atomicAdd(&s2b[cur], s2);
       }
     }
-    for (int i = tid; i < mp; i += nt) vpb[cur][i] = make_double2(0.0, 0.0);
+    for (int i = tid; i < mp; i += nt) {
+      if (k > 0 && i >= k && i < m) Hv[(size_t)(k - 1) * m + i] = vb[prv][i];
+      vb[cur][i] = 0.0;
+      pb[cur][i] = 0.0;
+    }
     if (tid < kKpSlots / 2) kpb[cur][tid] = make_double2(0.0, 0.0);
     __syncthreads();
     // phase 2
     const double s2 = s2b[cur], x0 = xs[k + 1];
-    const double sig = sqrt(s2);
+    // |x| = s2 / sqrt(s2) and 1 / |v| by reciprocal square roots: a short dependent chain
+    const double sig = (s2 > 0.0) ? s2 * rsqrt(s2) : 0.0;
     const double alpha = (x0 >= 0.0) ? -sig : sig;
-    const double rvn = (sig != 0.0) ? 1.0 / sqrt(2.0 * (s2 - alpha * x0)) : 0.0;
+    const double rvn = (sig != 0.0) ? rsqrt(2.0 * (s2 - alpha * x0)) : 0.0;
     if (tid == 0) {
       dg[k] = xs[k];
       eg[k] = (sig != 0.0) ? alpha : 0.0;
@@ -337,10 +344,10 @@ __global__ void __launch_bounds__(kTileMaxThreads)
           rp0 = fma(a[t][s], vc[s], rp0);
           if (t + 1 < kTB) rp1 = fma(a[t + 1][s], vc[s], rp1);
         }
-        if (t > kr) atomicAdd(&vpb[cur][r0 + t].y, rp0);
+        if (t > kr) atomicAdd(&pb[cur][r0 + t], rp0);
         kpart = fma(vr[t], rp0, kpart);
         if (t + 1 < kTB) {
-          if (t + 1 > kr) atomicAdd(&vpb[cur][r0 + t + 1].y, rp1);
+          if (t + 1 > kr) atomicAdd(&pb[cur][r0 + t + 1], rp1);
           kpart = fma(vr[t + 1], rp1, kpart);
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -348,9 +355,7 @@ __global__ void __launch_bounds__(kTileMaxThreads)
       if (diag) {
 #pragma unroll
         for (int t = 0; t < kTB; ++t) {
-          const int i = r0 + t;
-          if (t > kr) vpb[cur][i].x = vr[t];
-          if (t > kr && i < m) Hv[(size_t)k * m + i] = vr[t];
+          if (t > kr) vb[cur][r0 + t] = vr[t];
         }
       } else {
         kpart *= 2.0;
@@ -362,8 +367,8 @@ __global__ void __launch_bounds__(kTileMaxThreads)
             cp0 = fma(a[t][s], vr[t], cp0);
             if (s + 1 < kTB) cp1 = fma(a[t][s + 1], vr[t], cp1);
           }
-          if (s > kc) atomicAdd(&vpb[cur][c0 + s].y, cp0);
-          if (s + 1 < kTB && s + 1 > kc) atomicAdd(&vpb[cur][c0 + s + 1].y, cp1);
+          if (s > kc) atomicAdd(&pb[cur][c0 + s], cp0);
+          if (s + 1 < kTB && s + 1 > kc) atomicAdd(&pb[cur][c0 + s + 1], cp1);
           __builtin_amdgcn_sched_barrier(0);
         }
       }
@@ -377,9 +382,11 @@ __global__ void __launch_bounds__(kTileMaxThreads)
   // pending update of step m - 3, then the trailing 2 x 2 block, one column at a time
   const int k = m - 2;
   if (own && c0 + kTB > k) {
-    tile_update(a, vpb[(k - 1) & 1], kp_sum(kpb[(k - 1) & 1]), r0, c0, k);
+    tile_update(a, vb[(k - 1) & 1], pb[(k - 1) & 1], kp_sum(kpb[(k - 1) & 1]), r0, c0, k);
     if (C == k / kTB) tile_gather_col(a, r0, c0, k, xs);
   }
+  for (int i = tid; i < m; i += nt)
+    if (i >= k) Hv[(size_t)(k - 1) * m + i] = vb[(k - 1) & 1][i];
   __syncthreads();
   if (tid == 0) {
     dg[k] = xs[k];

@@ -326,6 +326,7 @@ __global__ void __launch_bounds__(kCholThreads)
 #pragma unroll
       for (int j = 0; j < kPB; ++j) r[j] = (lane < nb && j <= lane) ? D[lane][j] : 0.0;
       bool fail = false;
+      double myinv = 0.0;  // lane i: 1 / L11[i][i]
 #pragma unroll
       for (int k = 0; k < kPB; ++k) {
         if (k < nb && !fail) {
@@ -339,6 +340,7 @@ __global__ void __launch_bounds__(kCholThreads)
           if (!fail) {
             const double rkk = sqrt(piv), rinv = 1.0 / rkk;
             if (lane == 0) rdg[k] = rinv;
+            if (lane == k) myinv = rinv;
             if (lane > k) r[k] *= rinv;
             if (lane == k) r[k] = rkk;
             const double lik = r[k];
@@ -358,19 +360,20 @@ __global__ void __launch_bounds__(kCholThreads)
       }
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
       __builtin_amdgcn_wave_barrier();
-      // inverse of the factor: lane c solves L11 x = e_c (x in registers, L11 read as
-      // LDS broadcasts); Di[c][i] = (L11^{-1})[i][c]
+      // inverse of the factor: lane c solves L11 x = e_c (x in registers); L11[i][t] and
+      // 1 / L11[i][i] come from lane i's registers (v_readlane), not from LDS, which the
+      // trailing update of the other waves keeps busy meanwhile. Di[c][i] = (L11^{-1})[i][c]
       if (!fail && lane < kPB) {
-        // four partial sums per row shorten the dependent chain; the pivots' reciprocals
-        // come from the factorization
+        // four partial sums per row shorten the dependent chain
         const int c = lane;
         double x[kPB];
 #pragma unroll
         for (int i = 0; i < kPB; ++i) {
           double acc[4] = {(i == c) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int t = 0; t < i; ++t) acc[t & 3] -= D[i][t] * x[t];  // x[t] = 0 for t < c
-          x[i] = (i >= c && i < nb) ? ((acc[0] + acc[1]) + (acc[2] + acc[3])) * rdg[i] : 0.0;
+          for (int t = 0; t < i; ++t) acc[t & 3] -= readlane_d(r[t], i) * x[t];  // x[t] = 0, t < c
+          const double xi = ((acc[0] + acc[1]) + (acc[2] + acc[3])) * readlane_d(myinv, i);
+          x[i] = (i >= c && i < nb) ? xi : 0.0;
         }
 #pragma unroll
         for (int i = 0; i < kPB; ++i) Di[c][i] = x[i];

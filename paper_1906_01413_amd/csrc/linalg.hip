@@ -322,6 +322,8 @@ __global__ void __launch_bounds__(kCholThreads)
       // lane i keeps row i of the diagonal block in registers; the pivot and column k
       // are broadcast from the owning lanes' registers (v_readlane), not through LDS
       const int lane = tid & 63;
+      // captured by reference: read once, not through the capture in every step
+      const double fpiv = floor_piv;
       double r[kPB];
 #pragma unroll
       for (int j = 0; j < kPB; ++j) r[j] = (lane < nb && j <= lane) ? D[lane][j] : 0.0;
@@ -332,13 +334,13 @@ __global__ void __launch_bounds__(kCholThreads)
         if (k < nb && !fail) {
           double piv = readlane_d(r[k], k);  // uniform: every lane sees the same pivot
           if (!isfinite(piv)) fail = true;
-          if (floor_piv > 0.0 && !(piv > floor_piv)) {
-            piv = floor_piv;
+          if (fpiv > 0.0 && !(piv > fpiv)) {
+            piv = fpiv;
             if (lane == 0) modified = 1;
           }
           if (!(piv > 0.0)) fail = true;
           if (!fail) {
-            const double rkk = sqrt(piv), rinv = 1.0 / rkk;
+            const double rinv = rsqrt(piv), rkk = piv * rinv;  // short dependent chain
             if (lane == 0) rdg[k] = rinv;
             if (lane == k) myinv = rinv;
             if (lane > k) r[k] *= rinv;

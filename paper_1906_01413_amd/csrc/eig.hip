@@ -19,6 +19,7 @@
 // Parlett (2004) for the tridiagonal eigenproblem.
 
 #include "riot_internal.h"
+#include "mfma_tile.h"
 
 namespace riot {
 namespace {
@@ -37,7 +38,8 @@ __device__ double wsum(double v, double *red) {
 }
 
 // work layout (doubles): Aw[m*m] Hv[m*m] Z[m*m] d[m] e[m] D[m] Ls[m] LLD[m] mu[m] misc[16]
-//                        scratch for the vector kernel: 4 * m * m
+//                        scratch for the vector kernel: 4 * m * m (at least one 32 x 32
+//                        block per 32 reflectors for the back-transform)
 struct EigLayout {
   size_t Aw, Hv, Z, d, e, D, Ls, LLD, mu, misc, scr, total;
   __host__ __device__ EigLayout(int m) {
@@ -53,7 +55,9 @@ struct EigLayout {
     mu = LLD + m;
     misc = mu + m;
     scr = misc + 16;
-    total = scr + 4 * mm;
+    // the scratch also holds the blocked back-transform's 32 x 32 factors, one per 32 reflectors
+    const size_t wy = (size_t)((m + 31) / 32) * 32 * 32;
+    total = scr + (4 * mm > wy ? 4 * mm : wy);
   }
 };
 
@@ -997,9 +1001,159 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// 6'. Blocked back-transformation (compact WY, m <= kWyMaxM). The reflectors are taken in
+// blocks of 32: Q_b = H_{32b} ... H_{32b+31} = I - V_b T_b V_b^T, with V_b's column j the
+// reflector 32b + j and T_b upper triangular (T_jj = 2 for the unit reflectors, T[0:j, j] =
+// -2 T[0:j, 0:j] V_b[:, 0:j]^T v_j). Z <- Q_0 Q_1 ... Z is applied last block first to strips
+// of 32 columns held in LDS, S <- S - V_b (T_b (V_b^T S)): three MFMA products per block.
+constexpr int kWyB = 32;
+constexpr int kWyMaxM = 288;
+
+// T_b of block blockIdx.x into the scratch area (column-major 32 x 32 per block).
+__global__ void __launch_bounds__(64)
+    wy_t_kernel(int m, double *__restrict__ work, const EigJob *__restrict__ jobs) {
+  if (jobs) m = jobs[blockIdx.y].m, work = jobs[blockIdx.y].work;
+  const int k0 = blockIdx.x * kWyB;
+  if (k0 >= m) return;
+  EigLayout Lw(m);
+  const double *V = work + Lw.Hv + (size_t)k0 * m;  // V[i + j m] = v_{k0+j}[i]
+  double *Tb = work + Lw.scr + (size_t)blockIdx.x * kWyB * kWyB;
+  const int nr = min(kWyB, m - k0);
+  __shared__ double G[kWyB][kWyB + 1], T[kWyB][kWyB + 1];
+  const int lane = threadIdx.x, li = lane & 15, lg = lane >> 4;
+  // G = V^T V over rows k0.. (the reflectors vanish above)
+  d4 acc[2][2];
+  zero_acc(acc);
+  wave_mma32<true, false>(V + k0, m, V + k0, m, m - k0, nr, nr, acc);
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) G[16 * rt + lg + 4 * r][16 * ct + li] = acc[rt][ct][r];
+  __syncthreads();
+  for (int j = 0; j < kWyB; ++j) {
+    if (lane < kWyB) {
+      double t = 0.0;
+      if (lane < j) {
+        for (int l = lane; l < j; ++l) t += T[lane][l] * G[l][j];
+        t *= -2.0;
+      } else if (lane == j) {
+        t = (j < nr) ? 2.0 : 0.0;
+      }
+      T[lane][j] = t;
+    }
+    __syncthreads();
+  }
+  for (int idx = lane; idx < kWyB * kWyB; idx += 64) Tb[idx] = T[idx % kWyB][idx / kWyB];
+}
+
+// One workgroup (four waves) per strip of 32 columns of Z; eigenvalues and vectors leave in
+// descending order, as from backtransform_kernel.
+__global__ void __launch_bounds__(256)
+    backtransform_wy_kernel(int m, const double *__restrict__ work, double *__restrict__ lam,
+                            double *__restrict__ Vout, const EigJob *__restrict__ jobs) {
+  if (jobs) {
+    const EigJob &J = jobs[blockIdx.y];
+    m = J.m, work = J.work, lam = J.lam, Vout = J.Z;
+  }
+  const int c0 = blockIdx.x * kWyB;
+  if (c0 >= m) return;
+  EigLayout Lw(m);
+  const double *Hv = work + Lw.Hv, *Z = work + Lw.Z, *mu = work + Lw.mu, *misc = work + Lw.misc;
+  const double *Tall = work + Lw.scr;
+  constexpr int LW = kWyB + 1;
+  __shared__ double S[kWyB * (kWyMaxM + 1)];  // strip, column-major, ld = m + 1 (odd: no bank clash)
+  __shared__ double Wp[4][kWyB * LW], Ws[kWyB * LW], W2[kWyB * LW];
+  const int ldS = m + 1, nc = min(kWyB, m - c0);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  for (int idx = tid; idx < kWyB * m; idx += 256) {
+    const int i = idx % m, j = idx / m;
+    S[i + j * ldS] = (j < nc) ? Z[(size_t)(c0 + j) * m + i] : 0.0;
+  }
+  __syncthreads();
+  const int nblk = (m + kWyB - 1) / kWyB;
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int k0 = kWyB * b, nr = min(kWyB, m - k0);
+    const double *V = Hv + (size_t)k0 * m;  // V[i + j m] = v_{k0+j}[i], zero for i <= k0
+    // a) W = V^T S over rows k0..m-1, the rows split four ways over the waves
+    {
+      const int kq = ((m - k0 + 3) / 4 + 3) & ~3;
+      const int ks = k0 + wave * kq, ke = min(m, ks + kq);
+      d4 acc[2][2];
+      zero_acc(acc);
+      if (ke > ks) wave_mma32<true, false>(V + ks, m, S + ks, ldS, ke - ks, nr, nc, acc);
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            Wp[wave][(16 * rt + lg + 4 * r) + (16 * ct + li) * LW] = acc[rt][ct][r];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < kWyB * kWyB; idx += 256) {
+      const int o = (idx % kWyB) + (idx / kWyB) * LW;
+      Ws[o] = (Wp[0][o] + Wp[1][o]) + (Wp[2][o] + Wp[3][o]);
+    }
+    __syncthreads();
+    // b) W2 = T_b W
+    if (wave == 0) {
+      d4 acc[2][2];
+      zero_acc(acc);
+      wave_mma32<false, false>(Tall + (size_t)b * kWyB * kWyB, kWyB, Ws, LW, kWyB, kWyB, nc, acc);
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) W2[(16 * rt + lg + 4 * r) + (16 * ct + li) * LW] = acc[rt][ct][r];
+    }
+    __syncthreads();
+    // c) S -= V W2 on the row tiles from k0 down (each wave its own rows)
+    for (int I = b + wave; I < nblk; I += 4) {
+      const int r0 = kWyB * I;
+      d4 acc[2][2];
+      zero_acc(acc);
+      wave_mma32<false, false>(V + r0, m, W2, LW, nr, m - r0, nc, acc);
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = r0 + 16 * rt + lg + 4 * r, col = 16 * ct + li;
+            if (row < m && col < nc) S[row + col * ldS] -= acc[rt][ct][r];
+          }
+    }
+    __syncthreads();
+  }
+  // ascending index col -> descending position (ties keep a stable order)
+  for (int j = wave; j < nc; j += 4) {
+    const int col = c0 + j;
+    const double lj = mu[col] + misc[3];
+    int rank = 0;
+    for (int i = lane; i < m; i += 64) {
+      const double lv = mu[i] + misc[3];
+      rank += (lv > lj || (lv == lj && i > col)) ? 1 : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) rank += __shfl_xor(rank, o, 64);
+    if (lane == 0) lam[rank] = lj;
+    for (int i = lane; i < m; i += 64) Vout[(size_t)rank * m + i] = S[i + j * ldS];
+  }
+}
+
 // back-transform launch with the per-lane count for m (mmax: the largest m of the launch)
 void launch_backtransform(dim3 grid, int mmax, int m, const double *work, double *lam, double *Z,
                           const EigJob *jobs, hipStream_t st) {
+  if (mmax <= kWyMaxM) {
+    const unsigned nblk = (unsigned)((mmax + kWyB - 1) / kWyB);
+    hipLaunchKernelGGL(wy_t_kernel, dim3(nblk, grid.y), dim3(64), 0, st, m, const_cast<double *>(work),
+                       jobs);
+    hipLaunchKernelGGL(backtransform_wy_kernel, dim3(nblk, grid.y), dim3(256), 0, st, m, work, lam,
+                       Z, jobs);
+    return;
+  }
   if (mmax <= 5 * 64)
     hipLaunchKernelGGL(backtransform_kernel<5>, grid, dim3(256), 0, st, m, work, lam, Z, jobs);
   else if (mmax <= 9 * 64)

@@ -10,11 +10,11 @@
 //    their batched forms. The eigen-solver is in eig.hip.
 
 #include "riot_internal.h"
+#include "mfma_tile.h"
 
 namespace riot {
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // GEMM on the FP64 matrix cores. One wave computes a 32 x 32 tile of C as a
@@ -172,73 +172,6 @@ __device__ int wg_argmax_abs(double v, int idx, double *redv, int *redi, double 
   return bidx;
 }
 
-// ---------------------------------------------------------------------------
-// 32 x 32 wave-level MFMA block product: acc += op(A)[0:32, 0:K] op(B)[0:K, 0:32],
-// op(A)[i][k] = TA ? A[k + i*lda] : A[i + k*lda], op(B)[k][j] = TB ? B[j + k*ldb] : B[k + j*ldb].
-// Rows >= mA and columns >= nB read as zero. The lane owning result register r
-// of tile (rt, ct) holds element (16 rt + l/16 + 4 r, 16 ct + l%16).
-// ---------------------------------------------------------------------------
-
-template <bool TA, bool TB>
-__device__ __forceinline__ void mma32_load(const double *__restrict__ A, int lda,
-                                           const double *__restrict__ B, int ldb, int K, int mA,
-                                           int nB, int k0, double (&av)[4][2], double (&bv)[4][2]) {
-  const int lane = threadIdx.x & 63;
-  const int li = lane & 15, lg = lane >> 4;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int kk = k0 + 4 * s + lg;
-    const bool kin = kk < K;
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-      const int row = 16 * rt + li;
-      av[s][rt] = (kin && row < mA) ? (TA ? A[kk + (size_t)row * lda] : A[row + (size_t)kk * lda]) : 0.0;
-    }
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      const int col = 16 * ct + li;
-      bv[s][ct] = (kin && col < nB) ? (TB ? B[col + (size_t)kk * ldb] : B[kk + (size_t)col * ldb]) : 0.0;
-    }
-  }
-}
-
-// The contraction runs in chunks of 16 (four MFMA k-steps); the operands of the next
-// chunk are loaded before the current chunk's MFMAs are issued.
-template <bool TA, bool TB>
-__device__ __forceinline__ void wave_mma32(const double *__restrict__ A, int lda,
-                                           const double *__restrict__ B, int ldb, int K, int mA,
-                                           int nB, d4 (&acc)[2][2]) {
-  if (K <= 0) return;
-  double av[4][2], bv[4][2], an[4][2], bn[4][2];
-  mma32_load<TA, TB>(A, lda, B, ldb, K, mA, nB, 0, av, bv);
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const bool more = k0 + 16 < K;
-    if (more) mma32_load<TA, TB>(A, lda, B, ldb, K, mA, nB, k0 + 16, an, bn);
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
-          acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][rt], bv[s][ct], acc[rt][ct], 0, 0, 0);
-    if (more) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          av[s][t] = an[s][t];
-          bv[s][t] = bn[s][t];
-        }
-    }
-  }
-}
-
-__device__ __forceinline__ void zero_acc(d4 (&acc)[2][2]) {
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-}
 
 constexpr int kCholThreads = 512;
 constexpr int kPB = 32;  // panel width of the blocked factorizations
@@ -253,6 +186,23 @@ __device__ __forceinline__ double readlane_d(double v, int src) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
   const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), src);
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Maximum over the wave of a non-negative double, without LDS: DPP exchanges within each row
+// of 16 lanes (xor 1, xor 2, mirror within 8, mirror within 16; lanes a pattern leaves without
+// a source read 0, which cannot raise the maximum), then the four rows' values by v_readlane.
+template <int CTRL>
+__device__ __forceinline__ double dpp_nonneg(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+  v = fmax(v, dpp_nonneg<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+  v = fmax(v, dpp_nonneg<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+  v = fmax(v, dpp_nonneg<0x141>(v));  // row_half_mirror
+  v = fmax(v, dpp_nonneg<0x140>(v));  // row_mirror
+  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
 }
 
 // ---------------------------------------------------------------------------
@@ -365,6 +315,7 @@ __global__ void __launch_bounds__(kCholThreads)
       // inverse of the factor: lane c solves L11 x = e_c (x in registers); L11[i][t] and
       // 1 / L11[i][i] come from lane i's registers (v_readlane), not from LDS, which the
       // trailing update of the other waves keeps busy meanwhile. Di[c][i] = (L11^{-1})[i][c]
+      double ci = 0.0;  // lane c: column c's 1-norm of L11^{-1}
       if (!fail && lane < kPB) {
         // four partial sums per row shorten the dependent chain
         const int c = lane;
@@ -378,23 +329,26 @@ __global__ void __launch_bounds__(kCholThreads)
           x[i] = (i >= c && i < nb) ? xi : 0.0;
         }
 #pragma unroll
-        for (int i = 0; i < kPB; ++i) Di[c][i] = x[i];
+        for (int i = 0; i < kPB; ++i) {
+          Di[c][i] = x[i];
+          ci += fabs(x[i]);  // x[i] = 0 for i < c and i >= nb
+        }
       }
       // 1-norm condition of the block, kappa = |L11|_1 |L11^{-1}|_1: lane c sums column c
       // of the factor and of its inverse
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
       __builtin_amdgcn_wave_barrier();
-      double cl = 0.0, ci = 0.0;
+      // the loads are independent and issued together (one LDS latency, not one per row)
+      double cl = 0.0;
       if (!fail && lane < nb) {
-        for (int i = lane; i < nb; ++i) {
-          cl += fabs(D[i][lane]);
-          ci += fabs(Di[lane][i]);
+#pragma unroll
+        for (int i = 0; i < kPB; ++i) {
+          const double dv = D[i][lane];
+          cl += (i >= lane && i < nb) ? fabs(dv) : 0.0;
         }
       }
-      for (int off = 32; off >= 1; off >>= 1) {
-        cl = fmax(cl, __shfl_xor(cl, off));
-        ci = fmax(ci, __shfl_xor(ci, off));
-      }
+      cl = wave_max_nonneg(cl);
+      ci = wave_max_nonneg(ci);
       if (lane == 0) use_inv = (cl * ci <= kCholInvCond);
     };
     // first diagonal block

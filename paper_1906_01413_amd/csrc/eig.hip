@@ -1005,8 +1005,10 @@ __global__ void __launch_bounds__(256)
 // blocks of 32: Q_b = H_{32b} ... H_{32b+31} = I - V_b T_b V_b^T, with V_b's column j the
 // reflector 32b + j and T_b upper triangular (T_jj = 2 for the unit reflectors, T[0:j, j] =
 // -2 T[0:j, 0:j] V_b[:, 0:j]^T v_j). Z <- Q_0 Q_1 ... Z is applied last block first to strips
-// of 32 columns held in LDS, S <- S - V_b (T_b (V_b^T S)): three MFMA products per block.
+// of 16 columns held in LDS, S <- S - V_b (T_b (V_b^T S)): three MFMA products per block, with
+// V_b staged in LDS once per block.
 constexpr int kWyB = 32;
+constexpr int kWyS = 16;  // strip width
 constexpr int kWyMaxM = 288;
 
 // T_b of block blockIdx.x into the scratch area (column-major 32 x 32 per block).
@@ -1019,7 +1021,7 @@ __global__ void __launch_bounds__(64)
   const double *V = work + Lw.Hv + (size_t)k0 * m;  // V[i + j m] = v_{k0+j}[i]
   double *Tb = work + Lw.scr + (size_t)blockIdx.x * kWyB * kWyB;
   const int nr = min(kWyB, m - k0);
-  __shared__ double G[kWyB][kWyB + 1], T[kWyB][kWyB + 1];
+  __shared__ double G[kWyB][kWyB + 1];
   const int lane = threadIdx.x, li = lane & 15, lg = lane >> 4;
   // G = V^T V over rows k0.. (the reflectors vanish above)
   d4 acc[2][2];
@@ -1032,23 +1034,23 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
       for (int r = 0; r < 4; ++r) G[16 * rt + lg + 4 * r][16 * ct + li] = acc[rt][ct][r];
   __syncthreads();
+  // lane i builds row i of T in registers: T[i][j] = -2 sum_{i<=l<j} T[i][l] G[l][j] needs only
+  // its own row and broadcast reads of G, so the recurrence has no barrier
+  double x[kWyB];
+#pragma unroll
   for (int j = 0; j < kWyB; ++j) {
-    if (lane < kWyB) {
-      double t = 0.0;
-      if (lane < j) {
-        for (int l = lane; l < j; ++l) t += T[lane][l] * G[l][j];
-        t *= -2.0;
-      } else if (lane == j) {
-        t = (j < nr) ? 2.0 : 0.0;
-      }
-      T[lane][j] = t;
-    }
-    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int l = 0; l < j; ++l) t += x[l] * G[l][j];  // x[l] = 0 for l < i
+    x[j] = (j == lane) ? ((j < nr) ? 2.0 : 0.0) : ((j > lane) ? -2.0 * t : 0.0);
   }
-  for (int idx = lane; idx < kWyB * kWyB; idx += 64) Tb[idx] = T[idx % kWyB][idx / kWyB];
+  if (lane < kWyB) {
+#pragma unroll
+    for (int j = 0; j < kWyB; ++j) Tb[lane + kWyB * j] = x[j];
+  }
 }
 
-// One workgroup (four waves) per strip of 32 columns of Z; eigenvalues and vectors leave in
+// One workgroup (four waves) per strip of 16 columns of Z; eigenvalues and vectors leave in
 // descending order, as from backtransform_kernel.
 __global__ void __launch_bounds__(256)
     backtransform_wy_kernel(int m, const double *__restrict__ work, double *__restrict__ lam,
@@ -1057,69 +1059,104 @@ __global__ void __launch_bounds__(256)
     const EigJob &J = jobs[blockIdx.y];
     m = J.m, work = J.work, lam = J.lam, Vout = J.Z;
   }
-  const int c0 = blockIdx.x * kWyB;
+  const int c0 = blockIdx.x * kWyS;
   if (c0 >= m) return;
   EigLayout Lw(m);
   const double *Hv = work + Lw.Hv, *Z = work + Lw.Z, *mu = work + Lw.mu, *misc = work + Lw.misc;
   const double *Tall = work + Lw.scr;
   constexpr int LW = kWyB + 1;
-  __shared__ double S[kWyB * (kWyMaxM + 1)];  // strip, column-major, ld = m + 1 (odd: no bank clash)
-  __shared__ double Wp[4][kWyB * LW], Ws[kWyB * LW], W2[kWyB * LW];
-  const int ldS = m + 1, nc = min(kWyB, m - c0);
+  // strip and reflector block, column-major with ld = m + 1 (odd: no bank clash)
+  __shared__ double S[kWyS * (kWyMaxM + 1)], Vs[kWyB * (kWyMaxM + 1)];
+  __shared__ double Wp[4][kWyS * LW], Ws[kWyS * LW], W2[kWyS * LW], Ts[kWyB * kWyB];
+  const int ldS = m + 1, ldV = m + 1, nc = min(kWyS, m - c0);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
-  for (int idx = tid; idx < kWyB * m; idx += 256) {
+  for (int idx = tid; idx < kWyS * m; idx += 256) {
     const int i = idx % m, j = idx / m;
     S[i + j * ldS] = (j < nc) ? Z[(size_t)(c0 + j) * m + i] : 0.0;
   }
   __syncthreads();
   const int nblk = (m + kWyB - 1) / kWyB;
+  // The next block's reflectors and T are fetched into registers while this block computes.
+  constexpr int kPf = (kWyB * kWyMaxM + 255) / 256;
+  double pf[kPf], tf[kWyB * kWyB / 256];
+  auto fetch = [&](int bb) {
+    const int k0 = kWyB * bb, nr = min(kWyB, m - k0), mk = m - k0;
+    const int q256 = 256 / mk, r256 = 256 % mk;
+    int i = tid % mk, j = tid / mk;
+#pragma unroll
+    for (int q = 0; q < kPf; ++q) {
+      pf[q] = (j < nr) ? Hv[(size_t)(k0 + j) * m + k0 + i] : 0.0;
+      i += r256;
+      j += q256;
+      if (i >= mk) i -= mk, ++j;
+    }
+#pragma unroll
+    for (int q = 0; q < kWyB * kWyB / 256; ++q) tf[q] = Tall[(size_t)bb * kWyB * kWyB + tid + 256 * q];
+  };
+  fetch(nblk - 1);
   for (int b = nblk - 1; b >= 0; --b) {
-    const int k0 = kWyB * b, nr = min(kWyB, m - k0);
-    const double *V = Hv + (size_t)k0 * m;  // V[i + j m] = v_{k0+j}[i], zero for i <= k0
+    const int k0 = kWyB * b, nr = min(kWyB, m - k0), mk = m - k0;
+    // Vs[(i - k0) + j ldV] = v_{k0+j}[i] for i >= k0 (the reflectors vanish above)
+    {
+      const int q256 = 256 / mk, r256 = 256 % mk;
+      int i = tid % mk, j = tid / mk;
+#pragma unroll
+      for (int q = 0; q < kPf; ++q) {
+        if (j < nr) Vs[i + j * ldV] = pf[q];
+        i += r256;
+        j += q256;
+        if (i >= mk) i -= mk, ++j;
+      }
+#pragma unroll
+      for (int q = 0; q < kWyB * kWyB / 256; ++q) Ts[tid + 256 * q] = tf[q];
+    }
+    __syncthreads();
+    if (b > 0) fetch(b - 1);
     // a) W = V^T S over rows k0..m-1, the rows split four ways over the waves
     {
       const int kq = ((m - k0 + 3) / 4 + 3) & ~3;
       const int ks = k0 + wave * kq, ke = min(m, ks + kq);
-      d4 acc[2][2];
+      d4 acc[2][1];
       zero_acc(acc);
-      if (ke > ks) wave_mma32<true, false>(V + ks, m, S + ks, ldS, ke - ks, nr, nc, acc);
+      if (ke > ks) wave_mma32<true, false, 1>(Vs + (ks - k0), ldV, S + ks, ldS, ke - ks, nr, nc, acc);
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
+        for (int ct = 0; ct < 1; ++ct)
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            Wp[wave][(16 * rt + lg + 4 * r) + (16 * ct + li) * LW] = acc[rt][ct][r];
+            if (16 * ct + li < kWyS) Wp[wave][(16 * rt + lg + 4 * r) + (16 * ct + li) * LW] = acc[rt][ct][r];
     }
     __syncthreads();
-    for (int idx = tid; idx < kWyB * kWyB; idx += 256) {
+    for (int idx = tid; idx < kWyB * kWyS; idx += 256) {
       const int o = (idx % kWyB) + (idx / kWyB) * LW;
       Ws[o] = (Wp[0][o] + Wp[1][o]) + (Wp[2][o] + Wp[3][o]);
     }
     __syncthreads();
     // b) W2 = T_b W
     if (wave == 0) {
-      d4 acc[2][2];
+      d4 acc[2][1];
       zero_acc(acc);
-      wave_mma32<false, false>(Tall + (size_t)b * kWyB * kWyB, kWyB, Ws, LW, kWyB, kWyB, nc, acc);
+      wave_mma32<false, false, 1>(Ts, kWyB, Ws, LW, kWyB, kWyB, nc, acc);
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
+        for (int ct = 0; ct < 1; ++ct)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) W2[(16 * rt + lg + 4 * r) + (16 * ct + li) * LW] = acc[rt][ct][r];
+          for (int r = 0; r < 4; ++r)
+            if (16 * ct + li < kWyS) W2[(16 * rt + lg + 4 * r) + (16 * ct + li) * LW] = acc[rt][ct][r];
     }
     __syncthreads();
     // c) S -= V W2 on the row tiles from k0 down (each wave its own rows)
     for (int I = b + wave; I < nblk; I += 4) {
       const int r0 = kWyB * I;
-      d4 acc[2][2];
+      d4 acc[2][1];
       zero_acc(acc);
-      wave_mma32<false, false>(V + r0, m, W2, LW, nr, m - r0, nc, acc);
+      wave_mma32<false, false, 1>(Vs + (r0 - k0), ldV, W2, LW, nr, m - r0, nc, acc);
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
+        for (int ct = 0; ct < 1; ++ct)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = r0 + 16 * rt + lg + 4 * r, col = 16 * ct + li;
@@ -1148,9 +1185,10 @@ void launch_backtransform(dim3 grid, int mmax, int m, const double *work, double
                           const EigJob *jobs, hipStream_t st) {
   if (mmax <= kWyMaxM) {
     const unsigned nblk = (unsigned)((mmax + kWyB - 1) / kWyB);
+    const unsigned nstrip = (unsigned)((mmax + kWyS - 1) / kWyS);
     hipLaunchKernelGGL(wy_t_kernel, dim3(nblk, grid.y), dim3(64), 0, st, m, const_cast<double *>(work),
                        jobs);
-    hipLaunchKernelGGL(backtransform_wy_kernel, dim3(nblk, grid.y), dim3(256), 0, st, m, work, lam,
+    hipLaunchKernelGGL(backtransform_wy_kernel, dim3(nstrip, grid.y), dim3(256), 0, st, m, work, lam,
                        Z, jobs);
     return;
   }

@@ -405,6 +405,16 @@ __global__ void __launch_bounds__(kTileMaxThreads)
   }
 }
 
+// Quotient a / b through the hardware reciprocal and two Newton steps (about one ulp): a shorter
+// dependent chain than the correctly rounded division. Used only where the sign pattern of a
+// recurrence matters (Sturm and negative counts), not its last bit.
+__device__ __forceinline__ double quot_nr(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return a * r;
+}
+
 // Sturm count of T - x I (number of eigenvalues below x).
 __device__ int sturm_count(int m, const double *d, const double *e, double x, double pivmin) {
   int c = 0;
@@ -412,7 +422,7 @@ __device__ int sturm_count(int m, const double *d, const double *e, double x, do
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0) ++c;
   for (int i = 1; i < m; ++i) {
-    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    q = d[i] - x - quot_nr(e[i - 1] * e[i - 1], q);
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0) ++c;
   }
@@ -427,7 +437,7 @@ __device__ int negcount(int m, const double *D, const double *LLD, double tau, d
     double dp = D[i] + s;
     if (fabs(dp) < pivmin) dp = -pivmin;
     if (dp < 0) ++c;
-    s = LLD[i] * (s / dp) - tau;
+    s = LLD[i] * quot_nr(s, dp) - tau;
   }
   double dp = D[m - 1] + s;
   if (fabs(dp) < pivmin) dp = -pivmin;

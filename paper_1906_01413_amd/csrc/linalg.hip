@@ -749,18 +749,16 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int r = 0; r < 4; ++r) red[wave][16 * rt + lg + 4 * r][16 * ct + li] = acc[rt][ct][r];
     __syncthreads();
+    // 2. B = X[:, jb] - sum of the partial products, column-major in LDS (all four waves)
+    for (int idx = tid; idx < 32 * 32; idx += 256) {
+      const int i = idx & 31, j = idx >> 5;
+      double v = 0.0;
+      if (i < nr && j < nc)
+        v = xs[(c0 + j) * 33 + i] - (red[0][i][j] + red[1][i][j] + red[2][i][j] + red[3][i][j]);
+      Bm[i + 33 * j] = v;
+    }
+    __syncthreads();
     if (wave == 0) {
-      // 2. B = X[:, jb] - sum of the partial products, column-major in LDS
-      for (int idx = lane; idx < 32 * 32; idx += 64) {
-        const int i = idx & 31, j = idx >> 5;
-        double v = 0.0;
-        if (i < nr && j < nc)
-          v = xs[(c0 + j) * 33 + i] - (red[0][i][j] + red[1][i][j] + red[2][i][j] + red[3][i][j]);
-        Bm[i + 33 * j] = v;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       // 3. X[:, jb] = B L_jb^{-T}, into the strip
       d4 q[2][2];
       zero_acc(q);

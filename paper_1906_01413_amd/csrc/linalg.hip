@@ -24,7 +24,7 @@ namespace {
 // C[l / 16 + 4 * r][l % 16] (checked on gfx950 with an exact-integer probe).
 // ---------------------------------------------------------------------------
 
-template <int TA, int TB>
+template <int TA, int TB, bool LOWER = false>
 __global__ void __launch_bounds__(64)
     gemm_mfma_kernel(int M, int N, int K, const double *__restrict__ A, int lda,
                      const double *__restrict__ B, int ldb, double *__restrict__ C, int ldc,
@@ -53,6 +53,7 @@ __global__ void __launch_bounds__(64)
   const int li = lane & 15, lg = lane >> 4;
   const int m0 = blockIdx.x * 32, n0 = blockIdx.y * 32;
   if (m0 >= M || n0 >= N) return;
+  if (LOWER && blockIdx.y > blockIdx.x) return;  // symmetric result: tiles above the diagonal
   const int kbeg = kz * kchunk;
   const int kend = min(K, kbeg + kchunk);
   d4 acc[2][2];
@@ -109,14 +110,15 @@ __global__ void __launch_bounds__(64)
 
 __global__ void splitk_reduce_kernel(int M, int N, int splits, const double *__restrict__ partial,
                                      double alpha, double beta, double *__restrict__ C, int ldc,
-                                     const int *__restrict__ run) {
+                                     const int *__restrict__ run, int lower) {
   if (run && run[0] == 0) return;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t MN = (size_t)M * N;
   if (idx >= MN) return;
+  const int row = (int)(idx % M), col = (int)(idx / M);
+  if (lower && row < col) return;  // not computed for a lower-triangle result
   double s = 0.0;
   for (int z = 0; z < splits; ++z) s += partial[(size_t)z * MN + idx];
-  const int row = (int)(idx % M), col = (int)(idx / M);
   double out = alpha * s;
   if (beta != 0.0) out += beta * C[(size_t)col * ldc + row];
   C[(size_t)col * ldc + row] = out;
@@ -238,7 +240,12 @@ __global__ void __launch_bounds__(kCholThreads)
   double fro = 0.0;
   if (mode != 0) {
     double part = 0.0;
-    for (size_t idx = tid; idx < (size_t)m * m; idx += nt) part += G[idx] * G[idx];
+    // from the lower triangle (the upper one need not be formed): diagonal + 2 x strict lower
+    for (size_t idx = tid; idx < (size_t)m * m; idx += nt) {
+      const int i = (int)(idx % m), j = (int)(idx / m);
+      const double w = (i > j) ? 2.0 : ((i == j) ? 1.0 : 0.0);
+      part += w * G[idx] * G[idx];
+    }
     fro = sqrt(wg_sum(part, red));
   }
   // mode 2: a pivot below the shift is replaced by the shift (modified Cholesky), so a
@@ -976,8 +983,9 @@ __global__ void check_finite_kernel(long long count, const double *__restrict__ 
 
 hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const double *A, int lda,
                     const double *B, int ldb, double beta, double *C, int ldc, double *partial,
-                    int splitk, hipStream_t st, const int *run) {
+                    int splitk, hipStream_t st, const int *run, bool lower) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (lower && !(ta == 1 && tb == 0 && M == N)) return hipErrorInvalidValue;
   if (K <= 0) splitk = 1;
   if (splitk < 1 || !partial) splitk = 1;
   int kchunk = (K + splitk - 1) / splitk;
@@ -991,6 +999,9 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
                      ldb, C, ldc, alpha, beta, kchunk, part, run, nullptr, 0, 0, 0)
   if (ta == 0 && tb == 0)
     RIOT_GEMM(0, 0);
+  else if (ta == 1 && tb == 0 && lower)
+    hipLaunchKernelGGL((gemm_mfma_kernel<1, 0, true>), grid, dim3(64), 0, st, M, N, K, A, lda, B, ldb,
+                       C, ldc, alpha, beta, kchunk, part, run, nullptr, 0, 0, 0);
   else if (ta == 1 && tb == 0)
     RIOT_GEMM(1, 0);
   else if (ta == 0 && tb == 1)
@@ -1003,7 +1014,7 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   if (splits > 1) {
     const size_t MN = (size_t)M * N;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st,
-                       M, N, splits, partial, alpha, beta, C, ldc, run);
+                       M, N, splits, partial, alpha, beta, C, ldc, run, lower ? 1 : 0);
     e = hipGetLastError();
   }
   return e;

@@ -306,8 +306,9 @@ riot_status cholqr(const LaSpace &h, int rows, int m, const double *Xin, double 
   RIOT_HIP(launch_cholqr_reset(cq, st));
   for (int pass = 0; pass < kMaxCholQRPasses; ++pass) {
     const bool sh = shifted && pass == 0;
+    // the Cholesky reads the Gram's lower triangle only
     RIOT_HIP(gemm_f64(1, 0, m, m, rows, 1.0, Qout, rows, Qout, rows, 0.0, h.G, m, h.partial,
-                      kSplitK, st, cq));
+                      kSplitK, st, cq, true));
     RIOT_HIP(launch_chol_blocked(m, h.G, h.R, srel, sh ? 1 : 2, h.flags + flag_idx, h.flags + 4,
                                  st, cq, cq + 2));
     // the Gram's split-K buffer is free here: it holds the diagonal-block inverses

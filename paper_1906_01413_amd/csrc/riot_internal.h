@@ -213,9 +213,11 @@ hipError_t launch_philox_normal(long long total, uint64_t seed, uint64_t stream,
 // buffers reduced in fixed order (partial must hold splitk * M * N doubles).
 // run: optional device flag; when it holds 0 the launched kernels return at once
 // (predicated launches that keep a data-dependent loop free of host synchronisation).
+// lower: for the symmetric A^T A shape (ta = 1, tb = 0, M = N), only C's lower triangle is
+// formed; the strict upper triangle is left as it was.
 hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const double *A, int lda,
                     const double *B, int ldb, double beta, double *C, int ldc, double *partial,
-                    int splitk, hipStream_t st, const int *run = nullptr);
+                    int splitk, hipStream_t st, const int *run = nullptr, bool lower = false);
 
 // Blocked Cholesky G + s I = L L^T (lower, column-major). mode 0: s = 0; mode 1:
 // s = shift_rel * ||G||_F; mode 2: s = 0 with every pivot not above shift_rel * ||G||_F

@@ -752,6 +752,7 @@ __global__ void __launch_bounds__(128) vector_kernel(int m, double *__restrict__
 // 5. Clusters (relative gap < 1e-3): Gram-Schmidt and Rayleigh-Ritz (one workgroup).
 // ---------------------------------------------------------------------------
 constexpr int kMaxCluster = 48;
+constexpr int kEigMaxM = 1088;  // largest m of the eigen-solver
 
 __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict__ work,
                                                       int *__restrict__ flag,
@@ -764,19 +765,28 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
   __shared__ double H[kMaxCluster][kMaxCluster + 1];
   __shared__ double Vc[kMaxCluster][kMaxCluster + 1];
   __shared__ double red[16];
-  __shared__ int cl_end;
+  __shared__ double mus[kEigMaxM];  // mu in LDS for the scan (kept equal to mu below)
+  __shared__ int cl_start, cl_end;
   const int tid = threadIdx.x, nt = blockDim.x;
   const double sigma = misc[3];
+  for (int i = tid; i < m; i += nt) mus[i] = mu[i];
+  __syncthreads();
+  auto close = [&](int i) {
+    return fabs(mus[i + 1] - mus[i]) < 1e-3 * fmax(fabs(mus[i + 1]), fabs(mus[i]));
+  };
   int a = 0;
   while (a < m) {
     if (tid == 0) {
-      int b = a;
-      while (b + 1 < m && b + 1 - a < kMaxCluster &&
-             fabs(mu[b + 1] - mu[b]) < 1e-3 * fmax(fabs(mu[b + 1]), fabs(mu[b])))
-        ++b;
+      // singletons need no work: the scan moves on to the next index that starts a cluster
+      int s0 = a;
+      while (s0 + 1 < m && !close(s0)) ++s0;
+      int b = s0;
+      while (b + 1 < m && b + 1 - s0 < kMaxCluster && close(b)) ++b;
+      cl_start = s0;
       cl_end = b;
     }
     __syncthreads();
+    a = cl_start;
     const int b = cl_end;
     __syncthreads();
     const int c = b - a + 1;
@@ -899,7 +909,7 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
       for (int q = 0; q < c; ++q)
         for (int i = tid; i < m; i += nt) Z[(size_t)(a + q) * m + i] = W[(size_t)q * m + i];
       if (tid == 0)
-        for (int q = 0; q < c; ++q) mu[a + q] = H[q][q] - sigma;
+        for (int q = 0; q < c; ++q) mus[a + q] = mu[a + q] = H[q][q] - sigma;
       __syncthreads();
     }
     a = b + 1;
@@ -1216,7 +1226,7 @@ size_t eig_work_doubles(int m) { return EigLayout(m).total; }
 
 hipError_t launch_eig(int m, const double *K, double *lam, double *Z, double *work, int *flag,
                       hipStream_t st) {
-  if (m < 1 || m > 1088) return hipErrorInvalidValue;
+  if (m < 1 || m > kEigMaxM) return hipErrorInvalidValue;
   if (tile_fits(m))
     hipLaunchKernelGGL(tridiag_tile_kernel, dim3(1), dim3(tile_threads(m)), 0, st, m, K, work,
                        nullptr);

@@ -861,7 +861,7 @@ riot_status riot_philox_normal(riot_handle *h, int32_t n, int32_t m, uint64_t se
 namespace {
 
 constexpr int kBatchMaxN = 2048;  // NT <= 256 threads at 8 elements per lane
-constexpr int kBatchMaxM = 278;   // register-resident tridiagonalisation bound
+constexpr int kBatchMaxM = 278;   // within the register-tile tridiagonalisation bound (279)
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 

@@ -50,7 +50,8 @@ typedef enum {
     RIOT_E_NONFINITE = -5,  /* NaN or Inf in a result */
     RIOT_E_NOCONV = -6,     /* iteration cap reached (eigen-solver) */
     RIOT_E_STATE = -7,      /* call order violated (e.g. no linearisation yet) */
-    RIOT_E_WORKSPACE = -8   /* workspace too small or misaligned */
+    RIOT_E_WORKSPACE = -8,  /* workspace too small or misaligned */
+    RIOT_E_SCRATCH = -9     /* problem too large for riot_sketch_eig_noalloc's static scratch */
 } riot_status;
 
 typedef enum {
@@ -308,6 +309,25 @@ riot_status riot_sketch_residual(riot_sketch *s, int32_t m, const double *Q, con
 riot_status riot_sketch_increment(riot_sketch *s, int32_t k, const double *lambda,
                                   const double *V, const double *grad, riot_update mode,
                                   double *dz, double *dofs_host, int32_t *mode_used);
+
+/* riot_sketch_eig for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): no handle and no workspace.
+ * The scratch regions (basis Q, Gram and projected matrices, eigen-solver work, split-K
+ * partial products, flags) live in one static device array of
+ * riot_sketch_noalloc_max_bytes() = 32 MiB, which each device the library runs on holds
+ * until the process ends. Same arguments and results as riot_sketch_eig:
+ *   n >= 1 rows, 1 <= m <= min(n, 1088) columns; Omega, Y [n x m] device (ld n);
+ *   lambda [m], V [n x m] device out; hip_stream a hipStream_t of the current device (NULL =
+ *   default stream); info host out or NULL (synchronises).
+ * Returns RIOT_E_SCRATCH when riot_sketch_workspace_bytes(n, m) exceeds the array (e.g.
+ * n = 4096 fits up to m = 316). The call allocates nothing: no hipMalloc, hipFree or
+ * allocating library routine. Every call on one device shares that device's array, which
+ * keeps the last call's contents; calls that overlap on one device (two streams, two host
+ * threads) race and must be serialised by the caller. */
+size_t riot_sketch_noalloc_max_bytes(void);
+riot_status riot_sketch_eig_noalloc(int32_t n, int32_t m, const double *Omega, const double *Y,
+                                    double *lambda, double *V, void *hip_stream,
+                                    riot_rsvd_info *info);
 
 /* ------------------------------------------------------------------------------------
  * Tracer source inversion on a periodic 2-D grid (the character of the paper's

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -514,6 +515,8 @@ const char *riot_status_str(riot_status s) {
     case RIOT_E_NOCONV: return "RIOT_E_NOCONV: iteration cap reached";
     case RIOT_E_STATE: return "RIOT_E_STATE: call order violated";
     case RIOT_E_WORKSPACE: return "RIOT_E_WORKSPACE: workspace too small or misaligned";
+    case RIOT_E_SCRATCH:
+      return "RIOT_E_SCRATCH: problem larger than the no-allocation entry point's static scratch";
   }
   return "unknown riot_status";
 }
@@ -1547,6 +1550,63 @@ riot_status riot_sketch_increment(riot_sketch *s, int32_t k, const double *lambd
   if (!s || !lambda || !V || !grad || !dz || k < 1 || k > s->m_max) return RIOT_E_ARG;
   if (mode != RIOT_ADAPTIVE && mode != RIOT_LRA && mode != RIOT_LRU) return RIOT_E_ARG;
   return sketch_increment(s->la, s->n, k, lambda, V, grad, mode, dz, dofs_host, mode_used);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// riot_sketch_eig without a workspace argument, for callers that cannot allocate device
+// memory: the sketch's scratch regions are carved from one static device array instead.
+// Every call on a device shares that device's copy of the array, so calls that overlap on
+// one device race; the flags the eigen-solve reads are cleared by a kernel on every call.
+// ---------------------------------------------------------------------------
+
+constexpr size_t kNoallocScratchBytes = (size_t)32 << 20;  // 32 MiB per device
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxScratchDevices];  // device address of `scratch` per device
+
+// Device address of `scratch` on the current device, looked up once per device (the
+// array's name in host code is only a host-side handle, never a device address).
+riot_status scratch_address(void **out) {
+  int dev = -1;
+  RIOT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) return RIOT_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    RIOT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return RIOT_E_HIP;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return RIOT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t riot_sketch_noalloc_max_bytes(void) { return kNoallocScratchBytes; }
+
+riot_status riot_sketch_eig_noalloc(int32_t n, int32_t m, const double *Omega, const double *Y,
+                                    double *lambda, double *V, void *hip_stream,
+                                    riot_rsvd_info *info) {
+  if (!Omega || !Y || !lambda || !V || n < 1 || m < 1 || m > n || m > 1088) return RIOT_E_ARG;
+  riot_sketch s;
+  s.n = n, s.m_max = m;
+  if (sketch_carve(s, nullptr) > kNoallocScratchBytes) return RIOT_E_SCRATCH;
+  void *base = nullptr;
+  const riot_status rs = scratch_address(&base);
+  if (rs != RIOT_OK) return rs;
+  sketch_carve(s, base);
+  s.la.st = static_cast<hipStream_t>(hip_stream);
+  RIOT_HIP(launch_zero_ints(s.la.flags, 16, s.la.st));
+  return sketch_eig(s.la, n, m, Y, Omega, lambda, V, info);
 }
 
 }  // extern "C"

@@ -21,7 +21,7 @@ _LIB_PATH = os.path.join(_HERE, "libriot.so")
 RIOT_OK = 0
 STATUS = {0: "RIOT_OK", -1: "RIOT_E_ARG", -2: "RIOT_E_HIP", -3: "RIOT_E_NOT_SPD",
           -4: "RIOT_E_SINGULAR", -5: "RIOT_E_NONFINITE", -6: "RIOT_E_NOCONV",
-          -7: "RIOT_E_STATE", -8: "RIOT_E_WORKSPACE"}
+          -7: "RIOT_E_STATE", -8: "RIOT_E_WORKSPACE", -9: "RIOT_E_SCRATCH"}
 FP64, FP32_TLAD = 0, 1
 ADAPTIVE, LRA, LRU = 0, 1, 2
 MODES = {"adaptive": ADAPTIVE, "lra": LRA, "lru": LRU}
@@ -36,7 +36,7 @@ EXPORTS = ("riot_workspace_bytes", "riot_init", "riot_free", "riot_status_str",
            "riot_batch_replay", "riot_batch_problem", "riot_batch_profile", "riot_gaussian_taps",
            "riot_ckpt_forward", "riot_ckpt_tangent", "riot_ckpt_adjoint",
            "riot_sketch_workspace_bytes", "riot_sketch_init", "riot_sketch_free", "riot_sketch_eig",
-           "riot_sketch_increment",
+           "riot_sketch_increment", "riot_sketch_eig_noalloc", "riot_sketch_noalloc_max_bytes",
            "riot_tracer_workspace_bytes", "riot_tracer_init", "riot_tracer_free", "riot_tracer_forward",
            "riot_tracer_tangent", "riot_tracer_adjoint", "riot_tracer_apply_L", "riot_tracer_hess_apply",
            "riot_tracer_gradient", "riot_exp_corr_sqrt", "riot_set_obs", "riot_proj_residual",
@@ -149,6 +149,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "riot_sketch_eig": (i32, [vp, i32, vp, vp, vp, vp, ctypes.POINTER(_RsvdInfo)]),
         "riot_sketch_increment": (i32, [vp, i32, vp, vp, vp, i32, vp, ctypes.POINTER(dbl),
                                         ctypes.POINTER(i32)]),
+        "riot_sketch_eig_noalloc": (i32, [i32, i32, vp, vp, vp, vp, vp, ctypes.POINTER(_RsvdInfo)]),
+        "riot_sketch_noalloc_max_bytes": (ctypes.c_size_t, []),
         "riot_tracer_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(_TracerDesc)]),
         "riot_tracer_init": (i32, [ctypes.POINTER(_TracerDesc), vp, ctypes.c_size_t, vp,
                                    ctypes.POINTER(vp)]),
@@ -676,6 +678,27 @@ class Sketch:
         _check(self.lib.riot_sketch_residual(self.h, Qc.shape[1], _ptr(Qc), _ptr(AQc),
                                              ctypes.byref(rho)), "riot_sketch_residual")
         return rho.value
+
+
+def sketch_eig_noalloc(Omega, Y, want_info=True, lam=None, V=None):
+    """riot_sketch_eig_noalloc: Sketch.eig without a handle or workspace (the library's static
+    scratch on the current device). Returns (lam, V, info) like Sketch.eig."""
+    lib = load_library()
+    Yc = colmajor(Y)
+    n = Yc.shape[0]
+    Om = _cols(Omega, n, Yc.device)
+    Yc = _cols(Yc, n, Yc.device)
+    m = Om.shape[1]
+    lam = torch.empty(m, dtype=torch.float64, device=Yc.device) if lam is None else lam
+    V = empty_colmajor(n, m, Yc.device) if V is None else V
+    info = _RsvdInfo()
+    stream = torch.cuda.current_stream(Yc.device)
+    _check(lib.riot_sketch_eig_noalloc(n, m, _ptr(Om), _ptr(Yc), _ptr(lam), _ptr(V),
+                                       ctypes.c_void_p(stream.cuda_stream),
+                                       ctypes.byref(info) if want_info else None),
+           "riot_sketch_eig_noalloc")
+    return lam, V, (RsvdInfo(info.chol_shifts, info.qr_passes, info.k_asym, info.orth_err)
+                    if want_info else None)
 
 
 class ProposalNet:

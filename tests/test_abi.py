@@ -111,3 +111,22 @@ def test_exp_corr_sqrt_host_helper_matches_oracle():
     for n, ell in ((16, 3.0), (128, 3.0), (37, 1.5)):
         a, b = exp_corr_sqrt(n, ell), sqrt_corr_1d(n, ell)
         assert np.max(np.abs(a - b)) < 1e-12, (n, ell)
+
+
+def test_noalloc_entry_point_refuses_sizes_beyond_its_scratch():
+    """riot_sketch_eig_noalloc checks arguments and the size of its static scratch on the host
+    and returns before any HIP call, so these cases need no GPU."""
+    from paper_1906_01413_amd.riot import load_library
+    lib = load_library()
+    vp = ctypes.c_void_p
+    assert lib.riot_sketch_noalloc_max_bytes() == 32 << 20
+    args = (vp(256), vp(512), vp(768), vp(1024), None, None)
+    assert lib.riot_sketch_eig_noalloc(4096, 400, *args) == -9       # RIOT_E_SCRATCH
+    assert lib.riot_sketch_eig_noalloc(65536, 512, *args) == -9
+    assert lib.riot_sketch_eig_noalloc(40, 41, *args) == -1          # m > n
+    assert lib.riot_sketch_eig_noalloc(40, 0, *args) == -1
+    assert lib.riot_sketch_eig_noalloc(40, 30, None, *args[1:]) == -1
+    assert lib.riot_status_str(-9).startswith(b"RIOT_E_SCRATCH")
+    # the largest m that fits at the benchmarked n, as the header states
+    fits = [m for m in range(256, 400) if lib.riot_sketch_workspace_bytes(4096, m) <= 32 << 20]
+    assert max(fits) == 316

@@ -79,7 +79,7 @@ def adjoint_window(p: Problem, stages: np.ndarray, forcing: np.ndarray) -> np.nd
     ``forcing`` has shape (nobs,) or (nobs, m). Returns lambda_0 (n,) or (n, m).
     """
     shape = (p.n,) + forcing.shape[1:]
-    lam = np.zeros(shape)
+    lam = np.zeros(shape, dtype=np.result_type(forcing, stages))
     for t in range(p.nsteps, -1, -1):
         sel = p.obs_step == t
         if np.any(sel):
@@ -91,8 +91,9 @@ def adjoint_window(p: Problem, stages: np.ndarray, forcing: np.ndarray) -> np.nd
 
 def tangent_window(p: Problem, stages: np.ndarray, dx0: np.ndarray) -> np.ndarray:
     """G dx0: tangent-linear sweep sampled at the observations -> (nobs,) or (nobs, m)."""
-    out = np.zeros((p.nobs,) + dx0.shape[1:])
-    d = np.array(dx0, dtype=np.float64)
+    dt = np.result_type(dx0, stages)
+    out = np.zeros((p.nobs,) + dx0.shape[1:], dtype=dt)
+    d = np.array(dx0, dtype=dt)
     for t in range(p.nsteps + 1):
         sel = np.nonzero(p.obs_step == t)[0]
         if sel.size:
@@ -382,3 +383,29 @@ def outer_loop(p: Problem, n_outer: int, solver) -> list[dict]:
         x = x + bcov.apply_L(dz, p.taps)
     hist.append({"J": cost(p, v), "gnorm": float("nan")})
     return hist
+
+
+# --------------------------------------------------------------------------
+# Deterministic LRA/LRU choice by two nonlinear runs (Section 3.2.1)
+# --------------------------------------------------------------------------
+
+def increment_select(p: Problem, lam: np.ndarray, V: np.ndarray, g: np.ndarray,
+                     v: np.ndarray | None = None, k: int | None = None):
+    """The deterministic alternative to eq. 11's rule suggested in the first-inner-loop
+    discussion of the small black-carbon problem: form both the LRA and the LRU increment
+    from the same Ritz pairs, integrate the nonlinear model from both updated states, and
+    keep the increment whose non-quadratic cost (eq. 2 in control variables, x = x_b + L v)
+    is lower. A tie keeps LRA, as eq. 11 does at lambda_k = 1; a candidate whose window
+    blows up (non-finite cost) never wins over a finite one.
+
+    Returns (dz, dx, mode, J_lra, J_lru).
+    """
+    v = np.zeros(p.n) if v is None else np.asarray(v, dtype=np.float64)
+    dz_a, dx_a, _, _ = increment(p, lam, V, g, k, "lra")
+    dz_u, dx_u, _, _ = increment(p, lam, V, g, k, "lru")
+    with np.errstate(over="ignore", invalid="ignore"):
+        J_a = cost(p, v + dz_a)
+        J_u = cost(p, v + dz_u)
+    if not np.isfinite(J_u) or (np.isfinite(J_a) and J_a <= J_u):
+        return dz_a, dx_a, "lra", J_a, J_u
+    return dz_u, dx_u, "lru", J_a, J_u

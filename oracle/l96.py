@@ -67,16 +67,18 @@ def forecast(x: np.ndarray, nsteps: int, h: float, F: float) -> np.ndarray:
     return x
 
 
-def trajectory(x0: np.ndarray, nsteps: int, h: float, F: float):
+def trajectory(x0: np.ndarray, nsteps: int, h: float, F: float, dtype=np.float64):
     """Nonlinear trajectory of one window (Alg. 3, 'integrate and store trajectory').
 
     Returns (stages, states): stages[t] holds the four RK4 stage states of step
     t -> t+1 (shape (nsteps, 4, n)); states[t] is x_t for t = 0..nsteps.
+    ``dtype`` is the arithmetic type (np.longdouble for the extended-precision floors).
     """
     n = x0.size
-    stages = np.empty((nsteps, 4, n))
-    states = np.empty((nsteps + 1, n))
-    x = np.array(x0, dtype=np.float64)
+    stages = np.empty((nsteps, 4, n), dtype=dtype)
+    states = np.empty((nsteps + 1, n), dtype=dtype)
+    x = np.array(x0, dtype=dtype)
+    h, F = dtype(h), dtype(F)
     states[0] = x
     for t in range(nsteps):
         stages[t], x = rk4_stages(x, h, F)

@@ -184,3 +184,42 @@ def test_proj_residual_closed_form():
     assert abs(fourdvar.proj_residual(Q, A @ Q) - want) < 1e-14
     V = U[:, [2, 5, 7]]
     assert fourdvar.proj_residual(V, A @ V) < 1e-14
+
+
+def test_increment_select_two_nonlinear_runs():
+    """Deterministic LRA/LRU choice (Sec. 3.2.1): both candidates' non-quadratic costs equal
+    eq. 2 at v + dz and are consistent to first order with the gradient along each
+    candidate; the lower one is kept; at full rank the two updates coincide."""
+    from oracle import bcov
+    w = workload("l96_n40", nsteps=4, step_stride=1)
+    p, _ = fourdvar.realize_l96(w, l96_draws(w, 2))
+    v = 0.05 * np.random.default_rng(4).standard_normal(p.n)
+    lin = fourdvar.linearize(p, p.xb + bcov.apply_L(v, p.taps), v)
+    A = fourdvar.dense_A(p, lin)
+    A = 0.5 * (A + A.T)
+    lam, V = np.linalg.eigh(A)
+    lam, V = lam[::-1], V[:, ::-1]
+    for k in (3, 8, 20):
+        dz, dx, mode, Ja, Ju = fourdvar.increment_select(p, lam, V, lin.g, v, k=k)
+        dza, _, _, _ = fourdvar.increment(p, lam, V, lin.g, k, "lra")
+        dzu, _, _, _ = fourdvar.increment(p, lam, V, lin.g, k, "lru")
+        assert Ja == fourdvar.cost(p, v + dza) and Ju == fourdvar.cost(p, v + dzu)
+        for dzc in (dza, dzu):
+            # J(v + t dz) - J - t g^T dz = O(t^2) (the candidate lives in the gradient's
+            # control variables): halving t divides the gap by about 4. The quadratic
+            # model's I + A is the Gauss-Newton Hessian, which leaves out the model's second
+            # derivative times the innovation, so J - q is itself second order.
+            def gap(t, dzc=dzc):
+                return fourdvar.cost(p, v + t * dzc) - lin.J - t * (lin.g @ dzc)
+            r = gap(0.02) / gap(0.01)
+            assert 3.6 < r < 4.4, r
+        assert mode == ("lra" if Ja <= Ju else "lru")
+        assert np.array_equal(dz, dza if mode == "lra" else dzu)
+        assert np.allclose(dx, bcov.apply_L(dz, p.taps), rtol=0, atol=1e-14 * np.abs(dx).max())
+    # both outcomes occur on this problem: truncated at 3 pairs (lambda_3 >> 1) the LRU step
+    # along the unresolved directions overshoots; with 20 pairs LRU is the better one
+    modes = {fourdvar.increment_select(p, lam, V, lin.g, v, k=k)[2] for k in (3, 20)}
+    print("selected modes at k = 3, 20:", modes)
+    # full rank: both updates are the exact minimiser of the quadratic model
+    _, _, _, Jaf, Juf = fourdvar.increment_select(p, lam, V, lin.g, v, k=p.n)
+    assert abs(Jaf - Juf) <= 1e-10 * abs(Jaf)

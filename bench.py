@@ -88,28 +88,89 @@ def load_problem(name: str, seed: int):
     return {k: z[k] for k in z.files}
 
 
-def cpu_baseline(prob: dict, m: int, budget_s: float = 15.0) -> dict:
-    """Time the oracle's Hessian-probe products on a bounded sample of the same problem."""
+_POOL_STATE = {}
+
+
+def _pool_init(prob):
+    """Worker set-up: the oracle problem and its linearisation, built once per process."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from oracle import fourdvar
+    p = fourdvar.Problem(int(prob["n"]), int(prob["nsteps"]), float(prob["dt"]),
+                         float(prob["forcing"]), prob["obs_step"], prob["obs_idx"], prob["y"],
+                         prob["rinv"], prob["xb"], prob["taps"])
+    _POOL_STATE["p"] = p
+    _POOL_STATE["lin"] = fourdvar.linearize(p, p.xb)
+
+
+def _pool_hvp(W):
+    from oracle import fourdvar
+    return fourdvar.hvp(_POOL_STATE["p"], _POOL_STATE["lin"], W)
+
+
+def cpu_baseline(prob: dict, m: int, budget_s: float = 12.0) -> dict:
+    """The FP64 CPU oracle on a bounded sample of the same workload.
+
+    * Hessian-probe products over all host cores: a process pool (one worker per core the
+      process may run on, at most 16, one BLAS thread each) applies the oracle's product to
+      chunks of one m-column probe block; the main value is that rate.
+    * The same products in one process (single-core figure).
+    * The oracle's RSVD inner loop (probe products on the pool, then Householder QR, the K
+      solve, the eigendecomposition and the increment in the main process) and the oracle's
+      plain CG (one product per iteration, sequential), per iteration.
+    """
+    import multiprocessing as mp
+
     from oracle import fourdvar
     from synthetic import probe_block
 
-    p = fourdvar.Problem(int(prob["n"]), int(prob["nsteps"]), float(prob["dt"]), float(prob["forcing"]),
-                         prob["obs_step"], prob["obs_idx"], prob["y"], prob["rinv"], prob["xb"],
-                         prob["taps"])
-    lin = fourdvar.linearize(p, p.xb)
-    cols, done, t_used = 8, 0, 0.0
-    while True:
-        W = probe_block(11, done, p.n, cols)
+    _pool_init(prob)
+    p, lin = _POOL_STATE["p"], _POOL_STATE["lin"]
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    chunk = max(1, (m + cores - 1) // cores)
+    W = probe_block(11, 0, p.n, m)
+    parts = [W[:, c: c + chunk] for c in range(0, m, chunk)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores, initializer=_pool_init, initargs=(prob,)) as pool:
+        pool.map(_pool_hvp, [P[:, :1] for P in parts])  # warm every worker
         t0 = time.perf_counter()
-        fourdvar.hvp(p, lin, W)
-        t_used += time.perf_counter() - t0
+        Y = np.concatenate(pool.map(_pool_hvp, parts), axis=1)
+        t_pool = time.perf_counter() - t0
+        # oracle RSVD inner loop on the pool (k + p_os = m probes, q = 0, all m pairs kept)
+        t0 = time.perf_counter()
+        Yr = np.concatenate(pool.map(_pool_hvp, parts), axis=1)
+        Q = fourdvar.orth(Yr)
+        K = np.linalg.solve((Q.T @ W).T, (Q.T @ Yr).T).T
+        lam, Z = np.linalg.eigh(0.5 * (K + K.T))
+        lam, Z = lam[::-1], Z[:, ::-1]
+        fourdvar.increment(p, lam, Q @ Z, lin.g)
+        t_rsvd = time.perf_counter() - t0
+    del Y
+    # one process: products until the budget is spent
+    cols, done, t_one = 8, 0, 0.0
+    while done < m and t_one < budget_s:
+        t0 = time.perf_counter()
+        fourdvar.hvp(p, lin, W[:, done: done + cols])
+        t_one += time.perf_counter() - t0
         done += cols
-        if t_used > budget_s or done >= m:
-            break
-    return {"value": done / t_used, "unit": "HVP/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} Hessian-probe products (NumPy FP64, one process) on the same "
-                      f"n={p.n}, T={p.nsteps} problem, {t_used:.1f} s",
-            "host_cores_visible": len(os.sched_getaffinity(0))}
+    # plain CG, sequential products
+    its = 20
+    t0 = time.perf_counter()
+    fourdvar.cg(lambda x: x + fourdvar.hvp(p, lin, x), lin.g, its)
+    t_cg = (time.perf_counter() - t0) / its
+    try:
+        import numpy.__config__  # noqa: F401
+        blas = "1 per worker (OMP_NUM_THREADS)"
+    except Exception:
+        blas = "unknown"
+    return {"value": m / t_pool, "unit": "HVP/s", "cores": cores, "kind": "oracle",
+            "sample": f"one {m}-column probe block of Hessian-probe products (NumPy FP64) on the "
+                      f"same n={p.n}, T={p.nsteps} problem, {cores} worker processes, "
+                      f"{t_pool:.2f} s",
+            "host_cores_visible": len(os.sched_getaffinity(0)), "blas_threads": blas,
+            "single_core_hvp_per_s": done / t_one,
+            "oracle_rsvd_inner_loop_s": t_rsvd,
+            "oracle_rsvd_config": f"m={m}, q=0, probe products on {cores} processes",
+            "oracle_cg_s_per_iteration": t_cg}
 
 
 ACCURACY_SWEEP = {
@@ -119,7 +180,7 @@ ACCURACY_SWEEP = {
 }
 
 
-def time_to_accuracy(r, prob, xb, dev, target=1e-6, trials=3, cg_max=None, reps=5):
+def time_to_accuracy(r, prob, xb, dev, target=1e-6, trials=5, cg_max=None, reps=5):
     """Inner-loop seconds to a relative increment error target, RSVD against plain GPU CG.
 
     Error = ||dx - dx*|| / ||dx*|| against the stored exact minimiser dx* of the
@@ -134,7 +195,8 @@ def time_to_accuracy(r, prob, xb, dev, target=1e-6, trials=3, cg_max=None, reps=
     n, T = r.n, r.nsteps
     dxs = np.asarray(prob["dx"])
     floor = float(prob["floor"])
-    tgt = max(target, 10.0 * floor)
+    # 1e-6 is claimed only where the certified floor is at most a tenth of it
+    tgt = target if floor <= 0.1 * target else 10.0 * floor
     name = "l96_n4096" if n == 4096 else "l96_n40"
     stream = torch.cuda.current_stream(dev)
 
@@ -200,11 +262,98 @@ def time_to_accuracy(r, prob, xb, dev, target=1e-6, trials=3, cg_max=None, reps=
     cg["seconds"] = timed(run_cg, max(2, reps // 2))
     del its, dxi
     out = {"target": target, "target_used": tgt, "reference_floor": floor,
+           "floor_method": "certified: Dot2-refined exact solve of eq. 3 with a rigorous bound "
+                           f"({float(prob['floor_la']):.1e}) plus the FP64-vs-longdouble "
+                           f"Hessian-product discrepancy on dz* ({float(prob['floor_op']):.1e})",
            "error": "||dx - dx*|| / ||dx*|| against the oracle's exact minimiser",
+           "workload": f"Lorenz-96 n={n}, T={T}, {int(prob['obs_step'].size)} obs",
            "rsvd": rs_best, "cg": cg, "rsvd_sweep": sweep}
     if rs_best["reached"] and cg["reached"]:
         out["speedup_rsvd_over_cg"] = cg["seconds"] / rs_best["seconds"]
     return out
+
+
+def small_inner_loop(seed: int, dev) -> dict:
+    """Time to 1e-6 at the small Lorenz-96 configuration (n = 40, T = 40, 200 observations,
+    RSVD m = 30 with one power step as the reference setting), RSVD against plain GPU CG."""
+    from paper_1906_01413_amd import Riot
+    import torch
+
+    prob = load_problem("l96_n40", seed)
+    r = Riot(int(prob["n"]), int(prob["nsteps"]), float(prob["dt"]), float(prob["forcing"]),
+             prob["obs_step"], prob["obs_idx"], prob["y"], prob["rinv"], prob["taps"], m_max=40)
+    xb = torch.tensor(prob["xb"], device=dev)
+    return time_to_accuracy(r, prob, xb, dev, reps=20)
+
+
+def fp32_leg(prob, k, p_os, q, steps, warmup, dev, lam64, V64, g64) -> dict:
+    """The FP32 TL/AD variant on the benchmarked workload: the same inner-loop step, the
+    TL/AD launch alone, and the increment against the FP64 path's on the same Philox probes
+    and against the stored exact minimiser."""
+    import torch
+    from paper_1906_01413_amd import Riot, empty_colmajor
+
+    n, T = int(prob["n"]), int(prob["nsteps"])
+    m = k + p_os
+    nobs = int(prob["obs_step"].size)
+    r = Riot(n, T, float(prob["dt"]), float(prob["forcing"]), prob["obs_step"], prob["obs_idx"],
+             prob["y"], prob["rinv"], prob["taps"], m_max=m, prec=1)
+    xb = torch.tensor(prob["xb"], device=dev)
+    d = torch.empty(max(nobs, 1), dtype=torch.float64, device=dev)
+    g = torch.empty(n, dtype=torch.float64, device=dev)
+    lam = torch.empty(m, dtype=torch.float64, device=dev)
+    V = empty_colmajor(n, m, dev)
+    dz = torch.empty(n, dtype=torch.float64, device=dev)
+    dx = torch.empty(n, dtype=torch.float64, device=dev)
+
+    def step(i):
+        r.linearize(xb, want_cost=False, out=(d, g), defer_gradient=True)
+        r.rsvd(k, p_os, q=q, Omega=None, seed=1000 + i, want_info=False, lam=lam, V=V)
+        r.increment(lam, V, g, k=m, want_host=False, dz=dz, dx=dx)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        step(i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / steps
+    X = empty_colmajor(n, m, dev)
+    X.copy_(torch.randn(n, m, dtype=torch.float64, device=dev))
+    Yo = empty_colmajor(n, m, dev)
+    for _ in range(3):
+        r.gn_apply(X, out=Yo)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(10):
+        r.gn_apply(X, out=Yo)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_tlad = e0.elapsed_time(e1) / 10
+    # accuracy on the same probes as an FP64 handle's RSVD (seed 4242)
+    from paper_1906_01413_amd import Riot as _R
+    r64 = _R(n, T, float(prob["dt"]), float(prob["forcing"]), prob["obs_step"], prob["obs_idx"],
+             prob["y"], prob["rinv"], prob["taps"], m_max=m)
+    _, g_64, _ = r64.linearize(xb)
+    l64, V_64, _ = r64.rsvd(k, p_os, q=q, seed=4242, want_info=False)
+    _, dx64, _, _ = r64.increment(l64, V_64, g_64)
+    r.linearize(xb, want_cost=False, out=(d, g))
+    r.rsvd(k, p_os, q=q, seed=4242, want_info=False, lam=lam, V=V)
+    _, dx32, _, mode = r.increment(lam, V, g)
+    a, b = dx32.cpu().numpy(), dx64.cpu().numpy()
+    dxs = np.asarray(prob["dx"])
+    return {"workload": "the benchmarked workload with RIOT_FP32_TLAD",
+            "ms_per_step": ms_step, "hvp_per_s": m * (1 + q) / (ms_step / 1e3),
+            "tlad_ms_per_launch": ms_tlad,
+            "tlad_tflops": tlad_flops_per_column(n, T, nobs) * m / (ms_tlad / 1e3) / 1e12,
+            "increment_err_vs_fp64_rsvd": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+            "increment_err_vs_exact": float(np.linalg.norm(a - dxs) / np.linalg.norm(dxs)),
+            "fp64_increment_err_vs_exact": float(np.linalg.norm(b - dxs) / np.linalg.norm(dxs)),
+            "mode": mode}
 
 
 def batch_leg(nprob: int, seed: int, dev, reps: int = 5) -> dict:
@@ -394,6 +543,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the time-to-accuracy sweep")
     ap.add_argument("--hvp-reps", type=int, default=20)
+    ap.add_argument("--fp32", type=int, default=1,
+                    help="also run the FP32 TL/AD variant on the same workload (0 skips it)")
     ap.add_argument("--batch", type=int, default=1000,
                     help="problems in the batched-uneven leg (0 skips it)")
     ap.add_argument("--tracer", type=int, default=1,
@@ -464,15 +615,16 @@ def main():
         step(i)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream(dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    e0.record(stream)
+    evs[0].record(stream)
     for i in range(args.steps):
         step(args.warmup + i)
-    e1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_step = e0.elapsed_time(e1) / args.steps
+    ms_step = evs[0].elapsed_time(evs[-1]) / args.steps
+    per_step = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
     hvps_per_step = m * (1 + q)
     value = hvps_per_step / (ms_step / 1e3)
     print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step (wall {wall:.3f} s)",
@@ -513,6 +665,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_median": float(np.median(per_step)),
+        "ms_per_step_p90": float(np.percentile(per_step, 90)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -536,6 +690,26 @@ def main():
 
     if not args.no_accuracy:
         out["inner_loop"] = time_to_accuracy(r, prob, xb, dev)
+        il = out["inner_loop"]
+        print(f"[bench] inner loop n={n}: target {il['target_used']:.1e} (floor "
+              f"{il['reference_floor']:.1e}); RSVD m={il['rsvd']['m']} q={il['rsvd']['q']} "
+              f"err {il['rsvd']['max_err']:.2e} in {il['rsvd']['seconds']*1e3:.1f} ms; CG "
+              f"{il['cg']['iters']} it. err {il['cg']['err']:.2e} in {il['cg']['seconds']*1e3:.1f} ms",
+              file=sys.stderr, flush=True)
+        if args.workload != "l96_n40":
+            out["inner_loop_n40"] = small_inner_loop(args.seed, dev)
+            il = out["inner_loop_n40"]
+            print(f"[bench] inner loop n=40: RSVD m={il['rsvd']['m']} q={il['rsvd']['q']} err "
+                  f"{il['rsvd']['max_err']:.2e} in {il['rsvd']['seconds']*1e3:.2f} ms; CG "
+                  f"{il['cg']['iters']} it. err {il['cg']['err']:.2e} in "
+                  f"{il['cg']['seconds']*1e3:.2f} ms", file=sys.stderr, flush=True)
+
+    if args.fp32 and prec == 0:
+        out["fp32_tlad"] = fp32_leg(prob, k, p_os, q, args.steps, args.warmup, dev, lam, V, g)
+        fl = out["fp32_tlad"]
+        print(f"[bench] FP32 TL/AD: {fl['ms_per_step']:.3f} ms/step, TL/AD launch "
+              f"{fl['tlad_ms_per_launch']:.3f} ms; increment vs FP64 RSVD on the same probes "
+              f"{fl['increment_err_vs_fp64_rsvd']:.2e}", file=sys.stderr, flush=True)
 
     if args.batch > 0:
         print(f"[bench] batched leg: {args.batch} problems", file=sys.stderr, flush=True)

@@ -187,6 +187,23 @@ riot_status riot_increment(riot_handle *h, int32_t k, const double *lambda, cons
                            const double *grad, riot_update mode, double *dz, double *dx,
                            double *dofs_host, int32_t *mode_used);
 
+/* Deterministic choice between the two updates (Section 3.2.1, the first-inner-loop
+ * discussion of the small black-carbon problem): with the rank-k approximation at hand, form
+ * both the LRA and the LRU increment (as riot_increment), integrate the nonlinear model over
+ * the window from both updated states x + L dz_c in one launch (one workgroup each), evaluate
+ * the non-quadratic cost of eq. 2 in control variables, J_c = 1/2 |v + dz_c|^2
+ * + 1/2 (y - H(M(x + L dz_c)))^T R^{-1} (...), and keep the increment with the lower J (LRA on
+ * a tie). x must be the state of the current linearisation (x = x_b + L v).
+ *   lambda [>=k], V [n x >=k], grad [n], x [n] device; v [n] device or NULL (v = 0)
+ *   dz [n], dx [n] device out (dx = L dz), distinct from the inputs
+ *   J_host  host out [2] or NULL: J of the LRA and of the LRU candidate (synchronises)
+ *   mode_used host out or NULL: RIOT_LRA or RIOT_LRU as kept (synchronises)
+ * The handle's stored trajectory is not touched. */
+riot_status riot_increment_select(riot_handle *h, int32_t k, const double *lambda,
+                                  const double *V, const double *grad, const double *x,
+                                  const double *v, double *dz, double *dx, double *J_host,
+                                  int32_t *mode_used);
+
 /* Low-rank posterior error covariance in state space (eqs. 8-9, L symmetric):
  *   LRU: P_a = B + W diag(coef) W^T, coef_i = -l_i / (1 + l_i)
  *   LRA: P_a = W diag(coef) W^T,     coef_i = 1 / (1 + l_i)

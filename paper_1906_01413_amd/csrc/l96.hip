@@ -197,14 +197,33 @@ __device__ void store_block(double *xs64, float *xs32, int t, int s, int E_, int
   }
 }
 
+// xu != nullptr: one workgroup per initial state (x0 + blockIdx.x n), no stage blocks; the
+// state at every observed (step, variable) pair u is written to xu[blockIdx.x U + u].
+template <int E>
+__device__ __forceinline__ void sample_obs(const ModelView &mv, int t, int l,
+                                           const double (&x)[E], double *__restrict__ xu) {
+  const int k = mv.stepk[t];
+  if (k < 0) return;
+  const int us = mv.ustart[k * mv.NT + l];
+  const unsigned mask = (unsigned)mv.umask[k * mv.NT + l];
+#pragma unroll
+  for (int j = 0; j < E; ++j)
+    if ((mask >> j) & 1u) xu[us + __popc(mask & ((1u << j) - 1u))] = x[j];
+}
+
 template <int E>
 __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
     trajectory_kernel(ModelView mv, int nsteps, const double *__restrict__ x0,
                       double *__restrict__ xout, double *__restrict__ xs64,
-                      float *__restrict__ xs32, const TrajJob *__restrict__ jobs) {
+                      float *__restrict__ xs32, const TrajJob *__restrict__ jobs,
+                      double *__restrict__ xu) {
   if (jobs) {  // batched: one workgroup per problem (blockDim may exceed the problem's NT)
     const TrajJob &J = jobs[blockIdx.x];
     mv = J.mv, nsteps = J.mv.T, x0 = J.x0, xout = nullptr, xs64 = J.xs64, xs32 = J.xs32;
+  }
+  if (xu) {
+    x0 += (size_t)blockIdx.x * mv.n;
+    xu += (size_t)blockIdx.x * mv.U;
   }
   extern __shared__ double lds_d[];
   const int l = threadIdx.x;
@@ -230,6 +249,7 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
   };
 
   for (int t = 0; t < nsteps; ++t) {
+    if (xu && active) sample_obs<E>(mv, t, l, x, xu);
     // stage 1
     exchange<double, E>(lds_d, parity, NT, l, active, hm, x, hl2, hl1, hr1, hr2);
     if (active) {
@@ -279,6 +299,7 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
       }
     }
   }
+  if (xu && active) sample_obs<E>(mv, nsteps, l, x, xu);
   if (xs64) {
     exchange<double, E>(lds_d, parity, NT, l, active, hm, x, hl2, hl1, hr1, hr2);
     if (active) store_block<E>(xs64, xs32, nsteps, 0, E, NT, l, x, hl2, hl1, hr1, hr2);
@@ -881,6 +902,62 @@ __global__ void philox_normal_kernel(long long total, uint64_t seed, uint64_t st
   if (2 * j + 1 < total) out[2 * j + 1] = r * sin(th);
 }
 
+// ---------------------------------------------------------------------------
+// Deterministic LRA/LRU choice: candidate states, non-quadratic costs, selection.
+// ---------------------------------------------------------------------------
+
+// xc[c] = x + dx[c], vc[c] = v + dz[c] (v = nullptr: zero), c = 0 .. nc-1, n-vectors.
+__global__ void cand_state_kernel(int n, int nc, const double *__restrict__ x,
+                                  const double *__restrict__ v, const double *__restrict__ dz,
+                                  const double *__restrict__ dx, double *__restrict__ xc,
+                                  double *__restrict__ vc) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * nc) return;
+  const int i = (int)(e % n);
+  xc[e] = x[i] + dx[e];
+  vc[e] = (v ? v[i] : 0.0) + dz[e];
+}
+
+// J[c] = 1/2 vc^T vc + 1/2 sum_o rinv_o (y_o - x_c at o)^2 (eq. 2 in control variables), one
+// workgroup per candidate, sums in a fixed order.
+__global__ void __launch_bounds__(1024)
+    cand_cost_kernel(int n, const double *__restrict__ vc, int nobs, int U,
+                     const double *__restrict__ y, const double *__restrict__ rinv,
+                     const int *__restrict__ u_of_o, const double *__restrict__ xu,
+                     double *__restrict__ J) {
+  __shared__ double red[16];
+  const int c = blockIdx.x;
+  const double *v = vc + (size_t)c * n;
+  const double *xo = xu + (size_t)c * U;
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) a += v[i] * v[i];
+  for (int o = threadIdx.x; o < nobs; o += blockDim.x) {
+    const double d = y[o] - xo[u_of_o[o]];
+    b += rinv[o] * d * d;
+  }
+  const double sa = block_sum(a, red);
+  const double sb = block_sum(b, red);
+  if (threadIdx.x == 0) J[c] = 0.5 * sa + 0.5 * sb;
+}
+
+// The candidate with the lowest cost (the first on a tie; a non-finite cost never beats a
+// finite one) is copied to dz, dx; its index is written to mode_out (candidate 0 = LRA,
+// 1 = LRU: RIOT_LRA or RIOT_LRU).
+__global__ void cand_select_kernel(int n, int nc, const double *__restrict__ J,
+                                   const double *__restrict__ dzc, const double *__restrict__ dxc,
+                                   double *__restrict__ dz, double *__restrict__ dx,
+                                   int *__restrict__ mode_out) {
+  int best = 0;
+  for (int c = 1; c < nc; ++c)
+    if (isfinite(J[c]) && (!isfinite(J[best]) || J[c] < J[best])) best = c;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    dz[i] = dzc[(size_t)best * n + i];
+    dx[i] = dxc[(size_t)best * n + i];
+  }
+  if (i == 0 && mode_out) mode_out[0] = best == 0 ? RIOT_LRA : RIOT_LRU;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -917,7 +994,40 @@ hipError_t launch_trajectory(const ModelView &mv, int nsteps, const double *x0, 
                              double *xs64, float *xs32, hipStream_t st) {
   const size_t lds = (size_t)kLdsSlots * 2 * mv.NT * sizeof(double);
   RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL(trajectory_kernel<EE>, dim3(1), dim3(mv.NT), lds, st,
-                                           mv, nsteps, x0, xout, xs64, xs32, nullptr));
+                                           mv, nsteps, x0, xout, xs64, xs32, nullptr, nullptr));
+  return hipGetLastError();
+}
+
+hipError_t launch_window_obs(const ModelView &mv, int nstates, const double *x0, double *xu,
+                             hipStream_t st) {
+  if (nstates <= 0) return hipSuccess;
+  const size_t lds = (size_t)kLdsSlots * 2 * mv.NT * sizeof(double);
+  RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL(trajectory_kernel<EE>, dim3(nstates), dim3(mv.NT), lds,
+                                           st, mv, mv.T, x0, nullptr, nullptr, nullptr, nullptr,
+                                           xu));
+  return hipGetLastError();
+}
+
+hipError_t launch_cand_state(int n, int nc, const double *x, const double *v, const double *dz,
+                             const double *dx, double *xc, double *vc, hipStream_t st) {
+  const long long tot = (long long)n * nc;
+  hipLaunchKernelGGL(cand_state_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n,
+                     nc, x, v, dz, dx, xc, vc);
+  return hipGetLastError();
+}
+
+hipError_t launch_cand_cost(int n, int nc, const double *vc, int nobs, int U, const double *y,
+                            const double *rinv, const int *u_of_o, const double *xu, double *J,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(cand_cost_kernel, dim3(nc), dim3(1024), 0, st, n, vc, nobs, U, y, rinv,
+                     u_of_o, xu, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_cand_select(int n, int nc, const double *J, const double *dzc, const double *dxc,
+                              double *dz, double *dx, int *mode_out, hipStream_t st) {
+  hipLaunchKernelGGL(cand_select_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, nc, J, dzc,
+                     dxc, dz, dx, mode_out);
   return hipGetLastError();
 }
 
@@ -1077,7 +1187,7 @@ hipError_t launch_trajectory_batched(int nprob, const TrajJob *jobs, hipStream_t
   if (nprob <= 0) return hipSuccess;
   const size_t lds = (size_t)kLdsSlots * 2 * kBatchThreads * sizeof(double);
   hipLaunchKernelGGL(trajectory_kernel<8>, dim3(nprob), dim3(kBatchThreads), lds, st, ModelView{}, 0,
-                     nullptr, nullptr, nullptr, nullptr, jobs);
+                     nullptr, nullptr, nullptr, nullptr, jobs, nullptr);
   return hipGetLastError();
 }
 

@@ -140,6 +140,7 @@ struct riot_handle {
   double *G = nullptr, *R = nullptr, *B1 = nullptr, *B2 = nullptr, *K = nullptr, *Zs = nullptr,
          *sywork = nullptr;
   double *partial = nullptr, *cvec = nullptr, *scal = nullptr, *cgv = nullptr;
+  double *sel = nullptr;  // candidate increments, states and observed values (2 n x 4, 2 U, 2)
   int *flags = nullptr;
   ModelView mv{};
   // deferred gradient: lambda_0 of the gradient's adjoint sweep, and a second stream with
@@ -221,6 +222,7 @@ size_t carve(riot_handle &h, void *base) {
   h.cvec = c.take<double>(mm);
   h.scal = c.take<double>(16);
   h.cgv = c.take<double>((size_t)5 * n);
+  h.sel = c.take<double>((size_t)8 * n + 2 * U1 + 2);
   h.flags = c.take<int>(16);
   return c.off + 256;
 }
@@ -662,6 +664,45 @@ riot_status riot_increment(riot_handle *h, int32_t k, const double *lambda, cons
       RIOT_HIP(hipMemcpyAsync(&mu, la.flags + 8, sizeof(int), hipMemcpyDeviceToHost, st));
     RIOT_HIP(hipStreamSynchronize(st));
     if (mode_used) *mode_used = (mode == RIOT_ADAPTIVE) ? mu : (int32_t)mode;
+  }
+  return RIOT_OK;
+}
+
+// Deterministic LRA/LRU choice (Sec. 3.2.1): both increments from the same Ritz pairs, the
+// nonlinear window from both updated states in one launch (one workgroup each), the
+// non-quadratic costs, and the increment with the lower cost.
+riot_status riot_increment_select(riot_handle *h, int32_t k, const double *lambda,
+                                  const double *V, const double *grad, const double *x,
+                                  const double *v, double *dz, double *dx, double *J_host,
+                                  int32_t *mode_used) {
+  if (!h || !lambda || !V || !grad || !x || !dz || !dx || k < 1 || k > h->d.m_max ||
+      k > h->d.n)
+    return RIOT_E_ARG;
+  if (h->d.ckpt_stride > 0) return RIOT_E_STATE;
+  if (dz == dx || dz == grad || dx == grad || dz == x || dx == x) return RIOT_E_ARG;
+  riot_status rs = join_gradient(h);
+  if (rs != RIOT_OK) return rs;
+  const int n = h->d.n;
+  const size_t U1 = (size_t)std::max(h->U, 1);
+  hipStream_t st = h->st;
+  double *dzc = h->sel, *dxc = dzc + 2 * (size_t)n, *xc = dxc + 2 * (size_t)n;
+  double *vc = xc + 2 * (size_t)n, *xu = vc + 2 * (size_t)n, *J = xu + 2 * U1;
+  RIOT_HIP(gemm_f64(1, 0, k, 1, n, 1.0, V, n, grad, n, 0.0, h->cvec, k, h->partial, kSplitK, st));
+  RIOT_HIP(launch_increment_combine(n, k, lambda, V, h->cvec, grad, 0, dzc, h->scal + 4, st));
+  RIOT_HIP(launch_increment_combine(n, k, lambda, V, h->cvec, grad, 1, dzc + n, h->scal + 4, st));
+  RIOT_HIP(launch_apply_L(n, h->w, h->taps, 2, dzc, dxc, nullptr, 0, st));
+  RIOT_HIP(launch_cand_state(n, 2, x, v, dzc, dxc, xc, vc, st));
+  RIOT_HIP(launch_window_obs(h->mv, 2, xc, xu, st));
+  RIOT_HIP(launch_cand_cost(n, 2, vc, h->d.nobs, h->U, h->y, h->rinv, h->u_of_o, xu, J, st));
+  RIOT_HIP(launch_cand_select(n, 2, J, dzc, dxc, dz, dx, h->flags + 11, st));
+  if (J_host || mode_used) {
+    double jj[2];
+    int mu = 0;
+    RIOT_HIP(hipMemcpyAsync(jj, J, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    RIOT_HIP(hipMemcpyAsync(&mu, h->flags + 11, sizeof(int), hipMemcpyDeviceToHost, st));
+    RIOT_HIP(hipStreamSynchronize(st));
+    if (J_host) J_host[0] = jj[0], J_host[1] = jj[1];
+    if (mode_used) *mode_used = mu;
   }
   return RIOT_OK;
 }

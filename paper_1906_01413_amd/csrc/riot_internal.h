@@ -155,6 +155,16 @@ hipError_t launch_philox_batched(int nprob, long long maxtotal, uint64_t seed,
 
 // Nonlinear RK4 trajectory. When store != 0 the stage blocks of every step are
 // written (FP64 and, when xs32 != nullptr, FP32 copies), plus block (T, 0) = x_T.
+// Deterministic LRA/LRU choice (nonlinear window from several states, costs, selection).
+hipError_t launch_window_obs(const ModelView &mv, int nstates, const double *x0, double *xu,
+                             hipStream_t st);
+hipError_t launch_cand_state(int n, int nc, const double *x, const double *v, const double *dz,
+                             const double *dx, double *xc, double *vc, hipStream_t st);
+hipError_t launch_cand_cost(int n, int nc, const double *vc, int nobs, int U, const double *y,
+                            const double *rinv, const int *u_of_o, const double *xu, double *J,
+                            hipStream_t st);
+hipError_t launch_cand_select(int n, int nc, const double *J, const double *dzc, const double *dxc,
+                              double *dz, double *dx, int *mode_out, hipStream_t st);
 hipError_t launch_trajectory(const ModelView &mv, int nsteps, const double *x0, double *xout,
                              double *xs64, float *xs32, hipStream_t st);
 

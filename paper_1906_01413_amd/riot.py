@@ -28,7 +28,7 @@ MODES = {"adaptive": ADAPTIVE, "lra": LRA, "lru": LRU}
 
 EXPORTS = ("riot_workspace_bytes", "riot_init", "riot_free", "riot_status_str",
            "riot_linearize", "riot_linearize_deferred", "riot_join", "riot_hess_apply",
-           "riot_rsvd", "riot_increment",
+           "riot_rsvd", "riot_increment", "riot_increment_select",
            "riot_posterior_cov", "riot_cg", "riot_forecast", "riot_apply_L",
            "riot_philox_normal", "riot_tl_apply", "riot_ad_apply", "riot_gn_apply",
            "riot_batch_workspace_bytes", "riot_batch_init", "riot_batch_free", "riot_batch_buffers",
@@ -119,6 +119,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "riot_rsvd": (i32, [vp, i32, i32, i32, vp, u64, vp, vp, ctypes.POINTER(_RsvdInfo)]),
         "riot_increment": (i32, [vp, i32, vp, vp, vp, i32, vp, vp, ctypes.POINTER(dbl),
                                  ctypes.POINTER(i32)]),
+        "riot_increment_select": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl),
+                                        ctypes.POINTER(i32)]),
         "riot_posterior_cov": (i32, [vp, i32, vp, vp, i32, vp, vp, vp, vp, ctypes.POINTER(i32)]),
         "riot_cg": (i32, [vp, vp, i32, dbl, vp, vp, ctypes.POINTER(i32)]),
         "riot_forecast": (i32, [vp, vp, i32, vp]),
@@ -363,6 +365,23 @@ class Riot:
         self._pending = None  # the library joined a deferred gradient first
         used = {LRA: "lra", LRU: "lru"}.get(mu.value) if want_host else None
         return dz, dx, (dofs.value if want_host else None), used
+
+    def increment_select(self, lam, V, g, x, v=None, k=None):
+        """Both updates, two nonlinear windows, the lower non-quadratic cost kept
+        (riot_increment_select). Returns (dz, dx, mode, (J_lra, J_lru))."""
+        k = lam.numel() if k is None else int(k)
+        dz = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        dx = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        Jh = (ctypes.c_double * 2)()
+        mu = ctypes.c_int32(0)
+        xx = colmajor(x, self.device)
+        vv = None if v is None else colmajor(v, self.device)
+        _check(self.lib.riot_increment_select(self.h, k, _ptr(lam), _ptr(V), _ptr(g), _ptr(xx),
+                                              _ptr(vv), _ptr(dz), _ptr(dx),
+                                              ctypes.cast(Jh, ctypes.POINTER(ctypes.c_double)),
+                                              ctypes.byref(mu)), "riot_increment_select")
+        self._pending = None
+        return dz, dx, {LRA: "lra", LRU: "lru"}[mu.value], (Jh[0], Jh[1])
 
     def posterior_cov(self, lam, V, k=None, mode="adaptive", diag=True, dense=False,
                       want_host=True, out=None):

@@ -116,11 +116,27 @@ def test_fullsize_rsvd_properties_and_parity(big):
     # and the leading ones converge to them
     lam_ex = np.asarray(z["lam"])
     assert np.all(lam <= lam_ex[:272] * (1 + 1e-8) + 1e-8 * lam_ex[0])
-    assert np.max(np.abs(lam[:8] - lam_ex[:8]) / lam_ex[:8]) < 1e-3
+    # leading Ritz values within the range finder's error: Halko, Martinsson & Tropp (2011)
+    # Thm. 10.6 bounds E||(I - Q Q^T) A|| by (1 + sqrt(k/(p-1))) s_{k+1} + e sqrt(k+p)/p
+    # (sum_{j>k} s_j^2)^{1/2} (k = 256, p = 16, from the exact spectrum); a Ritz value moves
+    # by at most twice that norm (Weyl), and a further factor 2 leaves room for one draw
+    kk, po = 256, 16
+    halko = ((1 + np.sqrt(kk / (po - 1))) * lam_ex[kk]
+             + np.e * np.sqrt(kk + po) / po * np.sqrt(np.sum(lam_ex[kk:] ** 2)))
+    dev = np.abs(lam[:8] - lam_ex[:8])
+    print(f"leading Ritz values vs exact: {dev.max():.2e} (bound {4 * halko:.2e}; relative "
+          f"{np.max(dev / lam_ex[:8]):.1e})")
+    assert np.all(dev <= 4.0 * halko)
     # the oracle's RSVD on the same Philox probes (generated by its own Philox)
     Omo = philox.normal_columns(p.n, np.arange(272), seed=SEED, stream=0)
     ro = fourdvar.rsvd(lambda X: fourdvar.hvp(p, lin, X), Omo, q=0)
-    assert np.max(np.abs(lam - ro.lam)) <= 1e-9 * ro.lam[0]
+    # Ritz values to 1e-10 of the largest, unless the products themselves cannot agree that
+    # closely: the oracle's one-ulp sensitivity of its own products sets the floor
+    floor = _rounding_floor(p, lin, Omo[:, :4])
+    e_lam = float(np.max(np.abs(lam - ro.lam)) / ro.lam[0])
+    print(f"Ritz values vs oracle on the same probes: {e_lam:.2e} of lam1 "
+          f"(tolerance {max(1e-10, 10 * floor):.1e})")
+    assert e_lam <= max(1e-10, 10.0 * floor)
     dz, dx, dofs, mode = r.increment(torch.tensor(lam.copy(), device="cuda"),
                                      torch.tensor(V.T.copy(), device="cuda").t(),
                                      torch.tensor(g, device="cuda"))
@@ -131,15 +147,17 @@ def test_fullsize_rsvd_properties_and_parity(big):
     assert err < 1e-7
 
 
-@pytest.mark.parametrize("q,bound", [(0, 5e-4), (1, 1e-3)])
+@pytest.mark.parametrize("q,bound", [(0, 3e-4), (1, 1e-6)])
 def test_fullsize_wide_sketch_stays_orthonormal(q, bound):
     """m = 1088 probes: the sketch's singular values span the FP64 range (A's spectrum runs
     from 8e11 to rounding level), where a fixed three-pass CholeskyQR leaves Q far from
     orthonormal. The adaptive passes must give an orthonormal Q, Ritz values bounded by the
-    exact spectrum and an increment that converges to the stored exact minimiser (with one
-    power step the FP64 oracle, Householder QR, reaches 4.5e-5 on this problem). Two exact
-    FP64 solves of this problem differ by 5e-5; without a power step the bound is ten times
-    that, which a Cholesky whose panels lose accuracy with the Gram's condition misses."""
+    exact spectrum and an increment that converges to the stored exact minimiser. That
+    reference is certified to 5e-8 (refined solve plus the FP64-vs-extended-precision operator
+    shift), so with one power step the bound is the 1e-6 of the time-to-accuracy metric.
+    Without one the error is the sketch's own approximation error (3e-5 to 7e-5 over these
+    draws); a Cholesky whose panels lose accuracy with the Gram's condition missed its bound
+    (1.2e-3 on one draw)."""
     if not os.path.exists(REF):
         pytest.skip("reference problem not generated")
     z = dict(np.load(REF, allow_pickle=False))
@@ -160,3 +178,20 @@ def test_fullsize_wide_sketch_stays_orthonormal(q, bound):
         err = rel(to_np(dx), z["dx"])
         print(f"m=1088 q={q} seed {seed}: increment rel err vs exact {err:.2e}, mode {mode}")
         assert err < bound, seed
+
+
+def test_fullsize_posterior_covariance(big):
+    """Low-rank posterior covariance factors (eqs. 8-9) at n = 4096 from the 272 Ritz pairs
+    of the benchmarked sketch: W = L V, the coefficients and diag(P_a) for both updates
+    against the oracle on the same pairs."""
+    z, p, lin, r, g, J = big
+    lam, V, _ = r.rsvd(256, 16, q=0, Omega=None, seed=SEED, want_info=False)
+    lam_h, V_h = to_np(lam), to_np(V)
+    for mode in ("lru", "lra"):
+        W, coef, dg, _, used = r.posterior_cov(lam, V, mode=mode)
+        Wo, co, dgo, _, usedo = fourdvar.posterior_cov(p, lam_h, V_h, mode=mode)
+        e = (rel(to_np(W), Wo), rel(to_np(coef), co), rel(to_np(dg), dgo))
+        print(f"posterior covariance {mode} at n=4096: W {e[0]:.1e}, coef {e[1]:.1e}, "
+              f"diag {e[2]:.1e}")
+        assert used == usedo == mode
+        assert e[0] < 1e-13 and e[1] < 1e-14 and e[2] < 1e-12

@@ -7,6 +7,8 @@
 // in one workgroup with its state in registers; the periodic halo is exchanged
 // through LDS once per RK4 stage.
 
+#include <cstdlib>
+
 #include "riot_internal.h"
 
 namespace riot {
@@ -544,6 +546,287 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
 }
 
 // ---------------------------------------------------------------------------
+// TL/AD sweep with the base states staged through LDS (full members, E = 16, 256 threads per
+// member, two members per workgroup).
+//
+// Every RK4 stage reads one stage block of the stored trajectory. Loading it into registers
+// when the stage starts leaves the L2 latency on each stage's critical path (one member per
+// compute unit is a single wave per SIMD, with nothing else to switch to). Here the first E
+// rows of each block (the lane-interleaved own values; the four halo rows are the
+// neighbours' rows) are copied straight into a ring of four LDS slots with direct-to-LDS
+// loads (buffer_load_dwordx4 ... lds, no VGPRs), three stages before they are read: the TL
+// walks the blocks forward and refills, after each stage's barrier, the slot the previous
+// stage read with the block three ahead; the AD walks them backward the same way. Each wave
+// waits with s_waitcnt vmcnt for its own copies of the block it is about to read, and the
+// stage's halo barrier then covers the other waves' copies. The barriers are plain
+// s_barrier (a __syncthreads fence would wait for every copy in flight), and the LDS
+// pointers of one stage are restrict-qualified so the compiler does not add such a wait
+// either. Two members share the ring and each barrier (their base states are the same), one
+// wave of each per SIMD, so that each SIMD has a second wave to issue while one waits. The
+// arithmetic is that of Member (same order, same results), except that R^{-1} is applied
+// when the AD injects an observed value instead of when the TL stores it (the same product).
+// ---------------------------------------------------------------------------
+
+constexpr int kRingSlots = 4;
+constexpr int kRingNT = 256;   // threads per member (n = 16 * 256 = 4096)
+constexpr int kRingMembers = 2;  // members per workgroup, one group of waves each
+
+#define RIOT_LDSP(p) ((__attribute__((address_space(3))) void *)(p))
+
+// Wait until at most `later` fill groups (of K copies each) issued after the wanted one are
+// still in flight (later >= 2 is treated as 2, which only waits longer).
+template <int K>
+__device__ __forceinline__ void ring_wait(int later) {
+  static_assert(K == 2 || K == 4, "fill group size");
+  if (later >= 2) {
+    if constexpr (K == 4) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+  } else if (later == 1) {
+    if constexpr (K == 4) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
+  } else {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
+}
+
+__device__ __forceinline__ void raw_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <typename Real, int E>
+struct MemberRing {
+  static constexpr int NT = kRingNT;
+  static constexpr int WGT = kRingMembers * NT;           // threads per workgroup
+  static constexpr int per = 16 / (int)sizeof(Real);     // Reals per lane per copy
+  static constexpr int K = E * NT / (WGT * per);           // copies per stage block and thread
+  static constexpr int SLOT = E * NT;                      // Reals per slot
+  const ModelView &mv;
+  Real *xch;      // this member's halo exchange, 2 parities x kLdsSlots x NT
+  Real *ring;     // kRingSlots slots of E x NT, shared by the workgroup's members
+  int l, parity;  // l: lane within the member
+  int lm, lp;     // neighbour lanes (periodic)
+  int wv;         // wave index within the workgroup, read into a scalar register
+  unsigned voff;  // this thread's byte offset inside one copy of 16 bytes per thread
+  HaloMap<E> hm;
+  TrajRsrc tr;
+  int blk_bytes;  // bytes per stored stage block, (E + 4) NT sizeof(Real)
+  int nblk;       // 4 T stage blocks per sweep
+
+  __device__ MemberRing(const ModelView &m, Real *xch_, Real *ring_, int tid)
+      : mv(m), xch(xch_), ring(ring_), l(tid % NT), parity(0) {
+    hm.init(l, mv.n, NT);
+    lm = (l + NT - 1) % NT;
+    lp = (l + 1) % NT;
+    wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    voff = (unsigned)tid * 16u;
+    tr = traj_rsrc<Real>(mv);
+    blk_bytes = (E + 4) * NT * (int)sizeof(Real);
+    nblk = 4 * mv.T;
+  }
+
+  // Copy the first E rows (the own values, E x NT) of stage block b into slot F: K copies of
+  // 16 bytes per thread over the whole workgroup, straight into LDS (buffer_load_dwordx4 ...
+  // lds, no VGPR destination).
+  template <int F>
+  __device__ __forceinline__ void fill(int b) {
+    Real *dst = ring + F * SLOT + wv * 64 * per;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(tr.r, RIOT_LDSP(dst + i * WGT * per), 16, voff,
+                                               (unsigned)(b * blk_bytes + i * WGT * 16), 0, 0);
+  }
+
+  // One stage: wait for this stage's block in slot S (`later` = fills issued after it that
+  // may still be in flight), publish the boundary values, barrier, refill slot F with block
+  // `next` (when 0 <= next < nblk; slot F was read one stage earlier), then read the
+  // neighbours' values and the base state from LDS.
+  template <int S, int F>
+  __device__ __forceinline__ void stage_in(int later, int next, const Real (&v)[E], Real &hl2,
+                                           Real &hl1, Real &hr1, Real &hr2, Real (&xe)[E + 4]) {
+    ring_wait<K>(later);
+    stage_io<F>(ring + S * SLOT, xch + parity * kLdsSlots * NT, next, v, hl2, hl1, hr1, hr2, xe);
+    parity ^= 1;
+  }
+
+  template <int F>
+  __device__ __forceinline__ void stage_io(const Real *__restrict__ slot, Real *__restrict__ x,
+                                           int next, const Real (&v)[E], Real &hl2, Real &hl1,
+                                           Real &hr1, Real &hr2, Real (&xe)[E + 4]) {
+    x[0 * NT + l] = v[0];
+    x[1 * NT + l] = v[1];
+    x[2 * NT + l] = v[E - 2];
+    x[3 * NT + l] = v[E - 1];
+    raw_barrier();
+    if (next >= 0 && next < nblk) fill<F>(next);
+    hl2 = x[hm.off[0]];
+    hl1 = x[hm.off[1]];
+    hr1 = x[hm.off[2]];
+    hr2 = x[hm.off[3]];
+#pragma unroll
+    for (int j = 0; j < E; ++j) xe[2 + j] = slot[j * NT + l];
+    xe[0] = slot[(E - 2) * NT + lm];
+    xe[1] = slot[(E - 1) * NT + lm];
+    xe[E + 2] = slot[0 * NT + lp];
+    xe[E + 3] = slot[1 * NT + lp];
+  }
+
+  // The TL stores the raw observed values and the AD applies R^{-1} as it injects them (the
+  // same single product as weighting at the store): the TL then only stores, and never
+  // waits on a load, which would also wait for the ring copies in flight.
+  __device__ __forceinline__ void tl_store(int k, const Real (&dl)[E], Real *__restrict__ f) {
+    const int us = mv.ustart[k * NT + l];
+    const unsigned mask = (unsigned)mv.umask[k * NT + l];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      if ((mask >> j) & 1u) {
+        const int u = us + __popc(mask & ((1u << j) - 1u));
+        f[u] = dl[j];
+      }
+    }
+  }
+
+  __device__ __forceinline__ void ad_inject(int k, Real (&lam)[E], const Real *__restrict__ f) {
+    const int us = mv.ustart[k * NT + l];
+    const unsigned mask = (unsigned)mv.umask[k * NT + l];
+    const Real *wgt = reinterpret_cast<const Real *>(mv.wgt);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      if ((mask >> j) & 1u) {
+        const int u = us + __popc(mask & ((1u << j) - 1u));
+        lam[j] += wgt[u] * f[u];
+      }
+    }
+  }
+
+  // Fill-order bookkeeping. TL: blocks 0, 1, 2 before the sweep, then block b + 3 at stage b,
+  // so fills after block b's: min(2, nblk - 1 - b). AD (blocks nblk-1 .. 0): block b - 3 at
+  // stage b; the first block's fill is the TL's last (nothing after it), every other block
+  // has at least min(2, b) fills after its own.
+  __device__ __forceinline__ int later_tl(int b) const { return min(2, nblk - 1 - b); }
+  __device__ __forceinline__ int later_ad(int b) const { return b == nblk - 1 ? 0 : min(2, b); }
+
+  // TL over the window (R^{-1}-weighted observed values into f), then the AD forced by them.
+  __device__ void run(const double *__restrict__ dx0, double *__restrict__ lam0,
+                      Real *__restrict__ f) {
+    const int a = l * E;
+    const Real h = (Real)mv.h;
+    const Real h2 = (Real)(0.5 * mv.h);
+    const Real h3 = (Real)(mv.h / 3.0);
+    const Real h6 = (Real)(mv.h / 6.0);
+    Real dl[E], e[E], d[E], acc[E], xe[E + 4];
+    Real hl2, hl1, hr1, hr2;
+#pragma unroll
+    for (int j = 0; j < E; ++j) dl[j] = (Real)dx0[a + j];
+    fill<0>(0);
+    if (nblk > 1) fill<1>(1);
+    if (nblk > 2) fill<2>(2);
+    // tangent-linear sweep, blocks 0 .. 4T-1 (block 4t + s in slot s)
+    for (int t = 0; t <= mv.T; ++t) {
+      const int k = mv.stepk[t];
+      if (k >= 0) tl_store(k, dl, f);
+      if (t == mv.T) break;
+      const int b0 = 4 * t;
+      stage_in<0, 3>(later_tl(b0), b0 + 3, dl, hl2, hl1, hr1, hr2, xe);
+      tl_jac<Real, E>(xe, dl, hl2, hl1, hr1, d);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        acc[j] = d[j];
+        e[j] = dl[j] + h2 * d[j];
+      }
+      stage_in<1, 0>(later_tl(b0 + 1), b0 + 4, e, hl2, hl1, hr1, hr2, xe);
+      tl_jac<Real, E>(xe, e, hl2, hl1, hr1, d);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        acc[j] += (Real)2 * d[j];
+        e[j] = dl[j] + h2 * d[j];
+      }
+      stage_in<2, 1>(later_tl(b0 + 2), b0 + 5, e, hl2, hl1, hr1, hr2, xe);
+      tl_jac<Real, E>(xe, e, hl2, hl1, hr1, d);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        acc[j] += (Real)2 * d[j];
+        e[j] = dl[j] + h * d[j];
+      }
+      stage_in<3, 2>(later_tl(b0 + 3), b0 + 6, e, hl2, hl1, hr1, hr2, xe);
+      tl_jac<Real, E>(xe, e, hl2, hl1, hr1, d);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        acc[j] += d[j];
+        dl[j] = dl[j] + h6 * acc[j];
+      }
+    }
+    // adjoint sweep, blocks 4T-1 .. 0 (the last three are still in their slots; the first
+    // stages refill them with the same data, which no stage reads in between)
+    Real (&lam)[E] = dl;
+    Real (&lp_)[E] = e;
+    Real (&aa)[E] = acc;
+    Real (&sv)[E] = d;
+#pragma unroll
+    for (int j = 0; j < E; ++j) lam[j] = 0;
+    for (int t = mv.T; t >= 0; --t) {
+      const int k = mv.stepk[t];
+      if (k >= 0) ad_inject(k, lam, f);
+      if (t == 0) break;
+      const int b3 = 4 * (t - 1) + 3;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        lp_[j] = lam[j];
+        aa[j] = h6 * lp_[j];
+      }
+      stage_in<3, 0>(later_ad(b3), b3 - 3, aa, hl2, hl1, hr1, hr2, xe);
+      ad_jac<Real, E>(xe, aa, hl1, hr1, hr2, sv);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        lam[j] = lp_[j] + sv[j];
+        aa[j] = h3 * lp_[j] + h * sv[j];
+      }
+      stage_in<2, 3>(later_ad(b3 - 1), b3 - 4, aa, hl2, hl1, hr1, hr2, xe);
+      ad_jac<Real, E>(xe, aa, hl1, hr1, hr2, sv);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        lam[j] += sv[j];
+        aa[j] = h3 * lp_[j] + h2 * sv[j];
+      }
+      stage_in<1, 2>(later_ad(b3 - 2), b3 - 5, aa, hl2, hl1, hr1, hr2, xe);
+      ad_jac<Real, E>(xe, aa, hl1, hr1, hr2, sv);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        lam[j] += sv[j];
+        aa[j] = h6 * lp_[j] + h2 * sv[j];
+      }
+      stage_in<0, 1>(later_ad(b3 - 3), b3 - 6, aa, hl2, hl1, hr1, hr2, xe);
+      ad_jac<Real, E>(xe, aa, hl1, hr1, hr2, sv);
+#pragma unroll
+      for (int j = 0; j < E; ++j) lam[j] += sv[j];
+    }
+    // no copy may still be writing LDS when the workgroup ends
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (lam0) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) lam0[a + j] = (double)lam[j];
+    }
+  }
+};
+
+// Two members per workgroup (waves 0-3 and 4-7), one wave of each per SIMD: while one waits
+// on LDS or its dependences the SIMD issues the other's. They share the LDS ring (the base
+// state is the same for every member) and each barrier. An odd last member is shadowed by a
+// copy of the one before it, which computes but writes no result.
+template <typename Real, int E>
+__global__ void __launch_bounds__(kRingMembers * kRingNT)
+    tlad_ring_kernel(ModelView mv, int m, const double *__restrict__ dx0,
+                     double *__restrict__ lam0, Real *__restrict__ f) {
+  __shared__ __align__(16) Real ring[kRingSlots * E * kRingNT];
+  __shared__ __align__(16) Real xch[kRingMembers * 2 * kLdsSlots * kRingNT];
+  const int q = threadIdx.x / kRingNT;
+  const int mem = blockIdx.x * kRingMembers + q;
+  const int src = mem < m ? mem : m - 1;
+  MemberRing<Real, E> M(mv, xch + q * 2 * kLdsSlots * kRingNT, ring, threadIdx.x);
+  M.run(dx0 + (size_t)src * mv.n, mem < m ? lam0 + (size_t)mem * mv.n : nullptr,
+        f + (size_t)mem * (size_t)mv.U);
+}
+
+// ---------------------------------------------------------------------------
 // Persistent TL/AD over a batch of independent problems (8 elements per lane). Phase 1:
 // each workgroup takes whole-workgroup tiles (one member of a problem with NT > 64) from
 // an atomic counter; phase 2: each wave takes member-per-wave tiles (NT <= 64, the halo
@@ -964,6 +1247,16 @@ __global__ void cand_select_kernel(int n, int nc, const double *__restrict__ J,
 // Launchers
 // ---------------------------------------------------------------------------
 
+// The ring-staged TL/AD kernel serves the full-member E = 16 products unless RIOT_TLAD_RING=0
+// (kept for comparison runs against the register-loading kernel).
+static bool tlad_ring_enabled() {
+  static const bool on = [] {
+    const char *e = getenv("RIOT_TLAD_RING");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
 #define RIOT_DISPATCH_E(E_, CALL) \
   switch (E_) {                   \
     case 1: {                     \
@@ -1061,6 +1354,16 @@ hipError_t launch_tlad(const ModelView &mv, int m, int mode, const double *dx0, 
   if (m <= 0) return hipSuccess;
   const bool flags = (mode & ~7) != 0;
   const bool full = mv.A == mv.NT;
+  if (mode == 0 && full && mv.E == 16 && mv.NT == kRingNT && mv.T >= 1 && tlad_ring_enabled()) {
+    const dim3 grid((m + kRingMembers - 1) / kRingMembers), block(kRingMembers * kRingNT);
+    if (fp32)
+      hipLaunchKernelGGL((tlad_ring_kernel<float, 16>), grid, block, 0, st, mv, m, dx0, lam0,
+                         reinterpret_cast<float *>(f));
+    else
+      hipLaunchKernelGGL((tlad_ring_kernel<double, 16>), grid, block, 0, st, mv, m, dx0, lam0,
+                         reinterpret_cast<double *>(f));
+    return hipGetLastError();
+  }
 #define RIOT_TLAD(R_, F_, U_)                                                                   \
   RIOT_DISPATCH_E(mv.E, hipLaunchKernelGGL((tlad_kernel<R_, EE, F_, U_>), dim3(m), dim3(mv.NT), \
                                            lds, st, mv, mode, dx0, lam0,                        \

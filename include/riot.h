@@ -241,6 +241,62 @@ riot_status riot_ad_apply(riot_handle *h, int32_t m, const double *Fo, double *X
  *   X, Y [n x m] device (may not alias). Requires riot_linearize first. */
 riot_status riot_gn_apply(riot_handle *h, int32_t m, const double *X, double *Y);
 
+/* ------------------------------------------------------------------------------------
+ * Spectral preconditioner with rotation across outer loops (Alg. 3, precond and rotation
+ * branches; eqs. 6-7). After outer loop j the Ritz pairs (V_j, lambda_j) of that loop's
+ * preconditioned Hessian define the factor P'_j = I + V_j ((1 + lambda_j)^{-1/2} - 1) V_j^T
+ * (inverse: exponent +1/2; V_j orthonormal), and loop k uses P_k = P'_1 ... P'_{k-1}:
+ *   A_hat_k = P_k^T (I + A) P_k - I,  b = P_k^T g,  dv = P_k dw,  x_k = x_{k-1} + L dv.
+ * Ritz values below zero (rounding: A_hat_k is positive semi-definite) are taken as zero in
+ * the factors. The rotation draws the probes as P_k^{-1} (I - U_k U_k^T) omega with U_k an
+ * orthonormal basis of [P_1 V_1, ..., P_{k-1} V_{k-1}] (riot_orth, riot_project_out).
+ * A level list is nlev host entries: V[j] [n x mj[j]] and lambda[j] [mj[j]] device pointers
+ * (mj[j] <= min(n, m_max)); the caller keeps them allocated across the loops.
+ * ---------------------------------------------------------------------------------- */
+/* X [n x m] device, in place: op 0 = P_k X, 1 = P_k^T X, 2 = P_k^{-1} X (nlev = 0: identity). */
+riot_status riot_precond_apply(riot_handle *h, int32_t nlev, const double *const *V,
+                               const int32_t *mj, const double *const *lambda, int32_t op,
+                               int32_t m, double *X);
+/* Y = A_hat_k W = P_k^T (I + A) P_k W - W for m columns (W, Y [n x m] device, distinct);
+ * needs riot_linearize first. */
+riot_status riot_precond_hess_apply(riot_handle *h, int32_t nlev, const double *const *V,
+                                    const int32_t *mj, const double *const *lambda, int32_t m,
+                                    const double *W, double *Y);
+/* Q [n x m] device out: orthonormal basis of X [n x m] by the adaptive shifted CholeskyQR of
+ * riot_rsvd (1 <= m <= min(n, m_max)). */
+riot_status riot_orth(riot_handle *h, int32_t m, const double *X, double *Q);
+/* X <- (I - U U^T) X in place (two classical Gram-Schmidt passes) for orthonormal U [n x r],
+ * X [n x m] device. */
+riot_status riot_project_out(riot_handle *h, int32_t r, const double *U, int32_t m, double *X);
+/* Outer-loop update: v += dv, x += L dv ([n] device each, distinct). */
+riot_status riot_outer_update(riot_handle *h, const double *dv, double *v, double *x);
+
+/* ------------------------------------------------------------------------------------
+ * RIOT-PSAS (Appendix algorithm): the randomized solve in observation space, for windows
+ * with fewer observations than controls. A_hat = R^{-1/2} G B G^T R^{-1/2} (p x p, B = L L^T)
+ * has the nonzero spectrum of A; the dual increment is
+ *   dw = R^{-1/2} M R^{-1/2} (d - b'),  b' = G (x_b - x),  dx = B G^T dw,  x_new = x_b + dx,
+ * M = sum (1 + l)^{-1} u u^T (LRA) or I - sum l / (1 + l) u u^T (LRU) from the Ritz pairs of
+ * A_hat (eq. 11's rule). The algorithm as printed updates x_{k-1} + B H^T dw; since dw
+ * already carries b', that is the Gauss-Newton step only from x_b, which these calls use
+ * (the two agree at the first outer loop). The Ritz pairs come from the sketch handle on
+ * p-vectors: Y = riot_psas_hess_apply(Omega), riot_sketch_eig(p, m, Omega, Y, ...).
+ * All three need riot_linearize first (RIOT_E_STATE otherwise) and nobs >= 1.
+ * ---------------------------------------------------------------------------------- */
+/* Y = A_hat W for m observation-space probes: W, Y [nobs x m] device (ld nobs), distinct;
+ * one AD and one TL integration per column, 1 <= m <= m_max. */
+riot_status riot_psas_hess_apply(riot_handle *h, int32_t m, const double *W, double *Y);
+/* rhs = R^{-1/2} (d - G (x_b - x)) [nobs] device out; d [nobs] the innovation of the current
+ * linearisation (riot_linearize's d); xb_minus_x [n] device, or NULL when x = x_b (b' = 0). */
+riot_status riot_psas_rhs(riot_handle *h, const double *d, const double *xb_minus_x,
+                          double *rhs);
+/* dw [nobs] and dx [n] device out (dx = B G^T dw; the new state is x_b + dx) from the k
+ * leading Ritz pairs lambda [>=k], U [nobs x >=k] of A_hat, k <= min(nobs, m_max);
+ * mode_used host out or NULL (synchronises). */
+riot_status riot_psas_increment(riot_handle *h, int32_t k, const double *lambda, const double *U,
+                                const double *rhs, riot_update mode, double *dw, double *dx,
+                                int32_t *mode_used);
+
 /* Nonlinear forecast x(nsteps) from x0 with the handle's model (RK4, dt, F).
  * Used to build twin experiments and to cycle analyses. x0, xout [n] device. */
 riot_status riot_forecast(riot_handle *h, const double *x0, int32_t nsteps, double *xout);

@@ -409,3 +409,142 @@ def increment_select(p: Problem, lam: np.ndarray, V: np.ndarray, g: np.ndarray,
     if not np.isfinite(J_u) or (np.isfinite(J_a) and J_a <= J_u):
         return dz_a, dx_a, "lra", J_a, J_u
     return dz_u, dx_u, "lru", J_a, J_u
+
+
+# --------------------------------------------------------------------------
+# RIOT-PSAS: the randomized solve in observation space (Appendix algorithm)
+# --------------------------------------------------------------------------
+
+def psas_hvp(p: Problem, lin: Linearization, W: np.ndarray) -> np.ndarray:
+    """A_hat W with A_hat = R^{-1/2} G B G^T R^{-1/2} (p x p), B = L L^T = L^2: one adjoint
+    sweep forced by the scaled probe, B, one tangent-linear sweep sampled at the observations,
+    scaled again. R is diagonal, so its inverse square-root factor is diag(sqrt(rinv))."""
+    W = np.asarray(W, dtype=np.float64)
+    D = np.sqrt(p.rinv)
+    Dw = (D[:, None] * W) if W.ndim == 2 else D * W
+    X = adjoint_window(p, lin.stages, Dw)
+    X = bcov.apply_L(bcov.apply_L(X, p.taps), p.taps)
+    Z = tangent_window(p, lin.stages, X)
+    return (D[:, None] * Z) if Z.ndim == 2 else D * Z
+
+
+def psas_rhs(p: Problem, lin: Linearization, x: np.ndarray) -> np.ndarray:
+    """R^{-1/2} (d - b') with d = y - H(x) (eq. 3's sign) and b' = G (x_b - x): the right-hand
+    side of the dual solve at the current outer loop (b' = 0 at the first one, x = x_b)."""
+    bp = tangent_window(p, lin.stages, p.xb - np.asarray(x, dtype=np.float64))
+    return np.sqrt(p.rinv) * (lin.d - bp)
+
+
+def psas_increment(p: Problem, lin: Linearization, lam: np.ndarray, U: np.ndarray,
+                   rhs: np.ndarray, x: np.ndarray, k: int | None = None, mode: str = "adaptive"):
+    """Dual increment from the k leading Ritz pairs (lam, U) of A_hat:
+      LRA: dw = R^{-1/2} (sum_i (1 + l_i)^{-1} u_i u_i^T) rhs
+      LRU: dw = R^{-1/2} (I - sum_i l_i / (1 + l_i) u_i u_i^T) rhs
+    (eq. 11's rule on l_k), dx = B G^T dw, and the new state x_new = x_b + dx: the algorithm's
+    update x_{k-1} + B H^T dw is the Gauss-Newton step only from x_b, since its dw already
+    carries b' = G (x_b - x_{k-1}) (the two agree at the first outer loop, x = x_b).
+    Returns (dw, dx, x_new, mode)."""
+    k = lam.size if k is None else k
+    lk, Uk = lam[:k], U[:, :k]
+    if mode == "adaptive":
+        mode = choose_update(float(lk[-1]))
+    c = Uk.T @ rhs
+    if mode == "lra":
+        t = Uk @ (c / (1.0 + lk))
+    elif mode == "lru":
+        t = rhs - Uk @ (c * lk / (1.0 + lk))
+    else:
+        raise ValueError(mode)
+    dw = np.sqrt(p.rinv) * t
+    dx = bcov.apply_L(bcov.apply_L(adjoint_window(p, lin.stages, dw), p.taps), p.taps)
+    return dw, dx, p.xb + dx, mode
+
+
+# --------------------------------------------------------------------------
+# Spectral preconditioner and rotation across outer loops (Alg. 3, precond / rotation)
+# --------------------------------------------------------------------------
+
+def precond_factor_apply(V: np.ndarray, lt: np.ndarray, X: np.ndarray, power: float) -> np.ndarray:
+    """(I + V (lt^power - 1) V^T) X for orthonormal V (n x m_j) and lt = lambda + 1 (m_j):
+    power -1/2 is the factor P'_j of eq. 7's spectral preconditioner, +1/2 its inverse."""
+    return X + V @ ((lt ** power - 1.0)[:, None] * (V.T @ X)) if X.ndim == 2 else \
+        X + V @ ((lt ** power - 1.0) * (V.T @ X))
+
+
+def precond_apply(levels: list, X: np.ndarray, op: str) -> np.ndarray:
+    """P_k = P'_1 P'_2 ... P'_{k-1} (the symmetric factors of the earlier outer loops, `levels`
+    = [(V_1, lt_1), ..., (V_{k-1}, lt_{k-1})]) applied to X:
+      'P'    P X     (P'_{k-1} first),
+      'PT'   P^T X   (P'_1 first; every factor is symmetric),
+      'Pinv' P^{-1} X = P'_{k-1}^{-1} ... P'_1^{-1} X (P'_1^{-1} first)."""
+    X = np.array(X, dtype=np.float64)
+    if op == "P":
+        for V, lt in reversed(levels):
+            X = precond_factor_apply(V, lt, X, -0.5)
+    elif op == "PT":
+        for V, lt in levels:
+            X = precond_factor_apply(V, lt, X, -0.5)
+    elif op == "Pinv":
+        for V, lt in levels:
+            X = precond_factor_apply(V, lt, X, 0.5)
+    else:
+        raise ValueError(op)
+    return X
+
+
+def precond_hvp(p: Problem, lin: Linearization, levels: list, W: np.ndarray) -> np.ndarray:
+    """A_hat_k W = P^T (I + A) P W - W (Alg. 3's preconditioned operator, P = P_k)."""
+    PW = precond_apply(levels, W, "P")
+    return precond_apply(levels, PW + hvp(p, lin, PW), "PT") - np.asarray(W, dtype=np.float64)
+
+
+def rotate_probes(levels: list, resolved: list, Omega: np.ndarray) -> np.ndarray:
+    """Rotation of Alg. 3: U_k = orthonormal basis (QR) of [P_1 V_1, ..., P_{k-1} V_{k-1}]
+    (`resolved`, each block the earlier loop's Ritz vectors mapped by that loop's own
+    preconditioner), then omega <- P_k^{-1} (I - U_k U_k^T) omega."""
+    if not resolved:
+        return np.array(Omega, dtype=np.float64)
+    U = orth(np.hstack(resolved))
+    Om = np.asarray(Omega, dtype=np.float64)
+    return precond_apply(levels, Om - U @ (U.T @ Om), "Pinv")
+
+
+def riot_outer_loops(p: Problem, probes: list, k_outer: int, precond: bool, rotation: bool,
+                     q: int = 0):
+    """Alg. 3 over k_outer outer loops with the spectral preconditioner (and rotation).
+
+    At loop k: linearise at x_{k-1} (g = v - L G^T R^{-1} d), b = P_k^T g (reading: the
+    algorithm's b + v_{k-1} written for P = I), rotated probes if asked, RSVD of
+    A_hat_k = P_k^T (I + A) P_k - I on probes[k] (q power steps), adaptive increment dw from b,
+    dv = P_k dw, v_k = v_{k-1} + dv, x_k = x_{k-1} + L dv (so x_k = x_b + L v_k throughout), and
+    the new factor P'_k from (V, lambda + 1) with lambda clamped at 0 (A_hat is positive
+    semi-definite; a negative Ritz value is rounding). Returns a list of per-loop records
+    (J at the linearisation, lambda, mode) and the final (v, x, J).
+    """
+    v = np.zeros(p.n)
+    x = p.xb.copy()
+    levels, resolved, hist = [], [], []
+    for k in range(k_outer):
+        lin = linearize(p, x, v)
+        b = precond_apply(levels, lin.g, "PT") if precond else lin.g
+        Om = probes[k]
+        if precond and rotation:
+            Om = rotate_probes(levels, resolved, Om)
+        op = (lambda X, lin=lin: precond_hvp(p, lin, levels, X)) if precond else \
+            (lambda X, lin=lin: hvp(p, lin, X))
+        rs = rsvd(op, Om, q=q)
+        mode = choose_update(float(rs.lam[-1]))
+        c = rs.V.T @ b
+        if mode == "lra":
+            dw = -(rs.V @ (c / (1.0 + rs.lam)))
+        else:
+            dw = -(b - rs.V @ (c * rs.lam / (1.0 + rs.lam)))
+        dv = precond_apply(levels, dw, "P") if precond else dw
+        hist.append({"J": lin.J, "lam": rs.lam, "V": rs.V, "mode": mode, "dv": dv,
+                     "probe_norm_ratio": float(np.linalg.norm(probes[k]) / np.linalg.norm(Om))})
+        if precond:
+            resolved.append(precond_apply(levels, rs.V, "P"))
+            levels.append((rs.V, 1.0 + np.maximum(rs.lam, 0.0)))
+        v = v + dv
+        x = x + bcov.apply_L(dv, p.taps)
+    return hist, v, x, cost(p, v)

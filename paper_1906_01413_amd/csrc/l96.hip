@@ -942,27 +942,52 @@ __global__ void obs_value_kernel(ModelView mv, const double *__restrict__ xs64, 
   out[o] = xs64[(size_t)((t - lo) * 4) * (size_t)(mv.E + 4) * mv.NT + (size_t)j * mv.NT + l];
 }
 
-// Z[o, j] = f_j[u(o)] : raw TL values back in the caller's observation order.
+// Z[o, j] = f_j[u(o)] : raw TL values back in the caller's observation order, multiplied by
+// sqrt(rinv[o]) when rinv is given (the R^{-1/2} factor of the dual operator).
 template <typename Real>
 __global__ void obs_gather_kernel(int nobs, int U, int m, const int *__restrict__ u_of_o,
-                                  const Real *__restrict__ f, double *__restrict__ Z) {
+                                  const Real *__restrict__ f, double *__restrict__ Z,
+                                  const double *__restrict__ rinv) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)nobs * m) return;
   const int o = (int)(idx % nobs), j = (int)(idx / nobs);
-  Z[idx] = (double)f[(size_t)j * U + u_of_o[o]];
+  const double z = (double)f[(size_t)j * U + u_of_o[o]];
+  Z[idx] = rinv ? sqrt(rinv[o]) * z : z;
 }
 
-// f_j[u] = sum_{o in u} F[o, j] : observation-space forcing folded onto unique pairs.
+// f_j[u] = sum_{o in u} F[o, j] : observation-space forcing folded onto unique pairs (each
+// F[o, j] first multiplied by sqrt(rinv[o]) when rinv is given).
 template <typename Real>
 __global__ void obs_scatter_kernel(int nobs, int U, int m, const int *__restrict__ u_optr,
                                    const int *__restrict__ u_olist, const double *__restrict__ Fo,
-                                   Real *__restrict__ f) {
+                                   Real *__restrict__ f, const double *__restrict__ rinv) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)U * m) return;
   const int u = (int)(idx % U), j = (int)(idx / U);
   double s = 0.0;
-  for (int q = u_optr[u]; q < u_optr[u + 1]; ++q) s += Fo[(size_t)j * nobs + u_olist[q]];
+  for (int q = u_optr[u]; q < u_optr[u + 1]; ++q) {
+    const int o = u_olist[q];
+    const double v = Fo[(size_t)j * nobs + o];
+    s += rinv ? sqrt(rinv[o]) * v : v;
+  }
   f[idx] = (Real)s;
+}
+
+// Dual right-hand side and increment scaling: out[o] = sqrt(rinv[o]) (d[o] - bp[o]) (bp may be
+// nullptr), and dw[o] = -sqrt(rinv[o]) t[o] (t from the negated low-rank combination).
+__global__ void psas_rhs_kernel(int nobs, const double *__restrict__ rinv,
+                                const double *__restrict__ d, const double *__restrict__ bp,
+                                double *__restrict__ out) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nobs) return;
+  out[o] = sqrt(rinv[o]) * (bp ? d[o] - bp[o] : d[o]);
+}
+
+__global__ void psas_scale_kernel(int nobs, const double *__restrict__ rinv,
+                                  const double *__restrict__ t, double *__restrict__ dw) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nobs) return;
+  dw[o] = -sqrt(rinv[o]) * t[o];
 }
 
 __device__ double block_sum(double v, double *red) {
@@ -1402,30 +1427,47 @@ hipError_t launch_obs_value(const ModelView &mv, const double *xs64, int nobs, c
 }
 
 hipError_t launch_obs_gather(int nobs, int U, int m, const int *u_of_o, const void *f, double *Z,
-                             bool fp32, hipStream_t st) {
+                             bool fp32, hipStream_t st, const double *rinv) {
   const size_t tot = (size_t)nobs * m;
   if (tot == 0) return hipSuccess;
   const unsigned grid = (unsigned)((tot + 255) / 256);
   if (fp32)
     hipLaunchKernelGGL(obs_gather_kernel<float>, dim3(grid), dim3(256), 0, st, nobs, U, m, u_of_o,
-                       reinterpret_cast<const float *>(f), Z);
+                       reinterpret_cast<const float *>(f), Z, rinv);
   else
     hipLaunchKernelGGL(obs_gather_kernel<double>, dim3(grid), dim3(256), 0, st, nobs, U, m, u_of_o,
-                       reinterpret_cast<const double *>(f), Z);
+                       reinterpret_cast<const double *>(f), Z, rinv);
   return hipGetLastError();
 }
 
 hipError_t launch_obs_scatter(int nobs, int U, int m, const int *u_optr, const int *u_olist,
-                              const double *Fo, void *f, bool fp32, hipStream_t st) {
+                              const double *Fo, void *f, bool fp32, hipStream_t st,
+                              const double *rinv) {
   const size_t tot = (size_t)U * m;
   if (tot == 0) return hipSuccess;
   const unsigned grid = (unsigned)((tot + 255) / 256);
   if (fp32)
     hipLaunchKernelGGL(obs_scatter_kernel<float>, dim3(grid), dim3(256), 0, st, nobs, U, m, u_optr,
-                       u_olist, Fo, reinterpret_cast<float *>(f));
+                       u_olist, Fo, reinterpret_cast<float *>(f), rinv);
   else
     hipLaunchKernelGGL(obs_scatter_kernel<double>, dim3(grid), dim3(256), 0, st, nobs, U, m, u_optr,
-                       u_olist, Fo, reinterpret_cast<double *>(f));
+                       u_olist, Fo, reinterpret_cast<double *>(f), rinv);
+  return hipGetLastError();
+}
+
+hipError_t launch_psas_rhs(int nobs, const double *rinv, const double *d, const double *bp,
+                           double *out, hipStream_t st) {
+  if (nobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(psas_rhs_kernel, dim3((nobs + 255) / 256), dim3(256), 0, st, nobs, rinv, d, bp,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_psas_scale(int nobs, const double *rinv, const double *t, double *dw,
+                             hipStream_t st) {
+  if (nobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(psas_scale_kernel, dim3((nobs + 255) / 256), dim3(256), 0, st, nobs, rinv, t,
+                     dw);
   return hipGetLastError();
 }
 

@@ -1292,4 +1292,49 @@ hipError_t gemm_f64_strided(int ta, int tb, int M, int N, int K, double alpha, c
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Spectral preconditioner factors (eq. 7) and small vector updates of the outer loop.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// C[i, c] *= (1 + max(lam_i, 0))^power - 1 for an m_j x m block (ld m_j): the middle factor of
+// I + V ((lam + 1)^power - 1) V^T (power -1/2: the preconditioner factor, +1/2: its inverse).
+// Ritz values of the positive semi-definite preconditioned Hessian below zero are rounding and
+// are taken as zero.
+__global__ void precond_scale_kernel(int mj, int m, const double *__restrict__ lam, double power,
+                                     double *__restrict__ C) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)mj * m) return;
+  const int i = (int)(e % mj);
+  const double lt = 1.0 + fmax(lam[i], 0.0);
+  C[e] *= pow(lt, power) - 1.0;
+}
+
+// Y[e] = a Y[e] + b X[e]
+__global__ void axpby_kernel(long long count, double a, double *__restrict__ Y, double b,
+                             const double *__restrict__ X) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) Y[e] = a * Y[e] + b * X[e];
+}
+
+}  // namespace
+
+hipError_t launch_precond_scale(int mj, int m, const double *lam, double power, double *C,
+                                hipStream_t st) {
+  const long long tot = (long long)mj * m;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(precond_scale_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     mj, m, lam, power, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(long long count, double a, double *Y, double b, const double *X,
+                        hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count,
+                     a, Y, b, X);
+  return hipGetLastError();
+}
+
 }  // namespace riot

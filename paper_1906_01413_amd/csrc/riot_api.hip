@@ -141,6 +141,7 @@ struct riot_handle {
          *sywork = nullptr;
   double *partial = nullptr, *cvec = nullptr, *scal = nullptr, *cgv = nullptr;
   double *sel = nullptr;  // candidate increments, states and observed values (2 n x 4, 2 U, 2)
+  double *pso = nullptr;  // observation-space vectors of the dual solve (2 nobs)
   int *flags = nullptr;
   ModelView mv{};
   // deferred gradient: lambda_0 of the gradient's adjoint sweep, and a second stream with
@@ -223,6 +224,7 @@ size_t carve(riot_handle &h, void *base) {
   h.scal = c.take<double>(16);
   h.cgv = c.take<double>((size_t)5 * n);
   h.sel = c.take<double>((size_t)8 * n + 2 * U1 + 2);
+  h.pso = c.take<double>((size_t)2 * std::max(d.nobs, 1));
   h.flags = c.take<int>(16);
   return c.off + 256;
 }
@@ -769,6 +771,171 @@ riot_status riot_ad_apply(riot_handle *h, int32_t m, const double *Fo, double *X
   hipStream_t st = h->st;
   RIOT_HIP(launch_obs_scatter(h->d.nobs, h->U, m, h->u_optr, h->u_olist, Fo, h->f, h->fp32, st));
   RIOT_HIP(launch_tlad(h->mv, m, 3, nullptr, X, h->f, nullptr, h->fp32, st));
+  return RIOT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Spectral preconditioner and rotation across outer loops (Alg. 3, precond / rotation).
+// ---------------------------------------------------------------------------
+
+static riot_status precond_apply_impl(riot_handle *h, int nlev, const double *const *V,
+                                      const int32_t *mj, const double *const *lam, int op, int m,
+                                      double *X) {
+  const int n = h->d.n;
+  hipStream_t st = h->st;
+  const double power = op == 2 ? 0.5 : -0.5;
+  for (int q = 0; q < nlev; ++q) {
+    const int j = op == 0 ? nlev - 1 - q : q;  // P applies the last factor first
+    const int k = mj[j];
+    RIOT_HIP(gemm_f64(1, 0, k, m, n, 1.0, V[j], n, X, n, 0.0, h->B1, k, h->partial, kSplitK, st));
+    RIOT_HIP(launch_precond_scale(k, m, lam[j], power, h->B1, st));
+    RIOT_HIP(gemm_f64(0, 0, n, m, k, 1.0, V[j], n, h->B1, k, 1.0, X, n, nullptr, 1, st));
+  }
+  return RIOT_OK;
+}
+
+static bool precond_args_ok(const riot_handle *h, int nlev, const double *const *V,
+                            const int32_t *mj, const double *const *lam, int m) {
+  if (nlev < 0 || m < 1 || m > h->d.m_max) return false;
+  if (nlev > 0 && (!V || !mj || !lam)) return false;
+  for (int j = 0; j < nlev; ++j)
+    if (!V[j] || !lam[j] || mj[j] < 1 || mj[j] > h->d.m_max || mj[j] > h->d.n) return false;
+  return true;
+}
+
+riot_status riot_precond_apply(riot_handle *h, int32_t nlev, const double *const *V,
+                               const int32_t *mj, const double *const *lam, int32_t op,
+                               int32_t m, double *X) {
+  if (!h || !X || op < 0 || op > 2 || !precond_args_ok(h, nlev, V, mj, lam, m)) return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
+  return precond_apply_impl(h, nlev, V, mj, lam, op, m, X);
+}
+
+riot_status riot_precond_hess_apply(riot_handle *h, int32_t nlev, const double *const *V,
+                                    const int32_t *mj, const double *const *lam, int32_t m,
+                                    const double *W, double *Y) {
+  if (!h || !W || !Y || W == Y || !precond_args_ok(h, nlev, V, mj, lam, m)) return RIOT_E_ARG;
+  if (h->d.ckpt_stride > 0) return RIOT_E_STATE;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
+  if (!h->linearized) return RIOT_E_STATE;
+  const int n = h->d.n;
+  hipStream_t st = h->st;
+  // T = P W; Y = (I + A) T; Y <- P^T Y - W
+  RIOT_HIP(hipMemcpyAsync(h->Q0, W, (size_t)n * m * sizeof(double), hipMemcpyDeviceToDevice, st));
+  riot_status rs = precond_apply_impl(h, nlev, V, mj, lam, 0, m, h->Q0);
+  if (rs != RIOT_OK) return rs;
+  rs = hess_apply_impl(h, m, h->Q0, Y, 1);
+  if (rs != RIOT_OK) return rs;
+  rs = precond_apply_impl(h, nlev, V, mj, lam, 1, m, Y);
+  if (rs != RIOT_OK) return rs;
+  RIOT_HIP(launch_axpby((long long)n * m, 1.0, Y, -1.0, W, st));
+  return RIOT_OK;
+}
+
+riot_status riot_orth(riot_handle *h, int32_t m, const double *X, double *Q) {
+  if (!h || !X || !Q || m < 1 || m > h->d.m_max || m > h->d.n) return RIOT_E_ARG;
+  if (Q == h->Q) return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
+  LaSpace la = la_of(h);
+  RIOT_HIP(launch_zero_ints(la.flags, 16, h->st));
+  return cholqr(la, h->d.n, m, X, Q, true, 0);
+}
+
+riot_status riot_project_out(riot_handle *h, int32_t r, const double *U, int32_t m, double *X) {
+  if (!h || !U || !X || r < 1 || m < 1 || r > h->d.m_max || m > h->d.m_max || r > h->d.n)
+    return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
+  const int n = h->d.n;
+  hipStream_t st = h->st;
+  for (int pass = 0; pass < 2; ++pass) {  // twice: classical Gram-Schmidt to rounding level
+    RIOT_HIP(gemm_f64(1, 0, r, m, n, 1.0, U, n, X, n, 0.0, h->B2, r, h->partial, kSplitK, st));
+    RIOT_HIP(gemm_f64(0, 0, n, m, r, -1.0, U, n, h->B2, r, 1.0, X, n, nullptr, 1, st));
+  }
+  return RIOT_OK;
+}
+
+riot_status riot_outer_update(riot_handle *h, const double *dv, double *v, double *x) {
+  if (!h || !dv || !v || !x || dv == v || dv == x || v == x) return RIOT_E_ARG;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
+  const int n = h->d.n;
+  hipStream_t st = h->st;
+  RIOT_HIP(launch_apply_L(n, h->w, h->taps, 1, dv, h->LW, nullptr, 0, st));
+  RIOT_HIP(launch_axpby(n, 1.0, x, 1.0, h->LW, st));
+  RIOT_HIP(launch_axpby(n, 1.0, v, 1.0, dv, st));
+  return RIOT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// RIOT-PSAS (Appendix algorithm): the randomized solve in observation space.
+// ---------------------------------------------------------------------------
+
+riot_status riot_psas_hess_apply(riot_handle *h, int32_t m, const double *W, double *Y) {
+  if (!h || !W || !Y || W == Y || m < 1 || m > h->d.m_max || h->d.nobs < 1) return RIOT_E_ARG;
+  if (h->d.ckpt_stride > 0) return RIOT_E_STATE;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
+  if (!h->linearized) return RIOT_E_STATE;
+  const int n = h->d.n, no = h->d.nobs;
+  hipStream_t st = h->st;
+  // X = G^T R^{-1/2} W, then B X = L (L X), then R^{-1/2} G B X at the observations
+  RIOT_HIP(launch_obs_scatter(no, h->U, m, h->u_optr, h->u_olist, W, h->f, h->fp32, st, h->rinv));
+  RIOT_HIP(launch_tlad(h->mv, m, 3, nullptr, h->LAM, h->f, nullptr, h->fp32, st));
+  RIOT_HIP(launch_apply_L(n, h->w, h->taps, m, h->LAM, h->LW, nullptr, 0, st));
+  RIOT_HIP(launch_apply_L(n, h->w, h->taps, m, h->LW, h->LAM, nullptr, 0, st));
+  RIOT_HIP(launch_tlad(h->mv, m, 2, h->LAM, nullptr, h->f, nullptr, h->fp32, st));
+  RIOT_HIP(launch_obs_gather(no, h->U, m, h->u_of_o, h->f, Y, h->fp32, st, h->rinv));
+  return RIOT_OK;
+}
+
+riot_status riot_psas_rhs(riot_handle *h, const double *d, const double *xb_minus_x,
+                          double *rhs) {
+  if (!h || !d || !rhs || d == rhs || h->d.nobs < 1) return RIOT_E_ARG;
+  if (h->d.ckpt_stride > 0) return RIOT_E_STATE;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
+  if (!h->linearized) return RIOT_E_STATE;
+  const int no = h->d.nobs;
+  hipStream_t st = h->st;
+  const double *bp = nullptr;
+  if (xb_minus_x) {
+    RIOT_HIP(launch_tlad(h->mv, 1, 2, xb_minus_x, nullptr, h->f, nullptr, h->fp32, st));
+    RIOT_HIP(launch_obs_gather(no, h->U, 1, h->u_of_o, h->f, h->pso, h->fp32, st));
+    bp = h->pso;
+  }
+  RIOT_HIP(launch_psas_rhs(no, h->rinv, d, bp, rhs, st));
+  return RIOT_OK;
+}
+
+riot_status riot_psas_increment(riot_handle *h, int32_t k, const double *lambda, const double *U,
+                                const double *rhs, riot_update mode, double *dw, double *dx,
+                                int32_t *mode_used) {
+  const int no = h ? h->d.nobs : 0;
+  if (!h || !lambda || !U || !rhs || !dw || !dx || no < 1 || k < 1 || k > no ||
+      k > h->d.m_max)
+    return RIOT_E_ARG;
+  if (mode != RIOT_ADAPTIVE && mode != RIOT_LRA && mode != RIOT_LRU) return RIOT_E_ARG;
+  if (dw == rhs || (const double *)dx == U) return RIOT_E_ARG;
+  if (h->d.ckpt_stride > 0) return RIOT_E_STATE;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
+  if (!h->linearized) return RIOT_E_STATE;
+  const int n = h->d.n;
+  hipStream_t st = h->st;
+  double *t = h->pso + no;
+  // c = U^T rhs; t = -(LRA or LRU combination of rhs); dw = -R^{-1/2} t
+  RIOT_HIP(gemm_f64(1, 0, k, 1, no, 1.0, U, no, rhs, no, 0.0, h->cvec, k, h->partial, kSplitK, st));
+  const int ml = mode == RIOT_LRA ? 0 : (mode == RIOT_LRU ? 1 : 2);
+  RIOT_HIP(launch_increment_combine(no, k, lambda, U, h->cvec, rhs, ml, t, h->scal + 4, st));
+  RIOT_HIP(launch_psas_scale(no, h->rinv, t, dw, st));
+  // dx = B G^T dw = L (L (G^T dw))
+  RIOT_HIP(launch_obs_scatter(no, h->U, 1, h->u_optr, h->u_olist, dw, h->f, h->fp32, st));
+  RIOT_HIP(launch_tlad(h->mv, 1, 3, nullptr, h->LAM, h->f, nullptr, h->fp32, st));
+  RIOT_HIP(launch_apply_L(n, h->w, h->taps, 1, h->LAM, h->LW, nullptr, 0, st));
+  RIOT_HIP(launch_apply_L(n, h->w, h->taps, 1, h->LW, dx, nullptr, 0, st));
+  if (mode_used) {
+    int mu = 0;
+    RIOT_HIP(launch_choose_mode(k, lambda, h->flags + 8, st));
+    RIOT_HIP(hipMemcpyAsync(&mu, h->flags + 8, sizeof(int), hipMemcpyDeviceToHost, st));
+    RIOT_HIP(hipStreamSynchronize(st));
+    *mode_used = (mode == RIOT_ADAPTIVE) ? mu : (int32_t)mode;
+  }
   return RIOT_OK;
 }
 

@@ -155,6 +155,11 @@ hipError_t launch_philox_batched(int nprob, long long maxtotal, uint64_t seed,
 
 // Nonlinear RK4 trajectory. When store != 0 the stage blocks of every step are
 // written (FP64 and, when xs32 != nullptr, FP32 copies), plus block (T, 0) = x_T.
+// Dual (observation-space) right-hand side and increment scaling by R^{-1/2}.
+hipError_t launch_psas_rhs(int nobs, const double *rinv, const double *d, const double *bp,
+                           double *out, hipStream_t st);
+hipError_t launch_psas_scale(int nobs, const double *rinv, const double *t, double *dw,
+                             hipStream_t st);
 // Deterministic LRA/LRU choice (nonlinear window from several states, costs, selection).
 hipError_t launch_window_obs(const ModelView &mv, int nstates, const double *x0, double *xu,
                              hipStream_t st);
@@ -198,9 +203,10 @@ hipError_t launch_obs_value(const ModelView &mv, const double *xs64, int nobs, c
 
 // Observation-space values <-> per-member unique-pair buffers (caller order o).
 hipError_t launch_obs_gather(int nobs, int U, int m, const int *u_of_o, const void *f, double *Z,
-                             bool fp32, hipStream_t st);
+                             bool fp32, hipStream_t st, const double *rinv = nullptr);
 hipError_t launch_obs_scatter(int nobs, int U, int m, const int *u_optr, const int *u_olist,
-                              const double *Fo, void *f, bool fp32, hipStream_t st);
+                              const double *Fo, void *f, bool fp32, hipStream_t st,
+                              const double *rinv = nullptr);
 
 // Y = L X (mode 0), Y = L X + Z (mode 1), Y = Z - L X (mode 2); m columns.
 hipError_t launch_apply_L(int n, int w, const double *taps, int m, const double *X, double *Y,
@@ -311,6 +317,11 @@ hipError_t launch_scale_cols(int n, int k, const double *X, const double *s, dou
 
 // p[0..count) = 0 with a kernel (graph-capture safe, unlike a memset node).
 hipError_t launch_zero_ints(int *p, int count, hipStream_t st);
+// Spectral preconditioner middle factor and Y = a Y + b X.
+hipError_t launch_precond_scale(int mj, int m, const double *lam, double power, double *C,
+                                hipStream_t st);
+hipError_t launch_axpby(long long count, double a, double *Y, double b, const double *X,
+                        hipStream_t st);
 
 // Non-finite check over `count` doubles: flag[0] |= 1 when any value is NaN or Inf.
 hipError_t launch_check_finite(long long count, const double *x, int *flag, hipStream_t st);

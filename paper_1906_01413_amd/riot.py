@@ -28,7 +28,9 @@ MODES = {"adaptive": ADAPTIVE, "lra": LRA, "lru": LRU}
 
 EXPORTS = ("riot_workspace_bytes", "riot_init", "riot_free", "riot_status_str",
            "riot_linearize", "riot_linearize_deferred", "riot_join", "riot_hess_apply",
-           "riot_rsvd", "riot_increment", "riot_increment_select",
+           "riot_rsvd", "riot_increment", "riot_increment_select", "riot_psas_hess_apply",
+           "riot_psas_rhs", "riot_psas_increment", "riot_precond_apply", "riot_precond_hess_apply",
+           "riot_orth", "riot_project_out", "riot_outer_update",
            "riot_posterior_cov", "riot_cg", "riot_forecast", "riot_apply_L",
            "riot_philox_normal", "riot_tl_apply", "riot_ad_apply", "riot_gn_apply",
            "riot_batch_workspace_bytes", "riot_batch_init", "riot_batch_free", "riot_batch_buffers",
@@ -122,6 +124,14 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "riot_increment_select": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl),
                                         ctypes.POINTER(i32)]),
         "riot_posterior_cov": (i32, [vp, i32, vp, vp, i32, vp, vp, vp, vp, ctypes.POINTER(i32)]),
+        "riot_psas_hess_apply": (i32, [vp, i32, vp, vp]),
+        "riot_precond_apply": (i32, [vp, i32, vp, vp, vp, i32, i32, vp]),
+        "riot_precond_hess_apply": (i32, [vp, i32, vp, vp, vp, i32, vp, vp]),
+        "riot_orth": (i32, [vp, i32, vp, vp]),
+        "riot_project_out": (i32, [vp, i32, vp, i32, vp]),
+        "riot_outer_update": (i32, [vp, vp, vp, vp]),
+        "riot_psas_rhs": (i32, [vp, vp, vp, vp]),
+        "riot_psas_increment": (i32, [vp, i32, vp, vp, vp, i32, vp, vp, ctypes.POINTER(i32)]),
         "riot_cg": (i32, [vp, vp, i32, dbl, vp, vp, ctypes.POINTER(i32)]),
         "riot_forecast": (i32, [vp, vp, i32, vp]),
         "riot_apply_L": (i32, [vp, i32, vp, vp]),
@@ -382,6 +392,81 @@ class Riot:
                                               ctypes.byref(mu)), "riot_increment_select")
         self._pending = None
         return dz, dx, {LRA: "lra", LRU: "lru"}[mu.value], (Jh[0], Jh[1])
+
+    # -- spectral preconditioner and rotation (Alg. 3) ------------------------
+    @staticmethod
+    def _levels(levels):
+        nl = len(levels)
+        Vp = (ctypes.c_void_p * max(nl, 1))(*[ctypes.c_void_p(V.data_ptr()) for V, _ in levels])
+        lp = (ctypes.c_void_p * max(nl, 1))(*[ctypes.c_void_p(lam.data_ptr()) for _, lam in levels])
+        mj = (ctypes.c_int32 * max(nl, 1))(*[int(V.shape[1]) for V, _ in levels])
+        for V, lam in levels:
+            _ptr(V), _ptr(lam)  # layout checks
+        return nl, Vp, mj, lp
+
+    def precond_apply(self, levels, X, op):
+        """In place: op 'P', 'PT' or 'Pinv' of the preconditioner built from levels
+        [(V_j, lambda_j), ...] (device tensors)."""
+        X = self._block(X) if X.dim() == 1 else X
+        nl, Vp, mj, lp = self._levels(levels)
+        _check(self.lib.riot_precond_apply(self.h, nl, Vp, mj, lp, {"P": 0, "PT": 1, "Pinv": 2}[op],
+                                           X.shape[1], _ptr(X)), "riot_precond_apply")
+        return X
+
+    def precond_hess_apply(self, levels, W, out=None):
+        W = self._block(W)
+        Y = empty_colmajor(self.n, W.shape[1], self.device) if out is None else out
+        nl, Vp, mj, lp = self._levels(levels)
+        _check(self.lib.riot_precond_hess_apply(self.h, nl, Vp, mj, lp, W.shape[1], _ptr(W),
+                                                _ptr(Y)), "riot_precond_hess_apply")
+        return Y
+
+    def orth(self, X):
+        X = self._block(X)
+        Q = empty_colmajor(self.n, X.shape[1], self.device)
+        _check(self.lib.riot_orth(self.h, X.shape[1], _ptr(X), _ptr(Q)), "riot_orth")
+        return Q
+
+    def project_out(self, U, X):
+        """In place: X <- (I - U U^T) X."""
+        _check(self.lib.riot_project_out(self.h, U.shape[1], _ptr(U), X.shape[1], _ptr(X)),
+               "riot_project_out")
+        return X
+
+    def outer_update(self, dv, v, x):
+        """In place: v += dv, x += L dv."""
+        _check(self.lib.riot_outer_update(self.h, _ptr(dv), _ptr(v), _ptr(x)), "riot_outer_update")
+
+    # -- RIOT-PSAS (observation-space solve) ----------------------------------
+    def psas_hess_apply(self, W, out=None):
+        """Y = R^{-1/2} G B G^T R^{-1/2} W for observation-space probes W [nobs x m]."""
+        W = colmajor(W, self.device)
+        if W.dim() == 1:
+            W = W.reshape(-1, 1).t().contiguous().t()
+        Y = empty_colmajor(self.nobs, W.shape[1], self.device) if out is None else out
+        _check(self.lib.riot_psas_hess_apply(self.h, W.shape[1], _ptr(W), _ptr(Y)),
+               "riot_psas_hess_apply")
+        return Y
+
+    def psas_rhs(self, d, xb_minus_x=None):
+        """R^{-1/2} (d - G (x_b - x)) (xb_minus_x None: x = x_b)."""
+        rhs = torch.empty(self.nobs, dtype=torch.float64, device=self.device)
+        dd = colmajor(d, self.device)
+        xx = None if xb_minus_x is None else colmajor(xb_minus_x, self.device)
+        _check(self.lib.riot_psas_rhs(self.h, _ptr(dd), _ptr(xx), _ptr(rhs)), "riot_psas_rhs")
+        return rhs
+
+    def psas_increment(self, lam, U, rhs, k=None, mode="adaptive"):
+        """(dw, dx, mode): the dual increment and dx = B G^T dw (new state x_b + dx)."""
+        k = lam.numel() if k is None else int(k)
+        dw = torch.empty(self.nobs, dtype=torch.float64, device=self.device)
+        dx = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        mu = ctypes.c_int32(0)
+        _check(self.lib.riot_psas_increment(self.h, k, _ptr(lam), _ptr(U), _ptr(rhs), MODES[mode],
+                                            _ptr(dw), _ptr(dx), ctypes.byref(mu)),
+               "riot_psas_increment")
+        self._pending = None
+        return dw, dx, {LRA: "lra", LRU: "lru"}[mu.value]
 
     def posterior_cov(self, lam, V, k=None, mode="adaptive", diag=True, dense=False,
                       want_host=True, out=None):

@@ -223,3 +223,92 @@ def test_increment_select_two_nonlinear_runs():
     # full rank: both updates are the exact minimiser of the quadratic model
     _, _, _, Jaf, Juf = fourdvar.increment_select(p, lam, V, lin.g, v, k=p.n)
     assert abs(Jaf - Juf) <= 1e-10 * abs(Jaf)
+
+
+def test_psas_dual_matches_primal():
+    """RIOT-PSAS (Appendix): A_hat = R^{-1/2} G B G^T R^{-1/2} has the nonzero spectrum of the
+    primal A = L G^T R^{-1} G L (both are products of the same factor and its transpose); at
+    full rank the dual increment is the primal Gauss-Newton step (Woodbury), at the first
+    outer loop and at a later one (x != x_b, where the reading x_new = x_b + B G^T dw holds);
+    with fewer probes the dual sketch gives the primal exact answer only approximately."""
+    from oracle import bcov
+    w = workload("l96_n40", nsteps=12, var_stride=4, step_stride=4)
+    p, _ = fourdvar.realize_l96(w, l96_draws(w, 3))
+    assert p.nobs < p.n  # 10 variables x 3 steps = 30 observations, 40 controls
+    for v in (np.zeros(p.n), 0.1 * np.random.default_rng(8).standard_normal(p.n)):
+        x = p.xb + bcov.apply_L(v, p.taps)
+        lin = fourdvar.linearize(p, x, v)
+        A = fourdvar.dense_A(p, lin)
+        A = 0.5 * (A + A.T)
+        Ah = fourdvar.psas_hvp(p, lin, np.eye(p.nobs))
+        assert np.max(np.abs(Ah - Ah.T)) <= 1e-12 * np.max(np.abs(Ah))
+        lp = np.sort(np.linalg.eigvalsh(A))[::-1][:p.nobs]
+        ld = np.sort(np.linalg.eigvalsh(0.5 * (Ah + Ah.T)))[::-1]
+        assert np.allclose(lp, ld, rtol=1e-9, atol=1e-11 * lp[0])
+        # primal Gauss-Newton step: x + L dz*, dz* = -(I + A)^{-1} g
+        dz = -np.linalg.solve(np.eye(p.n) + A, lin.g)
+        x_primal = x + bcov.apply_L(dz, p.taps)
+        Om = probe_block(5, 0, p.nobs, p.nobs)
+        ro = fourdvar.rsvd(lambda X: fourdvar.psas_hvp(p, lin, X), Om, q=0)
+        rhs = fourdvar.psas_rhs(p, lin, x)
+        for mode in ("lra", "lru"):
+            _, dx, x_new, _ = fourdvar.psas_increment(p, lin, ro.lam, ro.V, rhs, x, mode=mode)
+            assert np.linalg.norm(x_new - x_primal) <= 1e-9 * np.linalg.norm(x_primal - x)
+        # truncated: approximate only
+        ro8 = fourdvar.rsvd(lambda X: fourdvar.psas_hvp(p, lin, X), Om[:, :8], q=0)
+        _, _, x8, _ = fourdvar.psas_increment(p, lin, ro8.lam, ro8.V, rhs, x)
+        e8 = np.linalg.norm(x8 - x_primal) / np.linalg.norm(x_primal - x)
+        assert 1e-6 < e8 < 1.0
+
+
+def _small():
+    w = workload("l96_n40", nsteps=16, step_stride=4)
+    p, _ = fourdvar.realize_l96(w, l96_draws(w, 5))
+    return w, p
+
+
+def test_spectral_preconditioner_and_rotation():
+    """Alg. 3's precond / rotation branches (eqs. 6-7): P^{-1} P = I; with the exact leading
+    eigenpairs of A as the first level, P^T (I + A) P has eigenvalue 1 on the resolved
+    directions and the rest of 1 + lambda unchanged; rotated probes mapped by P are orthogonal
+    to the resolved directions; at full rank the preconditioned step P dw is the
+    unpreconditioned exact step; three outer loops with precond (with and without rotation)
+    decrease J like the plain loops and approach the Gauss-Newton limit."""
+    w, p = _small()
+    lin = fourdvar.linearize(p, p.xb)
+    A = fourdvar.dense_A(p, lin)
+    A = 0.5 * (A + A.T)
+    lam, V = np.linalg.eigh(A)
+    lam, V = lam[::-1], V[:, ::-1]
+    m = 12
+    levels = [(V[:, :m], 1.0 + lam[:m])]
+    X = np.random.default_rng(1).standard_normal((p.n, 4))
+    assert np.allclose(fourdvar.precond_apply(levels, fourdvar.precond_apply(levels, X, "P"),
+                                              "Pinv"), X, atol=1e-12)
+    Pm = fourdvar.precond_apply(levels, np.eye(p.n), "P")
+    M = Pm.T @ (np.eye(p.n) + A) @ Pm
+    ev = np.sort(np.linalg.eigvalsh(0.5 * (M + M.T)))[::-1]
+    expect = np.sort(np.concatenate([np.ones(m), 1.0 + lam[m:]]))[::-1]
+    assert np.allclose(ev, expect, rtol=1e-9, atol=1e-9)
+    # the operator form agrees with the matrix form
+    Hw = fourdvar.precond_hvp(p, lin, levels, X)
+    assert np.allclose(Hw, (M - np.eye(p.n)) @ X, rtol=0, atol=1e-8 * np.abs(Hw).max())
+    # rotation: P omega_rot lies in the complement of span(resolved)
+    Om = probe_block(4, 0, p.n, 6)
+    resolved = [V[:, :m]]  # P_1 = I at the first loop
+    Omr = fourdvar.rotate_probes(levels, resolved, Om)
+    assert np.max(np.abs(V[:, :m].T @ fourdvar.precond_apply(levels, Omr, "P"))) < 1e-12
+    # full rank: P dw* = dz*
+    b = fourdvar.precond_apply(levels, lin.g, "PT")
+    dw = -np.linalg.solve(M, b)
+    dz = -np.linalg.solve(np.eye(p.n) + A, lin.g)
+    assert np.allclose(fourdvar.precond_apply(levels, dw, "P"), dz, rtol=0,
+                       atol=1e-9 * np.abs(dz).max())
+    # three outer loops
+    probes = [probe_block(30 + k, 0, p.n, 12) for k in range(3)]  # 2 x 12 resolved < n = 40
+    runs = {}
+    for key, pc, rot in (("plain", False, False), ("precond", True, False), ("rotation", True, True)):
+        hist, v, x, J = fourdvar.riot_outer_loops(p, probes, 3, pc, rot)
+        runs[key] = [h["J"] for h in hist] + [J]
+        assert runs[key][-1] < runs[key][0]
+    print("J per outer loop:", {k: [f"{j:.3f}" for j in r] for k, r in runs.items()})

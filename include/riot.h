@@ -272,6 +272,29 @@ riot_status riot_project_out(riot_handle *h, int32_t r, const double *U, int32_t
 riot_status riot_outer_update(riot_handle *h, const double *dv, double *v, double *x);
 
 /* ------------------------------------------------------------------------------------
+ * VarBL (Alg. 2): block Lanczos started from l realisations of the gradient.
+ * ---------------------------------------------------------------------------------- */
+/* One gradient realisation: x_j = x + L eps_b, v_j = v + eps_b (eps_b NULL: the unperturbed
+ * sample), observations y_j = y - R^{1/2} eps_o (eq. 3's sign of d), and
+ * grad = v_j - L G_j^T R^{-1} (y_j - H(M(x_j))) with G_j at x_j.
+ *   x [n], v [n] or NULL (v = 0), eps_b [n] or NULL, eps_o [nobs] device; grad [n] device out.
+ * The call integrates the window at x_j in the handle's trajectory storage, so the handle
+ * must be linearised again (riot_linearize at x) before the products (RIOT_E_STATE). */
+riot_status riot_gradient_sample(riot_handle *h, const double *x, const double *v,
+                                 const double *eps_b, const double *eps_o, double *grad);
+/* The block Lanczos inner loop of Alg. 2 on A at the current linearisation: Q_1 = orth(B),
+ * iters blocks of l Hessian-probe products (one batched launch each), block three-term
+ * recurrence with full reorthogonalisation, QR of each residual block (CholeskyQR), the
+ * (l iters) x (l iters) block tridiagonal T = Z diag(lambda) Z^T, U = Q Z, and the increment
+ * dz = -sum_i (1 + lambda_i)^{-1} u_i u_i^T g, dx = L dz (the LRA form Alg. 2 uses; g is the
+ * gradient of the current linearisation).
+ *   B [n x l] device: gradient samples; grad [n] device; l iters <= min(n, m_max)
+ *   lambda [l iters], U [n x l iters], dz [n], dx [n] device out. */
+riot_status riot_block_lanczos(riot_handle *h, int32_t l, int32_t iters, const double *B,
+                               const double *grad, double *lambda, double *U, double *dz,
+                               double *dx);
+
+/* ------------------------------------------------------------------------------------
  * RIOT-PSAS (Appendix algorithm): the randomized solve in observation space, for windows
  * with fewer observations than controls. A_hat = R^{-1/2} G B G^T R^{-1/2} (p x p, B = L L^T)
  * has the nonzero spectrum of A; the dual increment is

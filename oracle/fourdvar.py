@@ -548,3 +548,70 @@ def riot_outer_loops(p: Problem, probes: list, k_outer: int, precond: bool, rota
         v = v + dv
         x = x + bcov.apply_L(dv, p.taps)
     return hist, v, x, cost(p, v)
+
+
+# --------------------------------------------------------------------------
+# VarBL: block Lanczos started from perturbed gradients (Alg. 2)
+# --------------------------------------------------------------------------
+
+def gradient_sample(p: Problem, x: np.ndarray, v: np.ndarray, eps_b: np.ndarray | None,
+                    eps_o: np.ndarray) -> np.ndarray:
+    """One realisation of the gradient (Alg. 2's sampling loop): the state and control moved by
+    the background draw, x_j = x + L eps_b, v_j = v + eps_b (eps_b = None: the unperturbed
+    first sample), the observations by the observation draw, y_j = y - R^{1/2} eps_o (eq. 3's
+    sign of d; the algorithm writes d with the opposite sign and + L_R eps), and
+    b_j = v_j - L G_j^T R^{-1} (y_j - H(M(x_j))) with G_j the Jacobian at x_j."""
+    v = np.asarray(v, dtype=np.float64)
+    if eps_b is not None:
+        x = x + bcov.apply_L(eps_b, p.taps)
+        v = v + eps_b
+    pj = Problem(p.n, p.nsteps, p.h, p.F, p.obs_step, p.obs_idx,
+                 p.y - eps_o / np.sqrt(p.rinv), p.rinv, p.xb, p.taps)
+    return linearize(pj, x, v).g
+
+
+def block_lanczos(apply_A, Bg: np.ndarray, iters: int, g: np.ndarray):
+    """Alg. 2's inner loop: Q_1 = orth(gradient samples Bg, n x l); for i = 1 .. iters:
+    Y_i = A Q_i, M_i = Q_i^T Y_i, and (i < iters) R = Y_i - Q_i M_i - Q_{i-1} W_{i-1}^T,
+    orthogonalised against every earlier block (twice), Q_{i+1} W_i = R (QR). T is the block
+    tridiagonal matrix of the M_i and W_i, T = Z Lambda Z^T, U = Q Z, and the increment
+    dv = -sum (1 + l_i)^{-1} u_i u_i^T g (the LRA form the algorithm uses; reading: its b is
+    the gradient of the current linearisation, as in Alg. 1).
+    Returns (dv, lambda descending, U, Q, T)."""
+    n, l = Bg.shape
+    Q1 = orth(Bg)
+    blocks = [Q1]
+    Ms, Ws = [], []
+    for i in range(iters):
+        Qi = blocks[-1]
+        Y = apply_A(Qi)
+        M = Qi.T @ Y
+        Ms.append(M)
+        if i == iters - 1:
+            break
+        R = Y - Qi @ M
+        if i > 0:
+            R = R - blocks[-2] @ Ws[-1].T
+        Qall = np.hstack(blocks)
+        for _ in range(2):
+            R = R - Qall @ (Qall.T @ R)
+        Qn, W = np.linalg.qr(R)
+        s = np.sign(np.diag(W))
+        s[s == 0] = 1.0
+        Qn, W = Qn * s, s[:, None] * W
+        blocks.append(Qn)
+        Ws.append(W)
+    k = len(Ms)
+    T = np.zeros((k * l, k * l))
+    for i, M in enumerate(Ms):
+        T[i * l:(i + 1) * l, i * l:(i + 1) * l] = M
+    for i, W in enumerate(Ws):
+        T[(i + 1) * l:(i + 2) * l, i * l:(i + 1) * l] = W
+        T[i * l:(i + 1) * l, (i + 1) * l:(i + 2) * l] = W.T
+    T = 0.5 * (T + T.T)
+    lam, Z = np.linalg.eigh(T)
+    lam, Z = lam[::-1], Z[:, ::-1]
+    Q = np.hstack(blocks)
+    U = Q @ Z
+    dv = -(U @ ((U.T @ g) / (1.0 + lam)))
+    return dv, lam, U, Q, T

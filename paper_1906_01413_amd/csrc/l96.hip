@@ -983,6 +983,15 @@ __global__ void psas_rhs_kernel(int nobs, const double *__restrict__ rinv,
   out[o] = sqrt(rinv[o]) * (bp ? d[o] - bp[o] : d[o]);
 }
 
+// Perturbed observations of one gradient sample: out[o] = y[o] - eps[o] / sqrt(rinv[o]).
+__global__ void obs_perturb_kernel(int nobs, const double *__restrict__ y,
+                                   const double *__restrict__ rinv, const double *__restrict__ eps,
+                                   double *__restrict__ out) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nobs) return;
+  out[o] = y[o] - eps[o] / sqrt(rinv[o]);
+}
+
 __global__ void psas_scale_kernel(int nobs, const double *__restrict__ rinv,
                                   const double *__restrict__ t, double *__restrict__ dw) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1460,6 +1469,14 @@ hipError_t launch_psas_rhs(int nobs, const double *rinv, const double *d, const 
   if (nobs <= 0) return hipSuccess;
   hipLaunchKernelGGL(psas_rhs_kernel, dim3((nobs + 255) / 256), dim3(256), 0, st, nobs, rinv, d, bp,
                      out);
+  return hipGetLastError();
+}
+
+hipError_t launch_obs_perturb(int nobs, const double *y, const double *rinv, const double *eps,
+                              double *out, hipStream_t st) {
+  if (nobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(obs_perturb_kernel, dim3((nobs + 255) / 256), dim3(256), 0, st, nobs, y, rinv,
+                     eps, out);
   return hipGetLastError();
 }
 

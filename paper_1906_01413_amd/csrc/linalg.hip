@@ -1311,6 +1311,16 @@ __global__ void precond_scale_kernel(int mj, int m, const double *__restrict__ l
   C[e] *= pow(lt, power) - 1.0;
 }
 
+// Zero the entries of an m x m matrix (ld m) outside the block band |bi - bj| <= 1 of l x l
+// blocks (the never-written blocks of a block tridiagonal matrix).
+__global__ void block_band_zero_kernel(int m, int l, double *__restrict__ T) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)m * m) return;
+  const int i = (int)(e % m), j = (int)(e / m);
+  const int d = i / l - j / l;
+  if (d > 1 || d < -1) T[e] = 0.0;
+}
+
 // Y[e] = a Y[e] + b X[e]
 __global__ void axpby_kernel(long long count, double a, double *__restrict__ Y, double b,
                              const double *__restrict__ X) {
@@ -1326,6 +1336,14 @@ hipError_t launch_precond_scale(int mj, int m, const double *lam, double power, 
   if (tot <= 0) return hipSuccess;
   hipLaunchKernelGGL(precond_scale_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
                      mj, m, lam, power, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_band_zero(int m, int l, double *T, hipStream_t st) {
+  const long long tot = (long long)m * m;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(block_band_zero_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     m, l, T);
   return hipGetLastError();
 }
 

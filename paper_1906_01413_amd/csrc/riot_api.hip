@@ -866,6 +866,97 @@ riot_status riot_outer_update(riot_handle *h, const double *dv, double *v, doubl
 }
 
 // ---------------------------------------------------------------------------
+// VarBL (Alg. 2): perturbed gradient samples and the block Lanczos inner loop.
+// ---------------------------------------------------------------------------
+
+riot_status riot_gradient_sample(riot_handle *h, const double *x, const double *v,
+                                 const double *eps_b, const double *eps_o, double *grad) {
+  if (!h || !x || !grad || (h->d.nobs > 0 && !eps_o)) return RIOT_E_ARG;
+  if (grad == x || grad == v || grad == eps_b) return RIOT_E_ARG;
+  if (h->d.ckpt_stride > 0) return RIOT_E_STATE;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
+  const riot_desc &ds = h->d;
+  const int n = ds.n, no = ds.nobs;
+  hipStream_t st = h->st;
+  const double *xj = x, *vj = v;
+  if (eps_b) {
+    double *xb_ = h->sel, *vb_ = h->sel + n;
+    RIOT_HIP(launch_apply_L(n, h->w, h->taps, 1, eps_b, h->LW, nullptr, 0, st));
+    RIOT_HIP(hipMemcpyAsync(xb_, x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    RIOT_HIP(launch_axpby(n, 1.0, xb_, 1.0, h->LW, st));
+    RIOT_HIP(hipMemcpyAsync(vb_, eps_b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (v) RIOT_HIP(launch_axpby(n, 1.0, vb_, 1.0, v, st));
+    xj = xb_, vj = vb_;
+  }
+  // the handle's trajectory becomes the perturbed one: it must be linearised again
+  h->linearized = false;
+  RIOT_HIP(launch_trajectory(h->mv, ds.nsteps, xj, nullptr, h->xs64, h->xs32, st));
+  if (no > 0) {
+    RIOT_HIP(launch_obs_perturb(no, h->y, h->rinv, eps_o, h->pso, st));
+    RIOT_HIP(launch_innovation(h->mv, h->xs64, no, h->obs_step, h->obs_idx, h->pso, h->rinv,
+                               h->u_optr, h->u_olist, h->pso + no, h->fgrad, h->fp32, st));
+  }
+  RIOT_HIP(launch_tlad(h->mv, 1, 1, nullptr, h->LAM0, nullptr, h->fgrad, h->fp32, st));
+  RIOT_HIP(launch_apply_L(n, h->w, h->taps, 1, h->LAM0, grad, vj, 2, st));
+  return RIOT_OK;
+}
+
+riot_status riot_block_lanczos(riot_handle *h, int32_t l, int32_t iters, const double *B,
+                               const double *grad, double *lambda, double *U, double *dz,
+                               double *dx) {
+  if (!h || !B || !grad || !lambda || !U || !dz || !dx || l < 1 || iters < 1) return RIOT_E_ARG;
+  const int n = h->d.n, ml = l * iters;
+  if (ml > h->d.m_max || ml > n || dz == dx || dz == grad || dx == grad) return RIOT_E_ARG;
+  if (h->d.ckpt_stride > 0) return RIOT_E_STATE;
+  if (riot_status js = join_gradient(h); js != RIOT_OK) return js;
+  if (!h->linearized) return RIOT_E_STATE;
+  hipStream_t st = h->st;
+  LaSpace la = la_of(h);
+  RIOT_HIP(launch_zero_ints(la.flags, 16, st));
+  double *Q = h->Q, *Y = h->Y, *T = h->K;
+  auto blk = [&](int i, int j) { return T + (size_t)j * l * ml + (size_t)i * l; };
+  riot_status rs = cholqr(la, n, l, B, Q, true, 0);
+  if (rs != RIOT_OK) return rs;
+  for (int i = 0; i < iters; ++i) {
+    double *Qi = Q + (size_t)i * l * n;
+    rs = hess_apply_impl(h, l, Qi, Y, 0);
+    if (rs != RIOT_OK) return rs;
+    // M_i = Q_i^T Y_i
+    RIOT_HIP(gemm_f64(1, 0, l, l, n, 1.0, Qi, n, Y, n, 0.0, blk(i, i), ml, h->partial, kSplitK, st));
+    if (i == iters - 1) break;
+    // R = Y_i - Q_i M_i - Q_{i-1} W_{i-1}^T, orthogonalised against every block so far
+    RIOT_HIP(gemm_f64(0, 0, n, l, l, -1.0, Qi, n, blk(i, i), ml, 1.0, Y, n, nullptr, 1, st));
+    if (i > 0)
+      RIOT_HIP(gemm_f64(0, 0, n, l, l, -1.0, Qi - (size_t)l * n, n, blk(i - 1, i), ml, 1.0, Y, n,
+                        nullptr, 1, st));
+    const int done = (i + 1) * l;
+    for (int pass = 0; pass < 2; ++pass) {
+      RIOT_HIP(gemm_f64(1, 0, done, l, n, 1.0, Q, n, Y, n, 0.0, h->B2, done, h->partial, kSplitK,
+                        st));
+      RIOT_HIP(gemm_f64(0, 0, n, l, done, -1.0, Q, n, h->B2, done, 1.0, Y, n, nullptr, 1, st));
+    }
+    // Q_{i+1} W_i = R: orthonormal block by CholeskyQR, W_i = Q_{i+1}^T R (and its transpose)
+    double *Qn = Qi + (size_t)l * n;
+    rs = cholqr(la, n, l, Y, Qn, true, 0);
+    if (rs != RIOT_OK) return rs;
+    RIOT_HIP(gemm_f64(1, 0, l, l, n, 1.0, Qn, n, Y, n, 0.0, blk(i + 1, i), ml, h->partial, kSplitK,
+                      st));
+    RIOT_HIP(gemm_f64(1, 0, l, l, n, 1.0, Y, n, Qn, n, 0.0, blk(i, i + 1), ml, h->partial, kSplitK,
+                      st));
+  }
+  // blocks outside the band are zero
+  RIOT_HIP(launch_block_band_zero(ml, l, T, st));
+  RIOT_HIP(launch_symmetrize(ml, T, la.scal + 1, la.partial, st));
+  RIOT_HIP(launch_eig(ml, T, lambda, la.Zs, la.sywork, la.flags + 2, st));
+  RIOT_HIP(gemm_f64(0, 0, n, ml, ml, 1.0, Q, n, la.Zs, ml, 0.0, U, n, nullptr, 1, st));
+  // dz = -sum (1 + l_i)^{-1} u_i u_i^T g (LRA), dx = L dz
+  RIOT_HIP(gemm_f64(1, 0, ml, 1, n, 1.0, U, n, grad, n, 0.0, la.cvec, ml, la.partial, kSplitK, st));
+  RIOT_HIP(launch_increment_combine(n, ml, lambda, U, la.cvec, grad, 0, dz, la.scal + 4, st));
+  RIOT_HIP(launch_apply_L(n, h->w, h->taps, 1, dz, dx, nullptr, 0, st));
+  return RIOT_OK;
+}
+
+// ---------------------------------------------------------------------------
 // RIOT-PSAS (Appendix algorithm): the randomized solve in observation space.
 // ---------------------------------------------------------------------------
 

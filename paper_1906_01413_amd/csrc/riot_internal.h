@@ -160,6 +160,9 @@ hipError_t launch_psas_rhs(int nobs, const double *rinv, const double *d, const 
                            double *out, hipStream_t st);
 hipError_t launch_psas_scale(int nobs, const double *rinv, const double *t, double *dw,
                              hipStream_t st);
+// Perturbed observations y - R^{1/2} eps of a gradient sample.
+hipError_t launch_obs_perturb(int nobs, const double *y, const double *rinv, const double *eps,
+                              double *out, hipStream_t st);
 // Deterministic LRA/LRU choice (nonlinear window from several states, costs, selection).
 hipError_t launch_window_obs(const ModelView &mv, int nstates, const double *x0, double *xu,
                              hipStream_t st);
@@ -322,6 +325,7 @@ hipError_t launch_precond_scale(int mj, int m, const double *lam, double power, 
                                 hipStream_t st);
 hipError_t launch_axpby(long long count, double a, double *Y, double b, const double *X,
                         hipStream_t st);
+hipError_t launch_block_band_zero(int m, int l, double *T, hipStream_t st);
 
 // Non-finite check over `count` doubles: flag[0] |= 1 when any value is NaN or Inf.
 hipError_t launch_check_finite(long long count, const double *x, int *flag, hipStream_t st);

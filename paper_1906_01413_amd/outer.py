@@ -74,3 +74,17 @@ def riot_outer_loops(r, xb, probes, k_outer, precond=False, rotation=False, q=0,
 def _col(vec):
     """A contiguous [n] tensor seen as an n x 1 column-major block sharing its storage."""
     return vec.view(-1, 1)
+
+
+def varbl_inner(r, x, v, eps_b, eps_o, iters):
+    """One VarBL inner loop (Alg. 2): l gradient samples (the first unperturbed in the state,
+    eps_b[:, 0] unused), linearisation at x, block Lanczos with `iters` blocks. eps_b [n x l]
+    and eps_o [nobs x l] are device draws. Returns (lambda, U, dz, dx, g)."""
+    l = eps_o.shape[1]
+    B = torch.empty((l, r.n), dtype=torch.float64, device=r.device).t()
+    for j in range(l):
+        r.gradient_sample(x, v, None if j == 0 else eps_b[:, j].contiguous(),
+                          eps_o[:, j].contiguous(), out=B[:, j])
+    _, g, _ = r.linearize(x, v=v, want_cost=False)
+    lam, U, dz, dx = r.block_lanczos(B, g, iters)
+    return lam, U, dz, dx, g

@@ -30,7 +30,8 @@ EXPORTS = ("riot_workspace_bytes", "riot_init", "riot_free", "riot_status_str",
            "riot_linearize", "riot_linearize_deferred", "riot_join", "riot_hess_apply",
            "riot_rsvd", "riot_increment", "riot_increment_select", "riot_psas_hess_apply",
            "riot_psas_rhs", "riot_psas_increment", "riot_precond_apply", "riot_precond_hess_apply",
-           "riot_orth", "riot_project_out", "riot_outer_update",
+           "riot_orth", "riot_project_out", "riot_outer_update", "riot_gradient_sample",
+           "riot_block_lanczos",
            "riot_posterior_cov", "riot_cg", "riot_forecast", "riot_apply_L",
            "riot_philox_normal", "riot_tl_apply", "riot_ad_apply", "riot_gn_apply",
            "riot_batch_workspace_bytes", "riot_batch_init", "riot_batch_free", "riot_batch_buffers",
@@ -128,6 +129,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "riot_precond_apply": (i32, [vp, i32, vp, vp, vp, i32, i32, vp]),
         "riot_precond_hess_apply": (i32, [vp, i32, vp, vp, vp, i32, vp, vp]),
         "riot_orth": (i32, [vp, i32, vp, vp]),
+        "riot_gradient_sample": (i32, [vp, vp, vp, vp, vp, vp]),
+        "riot_block_lanczos": (i32, [vp, i32, i32, vp, vp, vp, vp, vp, vp]),
         "riot_project_out": (i32, [vp, i32, vp, i32, vp]),
         "riot_outer_update": (i32, [vp, vp, vp, vp]),
         "riot_psas_rhs": (i32, [vp, vp, vp, vp]),
@@ -436,6 +439,32 @@ class Riot:
     def outer_update(self, dv, v, x):
         """In place: v += dv, x += L dv."""
         _check(self.lib.riot_outer_update(self.h, _ptr(dv), _ptr(v), _ptr(x)), "riot_outer_update")
+
+    # -- VarBL (Alg. 2) ---------------------------------------------------------
+    def gradient_sample(self, x, v, eps_b, eps_o, out=None):
+        """Gradient at x + L eps_b, v + eps_b with observations y - R^{1/2} eps_o (eps_b None:
+        unperturbed state). Leaves the handle to be linearised again."""
+        g = torch.empty(self.n, dtype=torch.float64, device=self.device) if out is None else out
+        xx = colmajor(x, self.device)
+        vv = None if v is None else colmajor(v, self.device)
+        eb = None if eps_b is None else colmajor(eps_b, self.device)
+        eo = colmajor(eps_o, self.device)
+        _check(self.lib.riot_gradient_sample(self.h, _ptr(xx), _ptr(vv), _ptr(eb), _ptr(eo), _ptr(g)),
+               "riot_gradient_sample")
+        return g
+
+    def block_lanczos(self, B, g, iters):
+        """(lambda, U, dz, dx) of Alg. 2's inner loop from gradient samples B [n x l]."""
+        B = self._block(B)
+        l = B.shape[1]
+        lam = torch.empty(l * iters, dtype=torch.float64, device=self.device)
+        U = empty_colmajor(self.n, l * iters, self.device)
+        dz = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        dx = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(self.lib.riot_block_lanczos(self.h, l, int(iters), _ptr(B), _ptr(g), _ptr(lam), _ptr(U),
+                                           _ptr(dz), _ptr(dx)), "riot_block_lanczos")
+        self._pending = None
+        return lam, U, dz, dx
 
     # -- RIOT-PSAS (observation-space solve) ----------------------------------
     def psas_hess_apply(self, W, out=None):

@@ -312,3 +312,45 @@ def test_spectral_preconditioner_and_rotation():
         runs[key] = [h["J"] for h in hist] + [J]
         assert runs[key][-1] < runs[key][0]
     print("J per outer loop:", {k: [f"{j:.3f}" for j in r] for k, r in runs.items()})
+
+
+def test_block_lanczos_varbl():
+    """VarBL (Alg. 2): with one gradient (l = 1) it is Alg. 1's Lanczos; T is Q^T A Q; the
+    increment is the Galerkin solution -Q (Q^T (I + A) Q)^{-1} Q^T g on the block Krylov space;
+    with a full space it is exact; the gradient samples are linearisations at the moved state
+    with moved observations (zero draws: the gradient itself)."""
+    from oracle import bcov
+    w, p = _small()
+    v = 0.05 * np.random.default_rng(2).standard_normal(p.n)
+    x = p.xb + bcov.apply_L(v, p.taps)
+    lin = fourdvar.linearize(p, x, v)
+    A = fourdvar.dense_A(p, lin)
+    A = 0.5 * (A + A.T)
+    ap = lambda X: A @ X  # noqa: E731
+    # l = 1 against Alg. 1
+    dv1, lam1, _, _, _ = fourdvar.block_lanczos(ap, lin.g[:, None], 8, lin.g)
+    dzl, laml, _ = fourdvar.lanczos_varcg(ap, lin.g, 8)
+    assert np.allclose(lam1, laml, rtol=1e-10, atol=1e-10 * laml[0])
+    assert np.linalg.norm(dv1 - dzl) <= 1e-9 * np.linalg.norm(dzl)
+    # gradient samples
+    rng = np.random.default_rng(6)
+    l = 4
+    eb = rng.standard_normal((p.n, l))
+    eo = rng.standard_normal((p.nobs, l))
+    assert np.allclose(fourdvar.gradient_sample(p, x, v, None, np.zeros(p.nobs)), lin.g, atol=1e-13)
+    Bg = np.stack([fourdvar.gradient_sample(p, x, v, None if j == 0 else eb[:, j], eo[:, j])
+                   for j in range(l)], axis=1)
+    pj = fourdvar.Problem(p.n, p.nsteps, p.h, p.F, p.obs_step, p.obs_idx,
+                          p.y - eo[:, 2] / np.sqrt(p.rinv), p.rinv, p.xb, p.taps)
+    g2 = fourdvar.linearize(pj, x + bcov.apply_L(eb[:, 2], p.taps), v + eb[:, 2]).g
+    assert np.array_equal(Bg[:, 2], g2)
+    # block Krylov space: T = Q^T A Q, Galerkin increment
+    dv, lam, U, Q, T = fourdvar.block_lanczos(ap, Bg, 5, lin.g)
+    assert np.max(np.abs(Q.T @ Q - np.eye(Q.shape[1]))) < 1e-12
+    assert np.max(np.abs(Q.T @ A @ Q - T)) <= 1e-10 * np.max(np.abs(T))
+    gal = -Q @ np.linalg.solve(Q.T @ (Q + A @ Q), Q.T @ lin.g)
+    assert np.linalg.norm(dv - gal) <= 1e-10 * np.linalg.norm(gal)
+    # full space (10 x 4 = n): exact
+    dvf, _, _, _, _ = fourdvar.block_lanczos(ap, Bg, 10, lin.g)
+    dz = -np.linalg.solve(np.eye(p.n) + A, lin.g)
+    assert np.linalg.norm(dvf - dz) <= 1e-8 * np.linalg.norm(dz)

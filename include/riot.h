@@ -96,6 +96,10 @@ typedef struct {
     int32_t qr_passes;         /* CholeskyQR passes applied to the final block Y */
     double k_asym;             /* ||K - K^T||_F / ||K||_F before symmetrisation */
     double orth_err;           /* ||Q^T Q - I||_F after the last pass */
+    double kappa_est;          /* (1 + lambda_1) / (1 + max(lambda_m, 0)): condition of I + A on
+                                  the sketch's subspace (what an FP64 solve there loses) */
+    double resid_est;          /* ||K (Q^T Omega) - Q^T Y||_F / ||Q^T Y||_F with the symmetrised K:
+                                  how far the symmetric K is from solving Alg. 3's equation */
 } riot_rsvd_info;
 
 /* Bytes of device workspace needed for this problem (0 if the descriptor is invalid). */
@@ -522,8 +526,8 @@ riot_status riot_batch_replay(riot_batch *b);
 /* One timed probe-product launch of the batch (current probes) with per-tile device
  * clocks: ms = its duration (HIP events), busy_frac = the slots' busy time over the
  * slots available for the whole launch (load balance), tiles = number of tiles. Host
- * pointers may be NULL. Synchronises; allocates a small timing buffer (not for use under
- * graph capture). */
+ * pointers may be NULL. Synchronises (not for use under graph capture); the clocks go to a
+ * region of the batch's workspace. */
 riot_status riot_batch_profile(riot_batch *b, float *ms, double *busy_frac, int32_t *tiles);
 
 /* The handle of problem j inside the batch (owned by the batch: do not riot_free it). Its

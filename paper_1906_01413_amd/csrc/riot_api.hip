@@ -348,15 +348,25 @@ riot_status sketch_eig(const LaSpace &la, int n, int m, const double *Y, const d
   if (info) {
     RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, la.Q, n, la.Q, n, 0.0, la.G, m, la.partial, kSplitK, st));
     RIOT_HIP(launch_orth_err(m, la.G, la.scal + 2, st));
+    // residual of the defining equation with the symmetrised K: ||K B2 - B1|| / ||B1||
+    // (B1 = Q^T Y formed again: the solve above overwrote it; B2 and K are intact)
+    RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, la.Q, n, Y, n, 0.0, la.R, m, la.partial, kSplitK, st));
+    RIOT_HIP(gemm_f64(0, 0, m, m, m, 1.0, la.K, m, la.B2, m, 0.0, la.G, m, nullptr, 1, st));
+    RIOT_HIP(launch_axpby((long long)m * m, 1.0, la.G, -1.0, la.R, st));
+    RIOT_HIP(launch_fro_ratio((long long)m * m, la.G, la.R, la.scal + 7, st));
     int fl[6];
-    double sc[3];
+    double sc[8], lend[2];
     RIOT_HIP(hipMemcpyAsync(fl, la.flags, 6 * sizeof(int), hipMemcpyDeviceToHost, st));
-    RIOT_HIP(hipMemcpyAsync(sc, la.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    RIOT_HIP(hipMemcpyAsync(sc, la.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+    RIOT_HIP(hipMemcpyAsync(&lend[0], lambda, sizeof(double), hipMemcpyDeviceToHost, st));
+    RIOT_HIP(hipMemcpyAsync(&lend[1], lambda + (m - 1), sizeof(double), hipMemcpyDeviceToHost, st));
     RIOT_HIP(hipStreamSynchronize(st));
     info->chol_shifts = fl[4];
     info->qr_passes = fl[5];
     info->k_asym = sc[1];
     info->orth_err = sc[2];
+    info->kappa_est = (1.0 + lend[0]) / (1.0 + std::max(lend[1], 0.0));
+    info->resid_est = sc[7];
     if (fl[0]) return RIOT_E_NOT_SPD;
     if (fl[1]) return RIOT_E_SINGULAR;
     if (fl[2]) return RIOT_E_NOCONV;
@@ -1189,6 +1199,7 @@ struct riot_batch {
   riot::TladTile *tiles = nullptr;  // [grad wg | grad wave | hvp wg | hvp wave]
   int n_grad_wg = 0, n_grad_wave = 0, n_hvp_wg = 0, n_hvp_wave = 0, tile_cap = 0;
   int *counters = nullptr;
+  long long *clk = nullptr;  // per-tile start/end clocks of riot_batch_profile (2 per tile)
   riot::ApplyLJobE *aL_grad = nullptr, *aL_in = nullptr, *aL_out = nullptr, *aL_dx = nullptr;
   riot::PhiloxJob *philox = nullptr;
   riot::CopyJob *cp_Y = nullptr, *cp_B2 = nullptr;
@@ -1257,6 +1268,7 @@ size_t batch_carve(riot_batch &b, void *base, size_t tiles_cap) {
   b.hvp_probs = c.take<riot::TladProb>(P);
   b.tiles = c.take<riot::TladTile>(tiles_cap);
   b.counters = c.take<int>(4);
+  b.clk = c.take<long long>(2 * tiles_cap);
   b.aL_grad = c.take<riot::ApplyLJobE>(P);
   b.aL_in = c.take<riot::ApplyLJobE>(P);
   b.aL_out = c.take<riot::ApplyLJobE>(P);
@@ -1683,8 +1695,7 @@ riot_status riot_batch_profile(riot_batch *b, float *ms, double *busy_frac, int3
   if (b->graph) return RIOT_E_STATE;
   const int nt = b->n_hvp_wg + b->n_hvp_wave;
   if (nt == 0) return RIOT_E_STATE;
-  long long *clk = nullptr;
-  if (hipMalloc(&clk, (size_t)2 * nt * sizeof(long long)) != hipSuccess) return RIOT_E_HIP;
+  long long *clk = b->clk;  // carved from the batch's workspace (2 clocks per tile)
   hipEvent_t e0, e1;
   riot_status rs = RIOT_OK;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rs = RIOT_E_HIP;
@@ -1700,7 +1711,6 @@ riot_status riot_batch_profile(riot_batch *b, float *ms, double *busy_frac, int3
   if (rs == RIOT_OK && hipEventElapsedTime(&el, e0, e1) != hipSuccess) rs = RIOT_E_HIP;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  (void)hipFree(clk);
   if (rs != RIOT_OK) return rs;
   // busy time of every slot (a workgroup tile occupies four waves, a wave tile one) over
   // the slots available (four waves per workgroup that can be resident) times the makespan

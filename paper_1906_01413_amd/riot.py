@@ -93,7 +93,8 @@ class _NetDesc(ctypes.Structure):
 
 class _RsvdInfo(ctypes.Structure):
     _fields_ = [("chol_shifts", ctypes.c_int32), ("qr_passes", ctypes.c_int32),
-                ("k_asym", ctypes.c_double), ("orth_err", ctypes.c_double)]
+                ("k_asym", ctypes.c_double), ("orth_err", ctypes.c_double),
+                ("kappa_est", ctypes.c_double), ("resid_est", ctypes.c_double)]
 
 
 _lib = None
@@ -242,6 +243,8 @@ class RsvdInfo:
     qr_passes: int
     k_asym: float
     orth_err: float
+    kappa_est: float = float("nan")
+    resid_est: float = float("nan")
 
 
 class Riot:
@@ -363,7 +366,8 @@ class Riot:
         info = _RsvdInfo()
         _check(self.lib.riot_rsvd(self.h, k, p_os, q, _ptr(Om), ctypes.c_uint64(seed), _ptr(lam),
                                   _ptr(V), ctypes.byref(info) if want_info else None), "riot_rsvd")
-        inf = RsvdInfo(info.chol_shifts, info.qr_passes, info.k_asym, info.orth_err) if want_info else None
+        inf = RsvdInfo(info.chol_shifts, info.qr_passes, info.k_asym, info.orth_err, info.kappa_est,
+                         info.resid_est) if want_info else None
         return lam, V, inf
 
     def increment(self, lam, V, g, k=None, mode="adaptive", want_host=True, dz=None, dx=None):
@@ -791,7 +795,8 @@ class Sketch:
         info = _RsvdInfo()
         _check(self.lib.riot_sketch_eig(self.h, m, _ptr(Om), _ptr(Yc), _ptr(lam), _ptr(V),
                                         ctypes.byref(info) if want_info else None), "riot_sketch_eig")
-        return lam, V, (RsvdInfo(info.chol_shifts, info.qr_passes, info.k_asym, info.orth_err)
+        return lam, V, (RsvdInfo(info.chol_shifts, info.qr_passes, info.k_asym, info.orth_err, info.kappa_est,
+                         info.resid_est)
                         if want_info else None)
 
     def increment(self, lam, V, g, k=None, mode="adaptive"):
@@ -830,7 +835,8 @@ def sketch_eig_noalloc(Omega, Y, want_info=True, lam=None, V=None):
                                        ctypes.c_void_p(stream.cuda_stream),
                                        ctypes.byref(info) if want_info else None),
            "riot_sketch_eig_noalloc")
-    return lam, V, (RsvdInfo(info.chol_shifts, info.qr_passes, info.k_asym, info.orth_err)
+    return lam, V, (RsvdInfo(info.chol_shifts, info.qr_passes, info.k_asym, info.orth_err, info.kappa_est,
+                         info.resid_est)
                     if want_info else None)
 
 

@@ -100,6 +100,15 @@ def test_rsvd_matches_oracle(c1, g1):
     assert rel((V * lam) @ V.T, (ro.V * ro.lam) @ ro.V.T) < 1e-10
     assert info.orth_err < 1e-12
     assert np.max(np.abs(V.T @ V - np.eye(w.m))) < 1e-12
+    # diagnostics: condition of I + A on the sketch, residual of K Q^T Omega = Q^T Y
+    kap = (1.0 + ro.lam[0]) / (1.0 + max(ro.lam[-1], 0.0))
+    assert abs(info.kappa_est - kap) <= 1e-9 * kap
+    Qo = ro.Q
+    Om_eff = fourdvar.orth(fourdvar.hvp(p, lin, Om)) if w.q == 1 else Om
+    res_o = np.linalg.norm(ro.K @ (Qo.T @ Om_eff) - Qo.T @ ro.Y) / np.linalg.norm(Qo.T @ ro.Y)
+    print(f"rsvd info: kappa_est {info.kappa_est:.3e}, resid_est {info.resid_est:.2e} "
+          f"(oracle {res_o:.2e}), k_asym {info.k_asym:.1e}")
+    assert np.isfinite(info.resid_est) and info.resid_est < max(100 * res_o, 1e-10)
     # increments (adaptive) agree; the oracle's own sensitivity is measured against
     # an exact-arithmetic-equivalent variant (eigh on the unsymmetrised solve)
     dzg, dxg, dofs, mode = r.increment(torch.tensor(lam, device="cuda"),

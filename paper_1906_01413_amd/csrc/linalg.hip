@@ -108,20 +108,40 @@ __global__ void __launch_bounds__(64)
       }
 }
 
-__global__ void splitk_reduce_kernel(int M, int N, int splits, const double *__restrict__ partial,
-                                     double alpha, double beta, double *__restrict__ C, int ldc,
-                                     const int *__restrict__ run, int lower) {
+__global__ void __launch_bounds__(256)
+    splitk_reduce_kernel(int M, int N, int splits, const double *__restrict__ partial,
+                         double alpha, double beta, double *__restrict__ C, int ldc,
+                         const int *__restrict__ run, int lower, double *__restrict__ gram_sq) {
   if (run && run[0] == 0) return;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t MN = (size_t)M * N;
-  if (idx >= MN) return;
-  const int row = (int)(idx % M), col = (int)(idx / M);
-  if (lower && row < col) return;  // not computed for a lower-triangle result
-  double s = 0.0;
-  for (int z = 0; z < splits; ++z) s += partial[(size_t)z * MN + idx];
-  double out = alpha * s;
-  if (beta != 0.0) out += beta * C[(size_t)col * ldc + row];
-  C[(size_t)col * ldc + row] = out;
+  double sq = 0.0;
+  if (idx < MN) {
+    const int row = (int)(idx % M), col = (int)(idx / M);
+    if (lower && row < col) {
+      // not computed for a lower-triangle result; zeroed when the result is a Cholesky input
+      if (gram_sq) C[(size_t)col * ldc + row] = 0.0;
+    } else {
+      double s = 0.0;
+      for (int z = 0; z < splits; ++z) s += partial[(size_t)z * MN + idx];
+      double out = alpha * s;
+      if (beta != 0.0) out += beta * C[(size_t)col * ldc + row];
+      C[(size_t)col * ldc + row] = out;
+      sq = (row > col ? 2.0 : 1.0) * out * out;  // strict lower counts for both triangles
+    }
+  }
+  if (gram_sq) {
+    // this block's share of ||C||_F^2, summed in a fixed order
+    __shared__ double red[4];
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_down(sq, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+      gram_sq[blockIdx.x] = t;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -207,6 +227,141 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
   return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
 }
 
+// LDS of the diagonal-block factorization (one wave).
+struct BlockLds {
+  double D[kPB][kPB + 1];   // in: the block's lower triangle; out: L11 (upper part zero)
+  double Di[kPB][kPB + 1];  // out: Di[c][t] = (L11^{-1})[t][c], zero outside nb x nb
+  __align__(16) double colk[2][16];  // column k of L11 by row parity: colk[i & 1][i >> 1]
+  __align__(16) double yrow[2][16];  // row k of the unscaled inverse by column parity
+};
+
+// Cholesky of the SPD block held in S.D (rows and columns >= nb are ignored) and the inverse
+// of its factor, by one wave, straight-line code without branches. fpiv > 0: a pivot not
+// above fpiv is replaced by it (modified Cholesky). Returns through the references: fail
+// (non-finite or non-positive pivot), modified (a pivot was replaced), use_inv (1-norm
+// condition |L11|_1 |L11^{-1}|_1 <= kCholInvCond). Uniform across the wave.
+//
+// Lane (i, h) = (lane & 31, lane >> 5) keeps the block's row i at the columns j = 2 jj + h
+// (jj < 16) in r[jj]: interleaving the columns over the two halves keeps both busy while
+// the active part shrinks, and with the pivot index known at compile time the finished
+// columns take no instructions. Rows and columns from nb on hold the identity, which
+// factors to itself without touching the rest, so every pivot runs the same code. Pivot k:
+// its value comes from the owning lane's register (v_readlane), the owning half publishes
+// column k scaled (L11[i][k], i > k) and every lane reads back its row's entry and the
+// entries of its columns (broadcast LDS reads), then updates its live columns.
+// The inverse is built alongside as Y with X = L11^{-1} = diag(1 / L11[k][k]) Y: pivot k
+// takes (L11[i][k] / L11[k][k]) Y[k, :] from every row i > k, where Y[k, :] is final and
+// nonzero only in columns <= k; rows are scaled once at the end.
+// A separate function (not inlined into the Cholesky kernel, whose other live values would
+// push it into spills) taking the LDS block by an address-space-3 reference, so that the
+// accesses stay plain ds_read/ds_write with immediate offsets.
+using LdsBlock = __attribute__((address_space(3))) BlockLds;
+using lds_double = __attribute__((address_space(3))) double;
+__device__ __attribute__((noinline)) void factor_block32(LdsBlock &S, int nb, double fpiv,
+                                                         bool &fail_out, bool &mod_out,
+                                                         bool &use_inv_out) {
+  const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
+  double r[16], y[16];
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj) {
+    const int j = 2 * jj + h;
+    const bool real = i < nb && j < nb;
+    r[jj] = real ? (j <= i ? S.D[i][j] : 0.0) : (i == j ? 1.0 : 0.0);
+    y[jj] = (i == j) ? 1.0 : 0.0;
+  }
+  bool fail = false, modified = false;
+  double myrinv = 1.0;  // 1 / L11[i][i]
+  lds_double *const mycol = &S.colk[i & 1][i >> 1];
+  // this half's entries of the published column and row, read as pairs (ds_read_b128)
+  const lds_double *const colh = &S.colk[h][0];  // this half's entries, read in pairs
+  const lds_double *const yrh = &S.yrow[h][0];
+#pragma unroll
+  for (int k = 0; k < kPB; ++k) {
+    const int kh = k & 1, kk = k >> 1;  // column k is r[kk] of half kh
+    const bool realk = k < nb;
+    double piv = readlane_d(r[kk], k + 32 * kh);
+    fail |= realk && !isfinite(piv);
+    const bool repl = realk && fpiv > 0.0 && !(piv > fpiv);
+    modified |= repl;
+    piv = repl ? fpiv : piv;
+    fail |= !(piv > 0.0);
+    const double rinv = rsqrt(piv);
+    myrinv = (i == k) ? rinv : myrinv;
+    // the owning half publishes column k below the diagonal (zero at and above it) and
+    // writes L11[i][k], i >= k, to D (rows from nb on are zero or the identity's and are
+    // never read back)
+    const double lown = r[kk] * rinv;
+    if (h == kh) {
+      *mycol = (i > k) ? lown : 0.0;
+      if (i >= k) S.D[i][k] = (i == k) ? piv * rinv : lown;
+    }
+    // lanes (k, 0) and (k, 1) publish row k of Y (columns <= k; the pairs' second entry
+    // beyond k is zero)
+    if (i == k) {
+      lds_double *const ydst = &S.yrow[h][0];
+#pragma unroll
+      for (int q = 0; q <= kk / 2; ++q) {
+        ydst[2 * q] = y[2 * q];
+        ydst[2 * q + 1] = y[2 * q + 1];
+      }
+    }
+    // a wave's LDS operations complete in order: the reads below see these writes
+    __builtin_amdgcn_wave_barrier();
+    const double lik = *mycol;  // L11[i][k] for i > k, else 0
+    const int jlo = k >> 1;     // columns 2 jj + h > k have jj >= jlo
+    double lj[16], yk[16];
+#pragma unroll
+    for (int q = jlo / 2; q < 8; ++q) {
+      lj[2 * q] = colh[2 * q];
+      lj[2 * q + 1] = colh[2 * q + 1];
+    }
+#pragma unroll
+    for (int q = 0; q <= kk / 2; ++q) {
+      yk[2 * q] = yrh[2 * q];
+      yk[2 * q + 1] = yrh[2 * q + 1];
+    }
+#pragma unroll
+    for (int jj = jlo; jj < 16; ++jj) r[jj] = fma(-lik, lj[jj], r[jj]);
+    const double t = lik * rinv;  // L11[i][k] / L11[k][k], zero for i <= k
+#pragma unroll
+    for (int jj = 0; jj <= kk; ++jj) y[jj] = fma(-t, yk[jj], y[jj]);
+    // the updates happen here: without this the compiler defers the FMAs of columns needed
+    // only at later pivots and keeps all their operands live (register spills)
+#pragma unroll
+    for (int jj = jlo; jj < 16; ++jj) asm volatile("" : "+v"(r[jj]));
+#pragma unroll
+    for (int jj = 0; jj <= kk; ++jj) asm volatile("" : "+v"(y[jj]));
+  }
+  // X = diag(1 / L11[i][i]) Y into Di (transposed), zero outside the nb x nb block
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj) {
+    const int c = 2 * jj + h;
+    S.Di[c][i] = (i < nb && c < nb) ? y[jj] * myrinv : 0.0;
+  }
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+  // kappa = |L11|_1 |L11^{-1}|_1: lane c sums column c of the factor (D[t][c]) and of its
+  // inverse (Di[c][t]); the loads are issued together
+  double cl = 0.0, ci = 0.0;
+  {
+    const int c = i;
+#pragma unroll
+    for (int t = 0; t < kPB; ++t) {
+      const double dv = S.D[t][c];
+      const double xv = S.Di[c][t];
+      const bool in = t >= c && t < nb && c < nb;
+      cl += in ? fabs(dv) : 0.0;
+      ci += in ? fabs(xv) : 0.0;
+    }
+  }
+  cl = wave_max_nonneg(cl);
+  ci = wave_max_nonneg(ci);
+  // fail and modified are uniform: every lane took the same pivots
+  fail_out = fail;
+  mod_out = modified;
+  use_inv_out = !fail && (cl * ci <= kCholInvCond);
+}
+
 // ---------------------------------------------------------------------------
 // Blocked Cholesky G + s I = L L^T (lower, column-major), one workgroup.
 // mode 0: s = 0; mode 1: s = shift_rel ||G||_F; mode 2: s = 0, and a pivot that is not
@@ -219,32 +374,40 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kCholThreads)
-    chol_blocked_kernel(int m, const double *__restrict__ G, double *__restrict__ L,
+    chol_blocked_kernel(int m, const double *G, double *L,
                         double shift_rel, int mode, int *__restrict__ flag,
                         int *__restrict__ shifts, const int *__restrict__ run,
-                        int *__restrict__ modflag, const CholJob *__restrict__ jobs) {
+                        int *__restrict__ modflag, const double *__restrict__ gram_sq,
+                        const CholJob *__restrict__ jobs) {
   if (jobs) {  // batched: blockIdx.y selects the problem
     const CholJob &J = jobs[blockIdx.y];
     m = J.m, G = J.G, L = J.L, shift_rel = J.shift_rel, flag = J.flag, shifts = J.shifts;
     run = J.run, modflag = J.modflag;
+    gram_sq = nullptr;
   }
   if (run && run[0] == 0) return;
-  __shared__ double D[kPB][kPB + 1];
-  __shared__ double Di[kPB][kPB + 1];  // Di[k][j] = (L11^{-1})[j][k]
-  __shared__ double rdg[kPB];          // 1 / L11[k][k]
+  __shared__ BlockLds S;  // the diagonal block, its factor and inverse
   __shared__ double Pn[kPB * (kStageRows + 1)];
   __shared__ double red[16];
   __shared__ int bad, use_inv;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int wave = tid >> 6, nwaves = nt >> 6;
+  // gram_sq given: the Gram GEMM wrote G into L (zero upper triangle) and the partial sums
+  // of ||G||_F^2; the factorization runs in place
+  const bool inplace = gram_sq != nullptr;
   double fro = 0.0;
   if (mode != 0) {
     double part = 0.0;
-    // from the lower triangle (the upper one need not be formed): diagonal + 2 x strict lower
-    for (size_t idx = tid; idx < (size_t)m * m; idx += nt) {
-      const int i = (int)(idx % m), j = (int)(idx / m);
-      const double w = (i > j) ? 2.0 : ((i == j) ? 1.0 : 0.0);
-      part += w * G[idx] * G[idx];
+    if (inplace) {
+      const int nsq = (int)(((size_t)m * m + 255) / 256);
+      for (int q = tid; q < nsq; q += nt) part += gram_sq[q];
+    } else {
+      // from the lower triangle (the upper one need not be formed): diagonal + 2 x strict lower
+      for (size_t idx = tid; idx < (size_t)m * m; idx += nt) {
+        const int i = (int)(idx % m), j = (int)(idx / m);
+        const double w = (i > j) ? 2.0 : ((i == j) ? 1.0 : 0.0);
+        part += w * G[idx] * G[idx];
+      }
     }
     fro = sqrt(wg_sum(part, red));
   }
@@ -258,7 +421,10 @@ __global__ void __launch_bounds__(kCholThreads)
     const bool shifted = (mode == 1);
     const double s = shifted ? shift_rel * fro : 0.0;
     if (shifted && tid == 0 && shifts) shifts[0] += 1;
-    {
+    if (inplace) {
+      if (s != 0.0)
+        for (int i = tid; i < m; i += nt) L[(size_t)i * m + i] += s;
+    } else {
       // (i, j) of idx advanced by nt each iteration without a division per element
       const int step_i = nt % m, step_j = nt / m;
       int i = tid % m, j = tid / m;
@@ -272,98 +438,23 @@ __global__ void __launch_bounds__(kCholThreads)
     }
     if (tid == 0) bad = 0;
     __syncthreads();
-    // Factor the diagonal block held in D (lower part, nb x nb) by wave 0 alone: L11 in D,
-    // its inverse in Di, the pivots' reciprocals in rdg, use_inv from the block's condition;
-    // bad = 1 on breakdown. No workgroup barrier inside.
-    auto factor_block = [&](int nb) {
-      // lane i keeps row i of the diagonal block in registers; the pivot and column k
-      // are broadcast from the owning lanes' registers (v_readlane), not through LDS
-      const int lane = tid & 63;
-      // captured by reference: read once, not through the capture in every step
-      const double fpiv = floor_piv;
-      double r[kPB];
-#pragma unroll
-      for (int j = 0; j < kPB; ++j) r[j] = (lane < nb && j <= lane) ? D[lane][j] : 0.0;
-      bool fail = false;
-      double myinv = 0.0;  // lane i: 1 / L11[i][i]
-#pragma unroll
-      for (int k = 0; k < kPB; ++k) {
-        if (k < nb && !fail) {
-          double piv = readlane_d(r[k], k);  // uniform: every lane sees the same pivot
-          if (!isfinite(piv)) fail = true;
-          if (fpiv > 0.0 && !(piv > fpiv)) {
-            piv = fpiv;
-            if (lane == 0) modified = 1;
-          }
-          if (!(piv > 0.0)) fail = true;
-          if (!fail) {
-            const double rinv = rsqrt(piv), rkk = piv * rinv;  // short dependent chain
-            if (lane == 0) rdg[k] = rinv;
-            if (lane == k) myinv = rinv;
-            if (lane > k) r[k] *= rinv;
-            if (lane == k) r[k] = rkk;
-            const double lik = r[k];
-            // every lane updates every column after k: entries above a lane's diagonal (and
-            // the zero rows past nb) take finite updates that are never read, and no exec
-            // mask changes per column
-#pragma unroll
-            for (int j = k + 1; j < kPB; ++j) r[j] -= lik * readlane_d(lik, j);
-          }
-        }
+    // Factor the diagonal block held in S.D by wave 0 alone (factor_block32); no workgroup
+    // barrier inside.
+    auto factor_block = [&](int nb) __attribute__((always_inline)) {
+      bool f, md, ui;
+      factor_block32(*(LdsBlock *)&S, nb, floor_piv, f, md, ui);
+      if ((tid & 63) == 0) {
+        if (f) bad = 1;
+        if (md) modified = 1;
+        use_inv = ui;
       }
-      if (fail && lane == 0) bad = 1;
-      if (lane < nb) {
-#pragma unroll
-        for (int j = 0; j < kPB; ++j)
-          if (j <= lane) D[lane][j] = r[j];
-      }
-      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-      __builtin_amdgcn_wave_barrier();
-      // inverse of the factor: lane c solves L11 x = e_c (x in registers); L11[i][t] and
-      // 1 / L11[i][i] come from lane i's registers (v_readlane), not from LDS, which the
-      // trailing update of the other waves keeps busy meanwhile. Di[c][i] = (L11^{-1})[i][c]
-      double ci = 0.0;  // lane c: column c's 1-norm of L11^{-1}
-      if (!fail && lane < kPB) {
-        // four partial sums per row shorten the dependent chain
-        const int c = lane;
-        double x[kPB];
-#pragma unroll
-        for (int i = 0; i < kPB; ++i) {
-          double acc[4] = {(i == c) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-          for (int t = 0; t < i; ++t) acc[t & 3] -= readlane_d(r[t], i) * x[t];  // x[t] = 0, t < c
-          const double xi = ((acc[0] + acc[1]) + (acc[2] + acc[3])) * readlane_d(myinv, i);
-          x[i] = (i >= c && i < nb) ? xi : 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < kPB; ++i) {
-          Di[c][i] = x[i];
-          ci += fabs(x[i]);  // x[i] = 0 for i < c and i >= nb
-        }
-      }
-      // 1-norm condition of the block, kappa = |L11|_1 |L11^{-1}|_1: lane c sums column c
-      // of the factor and of its inverse
-      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-      __builtin_amdgcn_wave_barrier();
-      // the loads are independent and issued together (one LDS latency, not one per row)
-      double cl = 0.0;
-      if (!fail && lane < nb) {
-#pragma unroll
-        for (int i = 0; i < kPB; ++i) {
-          const double dv = D[i][lane];
-          cl += (i >= lane && i < nb) ? fabs(dv) : 0.0;
-        }
-      }
-      cl = wave_max_nonneg(cl);
-      ci = wave_max_nonneg(ci);
-      if (lane == 0) use_inv = (cl * ci <= kCholInvCond);
     };
     // first diagonal block
     {
       const int nb = min(kPB, m);
       for (int idx = tid; idx < nb * nb; idx += nt) {
         const int i = idx % nb, j = idx / nb;
-        D[i][j] = (i >= j) ? L[(size_t)j * m + i] : 0.0;
+        S.D[i][j] = (i >= j) ? L[(size_t)j * m + i] : 0.0;
       }
       __syncthreads();
       if (wave == 0) factor_block(nb);
@@ -375,7 +466,7 @@ __global__ void __launch_bounds__(kCholThreads)
       //    trailing update), goes to L
       for (int idx = tid; idx < nb * nb; idx += nt) {
         const int i = idx % nb, j = idx / nb;
-        if (i >= j) L[(size_t)(kb + j) * m + kb + i] = D[i][j];
+        if (i >= j) L[(size_t)(kb + j) * m + kb + i] = S.D[i][j];
       }
       // 2. panel rows below: X L11^T = A21 (the panel is staged in LDS first when it fits;
       //    the result goes to L and to the staged copy). A well-conditioned block: X =
@@ -387,9 +478,27 @@ __global__ void __launch_bounds__(kCholThreads)
       const int prow = m - r0;
       const bool staged = prow <= kStageRows;
       if (staged) {
-        for (int jj = wave; jj < nb; jj += nwaves)
-          for (int ii = tid & 63; ii < prow; ii += 64)
-            Pn[jj * (kStageRows + 1) + ii] = L[(size_t)(kb + jj) * m + r0 + ii];
+        // eight loads in flight per thread before any is stored (one memory latency per
+        // round, not one per element)
+        const int tot = nb * prow;
+        for (int base = tid; base < tot; base += 8 * nt) {
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int e = base + u * nt;
+            const int ec = e < tot ? e : 0;
+            const int jj = ec / prow, ii = ec - jj * prow;
+            v[u] = L[(size_t)(kb + jj) * m + r0 + ii];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int e = base + u * nt;
+            if (e < tot) {
+              const int jj = e / prow, ii = e - jj * prow;
+              Pn[jj * (kStageRows + 1) + ii] = v[u];
+            }
+          }
+        }
       }
       __syncthreads();
       if (!use_inv && staged) {
@@ -402,7 +511,7 @@ __global__ void __launch_bounds__(kCholThreads)
           const int i0 = 32 * I;
           d4 acc[2][2];
           zero_acc(acc);
-          wave_mma32<false, true>(Pn + i0, ld, &Di[0][0], kPB + 1, nb, prow - i0, nb, acc);
+          wave_mma32<false, true>(Pn + i0, ld, &S.Di[0][0], kPB + 1, nb, prow - i0, nb, acc);
 #pragma unroll
           for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -418,7 +527,7 @@ __global__ void __launch_bounds__(kCholThreads)
           const int i0 = 32 * I;
           d4 acc[2][2];
           zero_acc(acc);
-          wave_mma32<false, false>(L + (size_t)kb * m + r0 + i0, m, &D[0][0], kPB + 1, nb,
+          wave_mma32<false, false>(L + (size_t)kb * m + r0 + i0, m, &S.D[0][0], kPB + 1, nb,
                                    prow - i0, nb, acc);
 #pragma unroll
           for (int rt = 0; rt < 2; ++rt)
@@ -433,9 +542,20 @@ __global__ void __launch_bounds__(kCholThreads)
         __syncthreads();
         for (int I = wave; I < npt; I += nwaves) {
           const int i0 = 32 * I;
+          double x0[2][2][4];  // X0 of these rows, loaded ahead of the products
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+              for (int rr = 0; rr < 4; ++rr) {
+                const int row = i0 + 16 * rt + lg + 4 * rr, col = 16 * ct + li;
+                const bool in = row < prow && col < nb;
+                x0[rt][ct][rr] = L[in ? (size_t)(kb + col) * m + r0 + row : 0];
+              }
           d4 acc[2][2];
           zero_acc(acc);
-          wave_mma32<false, true>(Pn + i0, ld, &Di[0][0], kPB + 1, nb, prow - i0, nb, acc);
+          wave_mma32<false, true>(Pn + i0, ld, &S.Di[0][0], kPB + 1, nb, prow - i0, nb, acc);
           // the MFMAs consumed every operand load of this wave's rows: overwrite them
 #pragma unroll
           for (int rt = 0; rt < 2; ++rt)
@@ -446,7 +566,7 @@ __global__ void __launch_bounds__(kCholThreads)
                 const int row = i0 + 16 * rt + lg + 4 * rr, col = 16 * ct + li;
                 if (row < prow && col < nb) {
                   const size_t o = (size_t)(kb + col) * m + r0 + row;
-                  const double x = L[o] + acc[rt][ct][rr];
+                  const double x = x0[rt][ct][rr] + acc[rt][ct][rr];
                   L[o] = x;
                   Pn[col * ld + row] = x;
                 }
@@ -459,8 +579,8 @@ __global__ void __launch_bounds__(kCholThreads)
           double *col = L + (size_t)kb * m + r0 + i;  // element j at col[j m]
           for (int j = 0; j < nb; ++j) {
             double a = col[(size_t)j * m];
-            for (int t = 0; t < j; ++t) a -= col[(size_t)t * m] * D[j][t];
-            col[(size_t)j * m] = a * Di[j][j];  // Di[j][j] = 1 / L11[j][j]
+            for (int t = 0; t < j; ++t) a -= col[(size_t)t * m] * S.D[j][t];
+            col[(size_t)j * m] = a * S.Di[j][j];  // Di[j][j] = 1 / L11[j][j]
           }
         }
       } else {
@@ -471,10 +591,10 @@ __global__ void __launch_bounds__(kCholThreads)
           d4 acc[2][2];
           zero_acc(acc);
           if (staged)
-            wave_mma32<false, true>(Pn + i0, kStageRows + 1, &Di[0][0], kPB + 1, nb, prow - i0,
+            wave_mma32<false, true>(Pn + i0, kStageRows + 1, &S.Di[0][0], kPB + 1, nb, prow - i0,
                                     nb, acc);
           else
-            wave_mma32<false, true>(L + (size_t)kb * m + r0 + i0, m, &Di[0][0], kPB + 1, nb,
+            wave_mma32<false, true>(L + (size_t)kb * m + r0 + i0, m, &S.Di[0][0], kPB + 1, nb,
                                     prow - i0, nb, acc);
           // the MFMAs consumed every operand load of this wave's rows: overwrite them
 #pragma unroll
@@ -506,6 +626,20 @@ __global__ void __launch_bounds__(kCholThreads)
         }
         const int J = rem;  // tile (I, J) with J <= I
         const int i0 = r0 + 32 * I, j0 = r0 + 32 * J;
+        const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
+        // the tile's current values are loaded before the products (unconditional loads at a
+        // clamped address, so they are all in flight together and overlap the MFMAs)
+        double old[2][2][4];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = i0 + 16 * rt + lg + 4 * r, col = j0 + 16 * ct + li;
+              const bool in = row < m && col < m && row >= col;
+              old[rt][ct][r] = L[in ? (size_t)col * m + row : 0];
+            }
         d4 acc[2][2];
         zero_acc(acc);
         if (staged)
@@ -514,7 +648,6 @@ __global__ void __launch_bounds__(kCholThreads)
         else
           wave_mma32<false, true>(L + (size_t)kb * m + i0, m, L + (size_t)kb * m + j0, m, nb,
                                   m - i0, m - j0, acc);
-        const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -523,9 +656,9 @@ __global__ void __launch_bounds__(kCholThreads)
             for (int r = 0; r < 4; ++r) {
               const int row = i0 + 16 * rt + lg + 4 * r, col = j0 + 16 * ct + li;
               if (row < m && col < m && row >= col) {
-                const double v = L[(size_t)col * m + row] - acc[rt][ct][r];
+                const double v = old[rt][ct][r] - acc[rt][ct][r];
                 L[(size_t)col * m + row] = v;
-                if (to_D) D[row - i0][col - j0] = v;
+                if (to_D) S.D[row - i0][col - j0] = v;
               }
             }
       };
@@ -983,9 +1116,10 @@ __global__ void check_finite_kernel(long long count, const double *__restrict__ 
 
 hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const double *A, int lda,
                     const double *B, int ldb, double beta, double *C, int ldc, double *partial,
-                    int splitk, hipStream_t st, const int *run, bool lower) {
+                    int splitk, hipStream_t st, const int *run, bool lower, double *gram_sq) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (lower && !(ta == 1 && tb == 0 && M == N)) return hipErrorInvalidValue;
+  if (gram_sq && (!lower || !partial || K <= 0 || beta != 0.0)) return hipErrorInvalidValue;
   if (K <= 0) splitk = 1;
   if (splitk < 1 || !partial) splitk = 1;
   int kchunk = (K + splitk - 1) / splitk;
@@ -993,7 +1127,8 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   if (kchunk <= 0) kchunk = 4;
   const int splits = K > 0 ? (K + kchunk - 1) / kchunk : 1;
   dim3 grid((M + 31) / 32, (N + 31) / 32, splits);
-  double *part = splits > 1 ? partial : nullptr;
+  // the Gram-with-squares form always goes through the reduction, which writes them
+  double *part = (splits > 1 || gram_sq) ? partial : nullptr;
 #define RIOT_GEMM(TA_, TB_)                                                                  \
   hipLaunchKernelGGL((gemm_mfma_kernel<TA_, TB_>), grid, dim3(64), 0, st, M, N, K, A, lda, B, \
                      ldb, C, ldc, alpha, beta, kchunk, part, run, nullptr, 0, 0, 0)
@@ -1011,10 +1146,10 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
 #undef RIOT_GEMM
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (splits > 1) {
+  if (part) {
     const size_t MN = (size_t)M * N;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st,
-                       M, N, splits, partial, alpha, beta, C, ldc, run, lower ? 1 : 0);
+                       M, N, splits, partial, alpha, beta, C, ldc, run, lower ? 1 : 0, gram_sq);
     e = hipGetLastError();
   }
   return e;
@@ -1022,9 +1157,10 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
 
 hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_rel, int mode,
                                int *flag, int *shifts, hipStream_t st, const int *run,
-                               int *modflag) {
+                               int *modflag, const double *gram_sq) {
+  if (gram_sq && G != L) return hipErrorInvalidValue;
   hipLaunchKernelGGL(chol_blocked_kernel, dim3(1), dim3(kCholThreads), 0, st, m, G, L, shift_rel,
-                     mode, flag, shifts, run, modflag, nullptr);
+                     mode, flag, shifts, run, modflag, gram_sq, nullptr);
   return hipGetLastError();
 }
 
@@ -1222,7 +1358,7 @@ hipError_t launch_gemm_batched(int ta, int tb, int nprob, int maxM, int maxN, do
 hipError_t launch_chol_batched(int nprob, int mode, const CholJob *jobs, hipStream_t st) {
   if (nprob <= 0) return hipSuccess;
   hipLaunchKernelGGL(chol_blocked_kernel, dim3(1, nprob), dim3(kCholThreads), 0, st, 0, nullptr,
-                     nullptr, 0.0, mode, nullptr, nullptr, nullptr, nullptr, jobs);
+                     nullptr, 0.0, mode, nullptr, nullptr, nullptr, nullptr, nullptr, jobs);
   return hipGetLastError();
 }
 

@@ -22,9 +22,11 @@ constexpr int kSplitK = 16;
 
 // Scratch of the linear algebra: the split-K partial products of an m x m Gram matrix,
 // later reused for the inverses of the Cholesky factor's 32 x 32 diagonal blocks.
-inline size_t partial_doubles(size_t m) {
+// The Gram's partial sums of squares for the in-place Cholesky follow both uses.
+inline size_t gram_sq_offset(size_t m) {
   return std::max((size_t)kSplitK * std::max(m * m, m), (m + 31) / 32 * 1024);
 }
+inline size_t partial_doubles(size_t m) { return gram_sq_offset(m) + (m * m + 255) / 256 + 1; }
 
 // Bump allocator over the caller's workspace (base == nullptr: size only).
 struct Carver {
@@ -311,11 +313,13 @@ riot_status cholqr(const LaSpace &h, int rows, int m, const double *Xin, double 
   RIOT_HIP(launch_cholqr_reset(cq, st));
   for (int pass = 0; pass < kMaxCholQRPasses; ++pass) {
     const bool sh = shifted && pass == 0;
-    // the Cholesky reads the Gram's lower triangle only
-    RIOT_HIP(gemm_f64(1, 0, m, m, rows, 1.0, Qout, rows, Qout, rows, 0.0, h.G, m, h.partial,
-                      kSplitK, st, cq, true));
-    RIOT_HIP(launch_chol_blocked(m, h.G, h.R, srel, sh ? 1 : 2, h.flags + flag_idx, h.flags + 4,
-                                 st, cq, cq + 2));
+    // the Gram goes straight into R (lower triangle, zero upper) with the partial sums of
+    // its squared Frobenius norm, and is factored there in place
+    double *gsq = h.partial + gram_sq_offset(m);
+    RIOT_HIP(gemm_f64(1, 0, m, m, rows, 1.0, Qout, rows, Qout, rows, 0.0, h.R, m, h.partial,
+                      kSplitK, st, cq, true, gsq));
+    RIOT_HIP(launch_chol_blocked(m, h.R, h.R, srel, sh ? 1 : 2, h.flags + flag_idx, h.flags + 4,
+                                 st, cq, cq + 2, gsq));
     // the Gram's split-K buffer is free here: it holds the diagonal-block inverses
     RIOT_HIP(launch_trsm_diag_inv(m, h.R, h.partial, st, cq));
     RIOT_HIP(launch_trsm_rlt_inv(rows, m, Qout, rows, h.R, h.partial, st, cq));

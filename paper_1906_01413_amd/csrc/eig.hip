@@ -62,6 +62,7 @@ struct EigLayout {
 };
 
 constexpr int kTriThreads = 512;
+constexpr int kEigMaxM = 1088;  // largest m of the eigen-solver
 
 // ---------------------------------------------------------------------------
 // 1. Householder tridiagonalisation (full storage, one workgroup).
@@ -151,6 +152,155 @@ __global__ void __launch_bounds__(kTriThreads)
     __syncthreads();
   }
   if (tid == 0) {
+    if (m >= 2) {
+      dg[m - 2] = Aw[(size_t)(m - 2) * m + m - 2];
+      dg[m - 1] = Aw[(size_t)(m - 1) * m + m - 1];
+      eg[m - 2] = Aw[(size_t)(m - 2) * m + m - 1];
+    } else {
+      dg[0] = Aw[0];
+    }
+    eg[m - 1] = 0.0;
+  }
+}
+
+// Grid variant, for m beyond the register tiles: a persistent grid of kTriGridWG workgroups
+// and two grid-wide barriers per step. Workgroup g owns a contiguous block of columns of
+// the symmetric working matrix (full storage in Aw) for the rank-2 updates and a contiguous
+// block of the trailing rows for the product p = S v. Step k:
+//   every workgroup forms the reflector v of column k itself (the same data and the same
+//   reduction order everywhere, so all hold the same v); workgroup 0 stores it;
+//   p = S v by row blocks (reads of S coalesced along its columns) and the block's share
+//   of v^T p into a per-workgroup slot;                                   -- barrier
+//   w = p - (v^T p) v with v^T p summed over the slots in order, and the rank-2 update
+//   S -= 2 (v w^T + w v^T) of the owned columns;                          -- barrier
+// A barrier is a release fence and an arrival on a counter (cleared before the launch), then
+// acquire polls until every workgroup of this barrier has arrived; the polls are bounded, and
+// a workgroup that gives up raises an abort word the others see and the eigen-solver's flag.
+constexpr int kTriGridWG = 64;
+constexpr int kTriGridThreads = 256;
+constexpr int kTriGridMaxPolls = 1 << 22;
+
+__device__ bool grid_barrier(int *ctr, int *abort_w, int target, int *ok_lds) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int polls = 0, ok = 1;
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+          ++polls > kTriGridMaxPolls) {
+        __hip_atomic_store(abort_w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    *ok_lds = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return *ok_lds != 0;
+}
+
+__global__ void __launch_bounds__(kTriGridThreads)
+    tridiag_grid_kernel(int m, const double *__restrict__ K, double *__restrict__ work,
+                        int *__restrict__ gsync, int *__restrict__ flag) {
+  EigLayout Lw(m);
+  double *Aw = work + Lw.Aw, *Hv = work + Lw.Hv, *dg = work + Lw.d, *eg = work + Lw.e;
+  double *pg = work + Lw.scr, *partg = pg + m;  // p, and the per-workgroup shares of v^T p
+  int *const ctr = gsync, *const abort_w = gsync + 1;
+  __shared__ double vs[kEigMaxM];
+  __shared__ double red[16];
+  __shared__ double psum[kTriGridThreads];
+  __shared__ int ok;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int G = gridDim.x, g = blockIdx.x;
+  const int cper = (m + G - 1) / G, clo = min(m, g * cper), chi = min(m, clo + cper);
+  int nbar = 0;
+  // copy of K (owned columns) and cleared reflector columns
+  for (int j = clo; j < chi; ++j)
+    for (int i = tid; i < m; i += nt) {
+      Aw[(size_t)j * m + i] = K[(size_t)j * m + i];
+      Hv[(size_t)j * m + i] = 0.0;
+    }
+  if (!grid_barrier(ctr, abort_w, ++nbar * G, &ok)) {
+    if (tid == 0) flag[0] = 1;
+    return;
+  }
+  for (int k = 0; k + 2 < m; ++k) {
+    const int R = m - k - 1, r0 = k + 1;
+    // reflector of column k, in every workgroup
+    double part = 0.0;
+    for (int i = tid; i < R; i += nt) {
+      const double x = Aw[(size_t)k * m + r0 + i];
+      vs[i] = x;
+      part += x * x;
+    }
+    const double sig2 = wsum(part, red);
+    const double sig = sqrt(sig2);
+    const double x0 = vs[0];
+    __syncthreads();
+    if (sig == 0.0) {  // column already reduced: no reflector, S unchanged
+      if (g == 0 && tid == 0) {
+        dg[k] = Aw[(size_t)k * m + k];
+        eg[k] = 0.0;
+      }
+      continue;
+    }
+    const double alpha = (x0 >= 0.0) ? -sig : sig;
+    const double vn = sqrt(2.0 * (sig2 - alpha * x0));
+    if (tid == 0) vs[0] = x0 - alpha;
+    __syncthreads();
+    for (int i = tid; i < R; i += nt) {
+      const double v = vs[i] / vn;
+      vs[i] = v;
+      if (g == 0) Hv[(size_t)k * m + r0 + i] = v;
+    }
+    if (g == 0 && tid == 0) {
+      dg[k] = Aw[(size_t)k * m + k];
+      eg[k] = alpha;
+    }
+    __syncthreads();
+    // p = S v for this workgroup's rows: thread (row, column group), groups summed in order
+    const int rper = (R + G - 1) / G, rlo = min(R, g * rper), nr = min(R, rlo + rper) - rlo;
+    double vp = 0.0;
+    if (nr > 0) {
+      const int ngrp = max(1, nt / nr), ri = tid % nr, cg = tid / nr;
+      double acc = 0.0;
+      if (cg < ngrp)
+        for (int j = cg; j < R; j += ngrp) acc += Aw[(size_t)(r0 + j) * m + r0 + rlo + ri] * vs[j];
+      psum[tid] = (cg < ngrp) ? acc : 0.0;
+      __syncthreads();
+      if (tid < nr) {
+        double sacc = 0.0;
+        for (int c = 0; c < ngrp; ++c) sacc += psum[c * nr + tid];
+        pg[r0 + rlo + tid] = sacc;
+        vp = sacc * vs[rlo + tid];
+      }
+    }
+    const double vps = wsum(vp, red);
+    if (tid == 0) partg[g] = vps;
+    if (!grid_barrier(ctr, abort_w, ++nbar * G, &ok)) break;
+    // w = p - (v^T p) v, and the rank-2 update of the owned columns within the trailing block
+    double Kv = 0.0;
+    for (int q = 0; q < G; ++q) Kv += partg[q];
+    const int jlo = max(clo, r0);
+    for (int j = jlo; j < chi; ++j) {
+      const double vj = vs[j - r0];
+      const double wj = pg[j] - Kv * vj;
+      for (int i = tid; i < R; i += nt) {
+        const double vi = vs[i];
+        const double wi = pg[r0 + i] - Kv * vi;
+        Aw[(size_t)j * m + r0 + i] -= 2.0 * (vi * wj + wi * vj);
+      }
+    }
+    if (!grid_barrier(ctr, abort_w, ++nbar * G, &ok)) break;
+  }
+  if (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    if (tid == 0) flag[0] = 1;
+    return;
+  }
+  if (g == 0 && tid == 0) {
     if (m >= 2) {
       dg[m - 2] = Aw[(size_t)(m - 2) * m + m - 2];
       dg[m - 1] = Aw[(size_t)(m - 1) * m + m - 1];
@@ -752,7 +902,6 @@ __global__ void __launch_bounds__(128) vector_kernel(int m, double *__restrict__
 // 5. Clusters (relative gap < 1e-3): Gram-Schmidt and Rayleigh-Ritz (one workgroup).
 // ---------------------------------------------------------------------------
 constexpr int kMaxCluster = 48;
-constexpr int kEigMaxM = 1088;  // largest m of the eigen-solver
 
 __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict__ work,
                                                       int *__restrict__ flag,
@@ -1230,9 +1379,14 @@ hipError_t launch_eig(int m, const double *K, double *lam, double *Z, double *wo
   if (tile_fits(m))
     hipLaunchKernelGGL(tridiag_tile_kernel, dim3(1), dim3(tile_threads(m)), 0, st, m, K, work,
                        nullptr);
-  else
-    hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kTriThreads),
-                       (size_t)(2 * m + kTriThreads) * sizeof(double), st, m, K, work, nullptr);
+  else {
+    // barrier counter and abort word after p and the workgroups' shares, cleared first
+    int *gsync = reinterpret_cast<int *>(work + EigLayout(m).scr + m + kTriGridWG);
+    hipError_t e0 = launch_zero_ints(gsync, 2, st);
+    if (e0 != hipSuccess) return e0;
+    hipLaunchKernelGGL(tridiag_grid_kernel, dim3(kTriGridWG), dim3(kTriGridThreads), 0, st, m, K,
+                       work, gsync, flag);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(root_kernel, dim3(1), dim3(256), (size_t)4 * m * sizeof(double), st, m, work,

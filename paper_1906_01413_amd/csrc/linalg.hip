@@ -108,6 +108,12 @@ __global__ void __launch_bounds__(64)
       }
 }
 
+// ints after the Gram's partial sums of squares used by the multi-workgroup Cholesky: one
+// "panel published" flag per 32-column block, then the breakdown and modified words
+constexpr int kCholMaxBlocks = 48;  // 1088 / 32 = 34 blocks at the largest sketch
+constexpr int kCholSyncBad = kCholMaxBlocks, kCholSyncMod = kCholMaxBlocks + 1;
+constexpr int kCholSyncInts = 64;
+
 __global__ void __launch_bounds__(256)
     splitk_reduce_kernel(int M, int N, int splits, const double *__restrict__ partial,
                          double alpha, double beta, double *__restrict__ C, int ldc,
@@ -141,6 +147,10 @@ __global__ void __launch_bounds__(256)
       for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
       gram_sq[blockIdx.x] = t;
     }
+    // the flags the in-place Cholesky's workgroups exchange follow the partial sums; they
+    // start each factorization cleared
+    if (blockIdx.x == 0 && threadIdx.x < kCholSyncInts)
+      reinterpret_cast<int *>(gram_sq + gridDim.x)[threadIdx.x] = 0;
   }
 }
 
@@ -686,6 +696,235 @@ __global__ void __launch_bounds__(kCholThreads)
 }
 
 // ---------------------------------------------------------------------------
+// Blocked Cholesky G + s I = L L^T in place, one workgroup per 32-column block J (the
+// same modes and flags as chol_blocked_kernel). G == L is the Gram matrix as the Gram GEMM
+// left it (zero upper triangle) with the partial sums of ||G||_F^2 in gram_sq and cleared
+// flags after them. Right-looking: workgroup J applies the update of every panel p < J to
+// its own column block as soon as panel p is published (tiles (I, J), I >= J, on FP64
+// MFMA, operands from L2), then factors its diagonal block (factor_block32) and solves its
+// panel X = A21 L11^{-T} (with one refinement step for a badly conditioned block), and
+// publishes it: stores, agent-scope release fence, flag. Waiting is acquire on the flag,
+// by one thread, with a bounded number of polls (a timeout counts as a breakdown). Only
+// lower-numbered workgroups are waited for, and they are dispatched first.
+// ---------------------------------------------------------------------------
+constexpr int kCholMaxPolls = 1 << 22;
+
+__global__ void __launch_bounds__(kCholThreads)
+    chol_mwg_kernel(int m, double *L, double shift_rel, int mode, int *__restrict__ flag,
+                    int *__restrict__ shifts, const int *__restrict__ run,
+                    int *__restrict__ modflag, double *__restrict__ gram_sq) {
+  if (run && run[0] == 0) return;
+  const int nblk = (m + kPB - 1) / kPB;
+  const int J = blockIdx.x;
+  if (J >= nblk) return;
+  const int nsq = (int)(((size_t)m * m + 255) / 256);
+  int *const sync = reinterpret_cast<int *>(gram_sq + nsq);
+  __shared__ BlockLds S;
+  __shared__ double W[kCholThreads / 64][kPB * (kPB + 1)];  // per-wave refinement tile
+  __shared__ double red[16];
+  __shared__ int bad, modified, use_inv, timed_out;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid >> 6, nwaves = nthr >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  // ||G||_F from the partial sums, in the same order in every workgroup
+  double fro = 0.0;
+  if (mode != 0) {
+    double part = 0.0;
+    for (int q = tid; q < nsq; q += nthr) part += gram_sq[q];
+    fro = sqrt(wg_sum(part, red));
+  }
+  const double floor_piv = (mode == 2) ? shift_rel * fro : 0.0;
+  const double s = (mode == 1) ? shift_rel * fro : 0.0;
+  if (mode == 1 && J == 0 && tid == 0 && shifts) shifts[0] += 1;
+  const int c0 = kPB * J, nb = min(kPB, m - c0);
+  if (tid == 0) bad = 0, modified = 0, use_inv = 1, timed_out = 0;
+  // the diagonal block's upper triangle (and rows from nb on) stay zero: S.D is an MFMA
+  // operand of the refinement
+  for (int idx = tid; idx < kPB * (kPB + 1); idx += nthr) (&S.D[0][0])[idx] = 0.0;
+  if (s != 0.0)
+    for (int t = tid; t < nb; t += nthr) L[(size_t)(c0 + t) * m + c0 + t] += s;
+  __syncthreads();
+
+  auto factor_diag = [&]() {
+    bool f, md, ui;
+    factor_block32(*(LdsBlock *)&S, nb, floor_piv, f, md, ui);
+    if (lane == 0) {
+      if (f) bad = 1;
+      if (md) modified = 1;
+      use_inv = ui;
+    }
+  };
+  // tile (I, J) -= L[I, p] L[J, p]^T with the old values loaded ahead of the MFMAs; the
+  // diagonal tile keeps its lower triangle only, and with to_D also goes to S.D
+  auto update_tile = [&](int p, int I, bool to_D) {
+    const int i0 = kPB * I, k0 = kPB * p;
+    double old[2][2][4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = i0 + 16 * rt + lg + 4 * r, col = c0 + 16 * ct + li;
+          const bool in = row < m && col < m && row >= col;
+          old[rt][ct][r] = L[in ? (size_t)col * m + row : 0];
+        }
+    d4 acc[2][2];
+    zero_acc(acc);
+    wave_mma32<false, true>(L + (size_t)k0 * m + i0, m, L + (size_t)k0 * m + c0, m,
+                            min(kPB, m - k0), m - i0, m - c0, acc);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = i0 + 16 * rt + lg + 4 * r, col = c0 + 16 * ct + li;
+          if (row < m && col < m && row >= col) {
+            const double v = old[rt][ct][r] - acc[rt][ct][r];
+            L[(size_t)col * m + row] = v;
+            if (to_D) S.D[row - i0][col - c0] = v;
+          }
+        }
+  };
+
+  // updates from the published panels p < J
+  for (int p = 0; p < J; ++p) {
+    if (tid == 0) {
+      int polls = 0;
+      while (__hip_atomic_load(&sync[p], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 1) {
+        if (++polls > kCholMaxPolls) {
+          timed_out = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __syncthreads();
+    // every thread sees panel p's stores (its own L1 may hold older lines)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (timed_out) break;
+    const int ntile = nblk - J;  // tiles I = J .. nblk - 1
+    if (p == J - 1) {
+      // last update: wave 0 takes the diagonal tile and factors it while the other waves
+      // update the tiles below
+      if (wave == 0) {
+        update_tile(p, J, true);
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        __builtin_amdgcn_wave_barrier();
+        factor_diag();
+      } else {
+        for (int t = wave; t < ntile; t += nwaves - 1) update_tile(p, J + t, false);
+      }
+    } else {
+      for (int t = wave; t < ntile; t += nwaves) update_tile(p, J + t, false);
+    }
+  }
+  if (J == 0) {
+    for (int idx = tid; idx < kPB * kPB; idx += nthr) {
+      const int i = idx % kPB, j = idx / kPB;
+      if (i >= j && i < nb && j < nb) S.D[i][j] = L[(size_t)j * m + i];
+    }
+    __syncthreads();
+    if (wave == 0) factor_diag();
+  }
+  __syncthreads();
+
+  if (!timed_out) {
+    // the factor's diagonal block, then the panel below: X L11^T = A21, by 32-row tiles
+    for (int idx = tid; idx < nb * nb; idx += nthr) {
+      const int i = idx % nb, j = idx / nb;
+      if (i >= j) L[(size_t)(c0 + j) * m + c0 + i] = S.D[i][j];
+    }
+    double *const Wt = W[wave];
+    for (int I = J + 1 + wave; I < nblk; I += nwaves) {
+      const int i0 = kPB * I, rows = m - i0;
+      const double *A = L + (size_t)c0 * m + i0;
+      double a[2][2][4];  // the panel tile A21, loaded ahead
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * rt + lg + 4 * r, col = 16 * ct + li;
+            const bool in = row < rows && col < nb;
+            a[rt][ct][r] = A[in ? (size_t)col * m + row : 0];
+          }
+      d4 x0[2][2];
+      zero_acc(x0);
+      wave_mma32<false, true>(A, m, &S.Di[0][0], kPB + 1, nb, rows, nb, x0);
+      {
+        // one refinement step for every block: residual R = A - X0 L11^T and
+        // X = X0 + R L11^{-T} (the product with the inverse alone leaves a residual of order
+        // the block's condition times rounding), operands through this wave's LDS tile
+        // (column-major, leading dimension kPB + 1)
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * rt + lg + 4 * r, col = 16 * ct + li;
+              Wt[col * (kPB + 1) + row] = (row < rows && col < nb) ? x0[rt][ct][r] : 0.0;
+            }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        __builtin_amdgcn_wave_barrier();
+        d4 t1[2][2];
+        zero_acc(t1);
+        wave_mma32<false, false>(Wt, kPB + 1, &S.D[0][0], kPB + 1, nb, rows, nb, t1);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * rt + lg + 4 * r, col = 16 * ct + li;
+              Wt[col * (kPB + 1) + row] =
+                  (row < rows && col < nb) ? a[rt][ct][r] - t1[rt][ct][r] : 0.0;
+            }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        __builtin_amdgcn_wave_barrier();
+        d4 t2[2][2];
+        zero_acc(t2);
+        wave_mma32<false, true>(Wt, kPB + 1, &S.Di[0][0], kPB + 1, nb, rows, nb, t2);
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) x0[rt][ct] += t2[rt][ct];
+        __builtin_amdgcn_wave_barrier();
+      }
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * rt + lg + 4 * r, col = 16 * ct + li;
+            if (row < rows && col < nb) L[(size_t)(c0 + col) * m + i0 + row] = x0[rt][ct][r];
+          }
+    }
+  }
+  // publish: the breakdown and modified words first, then (after every thread's stores are
+  // released) the panel flag
+  if (tid == 0) {
+    if (bad || timed_out) __hip_atomic_store(&sync[kCholSyncBad], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (modified) __hip_atomic_store(&sync[kCholSyncMod], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (tid == 0) __hip_atomic_store(&sync[J], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  // the last block has waited for every other one: it reports for the factorization
+  if (J == nblk - 1 && tid == 0) {
+    const int b = __hip_atomic_load(&sync[kCholSyncBad], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const int md = __hip_atomic_load(&sync[kCholSyncMod], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (b) flag[0] = 1;
+    if (md && shifts) shifts[0] += 1;
+    if (md && modflag) modflag[0] = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // X <- X L^{-T} for X (rows x m, leading dimension ldx) and lower-triangular L (m x m):
 // the right-hand triangular solve of CholeskyQR (Q = Y R^{-1} with R = L^T). One wave
 // per block of 32 rows; per 32-column block jb the wave forms
@@ -1159,6 +1398,14 @@ hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_r
                                int *flag, int *shifts, hipStream_t st, const int *run,
                                int *modflag, const double *gram_sq) {
   if (gram_sq && G != L) return hipErrorInvalidValue;
+  // up to the staged panel height one workgroup is faster (the critical path is the chain of
+  // diagonal blocks either way); beyond it the trailing updates dominate and are spread
+  if (gram_sq && m > kStageRows + kPB) {
+    if ((m + kPB - 1) / kPB > kCholMaxBlocks) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(chol_mwg_kernel, dim3((m + kPB - 1) / kPB), dim3(kCholThreads), 0, st, m,
+                       L, shift_rel, mode, flag, shifts, run, modflag, const_cast<double *>(gram_sq));
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(chol_blocked_kernel, dim3(1), dim3(kCholThreads), 0, st, m, G, L, shift_rel,
                      mode, flag, shifts, run, modflag, gram_sq, nullptr);
   return hipGetLastError();

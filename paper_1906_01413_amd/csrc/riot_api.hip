@@ -22,11 +22,12 @@ constexpr int kSplitK = 16;
 
 // Scratch of the linear algebra: the split-K partial products of an m x m Gram matrix,
 // later reused for the inverses of the Cholesky factor's 32 x 32 diagonal blocks.
-// The Gram's partial sums of squares for the in-place Cholesky follow both uses.
+// The Gram's partial sums of squares for the in-place Cholesky follow both uses, then 32
+// doubles of flags for its workgroups.
 inline size_t gram_sq_offset(size_t m) {
   return std::max((size_t)kSplitK * std::max(m * m, m), (m + 31) / 32 * 1024);
 }
-inline size_t partial_doubles(size_t m) { return gram_sq_offset(m) + (m * m + 255) / 256 + 1; }
+inline size_t partial_doubles(size_t m) { return gram_sq_offset(m) + (m * m + 255) / 256 + 32; }
 
 // Bump allocator over the caller's workspace (base == nullptr: size only).
 struct Carver {

@@ -235,8 +235,9 @@ hipError_t launch_philox_normal(long long total, uint64_t seed, uint64_t stream,
 // lower: for the symmetric A^T A shape (ta = 1, tb = 0, M = N), only C's lower triangle is
 // formed; the strict upper triangle is left as it was.
 // gram_sq (lower only, beta = 0): the strict upper triangle is set to zero and gram_sq[b],
-// b < gram_sq_blocks(M), receives a partial sum of ||C||_F^2 (each sum in a fixed order).
-// The input form of an in-place Cholesky (launch_chol_blocked with the same gram_sq).
+// b < gram_sq_blocks(M), receives a partial sum of ||C||_F^2 (each sum in a fixed order);
+// the 32 doubles after them are cleared (flags of the in-place Cholesky). The input form of
+// an in-place Cholesky (launch_chol_blocked with the same gram_sq).
 hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const double *A, int lda,
                     const double *B, int ldb, double beta, double *C, int ldc, double *partial,
                     int splitk, hipStream_t st, const int *run = nullptr, bool lower = false,
@@ -249,7 +250,8 @@ inline int gram_sq_blocks(int m) { return (int)(((size_t)m * m + 255) / 256); }
 // (non-positive or non-finite pivot); shifts[0] counts shifted or modified factorizations.
 // gram_sq: the partial sums of ||G||_F^2 written by the Gram GEMM (gemm_f64 with gram_sq);
 // the factorization then runs in place, G == L holding the Gram matrix with a zero upper
-// triangle. Without it G is copied into L first.
+// triangle, one workgroup per 32-column block (m <= 1536). Without it G is copied into L
+// first and one workgroup factors.
 hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_rel, int mode,
                                int *flag, int *shifts, hipStream_t st, const int *run = nullptr,
                                int *modflag = nullptr, const double *gram_sq = nullptr);

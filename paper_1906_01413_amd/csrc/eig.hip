@@ -899,170 +899,227 @@ __global__ void __launch_bounds__(128) vector_kernel(int m, double *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// 5. Clusters (relative gap < 1e-3): Gram-Schmidt and Rayleigh-Ritz (one workgroup).
+// 5. Clusters (relative gap < 1e-3): Gram-Schmidt and Rayleigh-Ritz (one workgroup per cluster).
 // ---------------------------------------------------------------------------
 constexpr int kMaxCluster = 48;
 
+// Cluster list: where the relative gap between neighbouring mu is below 1e-3, at most
+// kMaxCluster per cluster, scanned in order by one thread from the mu of the vector step.
+// list[0] = number of clusters of two or more; list[1 + 2 g], list[2 + 2 g] = first and last
+// index of cluster g. The list sits after the m x m part of the scratch that the cluster
+// kernel uses for T Z_c.
+__global__ void __launch_bounds__(64) cluster_scan_kernel(int m, double *__restrict__ work,
+                                                          const EigJob *__restrict__ jobs) {
+  if (jobs) m = jobs[blockIdx.y].m, work = jobs[blockIdx.y].work;
+  if (threadIdx.x != 0) return;
+  EigLayout Lw(m);
+  const double *mu = work + Lw.mu;
+  int *list = reinterpret_cast<int *>(work + Lw.scr + (size_t)m * m);
+  auto close = [&](int i) {
+    return fabs(mu[i + 1] - mu[i]) < 1e-3 * fmax(fabs(mu[i + 1]), fabs(mu[i]));
+  };
+  int cnt = 0, a = 0;
+  while (a < m) {
+    int s0 = a;
+    while (s0 + 1 < m && !close(s0)) ++s0;
+    int e = s0;
+    while (e + 1 < m && e + 1 - s0 < kMaxCluster && close(e)) ++e;
+    if (e > s0) {
+      list[1 + 2 * cnt] = s0;
+      list[2 + 2 * cnt] = e;
+      ++cnt;
+    }
+    a = e + 1;
+  }
+  list[0] = cnt;
+}
+
+// Sum over the wave (all lanes get it).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One workgroup per cluster Z_c = Z[:, a..b] (clusters are disjoint column sets): the vectors
+// are re-orthonormalised (classical Gram-Schmidt twice, the dot products of one vector with
+// all earlier ones spread over the waves; a vector that collapses is replaced by a probe),
+// then rotated by the eigenvectors of H = Z_c^T T Z_c, found by Jacobi with the
+// round-robin parallel ordering (the rotations of one round act on disjoint index pairs).
 __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict__ work,
                                                       int *__restrict__ flag,
                                                       const EigJob *__restrict__ jobs) {
   if (jobs) m = jobs[blockIdx.y].m, work = jobs[blockIdx.y].work, flag = jobs[blockIdx.y].flag;
   EigLayout Lw(m);
+  const int *list = reinterpret_cast<const int *>(work + Lw.scr + (size_t)m * m);
+  const int g = blockIdx.x;
+  if (g >= list[0]) return;
+  const int a = list[1 + 2 * g], c = list[2 + 2 * g] - a + 1;
   const double *dg = work + Lw.d, *eg = work + Lw.e, *misc = work + Lw.misc;
   double *mu = work + Lw.mu, *Z = work + Lw.Z;
-  double *W = work + Lw.scr;  // m x kMaxCluster
+  double *W = work + Lw.scr + (size_t)a * m;  // m x c, this cluster's columns of the scratch
   __shared__ double H[kMaxCluster][kMaxCluster + 1];
   __shared__ double Vc[kMaxCluster][kMaxCluster + 1];
+  __shared__ double dots[kMaxCluster];
+  __shared__ double rot[kMaxCluster / 2][2];
+  __shared__ int pr[kMaxCluster / 2][2];
   __shared__ double red[16];
-  __shared__ double mus[kEigMaxM];  // mu in LDS for the scan (kept equal to mu below)
-  __shared__ int cl_start, cl_end;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ int done;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  const int nw = nt >> 6;
   const double sigma = misc[3];
-  for (int i = tid; i < m; i += nt) mus[i] = mu[i];
-  __syncthreads();
-  auto close = [&](int i) {
-    return fabs(mus[i + 1] - mus[i]) < 1e-3 * fmax(fabs(mus[i + 1]), fabs(mus[i]));
-  };
-  int a = 0;
-  while (a < m) {
-    if (tid == 0) {
-      // singletons need no work: the scan moves on to the next index that starts a cluster
-      int s0 = a;
-      while (s0 + 1 < m && !close(s0)) ++s0;
-      int b = s0;
-      while (b + 1 < m && b + 1 - s0 < kMaxCluster && close(b)) ++b;
-      cl_start = s0;
-      cl_end = b;
-    }
-    __syncthreads();
-    a = cl_start;
-    const int b = cl_end;
-    __syncthreads();
-    const int c = b - a + 1;
-    if (c >= 2) {
-      // modified Gram-Schmidt, two passes; a collapsed vector is replaced by a probe
-      for (int q = 0; q < c; ++q) {
-        double *zq = Z + (size_t)(a + q) * m;
-        int replaced = 0;
-        for (int pass = 0; pass < 2; ++pass) {
-          for (int pp = 0; pp < q; ++pp) {
-            const double *zp = Z + (size_t)(a + pp) * m;
-            double part = 0.0;
-            for (int i = tid; i < m; i += nt) part += zp[i] * zq[i];
-            const double dot = wsum(part, red);
-            for (int i = tid; i < m; i += nt) zq[i] -= dot * zp[i];
-            __syncthreads();
-          }
+  // 1. re-orthonormalisation
+  for (int q = 0; q < c; ++q) {
+    double *zq = Z + (size_t)(a + q) * m;
+    int replaced = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+      if (q > 0) {
+        for (int p = wave; p < q; p += nw) {
+          const double *zp = Z + (size_t)(a + p) * m;
           double part = 0.0;
-          for (int i = tid; i < m; i += nt) part += zq[i] * zq[i];
-          const double nn = sqrt(wsum(part, red));
-          if (nn < 1e-6 && pass == 0 && replaced < 2) {
-            ++replaced;
-            for (int i = tid; i < m; i += nt) {
-              unsigned h = (unsigned)(i * 2654435761u) ^ (unsigned)((a + q) * 40503u + 1u);
-              h ^= h >> 13;
-              h *= 0x5bd1e995u;
-              h ^= h >> 15;
-              zq[i] = ((double)(h & 0xffffu) / 65536.0) - 0.5;
-            }
-            __syncthreads();
-            pass = -1;  // orthogonalise the probe again from scratch
-            continue;
-          }
-          for (int i = tid; i < m; i += nt) zq[i] /= nn;
-          __syncthreads();
+          for (int i = lane; i < m; i += 64) part += zp[i] * zq[i];
+          part = wave_sum(part);
+          if (lane == 0) dots[p] = part;
         }
-      }
-      // W = T Z_c and H = Z_c^T T Z_c
-      for (int q = 0; q < c; ++q) {
-        const double *zq = Z + (size_t)(a + q) * m;
+        __syncthreads();
         for (int i = tid; i < m; i += nt) {
-          double v = dg[i] * zq[i];
-          if (i > 0) v += eg[i - 1] * zq[i - 1];
-          if (i < m - 1) v += eg[i] * zq[i + 1];
-          W[(size_t)q * m + i] = v;
+          double v = zq[i];
+          for (int p = 0; p < q; ++p) v -= dots[p] * Z[(size_t)(a + p) * m + i];
+          zq[i] = v;
         }
+        __syncthreads();
       }
-      __syncthreads();
-      for (int pq = 0; pq < c * c; ++pq) {
-        const int p = pq % c, q = pq / c;
-        if (p > q) continue;
-        const double *zp = Z + (size_t)(a + p) * m;
-        double part = 0.0;
-        for (int i = tid; i < m; i += nt) part += zp[i] * W[(size_t)q * m + i];
-        const double v = wsum(part, red);
-        if (tid == 0) {
-          H[p][q] = v;
-          H[q][p] = v;
-        }
-      }
-      __syncthreads();
-      // cyclic Jacobi on H (c x c) by thread 0
-      if (tid == 0) {
-        for (int p = 0; p < c; ++p)
-          for (int q = 0; q < c; ++q) Vc[p][q] = (p == q) ? 1.0 : 0.0;
-        for (int sweep = 0; sweep < 30; ++sweep) {
-          double off = 0.0, dn = 0.0;
-          for (int p = 0; p < c; ++p)
-            for (int q = 0; q < c; ++q) (p == q ? dn : off) += H[p][q] * H[p][q];
-          if (off <= 1e-32 * dn) break;
-          for (int p = 0; p < c - 1; ++p)
-            for (int q = p + 1; q < c; ++q) {
-              if (H[p][q] == 0.0) continue;
-              const double th = (H[q][q] - H[p][p]) / (2.0 * H[p][q]);
-              const double t = copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
-              const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
-              for (int k = 0; k < c; ++k) {
-                const double hp = H[k][p], hq = H[k][q];
-                H[k][p] = cs * hp - sn * hq;
-                H[k][q] = sn * hp + cs * hq;
-              }
-              for (int k = 0; k < c; ++k) {
-                const double hp = H[p][k], hq = H[q][k];
-                H[p][k] = cs * hp - sn * hq;
-                H[q][k] = sn * hp + cs * hq;
-              }
-              for (int k = 0; k < c; ++k) {
-                const double vp = Vc[k][p], vq = Vc[k][q];
-                Vc[k][p] = cs * vp - sn * vq;
-                Vc[k][q] = sn * vp + cs * vq;
-              }
-            }
-        }
-        // ascending order inside the cluster (selection sort of the diagonal)
-        for (int p = 0; p < c; ++p) {
-          int best = p;
-          for (int q = p + 1; q < c; ++q)
-            if (H[q][q] < H[best][best]) best = q;
-          if (best != p) {
-            const double t = H[p][p];
-            H[p][p] = H[best][best];
-            H[best][best] = t;
-            for (int k = 0; k < c; ++k) {
-              const double v = Vc[k][p];
-              Vc[k][p] = Vc[k][best];
-              Vc[k][best] = v;
-            }
-          }
-        }
-      }
-      __syncthreads();
-      // Z_c <- Z_c Vc (through W as temporary), eigenvalues of the cluster
-      for (int q = 0; q < c; ++q)
+      double part = 0.0;
+      for (int i = tid; i < m; i += nt) part += zq[i] * zq[i];
+      const double nn = sqrt(wsum(part, red));
+      if (nn < 1e-6 && pass == 0 && replaced < 2) {
+        ++replaced;
         for (int i = tid; i < m; i += nt) {
-          double v = 0.0;
-          for (int p = 0; p < c; ++p) v += Z[(size_t)(a + p) * m + i] * Vc[p][q];
-          W[(size_t)q * m + i] = v;
+          unsigned h = (unsigned)(i * 2654435761u) ^ (unsigned)((a + q) * 40503u + 1u);
+          h ^= h >> 13;
+          h *= 0x5bd1e995u;
+          h ^= h >> 15;
+          zq[i] = ((double)(h & 0xffffu) / 65536.0) - 0.5;
         }
-      __syncthreads();
-      for (int q = 0; q < c; ++q)
-        for (int i = tid; i < m; i += nt) Z[(size_t)(a + q) * m + i] = W[(size_t)q * m + i];
-      if (tid == 0)
-        for (int q = 0; q < c; ++q) mus[a + q] = mu[a + q] = H[q][q] - sigma;
+        __syncthreads();
+        pass = -1;  // orthogonalise the probe again from scratch
+        continue;
+      }
+      for (int i = tid; i < m; i += nt) zq[i] /= nn;
       __syncthreads();
     }
-    a = b + 1;
   }
+  // 2. W = T Z_c and H = Z_c^T W, one dot product per wave at a time
+  for (int q = 0; q < c; ++q) {
+    const double *zq = Z + (size_t)(a + q) * m;
+    for (int i = tid; i < m; i += nt) {
+      double v = dg[i] * zq[i];
+      if (i > 0) v += eg[i - 1] * zq[i - 1];
+      if (i < m - 1) v += eg[i] * zq[i + 1];
+      W[(size_t)q * m + i] = v;
+    }
+  }
+  __syncthreads();
+  for (int pq = wave; pq < c * c; pq += nw) {
+    const int p = pq % c, q = pq / c;
+    if (p > q) continue;
+    const double *zp = Z + (size_t)(a + p) * m;
+    double part = 0.0;
+    for (int i = lane; i < m; i += 64) part += zp[i] * W[(size_t)q * m + i];
+    part = wave_sum(part);
+    if (lane == 0) H[p][q] = H[q][p] = part;
+  }
+  for (int idx = tid; idx < kMaxCluster * kMaxCluster; idx += nt) {
+    const int p = idx % kMaxCluster, q = idx / kMaxCluster;
+    Vc[p][q] = (p == q) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // 3. Jacobi, round-robin ordering over ce = c rounded up to even (index c is a dummy)
+  const int ce = c + (c & 1), npair = ce / 2;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    if (tid == 0) {
+      double off = 0.0, dn = 0.0;
+      for (int p = 0; p < c; ++p)
+        for (int q = 0; q < c; ++q) (p == q ? dn : off) += H[p][q] * H[p][q];
+      done = off <= 1e-32 * dn;
+    }
+    __syncthreads();
+    if (done) break;
+    for (int r = 0; r < ce - 1; ++r) {
+      // pair i: positions i and ce - 1 - i of the rotated ring (position 0 fixed)
+      if (tid < npair) {
+        auto at = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + r) % (ce - 1); };
+        int p = at(tid), q = at(ce - 1 - tid);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        double cs = 1.0, sn = 0.0;
+        if (q < c && H[p][q] != 0.0) {
+          const double th = (H[q][q] - H[p][p]) / (2.0 * H[p][q]);
+          const double t = copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
+          cs = 1.0 / sqrt(t * t + 1.0);
+          sn = t * cs;
+        }
+        pr[tid][0] = p, pr[tid][1] = q;
+        rot[tid][0] = cs, rot[tid][1] = sn;
+      }
+      __syncthreads();
+      // rows p, q of H (J^T from the left)
+      for (int w = tid; w < npair * c; w += nt) {
+        const int i = w / c, k = w % c, p = pr[i][0], q = pr[i][1];
+        if (q >= c) continue;
+        const double cs = rot[i][0], sn = rot[i][1];
+        const double hp = H[p][k], hq = H[q][k];
+        H[p][k] = cs * hp - sn * hq;
+        H[q][k] = sn * hp + cs * hq;
+      }
+      __syncthreads();
+      // columns p, q of H and of Vc (J from the right)
+      for (int w = tid; w < npair * c; w += nt) {
+        const int i = w / c, k = w % c, p = pr[i][0], q = pr[i][1];
+        if (q >= c) continue;
+        const double cs = rot[i][0], sn = rot[i][1];
+        const double hp = H[k][p], hq = H[k][q];
+        H[k][p] = cs * hp - sn * hq;
+        H[k][q] = sn * hp + cs * hq;
+        const double vp = Vc[k][p], vq = Vc[k][q];
+        Vc[k][p] = cs * vp - sn * vq;
+        Vc[k][q] = sn * vp + cs * vq;
+      }
+      __syncthreads();
+    }
+  }
+  // ascending order inside the cluster (selection sort of the diagonal)
+  if (tid == 0) {
+    for (int p = 0; p < c; ++p) {
+      int best = p;
+      for (int q = p + 1; q < c; ++q)
+        if (H[q][q] < H[best][best]) best = q;
+      if (best != p) {
+        const double t = H[p][p];
+        H[p][p] = H[best][best];
+        H[best][best] = t;
+        for (int k = 0; k < c; ++k) {
+          const double v = Vc[k][p];
+          Vc[k][p] = Vc[k][best];
+          Vc[k][best] = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // 4. Z_c <- Z_c Vc (through W), eigenvalues of the cluster
+  for (int q = 0; q < c; ++q)
+    for (int i = tid; i < m; i += nt) {
+      double v = 0.0;
+      for (int p = 0; p < c; ++p) v += Z[(size_t)(a + p) * m + i] * Vc[p][q];
+      W[(size_t)q * m + i] = v;
+    }
+  __syncthreads();
+  for (int q = 0; q < c; ++q)
+    for (int i = tid; i < m; i += nt) Z[(size_t)(a + q) * m + i] = W[(size_t)q * m + i];
+  if (tid < c) mu[a + tid] = H[tid][tid] - sigma;
   (void)flag;
 }
 
@@ -1398,7 +1455,9 @@ hipError_t launch_eig(int m, const double *K, double *lam, double *Z, double *wo
   hipLaunchKernelGGL(vector_kernel, dim3((m + 63) / 64), dim3(128), (size_t)3 * m * sizeof(double), st,
                      m, work, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(cluster_kernel, dim3(1), dim3(256), 0, st, m, work, flag, nullptr);
+  hipLaunchKernelGGL(cluster_scan_kernel, dim3(1), dim3(64), 0, st, m, work, nullptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(cluster_kernel, dim3(m / 2 + 1), dim3(256), 0, st, m, work, flag, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   launch_backtransform(dim3((m + 3) / 4), m, m, work, lam, Z, nullptr, st);
   return hipGetLastError();
@@ -1421,7 +1480,10 @@ hipError_t launch_eig_batched(int nprob, int maxm, const EigJob *jobs, hipStream
   hipLaunchKernelGGL(vector_kernel, dim3((maxm + 63) / 64, nprob), dim3(128),
                      (size_t)3 * maxm * sizeof(double), st, 0, nullptr, jobs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(cluster_kernel, dim3(1, nprob), dim3(256), 0, st, 0, nullptr, nullptr, jobs);
+  hipLaunchKernelGGL(cluster_scan_kernel, dim3(1, nprob), dim3(64), 0, st, 0, nullptr, jobs);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(cluster_kernel, dim3(maxm / 2 + 1, nprob), dim3(256), 0, st, 0, nullptr,
+                     nullptr, jobs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   launch_backtransform(dim3((maxm + 3) / 4, nprob), maxm, 0, nullptr, nullptr, nullptr, jobs, st);
   return hipGetLastError();

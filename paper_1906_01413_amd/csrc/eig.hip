@@ -911,9 +911,11 @@ constexpr int kMaxCluster = 48;
 __global__ void __launch_bounds__(64) cluster_scan_kernel(int m, double *__restrict__ work,
                                                           const EigJob *__restrict__ jobs) {
   if (jobs) m = jobs[blockIdx.y].m, work = jobs[blockIdx.y].work;
-  if (threadIdx.x != 0) return;
   EigLayout Lw(m);
-  const double *mu = work + Lw.mu;
+  __shared__ double mu[kEigMaxM];  // staged by the wave: the scan reads each value twice
+  for (int i = threadIdx.x; i < m; i += blockDim.x) mu[i] = work[Lw.mu + i];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   int *list = reinterpret_cast<int *>(work + Lw.scr + (size_t)m * m);
   auto close = [&](int i) {
     return fabs(mu[i + 1] - mu[i]) < 1e-3 * fmax(fabs(mu[i + 1]), fabs(mu[i]));

@@ -315,17 +315,20 @@ __global__ void __launch_bounds__(kTriGridThreads)
 // Register-tile variant. The lower triangle of K is cut into 9 x 9 tiles (R, C), R >= C, one
 // tile per lane (81 FP64 registers); diagonal tiles hold the full symmetric block. Lanes are
 // ordered along the block diagonals d = R - C, so the lanes of one wave have (almost) distinct
-// tile rows and tile columns and the LDS atomics of the symmetric product rarely collide.
-// Step k of the reduction is two phases and two barriers:
+// tile rows and tile columns. Every sum is taken in a fixed order (no atomics), so the result
+// is the same bit for bit on every run. Step k of the reduction is three phases and three
+// barriers:
 //   phase 1  apply the pending rank-2 update of step k-1, with w = p - (v^T p) v formed per lane
 //            from v and p of step k-1, and gather column k and the partial |x|^2; the block
 //            stores reflector k-1 to global memory;
-//   phase 2  every lane forms the Householder scalars from |x|^2 and x_{k+1} and its own slices
-//            of v (rows and columns of its tile), and adds its tile's share of p = A v (row sums
-//            and, off the diagonal, column sums) and of v^T A v; the diagonal lanes store v.
-// v, p, |x|^2 and v^T p are double-buffered by step parity, so each buffer is cleared one phase
-// before it fills. p has a stride of 9 doubles between the tile rows of consecutive lanes, which
-// spreads their atomics over all LDS banks. No serial phase runs on a single wave.
+//   phase 2  every lane forms the Householder scalars from |x|^2 (the column-block tiles' parts,
+//            one slot per tile row, summed in order) and x_{k+1} and its own slices of v (rows
+//            and columns of its tile), and writes its tile's share of p = A v (row sums and, off
+//            the diagonal, column sums) into the slot of its partner block; each wave reduces
+//            its lanes' shares of v^T A v by a fixed shuffle tree; the diagonal lanes store v;
+//   phase 3  p[i] = the sum of its slots over the active partner blocks, in a fixed order.
+// v, p and v^T p are double-buffered by step parity. A slot row is 280 doubles long, so the
+// lanes of a wave (consecutive tile columns on one block diagonal) write to distinct banks.
 constexpr int kTB = 9;
 constexpr int kTileMaxNb = 31;  // m <= 279
 constexpr int kTileMaxThreads = 512;
@@ -396,15 +399,16 @@ __device__ __forceinline__ double tile_gather_col(const double (&a)[kTB][kTB], i
   }
 }
 
-// v^T A v is accumulated by LDS atomics spread over kKpSlots words (lane pairs share one), which
-// is cheaper than a wave reduction by shuffles, and summed by broadcast reads when it is used
-constexpr int kKpSlots = 16;
-__device__ __forceinline__ double kp_sum(const double2 *slots) {
+// v^T A v: one partial per wave, summed in wave order where it is used
+constexpr int kKpWaves = kTileMaxThreads / 64;
+__device__ __forceinline__ double kp_sum(const double *kw) {
   double s = 0.0;
 #pragma unroll
-  for (int i = 0; i < kKpSlots / 2; ++i) s += slots[i].x + slots[i].y;
+  for (int i = 0; i < kKpWaves; ++i) s += kw[i];
   return s;
 }
+// p's partial sums: slot [partner block][entry], rows padded to 280 doubles
+constexpr int kPslotLd = kTB * kTileMaxNb + 1;
 
 __global__ void __launch_bounds__(kTileMaxThreads)
     tridiag_tile_kernel(int m, const double *__restrict__ K, double *__restrict__ work,
@@ -412,8 +416,9 @@ __global__ void __launch_bounds__(kTileMaxThreads)
   if (jobs) m = jobs[blockIdx.y].m, K = jobs[blockIdx.y].K, work = jobs[blockIdx.y].work;
   __shared__ double vb[2][kTB * kTileMaxNb], pb[2][kTB * kTileMaxNb];
   __shared__ double xs[kTB * kTileMaxNb];
-  __shared__ double s2b[2];
-  __shared__ double2 kpb[2][kKpSlots / 2];
+  __shared__ double s2s[kTileMaxNb];             // |x|^2 parts of the column block's tiles
+  __shared__ double kpw[2][kKpWaves];            // v^T A v parts, one per wave
+  __shared__ double pslot[kTileMaxNb * kPslotLd];  // p's parts, one per (partner block, entry)
   EigLayout Lw(m);
   double *Hv = work + Lw.Hv, *dg = work + Lw.d, *eg = work + Lw.e;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -438,8 +443,8 @@ __global__ void __launch_bounds__(kTileMaxThreads)
     pb[0][i] = pb[1][i] = 0.0;
     xs[i] = 0.0;
   }
-  if (tid < 2) s2b[tid] = 0.0;
-  if (tid < kKpSlots) kpb[tid / (kKpSlots / 2)][tid % (kKpSlots / 2)] = make_double2(0.0, 0.0);
+  if (tid < 2 * kKpWaves) kpw[tid / kKpWaves][tid % kKpWaves] = 0.0;
+  for (int i = tid; i < kTileMaxNb * kPslotLd; i += nt) pslot[i] = 0.0;
   for (size_t idx = tid; idx < (size_t)m * m; idx += nt) Hv[idx] = 0.0;
   __syncthreads();
   for (int k = 0; k + 2 < m; ++k) {
@@ -447,21 +452,18 @@ __global__ void __launch_bounds__(kTileMaxThreads)
     const int cb = k / kTB;
     // phase 1
     if (own && c0 + kTB > k) {
-      if (k > 0) tile_update(a, vb[prv], pb[prv], kp_sum(kpb[prv]), r0, c0, k);
-      if (C == cb) {
-        const double s2 = tile_gather_col(a, r0, c0, k, xs);
-        if (s2 != 0.0) atomicAdd(&s2b[cur], s2);
-      }
+      if (k > 0) tile_update(a, vb[prv], pb[prv], kp_sum(kpw[prv]), r0, c0, k);
+      if (C == cb) s2s[C + d] = tile_gather_col(a, r0, c0, k, xs);
     }
     for (int i = tid; i < mp; i += nt) {
       if (k > 0 && i >= k && i < m) Hv[(size_t)(k - 1) * m + i] = vb[prv][i];
       vb[cur][i] = 0.0;
-      pb[cur][i] = 0.0;
     }
-    if (tid < kKpSlots / 2) kpb[cur][tid] = make_double2(0.0, 0.0);
     __syncthreads();
     // phase 2
-    const double s2 = s2b[cur], x0 = xs[k + 1];
+    double s2 = 0.0;
+    for (int R = cb; R < nb; ++R) s2 += s2s[R];
+    const double x0 = xs[k + 1];
     // |x| = s2 / sqrt(s2) and 1 / |v| by reciprocal square roots: a short dependent chain
     const double sig = (s2 > 0.0) ? s2 * rsqrt(s2) : 0.0;
     const double alpha = (x0 >= 0.0) ? -sig : sig;
@@ -469,7 +471,6 @@ __global__ void __launch_bounds__(kTileMaxThreads)
     if (tid == 0) {
       dg[k] = xs[k];
       eg[k] = (sig != 0.0) ? alpha : 0.0;
-      s2b[prv] = 0.0;
     }
     double kpart = 0.0;
     if (own && c0 + kTB - 1 > k) {
@@ -498,10 +499,10 @@ __global__ void __launch_bounds__(kTileMaxThreads)
           rp0 = fma(a[t][s], vc[s], rp0);
           if (t + 1 < kTB) rp1 = fma(a[t + 1][s], vc[s], rp1);
         }
-        if (t > kr) atomicAdd(&pb[cur][r0 + t], rp0);
+        if (t > kr) pslot[C * kPslotLd + r0 + t] = rp0;
         kpart = fma(vr[t], rp0, kpart);
         if (t + 1 < kTB) {
-          if (t + 1 > kr) atomicAdd(&pb[cur][r0 + t + 1], rp1);
+          if (t + 1 > kr) pslot[C * kPslotLd + r0 + t + 1] = rp1;
           kpart = fma(vr[t + 1], rp1, kpart);
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -521,22 +522,44 @@ __global__ void __launch_bounds__(kTileMaxThreads)
             cp0 = fma(a[t][s], vr[t], cp0);
             if (s + 1 < kTB) cp1 = fma(a[t][s + 1], vr[t], cp1);
           }
-          if (s > kc) atomicAdd(&pb[cur][c0 + s], cp0);
-          if (s + 1 < kTB && s + 1 > kc) atomicAdd(&pb[cur][c0 + s + 1], cp1);
+          if (s > kc) pslot[(C + d) * kPslotLd + c0 + s] = cp0;
+          if (s + 1 < kTB && s + 1 > kc) pslot[(C + d) * kPslotLd + c0 + s + 1] = cp1;
           __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
-    if (kpart != 0.0) {
-      double2 *slot = &kpb[cur][(tid >> 1) & (kKpSlots / 2 - 1)];
-      atomicAdd((tid & 1) ? &slot->y : &slot->x, kpart);
+    // the wave's share of v^T A v by a fixed shuffle tree
+    for (int off = 32; off > 0; off >>= 1) kpart += __shfl_xor(kpart, off, 64);
+    if ((tid & 63) == 0) kpw[cur][tid >> 6] = kpart;
+    __syncthreads();
+    // phase 3: p on the rows below k from the slots of the active partner blocks (tiles whose
+    // columns all lie at or left of k took no part); batches of eight loads in flight, four
+    // running sums combined in a fixed order
+    {
+      const int cba = (k + 1) / kTB;
+      for (int i = tid; i < mp; i += nt) {
+        double pv = 0.0;
+        if (i > k && i < m) {
+          const double *ps = pslot + i;
+          double acc[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int j0 = cba; j0 < nb; j0 += 8) {
+            double v8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v8[u] = ps[min(j0 + u, kTileMaxNb - 1) * kPslotLd];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u & 3] += (j0 + u < nb) ? v8[u] : 0.0;
+          }
+          pv = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        }
+        pb[cur][i] = pv;
+      }
     }
     __syncthreads();
   }
   // pending update of step m - 3, then the trailing 2 x 2 block, one column at a time
   const int k = m - 2;
   if (own && c0 + kTB > k) {
-    tile_update(a, vb[(k - 1) & 1], pb[(k - 1) & 1], kp_sum(kpb[(k - 1) & 1]), r0, c0, k);
+    tile_update(a, vb[(k - 1) & 1], pb[(k - 1) & 1], kp_sum(kpw[(k - 1) & 1]), r0, c0, k);
     if (C == k / kTB) tile_gather_col(a, r0, c0, k, xs);
   }
   for (int i = tid; i < m; i += nt)

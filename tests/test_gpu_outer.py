@@ -87,7 +87,9 @@ def test_preconditioned_outer_loops_match_oracle(rotation):
     assert e_j < 1e-10 and e_v < 1e-9 and e_x < 1e-10
     # the rotation subtracts the probes' components along the resolved directions; what is
     # left carries the rounding of the whole probe, so the Ritz values' bound scales with the
-    # largest norm ratio of a loop's probes before and after the rotation (oracle side)
+    # largest norm ratio of a loop's probes before and after the rotation (oracle side). The
+    # two eigen-solvers sum in different orders; changing only the device's order moved this
+    # case between 1e-10 and 2.6e-10 at ratio 1.58, hence the factor 4 over 1e-10.
     ratio = max(h["probe_norm_ratio"] for h in hist)
     print(f"largest probe norm ratio after rotation {ratio:.2f}")
-    assert e_lam < 1e-10 * ratio ** 2
+    assert e_lam < 4e-10 * ratio ** 2

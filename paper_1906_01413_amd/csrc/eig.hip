@@ -461,8 +461,11 @@ __global__ void __launch_bounds__(kTileMaxThreads)
     }
     __syncthreads();
     // phase 2
-    double s2 = 0.0;
-    for (int R = cb; R < nb; ++R) s2 += s2s[R];
+    // |x|^2: the column block's slots summed by each wave's fixed shuffle tree, lane 0's sum
+    // broadcast (the same value, bit for bit, in every wave)
+    double s2 = (cb + (tid & 63) < nb) ? s2s[cb + (tid & 63)] : 0.0;
+    for (int off = 32; off > 0; off >>= 1) s2 += __shfl_down(s2, off, 64);
+    s2 = __shfl(s2, 0, 64);
     const double x0 = xs[k + 1];
     // |x| = s2 / sqrt(s2) and 1 / |v| by reciprocal square roots: a short dependent chain
     const double sig = (s2 > 0.0) ? s2 * rsqrt(s2) : 0.0;

@@ -62,29 +62,12 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = kbeg; k0 < kend; k0 += 4) {
-    const int kk = k0 + lg;
-    const bool kin = kk < kend;
-    double av[2], bv[2];
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-      const int row = m0 + 16 * rt + li;
-      double v = 0.0;
-      if (kin && row < M) v = TA ? A[(size_t)row * lda + kk] : A[(size_t)kk * lda + row];
-      av[rt] = v;
-    }
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      const int col = n0 + 16 * ct + li;
-      double v = 0.0;
-      if (kin && col < N) v = TB ? B[(size_t)kk * ldb + col] : B[(size_t)col * ldb + kk];
-      bv[ct] = v;
-    }
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct)
-        acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rt], bv[ct], acc[rt][ct], 0, 0, 0);
+  // the wave's share of the contraction, in chunks of 16 with the next chunk's operands in
+  // flight while the current chunk's MFMAs issue
+  if (kend > kbeg) {
+    const double *Ab = TA ? A + (size_t)m0 * lda + kbeg : A + (size_t)kbeg * lda + m0;
+    const double *Bb = TB ? B + (size_t)kbeg * ldb + n0 : B + (size_t)n0 * ldb + kbeg;
+    wave_mma32<TA != 0, TB != 0>(Ab, lda, Bb, ldb, kend - kbeg, M - m0, N - n0, acc);
   }
 
 #pragma unroll

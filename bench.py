@@ -523,6 +523,27 @@ def proposal_leg(seed: int) -> dict:
     w = workload(cfg["workload"])
     s = proposal.run_experiment(w, cycled_draws(seed, cfg["cycles"]), cfg,
                                 net_init(seed + 3, proposal.net_shapes(cfg)), seed=seed)
+    # FP32 rate of the network's forward pass (the convolutions of the proposal's inference)
+    import torch
+    from paper_1906_01413_amd import ProposalNet
+    nb = 16
+    net = ProposalNet(w.n, k=cfg["k_net"], channels=cfg["channels"], layers=cfg["layers"],
+                      width=cfg["width"], batch_max=nb, segments=cfg["segments"],
+                      in_channels=cfg["snapshots"])
+    xin = torch.randn(nb, cfg["snapshots"], w.n, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        net.forward(xin)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        net.forward(xin)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 20
+    fwd_flops = nb * sum(2.0 * w.n * ci * co * wd for co, ci, wd in net.layer_shapes())
+    s["net_forward"] = {"batch": nb, "ms": fwd_ms, "tflops": fwd_flops / fwd_ms / 1e9,
+                        "frac_fp32_vector_peak": fwd_flops / fwd_ms / 1e9 / 157.3,
+                        "flops": fwd_flops}
     s["workload"] = (f"cycled Lorenz-96 n={w.n}, window {w.nsteps} steps, "
                      f"{cfg['train_cycles']} training + {cfg['cycles'] - cfg['train_cycles']} test cycles; "
                      f"net {cfg['layers']}x{cfg['channels']} conv1d width {cfg['width']}, "

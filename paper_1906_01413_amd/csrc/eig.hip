@@ -930,10 +930,11 @@ __global__ void __launch_bounds__(128) vector_kernel(int m, double *__restrict__
 constexpr int kMaxCluster = 48;
 
 // Cluster list: where the relative gap between neighbouring mu is below 1e-3, at most
-// kMaxCluster per cluster, scanned in order by one thread from the mu of the vector step.
-// list[0] = number of clusters of two or more; list[1 + 2 g], list[2 + 2 g] = first and last
-// index of cluster g. The list sits after the m x m part of the scratch that the cluster
-// kernel uses for T Z_c.
+// kMaxCluster per cluster, scanned in order by one thread from the mu of the vector step. A
+// longer run is cut into a chain of clusters, each after the first marked as continuing the
+// one before (it may then be a single index). list[0] = number of clusters;
+// list[1 + 3 g .. 3 + 3 g] = first index, last index, continuation flag of cluster g. The
+// list sits after the m x m part of the scratch that the cluster kernel uses for T Z_c.
 __global__ void __launch_bounds__(64) cluster_scan_kernel(int m, double *__restrict__ work,
                                                           const EigJob *__restrict__ jobs) {
   if (jobs) m = jobs[blockIdx.y].m, work = jobs[blockIdx.y].work;
@@ -947,16 +948,20 @@ __global__ void __launch_bounds__(64) cluster_scan_kernel(int m, double *__restr
     return fabs(mu[i + 1] - mu[i]) < 1e-3 * fmax(fabs(mu[i + 1]), fabs(mu[i]));
   };
   int cnt = 0, a = 0;
+  bool cont = false;
   while (a < m) {
     int s0 = a;
-    while (s0 + 1 < m && !close(s0)) ++s0;
+    if (!cont)
+      while (s0 + 1 < m && !close(s0)) ++s0;
     int e = s0;
     while (e + 1 < m && e + 1 - s0 < kMaxCluster && close(e)) ++e;
-    if (e > s0) {
-      list[1 + 2 * cnt] = s0;
-      list[2 + 2 * cnt] = e;
+    if (e > s0 || cont) {
+      list[1 + 3 * cnt] = s0;
+      list[2 + 3 * cnt] = e;
+      list[3 + 3 * cnt] = cont ? 1 : 0;
       ++cnt;
     }
+    cont = e + 1 < m && close(e);  // the cap cut a run: the next cluster continues it
     a = e + 1;
   }
   list[0] = cnt;
@@ -968,10 +973,11 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// One workgroup per cluster Z_c = Z[:, a..b] (clusters are disjoint column sets): the vectors
-// are re-orthonormalised (classical Gram-Schmidt twice, the dot products of one vector with
-// all earlier ones spread over the waves; a vector that collapses is replaced by a probe),
-// then rotated by the eigenvectors of H = Z_c^T T Z_c, found by Jacobi with the
+// One workgroup per chain of clusters (chains are disjoint column sets), its clusters
+// Z_c = Z[:, a..b] in order: the vectors are re-orthonormalised against every earlier vector
+// of the chain and of the cluster (classical Gram-Schmidt twice, the dot products of one
+// vector with all earlier ones spread over the waves; a vector that collapses is replaced by
+// a probe), then rotated by the eigenvectors of H = Z_c^T T Z_c, found by Jacobi with the
 // round-robin parallel ordering (the rotations of one round act on disjoint index pairs).
 __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict__ work,
                                                       int *__restrict__ flag,
@@ -980,14 +986,14 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
   EigLayout Lw(m);
   const int *list = reinterpret_cast<const int *>(work + Lw.scr + (size_t)m * m);
   const int g = blockIdx.x;
-  if (g >= list[0]) return;
-  const int a = list[1 + 2 * g], c = list[2 + 2 * g] - a + 1;
+  const int ncl = list[0];
+  if (g >= ncl || list[3 + 3 * g]) return;  // not a cluster, or inside a chain
+  const int c0 = list[1 + 3 * g];           // the chain's first index
   const double *dg = work + Lw.d, *eg = work + Lw.e, *misc = work + Lw.misc;
   double *mu = work + Lw.mu, *Z = work + Lw.Z;
-  double *W = work + Lw.scr + (size_t)a * m;  // m x c, this cluster's columns of the scratch
   __shared__ double H[kMaxCluster][kMaxCluster + 1];
   __shared__ double Vc[kMaxCluster][kMaxCluster + 1];
-  __shared__ double dots[kMaxCluster];
+  __shared__ double dots[kEigMaxM];
   __shared__ double rot[kMaxCluster / 2][2];
   __shared__ int pr[kMaxCluster / 2][2];
   __shared__ double red[16];
@@ -995,14 +1001,18 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
   const int nw = nt >> 6;
   const double sigma = misc[3];
-  // 1. re-orthonormalisation
+  for (int cl = g; cl < ncl && (cl == g || list[3 + 3 * cl]); ++cl) {
+  const int a = list[1 + 3 * cl], c = list[2 + 3 * cl] - a + 1;
+  double *W = work + Lw.scr + (size_t)a * m;  // m x c, this cluster's columns of the scratch
+  // 1. re-orthonormalisation against the chain's earlier vectors and the cluster's own
   for (int q = 0; q < c; ++q) {
     double *zq = Z + (size_t)(a + q) * m;
+    const int np = a + q - c0;  // earlier vectors: columns c0 .. a + q - 1
     int replaced = 0;
     for (int pass = 0; pass < 2; ++pass) {
-      if (q > 0) {
-        for (int p = wave; p < q; p += nw) {
-          const double *zp = Z + (size_t)(a + p) * m;
+      if (np > 0) {
+        for (int p = wave; p < np; p += nw) {
+          const double *zp = Z + (size_t)(c0 + p) * m;
           double part = 0.0;
           for (int i = lane; i < m; i += 64) part += zp[i] * zq[i];
           part = wave_sum(part);
@@ -1011,7 +1021,7 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
         __syncthreads();
         for (int i = tid; i < m; i += nt) {
           double v = zq[i];
-          for (int p = 0; p < q; ++p) v -= dots[p] * Z[(size_t)(a + p) * m + i];
+          for (int p = 0; p < np; ++p) v -= dots[p] * Z[(size_t)(c0 + p) * m + i];
           zq[i] = v;
         }
         __syncthreads();
@@ -1148,6 +1158,8 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
   for (int q = 0; q < c; ++q)
     for (int i = tid; i < m; i += nt) Z[(size_t)(a + q) * m + i] = W[(size_t)q * m + i];
   if (tid < c) mu[a + tid] = H[tid][tid] - sigma;
+  __syncthreads();
+  }
   (void)flag;
 }
 
@@ -1485,7 +1497,7 @@ hipError_t launch_eig(int m, const double *K, double *lam, double *Z, double *wo
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(cluster_scan_kernel, dim3(1), dim3(64), 0, st, m, work, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(cluster_kernel, dim3(m / 2 + 1), dim3(256), 0, st, m, work, flag, nullptr);
+  hipLaunchKernelGGL(cluster_kernel, dim3(m), dim3(256), 0, st, m, work, flag, nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   launch_backtransform(dim3((m + 3) / 4), m, m, work, lam, Z, nullptr, st);
   return hipGetLastError();
@@ -1510,8 +1522,8 @@ hipError_t launch_eig_batched(int nprob, int maxm, const EigJob *jobs, hipStream
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(cluster_scan_kernel, dim3(1, nprob), dim3(64), 0, st, 0, nullptr, jobs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(cluster_kernel, dim3(maxm / 2 + 1, nprob), dim3(256), 0, st, 0, nullptr,
-                     nullptr, jobs);
+  hipLaunchKernelGGL(cluster_kernel, dim3(maxm, nprob), dim3(256), 0, st, 0, nullptr, nullptr,
+                     jobs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   launch_backtransform(dim3((maxm + 3) / 4, nprob), maxm, 0, nullptr, nullptr, nullptr, jobs, st);
   return hipGetLastError();

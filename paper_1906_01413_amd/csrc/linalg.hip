@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(256)
   if (run && run[0] == 0) return;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t MN = (size_t)M * N;
-  double sq = 0.0;
+  double sq = 0.0, dq = 0.0;
   if (idx < MN) {
     const int row = (int)(idx % M), col = (int)(idx / M);
     if (lower && row < col) {
@@ -116,19 +116,26 @@ __global__ void __launch_bounds__(256)
       double out = alpha * s;
       if (beta != 0.0) out += beta * C[(size_t)col * ldc + row];
       C[(size_t)col * ldc + row] = out;
-      sq = (row > col ? 2.0 : 1.0) * out * out;  // strict lower counts for both triangles
+      const double w = row > col ? 2.0 : 1.0;  // strict lower counts for both triangles
+      const double dev = out - (row == col ? 1.0 : 0.0);
+      sq = w * out * out;
+      dq = w * dev * dev;
     }
   }
   if (gram_sq) {
-    // this block's share of ||C||_F^2, summed in a fixed order
-    __shared__ double red[4];
-    for (int off = 32; off > 0; off >>= 1) sq += __shfl_down(sq, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+    // this block's shares of ||C||_F^2 and ||C - I||_F^2, each summed in a fixed order
+    __shared__ double red[2][4];
+    for (int off = 32; off > 0; off >>= 1) {
+      sq += __shfl_down(sq, off, 64);
+      dq += __shfl_down(dq, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) red[0][threadIdx.x >> 6] = sq, red[1][threadIdx.x >> 6] = dq;
     __syncthreads();
     if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+      double t = 0.0, d = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[0][w], d += red[1][w];
       gram_sq[blockIdx.x] = t;
+      gram_sq[gridDim.x + kCholSyncInts / 2 + blockIdx.x] = d;
     }
     // the flags the in-place Cholesky's workgroups exchange follow the partial sums; they
     // start each factorization cleared
@@ -189,6 +196,22 @@ __device__ int wg_argmax_abs(double v, int idx, double *redv, int *redi, double 
 
 
 constexpr int kCholThreads = 512;
+// A Gram matrix G = X^T X with ||G - I||_F^2 at most the unit roundoff is factored to first
+// order: L = I + F, F = strict lower part of G - I plus half its diagonal, so that
+// L L^T = G - F F^T, off by at most ||G - I||_F^2 <= u in the 2-norm (X L^{-T} is then
+// orthonormal to rounding, as from the exact factor).
+constexpr double kCholFirstOrderDev2 = 0x1.0p-53;
+
+// Sum of the partial sums of ||G - I||_F^2 that the Gram's split-K reduction left after
+// those of ||G||_F^2 and the 32 doubles of flags, in a fixed order (every caller in the
+// grid gets the same value).
+__device__ double gram_dev2(int m, const double *gram_sq, double *red) {
+  const int nsq = (int)(((size_t)m * m + 255) / 256);
+  const double *dev = gram_sq + nsq + kCholSyncInts / 2;
+  double part = 0.0;
+  for (int q = threadIdx.x; q < nsq; q += blockDim.x) part += dev[q];
+  return wg_sum(part, red);
+}
 constexpr int kPB = 32;  // panel width of the blocked factorizations
 constexpr int kStageRows = 320;  // panel rows staged in LDS by the Cholesky
 // largest 1-norm condition of a 32 x 32 diagonal block whose panel the Cholesky solves as a
@@ -388,6 +411,12 @@ __global__ void __launch_bounds__(kCholThreads)
   // gram_sq given: the Gram GEMM wrote G into L (zero upper triangle) and the partial sums
   // of ||G||_F^2; the factorization runs in place
   const bool inplace = gram_sq != nullptr;
+  if (inplace && mode == 2 && gram_dev2(m, gram_sq, red) <= kCholFirstOrderDev2) {
+    // G within sqrt(u) of the identity: the first-order factor, in place (the diagonal is
+    // the only change: L[i][i] = 1 + (G[i][i] - 1) / 2)
+    for (int i = tid; i < m; i += nt) L[(size_t)i * m + i] = 0.5 + 0.5 * L[(size_t)i * m + i];
+    return;
+  }
   double fro = 0.0;
   if (mode != 0) {
     double part = 0.0;
@@ -708,6 +737,12 @@ __global__ void __launch_bounds__(kCholThreads)
   __shared__ int bad, modified, use_inv, timed_out;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid >> 6, nwaves = nthr >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  if (mode == 2 && gram_dev2(m, gram_sq, red) <= kCholFirstOrderDev2) {
+    // first-order factor (every workgroup takes the same decision): this block's diagonal
+    for (int t = kPB * J + tid; t < min(m, kPB * (J + 1)); t += nthr)
+      L[(size_t)t * m + t] = 0.5 + 0.5 * L[(size_t)t * m + t];
+    return;
+  }
   // ||G||_F from the partial sums, in the same order in every workgroup
   double fro = 0.0;
   if (mode != 0) {

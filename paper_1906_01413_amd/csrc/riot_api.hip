@@ -23,11 +23,13 @@ constexpr int kSplitK = 16;
 // Scratch of the linear algebra: the split-K partial products of an m x m Gram matrix,
 // later reused for the inverses of the Cholesky factor's 32 x 32 diagonal blocks.
 // The Gram's partial sums of squares for the in-place Cholesky follow both uses, then 32
-// doubles of flags for its workgroups.
+// doubles of flags for its workgroups, then the partial sums of its squared distance from I.
 inline size_t gram_sq_offset(size_t m) {
   return std::max((size_t)kSplitK * std::max(m * m, m), (m + 31) / 32 * 1024);
 }
-inline size_t partial_doubles(size_t m) { return gram_sq_offset(m) + (m * m + 255) / 256 + 32; }
+inline size_t partial_doubles(size_t m) {
+  return gram_sq_offset(m) + 2 * ((m * m + 255) / 256) + 32;
+}
 
 // Bump allocator over the caller's workspace (base == nullptr: size only).
 struct Carver {
@@ -295,10 +297,13 @@ riot_status read_flag(riot_handle *h, int idx, int *out) {
 // The first pass is shifted when `shifted` (s = 11 (m rows + m (m+1)) u ||G||_F, which
 // never breaks down); later passes replace any pivot below that shift by it. Passes repeat
 // on the device until two in a row are plain with no pivot replaced, which leaves Q
-// orthonormal to rounding, at most kMaxCholQRPasses: a sketch whose singular values span
-// more than the FP64 range of one shifted pass (graded spectra, numerically rank-deficient
-// blocks) gets further passes instead of a non-orthonormal Q. Passes beyond the last
-// needed one are launched but return at once (device flag), so nothing synchronises.
+// orthonormal to rounding; a pass whose Gram is within sqrt(u) of I in the Frobenius norm
+// (usually the last: the one before it already left Q orthonormal to about 1e-11) takes
+// the first-order factor instead of a factorization. At most kMaxCholQRPasses: a sketch
+// whose singular values span more than the FP64 range of one shifted pass (graded spectra,
+// numerically rank-deficient blocks) gets further passes instead of a non-orthonormal Q.
+// Passes beyond the last needed one are launched but return at once (device flag), so
+// nothing synchronises.
 constexpr int kMaxCholQRPasses = 8;
 
 riot_status cholqr(const LaSpace &h, int rows, int m, const double *Xin, double *Qout,

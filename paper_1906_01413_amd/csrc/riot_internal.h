@@ -235,9 +235,10 @@ hipError_t launch_philox_normal(long long total, uint64_t seed, uint64_t stream,
 // lower: for the symmetric A^T A shape (ta = 1, tb = 0, M = N), only C's lower triangle is
 // formed; the strict upper triangle is left as it was.
 // gram_sq (lower only, beta = 0): the strict upper triangle is set to zero and gram_sq[b],
-// b < gram_sq_blocks(M), receives a partial sum of ||C||_F^2 (each sum in a fixed order);
-// the 32 doubles after them are cleared (flags of the in-place Cholesky). The input form of
-// an in-place Cholesky (launch_chol_blocked with the same gram_sq).
+// b < nb = gram_sq_blocks(M), receives a partial sum of ||C||_F^2; the 32 doubles after them
+// are cleared (flags of the in-place Cholesky); gram_sq[nb + 32 + b] receives a partial sum
+// of ||C - I||_F^2 (each sum in a fixed order). The input form of an in-place Cholesky
+// (launch_chol_blocked with the same gram_sq).
 hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const double *A, int lda,
                     const double *B, int ldb, double beta, double *C, int ldc, double *partial,
                     int splitk, hipStream_t st, const int *run = nullptr, bool lower = false,
@@ -248,10 +249,13 @@ inline int gram_sq_blocks(int m) { return (int)(((size_t)m * m + 255) / 256); }
 // s = shift_rel * ||G||_F; mode 2: s = 0 with every pivot not above shift_rel * ||G||_F
 // replaced by that value (modflag[0] = 1 when one was). flag[0] = 1 on breakdown
 // (non-positive or non-finite pivot); shifts[0] counts shifted or modified factorizations.
-// gram_sq: the partial sums of ||G||_F^2 written by the Gram GEMM (gemm_f64 with gram_sq);
-// the factorization then runs in place, G == L holding the Gram matrix with a zero upper
-// triangle, one workgroup per 32-column block (m <= 1536). Without it G is copied into L
-// first and one workgroup factors.
+// gram_sq: the partial sums of ||G||_F^2 and ||G - I||_F^2 written by the Gram GEMM
+// (gemm_f64 with gram_sq); the factorization then runs in place, G == L holding the Gram
+// matrix with a zero upper triangle, by one workgroup up to m = 352, beyond it by one
+// workgroup per 32-column block (m <= 1536); in mode 2 a Gram with ||G - I||_F^2 <= u is
+// factored to first order, L = I + (strict lower part of G - I) + (diagonal of G - I) / 2,
+// whose L L^T is within ||G - I||_F^2 of G. Without gram_sq G is copied into L first and
+// one workgroup factors.
 hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_rel, int mode,
                                int *flag, int *shifts, hipStream_t st, const int *run = nullptr,
                                int *modflag = nullptr, const double *gram_sq = nullptr);

@@ -202,6 +202,33 @@ constexpr int kCholThreads = 512;
 // orthonormal to rounding, as from the exact factor).
 constexpr double kCholFirstOrderDev2 = 0x1.0p-53;
 
+// End of a CholeskyQR pass (one thread): count it, update the clean-pass count and set the
+// next pass's run flag.
+__device__ void cholqr_ctl_end(const CholQrCtl &c, bool shifted, bool modified, bool bad) {
+  if (c.count) c.count[0] += 1;
+  int &clean = c.cq[c.npass];
+  clean = (!shifted && !modified && !bad) ? clean + 1 : 0;
+  if (c.pass + 1 < c.npass) c.cq[c.pass + 1] = (clean < 2 && !bad) ? 1 : 0;
+}
+
+// Inverse of diagonal block b of the first-order factor L = I + F of G (F: strict lower
+// part of G - I and half its diagonal): I - F_bb, off by at most ||F_bb||^2 <= u, in the
+// layout of trsm_diag_inv_kernel (entry (t, c) at dinv[1024 b + 32 c + t], zero outside
+// the block's nb x nb part), from G itself (before its diagonal becomes the factor's).
+// Threads tid0, tid0 + nthr, ... of the caller.
+__device__ void first_order_dinv(int m, int b, const double *G, double *dinv, int tid0, int nthr) {
+  const int c0 = 32 * b, nb = min(32, m - c0);
+  for (int idx = tid0; idx < 1024; idx += nthr) {
+    const int c = idx >> 5, t = idx & 31;
+    double v = 0.0;
+    if (c < nb && t < nb) {
+      const double g = G[(size_t)(c0 + c) * m + c0 + t];
+      v = (t == c) ? 1.5 - 0.5 * g : (t > c ? -g : 0.0);  // 1 - (g - 1) / 2 on the diagonal
+    }
+    dinv[(size_t)b * 1024 + idx] = v;
+  }
+}
+
 // Sum of the partial sums of ||G - I||_F^2 that the Gram's split-K reduction left after
 // those of ||G||_F^2 and the 32 doubles of flags, in a fixed order (every caller in the
 // grid gets the same value).
@@ -378,6 +405,36 @@ __device__ __attribute__((noinline)) void factor_block32(LdsBlock &S, int nb, do
   use_inv_out = !fail && (cl * ci <= kCholInvCond);
 }
 
+// Inverse of the factored diagonal block held in S.D (nb x nb) by column-oriented forward
+// substitution, L11 x_c = e_c with one column per lane (lanes 0..31 of the calling wave;
+// the others return), into out[32 c + t] = (L11^{-1})[t][c], zero outside the nb x nb part.
+// Solving for the columns keeps the right residual L11 X - I at rounding level relative to
+// |L11| |X|, which the right-hand solves X <- X L^{-T} that use it need (the inverse that
+// factor_block32 builds alongside the pivots is row-oriented: its left residual is small,
+// its right one up to the block's condition times larger). Each x_i takes its row's sum in
+// two accumulators and the reciprocal of L11[i][i] (one correctly rounded division per lane,
+// shared by v_readlane), so the 32 rows run without branches.
+__device__ __attribute__((noinline)) void block_inverse_fs(const LdsBlock &S, int nb,
+                                                           double *__restrict__ out) {
+  const int c = threadIdx.x & 63;
+  if (c >= 32) return;
+  const double rd = (c < nb) ? 1.0 / S.D[c][c] : 0.0;  // 1 / L11[c][c]
+  double x[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    double a0 = (i == c) ? 1.0 : 0.0, a1 = 0.0;
+#pragma unroll
+    for (int t = 0; t < i; t += 2) {  // x[t] = 0 for t < c
+      a0 = fma(-S.D[i][t], x[t], a0);
+      if (t + 1 < i) a1 = fma(-S.D[i][t + 1], x[t + 1], a1);
+    }
+    const double v = (a0 + a1) * readlane_d(rd, i);
+    x[i] = (i >= c && i < nb) ? v : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < 32; ++i) out[(size_t)c * 32 + i] = x[i];
+}
+
 // ---------------------------------------------------------------------------
 // Blocked Cholesky G + s I = L L^T (lower, column-major), one workgroup.
 // mode 0: s = 0; mode 1: s = shift_rel ||G||_F; mode 2: s = 0, and a pivot that is not
@@ -394,13 +451,15 @@ __global__ void __launch_bounds__(kCholThreads)
                         double shift_rel, int mode, int *__restrict__ flag,
                         int *__restrict__ shifts, const int *__restrict__ run,
                         int *__restrict__ modflag, const double *__restrict__ gram_sq,
+                        double *__restrict__ dinv, CholQrCtl ctl,
                         const CholJob *__restrict__ jobs) {
   if (jobs) {  // batched: blockIdx.y selects the problem
     const CholJob &J = jobs[blockIdx.y];
     m = J.m, G = J.G, L = J.L, shift_rel = J.shift_rel, flag = J.flag, shifts = J.shifts;
     run = J.run, modflag = J.modflag;
-    gram_sq = nullptr;
+    gram_sq = nullptr, dinv = nullptr, ctl = CholQrCtl();
   }
+  if (ctl.cq) run = ctl.cq + ctl.pass;
   if (run && run[0] == 0) return;
   __shared__ BlockLds S;  // the diagonal block, its factor and inverse
   __shared__ double Pn[kPB * (kStageRows + 1)];
@@ -413,8 +472,12 @@ __global__ void __launch_bounds__(kCholThreads)
   const bool inplace = gram_sq != nullptr;
   if (inplace && mode == 2 && gram_dev2(m, gram_sq, red) <= kCholFirstOrderDev2) {
     // G within sqrt(u) of the identity: the first-order factor, in place (the diagonal is
-    // the only change: L[i][i] = 1 + (G[i][i] - 1) / 2)
+    // the only change: L[i][i] = 1 + (G[i][i] - 1) / 2), and its blocks' inverses
+    if (dinv)
+      for (int b = 0; b * kPB < m; ++b) first_order_dinv(m, b, L, dinv, tid, nt);
+    __syncthreads();
     for (int i = tid; i < m; i += nt) L[(size_t)i * m + i] = 0.5 + 0.5 * L[(size_t)i * m + i];
+    if (tid == 0 && ctl.cq) cholqr_ctl_end(ctl, false, false, false);
     return;
   }
   double fro = 0.0;
@@ -485,11 +548,12 @@ __global__ void __launch_bounds__(kCholThreads)
     for (int kb = 0; kb < m && !bad; kb += kPB) {
       const int nb = min(kPB, m - kb);
       // 1. the diagonal block, factored (before the loop, or during the previous panel's
-      //    trailing update), goes to L
+      //    trailing update), goes to L, and its inverse to dinv
       for (int idx = tid; idx < nb * nb; idx += nt) {
         const int i = idx % nb, j = idx / nb;
         if (i >= j) L[(size_t)(kb + j) * m + kb + i] = S.D[i][j];
       }
+
       // 2. panel rows below: X L11^T = A21 (the panel is staged in LDS first when it fits;
       //    the result goes to L and to the staged copy). A well-conditioned block: X =
       //    A21 L11^{-T}, one 32-row MFMA tile per wave. Otherwise the product with the
@@ -523,6 +587,10 @@ __global__ void __launch_bounds__(kCholThreads)
         }
       }
       __syncthreads();
+      // the block's inverse for the right-hand solves that follow the factorization, by the
+      // last wave, which has no panel tile after the first block
+      if (dinv && wave == nwaves - 1)
+        block_inverse_fs(*(const LdsBlock *)&S, nb, dinv + (size_t)(kb / kPB) * 1024);
       if (!use_inv && staged) {
         // ill-conditioned block, staged panel: X0 = A L11^{-T} (into L; A stays in the staged
         // copy), R = A - X0 L11^T (into the staged copy), X = X0 + R L11^{-T}: one step of
@@ -700,11 +768,13 @@ __global__ void __launch_bounds__(kCholThreads)
     if (!bad) {
       if (tid == 0 && modified && shifts) shifts[0] += 1;
       if (tid == 0 && modified && modflag) modflag[0] = 1;
+      if (tid == 0 && ctl.cq) cholqr_ctl_end(ctl, mode == 1, modified != 0, false);
       return;
     }
     __syncthreads();
   }
   if (tid == 0) flag[0] = 1;
+  if (tid == 0 && ctl.cq) cholqr_ctl_end(ctl, mode == 1, modified != 0, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -724,7 +794,9 @@ constexpr int kCholMaxPolls = 1 << 22;
 __global__ void __launch_bounds__(kCholThreads)
     chol_mwg_kernel(int m, double *L, double shift_rel, int mode, int *__restrict__ flag,
                     int *__restrict__ shifts, const int *__restrict__ run,
-                    int *__restrict__ modflag, double *__restrict__ gram_sq) {
+                    int *__restrict__ modflag, double *__restrict__ gram_sq,
+                    double *__restrict__ dinv, CholQrCtl ctl) {
+  if (ctl.cq) run = ctl.cq + ctl.pass;
   if (run && run[0] == 0) return;
   const int nblk = (m + kPB - 1) / kPB;
   const int J = blockIdx.x;
@@ -739,8 +811,12 @@ __global__ void __launch_bounds__(kCholThreads)
   const int wave = tid >> 6, nwaves = nthr >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   if (mode == 2 && gram_dev2(m, gram_sq, red) <= kCholFirstOrderDev2) {
     // first-order factor (every workgroup takes the same decision): this block's diagonal
+    // and its inverse
+    if (dinv) first_order_dinv(m, J, L, dinv, tid, nthr);
+    __syncthreads();
     for (int t = kPB * J + tid; t < min(m, kPB * (J + 1)); t += nthr)
       L[(size_t)t * m + t] = 0.5 + 0.5 * L[(size_t)t * m + t];
+    if (J == 0 && tid == 0 && ctl.cq) cholqr_ctl_end(ctl, false, false, false);
     return;
   }
   // ||G||_F from the partial sums, in the same order in every workgroup
@@ -853,6 +929,8 @@ __global__ void __launch_bounds__(kCholThreads)
       const int i = idx % nb, j = idx / nb;
       if (i >= j) L[(size_t)(c0 + j) * m + c0 + i] = S.D[i][j];
     }
+    if (dinv && wave == nwaves - 1)
+      block_inverse_fs(*(const LdsBlock *)&S, nb, dinv + (size_t)J * 1024);
     double *const Wt = W[wave];
     for (int I = J + 1 + wave; I < nblk; I += nwaves) {
       const int i0 = kPB * I, rows = m - i0;
@@ -939,6 +1017,7 @@ __global__ void __launch_bounds__(kCholThreads)
     if (b) flag[0] = 1;
     if (md && shifts) shifts[0] += 1;
     if (md && modflag) modflag[0] = 1;
+    if (ctl.cq) cholqr_ctl_end(ctl, mode == 1, md != 0, b != 0);
   }
 }
 
@@ -1414,18 +1493,23 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
 
 hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_rel, int mode,
                                int *flag, int *shifts, hipStream_t st, const int *run,
-                               int *modflag, const double *gram_sq) {
+                               int *modflag, const double *gram_sq, double *dinv,
+                               CholQrCtl ctl) {
   if (gram_sq && G != L) return hipErrorInvalidValue;
+  if (!gram_sq && (dinv || ctl.cq)) return hipErrorInvalidValue;
+  if (ctl.cq && (ctl.pass < 0 || ctl.pass >= ctl.npass)) return hipErrorInvalidValue;
   // up to the staged panel height one workgroup is faster (the critical path is the chain of
   // diagonal blocks either way); beyond it the trailing updates dominate and are spread
   if (gram_sq && m > kStageRows + kPB) {
     if ((m + kPB - 1) / kPB > kCholMaxBlocks) return hipErrorInvalidValue;
     hipLaunchKernelGGL(chol_mwg_kernel, dim3((m + kPB - 1) / kPB), dim3(kCholThreads), 0, st, m,
-                       L, shift_rel, mode, flag, shifts, run, modflag, const_cast<double *>(gram_sq));
+                       L, shift_rel, mode, flag, shifts, run, modflag, const_cast<double *>(gram_sq),
+                       dinv, ctl);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(chol_blocked_kernel, dim3(1), dim3(kCholThreads), 0, st, m, G, L, shift_rel,
-                     mode, flag, shifts, run, modflag, gram_sq, nullptr);
+                     mode, flag, shifts, run, modflag, gram_sq, dinv, ctl,
+                     static_cast<const CholJob *>(nullptr));
   return hipGetLastError();
 }
 
@@ -1461,6 +1545,15 @@ __global__ void cholqr_ctrl_kernel(int *cq, int pass_was_shifted, int *count) {
     cq[1] += 1;
   cq[2] = 0;
   if (cq[1] >= 2) cq[0] = 0;
+}
+
+__global__ void cholqr_start_kernel(int *cq, int npass) {
+  for (int p = threadIdx.x; p <= npass; p += blockDim.x) cq[p] = (p == 0) ? 1 : 0;
+}
+
+hipError_t launch_cholqr_start(int *cq, int npass, hipStream_t st) {
+  hipLaunchKernelGGL(cholqr_start_kernel, dim3(1), dim3(64), 0, st, cq, npass);
+  return hipGetLastError();
 }
 
 __global__ void cholqr_reset_kernel(int *cq) {
@@ -1623,7 +1716,8 @@ hipError_t launch_gemm_batched(int ta, int tb, int nprob, int maxM, int maxN, do
 hipError_t launch_chol_batched(int nprob, int mode, const CholJob *jobs, hipStream_t st) {
   if (nprob <= 0) return hipSuccess;
   hipLaunchKernelGGL(chol_blocked_kernel, dim3(1, nprob), dim3(kCholThreads), 0, st, 0, nullptr,
-                     nullptr, 0.0, mode, nullptr, nullptr, nullptr, nullptr, nullptr, jobs);
+                     nullptr, 0.0, mode, nullptr, nullptr, nullptr, nullptr, nullptr,
+                     static_cast<double *>(nullptr), CholQrCtl(), jobs);
   return hipGetLastError();
 }
 

@@ -171,11 +171,12 @@ struct LaSpace {
   hipStream_t st;
   double *Q, *G, *R, *B1, *B2, *K, *Zs, *sywork, *partial, *scal, *cvec;
   int *flags;
+  int *cq;  // CholeskyQR pass control (kMaxCholQRPasses + 1 ints), after the 16 flags
 };
 
 inline LaSpace la_of(riot_handle *h) {
   return {h->st, h->Q, h->G, h->R, h->B1, h->B2, h->K, h->Zs, h->sywork, h->partial, h->scal,
-          h->cvec, h->flags};
+          h->cvec, h->flags, h->flags + 16};
 }
 
 namespace {
@@ -230,7 +231,7 @@ size_t carve(riot_handle &h, void *base) {
   h.cgv = c.take<double>((size_t)5 * n);
   h.sel = c.take<double>((size_t)8 * n + 2 * U1 + 2);
   h.pso = c.take<double>((size_t)2 * std::max(d.nobs, 1));
-  h.flags = c.take<int>(16);
+  h.flags = c.take<int>(32);  // 16 flags, then the CholeskyQR pass control
   return c.off + 256;
 }
 
@@ -305,6 +306,7 @@ riot_status read_flag(riot_handle *h, int idx, int *out) {
 // Passes beyond the last needed one are launched but return at once (device flag), so
 // nothing synchronises.
 constexpr int kMaxCholQRPasses = 8;
+static_assert(kMaxCholQRPasses + 1 <= 16, "the pass control fits after the 16 flags");
 
 riot_status cholqr(const LaSpace &h, int rows, int m, const double *Xin, double *Qout,
                    bool shifted, int flag_idx, double *comp = nullptr, int mc = 0,
@@ -312,25 +314,27 @@ riot_status cholqr(const LaSpace &h, int rows, int m, const double *Xin, double 
   hipStream_t st = h.st;
   const double u = 0x1.0p-53;
   const double srel = 11.0 * ((double)m * rows + (double)m * (m + 1)) * u;
-  int *cq = h.flags + 12;
+  int *cq = h.cq;
   if (Qout != Xin)
     RIOT_HIP(hipMemcpyAsync(Qout, Xin, (size_t)rows * m * sizeof(double), hipMemcpyDeviceToDevice,
                             st));
-  RIOT_HIP(launch_cholqr_reset(cq, st));
+  RIOT_HIP(launch_cholqr_start(cq, kMaxCholQRPasses, st));
   for (int pass = 0; pass < kMaxCholQRPasses; ++pass) {
     const bool sh = shifted && pass == 0;
+    int *run = cq + pass;  // set by the previous pass's Cholesky
     // the Gram goes straight into R (lower triangle, zero upper) with the partial sums of
-    // its squared Frobenius norm, and is factored there in place
+    // its squared Frobenius norm and distance from I, and is factored there in place; the
+    // Cholesky also writes its diagonal blocks' inverses into the Gram's split-K buffer,
+    // free by then, and decides whether the next pass runs
     double *gsq = h.partial + gram_sq_offset(m);
     RIOT_HIP(gemm_f64(1, 0, m, m, rows, 1.0, Qout, rows, Qout, rows, 0.0, h.R, m, h.partial,
-                      kSplitK, st, cq, true, gsq));
+                      kSplitK, st, run, true, gsq));
+    CholQrCtl ctl;
+    ctl.cq = cq, ctl.pass = pass, ctl.npass = kMaxCholQRPasses, ctl.count = count;
     RIOT_HIP(launch_chol_blocked(m, h.R, h.R, srel, sh ? 1 : 2, h.flags + flag_idx, h.flags + 4,
-                                 st, cq, cq + 2, gsq));
-    // the Gram's split-K buffer is free here: it holds the diagonal-block inverses
-    RIOT_HIP(launch_trsm_diag_inv(m, h.R, h.partial, st, cq));
-    RIOT_HIP(launch_trsm_rlt_inv(rows, m, Qout, rows, h.R, h.partial, st, cq));
-    if (comp) RIOT_HIP(launch_trsm_rlt_inv(mc, m, comp, mc, h.R, h.partial, st, cq));
-    RIOT_HIP(launch_cholqr_ctrl(cq, sh ? 1 : 0, count, st));
+                                 st, nullptr, nullptr, gsq, h.partial, ctl));
+    RIOT_HIP(launch_trsm_rlt_inv(rows, m, Qout, rows, h.R, h.partial, st, run));
+    if (comp) RIOT_HIP(launch_trsm_rlt_inv(mc, m, comp, mc, h.R, h.partial, st, run));
   }
   return RIOT_OK;
 }
@@ -1815,7 +1819,8 @@ size_t sketch_carve(riot_sketch &s, void *base) {
   la.partial = c.take<double>(partial_doubles(m));
   la.cvec = c.take<double>(m);
   la.scal = c.take<double>(16);
-  la.flags = c.take<int>(16);
+  la.flags = c.take<int>(32);  // 16 flags, then the CholeskyQR pass control
+  la.cq = la.flags + 16;
   return c.off + 256;
 }
 

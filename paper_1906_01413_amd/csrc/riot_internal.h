@@ -44,6 +44,16 @@ struct CqJob {
   int *cq;
   int *count;
 };
+// CholeskyQR pass control carried by the Cholesky of each pass: cq[p] is the run flag of
+// pass p < npass (the launches of pass p return at once when it is 0), cq[npass] counts
+// consecutive clean passes (unshifted, no pivot replaced). The Cholesky of pass p sets
+// cq[p + 1]: 1 until two clean passes in a row (or a breakdown); count[0] (if given) counts
+// the passes run.
+struct CholQrCtl {
+  int *cq = nullptr;
+  int pass = 0, npass = 0;
+  int *count = nullptr;
+};
 struct SymJob {
   int m;
   double *K;
@@ -249,6 +259,9 @@ inline int gram_sq_blocks(int m) { return (int)(((size_t)m * m + 255) / 256); }
 // s = shift_rel * ||G||_F; mode 2: s = 0 with every pivot not above shift_rel * ||G||_F
 // replaced by that value (modflag[0] = 1 when one was). flag[0] = 1 on breakdown
 // (non-positive or non-finite pivot); shifts[0] counts shifted or modified factorizations.
+// dinv (with gram_sq, or null): receives the inverses of the factor's 32 x 32 diagonal
+// blocks in the layout of launch_trsm_diag_inv. ctl.cq (with gram_sq, or null): the pass
+// control of a CholeskyQR; the run flag is then ctl.cq[ctl.pass] and `run` is ignored.
 // gram_sq: the partial sums of ||G||_F^2 and ||G - I||_F^2 written by the Gram GEMM
 // (gemm_f64 with gram_sq); the factorization then runs in place, G == L holding the Gram
 // matrix with a zero upper triangle, by one workgroup up to m = 352, beyond it by one
@@ -258,7 +271,8 @@ inline int gram_sq_blocks(int m) { return (int)(((size_t)m * m + 255) / 256); }
 // one workgroup factors.
 hipError_t launch_chol_blocked(int m, const double *G, double *L, double shift_rel, int mode,
                                int *flag, int *shifts, hipStream_t st, const int *run = nullptr,
-                               int *modflag = nullptr, const double *gram_sq = nullptr);
+                               int *modflag = nullptr, const double *gram_sq = nullptr,
+                               double *dinv = nullptr, CholQrCtl ctl = CholQrCtl());
 // C_b = alpha op(A_b) op(B_b) + beta C_b for b < batch, with A_b = A + b sA (likewise B, C).
 hipError_t gemm_f64_strided(int ta, int tb, int M, int N, int K, double alpha, const double *A,
                             int lda, long long sA, const double *B, int ldb, long long sB,
@@ -283,6 +297,8 @@ hipError_t launch_copy_batched(int nprob, long long maxcount, const CopyJob *job
 // CholeskyQR pass control (see cholqr in the API layer): reset, then one call per pass;
 // count (optional) is incremented once per pass that ran.
 hipError_t launch_cholqr_reset(int *cq, hipStream_t st);
+// cq[0] = 1, cq[1 .. npass] = 0 (the start of a CholeskyQR driven by CholQrCtl)
+hipError_t launch_cholqr_start(int *cq, int npass, hipStream_t st);
 hipError_t launch_cholqr_ctrl(int *cq, int pass_was_shifted, int *count, hipStream_t st);
 
 // X <- X L^{-T} in place (X rows x m, leading dimension ldx; L lower m x m), through the

@@ -86,10 +86,19 @@ def test_preconditioned_outer_loops_match_oracle(rotation):
     assert [rec["mode"] for rec in recs] == [h["mode"] for h in hist]
     assert e_j < 1e-10 and e_v < 1e-9 and e_x < 1e-10
     # the rotation subtracts the probes' components along the resolved directions; what is
-    # left carries the rounding of the whole probe, so the Ritz values' bound scales with the
-    # largest norm ratio of a loop's probes before and after the rotation (oracle side). The
-    # two eigen-solvers sum in different orders; changing only the device's order moved this
-    # case between 1e-10 and 2.6e-10 at ratio 1.58, hence the factor 4 over 1e-10.
+    # left carries the rounding of the whole probe, which the Ritz values then reflect. How
+    # far rounding alone moves them: the oracle again on probes perturbed by one unit of
+    # rounding (relative 2^-52 per entry). The device rounds differently in every step, not
+    # only in the probes, hence the factor 4 over that spread (and at least the 1e-10 of the
+    # other comparisons).
+    rng = np.random.default_rng(11)
+    spread = 2.5e-11
+    for _ in range(6):
+        bp = [b * (1.0 + 2.0 ** -52 * rng.standard_normal(b.shape)) for b in blocks]
+        hp, _, _, _ = fourdvar.riot_outer_loops(p, bp, 3, True, rotation)
+        spread = max(spread, max(float(np.max(np.abs(a["lam"] - b["lam"])) / b["lam"][0])
+                                 for a, b in zip(hp, hist)))
     ratio = max(h["probe_norm_ratio"] for h in hist)
-    print(f"largest probe norm ratio after rotation {ratio:.2f}")
-    assert e_lam < 4e-10 * ratio ** 2
+    print(f"largest probe norm ratio after rotation {ratio:.2f}; Ritz values moved by "
+          f"{spread:.1e} under one rounding of the probes")
+    assert e_lam < 4.0 * spread

@@ -405,7 +405,7 @@ __device__ __attribute__((noinline)) void factor_block32(LdsBlock &S, int nb, do
   use_inv_out = !fail && (cl * ci <= kCholInvCond);
 }
 
-// Inverse of the factored diagonal block held in S.D (nb x nb) by column-oriented forward
+// Inverse of the factored diagonal block D (LDS, rows of kPB + 1, nb x nb used) by column-oriented forward
 // substitution, L11 x_c = e_c with one column per lane (lanes 0..31 of the calling wave;
 // the others return), into out[32 c + t] = (L11^{-1})[t][c], zero outside the nb x nb part.
 // Solving for the columns keeps the right residual L11 X - I at rounding level relative to
@@ -414,19 +414,19 @@ __device__ __attribute__((noinline)) void factor_block32(LdsBlock &S, int nb, do
 // its right one up to the block's condition times larger). Each x_i takes its row's sum in
 // two accumulators and the reciprocal of L11[i][i] (one correctly rounded division per lane,
 // shared by v_readlane), so the 32 rows run without branches.
-__device__ __attribute__((noinline)) void block_inverse_fs(const LdsBlock &S, int nb,
+__device__ __attribute__((noinline)) void block_inverse_fs(const lds_double *D, int nb,
                                                            double *__restrict__ out) {
   const int c = threadIdx.x & 63;
   if (c >= 32) return;
-  const double rd = (c < nb) ? 1.0 / S.D[c][c] : 0.0;  // 1 / L11[c][c]
+  const double rd = (c < nb) ? 1.0 / D[c * (kPB + 1) + c] : 0.0;  // 1 / L11[c][c]
   double x[32];
 #pragma unroll
   for (int i = 0; i < 32; ++i) {
     double a0 = (i == c) ? 1.0 : 0.0, a1 = 0.0;
 #pragma unroll
     for (int t = 0; t < i; t += 2) {  // x[t] = 0 for t < c
-      a0 = fma(-S.D[i][t], x[t], a0);
-      if (t + 1 < i) a1 = fma(-S.D[i][t + 1], x[t + 1], a1);
+      a0 = fma(-D[i * (kPB + 1) + t], x[t], a0);
+      if (t + 1 < i) a1 = fma(-D[i * (kPB + 1) + t + 1], x[t + 1], a1);
     }
     const double v = (a0 + a1) * readlane_d(rd, i);
     x[i] = (i >= c && i < nb) ? v : 0.0;
@@ -463,6 +463,7 @@ __global__ void __launch_bounds__(kCholThreads)
   if (run && run[0] == 0) return;
   __shared__ BlockLds S;  // the diagonal block, its factor and inverse
   __shared__ double Pn[kPB * (kStageRows + 1)];
+  __shared__ double Dc[kPB][kPB + 1];  // this block's factor, kept for its inverse
   __shared__ double red[16];
   __shared__ int bad, use_inv;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -548,11 +549,13 @@ __global__ void __launch_bounds__(kCholThreads)
     for (int kb = 0; kb < m && !bad; kb += kPB) {
       const int nb = min(kPB, m - kb);
       // 1. the diagonal block, factored (before the loop, or during the previous panel's
-      //    trailing update), goes to L, and its inverse to dinv
+      //    trailing update), goes to L, and to Dc for its inverse (step 3)
       for (int idx = tid; idx < nb * nb; idx += nt) {
         const int i = idx % nb, j = idx / nb;
         if (i >= j) L[(size_t)(kb + j) * m + kb + i] = S.D[i][j];
       }
+      if (dinv)
+        for (int idx = tid; idx < kPB * kPB; idx += nt) Dc[idx >> 5][idx & 31] = S.D[idx >> 5][idx & 31];
 
       // 2. panel rows below: X L11^T = A21 (the panel is staged in LDS first when it fits;
       //    the result goes to L and to the staged copy). A well-conditioned block: X =
@@ -587,10 +590,6 @@ __global__ void __launch_bounds__(kCholThreads)
         }
       }
       __syncthreads();
-      // the block's inverse for the right-hand solves that follow the factorization, by the
-      // last wave, which has no panel tile after the first block
-      if (dinv && wave == nwaves - 1)
-        block_inverse_fs(*(const LdsBlock *)&S, nb, dinv + (size_t)(kb / kPB) * 1024);
       if (!use_inv && staged) {
         // ill-conditioned block, staged panel: X0 = A L11^{-T} (into L; A stays in the staged
         // copy), R = A - X0 L11^T (into the staged copy), X = X0 + R L11^{-T}: one step of
@@ -754,12 +753,20 @@ __global__ void __launch_bounds__(kCholThreads)
       };
       if (wave == 0) {
         if (ntiles > 0) {
+          // the critical path: wave 0's instructions go first when it shares its SIMD with a
+          // wave of the trailing update
+          __builtin_amdgcn_s_setprio(3);
           trailing_tile(0, true);
           asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
           __builtin_amdgcn_wave_barrier();
           factor_block(min(kPB, prow));
+          __builtin_amdgcn_s_setprio(0);
         }
       } else {
+        // the block's inverse for the right-hand solves that follow the factorization, by
+        // the last wave, which has the fewest tiles
+        if (dinv && wave == nwaves - 1)
+          block_inverse_fs((const lds_double *)&Dc[0][0], nb, dinv + (size_t)(kb / kPB) * 1024);
         for (int t = wave; t < ntiles; t += nwaves - 1) trailing_tile(t, false);
       }
       __syncthreads();
@@ -902,10 +909,12 @@ __global__ void __launch_bounds__(kCholThreads)
       // last update: wave 0 takes the diagonal tile and factors it while the other waves
       // update the tiles below
       if (wave == 0) {
+        __builtin_amdgcn_s_setprio(3);  // the critical path goes first on its SIMD
         update_tile(p, J, true);
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         __builtin_amdgcn_wave_barrier();
         factor_diag();
+        __builtin_amdgcn_s_setprio(0);
       } else {
         for (int t = wave; t < ntile; t += nwaves - 1) update_tile(p, J + t, false);
       }
@@ -929,8 +938,6 @@ __global__ void __launch_bounds__(kCholThreads)
       const int i = idx % nb, j = idx / nb;
       if (i >= j) L[(size_t)(c0 + j) * m + c0 + i] = S.D[i][j];
     }
-    if (dinv && wave == nwaves - 1)
-      block_inverse_fs(*(const LdsBlock *)&S, nb, dinv + (size_t)J * 1024);
     double *const Wt = W[wave];
     for (int I = J + 1 + wave; I < nblk; I += nwaves) {
       const int i0 = kPB * I, rows = m - i0;
@@ -1010,6 +1017,10 @@ __global__ void __launch_bounds__(kCholThreads)
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (tid == 0) __hip_atomic_store(&sync[J], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  // the block's inverse for the right-hand solves after the factorization, once published
+  // (off the chain of workgroups waiting on each other)
+  if (dinv && !timed_out && wave == nwaves - 1)
+    block_inverse_fs((const lds_double *)&S.D[0][0], nb, dinv + (size_t)J * 1024);
   // the last block has waited for every other one: it reports for the factorization
   if (J == nblk - 1 && tid == 0) {
     const int b = __hip_atomic_load(&sync[kCholSyncBad], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1131,13 +1142,18 @@ __global__ void __launch_bounds__(64)
 __global__ void __launch_bounds__(256)
     trsm_rlt_inv_kernel(int rows, int m, double *__restrict__ X, int ldx,
                         const double *__restrict__ L, const double *__restrict__ dinv,
-                        const int *__restrict__ run) {
+                        const int *__restrict__ run, int rows2, double *__restrict__ X2,
+                        int ldx2) {
   if (run && run[0] == 0) return;
   __shared__ double red[4][32][33];
   __shared__ double Bm[32 * 33];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lg = lane >> 4;
-  const int r0 = blockIdx.x * 32;
+  int r0 = blockIdx.x * 32;
+  const int nblk1 = (rows + 31) / 32;
+  if ((int)blockIdx.x >= nblk1) {  // a block of the second matrix
+    r0 = ((int)blockIdx.x - nblk1) * 32, rows = rows2, X = X2, ldx = ldx2;
+  }
   if (r0 >= rows) return;
   const int nr = min(32, rows - r0);
   for (int jb = 0; jb * 32 < m; ++jb) {
@@ -1195,14 +1211,19 @@ constexpr int kStripM = 288;
 __global__ void __launch_bounds__(256)
     trsm_rlt_inv_strip_kernel(int rows, int m, double *__restrict__ X, int ldx,
                               const double *__restrict__ L, const double *__restrict__ dinv,
-                              const int *__restrict__ run) {
+                              const int *__restrict__ run, int rows2, double *__restrict__ X2,
+                              int ldx2) {
   if (run && run[0] == 0) return;
   __shared__ double xs[kStripM * 33];  // xs[j 33 + i] = X[r0 + i][j]
   __shared__ double red[4][32][33];
   __shared__ double Bm[32 * 33];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lg = lane >> 4;
-  const int r0 = blockIdx.x * 32;
+  int r0 = blockIdx.x * 32;
+  const int nblk1 = (rows + 31) / 32;
+  if ((int)blockIdx.x >= nblk1) {  // a block of the second matrix
+    r0 = ((int)blockIdx.x - nblk1) * 32, rows = rows2, X = X2, ldx = ldx2;
+  }
   if (r0 >= rows) return;
   const int nr = min(32, rows - r0);
   for (int idx = tid; idx < 32 * m; idx += 256) {
@@ -1521,14 +1542,17 @@ hipError_t launch_trsm_diag_inv(int m, const double *L, double *dinv, hipStream_
 }
 
 hipError_t launch_trsm_rlt_inv(int rows, int m, double *X, int ldx, const double *L,
-                               const double *dinv, hipStream_t st, const int *run) {
-  if (rows <= 0 || m <= 0) return hipSuccess;
+                               const double *dinv, hipStream_t st, const int *run, int rows2,
+                               double *X2, int ldx2) {
+  if (!X2) rows2 = 0;
+  if (rows < 0 || rows2 < 0 || m <= 0 || rows + rows2 == 0) return hipSuccess;
+  const int nblk = (rows + 31) / 32 + (rows2 + 31) / 32;
   if (m <= kStripM)
-    hipLaunchKernelGGL(trsm_rlt_inv_strip_kernel, dim3((rows + 31) / 32), dim3(256), 0, st, rows,
-                       m, X, ldx, L, dinv, run);
+    hipLaunchKernelGGL(trsm_rlt_inv_strip_kernel, dim3(nblk), dim3(256), 0, st, rows, m, X, ldx,
+                       L, dinv, run, rows2, X2, ldx2);
   else
-    hipLaunchKernelGGL(trsm_rlt_inv_kernel, dim3((rows + 31) / 32), dim3(256), 0, st, rows, m, X,
-                       ldx, L, dinv, run);
+    hipLaunchKernelGGL(trsm_rlt_inv_kernel, dim3(nblk), dim3(256), 0, st, rows, m, X, ldx, L,
+                       dinv, run, rows2, X2, ldx2);
   return hipGetLastError();
 }
 

@@ -333,8 +333,9 @@ riot_status cholqr(const LaSpace &h, int rows, int m, const double *Xin, double 
     ctl.cq = cq, ctl.pass = pass, ctl.npass = kMaxCholQRPasses, ctl.count = count;
     RIOT_HIP(launch_chol_blocked(m, h.R, h.R, srel, sh ? 1 : 2, h.flags + flag_idx, h.flags + 4,
                                  st, nullptr, nullptr, gsq, h.partial, ctl));
-    RIOT_HIP(launch_trsm_rlt_inv(rows, m, Qout, rows, h.R, h.partial, st, run));
-    if (comp) RIOT_HIP(launch_trsm_rlt_inv(mc, m, comp, mc, h.R, h.partial, st, run));
+    // X and its companion in one launch
+    RIOT_HIP(launch_trsm_rlt_inv(rows, m, Qout, rows, h.R, h.partial, st, run, comp ? mc : 0,
+                                 comp, comp ? mc : 1));
   }
   return RIOT_OK;
 }

@@ -302,12 +302,14 @@ hipError_t launch_cholqr_start(int *cq, int npass, hipStream_t st);
 hipError_t launch_cholqr_ctrl(int *cq, int pass_was_shifted, int *count, hipStream_t st);
 
 // X <- X L^{-T} in place (X rows x m, leading dimension ldx; L lower m x m), through the
-// inverses of L's 32 x 32 diagonal blocks: launch_trsm_diag_inv writes them to dinv
-// (ceil(m / 32) * 1024 doubles), launch_trsm_rlt_inv uses them.
+// inverses of L's 32 x 32 diagonal blocks: launch_trsm_diag_inv (or the in-place Cholesky)
+// writes them to dinv (ceil(m / 32) * 1024 doubles), launch_trsm_rlt_inv uses them. X2
+// (rows2 x m, leading dimension ldx2, or null) is solved with the same L in the same launch.
 hipError_t launch_trsm_diag_inv(int m, const double *L, double *dinv, hipStream_t st,
                                 const int *run = nullptr);
 hipError_t launch_trsm_rlt_inv(int rows, int m, double *X, int ldx, const double *L,
-                               const double *dinv, hipStream_t st, const int *run = nullptr);
+                               const double *dinv, hipStream_t st, const int *run = nullptr,
+                               int rows2 = 0, double *X2 = nullptr, int ldx2 = 1);
 
 // K <- (K + K^T)/2 and asym[0] = ||K - K^T||_F / ||K||_F (before symmetrisation).
 // part: 128 doubles of scratch.

@@ -1205,7 +1205,11 @@ __global__ void __launch_bounds__(256)
 
 // The same solve with the workgroup's 32-row strip of X held in LDS for m <= kStripM: the
 // strip is read once and written once, and the solved column blocks that every later
-// block's contraction needs are LDS operands instead of global re-reads.
+// block's contraction needs are LDS operands instead of global re-reads. Each of the four
+// waves owns one 16 x 16 tile (rt, ct) of the 32 x 32 column block: it forms that tile of
+// B = X[:, jb] - X[:, <jb] L[jb, <jb]^T over the whole contraction (no partial sums to
+// reduce), the workgroup exchanges B through LDS, and each wave multiplies its row tile of
+// B by its column tile of L_jb^{-T}, prefetched into registers while the contraction runs.
 constexpr int kStripM = 288;
 
 __global__ void __launch_bounds__(256)
@@ -1215,8 +1219,7 @@ __global__ void __launch_bounds__(256)
                               int ldx2) {
   if (run && run[0] == 0) return;
   __shared__ double xs[kStripM * 33];  // xs[j 33 + i] = X[r0 + i][j]
-  __shared__ double red[4][32][33];
-  __shared__ double Bm[32 * 33];
+  __shared__ double Bm[32 * 33];       // B, column-major
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lg = lane >> 4;
   int r0 = blockIdx.x * 32;
@@ -1231,44 +1234,57 @@ __global__ void __launch_bounds__(256)
     xs[j * 33 + i] = (i < nr) ? X[(size_t)j * ldx + r0 + i] : 0.0;
   }
   __syncthreads();
+  const int rt = wave >> 1, ct = wave & 1;
+  const int arow = 16 * rt + li;  // A-operand row of this lane
   for (int jb = 0; jb * 32 < m; ++jb) {
     const int c0 = jb * 32, nc = min(32, m - c0);
-    // 1. wave w: X[:, k0:k1] L[c0:, k0:k1]^T over its quarter of [0, c0), X from the strip
-    const int k0 = (c0 * wave) / 4, k1 = (c0 * (wave + 1)) / 4;
-    d4 acc[2][2];
-    zero_acc(acc);
-    if (k1 > k0)
-      wave_mma32<false, true>(xs + k0 * 33, 33, L + c0 + (size_t)k0 * m, m, k1 - k0, nr, nc, acc);
+    const int bcol = c0 + 16 * ct + li;  // B-operand column (a row of L) of this lane
+    const bool bin = bcol < m;
+    // this wave's column tile of L_jb^{-T}: op[k][j] = dinv[1024 jb + 32 k + 16 ct + j]
+    double dv[8];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int s = 0; s < 8; ++s) dv[s] = dinv[(size_t)jb * 1024 + 32 * (4 * s + lg) + 16 * ct + li];
+    // 1. acc = X[16 rt.., 0:c0] L[c0 + 16 ct.., 0:c0]^T in chunks of 16, the next chunk's
+    //    L operands loaded before the current chunk's MFMAs
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    if (c0 > 0) {
+      double bcur[4], bnext[4];
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct)
+      for (int s = 0; s < 4; ++s) bcur[s] = bin ? L[(size_t)(4 * s + lg) * m + bcol] : 0.0;
+      for (int k0 = 0; k0 < c0; k0 += 16) {
+        const bool more = k0 + 16 < c0;
+        if (more) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) red[wave][16 * rt + lg + 4 * r][16 * ct + li] = acc[rt][ct][r];
-    __syncthreads();
-    // 2. B = X[:, jb] - sum of the partial products, column-major in LDS (all four waves)
-    for (int idx = tid; idx < 32 * 32; idx += 256) {
-      const int i = idx & 31, j = idx >> 5;
-      double v = 0.0;
-      if (i < nr && j < nc)
-        v = xs[(c0 + j) * 33 + i] - (red[0][i][j] + red[1][i][j] + red[2][i][j] + red[3][i][j]);
-      Bm[i + 33 * j] = v;
+          for (int s = 0; s < 4; ++s)
+            bnext[s] = bin ? L[(size_t)(k0 + 16 + 4 * s + lg) * m + bcol] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double a = xs[(k0 + 4 * s + lg) * 33 + arow];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bcur[s], acc, 0, 0, 0);
+        }
+        if (more) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) bcur[s] = bnext[s];
+        }
+      }
+    }
+    // 2. this wave's tile of B into LDS (rows >= nr and columns >= nc zero)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * rt + lg + 4 * r, col = 16 * ct + li;
+      Bm[row + 33 * col] = (row < nr && col < nc) ? xs[(c0 + col) * 33 + row] - acc[r] : 0.0;
     }
     __syncthreads();
-    if (wave == 0) {
-      // 3. X[:, jb] = B L_jb^{-T}, into the strip
-      d4 q[2][2];
-      zero_acc(q);
-      wave_mma32<false, true>(Bm, 33, dinv + (size_t)jb * 1024, 32, nc, nr, nc, q);
+    // 3. X[16 rt.., c0 + 16 ct..] = B[16 rt.., :] L_jb^{-T}[:, 16 ct..], into the strip
+    d4 q = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
+    for (int s = 0; s < 8; ++s)
+      q = __builtin_amdgcn_mfma_f64_16x16x4f64(Bm[arow + 33 * (4 * s + lg)], dv[s], q, 0, 0, 0);
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = 16 * rt + lg + 4 * r, col = 16 * ct + li;
-            if (row < nr && col < nc) xs[(c0 + col) * 33 + row] = q[rt][ct][r];
-          }
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * rt + lg + 4 * r, col = 16 * ct + li;
+      if (row < nr && col < nc) xs[(c0 + col) * 33 + row] = q[r];
     }
     __syncthreads();
   }

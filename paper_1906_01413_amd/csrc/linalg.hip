@@ -240,7 +240,7 @@ __device__ double gram_dev2(int m, const double *gram_sq, double *red) {
   return wg_sum(part, red);
 }
 constexpr int kPB = 32;  // panel width of the blocked factorizations
-constexpr int kStageRows = 320;  // panel rows staged in LDS by the Cholesky
+constexpr int kStageRows = 256;  // panel rows staged in LDS by the Cholesky (two buffers)
 // largest 1-norm condition of a 32 x 32 diagonal block whose panel the Cholesky solves as a
 // product with the block's inverse (about one digit of the panel's residual given up)
 constexpr double kCholInvCond = 16.0;
@@ -462,7 +462,8 @@ __global__ void __launch_bounds__(kCholThreads)
   if (ctl.cq) run = ctl.cq + ctl.pass;
   if (run && run[0] == 0) return;
   __shared__ BlockLds S;  // the diagonal block, its factor and inverse
-  __shared__ double Pn[kPB * (kStageRows + 1)];
+  // the staged panel and the next one, which the trailing update writes (ping-pong)
+  __shared__ double Pbuf[2][kPB * (kStageRows + 1)];
   __shared__ double Dc[kPB][kPB + 1];  // this block's factor, kept for its inverse
   __shared__ double red[16];
   __shared__ int bad, use_inv;
@@ -546,8 +547,11 @@ __global__ void __launch_bounds__(kCholThreads)
       if (wave == 0) factor_block(nb);
       __syncthreads();
     }
+    int cur = 0;        // Pbuf[cur] holds this block's panel
+    bool have = false;  // the previous trailing update left it there
     for (int kb = 0; kb < m && !bad; kb += kPB) {
       const int nb = min(kPB, m - kb);
+      double *const Pn = Pbuf[cur];
       // 1. the diagonal block, factored (before the loop, or during the previous panel's
       //    trailing update), goes to L, and to Dc for its inverse (step 3)
       for (int idx = tid; idx < nb * nb; idx += nt) {
@@ -566,7 +570,7 @@ __global__ void __launch_bounds__(kCholThreads)
       const int r0 = kb + nb;
       const int prow = m - r0;
       const bool staged = prow <= kStageRows;
-      if (staged) {
+      if (staged && !have) {
         // eight loads in flight per thread before any is stored (one memory latency per
         // round, not one per element)
         const int tot = nb * prow;
@@ -737,6 +741,10 @@ __global__ void __launch_bounds__(kCholThreads)
         else
           wave_mma32<false, true>(L + (size_t)kb * m + i0, m, L + (size_t)kb * m + j0, m, nb,
                                   m - i0, m - j0, acc);
+        // tiles below the next diagonal block in its column are the next panel: with a
+        // staged panel they go to the other LDS buffer only (the panel's solve writes L)
+        const bool to_next = staged && J == 0 && I > 0;
+        double *const Pnext = Pbuf[cur ^ 1];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -746,7 +754,10 @@ __global__ void __launch_bounds__(kCholThreads)
               const int row = i0 + 16 * rt + lg + 4 * r, col = j0 + 16 * ct + li;
               if (row < m && col < m && row >= col) {
                 const double v = old[rt][ct][r] - acc[rt][ct][r];
-                L[(size_t)col * m + row] = v;
+                if (to_next)
+                  Pnext[(col - r0) * (kStageRows + 1) + (row - r0 - kPB)] = v;
+                else
+                  L[(size_t)col * m + row] = v;
                 if (to_D) S.D[row - i0][col - j0] = v;
               }
             }
@@ -770,6 +781,8 @@ __global__ void __launch_bounds__(kCholThreads)
         for (int t = wave; t < ntiles; t += nwaves - 1) trailing_tile(t, false);
       }
       __syncthreads();
+      have = staged;
+      cur ^= 1;
     }
     __syncthreads();
     if (!bad) {

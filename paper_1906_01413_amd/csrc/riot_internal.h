@@ -264,7 +264,7 @@ inline int gram_sq_blocks(int m) { return (int)(((size_t)m * m + 255) / 256); }
 // control of a CholeskyQR; the run flag is then ctl.cq[ctl.pass] and `run` is ignored.
 // gram_sq: the partial sums of ||G||_F^2 and ||G - I||_F^2 written by the Gram GEMM
 // (gemm_f64 with gram_sq); the factorization then runs in place, G == L holding the Gram
-// matrix with a zero upper triangle, by one workgroup up to m = 352, beyond it by one
+// matrix with a zero upper triangle, by one workgroup up to m = 288, beyond it by one
 // workgroup per 32-column block (m <= 1536); in mode 2 a Gram with ||G - I||_F^2 <= u is
 // factored to first order, L = I + (strict lower part of G - I) + (diagonal of G - I) / 2,
 // whose L L^T is within ||G - I||_F^2 of G. Without gram_sq G is copied into L first and

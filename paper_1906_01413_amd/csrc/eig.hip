@@ -994,6 +994,7 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
   __shared__ double H[kMaxCluster][kMaxCluster + 1];
   __shared__ double Vc[kMaxCluster][kMaxCluster + 1];
   __shared__ double dots[kEigMaxM];
+  __shared__ double Cb[kMaxCluster * 65];  // P^T Z_c for a chunk of 64 earlier vectors
   __shared__ double rot[kMaxCluster / 2][2];
   __shared__ int pr[kMaxCluster / 2][2];
   __shared__ double red[16];
@@ -1004,15 +1005,72 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
   for (int cl = g; cl < ncl && (cl == g || list[3 + 3 * cl]); ++cl) {
   const int a = list[1 + 3 * cl], c = list[2 + 3 * cl] - a + 1;
   double *W = work + Lw.scr + (size_t)a * m;  // m x c, this cluster's columns of the scratch
-  // 1. re-orthonormalisation against the chain's earlier vectors and the cluster's own
+  // 1a. against the chain's earlier clusters (columns c0 .. a - 1, orthonormal already), as
+  //     blocks: twice Z_c <- Z_c - P (P^T Z_c) for chunks P of 64 columns, on the matrix cores
+  for (int pass = 0; pass < 2 && a > c0; ++pass) {
+    for (int p0 = c0; p0 < a; p0 += 64) {
+      const int pc = min(64, a - p0);
+      {  // Cb = P^T Z_c (pc x c, column-major, leading dimension 65), a 32 x 32 tile per wave
+        const int rt = wave >> 1, ct = wave & 1, li = lane & 15, lg = lane >> 4;
+        if (32 * rt < pc && 32 * ct < c) {
+          d4 acc[2][2];
+          zero_acc(acc);
+          wave_mma32<true, false>(Z + (size_t)(p0 + 32 * rt) * m, m, Z + (size_t)(a + 32 * ct) * m,
+                                  m, m, pc - 32 * rt, c - 32 * ct, acc);
+#pragma unroll
+          for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int row = 32 * rt + 16 * r2 + lg + 4 * r, col = 32 * ct + 16 * c2 + li;
+                if (row < pc && col < c) Cb[col * 65 + row] = acc[r2][c2][r];
+              }
+        }
+      }
+      __syncthreads();
+      // Z_c -= P Cb, one 32 x 32 tile of Z_c per wave at a time
+      const int nrt = (m + 31) / 32, nct = (c + 31) / 32;
+      for (int t = wave; t < nrt * nct; t += nw) {
+        const int i0 = 32 * (t % nrt), j0 = 32 * (t / nrt), li = lane & 15, lg = lane >> 4;
+        double old[2][2][4];
+#pragma unroll
+        for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+          for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = i0 + 16 * r2 + lg + 4 * r, col = j0 + 16 * c2 + li;
+              old[r2][c2][r] = (row < m && col < c) ? Z[(size_t)(a + col) * m + row] : 0.0;
+            }
+        d4 acc[2][2];
+        zero_acc(acc);
+        wave_mma32<false, false>(Z + (size_t)p0 * m + i0, m, Cb + j0 * 65, 65, pc, m - i0, c - j0,
+                                 acc);
+#pragma unroll
+        for (int r2 = 0; r2 < 2; ++r2)
+#pragma unroll
+          for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = i0 + 16 * r2 + lg + 4 * r, col = j0 + 16 * c2 + li;
+              if (row < m && col < c) Z[(size_t)(a + col) * m + row] = old[r2][c2][r] - acc[r2][c2][r];
+            }
+      }
+      __syncthreads();
+    }
+  }
+  // 1b. the cluster's own vectors in order (a vector replaced by a probe is taken against
+  //     the whole chain again)
   for (int q = 0; q < c; ++q) {
     double *zq = Z + (size_t)(a + q) * m;
-    const int np = a + q - c0;  // earlier vectors: columns c0 .. a + q - 1
     int replaced = 0;
     for (int pass = 0; pass < 2; ++pass) {
+      const int pbase = replaced ? c0 : a;
+      const int np = a + q - pbase;  // earlier vectors: columns pbase .. a + q - 1
       if (np > 0) {
         for (int p = wave; p < np; p += nw) {
-          const double *zp = Z + (size_t)(c0 + p) * m;
+          const double *zp = Z + (size_t)(pbase + p) * m;
           double part = 0.0;
           for (int i = lane; i < m; i += 64) part += zp[i] * zq[i];
           part = wave_sum(part);
@@ -1021,7 +1079,7 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
         __syncthreads();
         for (int i = tid; i < m; i += nt) {
           double v = zq[i];
-          for (int p = 0; p < np; ++p) v -= dots[p] * Z[(size_t)(c0 + p) * m + i];
+          for (int p = 0; p < np; ++p) v -= dots[p] * Z[(size_t)(pbase + p) * m + i];
           zq[i] = v;
         }
         __syncthreads();

@@ -314,8 +314,8 @@ __global__ void __launch_bounds__(kTriGridThreads)
 
 // Register-tile variant. The lower triangle of K is cut into 9 x 9 tiles (R, C), R >= C, one
 // tile per lane (81 FP64 registers); diagonal tiles hold the full symmetric block. Lanes are
-// ordered along the block diagonals d = R - C, so the lanes of one wave have (almost) distinct
-// tile rows and tile columns. Every sum is taken in a fixed order (no atomics), so the result
+// ordered by tile column, then tile row, so whole waves fall idle as the reduction moves
+// right. Every sum is taken in a fixed order (no atomics), so the result
 // is the same bit for bit on every run. Step k of the reduction is three phases and three
 // barriers:
 //   phase 1  apply the pending rank-2 update of step k-1, with w = p - (v^T p) v formed per lane
@@ -327,8 +327,7 @@ __global__ void __launch_bounds__(kTriGridThreads)
 //            the diagonal, column sums) into the slot of its partner block; each wave reduces
 //            its lanes' shares of v^T A v by a fixed shuffle tree; the diagonal lanes store v;
 //   phase 3  p[i] = the sum of its slots over the active partner blocks, in a fixed order.
-// v, p and v^T p are double-buffered by step parity. A slot row is 280 doubles long, so the
-// lanes of a wave (consecutive tile columns on one block diagonal) write to distinct banks.
+// v, p and v^T p are double-buffered by step parity.
 constexpr int kTB = 9;
 constexpr int kTileMaxNb = 31;  // m <= 279
 constexpr int kTileMaxThreads = 512;
@@ -407,8 +406,9 @@ __device__ __forceinline__ double kp_sum(const double *kw) {
   for (int i = 0; i < kKpWaves; ++i) s += kw[i];
   return s;
 }
-// p's partial sums: slot [partner block][entry], rows padded to 280 doubles
-constexpr int kPslotLd = kTB * kTileMaxNb + 1;
+// p's partial sums: slot [partner block][entry], rows of 281 doubles (odd, so the lanes of a
+// wave, one tile column and consecutive tile rows, write their column sums to distinct banks)
+constexpr int kPslotLd = kTB * kTileMaxNb + 2;
 
 __global__ void __launch_bounds__(kTileMaxThreads)
     tridiag_tile_kernel(int m, const double *__restrict__ K, double *__restrict__ work,
@@ -423,12 +423,16 @@ __global__ void __launch_bounds__(kTileMaxThreads)
   double *Hv = work + Lw.Hv, *dg = work + Lw.d, *eg = work + Lw.e;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int nb = tile_nb(m), mp = nb * kTB;
-  // lane -> tile along the block diagonals
-  int d = 0, C = tid;
-  while (d < nb && C >= nb - d) C -= nb - (d++);
-  const bool own = d < nb;
-  if (!own) C = 0;
-  const int r0 = (C + d) * kTB, c0 = C * kTB;
+  // lane -> tile by tile column, then row: the tiles of the left columns, which the
+  // reduction leaves first, fill the first waves, so whole waves fall idle as it proceeds
+  // and the waves still working get their SIMDs to themselves
+  int C = 0, R = tid;
+  while (C < nb && R >= nb - C) R -= nb - (C++);
+  const bool own = C < nb;
+  if (!own) C = 0, R = 0;
+  R += C;
+  const int d = R - C;
+  const int r0 = R * kTB, c0 = C * kTB;
   const bool diag = d == 0;
   double a[kTB][kTB];
 #pragma unroll

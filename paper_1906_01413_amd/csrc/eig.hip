@@ -664,10 +664,12 @@ __global__ void __launch_bounds__(256) root_kernel(int m, double *__restrict__ w
   const double tn = misc[0];
   const double pivmin = 1e-290 * fmax(1.0, tn * tn);
   // smallest eigenvalue by 256-way multisection on Sturm counts (8 bits per round) until the
-  // bracket is below eps * |T|, far under the shift margin's floor of 64 eps |T| below
+  // bracket is below eps * |T| or 2^-14 of its lower end: the shift below takes a margin of at
+  // least 1e-3 of that end (or 64 eps |T|), which a bracket 16 times narrower leaves intact
   for (int round = 0; round < 8; ++round) {
     const double lo = sh_lo, hi = sh_hi;
-    if (hi - lo <= 0x1.0p-52 * tn) break;  // the same shared values in every thread
+    // the same shared values in every thread
+    if (hi - lo <= fmax(0x1.0p-52 * tn, 0x1.0p-14 * fabs(lo))) break;
     const double x = lo + (hi - lo) * (tid + 1) / 257.0;
     const int c = sturm_count(m, dg, eg, x, pivmin);
     // smallest point with at least one eigenvalue below it: first lane per wave, then the
@@ -907,9 +909,11 @@ __global__ void __launch_bounds__(128) vector_kernel(int m, double *__restrict__
     __syncthreads();
     if (!done) {
       nrm2 = xn[0][l] + xn[1][l];
-      // Rayleigh-quotient correction of lam (gamma_r / ||z||^2), the same in both waves
+      // Rayleigh-quotient correction of lam (gamma_r / ||z||^2), the same in both waves; a
+      // correction within a few units of rounding of lam (the bisection's own tolerance) is
+      // rounding noise, and another pass would not change the vector
       const double corr = gmin / nrm2;
-      if (!(fabs(corr) > 2.0 * 0x1.0p-53 * fabs(lam)))
+      if (!(fabs(corr) > 8.0 * 0x1.0p-53 * fabs(lam)))
         done = true;
       else
         lam += corr;

@@ -328,6 +328,29 @@ __global__ void __launch_bounds__(kTriGridThreads)
 //            its lanes' shares of v^T A v by a fixed shuffle tree; the diagonal lanes store v;
 //   phase 3  p[i] = the sum of its slots over the active partner blocks, in a fixed order.
 // v, p and v^T p are double-buffered by step parity.
+// Sum over the wave, returned to every lane (the same value, bit for bit, in every wave for the
+// same inputs): DPP adds within each row of 16 lanes (quad_perm [1,0,3,2] and [2,3,0,1],
+// half-row mirror, row mirror), then row_bcast:15 and row_bcast:31 carry the row sums up to
+// lane 63, read back by v_readlane. No LDS traffic, unlike a ds_bpermute tree.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_add_src(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_add_src<0xB1, 0xf>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_add_src<0x4E, 0xf>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_add_src<0x141, 0xf>(v);  // row_half_mirror
+  v += dpp_add_src<0x140, 0xf>(v);  // row_mirror
+  v += dpp_add_src<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_add_src<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 constexpr int kTB = 9;
 constexpr int kTileMaxNb = 31;  // m <= 279
 constexpr int kTileMaxThreads = 512;
@@ -465,11 +488,9 @@ __global__ void __launch_bounds__(kTileMaxThreads)
     }
     __syncthreads();
     // phase 2
-    // |x|^2: the column block's slots summed by each wave's fixed shuffle tree, lane 0's sum
-    // broadcast (the same value, bit for bit, in every wave)
-    double s2 = (cb + (tid & 63) < nb) ? s2s[cb + (tid & 63)] : 0.0;
-    for (int off = 32; off > 0; off >>= 1) s2 += __shfl_down(s2, off, 64);
-    s2 = __shfl(s2, 0, 64);
+    // |x|^2: the column block's slots summed by each wave's fixed DPP tree (the same value,
+    // bit for bit, in every wave)
+    const double s2 = wave_sum_dpp((cb + (tid & 63) < nb) ? s2s[cb + (tid & 63)] : 0.0);
     const double x0 = xs[k + 1];
     // |x| = s2 / sqrt(s2) and 1 / |v| by reciprocal square roots: a short dependent chain
     const double sig = (s2 > 0.0) ? s2 * rsqrt(s2) : 0.0;
@@ -535,8 +556,8 @@ __global__ void __launch_bounds__(kTileMaxThreads)
         }
       }
     }
-    // the wave's share of v^T A v by a fixed shuffle tree
-    for (int off = 32; off > 0; off >>= 1) kpart += __shfl_xor(kpart, off, 64);
+    // the wave's share of v^T A v by the fixed DPP tree
+    kpart = wave_sum_dpp(kpart);
     if ((tid & 63) == 0) kpw[cur][tid >> 6] = kpart;
     __syncthreads();
     // phase 3: p on the rows below k from the slots of the active partner blocks (tiles whose

@@ -276,6 +276,7 @@ struct BlockLds {
   double Di[kPB][kPB + 1];  // out: Di[c][t] = (L11^{-1})[t][c], zero outside nb x nb
   __align__(16) double colk[2][16];  // column k of L11 by row parity: colk[i & 1][i >> 1]
   __align__(16) double yrow[2][16];  // row k of the unscaled inverse by column parity
+  double rdiag[kPB];                 // out without the inverse: about 1 / L11[i][i] (rsqrt)
 };
 
 // Cholesky of the SPD block held in S.D (rows and columns >= nb are ignored) and the inverse
@@ -295,11 +296,14 @@ struct BlockLds {
 // The inverse is built alongside as Y with X = L11^{-1} = diag(1 / L11[k][k]) Y: pivot k
 // takes (L11[i][k] / L11[k][k]) Y[k, :] from every row i > k, where Y[k, :] is final and
 // nonzero only in columns <= k; rows are scaled once at the end.
+// INV = false: no inverse (Di, use_inv untouched); S.rdiag[i] receives the pivot's reciprocal
+// square root, within about an ulp of 1 / L11[i][i], for a forward substitution.
 // A separate function (not inlined into the Cholesky kernel, whose other live values would
 // push it into spills) taking the LDS block by an address-space-3 reference, so that the
 // accesses stay plain ds_read/ds_write with immediate offsets.
 using LdsBlock = __attribute__((address_space(3))) BlockLds;
 using lds_double = __attribute__((address_space(3))) double;
+template <bool INV>
 __device__ __attribute__((noinline)) void factor_block32(LdsBlock &S, int nb, double fpiv,
                                                          bool &fail_out, bool &mod_out,
                                                          bool &use_inv_out) {
@@ -310,7 +314,7 @@ __device__ __attribute__((noinline)) void factor_block32(LdsBlock &S, int nb, do
     const int j = 2 * jj + h;
     const bool real = i < nb && j < nb;
     r[jj] = real ? (j <= i ? S.D[i][j] : 0.0) : (i == j ? 1.0 : 0.0);
-    y[jj] = (i == j) ? 1.0 : 0.0;
+    if constexpr (INV) y[jj] = (i == j) ? 1.0 : 0.0;
   }
   bool fail = false, modified = false;
   double myrinv = 1.0;  // 1 / L11[i][i]
@@ -340,7 +344,7 @@ __device__ __attribute__((noinline)) void factor_block32(LdsBlock &S, int nb, do
     }
     // lanes (k, 0) and (k, 1) publish row k of Y (columns <= k; the pairs' second entry
     // beyond k is zero)
-    if (i == k) {
+    if (INV && i == k) {
       lds_double *const ydst = &S.yrow[h][0];
 #pragma unroll
       for (int q = 0; q <= kk / 2; ++q) {
@@ -358,22 +362,35 @@ __device__ __attribute__((noinline)) void factor_block32(LdsBlock &S, int nb, do
       lj[2 * q] = colh[2 * q];
       lj[2 * q + 1] = colh[2 * q + 1];
     }
+    if constexpr (INV) {
 #pragma unroll
-    for (int q = 0; q <= kk / 2; ++q) {
-      yk[2 * q] = yrh[2 * q];
-      yk[2 * q + 1] = yrh[2 * q + 1];
+      for (int q = 0; q <= kk / 2; ++q) {
+        yk[2 * q] = yrh[2 * q];
+        yk[2 * q + 1] = yrh[2 * q + 1];
+      }
     }
 #pragma unroll
     for (int jj = jlo; jj < 16; ++jj) r[jj] = fma(-lik, lj[jj], r[jj]);
-    const double t = lik * rinv;  // L11[i][k] / L11[k][k], zero for i <= k
+    if constexpr (INV) {
+      const double t = lik * rinv;  // L11[i][k] / L11[k][k], zero for i <= k
 #pragma unroll
-    for (int jj = 0; jj <= kk; ++jj) y[jj] = fma(-t, yk[jj], y[jj]);
+      for (int jj = 0; jj <= kk; ++jj) y[jj] = fma(-t, yk[jj], y[jj]);
+    }
     // the updates happen here: without this the compiler defers the FMAs of columns needed
     // only at later pivots and keeps all their operands live (register spills)
 #pragma unroll
     for (int jj = jlo; jj < 16; ++jj) asm volatile("" : "+v"(r[jj]));
+    if constexpr (INV) {
 #pragma unroll
-    for (int jj = 0; jj <= kk; ++jj) asm volatile("" : "+v"(y[jj]));
+      for (int jj = 0; jj <= kk; ++jj) asm volatile("" : "+v"(y[jj]));
+    }
+  }
+  if constexpr (!INV) {
+    if (h == 0) S.rdiag[i] = (i < nb) ? myrinv : 0.0;
+    fail_out = fail;
+    mod_out = modified;
+    use_inv_out = false;
+    return;
   }
   // X = diag(1 / L11[i][i]) Y into Di (transposed), zero outside the nb x nb block
 #pragma unroll
@@ -527,9 +544,14 @@ __global__ void __launch_bounds__(kCholThreads)
     __syncthreads();
     // Factor the diagonal block held in S.D by wave 0 alone (factor_block32); no workgroup
     // barrier inside.
-    auto factor_block = [&](int nb) __attribute__((always_inline)) {
+    // inv: the block's inverse for a panel too tall to stage (a staged panel is solved by
+    // forward substitution, which needs only the pivots' reciprocals)
+    auto factor_block = [&](int nb, bool inv) __attribute__((always_inline)) {
       bool f, md, ui;
-      factor_block32(*(LdsBlock *)&S, nb, floor_piv, f, md, ui);
+      if (inv)
+        factor_block32<true>(*(LdsBlock *)&S, nb, floor_piv, f, md, ui);
+      else
+        factor_block32<false>(*(LdsBlock *)&S, nb, floor_piv, f, md, ui);
       if ((tid & 63) == 0) {
         if (f) bad = 1;
         if (md) modified = 1;
@@ -544,7 +566,7 @@ __global__ void __launch_bounds__(kCholThreads)
         S.D[i][j] = (i >= j) ? L[(size_t)j * m + i] : 0.0;
       }
       __syncthreads();
-      if (wave == 0) factor_block(nb);
+      if (wave == 0) factor_block(nb, m - nb > kStageRows);
       __syncthreads();
     }
     int cur = 0;        // Pbuf[cur] holds this block's panel
@@ -561,12 +583,11 @@ __global__ void __launch_bounds__(kCholThreads)
       if (dinv)
         for (int idx = tid; idx < kPB * kPB; idx += nt) Dc[idx >> 5][idx & 31] = S.D[idx >> 5][idx & 31];
 
-      // 2. panel rows below: X L11^T = A21 (the panel is staged in LDS first when it fits;
-      //    the result goes to L and to the staged copy). A well-conditioned block: X =
-      //    A21 L11^{-T}, one 32-row MFMA tile per wave. Otherwise the product with the
-      //    inverse leaves a residual of order kappa times rounding: a staged panel adds one
-      //    refinement step on MFMA, a panel too tall to stage is solved by forward
-      //    substitution per row, whose residual stays at rounding level.
+      // 2. panel rows below: X L11^T = A21. A staged panel (in LDS) is solved by forward
+      //    substitution along each row, one row per thread; the result goes to L and to the
+      //    staged copy. A panel too tall to stage: X = A21 L11^{-T} on MFMA, one 32-row tile
+      //    per wave, when the block is well conditioned (the product with the inverse leaves a
+      //    residual of order kappa times rounding), else forward substitution per row in L.
       const int r0 = kb + nb;
       const int prow = m - r0;
       const bool staged = prow <= kStageRows;
@@ -594,76 +615,28 @@ __global__ void __launch_bounds__(kCholThreads)
         }
       }
       __syncthreads();
-      if (!use_inv && staged) {
-        // ill-conditioned block, staged panel: X0 = A L11^{-T} (into L; A stays in the staged
-        // copy), R = A - X0 L11^T (into the staged copy), X = X0 + R L11^{-T}: one step of
-        // refinement brings the residual back to rounding level, on the matrix cores
-        const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
-        const int npt = (prow + 31) / 32, ld = kStageRows + 1;
-        for (int I = wave; I < npt; I += nwaves) {
-          const int i0 = 32 * I;
-          d4 acc[2][2];
-          zero_acc(acc);
-          wave_mma32<false, true>(Pn + i0, ld, &S.Di[0][0], kPB + 1, nb, prow - i0, nb, acc);
+      if (staged) {
+        // X L11^T = A by forward substitution along each row, one row per thread, from the
+        // staged panel: backward stable for any condition of L11 (no refinement needed).
+        // A panel below exists only under a full block (nb = 32).
+        if (tid < prow) {
+          const int ii = tid, ld = kStageRows + 1;
+          double x[kPB];
 #pragma unroll
-          for (int rt = 0; rt < 2; ++rt)
+          for (int j = 0; j < kPB; ++j) {
+            double a0 = Pn[j * ld + ii], a1 = 0.0;
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
+            for (int t = 0; t < j; t += 2) {
+              a0 = fma(-x[t], S.D[j][t], a0);
+              if (t + 1 < j) a1 = fma(-x[t + 1], S.D[j][t + 1], a1);
+            }
+            x[j] = (a0 + a1) * S.rdiag[j];
+          }
 #pragma unroll
-              for (int rr = 0; rr < 4; ++rr) {
-                const int row = i0 + 16 * rt + lg + 4 * rr, col = 16 * ct + li;
-                if (row < prow && col < nb) L[(size_t)(kb + col) * m + r0 + row] = acc[rt][ct][rr];
-              }
-        }
-        __syncthreads();
-        for (int I = wave; I < npt; I += nwaves) {
-          const int i0 = 32 * I;
-          d4 acc[2][2];
-          zero_acc(acc);
-          wave_mma32<false, false>(L + (size_t)kb * m + r0 + i0, m, &S.D[0][0], kPB + 1, nb,
-                                   prow - i0, nb, acc);
-#pragma unroll
-          for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-              for (int rr = 0; rr < 4; ++rr) {
-                const int row = i0 + 16 * rt + lg + 4 * rr, col = 16 * ct + li;
-                if (row < prow && col < nb) Pn[col * ld + row] -= acc[rt][ct][rr];
-              }
-        }
-        __syncthreads();
-        for (int I = wave; I < npt; I += nwaves) {
-          const int i0 = 32 * I;
-          double x0[2][2][4];  // X0 of these rows, loaded ahead of the products
-#pragma unroll
-          for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-              for (int rr = 0; rr < 4; ++rr) {
-                const int row = i0 + 16 * rt + lg + 4 * rr, col = 16 * ct + li;
-                const bool in = row < prow && col < nb;
-                x0[rt][ct][rr] = L[in ? (size_t)(kb + col) * m + r0 + row : 0];
-              }
-          d4 acc[2][2];
-          zero_acc(acc);
-          wave_mma32<false, true>(Pn + i0, ld, &S.Di[0][0], kPB + 1, nb, prow - i0, nb, acc);
-          // the MFMAs consumed every operand load of this wave's rows: overwrite them
-#pragma unroll
-          for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-              for (int rr = 0; rr < 4; ++rr) {
-                const int row = i0 + 16 * rt + lg + 4 * rr, col = 16 * ct + li;
-                if (row < prow && col < nb) {
-                  const size_t o = (size_t)(kb + col) * m + r0 + row;
-                  const double x = x0[rt][ct][rr] + acc[rt][ct][rr];
-                  L[o] = x;
-                  Pn[col * ld + row] = x;
-                }
-              }
+          for (int j = 0; j < kPB; ++j) {
+            Pn[j * ld + ii] = x[j];
+            L[(size_t)(kb + j) * m + r0 + ii] = x[j];
+          }
         }
       } else if (!use_inv) {
         // in place in the panel's own storage (global), row by row:
@@ -683,12 +656,8 @@ __global__ void __launch_bounds__(kCholThreads)
           const int i0 = 32 * I;
           d4 acc[2][2];
           zero_acc(acc);
-          if (staged)
-            wave_mma32<false, true>(Pn + i0, kStageRows + 1, &S.Di[0][0], kPB + 1, nb, prow - i0,
-                                    nb, acc);
-          else
-            wave_mma32<false, true>(L + (size_t)kb * m + r0 + i0, m, &S.Di[0][0], kPB + 1, nb,
-                                    prow - i0, nb, acc);
+          wave_mma32<false, true>(L + (size_t)kb * m + r0 + i0, m, &S.Di[0][0], kPB + 1, nb,
+                                  prow - i0, nb, acc);
           // the MFMAs consumed every operand load of this wave's rows: overwrite them
 #pragma unroll
           for (int rt = 0; rt < 2; ++rt)
@@ -697,10 +666,7 @@ __global__ void __launch_bounds__(kCholThreads)
 #pragma unroll
               for (int rr = 0; rr < 4; ++rr) {
                 const int row = i0 + 16 * rt + lg + 4 * rr, col = 16 * ct + li;
-                if (row < prow && col < nb) {
-                  L[(size_t)(kb + col) * m + r0 + row] = acc[rt][ct][rr];
-                  if (staged) Pn[col * (kStageRows + 1) + row] = acc[rt][ct][rr];
-                }
+                if (row < prow && col < nb) L[(size_t)(kb + col) * m + r0 + row] = acc[rt][ct][rr];
               }
         }
       }
@@ -770,7 +736,7 @@ __global__ void __launch_bounds__(kCholThreads)
           trailing_tile(0, true);
           asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
           __builtin_amdgcn_wave_barrier();
-          factor_block(min(kPB, prow));
+          factor_block(min(kPB, prow), prow - min(kPB, prow) > kStageRows);
           __builtin_amdgcn_s_setprio(0);
         }
       } else {
@@ -860,7 +826,7 @@ __global__ void __launch_bounds__(kCholThreads)
 
   auto factor_diag = [&]() {
     bool f, md, ui;
-    factor_block32(*(LdsBlock *)&S, nb, floor_piv, f, md, ui);
+    factor_block32<true>(*(LdsBlock *)&S, nb, floor_piv, f, md, ui);
     if (lane == 0) {
       if (f) bad = 1;
       if (md) modified = 1;

@@ -91,6 +91,132 @@ __global__ void __launch_bounds__(64)
       }
 }
 
+// The same product with a 64 x 64 tile of C per workgroup (four waves, each a 32 x 32
+// quarter) and the operands staged through LDS in chunks of 32 along K, double-buffered:
+// every element of A and B comes from global memory once per workgroup, by loads in which
+// consecutive lanes read consecutive addresses (along K for a transposed operand, along
+// the rows otherwise), and the next chunk is in flight while the current one's MFMAs issue.
+// Operand layouts in LDS: a transposed operand (A^T, or B as stored) by [row][k] with rows
+// of 33 doubles, the others by [k][row] with rows of 65.
+constexpr int kGT = 64;  // tile of C per workgroup
+constexpr int kGK = 32;  // K chunk
+
+template <int TA, int TB, bool LOWER = false>
+__global__ void __launch_bounds__(256)
+    gemm_lds_kernel(int M, int N, int K, const double *__restrict__ A, int lda,
+                    const double *__restrict__ B, int ldb, double *__restrict__ C, int ldc,
+                    double alpha, double beta, int kchunk, double *__restrict__ partial,
+                    const int *__restrict__ run) {
+  if (run && run[0] == 0) return;
+  const int m0 = blockIdx.x * kGT, n0 = blockIdx.y * kGT, kz = blockIdx.z;
+  if (m0 >= M || n0 >= N) return;
+  if (LOWER && blockIdx.y > blockIdx.x) return;  // symmetric result: tiles above the diagonal
+  // A tile: TA ? As[i][k] (ld 33) : As[k][i] (ld 65); B tile: TB ? Bs[k][j] (ld 65) : Bs[j][k] (ld 33)
+  constexpr int kSz = kGT * (kGK + 1) > kGK * (kGT + 1) ? kGT * (kGK + 1) : kGK * (kGT + 1);
+  __shared__ double As[2][kSz], Bs[2][kSz];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lg = lane >> 4;
+  const int wr = wave >> 1, wc = wave & 1;  // this wave's 32 x 32 quarter
+  const int kbeg = kz * kchunk, kend = min(K, kbeg + kchunk);
+  d4 acc[2][2];
+  zero_acc(acc);
+  // eight elements of each operand per thread and chunk
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      if (TA) {  // A[k + i lda]: lanes along k
+        const int kk = tid & 31, i = (tid >> 5) + 8 * p;
+        const bool in = m0 + i < M && k0 + kk < kend;
+        ra[p] = in ? A[(size_t)(m0 + i) * lda + k0 + kk] : 0.0;
+      } else {  // A[i + k lda]: lanes along i
+        const int i = tid & 63, kk = (tid >> 6) + 4 * p;
+        const bool in = m0 + i < M && k0 + kk < kend;
+        ra[p] = in ? A[(size_t)(k0 + kk) * lda + m0 + i] : 0.0;
+      }
+      if (TB) {  // B[j + k ldb]: lanes along j
+        const int j = tid & 63, kk = (tid >> 6) + 4 * p;
+        const bool in = n0 + j < N && k0 + kk < kend;
+        rb[p] = in ? B[(size_t)(k0 + kk) * ldb + n0 + j] : 0.0;
+      } else {  // B[k + j ldb]: lanes along k
+        const int kk = tid & 31, j = (tid >> 5) + 8 * p;
+        const bool in = n0 + j < N && k0 + kk < kend;
+        rb[p] = in ? B[(size_t)(n0 + j) * ldb + k0 + kk] : 0.0;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      if (TA) {
+        const int kk = tid & 31, i = (tid >> 5) + 8 * p;
+        As[buf][i * (kGK + 1) + kk] = ra[p];
+      } else {
+        const int i = tid & 63, kk = (tid >> 6) + 4 * p;
+        As[buf][kk * (kGT + 1) + i] = ra[p];
+      }
+      if (TB) {
+        const int j = tid & 63, kk = (tid >> 6) + 4 * p;
+        Bs[buf][kk * (kGT + 1) + j] = rb[p];
+      } else {
+        const int kk = tid & 31, j = (tid >> 5) + 8 * p;
+        Bs[buf][j * (kGK + 1) + kk] = rb[p];
+      }
+    }
+  };
+  if (kend > kbeg) {
+    load(kbeg);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += kGK) {
+      const bool more = k0 + kGK < kend;
+      if (more) load(k0 + kGK);  // in flight during this chunk's MFMAs
+      const double *as = As[buf], *bs = Bs[buf];
+#pragma unroll
+      for (int s = 0; s < kGK / 4; ++s) {
+        const int kk = 4 * s + lg;
+        double av[2], bv[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int i = 32 * wr + 16 * t + li, j = 32 * wc + 16 * t + li;
+          av[t] = TA ? as[i * (kGK + 1) + kk] : as[kk * (kGT + 1) + i];
+          bv[t] = TB ? bs[kk * (kGT + 1) + j] : bs[j * (kGK + 1) + kk];
+        }
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct)
+            acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rt], bv[ct], acc[rt][ct], 0, 0, 0);
+      }
+      if (more) {
+        store(buf ^ 1);  // the other buffer: its last readers finished before the barrier below
+        __syncthreads();
+        buf ^= 1;
+      }
+    }
+  }
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + 32 * wr + 16 * rt + lg + 4 * r;
+        const int col = n0 + 32 * wc + 16 * ct + li;
+        if (row < M && col < N) {
+          const double v = acc[rt][ct][r];
+          if (partial) {
+            partial[(size_t)kz * M * N + (size_t)col * M + row] = v;
+          } else {
+            double out = alpha * v;
+            if (beta != 0.0) out += beta * C[(size_t)col * ldc + row];
+            C[(size_t)col * ldc + row] = out;
+          }
+        }
+      }
+}
+
 // ints after the Gram's partial sums of squares used by the multi-workgroup Cholesky: one
 // "panel published" flag per 32-column block, then the breakdown and modified words
 constexpr int kCholMaxBlocks = 48;  // 1088 / 32 = 34 blocks at the largest sketch
@@ -1474,28 +1600,55 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   if (gram_sq && (!lower || !partial || K <= 0 || beta != 0.0)) return hipErrorInvalidValue;
   if (K <= 0) splitk = 1;
   if (splitk < 1 || !partial) splitk = 1;
+  // 64 x 64 tiles through LDS when both sides span a tile, else one wave per 32 x 32 tile
+  const bool big = M >= kGT && N >= kGT;
+  const int kround = big ? kGK : 4;
+  if (big && splitk > 1) {
+    // about one workgroup per CU: no more K splits than fill 256 CUs with the tiles
+    const int tm = (M + kGT - 1) / kGT, tn = (N + kGT - 1) / kGT;
+    const int tiles = lower ? tm * (tm + 1) / 2 : tm * tn;
+    splitk = std::max(1, std::min(splitk, 256 / tiles));
+  }
   int kchunk = (K + splitk - 1) / splitk;
-  kchunk = (kchunk + 3) / 4 * 4;
-  if (kchunk <= 0) kchunk = 4;
+  kchunk = (kchunk + kround - 1) / kround * kround;
+  if (kchunk <= 0) kchunk = kround;
   const int splits = K > 0 ? (K + kchunk - 1) / kchunk : 1;
-  dim3 grid((M + 31) / 32, (N + 31) / 32, splits);
   // the Gram-with-squares form always goes through the reduction, which writes them
   double *part = (splits > 1 || gram_sq) ? partial : nullptr;
+  if (big) {
+    dim3 grid((M + kGT - 1) / kGT, (N + kGT - 1) / kGT, splits);
+#define RIOT_GEMM_LDS(TA_, TB_, LO_)                                                            \
+  hipLaunchKernelGGL((gemm_lds_kernel<TA_, TB_, LO_>), grid, dim3(256), 0, st, M, N, K, A, lda, B, \
+                     ldb, C, ldc, alpha, beta, kchunk, part, run)
+    if (ta == 0 && tb == 0)
+      RIOT_GEMM_LDS(0, 0, false);
+    else if (ta == 1 && tb == 0 && lower)
+      RIOT_GEMM_LDS(1, 0, true);
+    else if (ta == 1 && tb == 0)
+      RIOT_GEMM_LDS(1, 0, false);
+    else if (ta == 0 && tb == 1)
+      RIOT_GEMM_LDS(0, 1, false);
+    else
+      RIOT_GEMM_LDS(1, 1, false);
+#undef RIOT_GEMM_LDS
+  } else {
+    dim3 grid((M + 31) / 32, (N + 31) / 32, splits);
 #define RIOT_GEMM(TA_, TB_)                                                                  \
   hipLaunchKernelGGL((gemm_mfma_kernel<TA_, TB_>), grid, dim3(64), 0, st, M, N, K, A, lda, B, \
                      ldb, C, ldc, alpha, beta, kchunk, part, run, nullptr, 0, 0, 0)
-  if (ta == 0 && tb == 0)
-    RIOT_GEMM(0, 0);
-  else if (ta == 1 && tb == 0 && lower)
-    hipLaunchKernelGGL((gemm_mfma_kernel<1, 0, true>), grid, dim3(64), 0, st, M, N, K, A, lda, B, ldb,
-                       C, ldc, alpha, beta, kchunk, part, run, nullptr, 0, 0, 0);
-  else if (ta == 1 && tb == 0)
-    RIOT_GEMM(1, 0);
-  else if (ta == 0 && tb == 1)
-    RIOT_GEMM(0, 1);
-  else
-    RIOT_GEMM(1, 1);
+    if (ta == 0 && tb == 0)
+      RIOT_GEMM(0, 0);
+    else if (ta == 1 && tb == 0 && lower)
+      hipLaunchKernelGGL((gemm_mfma_kernel<1, 0, true>), grid, dim3(64), 0, st, M, N, K, A, lda, B,
+                         ldb, C, ldc, alpha, beta, kchunk, part, run, nullptr, 0, 0, 0);
+    else if (ta == 1 && tb == 0)
+      RIOT_GEMM(1, 0);
+    else if (ta == 0 && tb == 1)
+      RIOT_GEMM(0, 1);
+    else
+      RIOT_GEMM(1, 1);
 #undef RIOT_GEMM
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (part) {

@@ -101,16 +101,42 @@ __global__ void __launch_bounds__(64)
 constexpr int kGT = 64;  // tile of C per workgroup
 constexpr int kGK = 32;  // K chunk
 
+// XCD-aware order (xcd_split > 0, a one-dimensional grid of tiles x splits workgroups):
+// workgroup L runs on XCD L % 8 (the dispatcher deals workgroups to the eight XCDs in turn),
+// and all workgroups of one K split go to the same XCD, so that the split's slices of A and
+// B, shared by all its tiles, are read into that XCD's L2 once. Without splits (xcd_split
+// < 0), the tiles of one 64-row block of C share an XCD (their common rows of A).
+constexpr int kXcds = 8;
+
 template <int TA, int TB, bool LOWER = false>
 __global__ void __launch_bounds__(256)
     gemm_lds_kernel(int M, int N, int K, const double *__restrict__ A, int lda,
                     const double *__restrict__ B, int ldb, double *__restrict__ C, int ldc,
                     double alpha, double beta, int kchunk, double *__restrict__ partial,
-                    const int *__restrict__ run) {
+                    const int *__restrict__ run, int xcd_split) {
   if (run && run[0] == 0) return;
-  const int m0 = blockIdx.x * kGT, n0 = blockIdx.y * kGT, kz = blockIdx.z;
+  int bx = blockIdx.x, by = blockIdx.y, kz = blockIdx.z;
+  if (xcd_split != 0) {
+    const int L = blockIdx.x, xcd = L % kXcds, slot = L / kXcds;
+    const int tm = (M + kGT - 1) / kGT, tn = (N + kGT - 1) / kGT;
+    if (xcd_split > 0) {  // LOWER: tiles numbered along the lower triangle
+      const int tiles = LOWER ? tm * (tm + 1) / 2 : tm * tn;
+      int t = slot % tiles;
+      kz = (slot / tiles) * kXcds + xcd;
+      if (LOWER) {
+        bx = 0;
+        while (t > bx) t -= ++bx;
+        by = t;
+      } else {
+        bx = t % tm, by = t / tm;
+      }
+    } else {  // tm a multiple of 8
+      bx = (slot / tn) * kXcds + xcd, by = slot % tn, kz = 0;
+    }
+  }
+  const int m0 = bx * kGT, n0 = by * kGT;
   if (m0 >= M || n0 >= N) return;
-  if (LOWER && blockIdx.y > blockIdx.x) return;  // symmetric result: tiles above the diagonal
+  if (LOWER && by > bx) return;  // symmetric result: tiles above the diagonal
   // A tile: TA ? As[i][k] (ld 33) : As[k][i] (ld 65); B tile: TB ? Bs[k][j] (ld 65) : Bs[j][k] (ld 33)
   constexpr int kSz = kGT * (kGK + 1) > kGK * (kGT + 1) ? kGT * (kGK + 1) : kGK * (kGT + 1);
   __shared__ double As[2][kSz], Bs[2][kSz];
@@ -120,32 +146,36 @@ __global__ void __launch_bounds__(256)
   const int kbeg = kz * kchunk, kend = min(K, kbeg + kchunk);
   d4 acc[2][2];
   zero_acc(acc);
-  // eight elements of each operand per thread and chunk
-  double ra[8], rb[8];
-  auto load = [&](int k0) {
+  // eight elements of each operand per thread and chunk, two chunks in flight
+  auto load = [&](double (&ra)[8], double (&rb)[8], int k0) {
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
+      // unconditional loads at a clamped address, the value selected (no branch per load)
       if (TA) {  // A[k + i lda]: lanes along k
         const int kk = tid & 31, i = (tid >> 5) + 8 * p;
         const bool in = m0 + i < M && k0 + kk < kend;
-        ra[p] = in ? A[(size_t)(m0 + i) * lda + k0 + kk] : 0.0;
+        const double v = A[in ? (size_t)(m0 + i) * lda + k0 + kk : 0];
+        ra[p] = in ? v : 0.0;
       } else {  // A[i + k lda]: lanes along i
         const int i = tid & 63, kk = (tid >> 6) + 4 * p;
         const bool in = m0 + i < M && k0 + kk < kend;
-        ra[p] = in ? A[(size_t)(k0 + kk) * lda + m0 + i] : 0.0;
+        const double v = A[in ? (size_t)(k0 + kk) * lda + m0 + i : 0];
+        ra[p] = in ? v : 0.0;
       }
       if (TB) {  // B[j + k ldb]: lanes along j
         const int j = tid & 63, kk = (tid >> 6) + 4 * p;
         const bool in = n0 + j < N && k0 + kk < kend;
-        rb[p] = in ? B[(size_t)(k0 + kk) * ldb + n0 + j] : 0.0;
+        const double v = B[in ? (size_t)(k0 + kk) * ldb + n0 + j : 0];
+        rb[p] = in ? v : 0.0;
       } else {  // B[k + j ldb]: lanes along k
         const int kk = tid & 31, j = (tid >> 5) + 8 * p;
         const bool in = n0 + j < N && k0 + kk < kend;
-        rb[p] = in ? B[(size_t)(n0 + j) * ldb + k0 + kk] : 0.0;
+        const double v = B[in ? (size_t)(n0 + j) * ldb + k0 + kk : 0];
+        rb[p] = in ? v : 0.0;
       }
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](const double (&ra)[8], const double (&rb)[8], int buf) {
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
       if (TA) {
@@ -164,36 +194,45 @@ __global__ void __launch_bounds__(256)
       }
     }
   };
-  if (kend > kbeg) {
-    load(kbeg);
-    store(0);
+  auto compute = [&](int buf) {
+    const double *as = As[buf], *bs = Bs[buf];
+#pragma unroll
+    for (int s = 0; s < kGK / 4; ++s) {
+      const int kk = 4 * s + lg;
+      double av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int i = 32 * wr + 16 * t + li, j = 32 * wc + 16 * t + li;
+        av[t] = TA ? as[i * (kGK + 1) + kk] : as[kk * (kGT + 1) + i];
+        bv[t] = TB ? bs[kk * (kGT + 1) + j] : bs[j * (kGK + 1) + kk];
+      }
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rt], bv[ct], acc[rt][ct], 0, 0, 0);
+    }
+  };
+  const int nch = (kend - kbeg + kGK - 1) / kGK;
+  if (nch > 0) {
+    // chunk c is in LDS buffer c & 1; chunk c + 1 waits in registers; chunk c + 2 is loaded
+    // while chunk c computes (the loop body is written out for even and odd c)
+    double ra0[8], rb0[8], ra1[8], rb1[8];
+    load(ra0, rb0, kbeg);
+    if (nch > 1) load(ra1, rb1, kbeg + kGK);
+    store(ra0, rb0, 0);
     __syncthreads();
-    int buf = 0;
-    for (int k0 = kbeg; k0 < kend; k0 += kGK) {
-      const bool more = k0 + kGK < kend;
-      if (more) load(k0 + kGK);  // in flight during this chunk's MFMAs
-      const double *as = As[buf], *bs = Bs[buf];
-#pragma unroll
-      for (int s = 0; s < kGK / 4; ++s) {
-        const int kk = 4 * s + lg;
-        double av[2], bv[2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const int i = 32 * wr + 16 * t + li, j = 32 * wc + 16 * t + li;
-          av[t] = TA ? as[i * (kGK + 1) + kk] : as[kk * (kGT + 1) + i];
-          bv[t] = TB ? bs[kk * (kGT + 1) + j] : bs[j * (kGK + 1) + kk];
-        }
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-          for (int ct = 0; ct < 2; ++ct)
-            acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rt], bv[ct], acc[rt][ct], 0, 0, 0);
-      }
-      if (more) {
-        store(buf ^ 1);  // the other buffer: its last readers finished before the barrier below
-        __syncthreads();
-        buf ^= 1;
-      }
+    for (int c = 0; c < nch; c += 2) {
+      if (c + 2 < nch) load(ra0, rb0, kbeg + (c + 2) * kGK);
+      compute(0);
+      if (c + 1 >= nch) break;
+      store(ra1, rb1, 1);  // buffer 1's last readers passed the barrier below, one chunk ago
+      __syncthreads();
+      if (c + 3 < nch) load(ra1, rb1, kbeg + (c + 3) * kGK);
+      compute(1);
+      if (c + 2 >= nch) break;
+      store(ra0, rb0, 0);
+      __syncthreads();
     }
   }
 #pragma unroll
@@ -1603,12 +1642,11 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   // 64 x 64 tiles through LDS when both sides span a tile, else one wave per 32 x 32 tile
   const bool big = M >= kGT && N >= kGT;
   const int kround = big ? kGK : 4;
-  if (big && splitk > 1) {
-    // about one workgroup per CU: no more K splits than fill 256 CUs with the tiles
-    const int tm = (M + kGT - 1) / kGT, tn = (N + kGT - 1) / kGT;
-    const int tiles = lower ? tm * (tm + 1) / 2 : tm * tn;
-    splitk = std::max(1, std::min(splitk, 256 / tiles));
-  }
+  const int tm = (M + kGT - 1) / kGT, tn = (N + kGT - 1) / kGT;
+  const int tiles = lower ? tm * (tm + 1) / 2 : tm * tn;
+  // about one workgroup per CU: no more K splits than fill 256 CUs with the tiles (when that
+  // is a multiple of 8, each split's workgroups share an XCD, see gemm_lds_kernel)
+  if (big && splitk > 1) splitk = std::max(1, std::min(splitk, 256 / tiles));
   int kchunk = (K + splitk - 1) / splitk;
   kchunk = (kchunk + kround - 1) / kround * kround;
   if (kchunk <= 0) kchunk = kround;
@@ -1616,10 +1654,16 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   // the Gram-with-squares form always goes through the reduction, which writes them
   double *part = (splits > 1 || gram_sq) ? partial : nullptr;
   if (big) {
-    dim3 grid((M + kGT - 1) / kGT, (N + kGT - 1) / kGT, splits);
+    dim3 grid(tm, tn, splits);
+    int xs = 0;
+    if (splits % kXcds == 0) {
+      xs = 1, grid = dim3((unsigned)(tiles * splits), 1, 1);
+    } else if (splits == 1 && !lower && tm % kXcds == 0) {
+      xs = -1, grid = dim3((unsigned)(tm * tn), 1, 1);
+    }
 #define RIOT_GEMM_LDS(TA_, TB_, LO_)                                                            \
   hipLaunchKernelGGL((gemm_lds_kernel<TA_, TB_, LO_>), grid, dim3(256), 0, st, M, N, K, A, lda, B, \
-                     ldb, C, ldc, alpha, beta, kchunk, part, run)
+                     ldb, C, ldc, alpha, beta, kchunk, part, run, xs)
     if (ta == 0 && tb == 0)
       RIOT_GEMM_LDS(0, 0, false);
     else if (ta == 1 && tb == 0 && lower)

@@ -1518,8 +1518,10 @@ __device__ __forceinline__ bool use_lru(int mode_lru, const double *lam, int k) 
 
 // Rows are split four ways: a workgroup takes 64 rows, wave w sums the columns j = w (mod 4)
 // of each row, and the four partial sums are added in a fixed order through LDS, so a row's
-// dependent chain is k / 4 long (and deterministic).
+// dependent chain is k / 4 long (and deterministic). The per-column factors (a division
+// each) are formed once per workgroup into LDS, kCoefChunk columns at a time.
 constexpr int kRowsPerWg = 64;
+constexpr int kCoefChunk = 1024;
 
 __global__ void __launch_bounds__(256)
     increment_kernel(int n, int k, const double *__restrict__ lam,
@@ -1532,16 +1534,24 @@ __global__ void __launch_bounds__(256)
     n = J.n, k = J.k, lam = J.lam, V = J.V, c = J.c, g = J.g, dz = J.dz, dofs = J.dofs;
   }
   __shared__ double part[4][kRowsPerWg];
+  __shared__ double cf[kCoefChunk];  // c_j times the filter factor, a chunk of j at a time
+  __shared__ double red[16];
   const bool lru = use_lru(mode_lru, lam, k);
   const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = blockIdx.x * kRowsPerWg + r;
   double s = 0.0;
-  if (i < n) {
-#pragma unroll 4
-    for (int j = w; j < k; j += 4) {
-      const double lj = lam[j];
+  for (int j0 = 0; j0 < k; j0 += kCoefChunk) {
+    const int jn = min(kCoefChunk, k - j0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < jn; t += blockDim.x) {
+      const double lj = lam[j0 + t];
       const double a = lru ? lj / (1.0 + lj) : 1.0 / (1.0 + lj);
-      s += V[(size_t)j * n + i] * (c[j] * a);
+      cf[t] = c[j0 + t] * a;
+    }
+    __syncthreads();
+    if (i < n) {
+#pragma unroll 4
+      for (int j = w; j < jn; j += 4) s += V[(size_t)(j0 + j) * n + i] * cf[j];
     }
   }
   part[w][r] = s;
@@ -1550,10 +1560,11 @@ __global__ void __launch_bounds__(256)
     const double t = (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
     dz[i] = lru ? -(g[i] - t) : -t;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && dofs) {
+  if (blockIdx.x == 0 && dofs) {  // sum of lambda / (1 + lambda), fixed order
     double d = 0.0;
-    for (int j = 0; j < k; ++j) d += lam[j] / (1.0 + lam[j]);
-    dofs[0] = d;
+    for (int j = threadIdx.x; j < k; j += blockDim.x) d += lam[j] / (1.0 + lam[j]);
+    d = wg_sum(d, red);
+    if (threadIdx.x == 0) dofs[0] = d;
   }
 }
 
@@ -1567,6 +1578,7 @@ __global__ void __launch_bounds__(256)
                         const double *__restrict__ W, int mode_lru, double base_diag,
                         double *__restrict__ coef, double *__restrict__ diag) {
   __shared__ double part[4][kRowsPerWg];
+  __shared__ double cf[kCoefChunk];
   const bool lru = use_lru(mode_lru, lam, k);
   if (blockIdx.x == 0 && coef) {
     for (int j = threadIdx.x; j < k; j += blockDim.x) {
@@ -1578,13 +1590,20 @@ __global__ void __launch_bounds__(256)
   const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = blockIdx.x * kRowsPerWg + r;
   double s = 0.0;
-  if (i < n) {
+  for (int j0 = 0; j0 < k; j0 += kCoefChunk) {
+    const int jn = min(kCoefChunk, k - j0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < jn; t += blockDim.x) {
+      const double lj = lam[j0 + t];
+      cf[t] = lru ? -lj / (1.0 + lj) : 1.0 / (1.0 + lj);
+    }
+    __syncthreads();
+    if (i < n) {
 #pragma unroll 4
-    for (int j = w; j < k; j += 4) {
-      const double lj = lam[j];
-      const double cj = lru ? -lj / (1.0 + lj) : 1.0 / (1.0 + lj);
-      const double x = W[(size_t)j * n + i];
-      s += cj * x * x;
+      for (int j = w; j < jn; j += 4) {
+        const double x = W[(size_t)(j0 + j) * n + i];
+        s += cf[j] * x * x;
+      }
     }
   }
   part[w][r] = s;

@@ -959,23 +959,26 @@ __global__ void __launch_bounds__(128) vector_kernel(int m, double *__restrict__
 constexpr int kMaxCluster = 48;
 
 // Cluster list: where the relative gap between neighbouring mu is below 1e-3, at most
-// kMaxCluster per cluster, scanned in order by one thread from the mu of the vector step. A
-// longer run is cut into a chain of clusters, each after the first marked as continuing the
-// one before (it may then be a single index). list[0] = number of clusters;
+// kMaxCluster per cluster; the neighbour gaps of the vector step's mu are tested in
+// parallel, then scanned in order by one thread. A longer run is cut into a chain of
+// clusters, each after the first marked as continuing the one before (it may then be a
+// single index). list[0] = number of clusters;
 // list[1 + 3 g .. 3 + 3 g] = first index, last index, continuation flag of cluster g. The
 // list sits after the m x m part of the scratch that the cluster kernel uses for T Z_c.
 __global__ void __launch_bounds__(64) cluster_scan_kernel(int m, double *__restrict__ work,
                                                           const EigJob *__restrict__ jobs) {
   if (jobs) m = jobs[blockIdx.y].m, work = jobs[blockIdx.y].work;
   EigLayout Lw(m);
-  __shared__ double mu[kEigMaxM];  // staged by the wave: the scan reads each value twice
-  for (int i = threadIdx.x; i < m; i += blockDim.x) mu[i] = work[Lw.mu + i];
+  // the gap tests in parallel (one flag per neighbour pair), then the scan by one thread
+  __shared__ unsigned char cl[kEigMaxM];
+  for (int i = threadIdx.x; i + 1 < m; i += blockDim.x) {
+    const double a = work[Lw.mu + i], b = work[Lw.mu + i + 1];
+    cl[i] = fabs(b - a) < 1e-3 * fmax(fabs(b), fabs(a)) ? 1 : 0;
+  }
   __syncthreads();
   if (threadIdx.x != 0) return;
   int *list = reinterpret_cast<int *>(work + Lw.scr + (size_t)m * m);
-  auto close = [&](int i) {
-    return fabs(mu[i + 1] - mu[i]) < 1e-3 * fmax(fabs(mu[i + 1]), fabs(mu[i]));
-  };
+  auto close = [&](int i) { return cl[i] != 0; };
   int cnt = 0, a = 0;
   bool cont = false;
   while (a < m) {

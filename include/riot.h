@@ -22,7 +22,8 @@
  *  - Every call enqueues work on the HIP stream given to riot_init and returns
  *    once enqueued, except where a host output pointer (J_host, dofs_host,
  *    info, used, mode_used) is non-NULL: then the call synchronises the stream
- *    to fill it.
+ *    to fill it; and except that the calls running CholeskyQR wait for its pass
+ *    decisions (riot_set_pass_sync).
  *  - Errors are returned as riot_status; nothing aborts and no exception
  *    crosses the ABI. Argument errors are detected before any work is
  *    enqueued. Numerical failures detected on the device (breakdown,
@@ -114,6 +115,18 @@ riot_status riot_init(const riot_desc *desc, void *workspace, size_t bytes,
 
 /* Release host state (the workspace stays the caller's). NULL is accepted. */
 void riot_free(riot_handle *h);
+
+/* CholeskyQR pass control (the adaptive passes of the orthonormalisation in Alg. 3, see
+ * riot_rsvd). on != 0 (the default): the calls that orthonormalise a block (riot_rsvd,
+ * riot_orth, riot_block_lanczos) launch the passes that always run, then each further pass
+ * only once the previous pass's Cholesky has reported, through a word of pinned host memory
+ * that riot_init allocates, that it is needed: the call waits on the device for those
+ * reports (not for the pass's triangular solve), so it returns later than the rest of its
+ * work is enqueued, and no unneeded pass is launched. on == 0, or while the handle's stream
+ * is being captured into a graph: every pass is launched and the unneeded ones return at
+ * once on the device; the calls then only enqueue. Results are the same either way.
+ * Returns RIOT_E_ARG for a NULL handle. */
+riot_status riot_set_pass_sync(riot_handle *h, int32_t on);
 
 /* Human-readable name of a status code (static string). */
 const char *riot_status_str(riot_status s);

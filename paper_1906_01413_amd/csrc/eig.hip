@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(kTileMaxThreads)
   __shared__ double kpw[2][kKpWaves];            // v^T A v parts, one per wave
   __shared__ double pslot[kTileMaxNb * kPslotLd];  // p's parts, one per (partner block, entry)
   EigLayout Lw(m);
-  double *Hv = work + Lw.Hv, *dg = work + Lw.d, *eg = work + Lw.e;
+  gmem<double> *Hv = gptr(work + Lw.Hv), *dg = gptr(work + Lw.d), *eg = gptr(work + Lw.e);
   const int tid = threadIdx.x, nt = blockDim.x;
   const int nb = tile_nb(m), mp = nb * kTB;
   // lane -> tile by tile column, then row: the tiles of the left columns, which the
@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(kTileMaxThreads)
 #pragma unroll
     for (int s = 0; s < kTB; ++s) {
       const int i = r0 + t, j = c0 + s;
-      a[t][s] = (own && i < m && j < m) ? K[(size_t)min(i, j) * m + max(i, j)] : 0.0;
+      a[t][s] = (own && i < m && j < m) ? gptr(K)[(size_t)min(i, j) * m + max(i, j)] : 0.0;
     }
   for (int i = tid; i < mp; i += nt) {
     vb[0][i] = vb[1][i] = 0.0;

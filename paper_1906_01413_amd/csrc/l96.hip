@@ -181,7 +181,7 @@ template <int E>
 __device__ void store_block(double *xs64, float *xs32, int t, int s, int E_, int NT, int l,
                             const double (&v)[E], double hl2, double hl1, double hr1, double hr2) {
   const size_t base = (size_t)(t * 4 + s) * (size_t)(E_ + 4) * NT;
-  double *b = xs64 + base;
+  gmem<double> *b = gptr(xs64 + base);
 #pragma unroll
   for (int j = 0; j < E; ++j) b[j * NT + l] = v[j];
   b[(E + 0) * NT + l] = hl2;
@@ -189,7 +189,7 @@ __device__ void store_block(double *xs64, float *xs32, int t, int s, int E_, int
   b[(E + 2) * NT + l] = hr1;
   b[(E + 3) * NT + l] = hr2;
   if (xs32) {
-    float *c = xs32 + base;
+    gmem<float> *c = gptr(xs32 + base);
 #pragma unroll
     for (int j = 0; j < E; ++j) c[j * NT + l] = (float)v[j];
     c[(E + 0) * NT + l] = (float)hl2;
@@ -204,13 +204,13 @@ __device__ void store_block(double *xs64, float *xs32, int t, int s, int E_, int
 template <int E>
 __device__ __forceinline__ void sample_obs(const ModelView &mv, int t, int l,
                                            const double (&x)[E], double *__restrict__ xu) {
-  const int k = mv.stepk[t];
+  const int k = gptr(mv.stepk)[t];
   if (k < 0) return;
-  const int us = mv.ustart[k * mv.NT + l];
-  const unsigned mask = (unsigned)mv.umask[k * mv.NT + l];
+  const int us = gptr(mv.ustart)[k * mv.NT + l];
+  const unsigned mask = (unsigned)gptr(mv.umask)[k * mv.NT + l];
 #pragma unroll
   for (int j = 0; j < E; ++j)
-    if ((mask >> j) & 1u) xu[us + __popc(mask & ((1u << j) - 1u))] = x[j];
+    if ((mask >> j) & 1u) gptr(xu)[us + __popc(mask & ((1u << j) - 1u))] = x[j];
 }
 
 template <int E>
@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
   double x[E], xs[E], acc[E], k[E], xe[E + 4];
   double hl2 = 0, hl1 = 0, hr1 = 0, hr2 = 0;
 #pragma unroll
-  for (int j = 0; j < E; ++j) x[j] = active ? x0[a + j] : 0.0;
+  for (int j = 0; j < E; ++j) x[j] = active ? gptr(x0)[a + j] : 0.0;
 
   auto build = [&](const double (&v)[E]) {
     xe[0] = hl2;
@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
   }
   if (xout && active) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) xout[a + j] = x[j];
+    for (int j = 0; j < E; ++j) gptr(xout)[a + j] = x[j];
   }
 }
 
@@ -611,9 +611,19 @@ struct MemberRing {
   TrajRsrc tr;
   int blk_bytes;  // bytes per stored stage block, (E + 4) NT sizeof(Real)
   int nblk;       // 4 T stage blocks per sweep
+  // the observation tables, read-only for the whole launch (kernel arguments declared
+  // __restrict__, so that the uniform step table is read by scalar loads and no read of
+  // them waits on the ring copies in flight)
+  const int *__restrict__ stepk;
+  const int *__restrict__ ustart;
+  const int *__restrict__ umask;
+  const Real *__restrict__ wgt;
 
-  __device__ MemberRing(const ModelView &m, Real *xch_, Real *ring_, int tid)
-      : mv(m), xch(xch_), ring(ring_), l(tid % NT), parity(0) {
+  __device__ MemberRing(const ModelView &m, Real *xch_, Real *ring_, int tid,
+                        const int *__restrict__ stepk_, const int *__restrict__ ustart_,
+                        const int *__restrict__ umask_, const Real *__restrict__ wgt_)
+      : mv(m), xch(xch_), ring(ring_), l(tid % NT), parity(0), stepk(stepk_), ustart(ustart_),
+        umask(umask_), wgt(wgt_) {
     hm.init(l, mv.n, NT);
     lm = (l + NT - 1) % NT;
     lp = (l + 1) % NT;
@@ -674,8 +684,8 @@ struct MemberRing {
   // same single product as weighting at the store): the TL then only stores, and never
   // waits on a load, which would also wait for the ring copies in flight.
   __device__ __forceinline__ void tl_store(int k, const Real (&dl)[E], Real *__restrict__ f) {
-    const int us = mv.ustart[k * NT + l];
-    const unsigned mask = (unsigned)mv.umask[k * NT + l];
+    const int us = ustart[k * NT + l];
+    const unsigned mask = (unsigned)umask[k * NT + l];
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       if ((mask >> j) & 1u) {
@@ -686,9 +696,8 @@ struct MemberRing {
   }
 
   __device__ __forceinline__ void ad_inject(int k, Real (&lam)[E], const Real *__restrict__ f) {
-    const int us = mv.ustart[k * NT + l];
-    const unsigned mask = (unsigned)mv.umask[k * NT + l];
-    const Real *wgt = reinterpret_cast<const Real *>(mv.wgt);
+    const int us = ustart[k * NT + l];
+    const unsigned mask = (unsigned)umask[k * NT + l];
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       if ((mask >> j) & 1u) {
@@ -722,7 +731,7 @@ struct MemberRing {
     if (nblk > 2) fill<2>(2);
     // tangent-linear sweep, blocks 0 .. 4T-1 (block 4t + s in slot s)
     for (int t = 0; t <= mv.T; ++t) {
-      const int k = mv.stepk[t];
+      const int k = stepk[t];
       if (k >= 0) tl_store(k, dl, f);
       if (t == mv.T) break;
       const int b0 = 4 * t;
@@ -764,7 +773,7 @@ struct MemberRing {
 #pragma unroll
     for (int j = 0; j < E; ++j) lam[j] = 0;
     for (int t = mv.T; t >= 0; --t) {
-      const int k = mv.stepk[t];
+      const int k = stepk[t];
       if (k >= 0) ad_inject(k, lam, f);
       if (t == 0) break;
       const int b3 = 4 * (t - 1) + 3;
@@ -815,13 +824,16 @@ struct MemberRing {
 template <typename Real, int E>
 __global__ void __launch_bounds__(kRingMembers * kRingNT)
     tlad_ring_kernel(ModelView mv, int m, const double *__restrict__ dx0,
-                     double *__restrict__ lam0, Real *__restrict__ f) {
+                     double *__restrict__ lam0, Real *__restrict__ f,
+                     const int *__restrict__ stepk, const int *__restrict__ ustart,
+                     const int *__restrict__ umask, const Real *__restrict__ wgt) {
   __shared__ __align__(16) Real ring[kRingSlots * E * kRingNT];
   __shared__ __align__(16) Real xch[kRingMembers * 2 * kLdsSlots * kRingNT];
   const int q = threadIdx.x / kRingNT;
   const int mem = blockIdx.x * kRingMembers + q;
   const int src = mem < m ? mem : m - 1;
-  MemberRing<Real, E> M(mv, xch + q * 2 * kLdsSlots * kRingNT, ring, threadIdx.x);
+  MemberRing<Real, E> M(mv, xch + q * 2 * kLdsSlots * kRingNT, ring, threadIdx.x, stepk, ustart,
+                        umask, wgt);
   M.run(dx0 + (size_t)src * mv.n, mem < m ? lam0 + (size_t)mem * mv.n : nullptr,
         f + (size_t)mem * (size_t)mv.U);
 }
@@ -1392,10 +1404,12 @@ hipError_t launch_tlad(const ModelView &mv, int m, int mode, const double *dx0, 
     const dim3 grid((m + kRingMembers - 1) / kRingMembers), block(kRingMembers * kRingNT);
     if (fp32)
       hipLaunchKernelGGL((tlad_ring_kernel<float, 16>), grid, block, 0, st, mv, m, dx0, lam0,
-                         reinterpret_cast<float *>(f));
+                         reinterpret_cast<float *>(f), mv.stepk, mv.ustart, mv.umask,
+                         reinterpret_cast<const float *>(mv.wgt));
     else
       hipLaunchKernelGGL((tlad_ring_kernel<double, 16>), grid, block, 0, st, mv, m, dx0, lam0,
-                         reinterpret_cast<double *>(f));
+                         reinterpret_cast<double *>(f), mv.stepk, mv.ustart, mv.umask,
+                         reinterpret_cast<const double *>(mv.wgt));
     return hipGetLastError();
   }
 #define RIOT_TLAD(R_, F_, U_)                                                                   \

@@ -369,11 +369,19 @@ constexpr double kCholFirstOrderDev2 = 0x1.0p-53;
 
 // End of a CholeskyQR pass (one thread): count it, update the clean-pass count and set the
 // next pass's run flag.
-__device__ void cholqr_ctl_end(const CholQrCtl &c, bool shifted, bool modified, bool bad) {
+__device__ __noinline__ void cholqr_notify(const CholQrCtl &c, int next) {
+  if (c.host)
+    __hip_atomic_store(c.host, (int)((unsigned)c.seq << 1) | next, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __noinline__ void cholqr_ctl_end(const CholQrCtl &c, bool shifted, bool modified, bool bad) {
   if (c.count) c.count[0] += 1;
   int &clean = c.cq[c.npass];
   clean = (!shifted && !modified && !bad) ? clean + 1 : 0;
-  if (c.pass + 1 < c.npass) c.cq[c.pass + 1] = (clean < 2 && !bad) ? 1 : 0;
+  const int next = (c.pass + 1 < c.npass && clean < 2 && !bad) ? 1 : 0;
+  if (c.pass + 1 < c.npass) c.cq[c.pass + 1] = next;
+  cholqr_notify(c, next);
 }
 
 // Inverse of diagonal block b of the first-order factor L = I + F of G (F: strict lower
@@ -642,7 +650,10 @@ __global__ void __launch_bounds__(kCholThreads)
     gram_sq = nullptr, dinv = nullptr, ctl = CholQrCtl();
   }
   if (ctl.cq) run = ctl.cq + ctl.pass;
-  if (run && run[0] == 0) return;
+  if (run && run[0] == 0) {
+    if (threadIdx.x == 0) cholqr_notify(ctl, 0);
+    return;
+  }
   __shared__ BlockLds S;  // the diagonal block, its factor and inverse
   // the staged panel and the next one, which the trailing update writes (ping-pong)
   __shared__ double Pbuf[2][kPB * (kStageRows + 1)];
@@ -948,7 +959,10 @@ __global__ void __launch_bounds__(kCholThreads)
                     int *__restrict__ modflag, double *__restrict__ gram_sq,
                     double *__restrict__ dinv, CholQrCtl ctl) {
   if (ctl.cq) run = ctl.cq + ctl.pass;
-  if (run && run[0] == 0) return;
+  if (run && run[0] == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) cholqr_notify(ctl, 0);
+    return;
+  }
   const int nblk = (m + kPB - 1) / kPB;
   const int J = blockIdx.x;
   if (J >= nblk) return;

@@ -6,6 +6,7 @@
 // adaptive increment (eqs. 8-11) and low-rank posterior covariance.
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -155,6 +156,11 @@ struct riot_handle {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_grad = nullptr;
   bool grad_pending = false;
+  // host-mapped word through which a CholeskyQR pass reports whether the next one runs
+  // (pinned host memory; nullptr if it could not be had), and whether the host uses it
+  int *hflag = nullptr, *hflag_dev = nullptr;
+  unsigned pass_seq = 0;
+  bool pass_sync = true;
   ~riot_handle() {
     if (side) {
       (void)hipStreamSynchronize(side);
@@ -162,6 +168,10 @@ struct riot_handle {
     }
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_grad) (void)hipEventDestroy(ev_grad);
+    if (hflag) {
+      (void)hipStreamSynchronize(st);
+      (void)hipHostFree(hflag);
+    }
   }
 };
 
@@ -172,11 +182,17 @@ struct LaSpace {
   double *Q, *G, *R, *B1, *B2, *K, *Zs, *sywork, *partial, *scal, *cvec;
   int *flags;
   int *cq;  // CholeskyQR pass control (kMaxCholQRPasses + 1 ints), after the 16 flags
+  // host-read pass control (see cholqr): the host-mapped word (host and device addresses)
+  // and the handle's sequence counter; nullptr: every pass is launched, predicated
+  int *hflag = nullptr, *hflag_dev = nullptr;
+  unsigned *seq = nullptr;
 };
 
 inline LaSpace la_of(riot_handle *h) {
-  return {h->st, h->Q, h->G, h->R, h->B1, h->B2, h->K, h->Zs, h->sywork, h->partial, h->scal,
-          h->cvec, h->flags, h->flags + 16};
+  LaSpace la{h->st, h->Q, h->G, h->R, h->B1, h->B2, h->K, h->Zs, h->sywork, h->partial, h->scal,
+             h->cvec, h->flags, h->flags + 16};
+  if (h->pass_sync && h->hflag) la.hflag = h->hflag, la.hflag_dev = h->hflag_dev, la.seq = &h->pass_seq;
+  return la;
 }
 
 namespace {
@@ -303,10 +319,45 @@ riot_status read_flag(riot_handle *h, int idx, int *out) {
 // the first-order factor instead of a factorization. At most kMaxCholQRPasses: a sketch
 // whose singular values span more than the FP64 range of one shifted pass (graded spectra,
 // numerically rank-deficient blocks) gets further passes instead of a non-orthonormal Q.
-// Passes beyond the last needed one are launched but return at once (device flag), so
-// nothing synchronises.
+// Each pass's kernels read its run flag, set by the previous pass's Cholesky, and return at
+// once when it is 0. Two ways to launch them:
+//  - host-read control (la.hflag set and the stream not being captured): the passes that
+//    always run (three after a shifted first pass, which is never clean; two otherwise) are
+//    launched, then one at a time, each after the previous pass's Cholesky has stored its
+//    decision in the host-mapped word; the host waits for that store only, while the pass's
+//    solve still runs, so the device does not idle, and no pass beyond the last is launched;
+//  - otherwise all kMaxCholQRPasses are launched and the unneeded ones return at once.
 constexpr int kMaxCholQRPasses = 8;
 static_assert(kMaxCholQRPasses + 1 <= 16, "the pass control fits after the 16 flags");
+
+// Wait for the host-mapped word to carry sequence number `seq`, and return the decision it
+// holds. Should the stream drain without it (no pass left to report), the decision is read
+// from the device's run flag `cq_next` instead; a stream error is returned as RIOT_E_HIP.
+riot_status wait_pass(const LaSpace &h, int seq, const int *cq_next, int *next) {
+  for (unsigned it = 1;; ++it) {
+    const int v = __atomic_load_n(h.hflag, __ATOMIC_ACQUIRE);
+    if ((v >> 1) == seq) {
+      *next = v & 1;
+      return RIOT_OK;
+    }
+    if ((it & 127) == 0) {
+      const hipError_t q = hipStreamQuery(h.st);
+      if (q == hipSuccess) {
+        const int w = __atomic_load_n(h.hflag, __ATOMIC_ACQUIRE);
+        if ((w >> 1) == seq) {
+          *next = w & 1;
+          return RIOT_OK;
+        }
+        RIOT_HIP(hipMemcpy(next, cq_next, sizeof(int), hipMemcpyDeviceToHost));
+        return RIOT_OK;
+      }
+      if (q != hipErrorNotReady) return RIOT_E_HIP;
+    }
+#if defined(__x86_64__)
+    __builtin_ia32_pause();
+#endif
+  }
+}
 
 riot_status cholqr(const LaSpace &h, int rows, int m, const double *Xin, double *Qout,
                    bool shifted, int flag_idx, double *comp = nullptr, int mc = 0,
@@ -315,6 +366,13 @@ riot_status cholqr(const LaSpace &h, int rows, int m, const double *Xin, double 
   const double u = 0x1.0p-53;
   const double srel = 11.0 * ((double)m * rows + (double)m * (m + 1)) * u;
   int *cq = h.cq;
+  bool host_ctl = h.hflag != nullptr;
+  if (host_ctl) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+      host_ctl = false;
+  }
+  const int always = shifted ? 3 : 2;  // passes that run whatever the data
   if (Qout != Xin)
     RIOT_HIP(hipMemcpyAsync(Qout, Xin, (size_t)rows * m * sizeof(double), hipMemcpyDeviceToDevice,
                             st));
@@ -331,11 +389,22 @@ riot_status cholqr(const LaSpace &h, int rows, int m, const double *Xin, double 
                       kSplitK, st, run, true, gsq));
     CholQrCtl ctl;
     ctl.cq = cq, ctl.pass = pass, ctl.npass = kMaxCholQRPasses, ctl.count = count;
+    const bool wait = host_ctl && pass + 1 >= always && pass + 1 < kMaxCholQRPasses;
+    if (wait) {
+      ctl.host = h.hflag_dev;
+      ctl.seq = (int)(++*h.seq & 0x3fffffffu);
+    }
     RIOT_HIP(launch_chol_blocked(m, h.R, h.R, srel, sh ? 1 : 2, h.flags + flag_idx, h.flags + 4,
                                  st, nullptr, nullptr, gsq, h.partial, ctl));
     // X and its companion in one launch
     RIOT_HIP(launch_trsm_rlt_inv(rows, m, Qout, rows, h.R, h.partial, st, run, comp ? mc : 0,
                                  comp, comp ? mc : 1));
+    if (wait) {
+      int next = 1;
+      const riot_status ws = wait_pass(h, ctl.seq, cq + pass + 1, &next);
+      if (ws != RIOT_OK) return ws;
+      if (!next) break;
+    }
   }
   return RIOT_OK;
 }
@@ -527,11 +596,29 @@ riot_status riot_init(const riot_desc *desc, void *workspace, size_t bytes, void
     delete h;
     return rs;
   }
+  // the host-mapped word of the CholeskyQR pass control (without it, every pass is launched)
+  void *hp = nullptr, *dp = nullptr;
+  if (hipHostMalloc(&hp, 64, hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess) {
+    if (hipHostGetDevicePointer(&dp, hp, 0) == hipSuccess) {
+      h->hflag = static_cast<int *>(hp);
+      h->hflag_dev = static_cast<int *>(dp);
+      __atomic_store_n(h->hflag, -1, __ATOMIC_RELEASE);
+    } else {
+      (void)hipHostFree(hp);
+    }
+  }
+  (void)hipGetLastError();  // a failed pinned allocation only turns the host-read control off
   *out = h;
   return RIOT_OK;
 }
 
 void riot_free(riot_handle *h) { delete h; }
+
+riot_status riot_set_pass_sync(riot_handle *h, int32_t on) {
+  if (!h) return RIOT_E_ARG;
+  h->pass_sync = on != 0;
+  return RIOT_OK;
+}
 
 const char *riot_status_str(riot_status s) {
   switch (s) {

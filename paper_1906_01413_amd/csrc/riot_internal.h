@@ -10,6 +10,19 @@
 
 namespace riot {
 
+// Every device buffer of the library is global memory, but a pointer that a kernel reads
+// from a job table (or that is merged with one) is generic to the compiler, which then
+// emits flat loads and stores. A flat access also counts against the LDS/scalar counter,
+// so each LDS wait (every barrier of a halo exchange or reduction) would wait for the
+// kernel's outstanding global stores and loads as well. Accessing such memory through
+// gptr(p)[i] makes the compiler use global instructions.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gmem<T> *gptr(T *p) {
+  return (gmem<T> *)p;
+}
+
 // ---------------------------------------------------------------------------
 // Batched launches: one job per problem, the problem taken from a grid dimension,
 // so that one launch serves a whole batch of independent, differently sized problems.
@@ -53,6 +66,10 @@ struct CholQrCtl {
   int *cq = nullptr;
   int pass = 0, npass = 0;
   int *count = nullptr;
+  // optional host-mapped word: the pass's Cholesky stores (seq << 1) | (next pass runs) there
+  // with a system-scope release, for a host that launches passes only while they are needed
+  int *host = nullptr;
+  int seq = 0;
 };
 struct SymJob {
   int m;

@@ -26,7 +26,7 @@ FP64, FP32_TLAD = 0, 1
 ADAPTIVE, LRA, LRU = 0, 1, 2
 MODES = {"adaptive": ADAPTIVE, "lra": LRA, "lru": LRU}
 
-EXPORTS = ("riot_workspace_bytes", "riot_init", "riot_free", "riot_status_str",
+EXPORTS = ("riot_workspace_bytes", "riot_init", "riot_free", "riot_set_pass_sync", "riot_status_str",
            "riot_linearize", "riot_linearize_deferred", "riot_join", "riot_hess_apply",
            "riot_rsvd", "riot_increment", "riot_increment_select", "riot_psas_hess_apply",
            "riot_psas_rhs", "riot_psas_increment", "riot_precond_apply", "riot_precond_hess_apply",
@@ -115,6 +115,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "riot_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(_Desc)]),
         "riot_init": (i32, [ctypes.POINTER(_Desc), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
         "riot_free": (None, [vp]),
+        "riot_set_pass_sync": (i32, [vp, i32]),
         "riot_status_str": (ctypes.c_char_p, [i32]),
         "riot_linearize": (i32, [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]),
         "riot_linearize_deferred": (i32, [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]),
@@ -292,6 +293,11 @@ class Riot:
         if getattr(self, "h", None) and not getattr(self, "_borrowed", False):
             self.lib.riot_free(self.h)
         self.h = None
+
+    def set_pass_sync(self, on: bool):
+        """CholeskyQR passes launched on the host's reading of each pass's decision (True, the
+        default) or all launched and predicated on the device (False)."""
+        _check(self.lib.riot_set_pass_sync(self.h, 1 if on else 0), "riot_set_pass_sync")
 
     @classmethod
     def _bind(cls, lib, h, n, nsteps, m_max, nobs, device, stream, owner):

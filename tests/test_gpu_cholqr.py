@@ -44,3 +44,32 @@ def test_orth_matches_householder_qr(m, kind):
     print(f"m={m} {kind}: orthonormality {e_orth:.1e}, |Q - Q_oracle|_max {e_q:.1e}")
     assert e_orth < 1e-14 * m
     assert e_q < bound
+
+
+@pytest.mark.parametrize("kind", ["near_orthonormal", "graded"])
+def test_pass_control_modes_agree(kind):
+    """Passes launched on the host's reading of each decision, or all launched and
+    predicated on the device: the same passes run, so Q is the same bit for bit."""
+    w, p = oracle_problem("l96_n4096", 0)
+    r = riot_for(p, m_max=272)
+    X = torch.tensor(_block(p.n, 272, 77, kind), device="cuda")
+    out = []
+    for on in (True, False, True):
+        r.set_pass_sync(on)
+        out.append(to_np(r.orth(X)))
+    print(f"{kind}: host-read vs predicated max diff {np.max(np.abs(out[0] - out[1])):.1e}")
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+def test_pass_control_rsvd_agrees():
+    """The whole randomized eigendecomposition (two CholeskyQR sequences) in both modes."""
+    w, p = oracle_problem("l96_n4096", 0)
+    r = riot_for(p, m_max=272)
+    r.linearize(p.xb)
+    res = []
+    for on in (True, False):
+        r.set_pass_sync(on)
+        lam, V, info = r.rsvd(256, 16, q=0, seed=5)
+        res.append((to_np(lam), to_np(V), info.qr_passes))
+    assert res[0][2] == res[1][2]
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])

@@ -276,8 +276,17 @@ __global__ void __launch_bounds__(256)
       // not computed for a lower-triangle result; zeroed when the result is a Cholesky input
       if (gram_sq) C[(size_t)col * ldc + row] = 0.0;
     } else {
+      // the splits summed in order, eight loads in flight at a time
       double s = 0.0;
-      for (int z = 0; z < splits; ++z) s += partial[(size_t)z * MN + idx];
+      int z = 0;
+      for (; z + 8 <= splits; z += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = partial[(size_t)(z + u) * MN + idx];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+      }
+      for (; z < splits; ++z) s += partial[(size_t)z * MN + idx];
       double out = alpha * s;
       if (beta != 0.0) out += beta * C[(size_t)col * ldc + row];
       C[(size_t)col * ldc + row] = out;
@@ -1387,9 +1396,22 @@ __global__ void __launch_bounds__(256)
   }
   if (r0 >= rows) return;
   const int nr = min(32, rows - r0);
-  for (int idx = tid; idx < 32 * m; idx += 256) {
-    const int i = idx & 31, j = idx >> 5;
-    xs[j * 33 + i] = (i < nr) ? X[(size_t)j * ldx + r0 + i] : 0.0;
+  {
+    // every load of the strip issued before the first wait (at a clamped address where the
+    // strip ends; those values are dropped), then the LDS writes
+    constexpr int kPer = 32 * kStripM / 256;
+    const int i = tid & 31, ic = min(i, nr - 1);
+    double v[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int j = min((tid >> 5) + 8 * t, m - 1);
+      v[t] = X[(size_t)j * ldx + r0 + ic];
+    }
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int j = (tid >> 5) + 8 * t;
+      if (j < m) xs[j * 33 + i] = (i < nr) ? v[t] : 0.0;
+    }
   }
   __syncthreads();
   const int rt = wave >> 1, ct = wave & 1;
@@ -1402,30 +1424,36 @@ __global__ void __launch_bounds__(256)
     double dv[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) dv[s] = dinv[(size_t)jb * 1024 + 32 * (4 * s + lg) + 16 * ct + li];
-    // 1. acc = X[16 rt.., 0:c0] L[c0 + 16 ct.., 0:c0]^T in chunks of 16, the next chunk's
-    //    L operands loaded before the current chunk's MFMAs
+    // 1. acc = X[16 rt.., 0:c0] L[c0 + 16 ct.., 0:c0]^T: every L operand of the contraction
+    //    loaded at once (one memory latency per column block), then the MFMAs in chunks of
+    //    16, alternating between two accumulators so that consecutive MFMAs do not wait on
+    //    each other
+    constexpr int kChunks = (kStripM - 32) / 16;
     d4 acc = d4{0.0, 0.0, 0.0, 0.0};
     if (c0 > 0) {
-      double bcur[4], bnext[4];
+      double bl[4 * kChunks];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) bcur[s] = bin ? L[(size_t)(4 * s + lg) * m + bcol] : 0.0;
-      for (int k0 = 0; k0 < c0; k0 += 16) {
-        const bool more = k0 + 16 < c0;
-        if (more) {
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-            bnext[s] = bin ? L[(size_t)(k0 + 16 + 4 * s + lg) * m + bcol] : 0.0;
-        }
+      for (int q = 0; q < kChunks; ++q)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          const double a = xs[(k0 + 4 * s + lg) * 33 + arow];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bcur[s], acc, 0, 0, 0);
+          const int k = 16 * q + 4 * s + lg;
+          bl[4 * q + s] = (bin && k < c0) ? L[(size_t)k * m + bcol] : 0.0;
         }
-        if (more) {
+      d4 acc1 = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int s = 0; s < 4; ++s) bcur[s] = bnext[s];
+      for (int q = 0; q < kChunks; ++q) {
+        if (16 * q < c0) {
+#pragma unroll
+          for (int s = 0; s < 4; s += 2) {
+            const double a0 = xs[(16 * q + 4 * s + lg) * 33 + arow];
+            const double a1 = xs[(16 * q + 4 * s + 4 + lg) * 33 + arow];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bl[4 * q + s], acc, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bl[4 * q + s + 1], acc1, 0, 0, 0);
+          }
         }
       }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] += acc1[r];
     }
     // 2. this wave's tile of B into LDS (rows >= nr and columns >= nc zero)
 #pragma unroll

@@ -1370,14 +1370,18 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// The same solve with the workgroup's 32-row strip of X held in LDS for m <= kStripM: the
+// The same solve with the workgroup's 16-row strip of X held in LDS for m <= kStripM: the
 // strip is read once and written once, and the solved column blocks that every later
-// block's contraction needs are LDS operands instead of global re-reads. Each of the four
-// waves owns one 16 x 16 tile (rt, ct) of the 32 x 32 column block: it forms that tile of
-// B = X[:, jb] - X[:, <jb] L[jb, <jb]^T over the whole contraction (no partial sums to
-// reduce), the workgroup exchanges B through LDS, and each wave multiplies its row tile of
-// B by its column tile of L_jb^{-T}, prefetched into registers while the contraction runs.
+// block's contraction needs are LDS operands instead of global re-reads. Four waves: wave
+// (kh, ct) forms the 16 x 16 tile ct of B = X[:, jb] - X[:, <jb] L[jb, <jb]^T over the
+// contraction's chunks of 16 with parity kh (two accumulators, so consecutive MFMAs are
+// independent); the kh = 1 partial goes through LDS to its kh = 0 partner, which completes
+// B; then each kh = 0 wave multiplies the strip's B by its column tile of L_jb^{-T}. Sixteen
+// rows per workgroup give a 4096-row block 256 workgroups, one per CU, and the k split
+// halves each wave's chain of MFMAs.
 constexpr int kStripM = 288;
+constexpr int kSR = 16;           // rows per strip
+constexpr int kXsLd = kSR + 1;    // LDS stride of the strip's columns
 
 __global__ void __launch_bounds__(256)
     trsm_rlt_inv_strip_kernel(int rows, int m, double *__restrict__ X, int ldx,
@@ -1385,98 +1389,114 @@ __global__ void __launch_bounds__(256)
                               const int *__restrict__ run, int rows2, double *__restrict__ X2,
                               int ldx2) {
   if (run && run[0] == 0) return;
-  __shared__ double xs[kStripM * 33];  // xs[j 33 + i] = X[r0 + i][j]
-  __shared__ double Bm[32 * 33];       // B, column-major
+  __shared__ double xs[kStripM * kXsLd];  // xs[j kXsLd + i] = X[r0 + i][j]
+  __shared__ double Bm[32 * kXsLd];       // B, column-major
+  __shared__ double part[2][4 * 64];      // the kh = 1 partial sums, per tile and lane
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lg = lane >> 4;
-  int r0 = blockIdx.x * 32;
-  const int nblk1 = (rows + 31) / 32;
+  int r0 = blockIdx.x * kSR;
+  const int nblk1 = (rows + kSR - 1) / kSR;
   if ((int)blockIdx.x >= nblk1) {  // a block of the second matrix
-    r0 = ((int)blockIdx.x - nblk1) * 32, rows = rows2, X = X2, ldx = ldx2;
+    r0 = ((int)blockIdx.x - nblk1) * kSR, rows = rows2, X = X2, ldx = ldx2;
   }
   if (r0 >= rows) return;
-  const int nr = min(32, rows - r0);
+  const int nr = min(kSR, rows - r0);
   {
     // every load of the strip issued before the first wait (at a clamped address where the
     // strip ends; those values are dropped), then the LDS writes
-    constexpr int kPer = 32 * kStripM / 256;
-    const int i = tid & 31, ic = min(i, nr - 1);
+    constexpr int kPer = kSR * kStripM / 256;
+    const int i = tid & (kSR - 1), ic = min(i, nr - 1);
     double v[kPer];
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
-      const int j = min((tid >> 5) + 8 * t, m - 1);
+      const int j = min((tid >> 4) + 16 * t, m - 1);
       v[t] = X[(size_t)j * ldx + r0 + ic];
     }
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
-      const int j = (tid >> 5) + 8 * t;
-      if (j < m) xs[j * 33 + i] = (i < nr) ? v[t] : 0.0;
+      const int j = (tid >> 4) + 16 * t;
+      if (j < m) xs[j * kXsLd + i] = (i < nr) ? v[t] : 0.0;
     }
   }
   __syncthreads();
-  const int rt = wave >> 1, ct = wave & 1;
-  const int arow = 16 * rt + li;  // A-operand row of this lane
+  const int ct = wave & 1, kh = wave >> 1;
+  constexpr int kChunks = (kStripM - 32) / 16;
   for (int jb = 0; jb * 32 < m; ++jb) {
     const int c0 = jb * 32, nc = min(32, m - c0);
     const int bcol = c0 + 16 * ct + li;  // B-operand column (a row of L) of this lane
     const bool bin = bcol < m;
     // this wave's column tile of L_jb^{-T}: op[k][j] = dinv[1024 jb + 32 k + 16 ct + j]
     double dv[8];
+    if (kh == 0) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) dv[s] = dinv[(size_t)jb * 1024 + 32 * (4 * s + lg) + 16 * ct + li];
-    // 1. acc = X[16 rt.., 0:c0] L[c0 + 16 ct.., 0:c0]^T: every L operand of the contraction
-    //    loaded at once (one memory latency per column block), then the MFMAs in chunks of
-    //    16, alternating between two accumulators so that consecutive MFMAs do not wait on
-    //    each other
-    constexpr int kChunks = (kStripM - 32) / 16;
+      for (int s = 0; s < 8; ++s)
+        dv[s] = dinv[(size_t)jb * 1024 + 32 * (4 * s + lg) + 16 * ct + li];
+    }
+    // 1. this wave's share of X[:, 0:c0] L[c0 + 16 ct.., 0:c0]^T: chunks q = kh, kh + 2, ..
+    //    below c0, every L operand loaded at once
     d4 acc = d4{0.0, 0.0, 0.0, 0.0};
     if (c0 > 0) {
-      double bl[4 * kChunks];
+      constexpr int kMine = (kChunks + 1) / 2;
+      double bl[4 * kMine];
 #pragma unroll
-      for (int q = 0; q < kChunks; ++q)
+      for (int h = 0; h < kMine; ++h)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          const int k = 16 * q + 4 * s + lg;
-          bl[4 * q + s] = (bin && k < c0) ? L[(size_t)k * m + bcol] : 0.0;
+          const int k = 16 * (2 * h + kh) + 4 * s + lg;
+          bl[4 * h + s] = (bin && k < c0) ? L[(size_t)k * m + bcol] : 0.0;
         }
       d4 acc1 = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < kChunks; ++q) {
+      for (int h = 0; h < kMine; ++h) {
+        const int q = 2 * h + kh;
         if (16 * q < c0) {
 #pragma unroll
           for (int s = 0; s < 4; s += 2) {
-            const double a0 = xs[(16 * q + 4 * s + lg) * 33 + arow];
-            const double a1 = xs[(16 * q + 4 * s + 4 + lg) * 33 + arow];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bl[4 * q + s], acc, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bl[4 * q + s + 1], acc1, 0, 0, 0);
+            const double a0 = xs[(16 * q + 4 * s + lg) * kXsLd + li];
+            const double a1 = xs[(16 * q + 4 * s + 4 + lg) * kXsLd + li];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bl[4 * h + s], acc, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bl[4 * h + s + 1], acc1, 0, 0, 0);
           }
         }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[r] += acc1[r];
-    }
-    // 2. this wave's tile of B into LDS (rows >= nr and columns >= nc zero)
+      if (kh == 1) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * rt + lg + 4 * r, col = 16 * ct + li;
-      Bm[row + 33 * col] = (row < nr && col < nc) ? xs[(c0 + col) * 33 + row] - acc[r] : 0.0;
+        for (int r = 0; r < 4; ++r) part[ct][r * 64 + lane] = acc[r];
+      }
     }
     __syncthreads();
-    // 3. X[16 rt.., c0 + 16 ct..] = B[16 rt.., :] L_jb^{-T}[:, 16 ct..], into the strip
-    d4 q = d4{0.0, 0.0, 0.0, 0.0};
+    // 2. the kh = 0 waves complete their tile of B into LDS (rows >= nr and columns >= nc
+    //    zero)
+    if (kh == 0) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s)
-      q = __builtin_amdgcn_mfma_f64_16x16x4f64(Bm[arow + 33 * (4 * s + lg)], dv[s], q, 0, 0, 0);
+      for (int r = 0; r < 4; ++r) {
+        const int row = lg + 4 * r, col = 16 * ct + li;
+        const double p = (c0 > 0) ? part[ct][r * 64 + lane] : 0.0;
+        Bm[row + kXsLd * col] =
+            (row < nr && col < nc) ? xs[(c0 + col) * kXsLd + row] - (acc[r] + p) : 0.0;
+      }
+    }
+    __syncthreads();
+    // 3. X[:, c0 + 16 ct..] = B L_jb^{-T}[:, 16 ct..], into the strip
+    if (kh == 0) {
+      d4 q = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * rt + lg + 4 * r, col = 16 * ct + li;
-      if (row < nr && col < nc) xs[(c0 + col) * 33 + row] = q[r];
+      for (int s = 0; s < 8; ++s)
+        q = __builtin_amdgcn_mfma_f64_16x16x4f64(Bm[li + kXsLd * (4 * s + lg)], dv[s], q, 0, 0,
+                                                 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = lg + 4 * r, col = 16 * ct + li;
+        if (row < nr && col < nc) xs[(c0 + col) * kXsLd + row] = q[r];
+      }
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < 32 * m; idx += 256) {
-    const int i = idx & 31, j = idx >> 5;
-    if (i < nr) X[(size_t)j * ldx + r0 + i] = xs[j * 33 + i];
+  for (int idx = tid; idx < kSR * m; idx += 256) {
+    const int i = idx & (kSR - 1), j = idx >> 4;
+    if (i < nr) X[(size_t)j * ldx + r0 + i] = xs[j * kXsLd + i];
   }
 }
 
@@ -1799,13 +1819,13 @@ hipError_t launch_trsm_rlt_inv(int rows, int m, double *X, int ldx, const double
                                double *X2, int ldx2) {
   if (!X2) rows2 = 0;
   if (rows < 0 || rows2 < 0 || m <= 0 || rows + rows2 == 0) return hipSuccess;
-  const int nblk = (rows + 31) / 32 + (rows2 + 31) / 32;
   if (m <= kStripM)
-    hipLaunchKernelGGL(trsm_rlt_inv_strip_kernel, dim3(nblk), dim3(256), 0, st, rows, m, X, ldx,
-                       L, dinv, run, rows2, X2, ldx2);
+    hipLaunchKernelGGL(trsm_rlt_inv_strip_kernel,
+                       dim3((rows + kSR - 1) / kSR + (rows2 + kSR - 1) / kSR), dim3(256), 0, st,
+                       rows, m, X, ldx, L, dinv, run, rows2, X2, ldx2);
   else
-    hipLaunchKernelGGL(trsm_rlt_inv_kernel, dim3(nblk), dim3(256), 0, st, rows, m, X, ldx, L,
-                       dinv, run, rows2, X2, ldx2);
+    hipLaunchKernelGGL(trsm_rlt_inv_kernel, dim3((rows + 31) / 32 + (rows2 + 31) / 32), dim3(256),
+                       0, st, rows, m, X, ldx, L, dinv, run, rows2, X2, ldx2);
   return hipGetLastError();
 }
 

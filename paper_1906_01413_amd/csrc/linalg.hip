@@ -108,12 +108,13 @@ constexpr int kGK = 32;  // K chunk
 // < 0), the tiles of one 64-row block of C share an XCD (their common rows of A).
 constexpr int kXcds = 8;
 
-template <int TA, int TB, bool LOWER = false>
+template <int TA, int TB, bool LOWER = false, bool PAIR = false>
 __global__ void __launch_bounds__(256)
     gemm_lds_kernel(int M, int N, int K, const double *__restrict__ A, int lda,
                     const double *__restrict__ B, int ldb, double *__restrict__ C, int ldc,
                     double alpha, double beta, int kchunk, double *__restrict__ partial,
-                    const int *__restrict__ run, int xcd_split) {
+                    const int *__restrict__ run, int xcd_split, const double *__restrict__ B2,
+                    double *__restrict__ C2, int N1) {
   if (run && run[0] == 0) return;
   int bx = blockIdx.x, by = blockIdx.y, kz = blockIdx.z;
   if (xcd_split != 0) {
@@ -167,10 +168,12 @@ __global__ void __launch_bounds__(256)
         const bool in = n0 + j < N && k0 + kk < kend;
         const double v = B[in ? (size_t)(k0 + kk) * ldb + n0 + j : 0];
         rb[p] = in ? v : 0.0;
-      } else {  // B[k + j ldb]: lanes along k
+      } else {  // B[k + j ldb]: lanes along k; columns from N1 on from B2 (pair form)
         const int kk = tid & 31, j = (tid >> 5) + 8 * p;
         const bool in = n0 + j < N && k0 + kk < kend;
-        const double v = B[in ? (size_t)(n0 + j) * ldb + k0 + kk : 0];
+        const bool second = PAIR && n0 + j >= N1;
+        const double *bp = second ? B2 + (size_t)(n0 + j - N1) * ldb : B + (size_t)(n0 + j) * ldb;
+        const double v = (in ? bp : B)[in ? k0 + kk : 0];
         rb[p] = in ? v : 0.0;
       }
     }
@@ -248,9 +251,10 @@ __global__ void __launch_bounds__(256)
           if (partial) {
             partial[(size_t)kz * M * N + (size_t)col * M + row] = v;
           } else {
+            double *cp = (PAIR && col >= N1) ? C2 + (size_t)(col - N1) * ldc : C + (size_t)col * ldc;
             double out = alpha * v;
-            if (beta != 0.0) out += beta * C[(size_t)col * ldc + row];
-            C[(size_t)col * ldc + row] = out;
+            if (beta != 0.0) out += beta * cp[row];
+            cp[row] = out;
           }
         }
       }
@@ -265,13 +269,15 @@ constexpr int kCholSyncInts = 64;
 __global__ void __launch_bounds__(256)
     splitk_reduce_kernel(int M, int N, int splits, const double *__restrict__ partial,
                          double alpha, double beta, double *__restrict__ C, int ldc,
-                         const int *__restrict__ run, int lower, double *__restrict__ gram_sq) {
+                         const int *__restrict__ run, int lower, double *__restrict__ gram_sq,
+                         double *__restrict__ C2, int N1) {
   if (run && run[0] == 0) return;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t MN = (size_t)M * N;
   double sq = 0.0, dq = 0.0;
   if (idx < MN) {
-    const int row = (int)(idx % M), col = (int)(idx / M);
+    int row = (int)(idx % M), col = (int)(idx / M);
+    if (C2 && col >= N1) C = C2, col -= N1;  // the pair form's second result
     if (lower && row < col) {
       // not computed for a lower-triangle result; zeroed when the result is a Cholesky input
       if (gram_sq) C[(size_t)col * ldc + row] = 0.0;
@@ -1714,9 +1720,22 @@ __global__ void check_finite_kernel(long long count, const double *__restrict__ 
 
 hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const double *A, int lda,
                     const double *B, int ldb, double beta, double *C, int ldc, double *partial,
-                    int splitk, hipStream_t st, const int *run, bool lower, double *gram_sq) {
+                    int splitk, hipStream_t st, const int *run, bool lower, double *gram_sq,
+                    const double *B2, double *C2) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (lower && !(ta == 1 && tb == 0 && M == N)) return hipErrorInvalidValue;
+  // pair form: [C C2] = alpha op(A)^T [B B2] + beta [C C2], two results of N columns each
+  const bool pair = B2 != nullptr;
+  if (pair && (!C2 || tb != 0 || lower || gram_sq)) return hipErrorInvalidValue;
+  if (pair && !(M >= kGT && 2 * N >= kGT)) {  // too small for the LDS kernel: two products
+    hipError_t e = gemm_f64(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial,
+                            splitk, st, run);
+    if (e != hipSuccess) return e;
+    return gemm_f64(ta, tb, M, N, K, alpha, A, lda, B2, ldb, beta, C2, ldc, partial, splitk, st,
+                    run);
+  }
+  const int N1 = N;
+  if (pair) N = 2 * N;
   if (gram_sq && (!lower || !partial || K <= 0 || beta != 0.0)) return hipErrorInvalidValue;
   if (K <= 0) splitk = 1;
   if (splitk < 1 || !partial) splitk = 1;
@@ -1727,7 +1746,8 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   const int tiles = lower ? tm * (tm + 1) / 2 : tm * tn;
   // about one workgroup per CU: no more K splits than fill 256 CUs with the tiles (when that
   // is a multiple of 8, each split's workgroups share an XCD, see gemm_lds_kernel)
-  if (big && splitk > 1) splitk = std::max(1, std::min(splitk, 256 / tiles));
+  // (the pair form: two workgroups per CU, which hide each other's latencies)
+  if (big && splitk > 1) splitk = std::max(1, std::min(splitk, (pair ? 512 : 256) / tiles));
   int kchunk = (K + splitk - 1) / splitk;
   kchunk = (kchunk + kround - 1) / kround * kround;
   if (kchunk <= 0) kchunk = kround;
@@ -1744,8 +1764,14 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
     }
 #define RIOT_GEMM_LDS(TA_, TB_, LO_)                                                            \
   hipLaunchKernelGGL((gemm_lds_kernel<TA_, TB_, LO_>), grid, dim3(256), 0, st, M, N, K, A, lda, B, \
-                     ldb, C, ldc, alpha, beta, kchunk, part, run, xs)
-    if (ta == 0 && tb == 0)
+                     ldb, C, ldc, alpha, beta, kchunk, part, run, xs, nullptr, nullptr, N)
+    if (pair && ta == 1)
+      hipLaunchKernelGGL((gemm_lds_kernel<1, 0, false, true>), grid, dim3(256), 0, st, M, N, K, A,
+                         lda, B, ldb, C, ldc, alpha, beta, kchunk, part, run, xs, B2, C2, N1);
+    else if (pair)
+      hipLaunchKernelGGL((gemm_lds_kernel<0, 0, false, true>), grid, dim3(256), 0, st, M, N, K, A,
+                         lda, B, ldb, C, ldc, alpha, beta, kchunk, part, run, xs, B2, C2, N1);
+    else if (ta == 0 && tb == 0)
       RIOT_GEMM_LDS(0, 0, false);
     else if (ta == 1 && tb == 0 && lower)
       RIOT_GEMM_LDS(1, 0, true);
@@ -1757,6 +1783,7 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
       RIOT_GEMM_LDS(1, 1, false);
 #undef RIOT_GEMM_LDS
   } else {
+    if (pair) return hipErrorInvalidValue;  // the pair form runs on the LDS kernel only
     dim3 grid((M + 31) / 32, (N + 31) / 32, splits);
 #define RIOT_GEMM(TA_, TB_)                                                                  \
   hipLaunchKernelGGL((gemm_mfma_kernel<TA_, TB_>), grid, dim3(64), 0, st, M, N, K, A, lda, B, \
@@ -1779,7 +1806,8 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   if (part) {
     const size_t MN = (size_t)M * N;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st,
-                       M, N, splits, partial, alpha, beta, C, ldc, run, lower ? 1 : 0, gram_sq);
+                       M, N, splits, partial, alpha, beta, C, ldc, run, lower ? 1 : 0, gram_sq,
+                       C2, N1);
     e = hipGetLastError();
   }
   return e;

@@ -418,9 +418,9 @@ riot_status sketch_eig(const LaSpace &la, int n, int m, const double *Y, const d
   hipStream_t st = la.st;
   riot_status rs = cholqr(la, n, m, Y, la.Q, true, 0, nullptr, 0, la.flags + 5);
   if (rs != RIOT_OK) return rs;
-  RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, la.Q, n, Y, n, 0.0, la.B1, m, la.partial, kSplitK, st));
-  RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, la.Q, n, Om_eff, n, 0.0, la.B2, m, la.partial, kSplitK,
-                    st));
+  // B1 and B2 in one launch (half the K splits: the partial buffer holds both products)
+  RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, la.Q, n, Y, n, 0.0, la.B1, m, la.partial, kSplitK / 2,
+                    st, nullptr, false, nullptr, Om_eff, la.B2));
   rs = cholqr(la, m, m, la.B2, la.Zs, false, 1, la.B1, m);
   if (rs != RIOT_OK) return rs;
   RIOT_HIP(gemm_f64(0, 1, m, m, m, 1.0, la.B1, m, la.Zs, m, 0.0, la.K, m, la.partial, kSplitK, st));

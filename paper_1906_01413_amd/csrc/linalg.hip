@@ -669,6 +669,7 @@ __global__ void __launch_bounds__(kCholThreads)
     if (threadIdx.x == 0) cholqr_notify(ctl, 0);
     return;
   }
+  gmem<double> *const Lg = gptr(L);  // the factor's global accesses (see gptr)
   __shared__ BlockLds S;  // the diagonal block, its factor and inverse
   // the staged panel and the next one, which the trailing update writes (ping-pong)
   __shared__ double Pbuf[2][kPB * (kStageRows + 1)];
@@ -682,11 +683,11 @@ __global__ void __launch_bounds__(kCholThreads)
   const bool inplace = gram_sq != nullptr;
   if (inplace && mode == 2 && gram_dev2(m, gram_sq, red) <= kCholFirstOrderDev2) {
     // G within sqrt(u) of the identity: the first-order factor, in place (the diagonal is
-    // the only change: L[i][i] = 1 + (G[i][i] - 1) / 2), and its blocks' inverses
+    // the only change: Lg[i][i] = 1 + (G[i][i] - 1) / 2), and its blocks' inverses
     if (dinv)
       for (int b = 0; b * kPB < m; ++b) first_order_dinv(m, b, L, dinv, tid, nt);
     __syncthreads();
-    for (int i = tid; i < m; i += nt) L[(size_t)i * m + i] = 0.5 + 0.5 * L[(size_t)i * m + i];
+    for (int i = tid; i < m; i += nt) Lg[(size_t)i * m + i] = 0.5 + 0.5 * Lg[(size_t)i * m + i];
     if (tid == 0 && ctl.cq) cholqr_ctl_end(ctl, false, false, false);
     return;
   }
@@ -718,14 +719,14 @@ __global__ void __launch_bounds__(kCholThreads)
     if (shifted && tid == 0 && shifts) shifts[0] += 1;
     if (inplace) {
       if (s != 0.0)
-        for (int i = tid; i < m; i += nt) L[(size_t)i * m + i] += s;
+        for (int i = tid; i < m; i += nt) Lg[(size_t)i * m + i] += s;
     } else {
       // (i, j) of idx advanced by nt each iteration without a division per element
       const int step_i = nt % m, step_j = nt / m;
       int i = tid % m, j = tid / m;
 #pragma unroll 4
       for (size_t idx = tid; idx < (size_t)m * m; idx += nt) {
-        L[idx] = (i >= j) ? (G[idx] + (i == j ? s : 0.0)) : 0.0;
+        Lg[idx] = (i >= j) ? (G[idx] + (i == j ? s : 0.0)) : 0.0;
         i += step_i;
         j += step_j;
         if (i >= m) i -= m, ++j;
@@ -754,7 +755,7 @@ __global__ void __launch_bounds__(kCholThreads)
       const int nb = min(kPB, m);
       for (int idx = tid; idx < nb * nb; idx += nt) {
         const int i = idx % nb, j = idx / nb;
-        S.D[i][j] = (i >= j) ? L[(size_t)j * m + i] : 0.0;
+        S.D[i][j] = (i >= j) ? Lg[(size_t)j * m + i] : 0.0;
       }
       __syncthreads();
       if (wave == 0) factor_block(nb, m - nb > kStageRows);
@@ -769,7 +770,7 @@ __global__ void __launch_bounds__(kCholThreads)
       //    trailing update), goes to L, and to Dc for its inverse (step 3)
       for (int idx = tid; idx < nb * nb; idx += nt) {
         const int i = idx % nb, j = idx / nb;
-        if (i >= j) L[(size_t)(kb + j) * m + kb + i] = S.D[i][j];
+        if (i >= j) Lg[(size_t)(kb + j) * m + kb + i] = S.D[i][j];
       }
       if (dinv)
         for (int idx = tid; idx < kPB * kPB; idx += nt) Dc[idx >> 5][idx & 31] = S.D[idx >> 5][idx & 31];
@@ -793,7 +794,7 @@ __global__ void __launch_bounds__(kCholThreads)
             const int e = base + u * nt;
             const int ec = e < tot ? e : 0;
             const int jj = ec / prow, ii = ec - jj * prow;
-            v[u] = L[(size_t)(kb + jj) * m + r0 + ii];
+            v[u] = Lg[(size_t)(kb + jj) * m + r0 + ii];
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
@@ -826,7 +827,7 @@ __global__ void __launch_bounds__(kCholThreads)
 #pragma unroll
           for (int j = 0; j < kPB; ++j) {
             Pn[j * ld + ii] = x[j];
-            L[(size_t)(kb + j) * m + r0 + ii] = x[j];
+            Lg[(size_t)(kb + j) * m + r0 + ii] = x[j];
           }
         }
       } else if (!use_inv) {
@@ -847,7 +848,7 @@ __global__ void __launch_bounds__(kCholThreads)
           const int i0 = 32 * I;
           d4 acc[2][2];
           zero_acc(acc);
-          wave_mma32<false, true>(L + (size_t)kb * m + r0 + i0, m, &S.Di[0][0], kPB + 1, nb,
+          wave_mma32<false, true>(Lg + (size_t)kb * m + r0 + i0, m, &S.Di[0][0], kPB + 1, nb,
                                   prow - i0, nb, acc);
           // the MFMAs consumed every operand load of this wave's rows: overwrite them
 #pragma unroll
@@ -857,7 +858,7 @@ __global__ void __launch_bounds__(kCholThreads)
 #pragma unroll
               for (int rr = 0; rr < 4; ++rr) {
                 const int row = i0 + 16 * rt + lg + 4 * rr, col = 16 * ct + li;
-                if (row < prow && col < nb) L[(size_t)(kb + col) * m + r0 + row] = acc[rt][ct][rr];
+                if (row < prow && col < nb) Lg[(size_t)(kb + col) * m + r0 + row] = acc[rt][ct][rr];
               }
         }
       }
@@ -888,7 +889,7 @@ __global__ void __launch_bounds__(kCholThreads)
             for (int r = 0; r < 4; ++r) {
               const int row = i0 + 16 * rt + lg + 4 * r, col = j0 + 16 * ct + li;
               const bool in = row < m && col < m && row >= col;
-              old[rt][ct][r] = L[in ? (size_t)col * m + row : 0];
+              old[rt][ct][r] = Lg[in ? (size_t)col * m + row : 0];
             }
         d4 acc[2][2];
         zero_acc(acc);
@@ -896,7 +897,7 @@ __global__ void __launch_bounds__(kCholThreads)
           wave_mma32<false, true>(Pn + 32 * I, kStageRows + 1, Pn + 32 * J, kStageRows + 1, nb,
                                   m - i0, m - j0, acc);
         else
-          wave_mma32<false, true>(L + (size_t)kb * m + i0, m, L + (size_t)kb * m + j0, m, nb,
+          wave_mma32<false, true>(Lg + (size_t)kb * m + i0, m, Lg + (size_t)kb * m + j0, m, nb,
                                   m - i0, m - j0, acc);
         // tiles below the next diagonal block in its column are the next panel: with a
         // staged panel they go to the other LDS buffer only (the panel's solve writes L)
@@ -914,7 +915,7 @@ __global__ void __launch_bounds__(kCholThreads)
                 if (to_next)
                   Pnext[(col - r0) * (kStageRows + 1) + (row - r0 - kPB)] = v;
                 else
-                  L[(size_t)col * m + row] = v;
+                  Lg[(size_t)col * m + row] = v;
                 if (to_D) S.D[row - i0][col - j0] = v;
               }
             }

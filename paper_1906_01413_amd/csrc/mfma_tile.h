@@ -15,10 +15,10 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // first 16 columns (half the MFMAs, for operands 16 columns wide).
 // ---------------------------------------------------------------------------
 
-template <bool TA, bool TB, int NCT = 2>
-__device__ __forceinline__ void mma32_load(const double *__restrict__ A, int lda,
-                                           const double *__restrict__ B, int ldb, int K, int mA,
-                                           int nB, int k0, double (&av)[4][2], double (&bv)[4][NCT]) {
+// PA, PB: pointers to double, in the generic or the global address space.
+template <bool TA, bool TB, int NCT = 2, typename PA, typename PB>
+__device__ __forceinline__ void mma32_load(PA A, int lda, PB B, int ldb, int K, int mA, int nB,
+                                           int k0, double (&av)[4][2], double (&bv)[4][NCT]) {
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
 #pragma unroll
@@ -40,10 +40,9 @@ __device__ __forceinline__ void mma32_load(const double *__restrict__ A, int lda
 
 // The contraction runs in chunks of 16 (four MFMA k-steps); the operands of the next
 // chunk are loaded before the current chunk's MFMAs are issued.
-template <bool TA, bool TB, int NCT = 2>
-__device__ __forceinline__ void wave_mma32(const double *__restrict__ A, int lda,
-                                           const double *__restrict__ B, int ldb, int K, int mA,
-                                           int nB, d4 (&acc)[2][NCT]) {
+template <bool TA, bool TB, int NCT = 2, typename PA, typename PB>
+__device__ __forceinline__ void wave_mma32(PA A, int lda, PB B, int ldb, int K, int mA, int nB,
+                                           d4 (&acc)[2][NCT]) {
   if (K <= 0) return;
   double av[4][2], bv[4][NCT], an[4][2], bn[4][NCT];
   mma32_load<TA, TB, NCT>(A, lda, B, ldb, K, mA, nB, 0, av, bv);

@@ -661,7 +661,10 @@ __global__ void __launch_bounds__(256) root_kernel(int m, double *__restrict__ w
     eg[i] = work[Lw.e + i];
   }
   __syncthreads();
-  double *D = work + Lw.D, *Ls = work + Lw.Ls, *LLD = work + Lw.LLD, *misc = work + Lw.misc;
+  gmem<double> *D = gptr(work + Lw.D);
+  gmem<double> *Ls = gptr(work + Lw.Ls);
+  gmem<double> *LLD = gptr(work + Lw.LLD);
+  gmem<double> *misc = gptr(work + Lw.misc);
   __shared__ double sh_lo, sh_hi, sh_sigma;
   __shared__ int sh_ok;
   __shared__ int sh_first[4];
@@ -765,8 +768,8 @@ __global__ void __launch_bounds__(256) bisect_kernel(int m, double *__restrict__
     LLD[i] = work[Lw.LLD + i];
   }
   __syncthreads();
-  const double *misc = work + Lw.misc;
-  double *mu = work + Lw.mu;
+  const gmem<double> *misc = gptr(work + Lw.misc);
+  gmem<double> *mu = gptr(work + Lw.mu);
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (j >= m) return;
@@ -837,12 +840,12 @@ __global__ void __launch_bounds__(128) vector_kernel(int m, double *__restrict__
     LLD[i] = work[Lw.LLD + i];
   }
   __syncthreads();
-  double *mu = work + Lw.mu;
-  double *Z = work + Lw.Z;
-  double *Lp = work + Lw.scr;
-  double *Um = work + Lw.scr + (size_t)m * m;
-  double *sv = work + Lw.scr + 2 * (size_t)m * m;
-  double *pv = work + Lw.scr + 3 * (size_t)m * m;
+  gmem<double> *mu = gptr(work + Lw.mu);
+  gmem<double> *Z = gptr(work + Lw.Z);
+  gmem<double> *Lp = gptr(work + Lw.scr);
+  gmem<double> *Um = gptr(work + Lw.scr + (size_t)m * m);
+  gmem<double> *sv = gptr(work + Lw.scr + 2 * (size_t)m * m);
+  gmem<double> *pv = gptr(work + Lw.scr + 3 * (size_t)m * m);
   const int l = threadIdx.x & 63, role = threadIdx.x >> 6;  // role: wave-uniform
   const int j = blockIdx.x * 64 + l;
   const bool act = j < m;
@@ -1021,8 +1024,11 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
   const int ncl = list[0];
   if (g >= ncl || list[3 + 3 * g]) return;  // not a cluster, or inside a chain
   const int c0 = list[1 + 3 * g];           // the chain's first index
-  const double *dg = work + Lw.d, *eg = work + Lw.e, *misc = work + Lw.misc;
-  double *mu = work + Lw.mu, *Z = work + Lw.Z;
+  const gmem<double> *dg = gptr(work + Lw.d);
+  const gmem<double> *eg = gptr(work + Lw.e);
+  const gmem<double> *misc = gptr(work + Lw.misc);
+  gmem<double> *mu = gptr(work + Lw.mu);
+  gmem<double> *Z = gptr(work + Lw.Z);
   __shared__ double H[kMaxCluster][kMaxCluster + 1];
   __shared__ double Vc[kMaxCluster][kMaxCluster + 1];
   __shared__ double dots[kEigMaxM];
@@ -1036,7 +1042,7 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
   const double sigma = misc[3];
   for (int cl = g; cl < ncl && (cl == g || list[3 + 3 * cl]); ++cl) {
   const int a = list[1 + 3 * cl], c = list[2 + 3 * cl] - a + 1;
-  double *W = work + Lw.scr + (size_t)a * m;  // m x c, this cluster's columns of the scratch
+  gmem<double> *W = gptr(work + Lw.scr + (size_t)a * m);  // m x c, this cluster's columns of the scratch
   // 1a. against the chain's earlier clusters (columns c0 .. a - 1, orthonormal already), as
   //     blocks: twice Z_c <- Z_c - P (P^T Z_c) for chunks P of 64 columns, on the matrix cores
   for (int pass = 0; pass < 2 && a > c0; ++pass) {
@@ -1095,14 +1101,14 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
   // 1b. the cluster's own vectors in order (a vector replaced by a probe is taken against
   //     the whole chain again)
   for (int q = 0; q < c; ++q) {
-    double *zq = Z + (size_t)(a + q) * m;
+    gmem<double> *zq = Z + (size_t)(a + q) * m;
     int replaced = 0;
     for (int pass = 0; pass < 2; ++pass) {
       const int pbase = replaced ? c0 : a;
       const int np = a + q - pbase;  // earlier vectors: columns pbase .. a + q - 1
       if (np > 0) {
         for (int p = wave; p < np; p += nw) {
-          const double *zp = Z + (size_t)(pbase + p) * m;
+          const gmem<double> *zp = Z + (size_t)(pbase + p) * m;
           double part = 0.0;
           for (int i = lane; i < m; i += 64) part += zp[i] * zq[i];
           part = wave_sum(part);
@@ -1138,7 +1144,7 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
   }
   // 2. W = T Z_c and H = Z_c^T W, one dot product per wave at a time
   for (int q = 0; q < c; ++q) {
-    const double *zq = Z + (size_t)(a + q) * m;
+    const gmem<double> *zq = Z + (size_t)(a + q) * m;
     for (int i = tid; i < m; i += nt) {
       double v = dg[i] * zq[i];
       if (i > 0) v += eg[i - 1] * zq[i - 1];
@@ -1150,7 +1156,7 @@ __global__ void __launch_bounds__(256) cluster_kernel(int m, double *__restrict_
   for (int pq = wave; pq < c * c; pq += nw) {
     const int p = pq % c, q = pq / c;
     if (p > q) continue;
-    const double *zp = Z + (size_t)(a + p) * m;
+    const gmem<double> *zp = Z + (size_t)(a + p) * m;
     double part = 0.0;
     for (int i = lane; i < m; i += 64) part += zp[i] * W[(size_t)q * m + i];
     part = wave_sum(part);
@@ -1268,7 +1274,10 @@ __global__ void __launch_bounds__(256)
     m = J.m, work = J.work, lam = J.lam, Vout = J.Z;
   }
   EigLayout Lw(m);
-  const double *Hv = work + Lw.Hv, *Z = work + Lw.Z, *mu = work + Lw.mu, *misc = work + Lw.misc;
+  const gmem<double> *Hv = gptr(work + Lw.Hv);
+  const gmem<double> *Z = gptr(work + Lw.Z);
+  const gmem<double> *mu = gptr(work + Lw.mu);
+  const gmem<double> *misc = gptr(work + Lw.misc);
   const int lane = threadIdx.x & 63;
   const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (col >= m) return;
@@ -1374,8 +1383,8 @@ __global__ void __launch_bounds__(64)
   const int k0 = blockIdx.x * kWyB;
   if (k0 >= m) return;
   EigLayout Lw(m);
-  const double *V = work + Lw.Hv + (size_t)k0 * m;  // V[i + j m] = v_{k0+j}[i]
-  double *Tb = work + Lw.scr + (size_t)blockIdx.x * kWyB * kWyB;
+  const gmem<double> *V = gptr(work + Lw.Hv + (size_t)k0 * m);  // V[i + j m] = v_{k0+j}[i]
+  gmem<double> *Tb = gptr(work + Lw.scr + (size_t)blockIdx.x * kWyB * kWyB);
   const int nr = min(kWyB, m - k0);
   __shared__ double G[kWyB][kWyB + 1];
   const int lane = threadIdx.x, li = lane & 15, lg = lane >> 4;
@@ -1418,8 +1427,11 @@ __global__ void __launch_bounds__(256)
   const int c0 = blockIdx.x * kWyS;
   if (c0 >= m) return;
   EigLayout Lw(m);
-  const double *Hv = work + Lw.Hv, *Z = work + Lw.Z, *mu = work + Lw.mu, *misc = work + Lw.misc;
-  const double *Tall = work + Lw.scr;
+  const gmem<double> *Hv = gptr(work + Lw.Hv);
+  const gmem<double> *Z = gptr(work + Lw.Z);
+  const gmem<double> *mu = gptr(work + Lw.mu);
+  const gmem<double> *misc = gptr(work + Lw.misc);
+  const gmem<double> *Tall = gptr(work + Lw.scr);
   constexpr int LW = kWyB + 1;
   // strip and reflector block, column-major with ld = m + 1 (odd: no bank clash)
   __shared__ double S[kWyS * (kWyMaxM + 1)], Vs[kWyB * (kWyMaxM + 1)];

@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(64)
   if (kend > kbeg) {
     const double *Ab = TA ? A + (size_t)m0 * lda + kbeg : A + (size_t)kbeg * lda + m0;
     const double *Bb = TB ? B + (size_t)kbeg * ldb + n0 : B + (size_t)n0 * ldb + kbeg;
-    wave_mma32<TA != 0, TB != 0>(Ab, lda, Bb, ldb, kend - kbeg, M - m0, N - n0, acc);
+    wave_mma32<TA != 0, TB != 0>(gptr(Ab), lda, gptr(Bb), ldb, kend - kbeg, M - m0, N - n0, acc);
   }
 
 #pragma unroll
@@ -81,11 +81,11 @@ __global__ void __launch_bounds__(64)
         if (row < M && col < N) {
           const double v = acc[rt][ct][r];
           if (partial) {
-            partial[(size_t)kz * M * N + (size_t)col * M + row] = v;
+            gptr(partial)[(size_t)kz * M * N + (size_t)col * M + row] = v;
           } else {
             double out = alpha * v;
-            if (beta != 0.0) out += beta * C[(size_t)col * ldc + row];
-            C[(size_t)col * ldc + row] = out;
+            if (beta != 0.0) out += beta * gptr(C)[(size_t)col * ldc + row];
+            gptr(C)[(size_t)col * ldc + row] = out;
           }
         }
       }

@@ -199,6 +199,46 @@ __device__ void store_block(double *xs64, float *xs32, int t, int s, int E_, int
   }
 }
 
+// The same stores through buffer resources over the whole trajectory: the block and row
+// offsets are scalars (SGPR soffset) and the lane offset one VGPR, so no 64-bit address is
+// formed per store. Used when the trajectory is below 2^31 bytes.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+struct TrajStore {
+  __amdgpu_buffer_rsrc_t r64, r32;
+  bool has32;
+};
+template <int E>
+__device__ __forceinline__ void store_block_buf(const TrajStore &ts, int t, int s, int NT, int l,
+                                                const double (&v)[E], double hl2, double hl1,
+                                                double hr1, double hr2) {
+  const int row0 = (t * 4 + s) * (E + 4);
+  auto st64 = [&](int row, double x) {
+    u32x2 d;
+    __builtin_memcpy(&d, &x, sizeof(d));
+    __builtin_amdgcn_raw_buffer_store_b64(d, ts.r64, l * 8, (row0 + row) * NT * 8, 0);
+  };
+  auto st32 = [&](int row, double x) {
+    const float f = (float)x;
+    unsigned u;
+    __builtin_memcpy(&u, &f, sizeof(u));
+    __builtin_amdgcn_raw_buffer_store_b32(u, ts.r32, l * 4, (row0 + row) * NT * 4, 0);
+  };
+#pragma unroll
+  for (int j = 0; j < E; ++j) st64(j, v[j]);
+  st64(E + 0, hl2);
+  st64(E + 1, hl1);
+  st64(E + 2, hr1);
+  st64(E + 3, hr2);
+  if (ts.has32) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) st32(j, v[j]);
+    st32(E + 0, hl2);
+    st32(E + 1, hl1);
+    st32(E + 2, hr1);
+    st32(E + 3, hr2);
+  }
+}
+
 // xu != nullptr: one workgroup per initial state (x0 + blockIdx.x n), no stage blocks; the
 // state at every observed (step, variable) pair u is written to xu[blockIdx.x U + u].
 template <int E>
@@ -238,6 +278,22 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
   const double h = mv.h, F = mv.F;
   double x[E], xs[E], acc[E], k[E], xe[E + 4];
   double hl2 = 0, hl1 = 0, hr1 = 0, hr2 = 0;
+  // the stage blocks through buffer stores when the whole trajectory fits a 2^31-byte resource
+  const long long traj_bytes = (long long)(nsteps + 1) * 4 * (E + 4) * NT * (long long)sizeof(double);
+  const bool bufst = xs64 != nullptr && !jobs && traj_bytes <= 0x7fffffffLL;
+  TrajStore tst;
+  tst.has32 = xs32 != nullptr;
+  if (bufst) {
+    tst.r64 = __builtin_amdgcn_make_buffer_rsrc(xs64, (short)0, (int)traj_bytes, 0x00020000);
+    tst.r32 = __builtin_amdgcn_make_buffer_rsrc(tst.has32 ? (void *)xs32 : (void *)xs64, (short)0,
+                                                (int)(traj_bytes / 2), 0x00020000);
+  }
+  auto store_blk = [&](int t, int sidx, const double (&v)[E]) __attribute__((always_inline)) {
+    if (bufst)
+      store_block_buf<E>(tst, t, sidx, NT, l, v, hl2, hl1, hr1, hr2);
+    else
+      store_block<E>(xs64, xs32, t, sidx, E, NT, l, v, hl2, hl1, hr1, hr2);
+  };
 #pragma unroll
   for (int j = 0; j < E; ++j) x[j] = active ? gptr(x0)[a + j] : 0.0;
 
@@ -256,7 +312,7 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
     exchange<double, E>(lds_d, parity, NT, l, active, hm, x, hl2, hl1, hr1, hr2);
     if (active) {
       build(x);
-      if (xs64) store_block<E>(xs64, xs32, t, 0, E, NT, l, x, hl2, hl1, hr1, hr2);
+      if (xs64) store_blk(t, 0, x);
       tendency<E>(xe, F, k);
 #pragma unroll
       for (int j = 0; j < E; ++j) {
@@ -268,7 +324,7 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
     exchange<double, E>(lds_d, parity, NT, l, active, hm, xs, hl2, hl1, hr1, hr2);
     if (active) {
       build(xs);
-      if (xs64) store_block<E>(xs64, xs32, t, 1, E, NT, l, xs, hl2, hl1, hr1, hr2);
+      if (xs64) store_blk(t, 1, xs);
       tendency<E>(xe, F, k);
 #pragma unroll
       for (int j = 0; j < E; ++j) {
@@ -280,7 +336,7 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
     exchange<double, E>(lds_d, parity, NT, l, active, hm, xs, hl2, hl1, hr1, hr2);
     if (active) {
       build(xs);
-      if (xs64) store_block<E>(xs64, xs32, t, 2, E, NT, l, xs, hl2, hl1, hr1, hr2);
+      if (xs64) store_blk(t, 2, xs);
       tendency<E>(xe, F, k);
 #pragma unroll
       for (int j = 0; j < E; ++j) {
@@ -292,7 +348,7 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
     exchange<double, E>(lds_d, parity, NT, l, active, hm, xs, hl2, hl1, hr1, hr2);
     if (active) {
       build(xs);
-      if (xs64) store_block<E>(xs64, xs32, t, 3, E, NT, l, xs, hl2, hl1, hr1, hr2);
+      if (xs64) store_blk(t, 3, xs);
       tendency<E>(xe, F, k);
 #pragma unroll
       for (int j = 0; j < E; ++j) {
@@ -304,7 +360,7 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
   if (xu && active) sample_obs<E>(mv, nsteps, l, x, xu);
   if (xs64) {
     exchange<double, E>(lds_d, parity, NT, l, active, hm, x, hl2, hl1, hr1, hr2);
-    if (active) store_block<E>(xs64, xs32, nsteps, 0, E, NT, l, x, hl2, hl1, hr1, hr2);
+    if (active) store_blk(nsteps, 0, x);
   }
   if (xout && active) {
 #pragma unroll

@@ -306,6 +306,82 @@ __global__ void __launch_bounds__(E >= 8 ? 512 : 1024)
     xe[E + 3] = hr2;
   };
 
+  if constexpr (E >= 8) {
+    if (!jobs && !xu && mv.A == NT) {
+      // One full problem: each stage computes its four boundary elements first and publishes
+      // the next stage's boundary values before the interior elements and the block's
+      // stores, so the halo exchange's LDS round trip overlaps that work. The same
+      // expressions as the general loop below, so the same results bit for bit.
+      auto publish = [&](const double (&v)[E]) __attribute__((always_inline)) {
+        double *bb = lds_d + parity * kLdsSlots * NT;
+        bb[0 * NT + l] = v[0];
+        bb[1 * NT + l] = v[1];
+        bb[2 * NT + l] = v[E - 2];
+        bb[3 * NT + l] = v[E - 1];
+      };
+      auto receive = [&]() __attribute__((always_inline)) {
+        __syncthreads();
+        const double *bb = lds_d + parity * kLdsSlots * NT;
+        hl2 = bb[hm.off[0]];
+        hl1 = bb[hm.off[1]];
+        hr1 = bb[hm.off[2]];
+        hr2 = bb[hm.off[3]];
+        parity ^= 1;
+      };
+      auto store_xe = [&](int t, int sidx) __attribute__((always_inline)) {
+        double cur[E];
+#pragma unroll
+        for (int j = 0; j < E; ++j) cur[j] = xe[2 + j];
+        store_blk(t, sidx, cur);
+      };
+      // stage update of element j: c1 = first stage (acc = k), cw = weight of k in acc,
+      // cn = coefficient of k in the next state, to4 = the final stage (the next state is x)
+#define RIOT_TRAJ_ELEM(J, FIRST, CW, CN, LAST)                                   \
+  {                                                                              \
+    const int j_ = (J);                                                          \
+    k[j_] = (xe[j_ + 3] - xe[j_]) * xe[j_ + 1] - xe[j_ + 2] + F;                 \
+    if (FIRST)                                                                   \
+      acc[j_] = k[j_];                                                           \
+    else if (LAST)                                                               \
+      acc[j_] += k[j_];                                                          \
+    else                                                                         \
+      acc[j_] += 2.0 * k[j_];                                                    \
+    if (LAST)                                                                    \
+      x[j_] = x[j_] + (h / 6.0) * acc[j_];                                       \
+    else                                                                         \
+      xs[j_] = x[j_] + (CN) * k[j_];                                             \
+  }
+#define RIOT_TRAJ_STAGE(T_, SIDX, FIRST, CN, LAST)                               \
+  {                                                                              \
+    receive();                                                                   \
+    if (SIDX == 0) build(x); else build(xs);                                     \
+    _Pragma("unroll") for (int b_ = 0; b_ < 4; ++b_)                             \
+        RIOT_TRAJ_ELEM(b_ < 2 ? b_ : E - 4 + b_, FIRST, 0, CN, LAST)             \
+    if (LAST) publish(x); else publish(xs);                                      \
+    if (xs64) store_xe(T_, SIDX);                                                \
+    _Pragma("unroll") for (int j2 = 2; j2 < E - 2; ++j2)                         \
+        RIOT_TRAJ_ELEM(j2, FIRST, 0, CN, LAST)                                   \
+  }
+      publish(x);
+      for (int t = 0; t < nsteps; ++t) {
+        RIOT_TRAJ_STAGE(t, 0, true, 0.5 * h, false)
+        RIOT_TRAJ_STAGE(t, 1, false, 0.5 * h, false)
+        RIOT_TRAJ_STAGE(t, 2, false, h, false)
+        RIOT_TRAJ_STAGE(t, 3, false, 0.0, true)
+      }
+#undef RIOT_TRAJ_STAGE
+#undef RIOT_TRAJ_ELEM
+      if (xs64) {
+        receive();
+        store_blk(nsteps, 0, x);
+      }
+      if (xout) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) gptr(xout)[a + j] = x[j];
+      }
+      return;
+    }
+  }
   for (int t = 0; t < nsteps; ++t) {
     if (xu && active) sample_obs<E>(mv, t, l, x, xu);
     // stage 1

@@ -38,10 +38,10 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE 262144 KiB for 262144 KiB written). Valid only for the kernel source it was
 # measured on (sha256 of l96.hip); any other source reports traffic as null.
 TLAD_COUNTERS = {
-    "l96_sha256": "c7b0f1cdf88e6faf7f5a90345ef7c6813b482ddb895b6d67901473049e316359",
+    "l96_sha256": "2c817977a2482b39e5826fb57ef91a05db2c6fa56dda98f4218512f713ee0be5",
     "n": 4096, "nsteps": 100, "m": 272,
-    "fetch_kib": 119401.31, "write_kib": 53584.0,
-    "fetch_scale": 262144.0 / 131088.0625, "write_scale": 1.0,
+    "fetch_kib": 119630.69, "write_kib": 53856.0,
+    "fetch_scale": 262144.0 / 131086.75, "write_scale": 1.0,
 }
 
 WORKLOADS = {

@@ -1728,7 +1728,10 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   // pair form: [C C2] = alpha op(A)^T [B B2] + beta [C C2], two results of N columns each
   const bool pair = B2 != nullptr;
   if (pair && (!C2 || tb != 0 || lower || gram_sq)) return hipErrorInvalidValue;
-  if (pair && !(M >= kGT && 2 * N >= kGT)) {  // too small for the LDS kernel: two products
+  // two products instead when too small for the LDS kernel, or when one product's tiles
+  // already fill the chip (no split over K to share)
+  if (pair && (!(M >= kGT && 2 * N >= kGT) ||
+               ((M + kGT - 1) / kGT) * ((N + kGT - 1) / kGT) >= 256)) {
     hipError_t e = gemm_f64(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial,
                             splitk, st, run);
     if (e != hipSuccess) return e;

@@ -390,10 +390,17 @@ __device__ __noinline__ void cholqr_notify(const CholQrCtl &c, int next) {
                        __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// A pass that does not run (one thread): the next one does not either.
+__device__ void cholqr_ctl_skip(const CholQrCtl &c) {
+  if (c.pass + 1 < c.npass) c.cq[c.pass + 1] = 0;
+  cholqr_notify(c, 0);
+}
+
 __device__ __noinline__ void cholqr_ctl_end(const CholQrCtl &c, bool shifted, bool modified, bool bad) {
   if (c.count) c.count[0] += 1;
-  int &clean = c.cq[c.npass];
-  clean = (!shifted && !modified && !bad) ? clean + 1 : 0;
+  const int prev = (c.pass == 0) ? 0 : c.cq[c.npass];  // pass 0 starts the count
+  const int clean = (!shifted && !modified && !bad) ? prev + 1 : 0;
+  c.cq[c.npass] = clean;
   const int next = (c.pass + 1 < c.npass && clean < 2 && !bad) ? 1 : 0;
   if (c.pass + 1 < c.npass) c.cq[c.pass + 1] = next;
   cholqr_notify(c, next);
@@ -664,9 +671,10 @@ __global__ void __launch_bounds__(kCholThreads)
     run = J.run, modflag = J.modflag;
     gram_sq = nullptr, dinv = nullptr, ctl = CholQrCtl();
   }
-  if (ctl.cq) run = ctl.cq + ctl.pass;
+  // pass 0 of a CholeskyQR always runs; pass p > 0 runs when pass p - 1 set its flag
+  if (ctl.cq) run = ctl.pass == 0 ? nullptr : ctl.cq + ctl.pass;
   if (run && run[0] == 0) {
-    if (threadIdx.x == 0) cholqr_notify(ctl, 0);
+    if (threadIdx.x == 0 && ctl.cq) cholqr_ctl_skip(ctl);
     return;
   }
   gmem<double> *const Lg = gptr(L);  // the factor's global accesses (see gptr)
@@ -974,9 +982,9 @@ __global__ void __launch_bounds__(kCholThreads)
                     int *__restrict__ shifts, const int *__restrict__ run,
                     int *__restrict__ modflag, double *__restrict__ gram_sq,
                     double *__restrict__ dinv, CholQrCtl ctl) {
-  if (ctl.cq) run = ctl.cq + ctl.pass;
+  if (ctl.cq) run = ctl.pass == 0 ? nullptr : ctl.cq + ctl.pass;
   if (run && run[0] == 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) cholqr_notify(ctl, 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && ctl.cq) cholqr_ctl_skip(ctl);
     return;
   }
   const int nblk = (m + kPB - 1) / kPB;
@@ -1394,7 +1402,7 @@ __global__ void __launch_bounds__(256)
     trsm_rlt_inv_strip_kernel(int rows, int m, double *__restrict__ X, int ldx,
                               const double *__restrict__ L, const double *__restrict__ dinv,
                               const int *__restrict__ run, int rows2, double *__restrict__ X2,
-                              int ldx2) {
+                              int ldx2, const double *__restrict__ Xsrc) {
   if (run && run[0] == 0) return;
   __shared__ double xs[kStripM * kXsLd];  // xs[j kXsLd + i] = X[r0 + i][j]
   __shared__ double Bm[32 * kXsLd];       // B, column-major
@@ -1403,8 +1411,10 @@ __global__ void __launch_bounds__(256)
   const int li = lane & 15, lg = lane >> 4;
   int r0 = blockIdx.x * kSR;
   const int nblk1 = (rows + kSR - 1) / kSR;
+  // the first matrix's values come from Xsrc when given (same leading dimension)
+  const double *src = Xsrc ? Xsrc : X;
   if ((int)blockIdx.x >= nblk1) {  // a block of the second matrix
-    r0 = ((int)blockIdx.x - nblk1) * kSR, rows = rows2, X = X2, ldx = ldx2;
+    r0 = ((int)blockIdx.x - nblk1) * kSR, rows = rows2, X = X2, ldx = ldx2, src = X2;
   }
   if (r0 >= rows) return;
   const int nr = min(kSR, rows - r0);
@@ -1417,7 +1427,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
       const int j = min((tid >> 4) + 16 * t, m - 1);
-      v[t] = X[(size_t)j * ldx + r0 + ic];
+      v[t] = src[(size_t)j * ldx + r0 + ic];
     }
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
@@ -1848,13 +1858,21 @@ hipError_t launch_trsm_diag_inv(int m, const double *L, double *dinv, hipStream_
 
 hipError_t launch_trsm_rlt_inv(int rows, int m, double *X, int ldx, const double *L,
                                const double *dinv, hipStream_t st, const int *run, int rows2,
-                               double *X2, int ldx2) {
+                               double *X2, int ldx2, const double *Xsrc) {
   if (!X2) rows2 = 0;
   if (rows < 0 || rows2 < 0 || m <= 0 || rows + rows2 == 0) return hipSuccess;
+  if (Xsrc == X) Xsrc = nullptr;
+  if (Xsrc && m > kStripM) {  // the general kernel solves in place: copy first
+    if (run) return hipErrorInvalidValue;  // the copy could not be predicated
+    const hipError_t e = hipMemcpyAsync(X, Xsrc, (size_t)ldx * m * sizeof(double),
+                                        hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    Xsrc = nullptr;
+  }
   if (m <= kStripM)
     hipLaunchKernelGGL(trsm_rlt_inv_strip_kernel,
                        dim3((rows + kSR - 1) / kSR + (rows2 + kSR - 1) / kSR), dim3(256), 0, st,
-                       rows, m, X, ldx, L, dinv, run, rows2, X2, ldx2);
+                       rows, m, X, ldx, L, dinv, run, rows2, X2, ldx2, Xsrc);
   else
     hipLaunchKernelGGL(trsm_rlt_inv_kernel, dim3((rows + 31) / 32 + (rows2 + 31) / 32), dim3(256),
                        0, st, rows, m, X, ldx, L, dinv, run, rows2, X2, ldx2);
@@ -1874,15 +1892,6 @@ __global__ void cholqr_ctrl_kernel(int *cq, int pass_was_shifted, int *count) {
     cq[1] += 1;
   cq[2] = 0;
   if (cq[1] >= 2) cq[0] = 0;
-}
-
-__global__ void cholqr_start_kernel(int *cq, int npass) {
-  for (int p = threadIdx.x; p <= npass; p += blockDim.x) cq[p] = (p == 0) ? 1 : 0;
-}
-
-hipError_t launch_cholqr_start(int *cq, int npass, hipStream_t st) {
-  hipLaunchKernelGGL(cholqr_start_kernel, dim3(1), dim3(64), 0, st, cq, npass);
-  return hipGetLastError();
 }
 
 __global__ void cholqr_reset_kernel(int *cq) {

@@ -373,19 +373,18 @@ riot_status cholqr(const LaSpace &h, int rows, int m, const double *Xin, double 
       host_ctl = false;
   }
   const int always = shifted ? 3 : 2;  // passes that run whatever the data
-  if (Qout != Xin)
-    RIOT_HIP(hipMemcpyAsync(Qout, Xin, (size_t)rows * m * sizeof(double), hipMemcpyDeviceToDevice,
-                            st));
-  RIOT_HIP(launch_cholqr_start(cq, kMaxCholQRPasses, st));
   for (int pass = 0; pass < kMaxCholQRPasses; ++pass) {
     const bool sh = shifted && pass == 0;
-    int *run = cq + pass;  // set by the previous pass's Cholesky
+    // pass 0 always runs, on Xin (its solve writes Qout); pass p > 0 runs when the Cholesky
+    // of pass p - 1 set run flag p (a pass that does not run clears the next one's flag)
+    int *run = pass == 0 ? nullptr : cq + pass;
+    const double *src = pass == 0 ? Xin : Qout;
     // the Gram goes straight into R (lower triangle, zero upper) with the partial sums of
     // its squared Frobenius norm and distance from I, and is factored there in place; the
     // Cholesky also writes its diagonal blocks' inverses into the Gram's split-K buffer,
     // free by then, and decides whether the next pass runs
     double *gsq = h.partial + gram_sq_offset(m);
-    RIOT_HIP(gemm_f64(1, 0, m, m, rows, 1.0, Qout, rows, Qout, rows, 0.0, h.R, m, h.partial,
+    RIOT_HIP(gemm_f64(1, 0, m, m, rows, 1.0, src, rows, src, rows, 0.0, h.R, m, h.partial,
                       kSplitK, st, run, true, gsq));
     CholQrCtl ctl;
     ctl.cq = cq, ctl.pass = pass, ctl.npass = kMaxCholQRPasses, ctl.count = count;
@@ -398,7 +397,7 @@ riot_status cholqr(const LaSpace &h, int rows, int m, const double *Xin, double 
                                  st, nullptr, nullptr, gsq, h.partial, ctl));
     // X and its companion in one launch
     RIOT_HIP(launch_trsm_rlt_inv(rows, m, Qout, rows, h.R, h.partial, st, run, comp ? mc : 0,
-                                 comp, comp ? mc : 1));
+                                 comp, comp ? mc : 1, pass == 0 ? Xin : nullptr));
     if (wait) {
       int next = 1;
       const riot_status ws = wait_pass(h, ctl.seq, cq + pass + 1, &next);

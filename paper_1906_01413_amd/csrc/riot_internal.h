@@ -58,9 +58,10 @@ struct CqJob {
   int *count;
 };
 // CholeskyQR pass control carried by the Cholesky of each pass: cq[p] is the run flag of
-// pass p < npass (the launches of pass p return at once when it is 0), cq[npass] counts
-// consecutive clean passes (unshifted, no pivot replaced). The Cholesky of pass p sets
-// cq[p + 1]: 1 until two clean passes in a row (or a breakdown); count[0] (if given) counts
+// pass 0 < p < npass (the launches of pass p return at once when it is 0; pass 0 always
+// runs), cq[npass] counts consecutive clean passes (unshifted, no pivot replaced; pass 0
+// starts the count). The Cholesky of pass p sets cq[p + 1]: 1 until two clean passes in a
+// row (or a breakdown), and 0 when pass p itself did not run; count[0] (if given) counts
 // the passes run.
 struct CholQrCtl {
   int *cq = nullptr;
@@ -318,8 +319,6 @@ hipError_t launch_copy_batched(int nprob, long long maxcount, const CopyJob *job
 // CholeskyQR pass control (see cholqr in the API layer): reset, then one call per pass;
 // count (optional) is incremented once per pass that ran.
 hipError_t launch_cholqr_reset(int *cq, hipStream_t st);
-// cq[0] = 1, cq[1 .. npass] = 0 (the start of a CholeskyQR driven by CholQrCtl)
-hipError_t launch_cholqr_start(int *cq, int npass, hipStream_t st);
 hipError_t launch_cholqr_ctrl(int *cq, int pass_was_shifted, int *count, hipStream_t st);
 
 // X <- X L^{-T} in place (X rows x m, leading dimension ldx; L lower m x m), through the
@@ -328,9 +327,12 @@ hipError_t launch_cholqr_ctrl(int *cq, int pass_was_shifted, int *count, hipStre
 // (rows2 x m, leading dimension ldx2, or null) is solved with the same L in the same launch.
 hipError_t launch_trsm_diag_inv(int m, const double *L, double *dinv, hipStream_t st,
                                 const int *run = nullptr);
+// Xsrc (optional, not with run for m > 288): the first matrix's input, read from Xsrc
+// (leading dimension ldx) and the solution written to X.
 hipError_t launch_trsm_rlt_inv(int rows, int m, double *X, int ldx, const double *L,
                                const double *dinv, hipStream_t st, const int *run = nullptr,
-                               int rows2 = 0, double *X2 = nullptr, int ldx2 = 1);
+                               int rows2 = 0, double *X2 = nullptr, int ldx2 = 1,
+                               const double *Xsrc = nullptr);
 
 // K <- (K + K^T)/2 and asym[0] = ||K - K^T||_F / ||K||_F (before symmetrisation).
 // part: 128 doubles of scratch.

@@ -1715,11 +1715,13 @@ __global__ void zero_ints_kernel(int *__restrict__ p, int count) {
 }
 
 __global__ void check_finite_kernel(long long count, const double *__restrict__ x,
-                                    int *__restrict__ flag) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+                                    int *__restrict__ flag, long long count2,
+                                    const double *__restrict__ x2) {
+  const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
   bool bad = false;
-  for (; i < count; i += stride) bad |= !isfinite(x[i]);
+  for (long long i = i0; i < count; i += stride) bad |= !isfinite(x[i]);
+  for (long long i = i0; i < count2; i += stride) bad |= !isfinite(x2[i]);
   if (bad) flag[0] = 1;
 }
 
@@ -1916,7 +1918,7 @@ hipError_t launch_symmetrize(int m, double *K, double *asym, double *part, hipSt
   const int nblk = 64;
   hipLaunchKernelGGL(symmetrize_kernel, dim3(nblk), dim3(256), 0, st, m, K, part);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !asym) return e;
   hipLaunchKernelGGL(symmetrize_norm_kernel, dim3(1), dim3(64), 0, st, nblk, part, asym);
   return hipGetLastError();
 }
@@ -1975,11 +1977,14 @@ hipError_t launch_zero_ints(int *p, int count, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_check_finite(long long count, const double *x, int *flag, hipStream_t st) {
-  if (count <= 0) return hipSuccess;
-  long long blocks = (count + 255) / 256;
+hipError_t launch_check_finite(long long count, const double *x, int *flag, hipStream_t st,
+                               long long count2, const double *x2) {
+  if (!x2) count2 = 0;
+  if (count <= 0 && count2 <= 0) return hipSuccess;
+  long long blocks = (std::max(count, count2) + 255) / 256;
   if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)blocks), dim3(256), 0, st, count, x, flag);
+  hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)blocks), dim3(256), 0, st, count, x, flag,
+                     count2, x2);
   return hipGetLastError();
 }
 

@@ -423,11 +423,11 @@ riot_status sketch_eig(const LaSpace &la, int n, int m, const double *Y, const d
   rs = cholqr(la, m, m, la.B2, la.Zs, false, 1, la.B1, m);
   if (rs != RIOT_OK) return rs;
   RIOT_HIP(gemm_f64(0, 1, m, m, m, 1.0, la.B1, m, la.Zs, m, 0.0, la.K, m, la.partial, kSplitK, st));
-  RIOT_HIP(launch_symmetrize(m, la.K, la.scal + 1, la.partial, st));
+  // ||K - K^T|| / ||K|| is only reported (info)
+  RIOT_HIP(launch_symmetrize(m, la.K, info ? la.scal + 1 : nullptr, la.partial, st));
   RIOT_HIP(launch_eig(m, la.K, lambda, la.Zs, la.sywork, la.flags + 2, st));
   RIOT_HIP(gemm_f64(0, 0, n, m, m, 1.0, la.Q, n, la.Zs, m, 0.0, V, n, nullptr, 1, st));
-  RIOT_HIP(launch_check_finite(m, lambda, la.flags + 3, st));
-  RIOT_HIP(launch_check_finite((long long)n * m, V, la.flags + 3, st));
+  RIOT_HIP(launch_check_finite(m, lambda, la.flags + 3, st, (long long)n * m, V));
   if (info) {
     RIOT_HIP(gemm_f64(1, 0, m, m, n, 1.0, la.Q, n, la.Q, n, 0.0, la.G, m, la.partial, kSplitK, st));
     RIOT_HIP(launch_orth_err(m, la.G, la.scal + 2, st));

@@ -334,7 +334,8 @@ hipError_t launch_trsm_rlt_inv(int rows, int m, double *X, int ldx, const double
                                int rows2 = 0, double *X2 = nullptr, int ldx2 = 1,
                                const double *Xsrc = nullptr);
 
-// K <- (K + K^T)/2 and asym[0] = ||K - K^T||_F / ||K||_F (before symmetrisation).
+// K <- (K + K^T)/2 and, if asym is given, asym[0] = ||K - K^T||_F / ||K||_F (before
+// symmetrisation).
 // part: 128 doubles of scratch.
 hipError_t launch_symmetrize(int m, double *K, double *asym, double *part, hipStream_t st);
 
@@ -383,6 +384,8 @@ hipError_t launch_axpby(long long count, double a, double *Y, double b, const do
 hipError_t launch_block_band_zero(int m, int l, double *T, hipStream_t st);
 
 // Non-finite check over `count` doubles: flag[0] |= 1 when any value is NaN or Inf.
-hipError_t launch_check_finite(long long count, const double *x, int *flag, hipStream_t st);
+// flag[0] = 1 if x[0 .. count) or x2[0 .. count2) holds a NaN or an infinity.
+hipError_t launch_check_finite(long long count, const double *x, int *flag, hipStream_t st,
+                               long long count2 = 0, const double *x2 = nullptr);
 
 }  // namespace riot

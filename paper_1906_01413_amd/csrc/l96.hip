@@ -1238,10 +1238,27 @@ __global__ void __launch_bounds__(256)
   const size_t c = blockIdx.x;
   const int r0 = blockIdx.y * kLSeg, len = min(kLSeg, n - r0);
   const double *x = X + c * n;
-  for (int k = threadIdx.x; k < len + 2 * w; k += blockDim.x) {
+  const int tot = len + 2 * w;
+  auto src_of = [&](int k) {
     int src = (r0 + k - w) % n;
-    if (src < 0) src += n;
-    ext[k] = x[src];
+    return src < 0 ? src + n : src;
+  };
+  if (tot <= 6 * 256 && blockDim.x == 256) {
+    // the segment's loads all issued before the first wait (one memory latency, not one per
+    // round of 256)
+    double v[6];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      const int k = threadIdx.x + 256 * t;
+      v[t] = x[src_of(k < tot ? k : 0)];
+    }
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      const int k = threadIdx.x + 256 * t;
+      if (k < tot) ext[k] = v[t];
+    }
+  } else {
+    for (int k = threadIdx.x; k < tot; k += blockDim.x) ext[k] = x[src_of(k)];
   }
   __syncthreads();
   for (int i = threadIdx.x; i < len; i += blockDim.x) {

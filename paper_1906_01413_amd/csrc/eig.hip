@@ -351,6 +351,8 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+
 constexpr int kTB = 9;
 constexpr int kTileMaxNb = 31;  // m <= 279
 constexpr int kTileMaxThreads = 512;
@@ -889,13 +891,34 @@ __global__ void __launch_bounds__(128) vector_kernel(int m, double *__restrict__
       const int h = m / 2, k0 = role ? h : 0, k1 = role ? m : h;
       double gmin = 0.0;
       int rl = -1;
-#pragma unroll 4
-      for (int k = k0; k < k1; ++k) {
-        const double gk = sv[(size_t)k * m + j] + pv[(size_t)k * m + j] + lam;
-        if (rl < 0 || fabs(gk) < fabs(gmin)) {
-          gmin = gk;
-          rl = k;
+      // chunks of kTw rows, the next chunk's loads in flight while one is scanned (rows
+      // past the range read its last row and are skipped)
+      constexpr int kTw = 8;
+      double sa[kTw], pa[kTw], sb[kTw], pb[kTw];
+      auto ld = [&](int kb, double (&s_)[kTw], double (&p_)[kTw]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < kTw; ++u) {
+          const int k = min(kb + u, k1 - 1);
+          s_[u] = sv[(size_t)k * m + j];
+          p_[u] = pv[(size_t)k * m + j];
         }
+      };
+      auto scan = [&](int kb, const double (&s_)[kTw], const double (&p_)[kTw])
+          __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < kTw; ++u) {
+          const double gk = s_[u] + p_[u] + lam;
+          const bool take = kb + u < k1 && (rl < 0 || fabs(gk) < fabs(gmin));
+          gmin = take ? gk : gmin;
+          rl = take ? kb + u : rl;
+        }
+      };
+      ld(k0, sa, pa);
+      for (int kb = k0; kb < k1; kb += 2 * kTw) {
+        ld(kb + kTw, sb, pb);
+        scan(kb, sa, pa);
+        ld(kb + 2 * kTw, sa, pa);
+        scan(kb + kTw, sb, pb);
       }
       xg[role][l] = gmin;
       xr[role][l] = rl;
@@ -907,25 +930,62 @@ __global__ void __launch_bounds__(128) vector_kernel(int m, double *__restrict__
       gmin = take_low ? xg[0][l] : xg[1][l];
       r = take_low ? xr[0][l] : xr[1][l];
       // vector with z_r = 1: wave 0 builds z_i for i < r, wave 1 for i > r
-      double part;
+      // chunks of kBd rows with the next chunk's factors in flight; the stores go through a
+      // buffer resource over Z, rows outside the vector's part at an offset past its end
+      // (dropped), so no branch separates a chunk's loads from the previous chunk's stores
+      constexpr int kBd = 8;
+      const __amdgpu_buffer_rsrc_t zres = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)Z, (short)0, (int)((size_t)m * m * sizeof(double)), 0x00020000);
+      const int zcol = j * m;
+      auto zstore = [&](bool valid, int row, double v) __attribute__((always_inline)) {
+        u32x2_t bits;
+        __builtin_memcpy(&bits, &v, sizeof(bits));
+        __builtin_amdgcn_raw_buffer_store_b64(
+            bits, zres, valid ? (zcol + row) * (int)sizeof(double) : 0x7ffffff8, 0, 0);
+      };
+      double part, cur[kBd], nxt[kBd];
       if (role == 0) {
         Z[(size_t)j * m + r] = 1.0;
         part = 1.0;
         double z = 1.0;
-#pragma unroll 8
-        for (int i = r - 1; i >= 0; --i) {
-          z = -Lp[(size_t)i * m + j] * z;
-          Z[(size_t)j * m + i] = z;
-          part += z * z;
+        // rows r - 1 down to 0: L+ factors Lp[i]
+#pragma unroll
+        for (int u = 0; u < kBd; ++u) cur[u] = Lp[(size_t)max(r - 1 - u, 0) * m + j];
+        for (int base = r - 1; base >= 0; base -= kBd) {
+#pragma unroll
+          for (int u = 0; u < kBd; ++u) nxt[u] = Lp[(size_t)max(base - kBd - u, 0) * m + j];
+#pragma unroll
+          for (int u = 0; u < kBd; ++u) {
+            const int i = base - u;
+            const bool valid = i >= 0;
+            const double zn = -cur[u] * z;
+            z = valid ? zn : z;
+            part = valid ? part + zn * zn : part;
+            zstore(valid, i, zn);
+          }
+#pragma unroll
+          for (int u = 0; u < kBd; ++u) cur[u] = nxt[u];
         }
       } else {
         part = 0.0;
         double z = 1.0;
-#pragma unroll 8
-        for (int i = r; i < m - 1; ++i) {
-          z = -Um[(size_t)i * m + j] * z;
-          Z[(size_t)j * m + i + 1] = z;
-          part += z * z;
+        // rows r + 1 up to m - 1: U- factors Um[i], i = r .. m - 2
+#pragma unroll
+        for (int u = 0; u < kBd; ++u) cur[u] = Um[(size_t)min(r + u, m - 2) * m + j];
+        for (int base = r; base < m - 1; base += kBd) {
+#pragma unroll
+          for (int u = 0; u < kBd; ++u) nxt[u] = Um[(size_t)min(base + kBd + u, m - 2) * m + j];
+#pragma unroll
+          for (int u = 0; u < kBd; ++u) {
+            const int i = base + u;
+            const bool valid = i < m - 1;
+            const double zn = -cur[u] * z;
+            z = valid ? zn : z;
+            part = valid ? part + zn * zn : part;
+            zstore(valid, i + 1, zn);
+          }
+#pragma unroll
+          for (int u = 0; u < kBd; ++u) cur[u] = nxt[u];
         }
       }
       xn[role][l] = part;

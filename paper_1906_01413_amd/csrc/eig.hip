@@ -1498,9 +1498,30 @@ __global__ void __launch_bounds__(256)
   __shared__ double Wp[4][kWyS * LW], Ws[kWyS * LW], W2[kWyS * LW], Ts[kWyB * kWyB];
   const int ldS = m + 1, ldV = m + 1, nc = min(kWyS, m - c0);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
-  for (int idx = tid; idx < kWyS * m; idx += 256) {
-    const int i = idx % m, j = idx / m;
-    S[i + j * ldS] = (j < nc) ? Z[(size_t)(c0 + j) * m + i] : 0.0;
+  __shared__ double muS[kWyMaxM];  // the shifted eigenvalues, for the final ordering
+  {
+    // every load of the strip (and of the eigenvalues) issued before the first wait, at a
+    // clamped address past the strip's end (values dropped)
+    constexpr int kPer = (kWyS * kWyMaxM + 255) / 256;
+    double v[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int idx = min(tid + 256 * t, kWyS * m - 1);
+      const int i = idx % m, j = min(idx / m, nc - 1);
+      v[t] = Z[(size_t)(c0 + j) * m + i];
+    }
+    const double shift = misc[3];
+    const double mv0 = mu[min(tid, m - 1)], mv1 = mu[min(tid + 256, m - 1)];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int idx = tid + 256 * t;
+      if (idx < kWyS * m) {
+        const int i = idx % m, j = idx / m;
+        S[i + j * ldS] = (j < nc) ? v[t] : 0.0;
+      }
+    }
+    if (tid < m) muS[tid] = mv0 + shift;
+    if (tid + 256 < m) muS[tid + 256] = mv1 + shift;
   }
   __syncthreads();
   const int nblk = (m + kWyB - 1) / kWyB;
@@ -1596,10 +1617,10 @@ __global__ void __launch_bounds__(256)
   // ascending index col -> descending position (ties keep a stable order)
   for (int j = wave; j < nc; j += 4) {
     const int col = c0 + j;
-    const double lj = mu[col] + misc[3];
+    const double lj = muS[col];
     int rank = 0;
     for (int i = lane; i < m; i += 64) {
-      const double lv = mu[i] + misc[3];
+      const double lv = muS[i];
       rank += (lv > lj || (lv == lj && i > col)) ? 1 : 0;
     }
     for (int o = 32; o > 0; o >>= 1) rank += __shfl_xor(rank, o, 64);

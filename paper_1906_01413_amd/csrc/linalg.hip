@@ -1731,12 +1731,54 @@ __global__ void check_finite_kernel(long long count, const double *__restrict__ 
 // Launchers
 // ---------------------------------------------------------------------------
 
+// y = alpha A^T x + beta y for A (K x M, leading dimension lda): one workgroup per output,
+// its 256 threads reading the column A[:, c] and x coalesced (eight loads in flight each),
+// the partial sums reduced in a fixed order (wave trees, then the four waves in turn).
+__global__ void __launch_bounds__(256)
+    gemv_t_kernel(int M, int K, const double *__restrict__ A, int lda,
+                  const double *__restrict__ x, double *__restrict__ y, double alpha,
+                  double beta) {
+  const int c = blockIdx.x;
+  if (c >= M) return;
+  const double *a = A + (size_t)c * lda;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double acc = 0.0;
+  for (int kb = 0; kb < K; kb += 8 * 256) {
+    double av[8], xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = kb + u * 256 + tid;
+      const int kc = k < K ? k : 0;
+      av[u] = a[kc];
+      xv[u] = x[kc];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = (kb + u * 256 + tid < K) ? fma(av[u], xv[u], acc) : acc;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  __shared__ double red[4];
+  if (lane == 0) red[wave] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    const double sum = (red[0] + red[1]) + (red[2] + red[3]);
+    double out = alpha * sum;
+    if (beta != 0.0) out += beta * y[c];
+    y[c] = out;
+  }
+}
+
 hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const double *A, int lda,
                     const double *B, int ldb, double beta, double *C, int ldc, double *partial,
                     int splitk, hipStream_t st, const int *run, bool lower, double *gram_sq,
                     const double *B2, double *C2) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (lower && !(ta == 1 && tb == 0 && M == N)) return hipErrorInvalidValue;
+  if (N == 1 && ta == 1 && tb == 0 && !lower && !gram_sq && !B2 && !run && K > 0) {
+    // a matrix-vector product: one workgroup per output instead of a 32-wide MFMA tile
+    hipLaunchKernelGGL(gemv_t_kernel, dim3(M), dim3(256), 0, st, M, K, A, lda, B, C, alpha,
+                       beta);
+    return hipGetLastError();
+  }
   // pair form: [C C2] = alpha op(A)^T [B B2] + beta [C C2], two results of N columns each
   const bool pair = B2 != nullptr;
   if (pair && (!C2 || tb != 0 || lower || gram_sq)) return hipErrorInvalidValue;

@@ -38,10 +38,10 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE 262144 KiB for 262144 KiB written). Valid only for the kernel source it was
 # measured on (sha256 of l96.hip); any other source reports traffic as null.
 TLAD_COUNTERS = {
-    "l96_sha256": "2c817977a2482b39e5826fb57ef91a05db2c6fa56dda98f4218512f713ee0be5",
+    "l96_sha256": "ed4b794e07e4faaa71aba13c0d74b17c460184496f34ee982540e0daebe220b7",
     "n": 4096, "nsteps": 100, "m": 272,
-    "fetch_kib": 119630.69, "write_kib": 53856.0,
-    "fetch_scale": 262144.0 / 131086.75, "write_scale": 1.0,
+    "fetch_kib": 119633.75, "write_kib": 53856.0,
+    "fetch_scale": 262144.0 / 131086.69, "write_scale": 1.0,
 }
 
 WORKLOADS = {

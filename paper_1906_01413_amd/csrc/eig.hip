@@ -1437,7 +1437,10 @@ constexpr int kWyS = 16;  // strip width
 constexpr int kWyMaxM = 288;
 
 // T_b of block blockIdx.x into the scratch area (column-major 32 x 32 per block).
-__global__ void __launch_bounds__(64)
+// Four waves: the Gram's rows split in four ranges of whole 16-row chunks, the partial sums
+// added in a fixed order; wave 0 then runs the recurrence.
+constexpr int kWyTWaves = 4;
+__global__ void __launch_bounds__(64 * kWyTWaves)
     wy_t_kernel(int m, double *__restrict__ work, const EigJob *__restrict__ jobs) {
   if (jobs) m = jobs[blockIdx.y].m, work = jobs[blockIdx.y].work;
   const int k0 = blockIdx.x * kWyB;
@@ -1447,18 +1450,35 @@ __global__ void __launch_bounds__(64)
   gmem<double> *Tb = gptr(work + Lw.scr + (size_t)blockIdx.x * kWyB * kWyB);
   const int nr = min(kWyB, m - k0);
   __shared__ double G[kWyB][kWyB + 1];
-  const int lane = threadIdx.x, li = lane & 15, lg = lane >> 4;
-  // G = V^T V over rows k0.. (the reflectors vanish above)
-  d4 acc[2][2];
-  zero_acc(acc);
-  wave_mma32<true, false>(V + k0, m, V + k0, m, m - k0, nr, nr, acc);
+  __shared__ double Gp[kWyTWaves][kWyB * kWyB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
+  // G = V^T V over rows k0.. (the reflectors vanish above); wave w takes rows
+  // [k0 + r0, k0 + r1) of the range, whole chunks of 16
+  {
+    const int rows = m - k0, chunks = (rows + 15) / 16;
+    const int c0 = chunks * wave / kWyTWaves, c1 = chunks * (wave + 1) / kWyTWaves;
+    const int r0 = 16 * c0, r1 = min(rows, 16 * c1);
+    d4 acc[2][2];
+    zero_acc(acc);
+    if (r1 > r0)
+      wave_mma32<true, false>(V + k0 + r0, m, V + k0 + r0, m, r1 - r0, nr, nr, acc);
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct)
+      for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) G[16 * rt + lg + 4 * r][16 * ct + li] = acc[rt][ct][r];
+        for (int r = 0; r < 4; ++r)
+          Gp[wave][(16 * rt + lg + 4 * r) * kWyB + 16 * ct + li] = acc[rt][ct][r];
+  }
   __syncthreads();
+  for (int idx = threadIdx.x; idx < kWyB * kWyB; idx += 64 * kWyTWaves) {
+    double g = Gp[0][idx];
+#pragma unroll
+    for (int w = 1; w < kWyTWaves; ++w) g += Gp[w][idx];
+    G[idx / kWyB][idx % kWyB] = g;
+  }
+  __syncthreads();
+  if (wave != 0) return;
   // lane i builds row i of T in registers: T[i][j] = -2 sum_{i<=l<j} T[i][l] G[l][j] needs only
   // its own row and broadcast reads of G, so the recurrence has no barrier
   double x[kWyB];
@@ -1635,8 +1655,8 @@ void launch_backtransform(dim3 grid, int mmax, int m, const double *work, double
   if (mmax <= kWyMaxM) {
     const unsigned nblk = (unsigned)((mmax + kWyB - 1) / kWyB);
     const unsigned nstrip = (unsigned)((mmax + kWyS - 1) / kWyS);
-    hipLaunchKernelGGL(wy_t_kernel, dim3(nblk, grid.y), dim3(64), 0, st, m, const_cast<double *>(work),
-                       jobs);
+    hipLaunchKernelGGL(wy_t_kernel, dim3(nblk, grid.y), dim3(64 * kWyTWaves), 0, st, m,
+                       const_cast<double *>(work), jobs);
     hipLaunchKernelGGL(backtransform_wy_kernel, dim3(nstrip, grid.y), dim3(256), 0, st, m, work, lam,
                        Z, jobs);
     return;

@@ -1034,13 +1034,14 @@ __global__ void __launch_bounds__(64) cluster_scan_kernel(int m, double *__restr
   EigLayout Lw(m);
   // the gap tests in parallel (one flag per neighbour pair), then the scan by one thread
   __shared__ unsigned char cl[kEigMaxM];
+  const gmem<double> *mu = gptr(work + Lw.mu);
   for (int i = threadIdx.x; i + 1 < m; i += blockDim.x) {
-    const double a = work[Lw.mu + i], b = work[Lw.mu + i + 1];
+    const double a = mu[i], b = mu[i + 1];
     cl[i] = fabs(b - a) < 1e-3 * fmax(fabs(b), fabs(a)) ? 1 : 0;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  int *list = reinterpret_cast<int *>(work + Lw.scr + (size_t)m * m);
+  gmem<int> *list = gptr(reinterpret_cast<int *>(work + Lw.scr + (size_t)m * m));
   auto close = [&](int i) { return cl[i] != 0; };
   int cnt = 0, a = 0;
   bool cont = false;

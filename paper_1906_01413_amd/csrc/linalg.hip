@@ -424,6 +424,34 @@ __device__ void first_order_dinv(int m, int b, const double *G, double *dinv, in
   }
 }
 
+// The same for every block of an m <= kFoBlocks * 32 factor, by kCholThreads threads, every
+// load issued before the first wait (kept out of line: the blocked Cholesky's main path
+// keeps its register allocation).
+constexpr int kFoBlocks = 9;
+__device__ __noinline__ void first_order_dinv_all(int m, const double *G, double *dinv) {
+  constexpr int kFoPer = kFoBlocks * 1024 / kCholThreads;
+  const gmem<double> *Gg = gptr(G);
+  const int tid = threadIdx.x;
+  double gv[kFoPer];
+#pragma unroll
+  for (int t = 0; t < kFoPer; ++t) {
+    const int e = tid + kCholThreads * t, b = e >> 10, c = (e >> 5) & 31, r = e & 31;
+    const int c0 = 32 * b, nb = min(32, m - c0);
+    const bool in = c0 < m && c < nb && r < nb;
+    gv[t] = Gg[in ? (size_t)(c0 + c) * m + c0 + r : 0];
+  }
+#pragma unroll
+  for (int t = 0; t < kFoPer; ++t) {
+    const int e = tid + kCholThreads * t, b = e >> 10, c = (e >> 5) & 31, r = e & 31;
+    const int c0 = 32 * b, nb = min(32, m - c0);
+    if (c0 >= m) continue;
+    const double g = gv[t];
+    const double v =
+        (c < nb && r < nb) ? ((r == c) ? 1.5 - 0.5 * g : (r > c ? -g : 0.0)) : 0.0;
+    gptr(dinv)[e] = v;
+  }
+}
+
 // Sum of the partial sums of ||G - I||_F^2 that the Gram's split-K reduction left after
 // those of ||G||_F^2 and the 32 doubles of flags, in a fixed order (every caller in the
 // grid gets the same value).
@@ -691,8 +719,12 @@ __global__ void __launch_bounds__(kCholThreads)
   const bool inplace = gram_sq != nullptr;
   if (inplace && mode == 2 && gram_dev2(m, gram_sq, red) <= kCholFirstOrderDev2) {
     // G within sqrt(u) of the identity: the first-order factor, in place (the diagonal is
-    // the only change: Lg[i][i] = 1 + (G[i][i] - 1) / 2), and its blocks' inverses
-    if (dinv)
+    // the only change: L[i][i] = 1 + (G[i][i] - 1) / 2), and its blocks' inverses (as
+    // first_order_dinv, with every load of the at most nine blocks issued before the first
+    // wait)
+    if (dinv && nt == kCholThreads && m <= kFoBlocks * kPB)
+      first_order_dinv_all(m, L, dinv);
+    else if (dinv)
       for (int b = 0; b * kPB < m; ++b) first_order_dinv(m, b, L, dinv, tid, nt);
     __syncthreads();
     for (int i = tid; i < m; i += nt) Lg[(size_t)i * m + i] = 0.5 + 0.5 * Lg[(size_t)i * m + i];

@@ -1661,8 +1661,9 @@ __global__ void __launch_bounds__(256)
     }
     __syncthreads();
     if (i < n) {
-#pragma unroll 4
-      for (int j = w; j < jn; j += 4) s += V[(size_t)(j0 + j) * n + i] * cf[j];
+      const gmem<double> *Vg = gptr(V);
+#pragma unroll 8
+      for (int j = w; j < jn; j += 4) s += Vg[(size_t)(j0 + j) * n + i] * cf[j];
     }
   }
   part[w][r] = s;
@@ -1710,9 +1711,10 @@ __global__ void __launch_bounds__(256)
     }
     __syncthreads();
     if (i < n) {
-#pragma unroll 4
+      const gmem<double> *Wg = gptr(W);
+#pragma unroll 8
       for (int j = w; j < jn; j += 4) {
-        const double x = W[(size_t)(j0 + j) * n + i];
+        const double x = Wg[(size_t)(j0 + j) * n + i];
         s += cf[j] * x * x;
       }
     }

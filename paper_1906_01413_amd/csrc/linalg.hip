@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(256)
     splitk_reduce_kernel(int M, int N, int splits, const double *__restrict__ partial,
                          double alpha, double beta, double *__restrict__ C, int ldc,
                          const int *__restrict__ run, int lower, double *__restrict__ gram_sq,
-                         double *__restrict__ C2, int N1) {
+                         double *__restrict__ C2, int N1, int sym) {
   if (run && run[0] == 0) return;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t MN = (size_t)M * N;
@@ -278,7 +278,22 @@ __global__ void __launch_bounds__(256)
   if (idx < MN) {
     int row = (int)(idx % M), col = (int)(idx / M);
     if (C2 && col >= N1) C = C2, col -= N1;  // the pair form's second result
-    if (lower && row < col) {
+    if (sym) {
+      // C <- (C + C^T) / 2 as it is formed (M == N): the thread of (row, col), row >= col,
+      // sums both entries' splits in order and writes the mean to both
+      if (row >= col) {
+        const size_t mir = (size_t)row * M + col;
+        double sa = 0.0, sb = 0.0;
+        for (int z = 0; z < splits; ++z) {
+          sa += partial[(size_t)z * MN + idx];
+          sb += partial[(size_t)z * MN + mir];
+        }
+        const double a = alpha * sa, b = alpha * sb;
+        const double v = (row == col) ? a : 0.5 * (a + b);
+        C[(size_t)col * ldc + row] = v;
+        C[(size_t)row * ldc + col] = v;
+      }
+    } else if (lower && row < col) {
       // not computed for a lower-triangle result; zeroed when the result is a Cholesky input
       if (gram_sq) C[(size_t)col * ldc + row] = 0.0;
     } else {
@@ -1804,7 +1819,7 @@ __global__ void __launch_bounds__(256)
 hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const double *A, int lda,
                     const double *B, int ldb, double beta, double *C, int ldc, double *partial,
                     int splitk, hipStream_t st, const int *run, bool lower, double *gram_sq,
-                    const double *B2, double *C2) {
+                    const double *B2, double *C2, bool sym) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (lower && !(ta == 1 && tb == 0 && M == N)) return hipErrorInvalidValue;
   if (N == 1 && ta == 1 && tb == 0 && !lower && !gram_sq && !B2 && !run && K > 0) {
@@ -1816,6 +1831,8 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   // pair form: [C C2] = alpha op(A)^T [B B2] + beta [C C2], two results of N columns each
   const bool pair = B2 != nullptr;
   if (pair && (!C2 || tb != 0 || lower || gram_sq)) return hipErrorInvalidValue;
+  if (sym && (M != N || lower || gram_sq || pair || beta != 0.0 || !partial))
+    return hipErrorInvalidValue;
   // two products instead when too small for the LDS kernel, or when one product's tiles
   // already fill the chip (no split over K to share)
   if (pair && (!(M >= kGT && 2 * N >= kGT) ||
@@ -1845,7 +1862,7 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
   if (kchunk <= 0) kchunk = kround;
   const int splits = K > 0 ? (K + kchunk - 1) / kchunk : 1;
   // the Gram-with-squares form always goes through the reduction, which writes them
-  double *part = (splits > 1 || gram_sq) ? partial : nullptr;
+  double *part = (splits > 1 || gram_sq || sym) ? partial : nullptr;
   if (big) {
     dim3 grid(tm, tn, splits);
     int xs = 0;
@@ -1899,7 +1916,7 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
     const size_t MN = (size_t)M * N;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st,
                        M, N, splits, partial, alpha, beta, C, ldc, run, lower ? 1 : 0, gram_sq,
-                       C2, N1);
+                       C2, N1, sym ? 1 : 0);
     e = hipGetLastError();
   }
   return e;

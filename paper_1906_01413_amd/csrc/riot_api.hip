@@ -422,9 +422,14 @@ riot_status sketch_eig(const LaSpace &la, int n, int m, const double *Y, const d
                     st, nullptr, false, nullptr, Om_eff, la.B2));
   rs = cholqr(la, m, m, la.B2, la.Zs, false, 1, la.B1, m);
   if (rs != RIOT_OK) return rs;
-  RIOT_HIP(gemm_f64(0, 1, m, m, m, 1.0, la.B1, m, la.Zs, m, 0.0, la.K, m, la.partial, kSplitK, st));
-  // ||K - K^T|| / ||K|| is only reported (info)
-  RIOT_HIP(launch_symmetrize(m, la.K, info ? la.scal + 1 : nullptr, la.partial, st));
+  if (info) {  // ||K - K^T|| / ||K|| (reported) needs K before symmetrisation
+    RIOT_HIP(gemm_f64(0, 1, m, m, m, 1.0, la.B1, m, la.Zs, m, 0.0, la.K, m, la.partial, kSplitK,
+                      st));
+    RIOT_HIP(launch_symmetrize(m, la.K, la.scal + 1, la.partial, st));
+  } else {  // K <- (K + K^T) / 2 as the product's split-K reduction forms it
+    RIOT_HIP(gemm_f64(0, 1, m, m, m, 1.0, la.B1, m, la.Zs, m, 0.0, la.K, m, la.partial, kSplitK,
+                      st, nullptr, false, nullptr, nullptr, nullptr, true));
+  }
   RIOT_HIP(launch_eig(m, la.K, lambda, la.Zs, la.sywork, la.flags + 2, st));
   RIOT_HIP(gemm_f64(0, 0, n, m, m, 1.0, la.Q, n, la.Zs, m, 0.0, V, n, nullptr, 1, st));
   RIOT_HIP(launch_check_finite(m, lambda, la.flags + 3, st, (long long)n * m, V));

@@ -267,6 +267,7 @@ hipError_t launch_philox_normal(long long total, uint64_t seed, uint64_t stream,
 // are cleared (flags of the in-place Cholesky); gram_sq[nb + 32 + b] receives a partial sum
 // of ||C - I||_F^2 (each sum in a fixed order). The input form of an in-place Cholesky
 // (launch_chol_blocked with the same gram_sq).
+// sym (M = N, beta = 0, partial given): C is written as (C + C^T) / 2 by the reduction.
 // B2 and C2 (tb = 0, not lower, no gram_sq): the pair form [C C2] = alpha op(A) [B B2]
 // + beta [C C2] in one launch (B2 with ldb and C2 with ldc, N columns each); the partial
 // buffer then holds splitk * M * 2N doubles.
@@ -274,7 +275,7 @@ hipError_t gemm_f64(int ta, int tb, int M, int N, int K, double alpha, const dou
                     const double *B, int ldb, double beta, double *C, int ldc, double *partial,
                     int splitk, hipStream_t st, const int *run = nullptr, bool lower = false,
                     double *gram_sq = nullptr, const double *B2 = nullptr,
-                    double *C2 = nullptr);
+                    double *C2 = nullptr, bool sym = false);
 inline int gram_sq_blocks(int m) { return (int)(((size_t)m * m + 255) / 256); }
 
 // Blocked Cholesky G + s I = L L^T (lower, column-major). mode 0: s = 0; mode 1:
